@@ -1,0 +1,255 @@
+#!/usr/bin/env python
+"""Benchmark of the adaptive-multigrid Wilson-Dirac solve on one MI355X.
+
+One step = one pass of the whole hot path over one batch of right-hand sides:
+the adaptive setup (MR relaxation of the Nv starting vectors on D v = 0,
+FP64 block orthonormalisation, Galerkin coarse operator) followed by the
+MG-preconditioned flexible GCR(50) solve of every right-hand side to true
+relative residual 1e-10 (FP64).  `value` is the step's wall time per
+right-hand side, inputs resident in HBM before the timed region.
+
+Default workload: the 16^4 lattice with links exp(i 0.3 H), antiperiodic
+time, m = m_crit + 0.01 (m_crit from the oracle's Arnoldi, stored in
+tests/golden/mcrit.json), 2-level MG with 4^4 aggregates and Nv = 20, FP64
+throughout, one Gaussian right-hand side.  Unpreconditioned FP64 BiCGStab on
+the same GPU is timed beside it, outside the K steps.
+
+The JSON line also carries the roofline of the dominant kernel (timed with
+HIP events on the library's stream during the timed steps), Dslash bandwidth
+on a lattice larger than the 256 MB Infinity Cache, and the FP64 oracle timed
+on the host as `cpu_baseline`.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MG time-to-solution @ rel.res 1e-10 (s/RHS); Dslash GB/s; D_c MFMA util"
+HBM_PEAK_GBS = 8000.0
+# Algorithmic (compulsory) bytes per work unit, per kernel.
+DSLASH_BYTES = {"f64": 960, "f32": 480}          # per fine site: psi in, 4 links, out
+
+
+def dc_bytes(prec, nv):                            # per coarse site: 9 blocks + in + out
+    b = 16 if prec == "f64" else 8
+    n2 = 2 * nv
+    return 9 * n2 * n2 * b + 2 * n2 * b
+
+
+def transfer_bytes(prec, nv):                      # per fine site: Nv columns (12 cplx) + fine + coarse share
+    b = 16 if prec == "f64" else 8
+    return 12 * nv * b + 12 * b
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--L", type=int, default=16, help="lattice extent (L^4)")
+    ap.add_argument("--eps", type=float, default=0.3)
+    ap.add_argument("--delta", type=float, default=0.01, help="m - m_crit")
+    ap.add_argument("--nv", type=int, default=20)
+    ap.add_argument("--setup-iters", type=int, default=100)
+    ap.add_argument("--nrhs", type=int, default=1)
+    ap.add_argument("--mg-prec", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--coarse-tol", type=float, default=1e-2)
+    ap.add_argument("--big-L", type=int, default=32, help="lattice for the out-of-cache Dslash figure (0: skip)")
+    ap.add_argument("--no-bicgstab", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def load_mcrit(dims, eps, seed):
+    path = os.path.join(ROOT, "tests", "golden", "mcrit.json")
+    key = "x".join(str(d) for d in dims) + f"_eps{eps}_seed{seed}"
+    with open(path) as fh:
+        data = json.load(fh)
+    if key not in data:
+        raise SystemExit(f"no oracle m_crit for {key} in {path}; run tests/golden/make_mcrit.py")
+    return float(data[key]["m_crit"])
+
+
+def dslash_bandwidth(wdmg, synthetic, torch, dev, L, reps=20):
+    """Dslash kernel time on an L^4 lattice (links exp(i 0.45 H)), FP64 and FP32."""
+    dims = (L, L, L, L)
+    u = synthetic.gauge_field(dims, 0.45, synthetic.gauge_seed(3, 2))
+    ctx = wdmg.Context(dims, dev)
+    ctx.set_gauge(torch.from_numpy(u).to(dev), t_bc=-1)
+    del u
+    ctx.set_mass(-1.0)
+    psi = torch.from_numpy(synthetic.gaussian_spinor(dims, 5)).to(dev)
+    out = {}
+    for prec, key in (("f64", "dslash_f64"), ("f32", "dslash_f32")):
+        x = psi if prec == "f64" else psi.to(torch.complex64)
+        ctx.apply_D(x, prec=prec)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        for _ in range(reps):
+            ctx.apply_D(x, prec=prec)
+        n, units, ms = ctx.profile_read()[key]
+        ctx.profile(False)
+        sec = ms / 1e3 / n
+        out[prec] = {"lattice": f"{L}^4", "us_per_launch": sec * 1e6,
+                     "GB_s": DSLASH_BYTES[prec] * units / n / sec / 1e9,
+                     "frac_hbm_peak": DSLASH_BYTES[prec] * units / n / sec / 1e9 / HBM_PEAK_GBS}
+    ctx.close()
+    return out
+
+
+def cpu_baseline(u, b, m, n_d_per_step, nrhs, seconds):
+    """The FP64 oracle's Wilson operator timed on the host (bounded sample)."""
+    from oracle import wilson
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        wilson.apply_D(u, b, m, -1.0)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el > seconds or reps >= 200:
+            break
+    t_apply = el / reps
+    return {
+        "value": t_apply * n_d_per_step / nrhs, "unit": "s/RHS", "cores": 1, "kind": "oracle",
+        "sample": (f"{reps} oracle FP64 Wilson applications on the same lattice ({t_apply:.3f} s each, "
+                   f"numpy, one thread), scaled by the {n_d_per_step} fine-operator applications of one "
+                   "GPU step; a lower bound for the oracle's MG step (coarse, QR and vector work "
+                   "excluded)"),
+        "host_cpus": os.cpu_count(),
+    }
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1",
+                          "n_gpus": a.gpus}))
+        sys.exit(2)
+    import torch
+
+    import synthetic
+    from paper_0811_4331_amd import wdmg
+
+    dev = torch.device("cuda:0")
+    L = a.L
+    dims = (L, L, L, L)
+    i_eps = {0.2: 0, 0.3: 1, 0.45: 2}.get(a.eps, 9)
+    cfg = 1 if L == 8 else 2  # workload numbering of the seeds: 8^4 -> 1, 16^4 -> 2
+    gseed = synthetic.gauge_seed(cfg, i_eps)
+    m = load_mcrit(dims, a.eps, gseed) + a.delta
+    u = synthetic.gauge_field(dims, a.eps, gseed)
+    ctx = wdmg.Context(dims, dev)
+    ctx.set_gauge(torch.from_numpy(u).to(dev), t_bc=-1)
+    ctx.set_mass(m)
+    v0 = torch.from_numpy(synthetic.gaussian_vectors((a.nv,) + ctx.fine_shape(), synthetic.null_seed(cfg))).to(dev)
+    bh = np.stack([synthetic.gaussian_spinor(dims, synthetic.rhs_seed(cfg, j)) for j in range(a.nrhs)])
+    b = torch.from_numpy(bh).to(dev)
+    levels = [{"block": (4, 4, 4, 4), "nv": a.nv, "setup_iters": a.setup_iters, "vectors": v0}]
+
+    def step():
+        t0 = time.perf_counter()
+        ctx.mg_setup(levels, coarse_tol=a.coarse_tol)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        x, st = ctx.solve(b, tol=1e-10, restart=50, maxit=2000, mg_prec=a.mg_prec)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        return x, st, t1 - t0, t2 - t1
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    t_start = time.perf_counter()
+    setups, solves, stats = [], [], []
+    for _ in range(a.steps):
+        x, st, ts, tv = step()
+        setups.append(ts)
+        solves.append(tv)
+        stats.append(st)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    last = stats[-1]
+    if not all(s["converged"] and s["true_res"] <= 1e-10 for st in stats for s in st):
+        raise SystemExit(f"solve did not reach 1e-10: {last}")
+    # independent check of the final residual with the library's FP64 D
+    r = b - ctx.apply_D(x)
+    true_res = float(torch.linalg.vector_norm(r) / torch.linalg.vector_norm(b))
+
+    ms_per_step = elapsed / a.steps * 1e3
+    value = elapsed / a.steps / a.nrhs
+
+    # dominant kernel of the step and its roofline
+    kinfo = {}
+    for name, (n, units, ms) in prof.items():
+        if n == 0:
+            continue
+        kinfo[name] = {"launches": n, "ms_total": ms, "us_per_launch": ms / n * 1e3, "units": units}
+    dom = max(kinfo, key=lambda k: kinfo[k]["ms_total"])
+    n, units, ms = prof[dom]
+    per_launch_s = ms / 1e3 / n
+    if dom.startswith("dslash"):
+        bpl = DSLASH_BYTES[dom[-3:]] * units / n
+    elif dom.startswith("dc_f"):
+        bpl = dc_bytes(dom[-3:], a.nv) * units / n
+    elif dom.startswith(("restrict", "prolong")):
+        bpl = transfer_bytes(dom[-3:], a.nv) * units / n
+    else:
+        bpl = None
+    roofline = None
+    if bpl is not None:
+        ach = bpl / per_launch_s / 1e9
+        roofline = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                    "bytes_per_launch": bpl, "us_per_launch": per_launch_s * 1e6}
+    ds = prof["dslash_f64"]
+    dslash_step = None
+    if ds[0]:
+        sec = ds[2] / 1e3 / ds[0]
+        dslash_step = {"lattice": f"{L}^4", "us_per_launch": sec * 1e6,
+                       "GB_s": DSLASH_BYTES["f64"] * ds[1] / ds[0] / sec / 1e9}
+
+    result = {
+        "metric": METRIC, "value": value, "unit": "s/RHS", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": ms_per_step, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if a.mg_prec == "f64" else "f64 outer / f32 V-cycle",
+        "data": "synthetic",
+        "config": {"workload": f"{L}^4 Wilson-Dirac, links exp(i {a.eps} H), m = m_crit + {a.delta}, "
+                               f"2-level MG 4^4 aggregates Nv={a.nv}, MR setup {a.setup_iters} iters, "
+                               f"FGCR(50) to 1e-10, {a.nrhs} Gaussian RHS",
+                   "lattice": list(dims), "eps": a.eps, "m": m, "m_crit": m - a.delta, "nv": a.nv,
+                   "nrhs": a.nrhs, "mg_prec": a.mg_prec, "coarse_tol": a.coarse_tol},
+        "setup_s": float(np.median(setups)), "solve_s_per_rhs": float(np.median(solves)) / a.nrhs,
+        "mg_iters": [s["iters"] for s in last], "mg_n_D": [s["n_D"] for s in last],
+        "mg_n_Dc": [s["n_Dc"][1] for s in last], "true_res": true_res,
+        "roofline": roofline, "kernels": kinfo, "dslash_in_step": dslash_step,
+    }
+    if not a.no_bicgstab:
+        t0 = time.perf_counter()
+        xb, sb = ctx.solve_bicgstab(b, tol=1e-10, maxit=100000)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        result["bicgstab"] = {"s_per_rhs": tb / a.nrhs, "iters": [s["iters"] for s in sb],
+                              "n_D": [s["n_D"] for s in sb], "converged": all(s["converged"] for s in sb)}
+    if a.big_L:
+        result["dslash_out_of_cache"] = dslash_bandwidth(wdmg, synthetic, torch, dev, a.big_L)
+    if not a.no_cpu_baseline:
+        n_d = int(np.sum([s["n_D"] for s in last])) + a.nv * (a.setup_iters + 1)
+        result["cpu_baseline"] = cpu_baseline(u, bh[0], m, n_d, a.nrhs, a.cpu_seconds)
+    ctx.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,198 @@
+/*
+ * wdmg.h -- C ABI of libwdmg, an adaptive-multigrid solver for the 4d SU(3)
+ * Wilson-Dirac system D x = b on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: M. A. Clark, J. Brannick, R. C. Brower, S. F. McCormick,
+ * T. A. Manteuffel, J. C. Osborn, C. Rebbi, "The removal of critical slowing
+ * down", Lattice 2008.  Section numbers below refer to that paper.
+ *
+ * General rules
+ *  - Every pointer argument named "device" is a device (HBM) pointer owned by
+ *    the caller; the library never frees it and never keeps it after the call
+ *    returns (inputs are copied into library-owned layouts).
+ *  - All work is enqueued on the HIP stream given to wdmg_create.  Calls that
+ *    return values to the host (setup, solve) synchronise that stream.
+ *  - Every call returns WDMG_OK (0) on success, a negative WDMG_ERR_* on
+ *    failure (nothing enqueued after the failing step; wdmg_last_error gives
+ *    a message), or WDMG_NOT_CONVERGED (> 0) when a solve stopped at its
+ *    iteration cap with its statistics filled.  No C++ exception crosses the
+ *    ABI.
+ *  - Canonical layouts (x fastest, complex interleaved re/im):
+ *      gauge field : [T][Z][Y][X][mu=4][3][3] complex128, U_mu(x)[a][b] takes
+ *                    colour b at x+mu to colour a at x; mu = 0..3 = x,y,z,t.
+ *      fine field  : [nrhs][T][Z][Y][X][spin=4][colour=3]
+ *      coarse field at level l >= 1 : [nrhs][T][Z][Y][X][chirality=2][Nv]
+ *    with the chiral gamma basis, gamma5 = diag(1,1,-1,-1): chirality + is
+ *    spins {0,1}.  Element type: complex128 for WDMG_F64, complex64 for the
+ *    other precisions (which run lower-precision kernels on FP32 I/O).
+ */
+#ifndef WDMG_H
+#define WDMG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  WDMG_OK = 0,
+  WDMG_NOT_CONVERGED = 1,
+  WDMG_ERR_ARG = -1,            /* null pointer, bad size, bad enum value   */
+  WDMG_ERR_DIMS = -2,           /* lattice or block extents not compatible  */
+  WDMG_ERR_OOM = -3,            /* device allocation failed                 */
+  WDMG_ERR_HIP = -4,            /* a HIP runtime call failed                */
+  WDMG_ERR_NOT_SETUP = -5,      /* gauge field or multigrid hierarchy missing */
+  WDMG_ERR_NAN = -6,            /* NaN/Inf met in a reduction or the input  */
+  WDMG_ERR_RANK_DEFICIENT = -7  /* candidate vectors dependent on an aggregate */
+};
+
+/* Arithmetic precision of a kernel path. */
+enum { WDMG_F64 = 0, WDMG_F32 = 1, WDMG_F16 = 2, WDMG_BF16 = 3 };
+
+#define WDMG_MAX_LEVELS 4
+
+typedef struct wdmg_ctx wdmg_ctx;
+
+/* Device-memory provider.  alloc(bytes, user) returns device memory or NULL;
+ * free(ptr, user) releases it.  Pass NULL to wdmg_create for hipMalloc/hipFree. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* user);
+  void (*free)(void* ptr, void* user);
+  void* user;
+} wdmg_alloc;
+
+/* Per coarsening l (level l -> l+1) of the hierarchy (Sec. 2 setup, Sec. 3
+ * blocking, Sec. 5 4d parameters). */
+typedef struct {
+  int block[4];          /* aggregate extents (bx,by,bz,bt); must divide the level's dims */
+  int nv;                /* near-null vectors Nv (coarse dof per site = 2 Nv), 1..32 */
+  int setup_iters;       /* MR relaxation steps on D v = 0 (0: take the vectors as given) */
+  const void* vectors;   /* device: nv starting vectors, canonical complex128 layout of
+                            level l ([nv][sites][dof]); required */
+} wdmg_level_params;
+
+typedef struct {
+  int n_levels;                  /* 2 or 3 (fine level included)                      */
+  wdmg_level_params level[WDMG_MAX_LEVELS - 1];
+  double omega;                  /* MR under-relaxation, paper value 0.8 (Sec. 3)     */
+  int nu_pre, nu_post;           /* V(nu_pre, nu_post), paper value 2, 2 (Sec. 5)      */
+  int coarse_cycles;             /* next-level cycles between the fine restriction and
+                                    prolongation of a 3-level hierarchy; paper 4 (Sec. 5) */
+  double coarse_tol;             /* relative tolerance of the coarsest GCR solve       */
+  int coarse_maxit;              /* iteration cap of the coarsest solve                 */
+  int coarse_restart;            /* restart length of the coarsest GCR                  */
+  int use_alpha;                 /* 1: minimal-residual step after prolongation (Sec. 3) */
+} wdmg_mg_params;
+
+typedef struct {
+  double tol;            /* stop when the true ||b - D x|| / ||b|| <= tol (FP64)   */
+  int restart;           /* FGCR restart length k (paper GCR(50), Sec. 5)          */
+  int maxit;             /* cap on outer iterations                                */
+  int precond;           /* 0: plain GCR, 1: multigrid V-cycle                      */
+  int mg_prec;           /* precision of the V-cycle: WDMG_F64 or WDMG_F32          */
+} wdmg_solve_params;
+
+typedef struct {
+  int iters;             /* outer iterations (BiCGStab: iterations, two D each)    */
+  int restarts;
+  int converged;
+  double true_res;       /* ||b - D x|| / ||b|| recomputed in FP64 at exit          */
+  long long n_D;         /* applications of the fine operator, all precisions      */
+  long long n_Dc[WDMG_MAX_LEVELS]; /* applications of the coarse operator per level */
+  double seconds;        /* wall time of the solve of this right-hand side         */
+} wdmg_solve_stats;
+
+/* Defaults equal to the paper's constants: omega 0.8, V(2,2), 4 coarse cycles,
+ * GCR(50), tol 1e-10. */
+void wdmg_default_mg_params(wdmg_mg_params* p);
+void wdmg_default_solve_params(wdmg_solve_params* p);
+
+/* Creates a context for a (Lx,Ly,Lz,Lt) lattice.  Extents >= 2.  hip_stream is
+ * a hipStream_t (NULL: the null stream).  alloc may be NULL.  On failure *out
+ * is NULL. */
+int wdmg_create(wdmg_ctx** out, const int dims[4], const wdmg_alloc* alloc, void* hip_stream);
+
+/* Frees every library-owned buffer; synchronises the stream first. */
+void wdmg_destroy(wdmg_ctx* ctx);
+
+/* Message of the last failure on ctx ("" if none).  Valid until the next call. */
+const char* wdmg_last_error(const wdmg_ctx* ctx);
+
+/* Sec. 1 / Sec. 3: the SU(3) links.  U: device, canonical complex128 gauge
+ * layout.  t_bc = -1 (antiperiodic time) or +1 (periodic).  Copied into the
+ * internal FP64 and FP32 layouts with the boundary sign folded in; the
+ * caller may free U afterwards.  Invalidates a multigrid hierarchy. */
+int wdmg_set_gauge(wdmg_ctx* ctx, const void* U, int t_bc);
+
+/* Sec. 1: the mass m in D = Dslash + m.  After a multigrid setup the coarse
+ * operators are shifted by (m_new - m_old) I, exact because P^dagger P = I. */
+int wdmg_set_mass(wdmg_ctx* ctx, double m);
+
+/* Sec. 1: out = D in for nrhs fine fields.  in, out: device, canonical fine
+ * layout, out != in.  prec WDMG_F64 (complex128 I/O) or WDMG_F32 (complex64). */
+int wdmg_apply_D(wdmg_ctx* ctx, void* out, const void* in, int nrhs, int prec);
+
+/* Sec. 2 (adaptive setup, block QR with P V_c = V and P^dagger P = I),
+ * Sec. 3 (geometric aggregates, chirality kept in the blocks, R = P^dagger),
+ * Sec. 2 (Galerkin D_c = P^dagger D P).  For each coarsening the starting
+ * vectors are relaxed with setup_iters MR steps on D v = 0 (each vector its
+ * own step size), normalised, block-orthonormalised in FP64 per (aggregate,
+ * chirality) and the coarse stencil is built.  Synchronises. */
+int wdmg_mg_setup(wdmg_ctx* ctx, const wdmg_mg_params* params);
+
+/* The orthonormalised columns of P from level l to l+1: device output,
+ * canonical complex128 layout of level l, [nv][sites][dof]. */
+int wdmg_get_prolongator(wdmg_ctx* ctx, int level, void* V_out);
+
+/* Sec. 2: out = D_c in on coarse level l >= 1 (nrhs fields).  Canonical
+ * coarse layout; prec WDMG_F64 (complex128) or WDMG_F32 (complex64). */
+int wdmg_apply_Dc(wdmg_ctx* ctx, int level, void* out, const void* in, int nrhs, int prec);
+
+/* Sec. 2 / Sec. 3: c_out = P^dagger f_in (restriction from level l to l+1)
+ * and f_out = P c_in (prolongation from level l+1 to l).  Canonical layouts
+ * of the two levels; precision as for wdmg_apply_D. */
+int wdmg_restrict(wdmg_ctx* ctx, int level, void* c_out, const void* f_in, int nrhs, int prec);
+int wdmg_prolong(wdmg_ctx* ctx, int level, void* f_out, const void* c_in, int nrhs, int prec);
+
+/* Sec. 3: iters under-relaxed MR steps (omega of the setup params, 0.8 if no
+ * setup) on A x = b at level l, starting from the given x (updated in place).
+ * Canonical layout of level l. */
+int wdmg_smooth(wdmg_ctx* ctx, int level, void* x, const void* b, int nrhs, int iters, int prec);
+
+/* Sec. 5: solve D x = b for nrhs right-hand sides with flexible GCR(k),
+ * preconditioned by the multigrid V-cycle (params->precond = 1) or not.
+ * x (device, canonical complex128) holds the initial guess and receives the
+ * solution; b is not modified.  stats: host array of nrhs entries or NULL.
+ * Synchronises. */
+int wdmg_solve(wdmg_ctx* ctx, void* x, const void* b, int nrhs,
+               const wdmg_solve_params* params, wdmg_solve_stats* stats);
+
+/* Sec. 5 comparator: unpreconditioned BiCGStab in FP64 from x = 0 to the same
+ * true-residual criterion.  Same layouts as wdmg_solve. */
+int wdmg_solve_bicgstab(wdmg_ctx* ctx, void* x, const void* b, int nrhs, double tol,
+                        int maxit, wdmg_solve_stats* stats);
+
+/* ---- instrumentation (not part of the method) ----------------------------
+ * Kernel timing with HIP events recorded on the context's stream around each
+ * launch of the kernels below.  `units` counts the work items the kernel
+ * processed: fine sites x rhs (D, P, P^dagger), coarse sites x rhs (D_c
+ * apply), coarse sites (D_c build) or (aggregate, chirality) blocks (QR). */
+enum {
+  WDMG_K_DSLASH_F64 = 0, WDMG_K_DSLASH_F32, WDMG_K_DC_F64, WDMG_K_DC_F32,
+  WDMG_K_RESTRICT_F64, WDMG_K_RESTRICT_F32, WDMG_K_PROLONG_F64, WDMG_K_PROLONG_F32,
+  WDMG_K_DC_BUILD, WDMG_K_BLOCK_QR, WDMG_K_COUNT
+};
+
+/* enable = 1 starts recording (and clears earlier records), 0 stops. */
+int wdmg_profile(wdmg_ctx* ctx, int enable);
+
+/* Totals since the last wdmg_profile(ctx, 1) for one kernel id: launches,
+ * work units and summed event time in milliseconds.  Synchronises. */
+int wdmg_profile_read(wdmg_ctx* ctx, int kernel, long long* launches, long long* units, double* ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WDMG_H */

@@ -1,0 +1,483 @@
+// extern "C" entry points of libwdmg (declared in include/wdmg.h).  Each call
+// validates its arguments on the host, runs the drivers, and turns any
+// wdmg::Error into a return code; no exception crosses the ABI.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+#include "solver.h"
+
+using namespace wdmg;
+
+struct wdmg_ctx : Ctx {};
+
+namespace {
+
+template <class F>
+int guarded(wdmg_ctx* c, F&& f) {
+  if (!c) return WDMG_ERR_ARG;
+  c->err.clear();
+  try {
+    return f();
+  } catch (const Error& e) {
+    c->err = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    c->err = "host allocation failed";
+    return WDMG_ERR_OOM;
+  } catch (const std::exception& e) {
+    c->err = e.what();
+    return WDMG_ERR_HIP;
+  }
+}
+
+void need_gauge(Ctx& c) {
+  if (!c.have_gauge) throw Error(WDMG_ERR_NOT_SETUP, "no gauge field set");
+}
+void need_mg(Ctx& c, int level, bool coarse) {
+  if (!c.have_mg) throw Error(WDMG_ERR_NOT_SETUP, "no multigrid hierarchy set up");
+  const int hi = coarse ? c.nlevels - 1 : c.nlevels - 2;
+  const int lo = coarse ? 1 : 0;
+  if (level < lo || level > hi) throw Error(WDMG_ERR_ARG, "level out of range");
+}
+void need_prec(int prec) {
+  if (prec == WDMG_F16 || prec == WDMG_BF16)
+    throw Error(WDMG_ERR_ARG, "16-bit storage is not available through this entry point");
+  if (prec != WDMG_F64 && prec != WDMG_F32) throw Error(WDMG_ERR_ARG, "unknown precision");
+}
+void need_ptr(const void* p, const char* what) {
+  if (!p) throw Error(WDMG_ERR_ARG, std::string("null pointer: ") + what);
+}
+void need_nrhs(int nrhs) {
+  if (nrhs < 1 || nrhs > 65535) throw Error(WDMG_ERR_ARG, "nrhs must be in 1..65535");
+}
+
+// canonical fine layout <-> level-0 internal layout, in precision R
+template <typename R>
+void fine_in(Ctx& c, const void* canon, cx<R>* dst, int nrhs) {
+  fine_to_internal<R, R>(c, c.g0, static_cast<const cx<R>*>(canon), dst, nrhs);
+}
+template <typename R>
+void fine_out(Ctx& c, const cx<R>* src, void* canon, int nrhs) {
+  fine_to_canonical<R, R>(c, c.g0, src, static_cast<cx<R>*>(canon), nrhs);
+}
+
+template <typename R>
+void apply_D_impl(Ctx& c, void* out, const void* in, int nrhs) {
+  const size_t n = (size_t)c.g0.vol * 12;
+  ensure_io(c, n * nrhs * sizeof(cx<R>));
+  cx<R>* a = static_cast<cx<R>*>(c.io_a);
+  cx<R>* b = static_cast<cx<R>*>(c.io_b);
+  fine_in<R>(c, in, a, nrhs);
+  dslash<R>(c, b, a, nrhs);
+  fine_out<R>(c, b, out, nrhs);
+}
+
+template <typename R>
+const cx<R>* dc_of(const Level& L) {
+  if constexpr (sizeof(R) == 8)
+    return L.Dc64;
+  else
+    return L.Dc32;
+}
+
+template <typename R>
+void restrict_impl(Ctx& c, int level, void* cout, const void* fin, int nrhs) {
+  cx<R>* co = static_cast<cx<R>*>(cout);
+  if (level == 0) {
+    const size_t n = c.lev[0].n;
+    ensure_io(c, n * nrhs * sizeof(cx<R>));
+    cx<R>* a = static_cast<cx<R>*>(c.io_a);
+    fine_in<R>(c, fin, a, nrhs);
+    restrict_to<R>(c, 0, a, co, nrhs);
+  } else {
+    restrict_to<R>(c, level, static_cast<const cx<R>*>(fin), co, nrhs);
+  }
+}
+
+template <typename R>
+void prolong_impl(Ctx& c, int level, void* fout, const void* cin, int nrhs) {
+  const cx<R>* ci = static_cast<const cx<R>*>(cin);
+  if (level == 0) {
+    const size_t n = c.lev[0].n;
+    ensure_io(c, n * nrhs * sizeof(cx<R>));
+    cx<R>* a = static_cast<cx<R>*>(c.io_a);
+    prolong_from<R>(c, 0, ci, a, nrhs);
+    fine_out<R>(c, a, fout, nrhs);
+  } else {
+    prolong_from<R>(c, level, ci, static_cast<cx<R>*>(fout), nrhs);
+  }
+}
+
+template <typename R>
+void smooth_impl(Ctx& c, int level, void* x, const void* b, int nrhs, int iters) {
+  Level& L = c.lev[level];
+  const size_t n = L.n;
+  ensure_io(c, 2 * n * sizeof(cx<R>));
+  cx<R>* xi = static_cast<cx<R>*>(c.io_a);
+  cx<R>* ri = xi + n;
+  cx<R>* p = static_cast<cx<R>*>(c.io_b);
+  cx<R>* bi = p + n;
+  const double omega = c.have_mg ? c.mg.omega : 0.8;
+  for (int k = 0; k < nrhs; ++k) {
+    if (level == 0) {
+      fine_in<R>(c, static_cast<const cx<R>*>(x) + (size_t)k * n, xi, 1);
+      fine_in<R>(c, static_cast<const cx<R>*>(b) + (size_t)k * n, bi, 1);
+    } else {
+      copy<R>(c, xi, static_cast<const cx<R>*>(x) + (size_t)k * n, n);
+      copy<R>(c, bi, static_cast<const cx<R>*>(b) + (size_t)k * n, n);
+    }
+    apply_op<R>(c, level, ri, xi, 1);
+    xmy<R>(c, bi, ri, n);
+    mr<R>(c, level, xi, ri, p, iters, omega);
+    if (level == 0)
+      fine_out<R>(c, xi, static_cast<cx<R>*>(x) + (size_t)k * n, 1);
+    else
+      copy<R>(c, static_cast<cx<R>*>(x) + (size_t)k * n, xi, n);
+  }
+}
+
+void ensure_solve_io(Ctx& c) {
+  const size_t n = (size_t)c.g0.vol * 12;
+  if (!c.sol_x) {
+    c.sol_x = static_cast<cx<double>*>(dev_alloc(c, n * sizeof(cx<double>)));
+    c.sol_b = static_cast<cx<double>*>(dev_alloc(c, n * sizeof(cx<double>)));
+  }
+}
+
+double now() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+extern "C" {
+
+void wdmg_default_mg_params(wdmg_mg_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->n_levels = 2;
+  for (int l = 0; l < WDMG_MAX_LEVELS - 1; ++l) {
+    for (int mu = 0; mu < 4; ++mu) p->level[l].block[mu] = 4;
+    p->level[l].nv = 20;
+    p->level[l].setup_iters = 100;
+    p->level[l].vectors = nullptr;
+  }
+  p->omega = 0.8;
+  p->nu_pre = 2;
+  p->nu_post = 2;
+  p->coarse_cycles = 4;
+  p->coarse_tol = 1e-2;
+  p->coarse_maxit = 200;
+  p->coarse_restart = 32;
+  p->use_alpha = 1;
+}
+
+void wdmg_default_solve_params(wdmg_solve_params* p) {
+  if (!p) return;
+  p->tol = 1e-10;
+  p->restart = 50;
+  p->maxit = 1000;
+  p->precond = 1;
+  p->mg_prec = WDMG_F64;
+}
+
+int wdmg_create(wdmg_ctx** out, const int dims[4], const wdmg_alloc* alloc, void* hip_stream) {
+  if (!out || !dims) return WDMG_ERR_ARG;
+  *out = nullptr;
+  long long vol = 1;
+  for (int mu = 0; mu < 4; ++mu) {
+    if (dims[mu] < 2) return WDMG_ERR_DIMS;
+    vol *= dims[mu];
+  }
+  if (vol * 12 > (1LL << 31)) return WDMG_ERR_DIMS;
+  wdmg_ctx* c = new (std::nothrow) wdmg_ctx();
+  if (!c) return WDMG_ERR_OOM;
+  std::memcpy(c->dims, dims, sizeof(c->dims));
+  int B[4];
+  for (int mu = 0; mu < 4; ++mu) B[mu] = dims[mu] % 4 == 0 ? 4 : (dims[mu] % 2 == 0 ? 2 : 1);
+  c->g0 = make_geom(dims, B);
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  if (alloc) {
+    c->alloc = *alloc;
+    if (!alloc->alloc || !alloc->free) {
+      delete c;
+      return WDMG_ERR_ARG;
+    }
+  }
+  int rc = guarded(c, [&]() {
+    c->dsc = static_cast<double*>(dev_alloc(*c, S_TOTAL * sizeof(double)));
+    c->partials = static_cast<double*>(dev_alloc(*c, 65536 * sizeof(double)));
+    c->counter = static_cast<unsigned*>(dev_alloc(*c, 256 * sizeof(unsigned)));
+    WDMG_HIP(hipMemsetAsync(c->dsc, 0, S_TOTAL * sizeof(double), c->stream));
+    WDMG_HIP(hipMemsetAsync(c->counter, 0, 256 * sizeof(unsigned), c->stream));
+    WDMG_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->hsc), 64 * sizeof(double), hipHostMallocDefault));
+    c->lev[0].l = 0;
+    std::memcpy(c->lev[0].dims, dims, sizeof(c->lev[0].dims));
+    c->lev[0].g = c->g0;
+    c->lev[0].nsite = c->g0.vol;
+    c->lev[0].dof = 12;
+    c->lev[0].n = (size_t)c->g0.vol * 12;
+    WDMG_HIP(hipStreamSynchronize(c->stream));
+    return WDMG_OK;
+  });
+  if (rc != WDMG_OK) {
+    wdmg_destroy(c);
+    return rc;
+  }
+  *out = c;
+  return WDMG_OK;
+}
+
+void wdmg_destroy(wdmg_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  while (!c->bufs.empty()) {
+    void* p = c->bufs.back().p;
+    c->bufs.pop_back();
+    if (c->alloc.free)
+      c->alloc.free(p, c->alloc.user);
+    else
+      (void)hipFree(p);
+  }
+  if (c->hsc) (void)hipHostFree(c->hsc);
+  for (auto& r : c->prof_recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (hipEvent_t e : c->prof_pool) (void)hipEventDestroy(e);
+  delete c;
+}
+
+const char* wdmg_last_error(const wdmg_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int wdmg_set_gauge(wdmg_ctx* c, const void* U, int t_bc) {
+  return guarded(c, [&]() {
+    need_ptr(U, "U");
+    if (t_bc != 1 && t_bc != -1) throw Error(WDMG_ERR_ARG, "t_bc must be +1 or -1");
+    if (c->have_mg) free_hierarchy(*c);
+    const size_t n = (size_t)c->g0.vol * 36;
+    if (!c->U64) {
+      c->U64 = static_cast<cx<double>*>(dev_alloc(*c, n * sizeof(cx<double>)));
+      c->U32 = static_cast<cx<float>*>(dev_alloc(*c, n * sizeof(cx<float>)));
+    }
+    gauge_import(*c, static_cast<const cx<double>*>(U), t_bc);
+    c->t_bc = t_bc;
+    c->have_gauge = true;
+    return WDMG_OK;
+  });
+}
+
+int wdmg_set_mass(wdmg_ctx* c, double m) {
+  return guarded(c, [&]() {
+    if (!std::isfinite(m)) throw Error(WDMG_ERR_ARG, "mass must be finite");
+    c->mass = m;
+    if (c->have_mg) {
+      const double dm = m - c->setup_mass;
+      for (int l = 1; l < c->nlevels; ++l) coarse_shift(*c, c->lev[l], dm);
+      c->setup_mass = m;
+    }
+    return WDMG_OK;
+  });
+}
+
+int wdmg_apply_D(wdmg_ctx* c, void* out, const void* in, int nrhs, int prec) {
+  return guarded(c, [&]() {
+    need_ptr(out, "out");
+    need_ptr(in, "in");
+    need_nrhs(nrhs);
+    need_prec(prec);
+    need_gauge(*c);
+    if (out == in) throw Error(WDMG_ERR_ARG, "out must differ from in");
+    if (prec == WDMG_F64)
+      apply_D_impl<double>(*c, out, in, nrhs);
+    else
+      apply_D_impl<float>(*c, out, in, nrhs);
+    return WDMG_OK;
+  });
+}
+
+int wdmg_mg_setup(wdmg_ctx* c, const wdmg_mg_params* p) {
+  return guarded(c, [&]() {
+    need_ptr(p, "params");
+    mg_setup(*c, *p);
+    return WDMG_OK;
+  });
+}
+
+int wdmg_get_prolongator(wdmg_ctx* c, int level, void* V_out) {
+  return guarded(c, [&]() {
+    need_ptr(V_out, "V_out");
+    need_mg(*c, level, false);
+    Level& L = c->lev[level];
+    if (level == 0)
+      fine_to_canonical<double, double>(*c, c->g0, L.V64, static_cast<cx<double>*>(V_out), L.nv);
+    else
+      copy<double>(*c, static_cast<cx<double>*>(V_out), L.V64, (size_t)L.nv * L.n);
+    return WDMG_OK;
+  });
+}
+
+int wdmg_apply_Dc(wdmg_ctx* c, int level, void* out, const void* in, int nrhs, int prec) {
+  return guarded(c, [&]() {
+    need_ptr(out, "out");
+    need_ptr(in, "in");
+    need_nrhs(nrhs);
+    need_prec(prec);
+    need_mg(*c, level, true);
+    if (out == in) throw Error(WDMG_ERR_ARG, "out must differ from in");
+    const Level& L = c->lev[level];
+    if (prec == WDMG_F64)
+      coarse_apply<double>(*c, L, dc_of<double>(L), static_cast<cx<double>*>(out),
+                           static_cast<const cx<double>*>(in), nrhs);
+    else
+      coarse_apply<float>(*c, L, dc_of<float>(L), static_cast<cx<float>*>(out), static_cast<const cx<float>*>(in),
+                          nrhs);
+    return WDMG_OK;
+  });
+}
+
+int wdmg_restrict(wdmg_ctx* c, int level, void* c_out, const void* f_in, int nrhs, int prec) {
+  return guarded(c, [&]() {
+    need_ptr(c_out, "c_out");
+    need_ptr(f_in, "f_in");
+    need_nrhs(nrhs);
+    need_prec(prec);
+    need_mg(*c, level, false);
+    if (prec == WDMG_F64)
+      restrict_impl<double>(*c, level, c_out, f_in, nrhs);
+    else
+      restrict_impl<float>(*c, level, c_out, f_in, nrhs);
+    return WDMG_OK;
+  });
+}
+
+int wdmg_prolong(wdmg_ctx* c, int level, void* f_out, const void* c_in, int nrhs, int prec) {
+  return guarded(c, [&]() {
+    need_ptr(f_out, "f_out");
+    need_ptr(c_in, "c_in");
+    need_nrhs(nrhs);
+    need_prec(prec);
+    need_mg(*c, level, false);
+    if (prec == WDMG_F64)
+      prolong_impl<double>(*c, level, f_out, c_in, nrhs);
+    else
+      prolong_impl<float>(*c, level, f_out, c_in, nrhs);
+    return WDMG_OK;
+  });
+}
+
+int wdmg_smooth(wdmg_ctx* c, int level, void* x, const void* b, int nrhs, int iters, int prec) {
+  return guarded(c, [&]() {
+    need_ptr(x, "x");
+    need_ptr(b, "b");
+    need_nrhs(nrhs);
+    need_prec(prec);
+    need_gauge(*c);
+    if (iters < 0) throw Error(WDMG_ERR_ARG, "iters must be >= 0");
+    if (level != 0) need_mg(*c, level, true);
+    if (prec == WDMG_F64)
+      smooth_impl<double>(*c, level, x, b, nrhs, iters);
+    else
+      smooth_impl<float>(*c, level, x, b, nrhs, iters);
+    return WDMG_OK;
+  });
+}
+
+int wdmg_solve(wdmg_ctx* c, void* x, const void* b, int nrhs, const wdmg_solve_params* p, wdmg_solve_stats* stats) {
+  return guarded(c, [&]() {
+    need_ptr(x, "x");
+    need_ptr(b, "b");
+    need_ptr(p, "params");
+    need_nrhs(nrhs);
+    need_gauge(*c);
+    if (!(p->tol > 0.0) || p->restart < 1 || p->restart > 128 || p->maxit < 1)
+      throw Error(WDMG_ERR_ARG, "bad solve parameters");
+    if (p->precond) {
+      if (!c->have_mg) throw Error(WDMG_ERR_NOT_SETUP, "no multigrid hierarchy set up");
+      if (p->mg_prec != WDMG_F64 && p->mg_prec != WDMG_F32)
+        throw Error(WDMG_ERR_ARG, "the V-cycle runs in WDMG_F64 or WDMG_F32");
+    }
+    ensure_solve_io(*c);
+    ensure_fine_work(*c);
+    const size_t n = (size_t)c->g0.vol * 12;
+    int worst = WDMG_OK;
+    for (int k = 0; k < nrhs; ++k) {
+      wdmg_solve_stats st{};
+      c->n_D = 0;
+      for (int l = 0; l < WDMG_MAX_LEVELS; ++l) c->n_Dc[l] = 0;
+      const double t0 = now();
+      fine_in<double>(*c, static_cast<const cx<double>*>(b) + k * n, c->sol_b, 1);
+      fine_in<double>(*c, static_cast<const cx<double>*>(x) + k * n, c->sol_x, 1);
+      const int rc = fgcr(*c, c->sol_x, c->sol_b, *p, st);
+      fine_out<double>(*c, c->sol_x, static_cast<cx<double>*>(x) + k * n, 1);
+      WDMG_HIP(hipStreamSynchronize(c->stream));
+      st.seconds = now() - t0;
+      st.n_D = c->n_D;
+      for (int l = 0; l < WDMG_MAX_LEVELS; ++l) st.n_Dc[l] = c->n_Dc[l];
+      if (stats) stats[k] = st;
+      if (rc != WDMG_OK) worst = rc;
+    }
+    return worst;
+  });
+}
+
+int wdmg_solve_bicgstab(wdmg_ctx* c, void* x, const void* b, int nrhs, double tol, int maxit,
+                        wdmg_solve_stats* stats) {
+  return guarded(c, [&]() {
+    need_ptr(x, "x");
+    need_ptr(b, "b");
+    need_nrhs(nrhs);
+    need_gauge(*c);
+    if (!(tol > 0.0) || maxit < 1) throw Error(WDMG_ERR_ARG, "bad solve parameters");
+    ensure_solve_io(*c);
+    const size_t n = (size_t)c->g0.vol * 12;
+    int worst = WDMG_OK;
+    for (int k = 0; k < nrhs; ++k) {
+      wdmg_solve_stats st{};
+      c->n_D = 0;
+      const double t0 = now();
+      fine_in<double>(*c, static_cast<const cx<double>*>(b) + k * n, c->sol_b, 1);
+      const int rc = bicgstab(*c, c->sol_x, c->sol_b, tol, maxit, st);
+      fine_out<double>(*c, c->sol_x, static_cast<cx<double>*>(x) + k * n, 1);
+      WDMG_HIP(hipStreamSynchronize(c->stream));
+      st.seconds = now() - t0;
+      st.n_D = c->n_D;
+      if (stats) stats[k] = st;
+      if (rc != WDMG_OK) worst = rc;
+    }
+    return worst;
+  });
+}
+
+int wdmg_profile(wdmg_ctx* c, int enable) {
+  return guarded(c, [&]() {
+    prof_collect(*c);
+    if (enable) {
+      for (int k = 0; k < WDMG_K_COUNT; ++k) {
+        c->prof_launch[k] = 0;
+        c->prof_units[k] = 0;
+        c->prof_ms[k] = 0.0;
+      }
+    }
+    c->prof_on = enable != 0;
+    return WDMG_OK;
+  });
+}
+
+int wdmg_profile_read(wdmg_ctx* c, int kernel, long long* launches, long long* units, double* ms) {
+  return guarded(c, [&]() {
+    if (kernel < 0 || kernel >= WDMG_K_COUNT) throw Error(WDMG_ERR_ARG, "unknown kernel id");
+    prof_collect(*c);
+    if (launches) *launches = c->prof_launch[kernel];
+    if (units) *units = c->prof_units[kernel];
+    if (ms) *ms = c->prof_ms[kernel];
+    return WDMG_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,515 @@
+// Vector kernels of the smoother and Krylov solvers: fused updates and
+// reductions whose results stay in device memory.
+//
+// Reductions are single launches: each workgroup writes its partial sums,
+// the last workgroup to finish (atomic ticket) adds the partials in a fixed
+// order and applies a finalising formula (an MR step size, a GCR
+// coefficient, ...) straight into the device scalar area.  The summation
+// order depends only on the vector length, so results are bitwise
+// reproducible run to run.
+#include "internal.h"
+
+namespace wdmg {
+namespace {
+
+constexpr int TPB = kReduceThreads;
+
+inline unsigned reduce_blocks(size_t n) {
+  size_t b = (n + (size_t)TPB * 4 - 1) / ((size_t)TPB * 4);
+  if (b < 1) b = 1;
+  if (b > (size_t)kMaxReduceBlocks) b = kMaxReduceBlocks;
+  return (unsigned)b;
+}
+
+__device__ __forceinline__ bool bad(double x) { return !isfinite(x); }
+
+template <class Op>
+__global__ __launch_bounds__(TPB) void k_reduce(Op op, size_t n, double* partials, unsigned* counter) {
+  constexpr int K = Op::K;
+  __shared__ double lds[K * (TPB / 64)];
+  __shared__ bool last;
+  double v[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = 0.0;
+  for (size_t i = blockIdx.x * (size_t)TPB + threadIdx.x; i < n; i += (size_t)gridDim.x * TPB) op.acc(i, v);
+  block_sum<K>(v, lds);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) partials[blockIdx.x * K + k] = v[k];
+    __threadfence();
+    last = atomicAdd(counter, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = 0.0;
+  for (unsigned b = threadIdx.x; b < gridDim.x; b += TPB) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] += load_coherent(&partials[b * K + k]);
+  }
+  block_sum<K>(v, lds);
+  if (threadIdx.x == 0) {
+    op.fin(v);
+    *counter = 0u;
+  }
+}
+
+template <class Op>
+void run_reduce(Ctx& c, const Op& op, size_t n) {
+  const unsigned nb = reduce_blocks(n);
+  hipLaunchKernelGGL((k_reduce<Op>), dim3(nb), dim3(TPB), 0, c.stream, op, n, c.partials, c.counter);
+  WDMG_HIP(hipGetLastError());
+}
+
+// ---- ops ------------------------------------------------------------------
+template <typename R>
+struct StepAlphaOp {
+  static constexpr int K = 3;
+  const cx<R>* a;
+  const cx<R>* b;
+  double scale;
+  double* dsc;
+  int slot;
+  __device__ void acc(size_t i, double* v) const {
+    const cx<R> x = a[i], y = b[i];
+    v[0] += (double)x.re * y.re + (double)x.im * y.im;
+    v[1] += (double)x.re * y.im - (double)x.im * y.re;
+    v[2] += (double)x.re * x.re + (double)x.im * x.im;
+  }
+  __device__ void fin(const double* v) const {
+    double re = 0.0, im = 0.0;
+    if (v[2] > 0.0) {
+      re = scale * v[0] / v[2];
+      im = scale * v[1] / v[2];
+    }
+    if (bad(v[0]) || bad(v[1]) || bad(v[2])) dsc[S_ERR] = 1.0;
+    dsc[slot] = re;
+    dsc[slot + 1] = im;
+  }
+};
+
+template <typename R>
+struct Norm2Op {
+  static constexpr int K = 1;
+  const cx<R>* a;
+  double* dsc;
+  int slot;
+  __device__ void acc(size_t i, double* v) const {
+    const cx<R> x = a[i];
+    v[0] += (double)x.re * x.re + (double)x.im * x.im;
+  }
+  __device__ void fin(const double* v) const {
+    if (bad(v[0])) dsc[S_ERR] = 1.0;
+    dsc[slot] = v[0];
+  }
+};
+
+template <typename R>
+struct DotOp {
+  static constexpr int K = 2;
+  const cx<R>* a;
+  const cx<R>* b;
+  double* dsc;
+  int slot;
+  __device__ void acc(size_t i, double* v) const {
+    const cx<R> x = a[i], y = b[i];
+    v[0] += (double)x.re * y.re + (double)x.im * y.im;
+    v[1] += (double)x.re * y.im - (double)x.im * y.re;
+  }
+  __device__ void fin(const double* v) const {
+    dsc[slot] = v[0];
+    dsc[slot + 1] = v[1];
+  }
+};
+
+// GCR: nrm_j = <w,w>, a = <w,r>/nrm_j.
+struct GcrCoefOp {
+  static constexpr int K = 3;
+  const cx<double>* w;
+  const cx<double>* r;
+  double* dsc;
+  int nrmslot, aslot;
+  __device__ void acc(size_t i, double* v) const {
+    const cx<double> x = w[i], y = r[i];
+    v[0] += x.re * x.re + x.im * x.im;
+    v[1] += x.re * y.re + x.im * y.im;
+    v[2] += x.re * y.im - x.im * y.re;
+  }
+  __device__ void fin(const double* v) const {
+    if (bad(v[0]) || bad(v[1]) || bad(v[2])) dsc[S_ERR] = 1.0;
+    dsc[nrmslot] = v[0];
+    dsc[aslot] = v[0] > 0.0 ? v[1] / v[0] : 0.0;
+    dsc[aslot + 1] = v[0] > 0.0 ? v[2] / v[0] : 0.0;
+  }
+};
+
+// x += a z; r -= a w; ||r||^2.
+struct GcrUpdateOp {
+  static constexpr int K = 1;
+  const cx<double>* w;
+  const cx<double>* z;
+  cx<double>* x;
+  cx<double>* r;
+  const double* a;
+  double* dsc;
+  int rslot;
+  __device__ void acc(size_t i, double* v) const {
+    const cx<double> s = mk(a[0], a[1]);
+    x[i] = x[i] + s * z[i];
+    const cx<double> ri = r[i] - s * w[i];
+    r[i] = ri;
+    v[0] += ri.re * ri.re + ri.im * ri.im;
+  }
+  __device__ void fin(const double* v) const {
+    if (bad(v[0])) dsc[S_ERR] = 1.0;
+    dsc[rslot] = v[0];
+  }
+};
+
+struct XmyNormOp {
+  static constexpr int K = 1;
+  const cx<double>* b;
+  cx<double>* y;
+  double* dsc;
+  int slot;
+  __device__ void acc(size_t i, double* v) const {
+    const cx<double> d = b[i] - y[i];
+    y[i] = d;
+    v[0] += d.re * d.re + d.im * d.im;
+  }
+  __device__ void fin(const double* v) const {
+    if (bad(v[0])) dsc[S_ERR] = 1.0;
+    dsc[slot] = v[0];
+  }
+};
+
+// ---- BiCGStab (slots relative to S_BICG) ----------------------------------
+enum { B_RHO_NEW = 0, B_RHO_OLD = 2, B_ALPHA = 4, B_OMEGA = 6, B_RNORM = 8 };
+
+__device__ __forceinline__ cx<double> cdiv(cx<double> a, cx<double> b) {
+  const double d = b.re * b.re + b.im * b.im;
+  return mk((a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d);
+}
+
+struct BicgAlphaOp {  // alpha = rho_new / <rhat, v>
+  static constexpr int K = 2;
+  const cx<double>* rhat;
+  const cx<double>* v_;
+  double* dsc;
+  __device__ void acc(size_t i, double* v) const {
+    const cx<double> x = rhat[i], y = v_[i];
+    v[0] += x.re * y.re + x.im * y.im;
+    v[1] += x.re * y.im - x.im * y.re;
+  }
+  __device__ void fin(const double* v) const {
+    double* b = dsc + S_BICG;
+    const cx<double> rn = mk(b[B_RHO_NEW], b[B_RHO_NEW + 1]);
+    cx<double> a = mk(0.0, 0.0);
+    if (v[0] != 0.0 || v[1] != 0.0) a = cdiv(rn, mk(v[0], v[1]));
+    if (bad(a.re) || bad(a.im)) dsc[S_ERR] = 1.0;
+    b[B_ALPHA] = a.re;
+    b[B_ALPHA + 1] = a.im;
+    b[B_RHO_OLD] = rn.re;
+    b[B_RHO_OLD + 1] = rn.im;
+  }
+};
+
+struct BicgOmegaOp {  // omega = <t, s> / <t, t>
+  static constexpr int K = 3;
+  const cx<double>* t;
+  const cx<double>* s;
+  double* dsc;
+  __device__ void acc(size_t i, double* v) const {
+    const cx<double> x = t[i], y = s[i];
+    v[0] += x.re * y.re + x.im * y.im;
+    v[1] += x.re * y.im - x.im * y.re;
+    v[2] += x.re * x.re + x.im * x.im;
+  }
+  __device__ void fin(const double* v) const {
+    double* b = dsc + S_BICG;
+    b[B_OMEGA] = v[2] > 0.0 ? v[0] / v[2] : 0.0;
+    b[B_OMEGA + 1] = v[2] > 0.0 ? v[1] / v[2] : 0.0;
+    if (bad(v[0]) || bad(v[2])) dsc[S_ERR] = 1.0;
+  }
+};
+
+struct BicgXrOp {  // x += alpha p + omega s ; r = s - omega t ; rho_new = <rhat, r>, ||r||^2
+  static constexpr int K = 3;
+  cx<double>* x;
+  cx<double>* r;
+  const cx<double>* p;
+  const cx<double>* s;
+  const cx<double>* t;
+  const cx<double>* rhat;
+  double* dsc;
+  __device__ void acc(size_t i, double* v) const {
+    const double* b = dsc + S_BICG;
+    const cx<double> al = mk(b[B_ALPHA], b[B_ALPHA + 1]), om = mk(b[B_OMEGA], b[B_OMEGA + 1]);
+    const cx<double> si = s[i];
+    x[i] = x[i] + al * p[i] + om * si;
+    const cx<double> ri = si - om * t[i];
+    r[i] = ri;
+    const cx<double> h = rhat[i];
+    v[0] += h.re * ri.re + h.im * ri.im;
+    v[1] += h.re * ri.im - h.im * ri.re;
+    v[2] += ri.re * ri.re + ri.im * ri.im;
+  }
+  __device__ void fin(const double* v) const {
+    double* b = dsc + S_BICG;
+    b[B_RHO_NEW] = v[0];
+    b[B_RHO_NEW + 1] = v[1];
+    b[B_RNORM] = v[2];
+    if (bad(v[2])) dsc[S_ERR] = 1.0;
+  }
+};
+
+// ---- elementwise kernels ---------------------------------------------------
+template <typename R>
+__global__ void k_zero(cx<R>* x, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    x[i] = mk<R>(0, 0);
+}
+
+template <typename R>
+__global__ void k_copy(cx<R>* __restrict__ y, const cx<R>* __restrict__ x, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    y[i] = x[i];
+}
+
+template <typename R>
+__global__ void k_neg(cx<R>* x, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    x[i] = mk<R>(-x[i].re, -x[i].im);
+}
+
+template <typename R>
+__global__ void k_xmy(const cx<R>* __restrict__ b, cx<R>* __restrict__ y, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    y[i] = b[i] - y[i];
+}
+
+template <typename R>
+__global__ void k_add(cx<R>* __restrict__ y, const cx<R>* __restrict__ x, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    y[i] = y[i] + x[i];
+}
+
+template <typename R>
+__global__ void k_update2(cx<R>* x, const cx<R>* u, cx<R>* r, const cx<R>* v, size_t n, const double* s) {
+  const cx<R> a = mk<R>((R)s[0], (R)s[1]);
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const cx<R> ui = u[i], vi = v[i];
+    x[i] = x[i] + a * ui;
+    r[i] = r[i] - a * vi;
+  }
+}
+
+__global__ void k_bicg_p(cx<double>* p, const cx<double>* r, const cx<double>* v, size_t n, const double* dsc,
+                         int first) {
+  const double* b = dsc + S_BICG;
+  cx<double> beta = mk(0.0, 0.0), om = mk(b[B_OMEGA], b[B_OMEGA + 1]);
+  if (!first) {
+    const cx<double> rn = mk(b[B_RHO_NEW], b[B_RHO_NEW + 1]), ro = mk(b[B_RHO_OLD], b[B_RHO_OLD + 1]);
+    const cx<double> al = mk(b[B_ALPHA], b[B_ALPHA + 1]);
+    beta = cdiv(rn, ro) * cdiv(al, om);
+  }
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    if (first)
+      p[i] = r[i];
+    else
+      p[i] = r[i] + beta * (p[i] - om * v[i]);
+  }
+}
+
+__global__ void k_bicg_s(cx<double>* s, const cx<double>* r, const cx<double>* v, size_t n, const double* dsc) {
+  const double* b = dsc + S_BICG;
+  const cx<double> al = mk(b[B_ALPHA], b[B_ALPHA + 1]);
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    s[i] = r[i] - al * v[i];
+}
+
+// GCR orthogonalisation: coefficients h_i = <W_i, w> / nrm_i for up to 8
+// basis vectors per workgroup row (blockIdx.y), then the last workgroup
+// finalises all of them.
+constexpr int GCR_G = 8;
+__global__ __launch_bounds__(TPB) void k_gcr_dots(const cx<double>* __restrict__ W, const cx<double>* __restrict__ w,
+                                                  size_t n, int j, double* partials, unsigned* counter, double* dsc,
+                                                  int hslot, int nrmslot) {
+  __shared__ double lds[2 * GCR_G * (TPB / 64)];
+  __shared__ bool last;
+  const int i0 = blockIdx.y * GCR_G;
+  const int ni = min(GCR_G, j - i0);
+  double v[2 * GCR_G];
+#pragma unroll
+  for (int k = 0; k < 2 * GCR_G; ++k) v[k] = 0.0;
+  for (size_t e = blockIdx.x * (size_t)TPB + threadIdx.x; e < n; e += (size_t)gridDim.x * TPB) {
+    const cx<double> y = w[e];
+#pragma unroll
+    for (int q = 0; q < GCR_G; ++q) {
+      if (q < ni) {
+        const cx<double> x = W[(size_t)(i0 + q) * n + e];
+        v[2 * q] += x.re * y.re + x.im * y.im;
+        v[2 * q + 1] += x.re * y.im - x.im * y.re;
+      }
+    }
+  }
+  block_sum<2 * GCR_G>(v, lds);
+  const unsigned nblk = gridDim.x * gridDim.y;
+  const unsigned myblk = blockIdx.y * gridDim.x + blockIdx.x;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < 2 * GCR_G; ++k) partials[(size_t)myblk * 2 * GCR_G + k] = v[k];
+    __threadfence();
+    last = atomicAdd(counter, 1u) == nblk - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  // thread t finalises value t = (group, k); blocks summed in fixed order
+  for (int t = threadIdx.x; t < 2 * j; t += TPB) {
+    const int i = t >> 1, part = t & 1;
+    const int gy = i / GCR_G, q = i % GCR_G;
+    double s = 0.0;
+    for (unsigned bx = 0; bx < gridDim.x; ++bx)
+      s += load_coherent(&partials[((size_t)gy * gridDim.x + bx) * 2 * GCR_G + 2 * q + part]);
+    const double nrm = dsc[nrmslot + i];
+    dsc[hslot + t] = nrm > 0.0 ? s / nrm : 0.0;
+  }
+  if (threadIdx.x == 0) *counter = 0u;
+}
+
+__global__ void k_gcr_axpy(const cx<double>* __restrict__ W, const cx<double>* __restrict__ Z, cx<double>* w,
+                           cx<double>* z, size_t n, int j, const double* h) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    cx<double> a = w[e], b = z[e];
+    for (int i = 0; i < j; ++i) {
+      const cx<double> hi = mk(h[2 * i], h[2 * i + 1]);
+      a = a - hi * W[(size_t)i * n + e];
+      b = b - hi * Z[(size_t)i * n + e];
+    }
+    w[e] = a;
+    z[e] = b;
+  }
+}
+
+__global__ void k_set_scalar(double* dsc, int slot, double re, double im) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    dsc[slot] = re;
+    dsc[slot + 1] = im;
+  }
+}
+
+inline unsigned ew_blocks(size_t n) {
+  size_t b = (n + 255) / 256;
+  if (b > 4096) b = 4096;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+}  // namespace
+
+template <typename R>
+void zero(Ctx& c, cx<R>* x, size_t n) {
+  hipLaunchKernelGGL((k_zero<R>), dim3(ew_blocks(n)), dim3(256), 0, c.stream, x, n);
+  WDMG_HIP(hipGetLastError());
+}
+template <typename R>
+void copy(Ctx& c, cx<R>* y, const cx<R>* x, size_t n) {
+  hipLaunchKernelGGL((k_copy<R>), dim3(ew_blocks(n)), dim3(256), 0, c.stream, y, x, n);
+  WDMG_HIP(hipGetLastError());
+}
+template <typename R>
+void neg(Ctx& c, cx<R>* x, size_t n) {
+  hipLaunchKernelGGL((k_neg<R>), dim3(ew_blocks(n)), dim3(256), 0, c.stream, x, n);
+  WDMG_HIP(hipGetLastError());
+}
+template <typename R>
+void xmy(Ctx& c, const cx<R>* b, cx<R>* y, size_t n) {
+  hipLaunchKernelGGL((k_xmy<R>), dim3(ew_blocks(n)), dim3(256), 0, c.stream, b, y, n);
+  WDMG_HIP(hipGetLastError());
+}
+template <typename R>
+void add(Ctx& c, cx<R>* y, const cx<R>* x, size_t n) {
+  hipLaunchKernelGGL((k_add<R>), dim3(ew_blocks(n)), dim3(256), 0, c.stream, y, x, n);
+  WDMG_HIP(hipGetLastError());
+}
+template <typename R>
+void step_alpha(Ctx& c, const cx<R>* a, const cx<R>* b, size_t n, double scale, int slot) {
+  run_reduce(c, StepAlphaOp<R>{a, b, scale, c.dsc, slot}, n);
+}
+template <typename R>
+void update2(Ctx& c, cx<R>* x, const cx<R>* u, cx<R>* r, const cx<R>* v, size_t n, int slot) {
+  hipLaunchKernelGGL((k_update2<R>), dim3(ew_blocks(n)), dim3(256), 0, c.stream, x, u, r, v, n, c.dsc + slot);
+  WDMG_HIP(hipGetLastError());
+}
+template <typename R>
+void norm2(Ctx& c, const cx<R>* a, size_t n, int slot) {
+  run_reduce(c, Norm2Op<R>{a, c.dsc, slot}, n);
+}
+template <typename R>
+void dot(Ctx& c, const cx<R>* a, const cx<R>* b, size_t n, int slot) {
+  run_reduce(c, DotOp<R>{a, b, c.dsc, slot}, n);
+}
+
+void gcr_orth(Ctx& c, const cx<double>* W, const cx<double>* Z, cx<double>* w, cx<double>* z, size_t n, int j,
+              int hslot, int nrmslot) {
+  if (j <= 0) return;
+  const unsigned gy = (unsigned)((j + GCR_G - 1) / GCR_G);
+  unsigned gx = reduce_blocks(n);
+  if (gx * gy > (unsigned)kMaxReduceBlocks * 2) gx = (kMaxReduceBlocks * 2) / gy;
+  hipLaunchKernelGGL(k_gcr_dots, dim3(gx, gy), dim3(TPB), 0, c.stream, W, w, n, j, c.partials, c.counter, c.dsc,
+                     hslot, nrmslot);
+  WDMG_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_gcr_axpy, dim3(ew_blocks(n)), dim3(256), 0, c.stream, W, Z, w, z, n, j, c.dsc + hslot);
+  WDMG_HIP(hipGetLastError());
+}
+
+void gcr_step(Ctx& c, const cx<double>* w, const cx<double>* z, cx<double>* x, cx<double>* r, size_t n, int j,
+              int nrmslot, int rslot) {
+  run_reduce(c, GcrCoefOp{w, r, c.dsc, nrmslot + j, S_TMP}, n);
+  run_reduce(c, GcrUpdateOp{w, z, x, r, c.dsc + S_TMP, c.dsc, rslot}, n);
+}
+
+void xmy_norm(Ctx& c, const cx<double>* b, cx<double>* y, size_t n, int slot) {
+  run_reduce(c, XmyNormOp{b, y, c.dsc, slot}, n);
+}
+
+void bicg_p(Ctx& c, cx<double>* p, const cx<double>* r, const cx<double>* v, size_t n, bool first) {
+  hipLaunchKernelGGL(k_bicg_p, dim3(ew_blocks(n)), dim3(256), 0, c.stream, p, r, v, n, c.dsc, first ? 1 : 0);
+  WDMG_HIP(hipGetLastError());
+}
+void bicg_alpha(Ctx& c, const cx<double>* rhat, const cx<double>* v, size_t n) {
+  run_reduce(c, BicgAlphaOp{rhat, v, c.dsc}, n);
+}
+void bicg_s(Ctx& c, cx<double>* s, const cx<double>* r, const cx<double>* v, size_t n) {
+  hipLaunchKernelGGL(k_bicg_s, dim3(ew_blocks(n)), dim3(256), 0, c.stream, s, r, v, n, c.dsc);
+  WDMG_HIP(hipGetLastError());
+}
+void bicg_omega(Ctx& c, const cx<double>* t, const cx<double>* s, size_t n) {
+  run_reduce(c, BicgOmegaOp{t, s, c.dsc}, n);
+}
+void bicg_xr(Ctx& c, cx<double>* x, cx<double>* r, const cx<double>* p, const cx<double>* s, const cx<double>* t,
+             const cx<double>* rhat, size_t n) {
+  run_reduce(c, BicgXrOp{x, r, p, s, t, rhat, c.dsc}, n);
+}
+void set_scalar(Ctx& c, int slot, double re, double im) {
+  hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(64), 0, c.stream, c.dsc, slot, re, im);
+  WDMG_HIP(hipGetLastError());
+}
+
+#define INST(R)                                                                            \
+  template void zero<R>(Ctx&, cx<R>*, size_t);                                             \
+  template void copy<R>(Ctx&, cx<R>*, const cx<R>*, size_t);                               \
+  template void neg<R>(Ctx&, cx<R>*, size_t);                                              \
+  template void xmy<R>(Ctx&, const cx<R>*, cx<R>*, size_t);                                \
+  template void add<R>(Ctx&, cx<R>*, const cx<R>*, size_t);                                \
+  template void step_alpha<R>(Ctx&, const cx<R>*, const cx<R>*, size_t, double, int);      \
+  template void update2<R>(Ctx&, cx<R>*, const cx<R>*, cx<R>*, const cx<R>*, size_t, int); \
+  template void norm2<R>(Ctx&, const cx<R>*, size_t, int);                                 \
+  template void dot<R>(Ctx&, const cx<R>*, const cx<R>*, size_t, int);
+INST(double)
+INST(float)
+#undef INST
+
+}  // namespace wdmg

@@ -1,0 +1,365 @@
+// Galerkin coarse operator D_c = P^dagger D P (Sec. 2) as a nearest-neighbour
+// stencil of dense complex (2Nv x 2Nv) blocks, and its application.
+//
+// Storage per coarse site: nine blocks, column-major ([col][row]), in the
+// order d = 2 mu (Y_{+mu}, couples to xhat + mu), d = 2 mu + 1 (Y_{-mu},
+// couples to xhat - mu), d = 8 (X, the site itself).
+//
+// Build: a fine-level coupling that leaves an aggregate through its +-mu face
+// lands in Y_{+-mu}; every other coupling (the diagonal term and the hops
+// that stay inside the aggregate) lands in X.  Each workgroup computes one
+// block of one coarse site: it applies the fine hops to the chirality-split
+// columns of P at a few sites at a time (staged in LDS) and contracts them
+// with the conjugated columns, all in FP64.
+#include "internal.h"
+#include "wilson_spin.h"
+
+namespace wdmg {
+namespace {
+
+struct AggGeom {
+  Geom g;       // geometry of the finer level
+  int b[4];     // aggregate extents
+  int nb[4];    // aggregates per direction
+  int bvol;
+};
+
+AggGeom make_agg(const Level& f) {
+  AggGeom a;
+  a.g = f.g;
+  a.bvol = 1;
+  for (int mu = 0; mu < 4; ++mu) {
+    a.b[mu] = f.block[mu];
+    a.nb[mu] = f.dims[mu] / f.block[mu];
+    a.bvol *= f.block[mu];
+  }
+  return a;
+}
+
+// Global coordinates of local site `i` of the sites visited for block d of
+// aggregate `agg`: the whole aggregate for d = 8, else its (mu, sign) face.
+__device__ __forceinline__ void block_site(const AggGeom& a, int agg, int d, int i, int c[4]) {
+  int base[4];
+  int t = agg;
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    base[mu] = (t % a.nb[mu]) * a.b[mu];
+    t /= a.nb[mu];
+  }
+  const int fmu = d < 8 ? (d >> 1) : -1;
+  int u = i;
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    int lc;
+    if (mu == fmu) {
+      lc = (d & 1) ? 0 : a.b[mu] - 1;
+    } else {
+      lc = u % a.b[mu];
+      u /= a.b[mu];
+    }
+    c[mu] = base[mu] + lc;
+  }
+}
+
+__device__ __forceinline__ int nsites_of_block(const AggGeom& a, int d) {
+  return d < 8 ? a.bvol / a.b[d >> 1] : a.bvol;
+}
+
+// Is the hop (mu, dir) from coordinates c inside the aggregate?
+__device__ __forceinline__ bool inside(const AggGeom& a, const int c[4], int mu, int dir) {
+  const int lc = c[mu] % a.b[mu];
+  return dir > 0 ? (lc < a.b[mu] - 1) : (lc > 0);
+}
+
+// ---- level 0: Wilson hops ---------------------------------------------------
+template <int MU, int SIGN>
+__device__ __forceinline__ void wilson_hop_col(const cx<double>* __restrict__ U, const cx<double>* __restrict__ vk,
+                                               size_t V, int s, int nb, int chi, cx<double> (&t)[12]) {
+  cx<double> p[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    const bool on = (k / 6) == chi;
+    p[k] = on ? vk[(size_t)k * V + nb] : mk(0.0, 0.0);
+  }
+  cx<double> h[6];
+  project<MU, SIGN>(p, h);
+  const int ls = SIGN > 0 ? s : nb;
+  cx<double> u[9];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) u[e] = U[(size_t)(MU * 9 + e) * V + ls];
+  cx<double> uh[6];
+#pragma unroll
+  for (int aa = 0; aa < 2; ++aa) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      cx<double> sacc = mk(0.0, 0.0);
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        if (SIGN > 0)
+          cmadd(sacc, u[i * 3 + b], h[aa * 3 + b]);
+        else
+          cmaddc(sacc, u[b * 3 + i], h[aa * 3 + b]);
+      }
+      uh[aa * 3 + i] = sacc;
+    }
+  }
+  expand_add<MU, SIGN>(uh, t);
+}
+
+__device__ void wilson_hop_dispatch(int mu, int dir, const cx<double>* U, const cx<double>* vk, size_t V, int s,
+                                    int nb, int chi, cx<double> (&t)[12]) {
+  switch (mu * 2 + (dir < 0)) {
+    case 0: wilson_hop_col<0, +1>(U, vk, V, s, nb, chi, t); break;
+    case 1: wilson_hop_col<0, -1>(U, vk, V, s, nb, chi, t); break;
+    case 2: wilson_hop_col<1, +1>(U, vk, V, s, nb, chi, t); break;
+    case 3: wilson_hop_col<1, -1>(U, vk, V, s, nb, chi, t); break;
+    case 4: wilson_hop_col<2, +1>(U, vk, V, s, nb, chi, t); break;
+    case 5: wilson_hop_col<2, -1>(U, vk, V, s, nb, chi, t); break;
+    case 6: wilson_hop_col<3, +1>(U, vk, V, s, nb, chi, t); break;
+    default: wilson_hop_col<3, -1>(U, vk, V, s, nb, chi, t); break;
+  }
+}
+
+struct WilsonSide {
+  const cx<double>* U;
+  double diag;  // 4 + m
+  static constexpr int kDof = 12;
+  // Element offset of dof e at site s in a field of this level.
+  __device__ __forceinline__ size_t off(size_t V, int s, int e) const { return (size_t)e * V + s; }
+  // T[q][e][cc] for columns col0 .. col0+ncc-1 at the chunk's sites.
+  __device__ void columns(const AggGeom& a, int d, const int* sites, const int (*crd)[4], int ncs, int col0, int ncc,
+                          int ldt, int nv, const cx<double>* Vv, size_t vstride, cx<double>* T) const {
+    const size_t V = a.g.vol;
+    for (int w = threadIdx.x; w < ncs * ncc; w += blockDim.x) {
+      const int q = w / ncc, cc = w % ncc;
+      const int col = col0 + cc, chi = col / nv, k = col % nv;
+      const cx<double>* vk = Vv + (size_t)k * vstride;
+      const int s = sites[q];
+      const int* c = crd[q];
+      cx<double> t[12];
+#pragma unroll
+      for (int e = 0; e < 12; ++e) t[e] = mk(0.0, 0.0);
+      if (d < 8) {
+        const int mu = d >> 1, dir = (d & 1) ? -1 : 1;
+        const int nb = dir > 0 ? nbr_fwd(a.g, s, c, mu) : nbr_bwd(a.g, s, c, mu);
+        wilson_hop_dispatch(mu, dir, U, vk, V, s, nb, chi, t);
+#pragma unroll
+        for (int e = 0; e < 12; ++e) t[e] = (-0.5) * t[e];
+      } else {
+        for (int mu = 0; mu < 4; ++mu) {
+          for (int dir = 1; dir >= -1; dir -= 2) {
+            if (!inside(a, c, mu, dir)) continue;
+            const int nb = dir > 0 ? nbr_fwd(a.g, s, c, mu) : nbr_bwd(a.g, s, c, mu);
+            wilson_hop_dispatch(mu, dir, U, vk, V, s, nb, chi, t);
+          }
+        }
+#pragma unroll
+        for (int e = 0; e < 12; ++e) {
+          const bool on = (e / 6) == chi;
+          const cx<double> f = on ? vk[(size_t)e * V + s] : mk(0.0, 0.0);
+          t[e] = mk(diag * f.re - 0.5 * t[e].re, diag * f.im - 0.5 * t[e].im);
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < 12; ++e) T[((size_t)q * 12 + e) * ldt + cc] = t[e];
+    }
+  }
+};
+
+// ---- level >= 1: stencil hops ----------------------------------------------
+struct StencilSide {
+  const cx<double>* Dc;  // finer level's stencil [site][9][col][row]
+  int dof;
+  __device__ __forceinline__ size_t off(size_t, int s, int e) const { return (size_t)s * dof + e; }
+  __device__ void columns(const AggGeom& a, int d, const int* sites, const int (*crd)[4], int ncs, int col0, int ncc,
+                          int ldt, int nv, const cx<double>* Vv, size_t vstride, cx<double>* T) const {
+    const int half = dof / 2;
+    const size_t bsz = (size_t)dof * dof;
+    for (int w = threadIdx.x; w < ncs * ncc * dof; w += blockDim.x) {
+      const int e = w % dof;
+      const int cc = (w / dof) % ncc;
+      const int q = w / (dof * ncc);
+      const int col = col0 + cc, chi = col / nv, k = col % nv;
+      const cx<double>* vk = Vv + (size_t)k * vstride;
+      const int s = sites[q];
+      const int* c = crd[q];
+      cx<double> acc = mk(0.0, 0.0);
+      for (int dd = 0; dd < 9; ++dd) {
+        int nb;
+        if (d < 8) {
+          if (dd != d) continue;
+        } else if (dd < 8) {
+          if (!inside(a, c, dd >> 1, (dd & 1) ? -1 : 1)) continue;
+        }
+        if (dd == 8)
+          nb = s;
+        else
+          nb = (dd & 1) ? nbr_bwd(a.g, s, c, dd >> 1) : nbr_fwd(a.g, s, c, dd >> 1);
+        const cx<double>* blk = Dc + ((size_t)s * 9 + dd) * bsz;
+        const cx<double>* f = vk + (size_t)nb * dof + chi * half;
+        for (int j = 0; j < half; ++j) cmadd(acc, blk[(size_t)(chi * half + j) * dof + e], f[j]);
+      }
+      T[((size_t)q * dof + e) * ldt + cc] = acc;
+    }
+  }
+};
+
+// ---- the build kernel ---------------------------------------------------------
+template <class Side>
+__global__ __launch_bounds__(256) void k_coarse_build(Side side, AggGeom a, const cx<double>* __restrict__ Vv,
+                                                      size_t vstride, int nv, int dof, int cs, int cc_max,
+                                                      cx<double>* __restrict__ Dc) {
+  extern __shared__ cx<double> sm[];
+  __shared__ int sites[8];
+  __shared__ int crd[8][4];
+  const int agg = blockIdx.x, d = blockIdx.y;
+  const int n2 = 2 * nv, half = dof / 2;
+  cx<double>* Vt = sm;                          // [cs][dof][nv]
+  cx<double>* T = sm + (size_t)cs * dof * nv;   // [cs][dof][cc_max]
+  const int nsites = nsites_of_block(a, d);
+  cx<double>* out = Dc + ((size_t)agg * 9 + d) * n2 * n2;
+  for (int col0 = 0; col0 < n2; col0 += cc_max) {
+    const int ncc = min(cc_max, n2 - col0);
+    const int nent = n2 * ncc;
+    cx<double> acc[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = mk(0.0, 0.0);
+    for (int i0 = 0; i0 < nsites; i0 += cs) {
+      const int ncs = min(cs, nsites - i0);
+      if (threadIdx.x < ncs) {
+        int c[4];
+        block_site(a, agg, d, i0 + threadIdx.x, c);
+        sites[threadIdx.x] = site_of(a.g, c[0], c[1], c[2], c[3]);
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) crd[threadIdx.x][mu] = c[mu];
+      }
+      __syncthreads();
+      for (int w = threadIdx.x; w < ncs * dof * nv; w += blockDim.x) {
+        const int k = w % nv, e = (w / nv) % dof, q = w / (nv * dof);
+        Vt[w] = Vv[(size_t)k * vstride + side.off(a.g.vol, sites[q], e)];
+      }
+      side.columns(a, d, sites, crd, ncs, col0, ncc, cc_max, nv, Vv, vstride, T);
+      __syncthreads();
+#pragma unroll
+      for (int slot = 0; slot < 16; ++slot) {
+        const int ent = threadIdx.x + slot * 256;
+        if (ent < nent) {
+          const int row = ent % n2, cc = ent / n2;
+          const int chi = row / nv, k = row % nv;
+          cx<double> s = acc[slot];
+          for (int q = 0; q < ncs; ++q) {
+            for (int m = 0; m < half; ++m) {
+              const int e = chi * half + m;
+              cmaddc(s, Vt[((size_t)q * dof + e) * nv + k], T[((size_t)q * dof + e) * cc_max + cc]);
+            }
+          }
+          acc[slot] = s;
+        }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int slot = 0; slot < 16; ++slot) {
+      const int ent = threadIdx.x + slot * 256;
+      if (ent < nent) {
+        const int row = ent % n2, cc = ent / n2;
+        out[(size_t)(col0 + cc) * n2 + row] = acc[slot];
+      }
+    }
+  }
+}
+
+// ---- application ----------------------------------------------------------------
+// One workgroup of nine waves per (coarse site, rhs); wave d applies block d
+// (lane = row), and the nine partial rows are summed in a fixed order.
+template <typename R>
+__global__ __launch_bounds__(576) void k_coarse_apply(Geom g, int n2, const cx<R>* __restrict__ Dc,
+                                                      const cx<R>* __restrict__ in, cx<R>* __restrict__ out) {
+  __shared__ cx<R> part[9][64];
+  const int s = blockIdx.x, rhs = blockIdx.y;
+  const int d = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const size_t nsite = g.vol;
+  in += (size_t)rhs * nsite * n2;
+  out += (size_t)rhs * nsite * n2;
+  int nb = s;
+  if (d < 8) {
+    int c[4];
+    coords_of(g, s, c);
+    nb = (d & 1) ? nbr_bwd(g, s, c, d >> 1) : nbr_fwd(g, s, c, d >> 1);
+  }
+  cx<R> acc = mk<R>(0, 0);
+  if (lane < n2) {
+    const cx<R>* blk = Dc + ((size_t)s * 9 + d) * n2 * n2 + lane;
+    const cx<R>* v = in + (size_t)nb * n2;
+    for (int j = 0; j < n2; ++j) cmadd(acc, blk[(size_t)j * n2], v[j]);
+  }
+  part[d][lane] = acc;
+  __syncthreads();
+  if (d == 0 && lane < n2) {
+    cx<R> t = part[8][lane];
+#pragma unroll
+    for (int dd = 0; dd < 8; ++dd) t = t + part[dd][lane];
+    out[(size_t)s * n2 + lane] = t;
+  }
+}
+
+template <typename R>
+__global__ void k_coarse_shift(cx<R>* Dc, int nsite, int n2, double dm) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nsite * n2) return;
+  const int s = i / n2, r = i % n2;
+  cx<R>* x = Dc + ((size_t)s * 9 + 8) * n2 * n2;
+  x[(size_t)r * n2 + r].re += (R)dm;
+}
+
+template <class Side>
+void launch_build(Ctx& c, const Side& side, const Level& f, Level& cl, int dof) {
+  const AggGeom a = make_agg(f);
+  const int n2 = 2 * f.nv;
+  // LDS budget ~48 KiB: cs sites of V (dof x nv) and T (dof x cc) columns.
+  int cc = n2;
+  int cs = 4;
+  auto bytes = [&](int cs_, int cc_) { return (size_t)cs_ * dof * (f.nv + cc_) * sizeof(cx<double>); };
+  while (cs > 1 && (bytes(cs, cc) > 48 * 1024 || cs * cc > 256)) --cs;
+  while (cc > 1 && (bytes(cs, cc) > 48 * 1024 || n2 * cc > 16 * 256)) cc = (cc + 1) / 2;
+  const int nagg = cl.nsite;
+  ProfScope ps(c, WDMG_K_DC_BUILD, nagg);
+  hipLaunchKernelGGL((k_coarse_build<Side>), dim3(nagg, 9), dim3(256), bytes(cs, cc), c.stream, side, a, f.V64,
+                     f.n, f.nv, dof, cs, cc, cl.Dc64);
+  WDMG_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+void coarse_build0(Ctx& c, const Level& f, Level& cl) {
+  WilsonSide side{c.U64, 4.0 + c.mass};
+  launch_build(c, side, f, cl, 12);
+}
+
+void coarse_buildC(Ctx& c, const Level& f, Level& cl) {
+  StencilSide side{f.Dc64, f.dof};
+  launch_build(c, side, f, cl, f.dof);
+}
+
+template <typename R>
+void coarse_apply(Ctx& c, const Level& cl, const cx<R>* Dc, cx<R>* out, const cx<R>* in, int nrhs) {
+  ProfScope ps(c, sizeof(R) == 8 ? WDMG_K_DC_F64 : WDMG_K_DC_F32, (long long)cl.nsite * nrhs);
+  hipLaunchKernelGGL((k_coarse_apply<R>), dim3(cl.nsite, nrhs), dim3(576), 0, c.stream, cl.g, cl.dof, Dc, in, out);
+  WDMG_HIP(hipGetLastError());
+  c.n_Dc[cl.l] += nrhs;
+}
+
+void coarse_shift(Ctx& c, Level& cl, double dm) {
+  const int n = cl.nsite * cl.dof;
+  hipLaunchKernelGGL((k_coarse_shift<double>), dim3((n + 255) / 256), dim3(256), 0, c.stream, cl.Dc64, cl.nsite,
+                     cl.dof, dm);
+  WDMG_HIP(hipGetLastError());
+  hipLaunchKernelGGL((k_coarse_shift<float>), dim3((n + 255) / 256), dim3(256), 0, c.stream, cl.Dc32, cl.nsite,
+                     cl.dof, dm);
+  WDMG_HIP(hipGetLastError());
+}
+
+template void coarse_apply<double>(Ctx&, const Level&, const cx<double>*, cx<double>*, const cx<double>*, int);
+template void coarse_apply<float>(Ctx&, const Level&, const cx<float>*, cx<float>*, const cx<float>*, int);
+
+}  // namespace wdmg

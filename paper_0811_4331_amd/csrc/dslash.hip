@@ -1,0 +1,111 @@
+// Wilson-Dirac operator on gfx950 (Sec. 1):
+//   (D psi)(x) = (4 + m) psi(x)
+//              - 1/2 sum_mu [ (1 - gamma_mu) U_mu(x) psi(x+mu) + (1 + gamma_mu) U_mu(x-mu)^+ psi(x-mu) ]
+// in the chiral basis (gamma5 = diag(1,1,-1,-1)).  Each hop projects the
+// neighbour spinor onto the two-dimensional image of (1 -+ gamma_mu), applies
+// the SU(3) link to the two colour vectors of that half spinor, and expands
+// back to four spins.  The antiperiodic time sign is folded into the stored
+// links U_t(x) at t = Lt-1, so it reaches both hop directions.
+//
+// Layout: fields [rhs][12][V] (component-major, sites tile-major), links
+// [mu][9][V]: every load of a wavefront is 64 consecutive elements.
+// One thread per (site, right-hand side).
+#include "internal.h"
+#include "wilson_spin.h"
+
+namespace wdmg {
+namespace {
+
+template <int MU, int SIGN, typename R>
+__device__ __forceinline__ void hop(const cx<R>* __restrict__ in, const cx<R>* __restrict__ U, size_t V,
+                                    int nb, int link_site, cx<R> (&acc)[12]) {
+  cx<R> p[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) p[k] = in[(size_t)k * V + nb];
+  cx<R> h[6];
+  project<MU, SIGN>(p, h);
+  cx<R> u[9];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) u[e] = U[(size_t)(MU * 9 + e) * V + link_site];
+  cx<R> uh[6];
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      cx<R> s = mk<R>(0, 0);
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        if (SIGN > 0)
+          cmadd(s, u[i * 3 + b], h[a * 3 + b]);   // U h
+        else
+          cmaddc(s, u[b * 3 + i], h[a * 3 + b]);  // U^+ h
+      }
+      uh[a * 3 + i] = s;
+    }
+  }
+  expand_add<MU, SIGN>(uh, acc);
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_dslash(Geom g, cx<R>* __restrict__ out, const cx<R>* __restrict__ in,
+                                                const cx<R>* __restrict__ U, R diag) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= g.vol) return;
+  const size_t V = g.vol;
+  const size_t off = (size_t)blockIdx.y * 12 * V;
+  in += off;
+  out += off;
+  int c[4];
+  coords_of(g, s, c);
+  cx<R> acc[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[k] = mk<R>(0, 0);
+  {
+    const int f = nbr_fwd(g, s, c, 0), b = nbr_bwd(g, s, c, 0);
+    hop<0, +1>(in, U, V, f, s, acc);
+    hop<0, -1>(in, U, V, b, b, acc);
+  }
+  {
+    const int f = nbr_fwd(g, s, c, 1), b = nbr_bwd(g, s, c, 1);
+    hop<1, +1>(in, U, V, f, s, acc);
+    hop<1, -1>(in, U, V, b, b, acc);
+  }
+  {
+    const int f = nbr_fwd(g, s, c, 2), b = nbr_bwd(g, s, c, 2);
+    hop<2, +1>(in, U, V, f, s, acc);
+    hop<2, -1>(in, U, V, b, b, acc);
+  }
+  {
+    const int f = nbr_fwd(g, s, c, 3), b = nbr_bwd(g, s, c, 3);
+    hop<3, +1>(in, U, V, f, s, acc);
+    hop<3, -1>(in, U, V, b, b, acc);
+  }
+  const R half = (R)0.5;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    const cx<R> p = in[(size_t)k * V + s];
+    out[(size_t)k * V + s] = mk<R>(diag * p.re - half * acc[k].re, diag * p.im - half * acc[k].im);
+  }
+}
+
+}  // namespace
+
+template <typename R>
+void dslash(Ctx& c, cx<R>* out, const cx<R>* in, int nrhs) {
+  const Geom& g = c.g0;
+  const cx<R>* U = nullptr;
+  if constexpr (sizeof(R) == 8)
+    U = c.U64;
+  else
+    U = c.U32;
+  dim3 grid((g.vol + 255) / 256, nrhs);
+  ProfScope ps(c, sizeof(R) == 8 ? WDMG_K_DSLASH_F64 : WDMG_K_DSLASH_F32, (long long)g.vol * nrhs);
+  hipLaunchKernelGGL((k_dslash<R>), grid, dim3(256), 0, c.stream, g, out, in, U, (R)(4.0 + c.mass));
+  WDMG_HIP(hipGetLastError());
+  c.n_D += nrhs;
+}
+
+template void dslash<double>(Ctx&, cx<double>*, const cx<double>*, int);
+template void dslash<float>(Ctx&, cx<float>*, const cx<float>*, int);
+
+}  // namespace wdmg

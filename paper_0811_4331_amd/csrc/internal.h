@@ -1,0 +1,226 @@
+// Host-side internals of libwdmg: context, levels, kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/wdmg.h"
+#include "common.h"
+
+namespace wdmg {
+
+// Error carried from the host drivers to the ABI layer.
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define WDMG_HIP(call)                                                                     \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      throw ::wdmg::Error(WDMG_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+Geom make_geom(const int L[4], const int B[4]);
+
+// ---------------------------------------------------------------------------
+// Device scalar area.  Solver coefficients live here and are consumed by
+// kernels directly; the host reads back only residual norms.
+enum ScalarSlot {
+  S_ERR = 0,        // NaN / rank flags (as doubles)
+  S_MR = 8,         // MR / correction step: alpha (re, im)
+  S_TMP = 16,       // misc: norms, dots
+  S_BICG = 32,      // BiCGStab: rho, alpha, omega, beta, ... (complex)
+  S_RNORM = 64,     // residual norm^2 per level (real)
+  S_GCR = 128,      // GCR coefficients: per level a block of 4 * 128 doubles
+  S_GCR_STRIDE = 512,
+  S_TOTAL = S_GCR + 4 * S_GCR_STRIDE
+};
+
+// ---------------------------------------------------------------------------
+// Memory owned by a context.
+struct Ctx;
+struct Buf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+// One multigrid level.  Level 0 is the Wilson operator on the fine lattice
+// (spinor fields stored [rhs][12][V] component-major over tile-major sites);
+// level l >= 1 is a coarse stencil with fields [rhs][site][2 Nv].
+struct Level {
+  int l = 0;
+  int dims[4] = {0, 0, 0, 0};
+  Geom g;
+  int nsite = 0;
+  int dof = 0;          // complex dof per site: 12 at level 0, 2*Nv_{l-1} above
+  size_t n = 0;         // complex elements per field = nsite * dof
+  // transfer to level l+1
+  int block[4] = {1, 1, 1, 1};
+  int nv = 0;
+  cx<double>* V64 = nullptr;   // orthonormal block columns, nv fields of this level
+  cx<float>* V32 = nullptr;
+  // coarse operator of this level (l >= 1): [site][9][col][row]
+  cx<double>* Dc64 = nullptr;
+  cx<float>* Dc32 = nullptr;
+  // work vectors of the V-cycle at this level
+  cx<double>* w64[8] = {};
+  cx<float>* w32[8] = {};
+  // GCR basis of the coarsest solve (coarsest level only)
+  cx<double>* basisZ = nullptr;
+  cx<double>* basisW = nullptr;
+};
+
+constexpr int kWork = 8;
+
+struct Ctx {
+  int dims[4];
+  Geom g0;
+  hipStream_t stream = nullptr;
+  wdmg_alloc alloc{};
+  bool own_alloc = true;
+  std::string err;
+  std::vector<Buf> bufs;
+
+  double mass = 0.0;
+  int t_bc = -1;
+  bool have_gauge = false;
+  cx<double>* U64 = nullptr;   // [4][9][V], t boundary sign folded in
+  cx<float>* U32 = nullptr;
+
+  double* dsc = nullptr;        // device scalars (S_TOTAL doubles)
+  double* partials = nullptr;   // reduction partials
+  unsigned* counter = nullptr;  // last-block counters
+  double* hsc = nullptr;        // pinned host mirror of a few scalars
+
+  // multigrid
+  bool have_mg = false;
+  wdmg_mg_params mg{};
+  int nlevels = 0;
+  Level lev[WDMG_MAX_LEVELS];
+  double setup_mass = 0.0;
+
+  // scratch fine / coarse fields for canonical <-> internal conversion
+  void* io_a = nullptr;
+  void* io_b = nullptr;
+  size_t io_bytes = 0;
+
+  // outer FGCR and BiCGStab work space (fine level, FP64)
+  int outer_k = 0;
+  cx<double>* outer_Z = nullptr;
+  cx<double>* outer_W = nullptr;
+  cx<double>* outer_r = nullptr;
+  cx<float>* outer_r32 = nullptr;
+  cx<float>* outer_z32 = nullptr;
+  cx<double>* bicg[6] = {};
+  cx<double>* sol_x = nullptr;   // internal x, b of a solve
+  cx<double>* sol_b = nullptr;
+
+  // kernel timing (instrumentation)
+  bool prof_on = false;
+  struct ProfRec {
+    int id;
+    long long units;
+    hipEvent_t a, b;
+  };
+  std::vector<ProfRec> prof_recs;
+  std::vector<hipEvent_t> prof_pool;
+  long long prof_launch[WDMG_K_COUNT] = {};
+  long long prof_units[WDMG_K_COUNT] = {};
+  double prof_ms[WDMG_K_COUNT] = {};
+
+  // counters of the current solve
+  long long n_D = 0;
+  long long n_Dc[WDMG_MAX_LEVELS] = {0, 0, 0, 0};
+};
+
+// Records HIP events around one kernel launch when timing is enabled.
+struct ProfScope {
+  Ctx& c;
+  int idx = -1;
+  ProfScope(Ctx& ctx, int id, long long units);
+  ~ProfScope();
+};
+void prof_collect(Ctx& c);
+
+void* dev_alloc(Ctx& c, size_t bytes);
+void dev_free(Ctx& c, void* p);
+void ensure_io(Ctx& c, size_t bytes);
+
+constexpr int kReduceThreads = 256;
+constexpr int kMaxReduceBlocks = 1024;
+constexpr int kPartialsPerBlock = 64;
+
+// ---------------------------------------------------------------------------
+// Layout conversion (layout.hip).
+void gauge_import(Ctx& c, const cx<double>* canon, int t_bc);
+template <typename Rio, typename R>
+void fine_to_internal(Ctx& c, const Geom& g, const cx<Rio>* canon, cx<R>* out, int nrhs);
+template <typename R, typename Rio>
+void fine_to_canonical(Ctx& c, const Geom& g, const cx<R>* in, cx<Rio>* canon, int nrhs);
+template <typename Rout, typename Rin>
+void convert(Ctx& c, cx<Rout>* out, const cx<Rin>* in, size_t n);
+
+// Wilson operator (dslash.hip): out = diag * in - 1/2 sum_mu hops.
+template <typename R>
+void dslash(Ctx& c, cx<R>* out, const cx<R>* in, int nrhs);
+
+// BLAS-1 and reductions (blas.hip).  Vectors are flat arrays of n complex.
+template <typename R> void zero(Ctx& c, cx<R>* x, size_t n);
+template <typename R> void copy(Ctx& c, cx<R>* y, const cx<R>* x, size_t n);
+template <typename R> void neg(Ctx& c, cx<R>* x, size_t n);           // x = -x
+template <typename R> void xmy(Ctx& c, const cx<R>* b, cx<R>* y, size_t n);  // y = b - y
+template <typename R> void add(Ctx& c, cx<R>* y, const cx<R>* x, size_t n);  // y += x
+// dsc[slot] = scale * <a, b> / <a, a>  (0 if <a,a> == 0); complex result.
+template <typename R> void step_alpha(Ctx& c, const cx<R>* a, const cx<R>* b, size_t n, double scale, int slot);
+// x += s u ; r -= s v with s = dsc[slot] (complex).
+template <typename R> void update2(Ctx& c, cx<R>* x, const cx<R>* u, cx<R>* r, const cx<R>* v, size_t n, int slot);
+// dsc[slot] = ||a||^2
+template <typename R> void norm2(Ctx& c, const cx<R>* a, size_t n, int slot);
+// dsc[slot] = <a, b>
+template <typename R> void dot(Ctx& c, const cx<R>* a, const cx<R>* b, size_t n, int slot);
+// GCR orthogonalisation: h_i = <W_i, w> / nrm_i (i < j) into dsc[hslot + 2 i];
+// then w -= sum h_i W_i, z -= sum h_i Z_i.  W, Z: j contiguous vectors of n.
+void gcr_orth(Ctx& c, const cx<double>* W, const cx<double>* Z, cx<double>* w, cx<double>* z,
+              size_t n, int j, int hslot, int nrmslot);
+// GCR step: nrm_j = <w,w> -> dsc[nrmslot + j]; a = <w, r> / nrm_j;
+// x += a z; r -= a w; dsc[rslot] = ||r||^2.
+void gcr_step(Ctx& c, const cx<double>* w, const cx<double>* z, cx<double>* x, cx<double>* r,
+              size_t n, int j, int nrmslot, int rslot);
+// y = b - y (residual from an operator application); dsc[slot] = ||y||^2.
+void xmy_norm(Ctx& c, const cx<double>* b, cx<double>* y, size_t n, int slot);
+// BiCGStab kernels (FP64).
+void bicg_p(Ctx& c, cx<double>* p, const cx<double>* r, const cx<double>* v, size_t n, bool first);
+void bicg_alpha(Ctx& c, const cx<double>* rhat, const cx<double>* v, size_t n);
+void bicg_s(Ctx& c, cx<double>* s, const cx<double>* r, const cx<double>* v, size_t n);
+void bicg_omega(Ctx& c, const cx<double>* t, const cx<double>* s, size_t n);
+void bicg_xr(Ctx& c, cx<double>* x, cx<double>* r, const cx<double>* p, const cx<double>* s,
+             const cx<double>* t, const cx<double>* rhat, size_t n);
+void set_scalar(Ctx& c, int slot, double re, double im);
+
+// Transfer (transfer.hip).
+template <typename R>
+void restrict0(Ctx& c, const Level& f, const cx<R>* V, const cx<R>* in, cx<R>* out, int nrhs);
+template <typename R>
+void prolong0(Ctx& c, const Level& f, const cx<R>* V, const cx<R>* in, cx<R>* out, int nrhs);
+template <typename R>
+void restrictC(Ctx& c, const Level& f, const cx<R>* V, const cx<R>* in, cx<R>* out, int nrhs);
+template <typename R>
+void prolongC(Ctx& c, const Level& f, const cx<R>* V, const cx<R>* in, cx<R>* out, int nrhs);
+// Block orthonormalisation in FP64, in place; sets dsc[S_ERR+1] != 0 on rank loss.
+void block_qr0(Ctx& c, const Level& f, cx<double>* V);
+void block_qrC(Ctx& c, const Level& f, cx<double>* V);
+
+// Coarse operator (coarse.hip).
+void coarse_build0(Ctx& c, const Level& f, Level& cl);
+void coarse_buildC(Ctx& c, const Level& f, Level& cl);
+template <typename R>
+void coarse_apply(Ctx& c, const Level& cl, const cx<R>* Dc, cx<R>* out, const cx<R>* in, int nrhs);
+void coarse_shift(Ctx& c, Level& cl, double dm);
+
+}  // namespace wdmg

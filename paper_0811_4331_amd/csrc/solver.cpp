@@ -1,0 +1,629 @@
+// Host drivers: MR smoother, coarse-grid correction, V-cycle, coarsest GCR,
+// flexible GCR outer solve, BiCGStab comparator and the adaptive setup.
+// Every arithmetic step runs in the kernels; the host only sequences launches
+// on the context's stream and reads back residual norms.
+//
+// Paper passages: MR smoother with omega (Sec. 3, last paragraph); coarse-grid
+// correction with the minimal-residual step alpha (Sec. 3, step-size
+// equation); V(nu_pre, nu_post) cycle (Sec. 2) and the modified 3-level cycle
+// with 4 next-coarser cycles between fine restriction and prolongation
+// (Sec. 5); GCR(k) outer solver, flexible because the preconditioner is not
+// stationary (Sec. 5); adaptive setup by relaxation of A v = 0 and block QR
+// (Sec. 2).
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "internal.h"
+#include "solver.h"
+
+namespace wdmg {
+
+// ---------------------------------------------------------------------------
+// memory
+void* dev_alloc(Ctx& c, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  void* p = nullptr;
+  if (c.alloc.alloc) {
+    p = c.alloc.alloc(bytes, c.alloc.user);
+    if (!p) throw Error(WDMG_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  } else {
+    if (hipMalloc(&p, bytes) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      throw Error(WDMG_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+  }
+  c.bufs.push_back(Buf{p, bytes});
+  return p;
+}
+
+void dev_free(Ctx& c, void* p) {
+  if (!p) return;
+  for (size_t i = 0; i < c.bufs.size(); ++i) {
+    if (c.bufs[i].p == p) {
+      c.bufs.erase(c.bufs.begin() + i);
+      break;
+    }
+  }
+  if (c.alloc.free)
+    c.alloc.free(p, c.alloc.user);
+  else
+    (void)hipFree(p);
+}
+
+void ensure_io(Ctx& c, size_t bytes) {
+  if (bytes <= c.io_bytes) return;
+  WDMG_HIP(hipStreamSynchronize(c.stream));
+  dev_free(c, c.io_a);
+  dev_free(c, c.io_b);
+  c.io_a = dev_alloc(c, bytes);
+  c.io_b = dev_alloc(c, bytes);
+  c.io_bytes = bytes;
+}
+
+ProfScope::ProfScope(Ctx& ctx, int id, long long units) : c(ctx) {
+  if (!c.prof_on) return;
+  Ctx::ProfRec r{id, units, nullptr, nullptr};
+  for (hipEvent_t* e : {&r.a, &r.b}) {
+    if (!c.prof_pool.empty()) {
+      *e = c.prof_pool.back();
+      c.prof_pool.pop_back();
+    } else {
+      WDMG_HIP(hipEventCreate(e));
+    }
+  }
+  WDMG_HIP(hipEventRecord(r.a, c.stream));
+  c.prof_recs.push_back(r);
+  idx = (int)c.prof_recs.size() - 1;
+}
+
+ProfScope::~ProfScope() {
+  if (idx >= 0) (void)hipEventRecord(c.prof_recs[idx].b, c.stream);
+}
+
+void prof_collect(Ctx& c) {
+  if (c.prof_recs.empty()) return;
+  WDMG_HIP(hipStreamSynchronize(c.stream));
+  for (auto& r : c.prof_recs) {
+    float ms = 0.f;
+    WDMG_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+    c.prof_launch[r.id] += 1;
+    c.prof_units[r.id] += r.units;
+    c.prof_ms[r.id] += ms;
+    c.prof_pool.push_back(r.a);
+    c.prof_pool.push_back(r.b);
+  }
+  c.prof_recs.clear();
+}
+
+double read_scalar(Ctx& c, int slot) {
+  WDMG_HIP(hipMemcpyAsync(c.hsc, c.dsc + slot, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+  WDMG_HIP(hipStreamSynchronize(c.stream));
+  return c.hsc[0];
+}
+
+void check_flags(Ctx& c) {
+  WDMG_HIP(hipMemcpyAsync(c.hsc, c.dsc + S_ERR, 2 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+  WDMG_HIP(hipStreamSynchronize(c.stream));
+  const double nan_flag = c.hsc[0], rank_flag = c.hsc[1];
+  if (nan_flag != 0.0 || rank_flag != 0.0) {
+    set_scalar(c, S_ERR, 0.0, 0.0);
+    WDMG_HIP(hipStreamSynchronize(c.stream));
+    if (rank_flag != 0.0) throw Error(WDMG_ERR_RANK_DEFICIENT, "candidate vectors are rank deficient on an aggregate");
+    throw Error(WDMG_ERR_NAN, "NaN or Inf met in a reduction");
+  }
+}
+
+// ---------------------------------------------------------------------------
+// level helpers
+template <typename R>
+cx<R>* work(Level& L, int i);
+template <>
+cx<double>* work<double>(Level& L, int i) {
+  return L.w64[i];
+}
+template <>
+cx<float>* work<float>(Level& L, int i) {
+  return L.w32[i];
+}
+template <typename R>
+const cx<R>* vecs(const Level& L);
+template <>
+const cx<double>* vecs<double>(const Level& L) {
+  return L.V64;
+}
+template <>
+const cx<float>* vecs<float>(const Level& L) {
+  return L.V32;
+}
+template <typename R>
+const cx<R>* stencil(const Level& L);
+template <>
+const cx<double>* stencil<double>(const Level& L) {
+  return L.Dc64;
+}
+template <>
+const cx<float>* stencil<float>(const Level& L) {
+  return L.Dc32;
+}
+
+template <typename R>
+void apply_op(Ctx& c, int l, cx<R>* out, const cx<R>* in, int nrhs) {
+  if (l == 0)
+    dslash<R>(c, out, in, nrhs);
+  else
+    coarse_apply<R>(c, c.lev[l], stencil<R>(c.lev[l]), out, in, nrhs);
+}
+
+template <typename R>
+void restrict_to(Ctx& c, int l, const cx<R>* fine, cx<R>* crs, int nrhs) {
+  if (l == 0)
+    restrict0<R>(c, c.lev[0], vecs<R>(c.lev[0]), fine, crs, nrhs);
+  else
+    restrictC<R>(c, c.lev[l], vecs<R>(c.lev[l]), fine, crs, nrhs);
+}
+
+template <typename R>
+void prolong_from(Ctx& c, int l, const cx<R>* crs, cx<R>* fine, int nrhs) {
+  if (l == 0)
+    prolong0<R>(c, c.lev[0], vecs<R>(c.lev[0]), crs, fine, nrhs);
+  else
+    prolongC<R>(c, c.lev[l], vecs<R>(c.lev[l]), crs, fine, nrhs);
+}
+
+// ---------------------------------------------------------------------------
+// MR smoother (Sec. 3): p = A r; alpha = omega <p,r>/<p,p>; x += alpha r; r -= alpha p.
+template <typename R>
+void mr(Ctx& c, int l, cx<R>* x, cx<R>* r, cx<R>* p, int iters, double omega) {
+  const size_t n = c.lev[l].n;
+  for (int it = 0; it < iters; ++it) {
+    apply_op<R>(c, l, p, r, 1);
+    step_alpha<R>(c, p, r, n, omega, S_MR);
+    update2<R>(c, x, r, r, p, n, S_MR);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Coarsest solve: GCR(restart) on D_c in FP64 to relative tolerance tol_c.
+void coarsest_solve(Ctx& c, cx<double>* x, const cx<double>* b) {
+  const int l = c.nlevels - 1;
+  Level& L = c.lev[l];
+  const size_t n = L.n;
+  const int k = c.mg.coarse_restart;
+  cx<double>* r = L.w64[1];
+  cx<double>* Zb = L.basisZ;
+  cx<double>* Wb = L.basisW;
+  const int hslot = S_GCR + l * S_GCR_STRIDE, nrmslot = hslot + 2 * 128;
+  zero<double>(c, x, n);
+  copy<double>(c, r, b, n);
+  norm2<double>(c, r, n, S_RNORM + l);
+  const double bn2 = read_scalar(c, S_RNORM + l);
+  if (!(bn2 > 0.0)) {
+    if (!std::isfinite(bn2)) throw Error(WDMG_ERR_NAN, "NaN in the coarsest right-hand side");
+    return;
+  }
+  const double tol2 = c.mg.coarse_tol * c.mg.coarse_tol * bn2;
+  int it = 0;
+  while (it < c.mg.coarse_maxit) {
+    for (int j = 0; j < k && it < c.mg.coarse_maxit; ++j, ++it) {
+      cx<double>* z = Zb + (size_t)j * n;
+      cx<double>* w = Wb + (size_t)j * n;
+      copy<double>(c, z, r, n);
+      apply_op<double>(c, l, w, z, 1);
+      gcr_orth(c, Wb, Zb, w, z, n, j, hslot, nrmslot);
+      gcr_step(c, w, z, x, r, n, j, nrmslot, S_RNORM + l);
+      const double rn2 = read_scalar(c, S_RNORM + l);
+      if (!std::isfinite(rn2)) throw Error(WDMG_ERR_NAN, "NaN in the coarsest solve");
+      if (rn2 <= tol2) return;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// V-cycle M_l (Sec. 2 / Sec. 3 / Sec. 5): x = M_l b from x = 0.
+template <typename R>
+void vcycle(Ctx& c, int l, cx<R>* x, const cx<R>* b);
+
+template <typename R>
+void coarse_correction(Ctx& c, int l, const cx<R>* res, cx<R>* y) {
+  Level& C = c.lev[l + 1];
+  const size_t nc = C.n;
+  cx<R>* rc = work<R>(C, 5);
+  cx<R>* ec = work<R>(C, 6);
+  restrict_to<R>(c, l, res, rc, 1);
+  if (l + 1 == c.nlevels - 1) {
+    // coarsest level: FP64 GCR
+    if constexpr (sizeof(R) == 8) {
+      coarsest_solve(c, ec, rc);
+    } else {
+      convert<double, float>(c, C.w64[5], rc, nc);
+      coarsest_solve(c, C.w64[6], C.w64[5]);
+      convert<float, double>(c, ec, C.w64[6], nc);
+    }
+  } else {
+    // stationary iteration e <- e + M_{l+1} (r_c - D_{l+1} e) from e = 0
+    const int ncyc = c.mg.coarse_cycles > 0 ? c.mg.coarse_cycles : 1;
+    cx<R>* t = work<R>(C, 7);
+    cx<R>* xo = work<R>(C, 0);
+    vcycle<R>(c, l + 1, xo, rc);
+    copy<R>(c, ec, xo, nc);
+    for (int it = 1; it < ncyc; ++it) {
+      apply_op<R>(c, l + 1, t, ec, 1);
+      xmy<R>(c, rc, t, nc);
+      vcycle<R>(c, l + 1, xo, t);
+      add<R>(c, ec, xo, nc);
+    }
+  }
+  prolong_from<R>(c, l, ec, y, 1);
+}
+
+template <typename R>
+void vcycle(Ctx& c, int l, cx<R>* x, const cx<R>* b) {
+  Level& L = c.lev[l];
+  const size_t n = L.n;
+  cx<R>* res = work<R>(L, 1);
+  cx<R>* p = work<R>(L, 2);
+  cx<R>* y = work<R>(L, 3);
+  cx<R>* dy = work<R>(L, 4);
+  zero<R>(c, x, n);
+  copy<R>(c, res, b, n);
+  mr<R>(c, l, x, res, p, c.mg.nu_pre, c.mg.omega);
+  coarse_correction<R>(c, l, res, y);
+  apply_op<R>(c, l, dy, y, 1);
+  if (c.mg.use_alpha)
+    step_alpha<R>(c, dy, res, n, 1.0, S_MR);
+  else
+    set_scalar(c, S_MR, 1.0, 0.0);
+  update2<R>(c, x, y, res, dy, n, S_MR);
+  mr<R>(c, l, x, res, p, c.mg.nu_post, c.mg.omega);
+}
+
+#define INST(R)                                                                \
+  template void vcycle<R>(Ctx&, int, cx<R>*, const cx<R>*);                   \
+  template void apply_op<R>(Ctx&, int, cx<R>*, const cx<R>*, int);            \
+  template void restrict_to<R>(Ctx&, int, const cx<R>*, cx<R>*, int);         \
+  template void prolong_from<R>(Ctx&, int, const cx<R>*, cx<R>*, int);        \
+  template void mr<R>(Ctx&, int, cx<R>*, cx<R>*, cx<R>*, int, double);
+INST(double)
+INST(float)
+#undef INST
+
+// ---------------------------------------------------------------------------
+// Outer flexible GCR(k) in FP64 (Sec. 5) for one right-hand side held in
+// internal layout: b (input), x (initial guess, output).
+int fgcr(Ctx& c, cx<double>* x, const cx<double>* b, const wdmg_solve_params& p, wdmg_solve_stats& st) {
+  Level& L = c.lev[0];
+  const size_t n = L.n;
+  const int k = p.restart;
+  ensure_outer(c, k, p.precond && p.mg_prec == WDMG_F32);
+  cx<double>* r = c.outer_r;
+  cx<double>* Zb = c.outer_Z;
+  cx<double>* Wb = c.outer_W;
+  const int hslot = S_GCR + 3 * S_GCR_STRIDE, nrmslot = hslot + 2 * 128;
+  set_scalar(c, S_ERR, 0.0, 0.0);
+  norm2<double>(c, b, n, S_TMP + 4);
+  const double bn2 = read_scalar(c, S_TMP + 4);
+  if (!std::isfinite(bn2)) throw Error(WDMG_ERR_NAN, "NaN or Inf in the right-hand side");
+  st.iters = 0;
+  st.restarts = 0;
+  st.converged = 0;
+  if (bn2 == 0.0) {
+    zero<double>(c, x, n);
+    st.converged = 1;
+    st.true_res = 0.0;
+    return WDMG_OK;
+  }
+  const double tol2 = p.tol * p.tol * bn2;
+  // r = b - D x
+  dslash<double>(c, r, x, 1);
+  xmy_norm(c, b, r, n, S_RNORM);
+  double rn2 = read_scalar(c, S_RNORM);
+  while (true) {
+    if (rn2 <= tol2) {
+      st.converged = 1;
+      break;
+    }
+    if (st.iters >= p.maxit) break;
+    for (int j = 0; j < k && st.iters < p.maxit; ++j) {
+      cx<double>* z = Zb + (size_t)j * n;
+      cx<double>* w = Wb + (size_t)j * n;
+      if (p.precond) {
+        if (p.mg_prec == WDMG_F32) {
+          convert<float, double>(c, c.outer_r32, r, n);
+          vcycle<float>(c, 0, c.outer_z32, c.outer_r32);
+          convert<double, float>(c, z, c.outer_z32, n);
+        } else {
+          vcycle<double>(c, 0, z, r);
+        }
+      } else {
+        copy<double>(c, z, r, n);
+      }
+      dslash<double>(c, w, z, 1);
+      gcr_orth(c, Wb, Zb, w, z, n, j, hslot, nrmslot);
+      gcr_step(c, w, z, x, r, n, j, nrmslot, S_RNORM);
+      ++st.iters;
+      rn2 = read_scalar(c, S_RNORM);
+      if (!std::isfinite(rn2)) throw Error(WDMG_ERR_NAN, "NaN in the outer solve");
+      if (rn2 <= tol2) break;
+    }
+    // restart (or claimed convergence): recompute the true residual in FP64
+    dslash<double>(c, r, x, 1);
+    xmy_norm(c, b, r, n, S_RNORM);
+    rn2 = read_scalar(c, S_RNORM);
+    if (rn2 <= tol2) {
+      st.converged = 1;
+      break;
+    }
+    ++st.restarts;
+  }
+  st.true_res = std::sqrt(rn2 / bn2);
+  check_flags(c);
+  return st.converged ? WDMG_OK : WDMG_NOT_CONVERGED;
+}
+
+// ---------------------------------------------------------------------------
+// BiCGStab (van der Vorst 1992), FP64, x = 0 start (Sec. 5 comparator).
+int bicgstab(Ctx& c, cx<double>* x, const cx<double>* b, double tol, int maxit, wdmg_solve_stats& st) {
+  const size_t n = c.lev[0].n;
+  ensure_bicg(c);
+  cx<double>* r = c.bicg[0];
+  cx<double>* rhat = c.bicg[1];
+  cx<double>* p = c.bicg[2];
+  cx<double>* v = c.bicg[3];
+  cx<double>* s = c.bicg[4];
+  cx<double>* t = c.bicg[5];
+  set_scalar(c, S_ERR, 0.0, 0.0);
+  norm2<double>(c, b, n, S_TMP + 4);
+  const double bn2 = read_scalar(c, S_TMP + 4);
+  if (!std::isfinite(bn2)) throw Error(WDMG_ERR_NAN, "NaN or Inf in the right-hand side");
+  st.iters = 0;
+  st.restarts = 0;
+  st.converged = 0;
+  zero<double>(c, x, n);
+  if (bn2 == 0.0) {
+    st.converged = 1;
+    st.true_res = 0.0;
+    return WDMG_OK;
+  }
+  const double tol2 = tol * tol * bn2;
+  copy<double>(c, r, b, n);
+  const int check_every = 8;
+  double rn2 = bn2;
+  while (st.iters < maxit) {
+    copy<double>(c, rhat, r, n);
+    dot<double>(c, rhat, r, n, S_BICG + 0);  // rho_new
+    set_scalar(c, S_BICG + 6, 1.0, 0.0);     // omega
+    bool first = true;
+    int since = 0;
+    bool breakdown = false;
+    while (st.iters < maxit) {
+      bicg_p(c, p, r, v, n, first);
+      first = false;
+      dslash<double>(c, v, p, 1);
+      bicg_alpha(c, rhat, v, n);
+      bicg_s(c, s, r, v, n);
+      dslash<double>(c, t, s, 1);
+      bicg_omega(c, t, s, n);
+      bicg_xr(c, x, r, p, s, t, rhat, n);
+      ++st.iters;
+      if (++since >= check_every || st.iters >= maxit) {
+        since = 0;
+        WDMG_HIP(hipMemcpyAsync(c.hsc, c.dsc + S_BICG, 10 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+        WDMG_HIP(hipStreamSynchronize(c.stream));
+        rn2 = c.hsc[8];
+        if (!std::isfinite(rn2)) throw Error(WDMG_ERR_NAN, "NaN in BiCGStab");
+        if (rn2 <= tol2) break;
+        if (c.hsc[0] == 0.0 && c.hsc[1] == 0.0) {
+          breakdown = true;
+          break;
+        }
+      }
+    }
+    // true residual
+    dslash<double>(c, r, x, 1);
+    xmy_norm(c, b, r, n, S_RNORM);
+    rn2 = read_scalar(c, S_RNORM);
+    if (rn2 <= tol2) {
+      st.converged = 1;
+      break;
+    }
+    (void)breakdown;
+    ++st.restarts;
+  }
+  st.true_res = std::sqrt(rn2 / bn2);
+  check_flags(c);
+  return st.converged ? WDMG_OK : WDMG_NOT_CONVERGED;
+}
+
+// ---------------------------------------------------------------------------
+// Adaptive setup (Sec. 2): relax the starting vectors on A v = 0, block QR,
+// Galerkin coarse operator; recursively.
+void free_hierarchy(Ctx& c) {
+  WDMG_HIP(hipStreamSynchronize(c.stream));
+  for (int l = 0; l < WDMG_MAX_LEVELS; ++l) {
+    Level& L = c.lev[l];
+    dev_free(c, L.V64);
+    dev_free(c, L.V32);
+    dev_free(c, L.Dc64);
+    dev_free(c, L.Dc32);
+    for (int i = 0; i < kWork; ++i) {
+      if (l > 0) {
+        dev_free(c, L.w64[i]);
+        dev_free(c, L.w32[i]);
+      }
+    }
+    dev_free(c, L.basisZ);
+    dev_free(c, L.basisW);
+    Level blank;
+    if (l == 0) {
+      // level 0 work vectors are owned by the context's fine pool
+      for (int i = 0; i < kWork; ++i) {
+        blank.w64[i] = L.w64[i];
+        blank.w32[i] = L.w32[i];
+      }
+    }
+    L = blank;
+  }
+  c.have_mg = false;
+  c.nlevels = 0;
+}
+
+static void relax(Ctx& c, int l, const wdmg_level_params& lp, double omega) {
+  Level& F = c.lev[l];
+  const size_t n = F.n;
+  const int nv = lp.nv;
+  const int kb = nv < 8 ? nv : 8;
+  cx<double>* R = static_cast<cx<double>*>(dev_alloc(c, (size_t)kb * n * sizeof(cx<double>)));
+  cx<double>* P = static_cast<cx<double>*>(dev_alloc(c, (size_t)kb * n * sizeof(cx<double>)));
+  for (int k0 = 0; k0 < nv; k0 += kb) {
+    const int nb = (nv - k0) < kb ? (nv - k0) : kb;
+    cx<double>* X = F.V64 + (size_t)k0 * n;
+    // r = 0 - A x
+    apply_op<double>(c, l, R, X, nb);
+    for (int q = 0; q < nb; ++q) neg<double>(c, R + (size_t)q * n, n);
+    for (int it = 0; it < lp.setup_iters; ++it) {
+      apply_op<double>(c, l, P, R, nb);
+      for (int q = 0; q < nb; ++q) {
+        cx<double>* x = X + (size_t)q * n;
+        cx<double>* r = R + (size_t)q * n;
+        cx<double>* p = P + (size_t)q * n;
+        step_alpha<double>(c, p, r, n, omega, S_MR);
+        update2<double>(c, x, r, r, p, n, S_MR);
+      }
+    }
+  }
+  WDMG_HIP(hipStreamSynchronize(c.stream));
+  dev_free(c, R);
+  dev_free(c, P);
+}
+
+void mg_setup(Ctx& c, const wdmg_mg_params& p) {
+  if (!c.have_gauge) throw Error(WDMG_ERR_NOT_SETUP, "set the gauge field before the multigrid setup");
+  if (p.n_levels < 2 || p.n_levels > WDMG_MAX_LEVELS - 1)
+    throw Error(WDMG_ERR_ARG, "n_levels must be 2 or 3");
+  if (!(p.omega > 0.0 && p.omega < 2.0)) throw Error(WDMG_ERR_ARG, "omega must lie in (0, 2)");
+  if (p.nu_pre < 0 || p.nu_post < 0 || p.coarse_maxit < 1 || p.coarse_restart < 1 || p.coarse_restart > 128 ||
+      !(p.coarse_tol > 0.0))
+    throw Error(WDMG_ERR_ARG, "bad cycle parameters");
+  // validate geometry of every level before allocating
+  int dims[4];
+  std::memcpy(dims, c.dims, sizeof(dims));
+  for (int l = 0; l < p.n_levels - 1; ++l) {
+    const wdmg_level_params& lp = p.level[l];
+    if (lp.nv < 1 || lp.nv > 32) throw Error(WDMG_ERR_ARG, "nv must be in 1..32");
+    if (lp.setup_iters < 0) throw Error(WDMG_ERR_ARG, "setup_iters must be >= 0");
+    if (!lp.vectors) throw Error(WDMG_ERR_ARG, "starting vectors are required for every level");
+    int bvol = 1;
+    for (int mu = 0; mu < 4; ++mu) {
+      if (lp.block[mu] < 1 || dims[mu] % lp.block[mu] != 0)
+        throw Error(WDMG_ERR_DIMS, "aggregate extents must divide the level's extents");
+      bvol *= lp.block[mu];
+      dims[mu] /= lp.block[mu];
+    }
+    const int dof = l == 0 ? 12 : 2 * p.level[l - 1].nv;
+    if (bvol * dof / 2 < lp.nv) throw Error(WDMG_ERR_DIMS, "aggregate too small for nv vectors");
+  }
+  free_hierarchy(c);
+  set_scalar(c, S_ERR, 0.0, 0.0);
+  c.mg = p;
+  c.nlevels = p.n_levels;
+  c.setup_mass = c.mass;
+  // level 0
+  {
+    Level& L = c.lev[0];
+    L.l = 0;
+    std::memcpy(L.dims, c.dims, sizeof(L.dims));
+    L.g = c.g0;
+    L.nsite = c.g0.vol;
+    L.dof = 12;
+    L.n = (size_t)L.nsite * 12;
+  }
+  for (int l = 0; l < p.n_levels - 1; ++l) {
+    const wdmg_level_params& lp = p.level[l];
+    Level& F = c.lev[l];
+    Level& C = c.lev[l + 1];
+    std::memcpy(F.block, lp.block, sizeof(F.block));
+    F.nv = lp.nv;
+    F.V64 = static_cast<cx<double>*>(dev_alloc(c, (size_t)lp.nv * F.n * sizeof(cx<double>)));
+    F.V32 = static_cast<cx<float>*>(dev_alloc(c, (size_t)lp.nv * F.n * sizeof(cx<float>)));
+    const cx<double>* src = static_cast<const cx<double>*>(lp.vectors);
+    if (l == 0)
+      fine_to_internal<double, double>(c, F.g, src, F.V64, lp.nv);
+    else
+      copy<double>(c, F.V64, src, (size_t)lp.nv * F.n);
+    if (lp.setup_iters > 0) relax(c, l, lp, p.omega);
+    if (l == 0)
+      block_qr0(c, F, F.V64);
+    else
+      block_qrC(c, F, F.V64);
+    check_flags(c);
+    convert<float, double>(c, F.V32, F.V64, (size_t)lp.nv * F.n);
+    // coarse level geometry
+    C.l = l + 1;
+    int one[4] = {1, 1, 1, 1};
+    for (int mu = 0; mu < 4; ++mu) C.dims[mu] = F.dims[mu] / lp.block[mu];
+    C.g = make_geom(C.dims, one);
+    C.nsite = C.g.vol;
+    C.dof = 2 * lp.nv;
+    C.n = (size_t)C.nsite * C.dof;
+    const size_t dcn = (size_t)C.nsite * 9 * C.dof * C.dof;
+    C.Dc64 = static_cast<cx<double>*>(dev_alloc(c, dcn * sizeof(cx<double>)));
+    C.Dc32 = static_cast<cx<float>*>(dev_alloc(c, dcn * sizeof(cx<float>)));
+    if (l == 0)
+      coarse_build0(c, F, C);
+    else
+      coarse_buildC(c, F, C);
+    convert<float, double>(c, C.Dc32, C.Dc64, dcn);
+    for (int i = 0; i < kWork; ++i) {
+      C.w64[i] = static_cast<cx<double>*>(dev_alloc(c, C.n * sizeof(cx<double>)));
+      C.w32[i] = static_cast<cx<float>*>(dev_alloc(c, C.n * sizeof(cx<float>)));
+    }
+  }
+  // coarsest GCR basis
+  {
+    Level& L = c.lev[p.n_levels - 1];
+    L.basisZ = static_cast<cx<double>*>(dev_alloc(c, (size_t)p.coarse_restart * L.n * sizeof(cx<double>)));
+    L.basisW = static_cast<cx<double>*>(dev_alloc(c, (size_t)p.coarse_restart * L.n * sizeof(cx<double>)));
+  }
+  ensure_fine_work(c);
+  WDMG_HIP(hipStreamSynchronize(c.stream));
+  check_flags(c);
+  c.have_mg = true;
+}
+
+void ensure_fine_work(Ctx& c) {
+  Level& L = c.lev[0];
+  if (L.w64[0]) return;
+  const size_t n = (size_t)c.g0.vol * 12;
+  for (int i = 0; i < kWork; ++i) {
+    L.w64[i] = static_cast<cx<double>*>(dev_alloc(c, n * sizeof(cx<double>)));
+    L.w32[i] = static_cast<cx<float>*>(dev_alloc(c, n * sizeof(cx<float>)));
+  }
+}
+
+void ensure_outer(Ctx& c, int k, bool need32) {
+  const size_t n = (size_t)c.g0.vol * 12;
+  if (k > c.outer_k) {
+    WDMG_HIP(hipStreamSynchronize(c.stream));
+    dev_free(c, c.outer_Z);
+    dev_free(c, c.outer_W);
+    c.outer_Z = static_cast<cx<double>*>(dev_alloc(c, (size_t)k * n * sizeof(cx<double>)));
+    c.outer_W = static_cast<cx<double>*>(dev_alloc(c, (size_t)k * n * sizeof(cx<double>)));
+    c.outer_k = k;
+  }
+  if (!c.outer_r) c.outer_r = static_cast<cx<double>*>(dev_alloc(c, n * sizeof(cx<double>)));
+  if (need32 && !c.outer_r32) {
+    c.outer_r32 = static_cast<cx<float>*>(dev_alloc(c, n * sizeof(cx<float>)));
+    c.outer_z32 = static_cast<cx<float>*>(dev_alloc(c, n * sizeof(cx<float>)));
+  }
+}
+
+void ensure_bicg(Ctx& c) {
+  if (c.bicg[0]) return;
+  const size_t n = (size_t)c.g0.vol * 12;
+  for (int i = 0; i < 6; ++i) c.bicg[i] = static_cast<cx<double>*>(dev_alloc(c, n * sizeof(cx<double>)));
+}
+
+}  // namespace wdmg

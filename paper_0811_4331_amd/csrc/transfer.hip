@@ -1,0 +1,316 @@
+// Restriction P^dagger, prolongation P and the FP64 block orthonormalisation
+// that builds P (Sec. 2: P V_c = V, P^dagger P = I through a QR of the
+// aggregated candidates; Sec. 3: geometric aggregates with chirality kept
+// intact, so R = P^dagger).
+//
+// P is stored as its Nv orthonormal block columns laid out like Nv fields of
+// the finer level; the column (xhat, chi, k) is field k restricted to the
+// aggregate xhat and to the dofs of chirality chi.  A coarse field is
+// [rhs][xhat][chi * Nv + k].
+//
+// Level 0 fields are [12][V] over tile-major sites; chirality chi owns the
+// components 6 chi .. 6 chi + 5.  Level >= 1 fields are [site][dof] with the
+// two chiralities as the two halves of dof.
+#include "internal.h"
+
+namespace wdmg {
+namespace {
+
+constexpr int KC = 8;  // coarse columns reduced per block-wide sum
+
+// Sites of aggregate `agg` of a level with geometry g and aggregate block b.
+struct AggMap {
+  Geom g;
+  int b[4];
+  int nb[4];   // aggregates per direction
+  int bvol;
+  __device__ __forceinline__ int site(int agg, int l) const {
+    int a[4], lc[4];
+    int t = agg;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+      a[mu] = t % nb[mu];
+      t /= nb[mu];
+    }
+    int u = l;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+      lc[mu] = u % b[mu];
+      u /= b[mu];
+    }
+    return site_of(g, a[0] * b[0] + lc[0], a[1] * b[1] + lc[1], a[2] * b[2] + lc[2], a[3] * b[3] + lc[3]);
+  }
+  __device__ __forceinline__ int agg_of(int s) const {
+    int c[4];
+    coords_of(g, s, c);
+    return (c[0] / b[0]) + nb[0] * ((c[1] / b[1]) + nb[1] * ((c[2] / b[2]) + nb[2] * (c[3] / b[3])));
+  }
+};
+
+AggMap make_map(const Level& f) {
+  AggMap m;
+  m.g = f.g;
+  m.bvol = 1;
+  for (int mu = 0; mu < 4; ++mu) {
+    m.b[mu] = f.block[mu];
+    m.nb[mu] = f.dims[mu] / f.block[mu];
+    m.bvol *= f.block[mu];
+  }
+  return m;
+}
+
+// Row accessors: row r of the (aggregate, chirality) block -> element offset.
+struct Rows0 {  // level 0: r = m * bvol + l, m in 0..5 (component within chirality)
+  AggMap map;
+  size_t V;
+  int nrows() const { return map.bvol * 6; }
+  __device__ __forceinline__ size_t off(int agg, int chi, int r) const {
+    const int m = r / map.bvol, l = r - m * map.bvol;
+    return (size_t)(6 * chi + m) * V + map.site(agg, l);
+  }
+};
+struct RowsC {  // level >= 1: r = d * bvol + l, d in 0..half-1
+  AggMap map;
+  int dof;
+  int nrows() const { return map.bvol * (dof / 2); }
+  __device__ __forceinline__ size_t off(int agg, int chi, int r) const {
+    const int d = r / map.bvol, l = r - d * map.bvol;
+    return (size_t)map.site(agg, l) * dof + chi * (dof / 2) + d;
+  }
+};
+
+// ---- restriction: one workgroup per (aggregate, rhs) ----------------------
+template <typename R, class Rows>
+__global__ __launch_bounds__(256) void k_restrict(Rows rows, int nrows, const cx<R>* __restrict__ Vv, size_t vstride,
+                                                  const cx<R>* __restrict__ in, size_t fstride, cx<R>* __restrict__ out,
+                                                  int nagg, int nv) {
+  __shared__ double lds[4 * KC * 4];
+  const int agg = blockIdx.x, rhs = blockIdx.y;
+  in += (size_t)rhs * fstride;
+  out += ((size_t)rhs * nagg + agg) * 2 * nv;
+  for (int k0 = 0; k0 < nv; k0 += KC) {
+    double v[4 * KC];
+#pragma unroll
+    for (int q = 0; q < 4 * KC; ++q) v[q] = 0.0;
+    for (int chi = 0; chi < 2; ++chi) {
+      for (int r = threadIdx.x; r < nrows; r += blockDim.x) {
+        const size_t o = rows.off(agg, chi, r);
+        const cx<R> f = in[o];
+#pragma unroll
+        for (int q = 0; q < KC; ++q) {
+          if (k0 + q < nv) {
+            const cx<R> w = Vv[(size_t)(k0 + q) * vstride + o];
+            v[4 * q + 2 * chi] += (double)w.re * f.re + (double)w.im * f.im;
+            v[4 * q + 2 * chi + 1] += (double)w.re * f.im - (double)w.im * f.re;
+          }
+        }
+      }
+    }
+    block_sum<4 * KC>(v, lds);
+    if (threadIdx.x == 0) {
+      for (int q = 0; q < KC && k0 + q < nv; ++q) {
+        out[k0 + q] = mk<R>((R)v[4 * q], (R)v[4 * q + 1]);
+        out[nv + k0 + q] = mk<R>((R)v[4 * q + 2], (R)v[4 * q + 3]);
+      }
+    }
+  }
+}
+
+// ---- prolongation: one thread per (row of a finer-level field) ------------
+template <typename R>
+__global__ __launch_bounds__(256) void k_prolong0(AggMap map, const cx<R>* __restrict__ Vv, const cx<R>* __restrict__ in,
+                                                  cx<R>* __restrict__ out, int nagg, int nv) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  const int rhs = blockIdx.y;
+  const size_t V = map.g.vol;
+  if (s >= (int)V) return;
+  const int agg = map.agg_of(s);
+  const cx<R>* ec = in + ((size_t)rhs * nagg + agg) * 2 * nv;
+  cx<R> acc[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[k] = mk<R>(0, 0);
+  for (int k = 0; k < nv; ++k) {
+    const cx<R> e0 = ec[k], e1 = ec[nv + k];
+    const cx<R>* vk = Vv + (size_t)k * 12 * V + s;
+#pragma unroll
+    for (int m = 0; m < 6; ++m) cmadd(acc[m], vk[(size_t)m * V], e0);
+#pragma unroll
+    for (int m = 6; m < 12; ++m) cmadd(acc[m], vk[(size_t)m * V], e1);
+  }
+  cx<R>* o = out + (size_t)rhs * 12 * V + s;
+#pragma unroll
+  for (int m = 0; m < 12; ++m) o[(size_t)m * V] = acc[m];
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_prolongC(AggMap map, int dof, const cx<R>* __restrict__ Vv,
+                                                  const cx<R>* __restrict__ in, cx<R>* __restrict__ out, int nagg,
+                                                  int nv) {
+  const size_t nsite = map.g.vol;
+  const size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  const int rhs = blockIdx.y;
+  if (idx >= nsite * dof) return;
+  const int s = (int)(idx / dof), e = (int)(idx % dof);
+  const int chi = e >= dof / 2;
+  const int agg = map.agg_of(s);
+  const cx<R>* ec = in + ((size_t)rhs * nagg + agg) * 2 * nv + chi * nv;
+  const size_t vstride = nsite * dof;
+  cx<R> acc = mk<R>(0, 0);
+  for (int k = 0; k < nv; ++k) cmadd(acc, Vv[(size_t)k * vstride + idx], ec[k]);
+  out[(size_t)rhs * vstride + idx] = acc;
+}
+
+// ---- block orthonormalisation (FP64): CGS with a second pass --------------
+// One workgroup per (aggregate, chirality); column j is orthogonalised
+// against columns 0..j-1 twice, then normalised by its (real, positive) norm,
+// which makes diag(R) real positive and Q unique.
+template <class Rows>
+__global__ __launch_bounds__(256) void k_block_qr(Rows rows, int nrows, cx<double>* Vv, size_t vstride, int nv,
+                                                  double* dsc) {
+  __shared__ double lds[2 * KC * 4];
+  __shared__ double coef[2 * 64];
+  __shared__ double scal;
+  const int agg = blockIdx.x, chi = blockIdx.y;
+  for (int j = 0; j < nv; ++j) {
+    cx<double>* vj = Vv + (size_t)j * vstride;
+    double n0[1] = {0.0};
+    for (int r = threadIdx.x; r < nrows; r += blockDim.x) {
+      const cx<double> a = vj[rows.off(agg, chi, r)];
+      n0[0] += a.re * a.re + a.im * a.im;
+    }
+    block_sum<1>(n0, lds);
+    if (threadIdx.x == 0) scal = sqrt(n0[0]);
+    __syncthreads();
+    const double norm0 = scal;
+    __syncthreads();
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int i0 = 0; i0 < j; i0 += KC) {
+        double v[2 * KC];
+#pragma unroll
+        for (int q = 0; q < 2 * KC; ++q) v[q] = 0.0;
+        for (int r = threadIdx.x; r < nrows; r += blockDim.x) {
+          const size_t o = rows.off(agg, chi, r);
+          const cx<double> a = vj[o];
+#pragma unroll
+          for (int q = 0; q < KC; ++q) {
+            if (i0 + q < j) {
+              const cx<double> b = Vv[(size_t)(i0 + q) * vstride + o];
+              v[2 * q] += b.re * a.re + b.im * a.im;
+              v[2 * q + 1] += b.re * a.im - b.im * a.re;
+            }
+          }
+        }
+        block_sum<2 * KC>(v, lds);
+        if (threadIdx.x == 0) {
+          for (int q = 0; q < 2 * KC; ++q) coef[2 * i0 + q] = v[q];
+        }
+        __syncthreads();
+      }
+      for (int r = threadIdx.x; r < nrows; r += blockDim.x) {
+        const size_t o = rows.off(agg, chi, r);
+        cx<double> a = vj[o];
+        for (int i = 0; i < j; ++i) a = a - mk(coef[2 * i], coef[2 * i + 1]) * Vv[(size_t)i * vstride + o];
+        vj[o] = a;
+      }
+      __syncthreads();
+    }
+    double n1[1] = {0.0};
+    for (int r = threadIdx.x; r < nrows; r += blockDim.x) {
+      const cx<double> a = vj[rows.off(agg, chi, r)];
+      n1[0] += a.re * a.re + a.im * a.im;
+    }
+    block_sum<1>(n1, lds);
+    if (threadIdx.x == 0) {
+      const double nr = sqrt(n1[0]);
+      if (!(nr > 1e-12 * norm0)) dsc[S_ERR + 1] = 1.0;  // rank lost (or NaN)
+      scal = nr > 0.0 ? 1.0 / nr : 0.0;
+    }
+    __syncthreads();
+    const double inv = scal;
+    for (int r = threadIdx.x; r < nrows; r += blockDim.x) {
+      const size_t o = rows.off(agg, chi, r);
+      const cx<double> a = vj[o];
+      vj[o] = mk(a.re * inv, a.im * inv);
+    }
+    __syncthreads();
+  }
+}
+
+inline int nagg_of(const Level& f) {
+  int n = 1;
+  for (int mu = 0; mu < 4; ++mu) n *= f.dims[mu] / f.block[mu];
+  return n;
+}
+
+inline int tpb_for(int nrows) {
+  int t = ((nrows + 63) / 64) * 64;
+  return t > 256 ? 256 : t;
+}
+
+}  // namespace
+
+template <typename R>
+void restrict0(Ctx& c, const Level& f, const cx<R>* V, const cx<R>* in, cx<R>* out, int nrhs) {
+  Rows0 rows{make_map(f), (size_t)f.nsite};
+  const int nrows = rows.nrows();
+  const int nagg = nagg_of(f);
+  ProfScope ps(c, sizeof(R) == 8 ? WDMG_K_RESTRICT_F64 : WDMG_K_RESTRICT_F32, (long long)f.nsite * nrhs);
+  hipLaunchKernelGGL((k_restrict<R, Rows0>), dim3(nagg, nrhs), dim3(tpb_for(nrows)), 0, c.stream, rows, nrows, V,
+                     f.n, in, f.n, out, nagg, f.nv);
+  WDMG_HIP(hipGetLastError());
+}
+
+template <typename R>
+void restrictC(Ctx& c, const Level& f, const cx<R>* V, const cx<R>* in, cx<R>* out, int nrhs) {
+  RowsC rows{make_map(f), f.dof};
+  const int nrows = rows.nrows();
+  const int nagg = nagg_of(f);
+  hipLaunchKernelGGL((k_restrict<R, RowsC>), dim3(nagg, nrhs), dim3(tpb_for(nrows)), 0, c.stream, rows, nrows, V,
+                     f.n, in, f.n, out, nagg, f.nv);
+  WDMG_HIP(hipGetLastError());
+}
+
+template <typename R>
+void prolong0(Ctx& c, const Level& f, const cx<R>* V, const cx<R>* in, cx<R>* out, int nrhs) {
+  const AggMap map = make_map(f);
+  ProfScope ps(c, sizeof(R) == 8 ? WDMG_K_PROLONG_F64 : WDMG_K_PROLONG_F32, (long long)f.nsite * nrhs);
+  hipLaunchKernelGGL((k_prolong0<R>), dim3((f.nsite + 255) / 256, nrhs), dim3(256), 0, c.stream, map, V, in, out,
+                     nagg_of(f), f.nv);
+  WDMG_HIP(hipGetLastError());
+}
+
+template <typename R>
+void prolongC(Ctx& c, const Level& f, const cx<R>* V, const cx<R>* in, cx<R>* out, int nrhs) {
+  const AggMap map = make_map(f);
+  hipLaunchKernelGGL((k_prolongC<R>), dim3((unsigned)((f.n + 255) / 256), nrhs), dim3(256), 0, c.stream, map, f.dof,
+                     V, in, out, nagg_of(f), f.nv);
+  WDMG_HIP(hipGetLastError());
+}
+
+void block_qr0(Ctx& c, const Level& f, cx<double>* V) {
+  Rows0 rows{make_map(f), (size_t)f.nsite};
+  const int nrows = rows.nrows();
+  ProfScope ps(c, WDMG_K_BLOCK_QR, (long long)nagg_of(f) * 2);
+  hipLaunchKernelGGL((k_block_qr<Rows0>), dim3(nagg_of(f), 2), dim3(tpb_for(nrows)), 0, c.stream, rows, nrows, V, f.n,
+                     f.nv, c.dsc);
+  WDMG_HIP(hipGetLastError());
+}
+
+void block_qrC(Ctx& c, const Level& f, cx<double>* V) {
+  RowsC rows{make_map(f), f.dof};
+  const int nrows = rows.nrows();
+  hipLaunchKernelGGL((k_block_qr<RowsC>), dim3(nagg_of(f), 2), dim3(tpb_for(nrows)), 0, c.stream, rows, nrows, V, f.n,
+                     f.nv, c.dsc);
+  WDMG_HIP(hipGetLastError());
+}
+
+#define INST(R)                                                                                 \
+  template void restrict0<R>(Ctx&, const Level&, const cx<R>*, const cx<R>*, cx<R>*, int);     \
+  template void restrictC<R>(Ctx&, const Level&, const cx<R>*, const cx<R>*, cx<R>*, int);     \
+  template void prolong0<R>(Ctx&, const Level&, const cx<R>*, const cx<R>*, cx<R>*, int);      \
+  template void prolongC<R>(Ctx&, const Level&, const cx<R>*, const cx<R>*, cx<R>*, int);
+INST(double)
+INST(float)
+#undef INST
+
+}  // namespace wdmg

@@ -1,0 +1,60 @@
+"""CPU checks of the C-ABI library: it loads and exports every declared symbol."""
+import ctypes
+import os
+import subprocess
+
+from paper_0811_4331_amd import wdmg
+
+
+def test_header_declares_the_boundary():
+    syms = wdmg.header_symbols()
+    for name in ("wdmg_create", "wdmg_destroy", "wdmg_set_gauge", "wdmg_set_mass", "wdmg_apply_D",
+                 "wdmg_mg_setup", "wdmg_apply_Dc", "wdmg_restrict", "wdmg_prolong", "wdmg_smooth",
+                 "wdmg_solve", "wdmg_solve_bicgstab", "wdmg_get_prolongator", "wdmg_last_error"):
+        assert name in syms
+
+
+def test_library_exports_every_declared_symbol():
+    lib = wdmg.load()
+    for name in wdmg.header_symbols():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", wdmg.LIB_PATH], capture_output=True, text=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if " T " in ln}
+    assert set(wdmg.header_symbols()) <= exported
+
+
+def test_default_params_are_the_papers_constants():
+    lib = wdmg.load()
+    p = wdmg.MgParams()
+    lib.wdmg_default_mg_params(ctypes.byref(p))
+    assert abs(p.omega - 0.8) < 1e-15 and p.nu_pre == 2 and p.nu_post == 2 and p.coarse_cycles == 4
+    s = wdmg.SolveParams()
+    lib.wdmg_default_solve_params(ctypes.byref(s))
+    assert s.restart == 50 and s.tol == 1e-10
+
+
+def test_create_rejects_bad_dims_without_a_gpu_call():
+    lib = wdmg.load()
+    h = ctypes.c_void_p()
+    dims = (ctypes.c_int * 4)(4, 4, 1, 4)
+    assert lib.wdmg_create(ctypes.byref(h), dims, None, None) == -2
+    assert lib.wdmg_create(None, dims, None, None) == -1
+
+
+def test_struct_layouts_match_header_sizes():
+    # the C structs as the compiler lays them out, compiled here with gcc
+    src = r'''
+#include <stdio.h>
+#include "wdmg.h"
+int main(void){printf("%zu %zu %zu %zu\n", sizeof(wdmg_level_params), sizeof(wdmg_mg_params),
+ sizeof(wdmg_solve_params), sizeof(wdmg_solve_stats)); return 0;}
+'''
+    import tempfile
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "s.c")
+        exe = os.path.join(d, "s")
+        open(c, "w").write(src)
+        subprocess.run(["gcc", "-I", os.path.dirname(wdmg.HEADER), c, "-o", exe], check=True)
+        sizes = [int(v) for v in subprocess.run([exe], capture_output=True, text=True).stdout.split()]
+    assert sizes == [ctypes.sizeof(wdmg.LevelParams), ctypes.sizeof(wdmg.MgParams),
+                     ctypes.sizeof(wdmg.SolveParams), ctypes.sizeof(wdmg.SolveStats)]
