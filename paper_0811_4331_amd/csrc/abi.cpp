@@ -8,6 +8,7 @@
 #include <cstring>
 #include <new>
 
+#include "fine_field.h"
 #include "internal.h"
 #include "solver.h"
 
@@ -68,7 +69,7 @@ void fine_out(Ctx& c, const cx<R>* src, void* canon, int nrhs) {
 
 template <typename R>
 void apply_D_impl(Ctx& c, void* out, const void* in, int nrhs) {
-  const size_t n = (size_t)c.g0.vol * 12;
+  const size_t n = (size_t)c.g0.vpad * 12;
   ensure_io(c, n * nrhs * sizeof(cx<R>));
   cx<R>* a = static_cast<cx<R>*>(c.io_a);
   cx<R>* b = static_cast<cx<R>*>(c.io_b);
@@ -117,6 +118,7 @@ template <typename R>
 void smooth_impl(Ctx& c, int level, void* x, const void* b, int nrhs, int iters) {
   Level& L = c.lev[level];
   const size_t n = L.n;
+  const size_t ncan = level == 0 ? (size_t)c.g0.vol * 12 : n;  // canonical stride per rhs
   ensure_io(c, 2 * n * sizeof(cx<R>));
   cx<R>* xi = static_cast<cx<R>*>(c.io_a);
   cx<R>* ri = xi + n;
@@ -125,8 +127,8 @@ void smooth_impl(Ctx& c, int level, void* x, const void* b, int nrhs, int iters)
   const double omega = c.have_mg ? c.mg.omega : 0.8;
   for (int k = 0; k < nrhs; ++k) {
     if (level == 0) {
-      fine_in<R>(c, static_cast<const cx<R>*>(x) + (size_t)k * n, xi, 1);
-      fine_in<R>(c, static_cast<const cx<R>*>(b) + (size_t)k * n, bi, 1);
+      fine_in<R>(c, static_cast<const cx<R>*>(x) + (size_t)k * ncan, xi, 1);
+      fine_in<R>(c, static_cast<const cx<R>*>(b) + (size_t)k * ncan, bi, 1);
     } else {
       copy<R>(c, xi, static_cast<const cx<R>*>(x) + (size_t)k * n, n);
       copy<R>(c, bi, static_cast<const cx<R>*>(b) + (size_t)k * n, n);
@@ -135,14 +137,14 @@ void smooth_impl(Ctx& c, int level, void* x, const void* b, int nrhs, int iters)
     xmy<R>(c, bi, ri, n);
     mr<R>(c, level, xi, ri, p, iters, omega);
     if (level == 0)
-      fine_out<R>(c, xi, static_cast<cx<R>*>(x) + (size_t)k * n, 1);
+      fine_out<R>(c, xi, static_cast<cx<R>*>(x) + (size_t)k * ncan, 1);
     else
       copy<R>(c, static_cast<cx<R>*>(x) + (size_t)k * n, xi, n);
   }
 }
 
 void ensure_solve_io(Ctx& c) {
-  const size_t n = (size_t)c.g0.vol * 12;
+  const size_t n = (size_t)c.g0.vpad * 12;
   if (!c.sol_x) {
     c.sol_x = static_cast<cx<double>*>(dev_alloc(c, n * sizeof(cx<double>)));
     c.sol_b = static_cast<cx<double>*>(dev_alloc(c, n * sizeof(cx<double>)));
@@ -211,17 +213,14 @@ int wdmg_create(wdmg_ctx** out, const int dims[4], const wdmg_alloc* alloc, void
   }
   int rc = guarded(c, [&]() {
     c->dsc = static_cast<double*>(dev_alloc(*c, S_TOTAL * sizeof(double)));
-    c->partials = static_cast<double*>(dev_alloc(*c, 65536 * sizeof(double)));
+    c->partials = static_cast<double*>(dev_alloc(*c, (size_t)64 * kMaxReduceBlocks * 3 * sizeof(double)));
     c->counter = static_cast<unsigned*>(dev_alloc(*c, 256 * sizeof(unsigned)));
     WDMG_HIP(hipMemsetAsync(c->dsc, 0, S_TOTAL * sizeof(double), c->stream));
     WDMG_HIP(hipMemsetAsync(c->counter, 0, 256 * sizeof(unsigned), c->stream));
     WDMG_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->hsc), 64 * sizeof(double), hipHostMallocDefault));
-    c->lev[0].l = 0;
-    std::memcpy(c->lev[0].dims, dims, sizeof(c->lev[0].dims));
-    c->lev[0].g = c->g0;
-    c->lev[0].nsite = c->g0.vol;
-    c->lev[0].dof = 12;
-    c->lev[0].n = (size_t)c->g0.vol * 12;
+    WDMG_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->hring), kRing * sizeof(double), hipHostMallocDefault));
+    for (int i = 0; i < kRing; ++i) WDMG_HIP(hipEventCreateWithFlags(&c->ring_ev[i], hipEventDisableTiming));
+    init_level0(*c);
     WDMG_HIP(hipStreamSynchronize(c->stream));
     return WDMG_OK;
   });
@@ -245,6 +244,9 @@ void wdmg_destroy(wdmg_ctx* c) {
       (void)hipFree(p);
   }
   if (c->hsc) (void)hipHostFree(c->hsc);
+  if (c->hring) (void)hipHostFree(c->hring);
+  for (int i = 0; i < kRing; ++i)
+    if (c->ring_ev[i]) (void)hipEventDestroy(c->ring_ev[i]);
   for (auto& r : c->prof_recs) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
@@ -260,13 +262,19 @@ int wdmg_set_gauge(wdmg_ctx* c, const void* U, int t_bc) {
     need_ptr(U, "U");
     if (t_bc != 1 && t_bc != -1) throw Error(WDMG_ERR_ARG, "t_bc must be +1 or -1");
     if (c->have_mg) free_hierarchy(*c);
-    const size_t n = (size_t)c->g0.vol * 36;
+    const size_t n = (size_t)c->g0.vpad * kLinkComp;
     if (!c->U64) {
       c->U64 = static_cast<cx<double>*>(dev_alloc(*c, n * sizeof(cx<double>)));
       c->U32 = static_cast<cx<float>*>(dev_alloc(*c, n * sizeof(cx<float>)));
     }
+    set_scalar(*c, S_ERR + 2, 0.0, 0.0);
     gauge_import(*c, static_cast<const cx<double>*>(U), t_bc);
     c->t_bc = t_bc;
+    c->have_gauge = false;
+    if (read_scalar(*c, S_ERR + 2) != 0.0) {
+      set_scalar(*c, S_ERR + 2, 0.0, 0.0);
+      throw Error(WDMG_ERR_ARG, "links must be SU(3): third row != conj(row0 x row1) to 1e-10");
+    }
     c->have_gauge = true;
     return WDMG_OK;
   });
@@ -404,7 +412,7 @@ int wdmg_solve(wdmg_ctx* c, void* x, const void* b, int nrhs, const wdmg_solve_p
     }
     ensure_solve_io(*c);
     ensure_fine_work(*c);
-    const size_t n = (size_t)c->g0.vol * 12;
+    const size_t n = (size_t)c->g0.vol * 12;  // canonical stride per rhs
     int worst = WDMG_OK;
     for (int k = 0; k < nrhs; ++k) {
       wdmg_solve_stats st{};
@@ -435,7 +443,7 @@ int wdmg_solve_bicgstab(wdmg_ctx* c, void* x, const void* b, int nrhs, double to
     need_gauge(*c);
     if (!(tol > 0.0) || maxit < 1) throw Error(WDMG_ERR_ARG, "bad solve parameters");
     ensure_solve_io(*c);
-    const size_t n = (size_t)c->g0.vol * 12;
+    const size_t n = (size_t)c->g0.vol * 12;  // canonical stride per rhs
     int worst = WDMG_OK;
     for (int k = 0; k < nrhs; ++k) {
       wdmg_solve_stats st{};

@@ -55,6 +55,42 @@ __global__ __launch_bounds__(TPB) void k_reduce(Op op, size_t n, double* partial
   }
 }
 
+// Batched form: blockIdx.y selects one of several independent vectors; each
+// has its own partials region and last-block ticket.
+template <class Op>
+__global__ __launch_bounds__(TPB) void k_reduce_b(Op op, size_t n, double* partials, unsigned* counter) {
+  constexpr int K = Op::K;
+  __shared__ double lds[K * (TPB / 64)];
+  __shared__ bool last;
+  const int y = blockIdx.y;
+  double* part = partials + (size_t)y * kMaxReduceBlocks * K;
+  double v[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = 0.0;
+  for (size_t i = blockIdx.x * (size_t)TPB + threadIdx.x; i < n; i += (size_t)gridDim.x * TPB) op.acc(i, y, v);
+  block_sum<K>(v, lds);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) part[blockIdx.x * K + k] = v[k];
+    __threadfence();
+    last = atomicAdd(counter + y, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = 0.0;
+  for (unsigned bb = threadIdx.x; bb < gridDim.x; bb += TPB) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] += load_coherent(&part[bb * K + k]);
+  }
+  block_sum<K>(v, lds);
+  if (threadIdx.x == 0) {
+    op.fin(v, y);
+    counter[y] = 0u;
+  }
+}
+
 template <class Op>
 void run_reduce(Ctx& c, const Op& op, size_t n) {
   const unsigned nb = reduce_blocks(n);
@@ -120,6 +156,34 @@ struct DotOp {
   __device__ void fin(const double* v) const {
     dsc[slot] = v[0];
     dsc[slot + 1] = v[1];
+  }
+};
+
+// Batched MR step sizes for nb vectors a_q, b_q (stride apart).
+template <typename R>
+struct StepAlphaBatchOp {
+  static constexpr int K = 3;
+  const cx<R>* a;
+  const cx<R>* b;
+  size_t stride;
+  double scale;
+  double* dsc;
+  int slot;
+  __device__ void acc(size_t i, int y, double* v) const {
+    const cx<R> x = a[y * stride + i], z = b[y * stride + i];
+    v[0] += (double)x.re * z.re + (double)x.im * z.im;
+    v[1] += (double)x.re * z.im - (double)x.im * z.re;
+    v[2] += (double)x.re * x.re + (double)x.im * x.im;
+  }
+  __device__ void fin(const double* v, int y) const {
+    double re = 0.0, im = 0.0;
+    if (v[2] > 0.0) {
+      re = scale * v[0] / v[2];
+      im = scale * v[1] / v[2];
+    }
+    if (bad(v[0]) || bad(v[1]) || bad(v[2])) dsc[S_ERR] = 1.0;
+    dsc[slot + 2 * y] = re;
+    dsc[slot + 2 * y + 1] = im;
   }
 };
 
@@ -296,6 +360,22 @@ __global__ void k_add(cx<R>* __restrict__ y, const cx<R>* __restrict__ x, size_t
 }
 
 template <typename R>
+__global__ void k_update2_batch(cx<R>* x, const cx<R>* u, cx<R>* r, const cx<R>* v, size_t n, size_t stride,
+                                const double* s) {
+  const int y = blockIdx.y;
+  const cx<R> a = mk<R>((R)s[2 * y], (R)s[2 * y + 1]);
+  x += y * stride;
+  u += y * stride;
+  r += y * stride;
+  v += y * stride;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const cx<R> ui = u[i], vi = v[i];
+    x[i] = x[i] + a * ui;
+    r[i] = r[i] - a * vi;
+  }
+}
+
+template <typename R>
 __global__ void k_update2(cx<R>* x, const cx<R>* u, cx<R>* r, const cx<R>* v, size_t n, const double* s) {
   const cx<R> a = mk<R>((R)s[0], (R)s[1]);
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
@@ -452,6 +532,24 @@ void dot(Ctx& c, const cx<R>* a, const cx<R>* b, size_t n, int slot) {
   run_reduce(c, DotOp<R>{a, b, c.dsc, slot}, n);
 }
 
+template <typename R>
+void step_alpha_batch(Ctx& c, const cx<R>* a, const cx<R>* b, size_t n, size_t stride, int nb, double scale,
+                      int slot) {
+  const unsigned nblk = reduce_blocks(n);
+  hipLaunchKernelGGL((k_reduce_b<StepAlphaBatchOp<R>>), dim3(nblk, nb), dim3(TPB), 0, c.stream,
+                     StepAlphaBatchOp<R>{a, b, stride, scale, c.dsc, slot}, n, c.partials, c.counter);
+  WDMG_HIP(hipGetLastError());
+}
+template <typename R>
+void update2_batch(Ctx& c, cx<R>* x, const cx<R>* u, cx<R>* r, const cx<R>* v, size_t n, size_t stride, int nb,
+                   int slot) {
+  unsigned gx = ew_blocks(n);
+  if (gx * nb > 8192) gx = (8192 + nb - 1) / nb;
+  hipLaunchKernelGGL((k_update2_batch<R>), dim3(gx, nb), dim3(256), 0, c.stream, x, u, r, v, n, stride,
+                     c.dsc + slot);
+  WDMG_HIP(hipGetLastError());
+}
+
 void gcr_orth(Ctx& c, const cx<double>* W, const cx<double>* Z, cx<double>* w, cx<double>* z, size_t n, int j,
               int hslot, int nrmslot) {
   if (j <= 0) return;
@@ -507,7 +605,9 @@ void set_scalar(Ctx& c, int slot, double re, double im) {
   template void step_alpha<R>(Ctx&, const cx<R>*, const cx<R>*, size_t, double, int);      \
   template void update2<R>(Ctx&, cx<R>*, const cx<R>*, cx<R>*, const cx<R>*, size_t, int); \
   template void norm2<R>(Ctx&, const cx<R>*, size_t, int);                                 \
-  template void dot<R>(Ctx&, const cx<R>*, const cx<R>*, size_t, int);
+  template void dot<R>(Ctx&, const cx<R>*, const cx<R>*, size_t, int);                      \
+  template void step_alpha_batch<R>(Ctx&, const cx<R>*, const cx<R>*, size_t, size_t, int, double, int); \
+  template void update2_batch<R>(Ctx&, cx<R>*, const cx<R>*, cx<R>*, const cx<R>*, size_t, size_t, int, int);
 INST(double)
 INST(float)
 #undef INST

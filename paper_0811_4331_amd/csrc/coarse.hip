@@ -11,6 +11,7 @@
 // block of one coarse site: it applies the fine hops to the chirality-split
 // columns of P at a few sites at a time (staged in LDS) and contracts them
 // with the conjugated columns, all in FP64.
+#include "fine_field.h"
 #include "internal.h"
 #include "wilson_spin.h"
 
@@ -74,19 +75,18 @@ __device__ __forceinline__ bool inside(const AggGeom& a, const int c[4], int mu,
 // ---- level 0: Wilson hops ---------------------------------------------------
 template <int MU, int SIGN>
 __device__ __forceinline__ void wilson_hop_col(const cx<double>* __restrict__ U, const cx<double>* __restrict__ vk,
-                                               size_t V, int s, int nb, int chi, cx<double> (&t)[12]) {
+                                               int s, int nb, bool neg, int chi, cx<double> (&t)[12]) {
   cx<double> p[12];
 #pragma unroll
   for (int k = 0; k < 12; ++k) {
     const bool on = (k / 6) == chi;
-    p[k] = on ? vk[(size_t)k * V + nb] : mk(0.0, 0.0);
+    p[k] = on ? vk[fidx(nb, k, 12)] : mk(0.0, 0.0);
   }
   cx<double> h[6];
   project<MU, SIGN>(p, h);
   const int ls = SIGN > 0 ? s : nb;
   cx<double> u[9];
-#pragma unroll
-  for (int e = 0; e < 9; ++e) u[e] = U[(size_t)(MU * 9 + e) * V + ls];
+  load_link(U, MU, ls, neg, u);
   cx<double> uh[6];
 #pragma unroll
   for (int aa = 0; aa < 2; ++aa) {
@@ -106,30 +106,33 @@ __device__ __forceinline__ void wilson_hop_col(const cx<double>* __restrict__ U,
   expand_add<MU, SIGN>(uh, t);
 }
 
-__device__ void wilson_hop_dispatch(int mu, int dir, const cx<double>* U, const cx<double>* vk, size_t V, int s,
-                                    int nb, int chi, cx<double> (&t)[12]) {
+__device__ void wilson_hop_dispatch(int mu, int dir, const cx<double>* U, const cx<double>* vk, int s, int nb,
+                                    bool neg, int chi, cx<double> (&t)[12]) {
   switch (mu * 2 + (dir < 0)) {
-    case 0: wilson_hop_col<0, +1>(U, vk, V, s, nb, chi, t); break;
-    case 1: wilson_hop_col<0, -1>(U, vk, V, s, nb, chi, t); break;
-    case 2: wilson_hop_col<1, +1>(U, vk, V, s, nb, chi, t); break;
-    case 3: wilson_hop_col<1, -1>(U, vk, V, s, nb, chi, t); break;
-    case 4: wilson_hop_col<2, +1>(U, vk, V, s, nb, chi, t); break;
-    case 5: wilson_hop_col<2, -1>(U, vk, V, s, nb, chi, t); break;
-    case 6: wilson_hop_col<3, +1>(U, vk, V, s, nb, chi, t); break;
-    default: wilson_hop_col<3, -1>(U, vk, V, s, nb, chi, t); break;
+    case 0: wilson_hop_col<0, +1>(U, vk, s, nb, neg, chi, t); break;
+    case 1: wilson_hop_col<0, -1>(U, vk, s, nb, neg, chi, t); break;
+    case 2: wilson_hop_col<1, +1>(U, vk, s, nb, neg, chi, t); break;
+    case 3: wilson_hop_col<1, -1>(U, vk, s, nb, neg, chi, t); break;
+    case 4: wilson_hop_col<2, +1>(U, vk, s, nb, neg, chi, t); break;
+    case 5: wilson_hop_col<2, -1>(U, vk, s, nb, neg, chi, t); break;
+    case 6: wilson_hop_col<3, +1>(U, vk, s, nb, neg, chi, t); break;
+    default: wilson_hop_col<3, -1>(U, vk, s, nb, neg, chi, t); break;
   }
 }
 
 struct WilsonSide {
   const cx<double>* U;
   double diag;  // 4 + m
+  int tneg;     // antiperiodic time: links at t = Lt-1 carry the sign
   static constexpr int kDof = 12;
   // Element offset of dof e at site s in a field of this level.
-  __device__ __forceinline__ size_t off(size_t V, int s, int e) const { return (size_t)e * V + s; }
+  __device__ __forceinline__ size_t off(size_t, int s, int e) const { return fidx(s, e, 12); }
+  __device__ __forceinline__ bool neg(const Geom& g, const int c[4], int mu, int dir) const {
+    return tneg && mu == 3 && c[3] == (dir > 0 ? g.L[3] - 1 : 0);
+  }
   // T[q][e][cc] for columns col0 .. col0+ncc-1 at the chunk's sites.
   __device__ void columns(const AggGeom& a, int d, const int* sites, const int (*crd)[4], int ncs, int col0, int ncc,
                           int ldt, int nv, const cx<double>* Vv, size_t vstride, cx<double>* T) const {
-    const size_t V = a.g.vol;
     for (int w = threadIdx.x; w < ncs * ncc; w += blockDim.x) {
       const int q = w / ncc, cc = w % ncc;
       const int col = col0 + cc, chi = col / nv, k = col % nv;
@@ -142,7 +145,7 @@ struct WilsonSide {
       if (d < 8) {
         const int mu = d >> 1, dir = (d & 1) ? -1 : 1;
         const int nb = dir > 0 ? nbr_fwd(a.g, s, c, mu) : nbr_bwd(a.g, s, c, mu);
-        wilson_hop_dispatch(mu, dir, U, vk, V, s, nb, chi, t);
+        wilson_hop_dispatch(mu, dir, U, vk, s, nb, neg(a.g, c, mu, dir), chi, t);
 #pragma unroll
         for (int e = 0; e < 12; ++e) t[e] = (-0.5) * t[e];
       } else {
@@ -150,13 +153,13 @@ struct WilsonSide {
           for (int dir = 1; dir >= -1; dir -= 2) {
             if (!inside(a, c, mu, dir)) continue;
             const int nb = dir > 0 ? nbr_fwd(a.g, s, c, mu) : nbr_bwd(a.g, s, c, mu);
-            wilson_hop_dispatch(mu, dir, U, vk, V, s, nb, chi, t);
+            wilson_hop_dispatch(mu, dir, U, vk, s, nb, neg(a.g, c, mu, dir), chi, t);
           }
         }
 #pragma unroll
         for (int e = 0; e < 12; ++e) {
           const bool on = (e / 6) == chi;
-          const cx<double> f = on ? vk[(size_t)e * V + s] : mk(0.0, 0.0);
+          const cx<double> f = on ? vk[fidx(s, e, 12)] : mk(0.0, 0.0);
           t[e] = mk(diag * f.re - 0.5 * t[e].re, diag * f.im - 0.5 * t[e].im);
         }
       }
@@ -332,7 +335,7 @@ void launch_build(Ctx& c, const Side& side, const Level& f, Level& cl, int dof) 
 }  // namespace
 
 void coarse_build0(Ctx& c, const Level& f, Level& cl) {
-  WilsonSide side{c.U64, 4.0 + c.mass};
+  WilsonSide side{c.U64, 4.0 + c.mass, c.t_bc < 0 ? 1 : 0};
   launch_build(c, side, f, cl, 12);
 }
 

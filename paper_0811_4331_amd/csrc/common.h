@@ -80,6 +80,7 @@ struct Geom {
   int sl[4];   // stride of a local coordinate inside a tile
   int st[4];   // stride (in sites) of a tile coordinate
   int vol;     // sites
+  int vpad;    // sites rounded up to a multiple of 64 (fine-field blocks)
   int tvol;    // sites per tile
   int ltvol;   // log2 tvol
 };

@@ -7,26 +7,28 @@
 // back to four spins.  The antiperiodic time sign is folded into the stored
 // links U_t(x) at t = Lt-1, so it reaches both hop directions.
 //
-// Layout: fields [rhs][12][V] (component-major, sites tile-major), links
-// [mu][9][V]: every load of a wavefront is 64 consecutive elements.
-// One thread per (site, right-hand side).
+// Layout: fields in 64-site blocks, links as their first two rows (see
+// fine_field.h).  One thread per (site, right-hand side); workgroups are
+// remapped so spatially adjacent tiles share an XCD's L2.
+#include "fine_field.h"
 #include "internal.h"
 #include "wilson_spin.h"
 
 namespace wdmg {
 namespace {
 
+constexpr int kDslashThreads = 128;
+
 template <int MU, int SIGN, typename R>
-__device__ __forceinline__ void hop(const cx<R>* __restrict__ in, const cx<R>* __restrict__ U, size_t V,
-                                    int nb, int link_site, cx<R> (&acc)[12]) {
+__device__ __forceinline__ void hop(const cx<R>* __restrict__ in, const cx<R>* __restrict__ U, int nb,
+                                    int link_site, bool neg, cx<R> (&acc)[12]) {
   cx<R> p[12];
 #pragma unroll
-  for (int k = 0; k < 12; ++k) p[k] = in[(size_t)k * V + nb];
+  for (int k = 0; k < 12; ++k) p[k] = in[fidx(nb, k, 12)];
   cx<R> h[6];
   project<MU, SIGN>(p, h);
   cx<R> u[9];
-#pragma unroll
-  for (int e = 0; e < 9; ++e) u[e] = U[(size_t)(MU * 9 + e) * V + link_site];
+  load_link(U, MU, link_site, neg, u);
   cx<R> uh[6];
 #pragma unroll
   for (int a = 0; a < 2; ++a) {
@@ -46,45 +48,54 @@ __device__ __forceinline__ void hop(const cx<R>* __restrict__ in, const cx<R>* _
   expand_add<MU, SIGN>(uh, acc);
 }
 
+// One thread per site; blockIdx.y = right-hand side.  Padding sites
+// (vol <= s < vpad) are written as zeros.
 template <typename R>
-__global__ __launch_bounds__(256) void k_dslash(Geom g, cx<R>* __restrict__ out, const cx<R>* __restrict__ in,
-                                                const cx<R>* __restrict__ U, R diag) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= g.vol) return;
-  const size_t V = g.vol;
-  const size_t off = (size_t)blockIdx.y * 12 * V;
+__global__ __launch_bounds__(kDslashThreads) void k_dslash(Geom g, cx<R>* __restrict__ out,
+                                                          const cx<R>* __restrict__ in,
+                                                          const cx<R>* __restrict__ U, R diag, int tneg) {
+  const int s = xcd_block() * kDslashThreads + threadIdx.x;
+  const size_t off = (size_t)blockIdx.y * 12 * g.vpad;
   in += off;
   out += off;
+  if (s >= g.vol) {
+    if (s < g.vpad) {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) out[fidx(s, k, 12)] = mk<R>(0, 0);
+    }
+    return;
+  }
   int c[4];
   coords_of(g, s, c);
   cx<R> acc[12];
 #pragma unroll
   for (int k = 0; k < 12; ++k) acc[k] = mk<R>(0, 0);
+  const bool tlast = tneg && c[3] == g.L[3] - 1, tfirst = tneg && c[3] == 0;
   {
     const int f = nbr_fwd(g, s, c, 0), b = nbr_bwd(g, s, c, 0);
-    hop<0, +1>(in, U, V, f, s, acc);
-    hop<0, -1>(in, U, V, b, b, acc);
+    hop<0, +1>(in, U, f, s, false, acc);
+    hop<0, -1>(in, U, b, b, false, acc);
   }
   {
     const int f = nbr_fwd(g, s, c, 1), b = nbr_bwd(g, s, c, 1);
-    hop<1, +1>(in, U, V, f, s, acc);
-    hop<1, -1>(in, U, V, b, b, acc);
+    hop<1, +1>(in, U, f, s, false, acc);
+    hop<1, -1>(in, U, b, b, false, acc);
   }
   {
     const int f = nbr_fwd(g, s, c, 2), b = nbr_bwd(g, s, c, 2);
-    hop<2, +1>(in, U, V, f, s, acc);
-    hop<2, -1>(in, U, V, b, b, acc);
+    hop<2, +1>(in, U, f, s, false, acc);
+    hop<2, -1>(in, U, b, b, false, acc);
   }
   {
     const int f = nbr_fwd(g, s, c, 3), b = nbr_bwd(g, s, c, 3);
-    hop<3, +1>(in, U, V, f, s, acc);
-    hop<3, -1>(in, U, V, b, b, acc);
+    hop<3, +1>(in, U, f, s, tlast, acc);
+    hop<3, -1>(in, U, b, b, tfirst, acc);
   }
   const R half = (R)0.5;
 #pragma unroll
   for (int k = 0; k < 12; ++k) {
-    const cx<R> p = in[(size_t)k * V + s];
-    out[(size_t)k * V + s] = mk<R>(diag * p.re - half * acc[k].re, diag * p.im - half * acc[k].im);
+    const cx<R> p = in[fidx(s, k, 12)];
+    out[fidx(s, k, 12)] = mk<R>(diag * p.re - half * acc[k].re, diag * p.im - half * acc[k].im);
   }
 }
 
@@ -98,9 +109,10 @@ void dslash(Ctx& c, cx<R>* out, const cx<R>* in, int nrhs) {
     U = c.U64;
   else
     U = c.U32;
-  dim3 grid((g.vol + 255) / 256, nrhs);
+  dim3 grid(g.vpad / kDslashThreads + (g.vpad % kDslashThreads != 0), nrhs);
   ProfScope ps(c, sizeof(R) == 8 ? WDMG_K_DSLASH_F64 : WDMG_K_DSLASH_F32, (long long)g.vol * nrhs);
-  hipLaunchKernelGGL((k_dslash<R>), grid, dim3(256), 0, c.stream, g, out, in, U, (R)(4.0 + c.mass));
+  hipLaunchKernelGGL((k_dslash<R>), grid, dim3(kDslashThreads), 0, c.stream, g, out, in, U, (R)(4.0 + c.mass),
+                     c.t_bc < 0 ? 1 : 0);
   WDMG_HIP(hipGetLastError());
   c.n_D += nrhs;
 }

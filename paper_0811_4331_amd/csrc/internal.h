@@ -39,7 +39,8 @@ enum ScalarSlot {
   S_RNORM = 64,     // residual norm^2 per level (real)
   S_GCR = 128,      // GCR coefficients: per level a block of 4 * 128 doubles
   S_GCR_STRIDE = 512,
-  S_TOTAL = S_GCR + 4 * S_GCR_STRIDE
+  S_BATCH = S_GCR + 4 * S_GCR_STRIDE,  // batched step sizes (64 complex)
+  S_TOTAL = S_BATCH + 128
 };
 
 // ---------------------------------------------------------------------------
@@ -78,6 +79,8 @@ struct Level {
 
 constexpr int kWork = 8;
 
+constexpr int kRing = 8;
+
 struct Ctx {
   int dims[4];
   Geom g0;
@@ -97,6 +100,8 @@ struct Ctx {
   double* partials = nullptr;   // reduction partials
   unsigned* counter = nullptr;  // last-block counters
   double* hsc = nullptr;        // pinned host mirror of a few scalars
+  double* hring = nullptr;      // pinned ring for lagged residual checks
+  hipEvent_t ring_ev[kRing] = {};
 
   // multigrid
   bool have_mg = false;
@@ -180,6 +185,14 @@ template <typename R> void add(Ctx& c, cx<R>* y, const cx<R>* x, size_t n);  // 
 template <typename R> void step_alpha(Ctx& c, const cx<R>* a, const cx<R>* b, size_t n, double scale, int slot);
 // x += s u ; r -= s v with s = dsc[slot] (complex).
 template <typename R> void update2(Ctx& c, cx<R>* x, const cx<R>* u, cx<R>* r, const cx<R>* v, size_t n, int slot);
+// Batched over nb vectors (stride apart): dsc[slot + 2 q] = scale <a_q,b_q>/<a_q,a_q>;
+// x_q += s_q u_q ; r_q -= s_q v_q.
+template <typename R>
+void step_alpha_batch(Ctx& c, const cx<R>* a, const cx<R>* b, size_t n, size_t stride, int nb, double scale,
+                      int slot);
+template <typename R>
+void update2_batch(Ctx& c, cx<R>* x, const cx<R>* u, cx<R>* r, const cx<R>* v, size_t n, size_t stride, int nb,
+                   int slot);
 // dsc[slot] = ||a||^2
 template <typename R> void norm2(Ctx& c, const cx<R>* a, size_t n, int slot);
 // dsc[slot] = <a, b>

@@ -1,5 +1,6 @@
 // Layout and precision conversion between the canonical ABI layouts and the
 // internal tile-major, component-major layouts.
+#include "fine_field.h"
 #include "internal.h"
 
 namespace wdmg {
@@ -19,6 +20,7 @@ Geom make_geom(const int L[4], const int B[4]) {
   g.tvol = B[0] * B[1] * B[2] * B[3];
   g.ltvol = lb_sum;
   g.vol = L[0] * L[1] * L[2] * L[3];
+  g.vpad = (g.vol + 63) / 64 * 64;
   g.sl[0] = 1;
   g.st[0] = g.tvol;
   for (int mu = 1; mu < 4; ++mu) {
@@ -30,39 +32,59 @@ Geom make_geom(const int L[4], const int B[4]) {
 
 namespace {
 
+// Canonical links -> first two rows of every link (FP64 and FP32) with the
+// antiperiodic sign folded into U_t at t = Lt-1.  Also checks that each link
+// is SU(3) to 1e-10: its third row must equal conj(row0 x row1).
 __global__ void k_gauge_import(Geom g, const cx<double>* __restrict__ canon, cx<double>* __restrict__ U64,
-                               cx<float>* __restrict__ U32, double tsign) {
+                               cx<float>* __restrict__ U32, double tsign, double* flag) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= g.vol) return;
+  if (s >= g.vpad) return;
+  if (s >= g.vol) {
+    for (int k = 0; k < kLinkComp; ++k) {
+      U64[fidx(s, k, kLinkComp)] = mk(0.0, 0.0);
+      U32[fidx(s, k, kLinkComp)] = mk(0.0f, 0.0f);
+    }
+    return;
+  }
   int c[4];
   coords_of(g, s, c);
   const size_t i = (size_t)c[0] + (size_t)g.L[0] * (c[1] + (size_t)g.L[1] * (c[2] + (size_t)g.L[2] * c[3]));
   const cx<double>* src = canon + i * 36;
+  double dev = 0.0;
   for (int mu = 0; mu < 4; ++mu) {
+    const cx<double>* u = src + mu * 9;
+    const cx<double> r[3] = {u[1] * u[5] - u[2] * u[4], u[2] * u[3] - u[0] * u[5], u[0] * u[4] - u[1] * u[3]};
+    for (int a = 0; a < 3; ++a) {
+      dev = fmax(dev, fabs(u[6 + a].re - r[a].re));
+      dev = fmax(dev, fabs(u[6 + a].im + r[a].im));
+    }
     const double sg = (mu == 3 && c[3] == g.L[3] - 1) ? tsign : 1.0;
-    for (int e = 0; e < 9; ++e) {
-      cx<double> u = src[mu * 9 + e];
-      u.re *= sg;
-      u.im *= sg;
-      const size_t o = (size_t)(mu * 9 + e) * g.vol + s;
-      U64[o] = u;
-      U32[o] = cvt<float>(u);
+    for (int e = 0; e < 6; ++e) {
+      const cx<double> v = mk(sg * u[e].re, sg * u[e].im);
+      U64[fidx(s, mu * 6 + e, kLinkComp)] = v;
+      U32[fidx(s, mu * 6 + e, kLinkComp)] = cvt<float>(v);
     }
   }
+  if (!(dev <= 1e-10)) flag[0] = 1.0;
 }
 
 template <typename Rio, typename R>
 __global__ void k_fine_in(Geom g, const cx<Rio>* __restrict__ canon, cx<R>* __restrict__ out) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
-  if (s >= g.vol) return;
+  if (s >= g.vpad) return;
+  cx<R>* dst = out + (size_t)r * 12 * g.vpad;
+  if (s >= g.vol) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) dst[fidx(s, k, 12)] = mk<R>(0, 0);
+    return;
+  }
   int c[4];
   coords_of(g, s, c);
   const size_t i = (size_t)c[0] + (size_t)g.L[0] * (c[1] + (size_t)g.L[1] * (c[2] + (size_t)g.L[2] * c[3]));
   const cx<Rio>* src = canon + ((size_t)r * g.vol + i) * 12;
-  cx<R>* dst = out + (size_t)r * 12 * g.vol + s;
 #pragma unroll
-  for (int k = 0; k < 12; ++k) dst[(size_t)k * g.vol] = cvt<R>(src[k]);
+  for (int k = 0; k < 12; ++k) dst[fidx(s, k, 12)] = cvt<R>(src[k]);
 }
 
 template <typename R, typename Rio>
@@ -74,9 +96,9 @@ __global__ void k_fine_out(Geom g, const cx<R>* __restrict__ in, cx<Rio>* __rest
   coords_of(g, s, c);
   const size_t i = (size_t)c[0] + (size_t)g.L[0] * (c[1] + (size_t)g.L[1] * (c[2] + (size_t)g.L[2] * c[3]));
   cx<Rio>* dst = canon + ((size_t)r * g.vol + i) * 12;
-  const cx<R>* src = in + (size_t)r * 12 * g.vol + s;
+  const cx<R>* src = in + (size_t)r * 12 * g.vpad;
 #pragma unroll
-  for (int k = 0; k < 12; ++k) dst[k] = cvt<Rio>(src[(size_t)k * g.vol]);
+  for (int k = 0; k < 12; ++k) dst[k] = cvt<Rio>(src[fidx(s, k, 12)]);
 }
 
 template <typename Rout, typename Rin>
@@ -89,14 +111,15 @@ __global__ void k_convert(cx<Rout>* __restrict__ out, const cx<Rin>* __restrict_
 
 void gauge_import(Ctx& c, const cx<double>* canon, int t_bc) {
   const Geom& g = c.g0;
-  dim3 grid((g.vol + 255) / 256);
-  hipLaunchKernelGGL(k_gauge_import, grid, dim3(256), 0, c.stream, g, canon, c.U64, c.U32, (double)t_bc);
+  dim3 grid((g.vpad + 255) / 256);
+  hipLaunchKernelGGL(k_gauge_import, grid, dim3(256), 0, c.stream, g, canon, c.U64, c.U32, (double)t_bc,
+                     c.dsc + S_ERR + 2);
   WDMG_HIP(hipGetLastError());
 }
 
 template <typename Rio, typename R>
 void fine_to_internal(Ctx& c, const Geom& g, const cx<Rio>* canon, cx<R>* out, int nrhs) {
-  dim3 grid((g.vol + 255) / 256, nrhs);
+  dim3 grid((g.vpad + 255) / 256, nrhs);
   hipLaunchKernelGGL((k_fine_in<Rio, R>), grid, dim3(256), 0, c.stream, g, canon, out);
   WDMG_HIP(hipGetLastError());
 }

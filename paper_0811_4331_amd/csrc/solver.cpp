@@ -205,7 +205,18 @@ void coarsest_solve(Ctx& c, cx<double>* x, const cx<double>* b) {
     return;
   }
   const double tol2 = c.mg.coarse_tol * c.mg.coarse_tol * bn2;
+  // The residual of iteration it is copied to pinned memory asynchronously
+  // and inspected `lag` iterations later, so the stream never drains while
+  // the host waits; up to `lag` extra iterations (which only reduce the
+  // residual further) are the price.
+  const int lag = 2;
   int it = 0;
+  auto converged_at = [&](int i) {
+    WDMG_HIP(hipEventSynchronize(c.ring_ev[i % kRing]));
+    const double rn2 = c.hring[i % kRing];
+    if (!std::isfinite(rn2)) throw Error(WDMG_ERR_NAN, "NaN in the coarsest solve");
+    return rn2 <= tol2;
+  };
   while (it < c.mg.coarse_maxit) {
     for (int j = 0; j < k && it < c.mg.coarse_maxit; ++j, ++it) {
       cx<double>* z = Zb + (size_t)j * n;
@@ -214,11 +225,14 @@ void coarsest_solve(Ctx& c, cx<double>* x, const cx<double>* b) {
       apply_op<double>(c, l, w, z, 1);
       gcr_orth(c, Wb, Zb, w, z, n, j, hslot, nrmslot);
       gcr_step(c, w, z, x, r, n, j, nrmslot, S_RNORM + l);
-      const double rn2 = read_scalar(c, S_RNORM + l);
-      if (!std::isfinite(rn2)) throw Error(WDMG_ERR_NAN, "NaN in the coarsest solve");
-      if (rn2 <= tol2) return;
+      WDMG_HIP(hipMemcpyAsync(c.hring + it % kRing, c.dsc + S_RNORM + l, sizeof(double), hipMemcpyDeviceToHost,
+                              c.stream));
+      WDMG_HIP(hipEventRecord(c.ring_ev[it % kRing], c.stream));
+      if (it >= lag && converged_at(it - lag)) return;
     }
   }
+  for (int i = it - lag < 0 ? 0 : it - lag; i < it; ++i)
+    if (converged_at(i)) return;
 }
 
 // ---------------------------------------------------------------------------
@@ -468,6 +482,17 @@ void free_hierarchy(Ctx& c) {
   }
   c.have_mg = false;
   c.nlevels = 0;
+  init_level0(c);
+}
+
+void init_level0(Ctx& c) {
+  Level& L = c.lev[0];
+  L.l = 0;
+  std::memcpy(L.dims, c.dims, sizeof(L.dims));
+  L.g = c.g0;
+  L.nsite = c.g0.vol;
+  L.dof = 12;
+  L.n = (size_t)c.g0.vpad * 12;
 }
 
 static void relax(Ctx& c, int l, const wdmg_level_params& lp, double omega) {
@@ -485,13 +510,8 @@ static void relax(Ctx& c, int l, const wdmg_level_params& lp, double omega) {
     for (int q = 0; q < nb; ++q) neg<double>(c, R + (size_t)q * n, n);
     for (int it = 0; it < lp.setup_iters; ++it) {
       apply_op<double>(c, l, P, R, nb);
-      for (int q = 0; q < nb; ++q) {
-        cx<double>* x = X + (size_t)q * n;
-        cx<double>* r = R + (size_t)q * n;
-        cx<double>* p = P + (size_t)q * n;
-        step_alpha<double>(c, p, r, n, omega, S_MR);
-        update2<double>(c, x, r, r, p, n, S_MR);
-      }
+      step_alpha_batch<double>(c, P, R, n, n, nb, omega, S_BATCH);
+      update2_batch<double>(c, X, R, R, P, n, n, nb, S_BATCH);
     }
   }
   WDMG_HIP(hipStreamSynchronize(c.stream));
@@ -530,16 +550,7 @@ void mg_setup(Ctx& c, const wdmg_mg_params& p) {
   c.mg = p;
   c.nlevels = p.n_levels;
   c.setup_mass = c.mass;
-  // level 0
-  {
-    Level& L = c.lev[0];
-    L.l = 0;
-    std::memcpy(L.dims, c.dims, sizeof(L.dims));
-    L.g = c.g0;
-    L.nsite = c.g0.vol;
-    L.dof = 12;
-    L.n = (size_t)L.nsite * 12;
-  }
+  init_level0(c);
   for (int l = 0; l < p.n_levels - 1; ++l) {
     const wdmg_level_params& lp = p.level[l];
     Level& F = c.lev[l];
@@ -596,7 +607,7 @@ void mg_setup(Ctx& c, const wdmg_mg_params& p) {
 void ensure_fine_work(Ctx& c) {
   Level& L = c.lev[0];
   if (L.w64[0]) return;
-  const size_t n = (size_t)c.g0.vol * 12;
+  const size_t n = (size_t)c.g0.vpad * 12;
   for (int i = 0; i < kWork; ++i) {
     L.w64[i] = static_cast<cx<double>*>(dev_alloc(c, n * sizeof(cx<double>)));
     L.w32[i] = static_cast<cx<float>*>(dev_alloc(c, n * sizeof(cx<float>)));
@@ -604,7 +615,7 @@ void ensure_fine_work(Ctx& c) {
 }
 
 void ensure_outer(Ctx& c, int k, bool need32) {
-  const size_t n = (size_t)c.g0.vol * 12;
+  const size_t n = (size_t)c.g0.vpad * 12;
   if (k > c.outer_k) {
     WDMG_HIP(hipStreamSynchronize(c.stream));
     dev_free(c, c.outer_Z);
@@ -622,7 +633,7 @@ void ensure_outer(Ctx& c, int k, bool need32) {
 
 void ensure_bicg(Ctx& c) {
   if (c.bicg[0]) return;
-  const size_t n = (size_t)c.g0.vol * 12;
+  const size_t n = (size_t)c.g0.vpad * 12;
   for (int i = 0; i < 6; ++i) c.bicg[i] = static_cast<cx<double>*>(dev_alloc(c, n * sizeof(cx<double>)));
 }
 

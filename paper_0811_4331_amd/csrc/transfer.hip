@@ -11,6 +11,7 @@
 // Level 0 fields are [12][V] over tile-major sites; chirality chi owns the
 // components 6 chi .. 6 chi + 5.  Level >= 1 fields are [site][dof] with the
 // two chiralities as the two halves of dof.
+#include "fine_field.h"
 #include "internal.h"
 
 namespace wdmg {
@@ -62,11 +63,10 @@ AggMap make_map(const Level& f) {
 // Row accessors: row r of the (aggregate, chirality) block -> element offset.
 struct Rows0 {  // level 0: r = m * bvol + l, m in 0..5 (component within chirality)
   AggMap map;
-  size_t V;
   int nrows() const { return map.bvol * 6; }
   __device__ __forceinline__ size_t off(int agg, int chi, int r) const {
     const int m = r / map.bvol, l = r - m * map.bvol;
-    return (size_t)(6 * chi + m) * V + map.site(agg, l);
+    return fidx(map.site(agg, l), 6 * chi + m, 12);
   }
 };
 struct RowsC {  // level >= 1: r = d * bvol + l, d in 0..half-1
@@ -122,24 +122,26 @@ __global__ __launch_bounds__(256) void k_prolong0(AggMap map, const cx<R>* __res
                                                   cx<R>* __restrict__ out, int nagg, int nv) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   const int rhs = blockIdx.y;
-  const size_t V = map.g.vol;
-  if (s >= (int)V) return;
-  const int agg = map.agg_of(s);
-  const cx<R>* ec = in + ((size_t)rhs * nagg + agg) * 2 * nv;
+  const size_t n = (size_t)12 * map.g.vpad;
+  if (s >= map.g.vpad) return;
+  cx<R>* o = out + (size_t)rhs * n;
   cx<R> acc[12];
 #pragma unroll
   for (int k = 0; k < 12; ++k) acc[k] = mk<R>(0, 0);
-  for (int k = 0; k < nv; ++k) {
-    const cx<R> e0 = ec[k], e1 = ec[nv + k];
-    const cx<R>* vk = Vv + (size_t)k * 12 * V + s;
+  if (s < map.g.vol) {
+    const int agg = map.agg_of(s);
+    const cx<R>* ec = in + ((size_t)rhs * nagg + agg) * 2 * nv;
+    for (int k = 0; k < nv; ++k) {
+      const cx<R> e0 = ec[k], e1 = ec[nv + k];
+      const cx<R>* vk = Vv + (size_t)k * n;
 #pragma unroll
-    for (int m = 0; m < 6; ++m) cmadd(acc[m], vk[(size_t)m * V], e0);
+      for (int m = 0; m < 6; ++m) cmadd(acc[m], vk[fidx(s, m, 12)], e0);
 #pragma unroll
-    for (int m = 6; m < 12; ++m) cmadd(acc[m], vk[(size_t)m * V], e1);
+      for (int m = 6; m < 12; ++m) cmadd(acc[m], vk[fidx(s, m, 12)], e1);
+    }
   }
-  cx<R>* o = out + (size_t)rhs * 12 * V + s;
 #pragma unroll
-  for (int m = 0; m < 12; ++m) o[(size_t)m * V] = acc[m];
+  for (int m = 0; m < 12; ++m) o[fidx(s, m, 12)] = acc[m];
 }
 
 template <typename R>
@@ -251,7 +253,7 @@ inline int tpb_for(int nrows) {
 
 template <typename R>
 void restrict0(Ctx& c, const Level& f, const cx<R>* V, const cx<R>* in, cx<R>* out, int nrhs) {
-  Rows0 rows{make_map(f), (size_t)f.nsite};
+  Rows0 rows{make_map(f)};
   const int nrows = rows.nrows();
   const int nagg = nagg_of(f);
   ProfScope ps(c, sizeof(R) == 8 ? WDMG_K_RESTRICT_F64 : WDMG_K_RESTRICT_F32, (long long)f.nsite * nrhs);
@@ -274,7 +276,7 @@ template <typename R>
 void prolong0(Ctx& c, const Level& f, const cx<R>* V, const cx<R>* in, cx<R>* out, int nrhs) {
   const AggMap map = make_map(f);
   ProfScope ps(c, sizeof(R) == 8 ? WDMG_K_PROLONG_F64 : WDMG_K_PROLONG_F32, (long long)f.nsite * nrhs);
-  hipLaunchKernelGGL((k_prolong0<R>), dim3((f.nsite + 255) / 256, nrhs), dim3(256), 0, c.stream, map, V, in, out,
+  hipLaunchKernelGGL((k_prolong0<R>), dim3((f.g.vpad + 255) / 256, nrhs), dim3(256), 0, c.stream, map, V, in, out,
                      nagg_of(f), f.nv);
   WDMG_HIP(hipGetLastError());
 }
@@ -288,7 +290,7 @@ void prolongC(Ctx& c, const Level& f, const cx<R>* V, const cx<R>* in, cx<R>* ou
 }
 
 void block_qr0(Ctx& c, const Level& f, cx<double>* V) {
-  Rows0 rows{make_map(f), (size_t)f.nsite};
+  Rows0 rows{make_map(f)};
   const int nrows = rows.nrows();
   ProfScope ps(c, WDMG_K_BLOCK_QR, (long long)nagg_of(f) * 2);
   hipLaunchKernelGGL((k_block_qr<Rows0>), dim3(nagg_of(f), 2), dim3(tpb_for(nrows)), 0, c.stream, rows, nrows, V, f.n,

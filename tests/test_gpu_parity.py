@@ -48,6 +48,8 @@ def make_ctx(dims, eps, seed, m, t_bc=-1):
     ((6, 4, 2, 10), -1),      # ragged: tiles 2 x 4 x 2 x 2
     ((12, 4, 4, 4), 1),       # periodic time
     ((4, 4, 4, 4), -1),       # a single tile
+    ((2, 2, 2, 2), -1),       # smallest lattice: 16 sites padded to one 64-site block
+    ((6, 6, 2, 2), 1),        # 144 sites: last 64-site block partly padding
 ])
 def test_apply_D_fp64_and_fp32(dims, t_bc):
     m = -0.37
@@ -246,3 +248,12 @@ def test_error_paths():
     with pytest.raises(wdmg.WdmgError) as e:
         ctx.apply_D(gpu(synthetic.gaussian_spinor(dims, 4).astype(np.complex64)), prec="bf16")
     assert e.value.name == "WDMG_ERR_ARG"
+    # links that are not SU(3) are rejected (the library stores two rows per link)
+    bad = u.copy()
+    bad[1, 2, 3, 4, 2] *= np.exp(0.3j)  # U(3), det != 1
+    with pytest.raises(wdmg.WdmgError) as e:
+        ctx.set_gauge(gpu(bad))
+    assert e.value.name == "WDMG_ERR_ARG"
+    with pytest.raises(wdmg.WdmgError) as e:  # the context has no valid gauge field now
+        ctx.apply_D(gpu(synthetic.gaussian_spinor(dims, 5)))
+    assert e.value.name == "WDMG_ERR_NOT_SETUP"
