@@ -62,10 +62,15 @@ def parse():
     ap.add_argument("--nrhs", type=int, default=1)
     ap.add_argument("--mg-prec", default="f64", choices=["f64", "f32"])
     ap.add_argument("--coarse-tol", type=float, default=1e-2)
+    ap.add_argument("--no-alpha", action="store_true",
+                    help="skip the minimal-residual step after prolongation (alpha = 1)")
     ap.add_argument("--big-L", type=int, default=32, help="lattice for the out-of-cache Dslash figure (0: skip)")
     ap.add_argument("--no-bicgstab", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--only-dslash", type=int, default=0, metavar="L",
+                    help="only time Dslash (FP64, FP32) on L^4 plus a plain 1 GiB device copy "
+                         "(the reference for hardware byte counters), then exit")
     return ap.parse_args()
 
 
@@ -106,6 +111,27 @@ def dslash_bandwidth(wdmg, synthetic, torch, dev, L, reps=20):
     return out
 
 
+def only_dslash(L, reps=10):
+    """Dslash on L^4 and a plain device copy of known size (counter calibration)."""
+    import torch
+
+    import synthetic
+    from paper_0811_4331_amd import wdmg
+    dev = torch.device("cuda:0")
+    res = {"dslash": dslash_bandwidth(wdmg, synthetic, torch, dev, L, reps=reps)}
+    src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)  # 1 GiB
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / 3
+    res["copy_1GiB"] = {"bytes_read": src.numel() * 8, "bytes_written": dst.numel() * 8,
+                        "GB_s_read_plus_write": 2 * src.numel() * 8 / dt / 1e9}
+    print(json.dumps(res), flush=True)
+
+
 def cpu_baseline(u, b, m, n_d_per_step, nrhs, seconds):
     """The FP64 oracle's Wilson operator timed on the host (bounded sample)."""
     from oracle import wilson
@@ -134,6 +160,9 @@ def main():
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1",
                           "n_gpus": a.gpus}))
         sys.exit(2)
+    if a.only_dslash:
+        only_dslash(a.only_dslash)
+        return
     import torch
 
     import synthetic
@@ -157,7 +186,7 @@ def main():
 
     def step():
         t0 = time.perf_counter()
-        ctx.mg_setup(levels, coarse_tol=a.coarse_tol)
+        ctx.mg_setup(levels, coarse_tol=a.coarse_tol, use_alpha=not a.no_alpha)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         x, st = ctx.solve(b, tol=1e-10, restart=50, maxit=2000, mg_prec=a.mg_prec)
@@ -229,7 +258,8 @@ def main():
                                f"2-level MG 4^4 aggregates Nv={a.nv}, MR setup {a.setup_iters} iters, "
                                f"FGCR(50) to 1e-10, {a.nrhs} Gaussian RHS",
                    "lattice": list(dims), "eps": a.eps, "m": m, "m_crit": m - a.delta, "nv": a.nv,
-                   "nrhs": a.nrhs, "mg_prec": a.mg_prec, "coarse_tol": a.coarse_tol},
+                   "nrhs": a.nrhs, "mg_prec": a.mg_prec, "coarse_tol": a.coarse_tol,
+                   "alpha_step": not a.no_alpha},
         "setup_s": float(np.median(setups)), "solve_s_per_rhs": float(np.median(solves)) / a.nrhs,
         "mg_iters": [s["iters"] for s in last], "mg_n_D": [s["n_D"] for s in last],
         "mg_n_Dc": [s["n_Dc"][1] for s in last], "true_res": true_res,

@@ -218,7 +218,9 @@ int wdmg_create(wdmg_ctx** out, const int dims[4], const wdmg_alloc* alloc, void
     WDMG_HIP(hipMemsetAsync(c->dsc, 0, S_TOTAL * sizeof(double), c->stream));
     WDMG_HIP(hipMemsetAsync(c->counter, 0, 256 * sizeof(unsigned), c->stream));
     WDMG_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->hsc), 64 * sizeof(double), hipHostMallocDefault));
-    WDMG_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->hring), kRing * sizeof(double), hipHostMallocDefault));
+    WDMG_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->hring), kRing * sizeof(double),
+                           hipHostMallocMapped | hipHostMallocCoherent));
+    WDMG_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&c->dring), c->hring, 0));
     for (int i = 0; i < kRing; ++i) WDMG_HIP(hipEventCreateWithFlags(&c->ring_ev[i], hipEventDisableTiming));
     init_level0(*c);
     WDMG_HIP(hipStreamSynchronize(c->stream));

@@ -23,11 +23,20 @@ inline unsigned reduce_blocks(size_t n) {
 
 __device__ __forceinline__ bool bad(double x) { return !isfinite(x); }
 
+
+// Reductions: each workgroup writes its partial sums; a second one-workgroup
+// launch adds them in a fixed order and applies the finalising formula.  A
+// vector small enough for one workgroup is reduced and finalised in a
+// single launch.  (A last-workgroup ticket with device-scope fences was
+// measured slower than the second launch once more than a few dozen
+// workgroups take part.)
+constexpr size_t kSingleBlockMax = 32768;
+constexpr int TPB1 = 1024;
+
 template <class Op>
-__global__ __launch_bounds__(TPB) void k_reduce(Op op, size_t n, double* partials, unsigned* counter) {
+__global__ __launch_bounds__(TPB) void k_reduce_part(Op op, size_t n, double* partials) {
   constexpr int K = Op::K;
   __shared__ double lds[K * (TPB / 64)];
-  __shared__ bool last;
   double v[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) v[k] = 0.0;
@@ -36,34 +45,42 @@ __global__ __launch_bounds__(TPB) void k_reduce(Op op, size_t n, double* partial
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int k = 0; k < K; ++k) partials[blockIdx.x * K + k] = v[k];
-    __threadfence();
-    last = atomicAdd(counter, 1u) == gridDim.x - 1;
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-#pragma unroll
-  for (int k = 0; k < K; ++k) v[k] = 0.0;
-  for (unsigned b = threadIdx.x; b < gridDim.x; b += TPB) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) v[k] += load_coherent(&partials[b * K + k]);
-  }
-  block_sum<K>(v, lds);
-  if (threadIdx.x == 0) {
-    op.fin(v);
-    *counter = 0u;
   }
 }
 
-// Batched form: blockIdx.y selects one of several independent vectors; each
-// has its own partials region and last-block ticket.
 template <class Op>
-__global__ __launch_bounds__(TPB) void k_reduce_b(Op op, size_t n, double* partials, unsigned* counter) {
+__global__ __launch_bounds__(TPB) void k_reduce_fin(Op op, int nb, const double* partials) {
   constexpr int K = Op::K;
   __shared__ double lds[K * (TPB / 64)];
-  __shared__ bool last;
+  double v[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = 0.0;
+  for (int b = threadIdx.x; b < nb; b += TPB) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] += partials[b * K + k];
+  }
+  block_sum<K>(v, lds);
+  if (threadIdx.x == 0) op.fin(v);
+}
+
+template <class Op>
+__global__ __launch_bounds__(TPB1) void k_reduce_one(Op op, size_t n) {
+  constexpr int K = Op::K;
+  __shared__ double lds[K * (TPB1 / 64)];
+  double v[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = 0.0;
+  for (size_t i = threadIdx.x; i < n; i += TPB1) op.acc(i, v);
+  block_sum<K>(v, lds);
+  if (threadIdx.x == 0) op.fin(v);
+}
+
+// Batched form: blockIdx.y selects one of several independent vectors.
+template <class Op>
+__global__ __launch_bounds__(TPB) void k_reduce_b_part(Op op, size_t n, double* partials) {
+  constexpr int K = Op::K;
+  __shared__ double lds[K * (TPB / 64)];
   const int y = blockIdx.y;
-  double* part = partials + (size_t)y * kMaxReduceBlocks * K;
   double v[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) v[k] = 0.0;
@@ -71,30 +88,37 @@ __global__ __launch_bounds__(TPB) void k_reduce_b(Op op, size_t n, double* parti
   block_sum<K>(v, lds);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) part[blockIdx.x * K + k] = v[k];
-    __threadfence();
-    last = atomicAdd(counter + y, 1u) == gridDim.x - 1;
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-#pragma unroll
-  for (int k = 0; k < K; ++k) v[k] = 0.0;
-  for (unsigned bb = threadIdx.x; bb < gridDim.x; bb += TPB) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) v[k] += load_coherent(&part[bb * K + k]);
-  }
-  block_sum<K>(v, lds);
-  if (threadIdx.x == 0) {
-    op.fin(v, y);
-    counter[y] = 0u;
+    for (int k = 0; k < K; ++k) partials[((size_t)y * gridDim.x + blockIdx.x) * K + k] = v[k];
   }
 }
 
 template <class Op>
+__global__ __launch_bounds__(TPB) void k_reduce_b_fin(Op op, int nb, const double* partials) {
+  constexpr int K = Op::K;
+  __shared__ double lds[K * (TPB / 64)];
+  const int y = blockIdx.x;
+  double v[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = 0.0;
+  for (int b = threadIdx.x; b < nb; b += TPB) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] += partials[((size_t)y * nb + b) * K + k];
+  }
+  block_sum<K>(v, lds);
+  if (threadIdx.x == 0) op.fin(v, y);
+}
+
+template <class Op>
 void run_reduce(Ctx& c, const Op& op, size_t n) {
+  if (n <= kSingleBlockMax) {
+    hipLaunchKernelGGL((k_reduce_one<Op>), dim3(1), dim3(TPB1), 0, c.stream, op, n);
+    WDMG_HIP(hipGetLastError());
+    return;
+  }
   const unsigned nb = reduce_blocks(n);
-  hipLaunchKernelGGL((k_reduce<Op>), dim3(nb), dim3(TPB), 0, c.stream, op, n, c.partials, c.counter);
+  hipLaunchKernelGGL((k_reduce_part<Op>), dim3(nb), dim3(TPB), 0, c.stream, op, n, c.partials);
+  WDMG_HIP(hipGetLastError());
+  hipLaunchKernelGGL((k_reduce_fin<Op>), dim3(1), dim3(TPB), 0, c.stream, op, (int)nb, c.partials);
   WDMG_HIP(hipGetLastError());
 }
 
@@ -208,7 +232,45 @@ struct GcrCoefOp {
   }
 };
 
-// x += a z; r -= a w; ||r||^2.
+// w -= sum_i h_i W_i ; z -= sum_i h_i Z_i  (i < j), then nrm_j = <w,w> and
+// a = <w, r> / nrm_j, in one pass.
+struct GcrAxpyCoefOp {
+  static constexpr int K = 3;
+  const cx<double>* W;
+  const cx<double>* Z;
+  cx<double>* w;
+  cx<double>* z;
+  const cx<double>* r;
+  const double* h;
+  size_t n;
+  int j;
+  double* dsc;
+  int nrmslot, aslot;
+  __device__ void acc(size_t e, double* v) const {
+    cx<double> a = w[e], b = z[e];
+    for (int i = 0; i < j; ++i) {
+      const cx<double> hi = mk(h[2 * i], h[2 * i + 1]);
+      a = a - hi * W[(size_t)i * n + e];
+      b = b - hi * Z[(size_t)i * n + e];
+    }
+    if (j > 0) {
+      w[e] = a;
+      z[e] = b;
+    }
+    const cx<double> y = r[e];
+    v[0] += a.re * a.re + a.im * a.im;
+    v[1] += a.re * y.re + a.im * y.im;
+    v[2] += a.re * y.im - a.im * y.re;
+  }
+  __device__ void fin(const double* v) const {
+    if (bad(v[0]) || bad(v[1]) || bad(v[2])) dsc[S_ERR] = 1.0;
+    dsc[nrmslot] = v[0];
+    dsc[aslot] = v[0] > 0.0 ? v[1] / v[0] : 0.0;
+    dsc[aslot + 1] = v[0] > 0.0 ? v[2] / v[0] : 0.0;
+  }
+};
+
+// x += a z; r -= a w; ||r||^2 (also to a host-visible slot when given).
 struct GcrUpdateOp {
   static constexpr int K = 1;
   const cx<double>* w;
@@ -218,6 +280,7 @@ struct GcrUpdateOp {
   const double* a;
   double* dsc;
   int rslot;
+  double* host;
   __device__ void acc(size_t i, double* v) const {
     const cx<double> s = mk(a[0], a[1]);
     x[i] = x[i] + s * z[i];
@@ -228,6 +291,7 @@ struct GcrUpdateOp {
   __device__ void fin(const double* v) const {
     if (bad(v[0])) dsc[S_ERR] = 1.0;
     dsc[rslot] = v[0];
+    if (host) host[0] = v[0];
   }
 };
 
@@ -409,15 +473,13 @@ __global__ void k_bicg_s(cx<double>* s, const cx<double>* r, const cx<double>* v
     s[i] = r[i] - al * v[i];
 }
 
-// GCR orthogonalisation: coefficients h_i = <W_i, w> / nrm_i for up to 8
-// basis vectors per workgroup row (blockIdx.y), then the last workgroup
-// finalises all of them.
+// GCR orthogonalisation: partial dot products <W_i, w> for up to 8 basis
+// vectors per workgroup row (blockIdx.y), then one workgroup finalises all
+// coefficients h_i = <W_i, w> / nrm_i.
 constexpr int GCR_G = 8;
 __global__ __launch_bounds__(TPB) void k_gcr_dots(const cx<double>* __restrict__ W, const cx<double>* __restrict__ w,
-                                                  size_t n, int j, double* partials, unsigned* counter, double* dsc,
-                                                  int hslot, int nrmslot) {
+                                                  size_t n, int j, double* partials) {
   __shared__ double lds[2 * GCR_G * (TPB / 64)];
-  __shared__ bool last;
   const int i0 = blockIdx.y * GCR_G;
   const int ni = min(GCR_G, j - i0);
   double v[2 * GCR_G];
@@ -435,28 +497,24 @@ __global__ __launch_bounds__(TPB) void k_gcr_dots(const cx<double>* __restrict__
     }
   }
   block_sum<2 * GCR_G>(v, lds);
-  const unsigned nblk = gridDim.x * gridDim.y;
-  const unsigned myblk = blockIdx.y * gridDim.x + blockIdx.x;
   if (threadIdx.x == 0) {
+    const size_t myblk = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
 #pragma unroll
-    for (int k = 0; k < 2 * GCR_G; ++k) partials[(size_t)myblk * 2 * GCR_G + k] = v[k];
-    __threadfence();
-    last = atomicAdd(counter, 1u) == nblk - 1;
+    for (int k = 0; k < 2 * GCR_G; ++k) partials[myblk * 2 * GCR_G + k] = v[k];
   }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  // thread t finalises value t = (group, k); blocks summed in fixed order
+}
+
+__global__ __launch_bounds__(TPB) void k_gcr_dots_fin(int j, int gx, const double* partials, double* dsc, int hslot,
+                                                      int nrmslot) {
+  // thread t finalises value t = (basis vector, re/im); workgroups summed in order
   for (int t = threadIdx.x; t < 2 * j; t += TPB) {
     const int i = t >> 1, part = t & 1;
     const int gy = i / GCR_G, q = i % GCR_G;
     double s = 0.0;
-    for (unsigned bx = 0; bx < gridDim.x; ++bx)
-      s += load_coherent(&partials[((size_t)gy * gridDim.x + bx) * 2 * GCR_G + 2 * q + part]);
+    for (int bx = 0; bx < gx; ++bx) s += partials[((size_t)gy * gx + bx) * 2 * GCR_G + 2 * q + part];
     const double nrm = dsc[nrmslot + i];
     dsc[hslot + t] = nrm > 0.0 ? s / nrm : 0.0;
   }
-  if (threadIdx.x == 0) *counter = 0u;
 }
 
 __global__ void k_gcr_axpy(const cx<double>* __restrict__ W, const cx<double>* __restrict__ Z, cx<double>* w,
@@ -536,8 +594,12 @@ template <typename R>
 void step_alpha_batch(Ctx& c, const cx<R>* a, const cx<R>* b, size_t n, size_t stride, int nb, double scale,
                       int slot) {
   const unsigned nblk = reduce_blocks(n);
-  hipLaunchKernelGGL((k_reduce_b<StepAlphaBatchOp<R>>), dim3(nblk, nb), dim3(TPB), 0, c.stream,
-                     StepAlphaBatchOp<R>{a, b, stride, scale, c.dsc, slot}, n, c.partials, c.counter);
+  const StepAlphaBatchOp<R> op{a, b, stride, scale, c.dsc, slot};
+  hipLaunchKernelGGL((k_reduce_b_part<StepAlphaBatchOp<R>>), dim3(nblk, nb), dim3(TPB), 0, c.stream, op, n,
+                     c.partials);
+  WDMG_HIP(hipGetLastError());
+  hipLaunchKernelGGL((k_reduce_b_fin<StepAlphaBatchOp<R>>), dim3(nb), dim3(TPB), 0, c.stream, op, (int)nblk,
+                     c.partials);
   WDMG_HIP(hipGetLastError());
 }
 template <typename R>
@@ -550,23 +612,24 @@ void update2_batch(Ctx& c, cx<R>* x, const cx<R>* u, cx<R>* r, const cx<R>* v, s
   WDMG_HIP(hipGetLastError());
 }
 
-void gcr_orth(Ctx& c, const cx<double>* W, const cx<double>* Z, cx<double>* w, cx<double>* z, size_t n, int j,
-              int hslot, int nrmslot) {
-  if (j <= 0) return;
-  const unsigned gy = (unsigned)((j + GCR_G - 1) / GCR_G);
-  unsigned gx = reduce_blocks(n);
-  if (gx * gy > (unsigned)kMaxReduceBlocks * 2) gx = (kMaxReduceBlocks * 2) / gy;
-  hipLaunchKernelGGL(k_gcr_dots, dim3(gx, gy), dim3(TPB), 0, c.stream, W, w, n, j, c.partials, c.counter, c.dsc,
-                     hslot, nrmslot);
-  WDMG_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_gcr_axpy, dim3(ew_blocks(n)), dim3(256), 0, c.stream, W, Z, w, z, n, j, c.dsc + hslot);
-  WDMG_HIP(hipGetLastError());
+void gcr_orth(Ctx& c, const cx<double>* W, const cx<double>* Z, cx<double>* w, cx<double>* z, const cx<double>* r,
+              size_t n, int j, int hslot, int nrmslot) {
+  if (j > 0) {
+    const unsigned gy = (unsigned)((j + GCR_G - 1) / GCR_G);
+    unsigned gx = reduce_blocks(n);
+    if (gx * gy > (unsigned)kMaxReduceBlocks * 2) gx = (kMaxReduceBlocks * 2) / gy;
+    hipLaunchKernelGGL(k_gcr_dots, dim3(gx, gy), dim3(TPB), 0, c.stream, W, w, n, j, c.partials);
+    WDMG_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_gcr_dots_fin, dim3(1), dim3(TPB), 0, c.stream, j, (int)gx, c.partials, c.dsc, hslot,
+                       nrmslot);
+    WDMG_HIP(hipGetLastError());
+  }
+  run_reduce(c, GcrAxpyCoefOp{W, Z, w, z, r, c.dsc + hslot, n, j, c.dsc, nrmslot + j, S_TMP}, n);
 }
 
-void gcr_step(Ctx& c, const cx<double>* w, const cx<double>* z, cx<double>* x, cx<double>* r, size_t n, int j,
-              int nrmslot, int rslot) {
-  run_reduce(c, GcrCoefOp{w, r, c.dsc, nrmslot + j, S_TMP}, n);
-  run_reduce(c, GcrUpdateOp{w, z, x, r, c.dsc + S_TMP, c.dsc, rslot}, n);
+void gcr_step(Ctx& c, const cx<double>* w, const cx<double>* z, cx<double>* x, cx<double>* r, size_t n, int rslot,
+              double* host) {
+  run_reduce(c, GcrUpdateOp{w, z, x, r, c.dsc + S_TMP, c.dsc, rslot, host}, n);
 }
 
 void xmy_norm(Ctx& c, const cx<double>* b, cx<double>* y, size_t n, int slot) {

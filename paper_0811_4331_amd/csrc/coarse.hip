@@ -277,13 +277,15 @@ __global__ __launch_bounds__(256) void k_coarse_build(Side side, AggGeom a, cons
 // (lane = row), and the nine partial rows are summed in a fixed order.
 template <typename R>
 __global__ __launch_bounds__(576) void k_coarse_apply(Geom g, int n2, const cx<R>* __restrict__ Dc,
-                                                      const cx<R>* __restrict__ in, cx<R>* __restrict__ out) {
+                                                      const cx<R>* __restrict__ in, cx<R>* __restrict__ out,
+                                                      cx<R>* __restrict__ copy) {
   __shared__ cx<R> part[9][64];
   const int s = blockIdx.x, rhs = blockIdx.y;
   const int d = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const size_t nsite = g.vol;
   in += (size_t)rhs * nsite * n2;
   out += (size_t)rhs * nsite * n2;
+  if (copy && d == 8 && lane < n2) copy[(size_t)rhs * nsite * n2 + (size_t)s * n2 + lane] = in[(size_t)s * n2 + lane];
   int nb = s;
   if (d < 8) {
     int c[4];
@@ -345,9 +347,10 @@ void coarse_buildC(Ctx& c, const Level& f, Level& cl) {
 }
 
 template <typename R>
-void coarse_apply(Ctx& c, const Level& cl, const cx<R>* Dc, cx<R>* out, const cx<R>* in, int nrhs) {
+void coarse_apply(Ctx& c, const Level& cl, const cx<R>* Dc, cx<R>* out, const cx<R>* in, int nrhs, cx<R>* copy) {
   ProfScope ps(c, sizeof(R) == 8 ? WDMG_K_DC_F64 : WDMG_K_DC_F32, (long long)cl.nsite * nrhs);
-  hipLaunchKernelGGL((k_coarse_apply<R>), dim3(cl.nsite, nrhs), dim3(576), 0, c.stream, cl.g, cl.dof, Dc, in, out);
+  hipLaunchKernelGGL((k_coarse_apply<R>), dim3(cl.nsite, nrhs), dim3(576), 0, c.stream, cl.g, cl.dof, Dc, in, out,
+                     copy);
   WDMG_HIP(hipGetLastError());
   c.n_Dc[cl.l] += nrhs;
 }
@@ -362,7 +365,9 @@ void coarse_shift(Ctx& c, Level& cl, double dm) {
   WDMG_HIP(hipGetLastError());
 }
 
-template void coarse_apply<double>(Ctx&, const Level&, const cx<double>*, cx<double>*, const cx<double>*, int);
-template void coarse_apply<float>(Ctx&, const Level&, const cx<float>*, cx<float>*, const cx<float>*, int);
+template void coarse_apply<double>(Ctx&, const Level&, const cx<double>*, cx<double>*, const cx<double>*, int,
+                                   cx<double>*);
+template void coarse_apply<float>(Ctx&, const Level&, const cx<float>*, cx<float>*, const cx<float>*, int,
+                                  cx<float>*);
 
 }  // namespace wdmg

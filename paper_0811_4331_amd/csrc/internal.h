@@ -100,7 +100,8 @@ struct Ctx {
   double* partials = nullptr;   // reduction partials
   unsigned* counter = nullptr;  // last-block counters
   double* hsc = nullptr;        // pinned host mirror of a few scalars
-  double* hring = nullptr;      // pinned ring for lagged residual checks
+  double* hring = nullptr;      // pinned ring for lagged residual checks (host view)
+  double* dring = nullptr;      // the same ring as seen from the device
   hipEvent_t ring_ev[kRing] = {};
 
   // multigrid
@@ -197,14 +198,16 @@ void update2_batch(Ctx& c, cx<R>* x, const cx<R>* u, cx<R>* r, const cx<R>* v, s
 template <typename R> void norm2(Ctx& c, const cx<R>* a, size_t n, int slot);
 // dsc[slot] = <a, b>
 template <typename R> void dot(Ctx& c, const cx<R>* a, const cx<R>* b, size_t n, int slot);
-// GCR orthogonalisation: h_i = <W_i, w> / nrm_i (i < j) into dsc[hslot + 2 i];
-// then w -= sum h_i W_i, z -= sum h_i Z_i.  W, Z: j contiguous vectors of n.
-void gcr_orth(Ctx& c, const cx<double>* W, const cx<double>* Z, cx<double>* w, cx<double>* z,
+// GCR orthogonalisation (classical Gram-Schmidt against the j earlier
+// directions): h_i = <W_i, w> / nrm_i into dsc[hslot + 2 i]; w -= sum h_i W_i,
+// z -= sum h_i Z_i; then nrm_j = <w,w> -> dsc[nrmslot + j] and the step
+// a = <w, r> / nrm_j -> dsc[S_TMP].  W, Z: j contiguous vectors of n.
+void gcr_orth(Ctx& c, const cx<double>* W, const cx<double>* Z, cx<double>* w, cx<double>* z, const cx<double>* r,
               size_t n, int j, int hslot, int nrmslot);
-// GCR step: nrm_j = <w,w> -> dsc[nrmslot + j]; a = <w, r> / nrm_j;
-// x += a z; r -= a w; dsc[rslot] = ||r||^2.
-void gcr_step(Ctx& c, const cx<double>* w, const cx<double>* z, cx<double>* x, cx<double>* r,
-              size_t n, int j, int nrmslot, int rslot);
+// GCR step: x += a z; r -= a w; dsc[rslot] = ||r||^2 (and *host when given,
+// a device-visible pinned host address).
+void gcr_step(Ctx& c, const cx<double>* w, const cx<double>* z, cx<double>* x, cx<double>* r, size_t n, int rslot,
+              double* host = nullptr);
 // y = b - y (residual from an operator application); dsc[slot] = ||y||^2.
 void xmy_norm(Ctx& c, const cx<double>* b, cx<double>* y, size_t n, int slot);
 // BiCGStab kernels (FP64).
@@ -232,8 +235,10 @@ void block_qrC(Ctx& c, const Level& f, cx<double>* V);
 // Coarse operator (coarse.hip).
 void coarse_build0(Ctx& c, const Level& f, Level& cl);
 void coarse_buildC(Ctx& c, const Level& f, Level& cl);
+// out = D_c in; when copy is given, copy = in as well (one pass).
 template <typename R>
-void coarse_apply(Ctx& c, const Level& cl, const cx<R>* Dc, cx<R>* out, const cx<R>* in, int nrhs);
+void coarse_apply(Ctx& c, const Level& cl, const cx<R>* Dc, cx<R>* out, const cx<R>* in, int nrhs,
+                  cx<R>* copy = nullptr);
 void coarse_shift(Ctx& c, Level& cl, double dm);
 
 }  // namespace wdmg

@@ -221,12 +221,9 @@ void coarsest_solve(Ctx& c, cx<double>* x, const cx<double>* b) {
     for (int j = 0; j < k && it < c.mg.coarse_maxit; ++j, ++it) {
       cx<double>* z = Zb + (size_t)j * n;
       cx<double>* w = Wb + (size_t)j * n;
-      copy<double>(c, z, r, n);
-      apply_op<double>(c, l, w, z, 1);
-      gcr_orth(c, Wb, Zb, w, z, n, j, hslot, nrmslot);
-      gcr_step(c, w, z, x, r, n, j, nrmslot, S_RNORM + l);
-      WDMG_HIP(hipMemcpyAsync(c.hring + it % kRing, c.dsc + S_RNORM + l, sizeof(double), hipMemcpyDeviceToHost,
-                              c.stream));
+      coarse_apply<double>(c, L, L.Dc64, w, r, 1, z);  // w = D_c r, z = r
+      gcr_orth(c, Wb, Zb, w, z, r, n, j, hslot, nrmslot);
+      gcr_step(c, w, z, x, r, n, S_RNORM + l, c.dring + it % kRing);
       WDMG_HIP(hipEventRecord(c.ring_ev[it % kRing], c.stream));
       if (it >= lag && converged_at(it - lag)) return;
     }
@@ -355,8 +352,8 @@ int fgcr(Ctx& c, cx<double>* x, const cx<double>* b, const wdmg_solve_params& p,
         copy<double>(c, z, r, n);
       }
       dslash<double>(c, w, z, 1);
-      gcr_orth(c, Wb, Zb, w, z, n, j, hslot, nrmslot);
-      gcr_step(c, w, z, x, r, n, j, nrmslot, S_RNORM);
+      gcr_orth(c, Wb, Zb, w, z, r, n, j, hslot, nrmslot);
+      gcr_step(c, w, z, x, r, n, S_RNORM);
       ++st.iters;
       rn2 = read_scalar(c, S_RNORM);
       if (!std::isfinite(rn2)) throw Error(WDMG_ERR_NAN, "NaN in the outer solve");
