@@ -160,11 +160,15 @@ int wdmg_prolong(wdmg_ctx* ctx, int level, void* f_out, const void* c_in, int nr
  * Canonical layout of level l. */
 int wdmg_smooth(wdmg_ctx* ctx, int level, void* x, const void* b, int nrhs, int iters, int prec);
 
-/* Sec. 5: solve D x = b for nrhs right-hand sides with flexible GCR(k),
- * preconditioned by the multigrid V-cycle (params->precond = 1) or not.
- * x (device, canonical complex128) holds the initial guess and receives the
- * solution; b is not modified.  stats: host array of nrhs entries or NULL.
- * Synchronises. */
+/* Sec. 5: solve D x = b for nrhs (1..64) right-hand sides with flexible
+ * GCR(k), preconditioned by the multigrid V-cycle (params->precond = 1) or
+ * not.  The right-hand sides are solved together: each keeps its own Krylov
+ * coefficients, step sizes and stopping test (a converged one is frozen),
+ * while every operator pass (D, V-cycle, D_c, P, P^dagger) is shared by the
+ * batch.  x (device, canonical complex128) holds the initial guesses and
+ * receives the solutions; b is not modified.  stats: host array of nrhs
+ * entries or NULL; `seconds`, `n_D` and `n_Dc` report the batch's totals
+ * divided by nrhs.  Synchronises. */
 int wdmg_solve(wdmg_ctx* ctx, void* x, const void* b, int nrhs,
                const wdmg_solve_params* params, wdmg_solve_stats* stats);
 

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "fine_field.h"
 #include "internal.h"
@@ -135,7 +136,7 @@ void smooth_impl(Ctx& c, int level, void* x, const void* b, int nrhs, int iters)
     }
     apply_op<R>(c, level, ri, xi, 1);
     xmy<R>(c, bi, ri, n);
-    mr<R>(c, level, xi, ri, p, iters, omega);
+    mr<R>(c, level, xi, ri, p, 1, iters, omega);
     if (level == 0)
       fine_out<R>(c, xi, static_cast<cx<R>*>(x) + (size_t)k * ncan, 1);
     else
@@ -143,11 +144,15 @@ void smooth_impl(Ctx& c, int level, void* x, const void* b, int nrhs, int iters)
   }
 }
 
-void ensure_solve_io(Ctx& c) {
+void ensure_solve_io(Ctx& c, int nrhs) {
   const size_t n = (size_t)c.g0.vpad * 12;
-  if (!c.sol_x) {
-    c.sol_x = static_cast<cx<double>*>(dev_alloc(c, n * sizeof(cx<double>)));
-    c.sol_b = static_cast<cx<double>*>(dev_alloc(c, n * sizeof(cx<double>)));
+  if (nrhs > c.sol_cap) {
+    WDMG_HIP(hipStreamSynchronize(c.stream));
+    dev_free(c, c.sol_x);
+    dev_free(c, c.sol_b);
+    c.sol_x = static_cast<cx<double>*>(dev_alloc(c, (size_t)nrhs * n * sizeof(cx<double>)));
+    c.sol_b = static_cast<cx<double>*>(dev_alloc(c, (size_t)nrhs * n * sizeof(cx<double>)));
+    c.sol_cap = nrhs;
   }
 }
 
@@ -213,12 +218,12 @@ int wdmg_create(wdmg_ctx** out, const int dims[4], const wdmg_alloc* alloc, void
   }
   int rc = guarded(c, [&]() {
     c->dsc = static_cast<double*>(dev_alloc(*c, S_TOTAL * sizeof(double)));
-    c->partials = static_cast<double*>(dev_alloc(*c, (size_t)64 * kMaxReduceBlocks * 3 * sizeof(double)));
+    c->partials = static_cast<double*>(dev_alloc(*c, (size_t)8192 * 16 * sizeof(double)));
     c->counter = static_cast<unsigned*>(dev_alloc(*c, 256 * sizeof(unsigned)));
     WDMG_HIP(hipMemsetAsync(c->dsc, 0, S_TOTAL * sizeof(double), c->stream));
     WDMG_HIP(hipMemsetAsync(c->counter, 0, 256 * sizeof(unsigned), c->stream));
-    WDMG_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->hsc), 64 * sizeof(double), hipHostMallocDefault));
-    WDMG_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->hring), kRing * sizeof(double),
+    WDMG_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->hsc), kHscSize * sizeof(double), hipHostMallocDefault));
+    WDMG_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->hring), kRing * kMaxRhs * sizeof(double),
                            hipHostMallocMapped | hipHostMallocCoherent));
     WDMG_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&c->dring), c->hring, 0));
     for (int i = 0; i < kRing; ++i) WDMG_HIP(hipEventCreateWithFlags(&c->ring_ev[i], hipEventDisableTiming));
@@ -403,36 +408,34 @@ int wdmg_solve(wdmg_ctx* c, void* x, const void* b, int nrhs, const wdmg_solve_p
     need_ptr(x, "x");
     need_ptr(b, "b");
     need_ptr(p, "params");
-    need_nrhs(nrhs);
     need_gauge(*c);
-    if (!(p->tol > 0.0) || p->restart < 1 || p->restart > 128 || p->maxit < 1)
+    if (nrhs < 1 || nrhs > kMaxRhs) throw Error(WDMG_ERR_ARG, "nrhs must be in 1..64 for a solve");
+    if (!(p->tol > 0.0) || p->restart < 1 || p->restart > kMaxKrylov || p->maxit < 1)
       throw Error(WDMG_ERR_ARG, "bad solve parameters");
     if (p->precond) {
       if (!c->have_mg) throw Error(WDMG_ERR_NOT_SETUP, "no multigrid hierarchy set up");
       if (p->mg_prec != WDMG_F64 && p->mg_prec != WDMG_F32)
         throw Error(WDMG_ERR_ARG, "the V-cycle runs in WDMG_F64 or WDMG_F32");
     }
-    ensure_solve_io(*c);
-    ensure_fine_work(*c);
-    const size_t n = (size_t)c->g0.vol * 12;  // canonical stride per rhs
-    int worst = WDMG_OK;
-    for (int k = 0; k < nrhs; ++k) {
-      wdmg_solve_stats st{};
-      c->n_D = 0;
-      for (int l = 0; l < WDMG_MAX_LEVELS; ++l) c->n_Dc[l] = 0;
-      const double t0 = now();
-      fine_in<double>(*c, static_cast<const cx<double>*>(b) + k * n, c->sol_b, 1);
-      fine_in<double>(*c, static_cast<const cx<double>*>(x) + k * n, c->sol_x, 1);
-      const int rc = fgcr(*c, c->sol_x, c->sol_b, *p, st);
-      fine_out<double>(*c, c->sol_x, static_cast<cx<double>*>(x) + k * n, 1);
-      WDMG_HIP(hipStreamSynchronize(c->stream));
-      st.seconds = now() - t0;
-      st.n_D = c->n_D;
-      for (int l = 0; l < WDMG_MAX_LEVELS; ++l) st.n_Dc[l] = c->n_Dc[l];
-      if (stats) stats[k] = st;
-      if (rc != WDMG_OK) worst = rc;
+    ensure_solve_io(*c, nrhs);
+    std::vector<wdmg_solve_stats> st(nrhs);
+    c->n_D = 0;
+    for (int l = 0; l < WDMG_MAX_LEVELS; ++l) c->n_Dc[l] = 0;
+    const double t0 = now();
+    fine_in<double>(*c, b, c->sol_b, nrhs);
+    fine_in<double>(*c, x, c->sol_x, nrhs);
+    const int rc = fgcr(*c, c->sol_x, c->sol_b, nrhs, *p, st.data());
+    fine_out<double>(*c, c->sol_x, x, nrhs);
+    WDMG_HIP(hipStreamSynchronize(c->stream));
+    const double secs = now() - t0;
+    for (int q = 0; q < nrhs; ++q) {
+      // operator applications and wall time are shared by the batch: per rhs
+      st[q].seconds = secs / nrhs;
+      st[q].n_D = c->n_D / nrhs;
+      for (int l = 0; l < WDMG_MAX_LEVELS; ++l) st[q].n_Dc[l] = c->n_Dc[l] / nrhs;
+      if (stats) stats[q] = st[q];
     }
-    return worst;
+    return rc;
   });
 }
 
@@ -444,7 +447,7 @@ int wdmg_solve_bicgstab(wdmg_ctx* c, void* x, const void* b, int nrhs, double to
     need_nrhs(nrhs);
     need_gauge(*c);
     if (!(tol > 0.0) || maxit < 1) throw Error(WDMG_ERR_ARG, "bad solve parameters");
-    ensure_solve_io(*c);
+    ensure_solve_io(*c, 1);
     const size_t n = (size_t)c->g0.vol * 12;  // canonical stride per rhs
     int worst = WDMG_OK;
     for (int k = 0; k < nrhs; ++k) {

@@ -531,6 +531,14 @@ __global__ void k_gcr_axpy(const cx<double>* __restrict__ W, const cx<double>* _
   }
 }
 
+__global__ void k_fill_pairs(double* dsc, int slot, int count, double re, double im) {
+  const int i = threadIdx.x;
+  if (i < count) {
+    dsc[slot + 2 * i] = re;
+    dsc[slot + 2 * i + 1] = im;
+  }
+}
+
 __global__ void k_set_scalar(double* dsc, int slot, double re, double im) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     dsc[slot] = re;
@@ -590,10 +598,171 @@ void dot(Ctx& c, const cx<R>* a, const cx<R>* b, size_t n, int slot) {
   run_reduce(c, DotOp<R>{a, b, c.dsc, slot}, n);
 }
 
+// ---- batched GCR ------------------------------------------------------------
+__global__ __launch_bounds__(TPB) void k_gcr_dots_b(const cx<double>* __restrict__ W, const cx<double>* __restrict__ w,
+                                                    size_t n, int nb, int j, int gx, int gy, double* partials) {
+  __shared__ double lds[2 * GCR_G * (TPB / 64)];
+  const int rhs = blockIdx.z;
+  const int i0 = blockIdx.y * GCR_G;
+  const int ni = min(GCR_G, j - i0);
+  const cx<double>* wr = w + (size_t)rhs * n;
+  double v[2 * GCR_G];
+#pragma unroll
+  for (int k = 0; k < 2 * GCR_G; ++k) v[k] = 0.0;
+  for (size_t e = blockIdx.x * (size_t)TPB + threadIdx.x; e < n; e += (size_t)gridDim.x * TPB) {
+    const cx<double> y = wr[e];
+#pragma unroll
+    for (int q = 0; q < GCR_G; ++q) {
+      if (q < ni) {
+        const cx<double> x = W[((size_t)(i0 + q) * nb + rhs) * n + e];
+        v[2 * q] += x.re * y.re + x.im * y.im;
+        v[2 * q + 1] += x.re * y.im - x.im * y.re;
+      }
+    }
+  }
+  block_sum<2 * GCR_G>(v, lds);
+  if (threadIdx.x == 0) {
+    const size_t myblk = ((size_t)rhs * gy + blockIdx.y) * gx + blockIdx.x;
+#pragma unroll
+    for (int k = 0; k < 2 * GCR_G; ++k) partials[myblk * 2 * GCR_G + k] = v[k];
+  }
+}
+
+__global__ __launch_bounds__(TPB) void k_gcr_dots_b_fin(int j, int gx, int gy, const double* partials, double* g) {
+  const int rhs = blockIdx.x;
+  for (int t = threadIdx.x; t < 2 * j; t += TPB) {
+    const int i = t >> 1, part = t & 1;
+    const int yy = i / GCR_G, q = i % GCR_G;
+    double s = 0.0;
+    for (int bx = 0; bx < gx; ++bx) s += partials[(((size_t)rhs * gy + yy) * gx + bx) * 2 * GCR_G + 2 * q + part];
+    const double nrm = g[G_NRM + rhs * kMaxKrylov + i];
+    g[G_H + rhs * 2 * kMaxKrylov + t] = nrm > 0.0 ? s / nrm : 0.0;
+  }
+}
+
+struct GcrAxpyCoefBOp {
+  static constexpr int K = 3;
+  const cx<double>* W;
+  const cx<double>* Z;
+  cx<double>* w;
+  cx<double>* z;
+  const cx<double>* r;
+  double* g;
+  double* dsc;
+  size_t n;
+  int nb, j;
+  __device__ void acc(size_t e, int rhs, double* v) const {
+    const size_t o = (size_t)rhs * n + e;
+    cx<double> a = w[o], b = z[o];
+    const double* h = g + G_H + rhs * 2 * kMaxKrylov;
+    for (int i = 0; i < j; ++i) {
+      const cx<double> hi = mk(h[2 * i], h[2 * i + 1]);
+      const size_t oi = ((size_t)i * nb + rhs) * n + e;
+      a = a - hi * W[oi];
+      b = b - hi * Z[oi];
+    }
+    if (j > 0) {
+      w[o] = a;
+      z[o] = b;
+    }
+    const cx<double> y = r[o];
+    v[0] += a.re * a.re + a.im * a.im;
+    v[1] += a.re * y.re + a.im * y.im;
+    v[2] += a.re * y.im - a.im * y.re;
+  }
+  __device__ void fin(const double* v, int rhs) const {
+    if (bad(v[0]) || bad(v[1]) || bad(v[2])) dsc[S_ERR] = 1.0;
+    g[G_NRM + rhs * kMaxKrylov + j] = v[0];
+    const bool on = g[G_ACT + rhs] != 0.0 && v[0] > 0.0;
+    g[G_A + 2 * rhs] = on ? v[1] / v[0] : 0.0;
+    g[G_A + 2 * rhs + 1] = on ? v[2] / v[0] : 0.0;
+  }
+};
+
+struct GcrUpdateBOp {
+  static constexpr int K = 1;
+  const cx<double>* w;
+  const cx<double>* z;
+  cx<double>* x;
+  cx<double>* r;
+  double* g;
+  double* dsc;
+  double* host;
+  size_t n;
+  __device__ void acc(size_t e, int rhs, double* v) const {
+    const size_t o = (size_t)rhs * n + e;
+    const cx<double> s = mk(g[G_A + 2 * rhs], g[G_A + 2 * rhs + 1]);
+    x[o] = x[o] + s * z[o];
+    const cx<double> ri = r[o] - s * w[o];
+    r[o] = ri;
+    v[0] += ri.re * ri.re + ri.im * ri.im;
+  }
+  __device__ void fin(const double* v, int rhs) const {
+    if (bad(v[0])) dsc[S_ERR] = 1.0;
+    g[G_RN + rhs] = v[0];
+    if (host) host[rhs] = v[0];
+  }
+};
+
+struct Norm2BOp {
+  static constexpr int K = 1;
+  const cx<double>* a;
+  double* g;
+  double* dsc;
+  double* host;
+  size_t n;
+  __device__ void acc(size_t e, int rhs, double* v) const {
+    const cx<double> x = a[(size_t)rhs * n + e];
+    v[0] += x.re * x.re + x.im * x.im;
+  }
+  __device__ void fin(const double* v, int rhs) const {
+    if (bad(v[0])) dsc[S_ERR] = 1.0;
+    g[G_RN + rhs] = v[0];
+    if (host) host[rhs] = v[0];
+  }
+};
+
+struct XmyNormBOp {
+  static constexpr int K = 1;
+  const cx<double>* b;
+  cx<double>* y;
+  double* g;
+  double* dsc;
+  size_t n;
+  __device__ void acc(size_t e, int rhs, double* v) const {
+    const size_t o = (size_t)rhs * n + e;
+    const cx<double> d = b[o] - y[o];
+    y[o] = d;
+    v[0] += d.re * d.re + d.im * d.im;
+  }
+  __device__ void fin(const double* v, int rhs) const {
+    if (bad(v[0])) dsc[S_ERR] = 1.0;
+    g[G_RN + rhs] = v[0];
+  }
+};
+
+template <class Op>
+void run_reduce_b(Ctx& c, const Op& op, size_t n, int nb) {
+  unsigned nblk = reduce_blocks(n);
+  if (nblk * nb > 8192) nblk = 8192 / nb;
+  if (nblk < 1) nblk = 1;
+  hipLaunchKernelGGL((k_reduce_b_part<Op>), dim3(nblk, nb), dim3(TPB), 0, c.stream, op, n, c.partials);
+  WDMG_HIP(hipGetLastError());
+  hipLaunchKernelGGL((k_reduce_b_fin<Op>), dim3(nb), dim3(TPB), 0, c.stream, op, (int)nblk, c.partials);
+  WDMG_HIP(hipGetLastError());
+}
+
+__global__ void k_set_active(double* g, const double* flags, int nb) {
+  const int i = threadIdx.x;
+  if (i < nb) g[G_ACT + i] = flags[i];
+}
+
 template <typename R>
 void step_alpha_batch(Ctx& c, const cx<R>* a, const cx<R>* b, size_t n, size_t stride, int nb, double scale,
                       int slot) {
-  const unsigned nblk = reduce_blocks(n);
+  unsigned nblk = reduce_blocks(n);
+  if (nblk * nb > 8192) nblk = 8192 / nb;
+  if (nblk < 1) nblk = 1;
   const StepAlphaBatchOp<R> op{a, b, stride, scale, c.dsc, slot};
   hipLaunchKernelGGL((k_reduce_b_part<StepAlphaBatchOp<R>>), dim3(nblk, nb), dim3(TPB), 0, c.stream, op, n,
                      c.partials);
@@ -632,6 +801,45 @@ void gcr_step(Ctx& c, const cx<double>* w, const cx<double>* z, cx<double>* x, c
   run_reduce(c, GcrUpdateOp{w, z, x, r, c.dsc + S_TMP, c.dsc, rslot, host}, n);
 }
 
+void gcr_orth_b(Ctx& c, const cx<double>* W, const cx<double>* Z, cx<double>* w, cx<double>* z,
+                const cx<double>* r, size_t n, int nb, int j, int gl) {
+  double* g = c.dsc + gcr_base(gl);
+  if (j > 0) {
+    const int gy = (j + GCR_G - 1) / GCR_G;
+    int gx = (int)reduce_blocks(n);
+    if ((size_t)gx * gy * nb > 8192) gx = 8192 / (gy * nb);
+    if (gx < 1) gx = 1;
+    hipLaunchKernelGGL(k_gcr_dots_b, dim3(gx, gy, nb), dim3(TPB), 0, c.stream, W, w, n, nb, j, gx, gy, c.partials);
+    WDMG_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_gcr_dots_b_fin, dim3(nb), dim3(TPB), 0, c.stream, j, gx, gy, c.partials, g);
+    WDMG_HIP(hipGetLastError());
+  }
+  run_reduce_b(c, GcrAxpyCoefBOp{W, Z, w, z, r, g, c.dsc, n, nb, j}, n, nb);
+}
+
+void gcr_step_b(Ctx& c, const cx<double>* w, const cx<double>* z, cx<double>* x, cx<double>* r, size_t n, int nb,
+                int gl, double* host) {
+  run_reduce_b(c, GcrUpdateBOp{w, z, x, r, c.dsc + gcr_base(gl), c.dsc, host, n}, n, nb);
+}
+
+void norm2_b(Ctx& c, const cx<double>* a, size_t n, int nb, int gl, double* host) {
+  run_reduce_b(c, Norm2BOp{a, c.dsc + gcr_base(gl), c.dsc, host, n}, n, nb);
+}
+
+void xmy_norm_b(Ctx& c, const cx<double>* b, cx<double>* y, size_t n, int nb, int gl) {
+  run_reduce_b(c, XmyNormBOp{b, y, c.dsc + gcr_base(gl), c.dsc, n}, n, nb);
+}
+
+void set_active(Ctx& c, int gl, const double* host_flags, int nb) {
+  // staged through pinned memory so the copy is asynchronous and stream-ordered;
+  // every reader of c.hsc synchronises the stream first, so the slot is free
+  double* stage = c.hsc + kHscFlags;
+  WDMG_HIP(hipStreamSynchronize(c.stream));
+  for (int i = 0; i < nb; ++i) stage[i] = host_flags[i];
+  WDMG_HIP(hipMemcpyAsync(c.dsc + gcr_base(gl) + G_ACT, stage, nb * sizeof(double), hipMemcpyHostToDevice,
+                          c.stream));
+}
+
 void xmy_norm(Ctx& c, const cx<double>* b, cx<double>* y, size_t n, int slot) {
   run_reduce(c, XmyNormOp{b, y, c.dsc, slot}, n);
 }
@@ -654,6 +862,11 @@ void bicg_xr(Ctx& c, cx<double>* x, cx<double>* r, const cx<double>* p, const cx
              const cx<double>* rhat, size_t n) {
   run_reduce(c, BicgXrOp{x, r, p, s, t, rhat, c.dsc}, n);
 }
+void fill_pairs(Ctx& c, int slot, int count, double re, double im) {
+  hipLaunchKernelGGL(k_fill_pairs, dim3(1), dim3(kMaxRhs), 0, c.stream, c.dsc, slot, count, re, im);
+  WDMG_HIP(hipGetLastError());
+}
+
 void set_scalar(Ctx& c, int slot, double re, double im) {
   hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(64), 0, c.stream, c.dsc, slot, re, im);
   WDMG_HIP(hipGetLastError());

@@ -31,17 +31,31 @@ Geom make_geom(const int L[4], const int B[4]);
 // ---------------------------------------------------------------------------
 // Device scalar area.  Solver coefficients live here and are consumed by
 // kernels directly; the host reads back only residual norms.
+constexpr int kMaxRhs = 64;     // right-hand sides solved together
+constexpr int kMaxKrylov = 128;  // GCR restart length limit
+
 enum ScalarSlot {
-  S_ERR = 0,        // NaN / rank flags (as doubles)
-  S_MR = 8,         // MR / correction step: alpha (re, im)
+  S_ERR = 0,        // NaN / rank / SU(3) flags (as doubles)
+  S_MR = 8,         // single MR / correction step: alpha (re, im)
   S_TMP = 16,       // misc: norms, dots
   S_BICG = 32,      // BiCGStab: rho, alpha, omega, beta, ... (complex)
   S_RNORM = 64,     // residual norm^2 per level (real)
-  S_GCR = 128,      // GCR coefficients: per level a block of 4 * 128 doubles
+  S_GCR = 128,      // unused (kept for layout stability)
   S_GCR_STRIDE = 512,
-  S_BATCH = S_GCR + 4 * S_GCR_STRIDE,  // batched step sizes (64 complex)
-  S_TOTAL = S_BATCH + 128
+  S_BATCH = S_GCR + 4 * S_GCR_STRIDE,  // batched step sizes: 2 per rhs
+  // Batched GCR state, one block per level (0..3) and one for the outer solve
+  // (index 4): h [rhs][2*kMaxKrylov], nrm [rhs][kMaxKrylov], a [rhs][2],
+  // rnorm^2 [rhs], active [rhs].
+  G_H = 0,
+  G_NRM = G_H + kMaxRhs * 2 * kMaxKrylov,
+  G_A = G_NRM + kMaxRhs * kMaxKrylov,
+  G_RN = G_A + 2 * kMaxRhs,
+  G_ACT = G_RN + kMaxRhs,
+  G_STRIDE = G_ACT + kMaxRhs,
+  S_G = S_BATCH + 2 * kMaxRhs,
+  S_TOTAL = S_G + 5 * G_STRIDE
 };
+inline int gcr_base(int slot_level) { return S_G + slot_level * G_STRIDE; }
 
 // ---------------------------------------------------------------------------
 // Memory owned by a context.
@@ -69,9 +83,11 @@ struct Level {
   // coarse operator of this level (l >= 1): [site][9][col][row]
   cx<double>* Dc64 = nullptr;
   cx<float>* Dc32 = nullptr;
-  // work vectors of the V-cycle at this level
+  // work vectors of the V-cycle at this level, each holding `cap` fields
   cx<double>* w64[8] = {};
   cx<float>* w32[8] = {};
+  int cap64 = 0, cap32 = 0;
+  int capB = 0;         // capacity (rhs) of the coarsest GCR basis
   // GCR basis of the coarsest solve (coarsest level only)
   cx<double>* basisZ = nullptr;
   cx<double>* basisW = nullptr;
@@ -80,6 +96,8 @@ struct Level {
 constexpr int kWork = 8;
 
 constexpr int kRing = 8;
+constexpr int kHscFlags = 128;   // offset of the active-flag staging area in Ctx::hsc
+constexpr int kHscSize = 256;
 
 struct Ctx {
   int dims[4];
@@ -100,7 +118,7 @@ struct Ctx {
   double* partials = nullptr;   // reduction partials
   unsigned* counter = nullptr;  // last-block counters
   double* hsc = nullptr;        // pinned host mirror of a few scalars
-  double* hring = nullptr;      // pinned ring for lagged residual checks (host view)
+  double* hring = nullptr;      // pinned ring [kRing][kMaxRhs] for lagged residual checks (host view)
   double* dring = nullptr;      // the same ring as seen from the device
   hipEvent_t ring_ev[kRing] = {};
 
@@ -126,6 +144,9 @@ struct Ctx {
   cx<double>* bicg[6] = {};
   cx<double>* sol_x = nullptr;   // internal x, b of a solve
   cx<double>* sol_b = nullptr;
+  int sol_cap = 0;
+  int outer_cap = 0;             // rhs capacity of the outer basis
+  int outer_cap32 = 0;
 
   // kernel timing (instrumentation)
   bool prof_on = false;
@@ -194,6 +215,21 @@ void step_alpha_batch(Ctx& c, const cx<R>* a, const cx<R>* b, size_t n, size_t s
 template <typename R>
 void update2_batch(Ctx& c, cx<R>* x, const cx<R>* u, cx<R>* r, const cx<R>* v, size_t n, size_t stride, int nb,
                    int slot);
+// Batched GCR over nb right-hand sides.  Fields of one rhs are n long and
+// consecutive (batch stride n); basis vector i of all rhs is W + i*nb*n.
+// State in the block gcr_base(g): h, nrm, a, rnorm^2, active (see ScalarSlot).
+void gcr_orth_b(Ctx& c, const cx<double>* W, const cx<double>* Z, cx<double>* w, cx<double>* z,
+                const cx<double>* r, size_t n, int nb, int j, int g);
+// x += a z; r -= a w per rhs (a = 0 for inactive rhs); rnorm^2 per rhs, also
+// to host (device-visible pinned address, nb doubles) when given.
+void gcr_step_b(Ctx& c, const cx<double>* w, const cx<double>* z, cx<double>* x, cx<double>* r, size_t n, int nb,
+                int g, double* host = nullptr);
+// rnorm^2 of nb fields into the block g (and host when given).
+void norm2_b(Ctx& c, const cx<double>* a, size_t n, int nb, int g, double* host = nullptr);
+// y = b - y per rhs, with rnorm^2 into block g.
+void xmy_norm_b(Ctx& c, const cx<double>* b, cx<double>* y, size_t n, int nb, int g);
+// sets active flags of block g from a host array (nb doubles, 1 or 0)
+void set_active(Ctx& c, int g, const double* host_flags, int nb);
 // dsc[slot] = ||a||^2
 template <typename R> void norm2(Ctx& c, const cx<R>* a, size_t n, int slot);
 // dsc[slot] = <a, b>
@@ -218,6 +254,8 @@ void bicg_omega(Ctx& c, const cx<double>* t, const cx<double>* s, size_t n);
 void bicg_xr(Ctx& c, cx<double>* x, cx<double>* r, const cx<double>* p, const cx<double>* s,
              const cx<double>* t, const cx<double>* rhat, size_t n);
 void set_scalar(Ctx& c, int slot, double re, double im);
+// dsc[slot + 2 i] = re, dsc[slot + 2 i + 1] = im for i < count (count <= kMaxRhs)
+void fill_pairs(Ctx& c, int slot, int count, double re, double im);
 
 // Transfer (transfer.hip).
 template <typename R>

@@ -174,20 +174,69 @@ void prolong_from(Ctx& c, int l, const cx<R>* crs, cx<R>* fine, int nrhs) {
 }
 
 // ---------------------------------------------------------------------------
-// MR smoother (Sec. 3): p = A r; alpha = omega <p,r>/<p,p>; x += alpha r; r -= alpha p.
+// Work space.  Every level keeps kWork fields per right-hand side in each
+// precision it runs in; the buffers grow to the largest batch seen.
 template <typename R>
-void mr(Ctx& c, int l, cx<R>* x, cx<R>* r, cx<R>* p, int iters, double omega) {
+void ensure_work(Ctx& c, int l, int nrhs) {
+  Level& L = c.lev[l];
+  int& cap = sizeof(R) == 8 ? L.cap64 : L.cap32;
+  if (nrhs <= cap) return;
+  WDMG_HIP(hipStreamSynchronize(c.stream));
+  for (int i = 0; i < kWork; ++i) {
+    if (l == 0 && (i == 0 || i > 4)) continue;  // the fine level uses work fields 1..4 only
+    if constexpr (sizeof(R) == 8) {
+      dev_free(c, L.w64[i]);
+      L.w64[i] = static_cast<cx<double>*>(dev_alloc(c, (size_t)nrhs * L.n * sizeof(cx<double>)));
+    } else {
+      dev_free(c, L.w32[i]);
+      L.w32[i] = static_cast<cx<float>*>(dev_alloc(c, (size_t)nrhs * L.n * sizeof(cx<float>)));
+    }
+  }
+  cap = nrhs;
+}
+
+void ensure_coarsest_basis(Ctx& c, int nrhs) {
+  Level& L = c.lev[c.nlevels - 1];
+  if (nrhs <= L.capB) return;
+  WDMG_HIP(hipStreamSynchronize(c.stream));
+  dev_free(c, L.basisZ);
+  dev_free(c, L.basisW);
+  const size_t sz = (size_t)c.mg.coarse_restart * nrhs * L.n * sizeof(cx<double>);
+  L.basisZ = static_cast<cx<double>*>(dev_alloc(c, sz));
+  L.basisW = static_cast<cx<double>*>(dev_alloc(c, sz));
+  L.capB = nrhs;
+}
+
+// Work space of a whole V-cycle solve with nrhs right-hand sides in precision prec.
+void ensure_mg_work(Ctx& c, int nrhs, int prec) {
+  for (int l = 0; l < c.nlevels; ++l) {
+    if (prec == WDMG_F32)
+      ensure_work<float>(c, l, nrhs);
+    else
+      ensure_work<double>(c, l, nrhs);
+  }
+  // the coarsest solve runs in FP64 whatever the V-cycle precision
+  ensure_work<double>(c, c.nlevels - 1, nrhs);
+  ensure_coarsest_basis(c, nrhs);
+}
+
+// ---------------------------------------------------------------------------
+// MR smoother (Sec. 3): p = A r; alpha = omega <p,r>/<p,p>; x += alpha r;
+// r -= alpha p, with one step size per right-hand side.
+template <typename R>
+void mr(Ctx& c, int l, cx<R>* x, cx<R>* r, cx<R>* p, int nrhs, int iters, double omega) {
   const size_t n = c.lev[l].n;
   for (int it = 0; it < iters; ++it) {
-    apply_op<R>(c, l, p, r, 1);
-    step_alpha<R>(c, p, r, n, omega, S_MR);
-    update2<R>(c, x, r, r, p, n, S_MR);
+    apply_op<R>(c, l, p, r, nrhs);
+    step_alpha_batch<R>(c, p, r, n, n, nrhs, omega, S_BATCH);
+    update2_batch<R>(c, x, r, r, p, n, n, nrhs, S_BATCH);
   }
 }
 
 // ---------------------------------------------------------------------------
-// Coarsest solve: GCR(restart) on D_c in FP64 to relative tolerance tol_c.
-void coarsest_solve(Ctx& c, cx<double>* x, const cx<double>* b) {
+// Coarsest solve: GCR(restart) on D_c in FP64 to relative tolerance tol_c,
+// for nrhs right-hand sides together (each with its own coefficients).
+void coarsest_solve(Ctx& c, cx<double>* x, const cx<double>* b, int nrhs) {
   const int l = c.nlevels - 1;
   Level& L = c.lev[l];
   const size_t n = L.n;
@@ -195,35 +244,44 @@ void coarsest_solve(Ctx& c, cx<double>* x, const cx<double>* b) {
   cx<double>* r = L.w64[1];
   cx<double>* Zb = L.basisZ;
   cx<double>* Wb = L.basisW;
-  const int hslot = S_GCR + l * S_GCR_STRIDE, nrmslot = hslot + 2 * 128;
-  zero<double>(c, x, n);
-  copy<double>(c, r, b, n);
-  norm2<double>(c, r, n, S_RNORM + l);
-  const double bn2 = read_scalar(c, S_RNORM + l);
-  if (!(bn2 > 0.0)) {
+  const size_t bs = (size_t)nrhs * n;  // one basis slot for all rhs
+  zero<double>(c, x, bs);
+  copy<double>(c, r, b, bs);
+  // |b|^2 per rhs, read once (synchronous)
+  norm2_b(c, r, n, nrhs, l, c.dring);
+  WDMG_HIP(hipStreamSynchronize(c.stream));
+  double tol2[kMaxRhs];
+  bool any = false;
+  for (int q = 0; q < nrhs; ++q) {
+    const double bn2 = c.hring[q];
     if (!std::isfinite(bn2)) throw Error(WDMG_ERR_NAN, "NaN in the coarsest right-hand side");
-    return;
+    tol2[q] = c.mg.coarse_tol * c.mg.coarse_tol * bn2;
+    any = any || bn2 > 0.0;
   }
-  const double tol2 = c.mg.coarse_tol * c.mg.coarse_tol * bn2;
-  // The residual of iteration it is copied to pinned memory asynchronously
-  // and inspected `lag` iterations later, so the stream never drains while
-  // the host waits; up to `lag` extra iterations (which only reduce the
-  // residual further) are the price.
+  if (!any) return;
+  // The residuals of iteration it land in pinned memory and are inspected
+  // `lag` iterations later, so the stream never drains while the host
+  // waits; up to `lag` extra iterations (which only reduce the residuals
+  // further) are the price.
   const int lag = 2;
   int it = 0;
   auto converged_at = [&](int i) {
     WDMG_HIP(hipEventSynchronize(c.ring_ev[i % kRing]));
-    const double rn2 = c.hring[i % kRing];
-    if (!std::isfinite(rn2)) throw Error(WDMG_ERR_NAN, "NaN in the coarsest solve");
-    return rn2 <= tol2;
+    const double* rn = c.hring + (size_t)(i % kRing) * kMaxRhs;
+    bool all = true;
+    for (int q = 0; q < nrhs; ++q) {
+      if (!std::isfinite(rn[q])) throw Error(WDMG_ERR_NAN, "NaN in the coarsest solve");
+      all = all && rn[q] <= tol2[q];
+    }
+    return all;
   };
   while (it < c.mg.coarse_maxit) {
     for (int j = 0; j < k && it < c.mg.coarse_maxit; ++j, ++it) {
-      cx<double>* z = Zb + (size_t)j * n;
-      cx<double>* w = Wb + (size_t)j * n;
-      coarse_apply<double>(c, L, L.Dc64, w, r, 1, z);  // w = D_c r, z = r
-      gcr_orth(c, Wb, Zb, w, z, r, n, j, hslot, nrmslot);
-      gcr_step(c, w, z, x, r, n, S_RNORM + l, c.dring + it % kRing);
+      cx<double>* z = Zb + (size_t)j * bs;
+      cx<double>* w = Wb + (size_t)j * bs;
+      coarse_apply<double>(c, L, L.Dc64, w, r, nrhs, z);  // w = D_c r, z = r
+      gcr_orth_b(c, Wb, Zb, w, z, r, n, nrhs, j, l);
+      gcr_step_b(c, w, z, x, r, n, nrhs, l, c.dring + (size_t)(it % kRing) * kMaxRhs);
       WDMG_HIP(hipEventRecord(c.ring_ev[it % kRing], c.stream));
       if (it >= lag && converged_at(it - lag)) return;
     }
@@ -235,143 +293,176 @@ void coarsest_solve(Ctx& c, cx<double>* x, const cx<double>* b) {
 // ---------------------------------------------------------------------------
 // V-cycle M_l (Sec. 2 / Sec. 3 / Sec. 5): x = M_l b from x = 0.
 template <typename R>
-void vcycle(Ctx& c, int l, cx<R>* x, const cx<R>* b);
+void vcycle(Ctx& c, int l, cx<R>* x, const cx<R>* b, int nrhs);
 
 template <typename R>
-void coarse_correction(Ctx& c, int l, const cx<R>* res, cx<R>* y) {
+void coarse_correction(Ctx& c, int l, const cx<R>* res, cx<R>* y, int nrhs) {
   Level& C = c.lev[l + 1];
-  const size_t nc = C.n;
+  const size_t nc = C.n * nrhs;
   cx<R>* rc = work<R>(C, 5);
   cx<R>* ec = work<R>(C, 6);
-  restrict_to<R>(c, l, res, rc, 1);
+  restrict_to<R>(c, l, res, rc, nrhs);
   if (l + 1 == c.nlevels - 1) {
     // coarsest level: FP64 GCR
     if constexpr (sizeof(R) == 8) {
-      coarsest_solve(c, ec, rc);
+      coarsest_solve(c, ec, rc, nrhs);
     } else {
       convert<double, float>(c, C.w64[5], rc, nc);
-      coarsest_solve(c, C.w64[6], C.w64[5]);
+      coarsest_solve(c, C.w64[6], C.w64[5], nrhs);
       convert<float, double>(c, ec, C.w64[6], nc);
     }
   } else {
-    // stationary iteration e <- e + M_{l+1} (r_c - D_{l+1} e) from e = 0
+    // Sec. 5: stationary iteration e <- e + M_{l+1} (r_c - D_{l+1} e) from e = 0
     const int ncyc = c.mg.coarse_cycles > 0 ? c.mg.coarse_cycles : 1;
     cx<R>* t = work<R>(C, 7);
     cx<R>* xo = work<R>(C, 0);
-    vcycle<R>(c, l + 1, xo, rc);
+    vcycle<R>(c, l + 1, xo, rc, nrhs);
     copy<R>(c, ec, xo, nc);
     for (int it = 1; it < ncyc; ++it) {
-      apply_op<R>(c, l + 1, t, ec, 1);
+      apply_op<R>(c, l + 1, t, ec, nrhs);
       xmy<R>(c, rc, t, nc);
-      vcycle<R>(c, l + 1, xo, t);
+      vcycle<R>(c, l + 1, xo, t, nrhs);
       add<R>(c, ec, xo, nc);
     }
   }
-  prolong_from<R>(c, l, ec, y, 1);
+  prolong_from<R>(c, l, ec, y, nrhs);
 }
 
 template <typename R>
-void vcycle(Ctx& c, int l, cx<R>* x, const cx<R>* b) {
+void vcycle(Ctx& c, int l, cx<R>* x, const cx<R>* b, int nrhs) {
   Level& L = c.lev[l];
   const size_t n = L.n;
   cx<R>* res = work<R>(L, 1);
   cx<R>* p = work<R>(L, 2);
   cx<R>* y = work<R>(L, 3);
   cx<R>* dy = work<R>(L, 4);
-  zero<R>(c, x, n);
-  copy<R>(c, res, b, n);
-  mr<R>(c, l, x, res, p, c.mg.nu_pre, c.mg.omega);
-  coarse_correction<R>(c, l, res, y);
-  apply_op<R>(c, l, dy, y, 1);
+  zero<R>(c, x, n * nrhs);
+  copy<R>(c, res, b, n * nrhs);
+  mr<R>(c, l, x, res, p, nrhs, c.mg.nu_pre, c.mg.omega);
+  coarse_correction<R>(c, l, res, y, nrhs);
+  apply_op<R>(c, l, dy, y, nrhs);
   if (c.mg.use_alpha)
-    step_alpha<R>(c, dy, res, n, 1.0, S_MR);
+    step_alpha_batch<R>(c, dy, res, n, n, nrhs, 1.0, S_BATCH);  // Sec. 3 step-size equation
   else
-    set_scalar(c, S_MR, 1.0, 0.0);
-  update2<R>(c, x, y, res, dy, n, S_MR);
-  mr<R>(c, l, x, res, p, c.mg.nu_post, c.mg.omega);
+    fill_pairs(c, S_BATCH, nrhs, 1.0, 0.0);
+  update2_batch<R>(c, x, y, res, dy, n, n, nrhs, S_BATCH);
+  mr<R>(c, l, x, res, p, nrhs, c.mg.nu_post, c.mg.omega);
 }
 
 #define INST(R)                                                                \
-  template void vcycle<R>(Ctx&, int, cx<R>*, const cx<R>*);                   \
+  template void vcycle<R>(Ctx&, int, cx<R>*, const cx<R>*, int);              \
   template void apply_op<R>(Ctx&, int, cx<R>*, const cx<R>*, int);            \
   template void restrict_to<R>(Ctx&, int, const cx<R>*, cx<R>*, int);         \
   template void prolong_from<R>(Ctx&, int, const cx<R>*, cx<R>*, int);        \
-  template void mr<R>(Ctx&, int, cx<R>*, cx<R>*, cx<R>*, int, double);
+  template void mr<R>(Ctx&, int, cx<R>*, cx<R>*, cx<R>*, int, int, double);   \
+  template void ensure_work<R>(Ctx&, int, int);
 INST(double)
 INST(float)
 #undef INST
 
 // ---------------------------------------------------------------------------
-// Outer flexible GCR(k) in FP64 (Sec. 5) for one right-hand side held in
-// internal layout: b (input), x (initial guess, output).
-int fgcr(Ctx& c, cx<double>* x, const cx<double>* b, const wdmg_solve_params& p, wdmg_solve_stats& st) {
+// Outer flexible GCR(k) in FP64 (Sec. 5) for nrhs right-hand sides in
+// lockstep, each with its own coefficients; a converged right-hand side is
+// frozen (its steps are zero).  b (input) and x (initial guess, output) are
+// nrhs internal fields.
+int fgcr(Ctx& c, cx<double>* x, const cx<double>* b, int nrhs, const wdmg_solve_params& p, wdmg_solve_stats* st) {
   Level& L = c.lev[0];
   const size_t n = L.n;
+  const size_t bs = n * nrhs;
   const int k = p.restart;
-  ensure_outer(c, k, p.precond && p.mg_prec == WDMG_F32);
+  const bool f32 = p.precond && p.mg_prec == WDMG_F32;
+  ensure_outer(c, k, nrhs, f32);
+  if (p.precond) ensure_mg_work(c, nrhs, f32 ? WDMG_F32 : WDMG_F64);
   cx<double>* r = c.outer_r;
   cx<double>* Zb = c.outer_Z;
   cx<double>* Wb = c.outer_W;
-  const int hslot = S_GCR + 3 * S_GCR_STRIDE, nrmslot = hslot + 2 * 128;
+  const int G = 4;  // scalar block of the outer solve
   set_scalar(c, S_ERR, 0.0, 0.0);
-  norm2<double>(c, b, n, S_TMP + 4);
-  const double bn2 = read_scalar(c, S_TMP + 4);
-  if (!std::isfinite(bn2)) throw Error(WDMG_ERR_NAN, "NaN or Inf in the right-hand side");
-  st.iters = 0;
-  st.restarts = 0;
-  st.converged = 0;
-  if (bn2 == 0.0) {
-    zero<double>(c, x, n);
-    st.converged = 1;
-    st.true_res = 0.0;
-    return WDMG_OK;
+  norm2_b(c, b, n, nrhs, G, c.dring);
+  WDMG_HIP(hipStreamSynchronize(c.stream));
+  double bn2[kMaxRhs], tol2[kMaxRhs], act[kMaxRhs];
+  int nact = 0;
+  for (int q = 0; q < nrhs; ++q) {
+    bn2[q] = c.hring[q];
+    if (!std::isfinite(bn2[q])) throw Error(WDMG_ERR_NAN, "NaN or Inf in the right-hand side");
+    tol2[q] = p.tol * p.tol * bn2[q];
+    st[q].iters = st[q].restarts = st[q].converged = 0;
+    st[q].true_res = 0.0;
   }
-  const double tol2 = p.tol * p.tol * bn2;
   // r = b - D x
-  dslash<double>(c, r, x, 1);
-  xmy_norm(c, b, r, n, S_RNORM);
-  double rn2 = read_scalar(c, S_RNORM);
-  while (true) {
-    if (rn2 <= tol2) {
-      st.converged = 1;
-      break;
+  dslash<double>(c, r, x, nrhs);
+  xmy_norm_b(c, b, r, n, nrhs, G);
+  auto read_rn = [&](double* out) {
+    WDMG_HIP(hipMemcpyAsync(c.hsc, c.dsc + gcr_base(G) + G_RN, nrhs * sizeof(double), hipMemcpyDeviceToHost,
+                            c.stream));
+    WDMG_HIP(hipStreamSynchronize(c.stream));
+    for (int q = 0; q < nrhs; ++q) {
+      out[q] = c.hsc[q];
+      if (!std::isfinite(out[q])) throw Error(WDMG_ERR_NAN, "NaN in the outer solve");
     }
-    if (st.iters >= p.maxit) break;
-    for (int j = 0; j < k && st.iters < p.maxit; ++j) {
-      cx<double>* z = Zb + (size_t)j * n;
-      cx<double>* w = Wb + (size_t)j * n;
+  };
+  double rn2[kMaxRhs];
+  read_rn(rn2);
+  auto update_active = [&]() {
+    nact = 0;
+    for (int q = 0; q < nrhs; ++q) {
+      const bool on = bn2[q] > 0.0 && rn2[q] > tol2[q] && st[q].iters < p.maxit;
+      act[q] = on ? 1.0 : 0.0;
+      nact += on;
+    }
+    set_active(c, G, act, nrhs);
+  };
+  int total = 0;
+  while (true) {
+    update_active();
+    if (nact == 0) break;
+    for (int j = 0; j < k && nact > 0; ++j) {
+      cx<double>* z = Zb + (size_t)j * bs;
+      cx<double>* w = Wb + (size_t)j * bs;
       if (p.precond) {
-        if (p.mg_prec == WDMG_F32) {
-          convert<float, double>(c, c.outer_r32, r, n);
-          vcycle<float>(c, 0, c.outer_z32, c.outer_r32);
-          convert<double, float>(c, z, c.outer_z32, n);
+        if (f32) {
+          convert<float, double>(c, c.outer_r32, r, bs);
+          vcycle<float>(c, 0, c.outer_z32, c.outer_r32, nrhs);
+          convert<double, float>(c, z, c.outer_z32, bs);
         } else {
-          vcycle<double>(c, 0, z, r);
+          vcycle<double>(c, 0, z, r, nrhs);
         }
       } else {
-        copy<double>(c, z, r, n);
+        copy<double>(c, z, r, bs);
       }
-      dslash<double>(c, w, z, 1);
-      gcr_orth(c, Wb, Zb, w, z, r, n, j, hslot, nrmslot);
-      gcr_step(c, w, z, x, r, n, S_RNORM);
-      ++st.iters;
-      rn2 = read_scalar(c, S_RNORM);
-      if (!std::isfinite(rn2)) throw Error(WDMG_ERR_NAN, "NaN in the outer solve");
-      if (rn2 <= tol2) break;
+      dslash<double>(c, w, z, nrhs);
+      gcr_orth_b(c, Wb, Zb, w, z, r, n, nrhs, j, G);
+      gcr_step_b(c, w, z, x, r, n, nrhs, G);
+      for (int q = 0; q < nrhs; ++q) st[q].iters += act[q] != 0.0;
+      ++total;
+      read_rn(rn2);
+      bool changed = false;
+      for (int q = 0; q < nrhs; ++q)
+        if (act[q] != 0.0 && (rn2[q] <= tol2[q] || st[q].iters >= p.maxit)) changed = true;
+      if (changed) update_active();
     }
     // restart (or claimed convergence): recompute the true residual in FP64
-    dslash<double>(c, r, x, 1);
-    xmy_norm(c, b, r, n, S_RNORM);
-    rn2 = read_scalar(c, S_RNORM);
-    if (rn2 <= tol2) {
-      st.converged = 1;
-      break;
+    dslash<double>(c, r, x, nrhs);
+    xmy_norm_b(c, b, r, n, nrhs, G);
+    read_rn(rn2);
+    bool again = false;
+    for (int q = 0; q < nrhs; ++q) {
+      if (bn2[q] > 0.0 && rn2[q] > tol2[q] && st[q].iters < p.maxit) {
+        ++st[q].restarts;
+        again = true;
+      }
     }
-    ++st.restarts;
+    if (!again) break;
   }
-  st.true_res = std::sqrt(rn2 / bn2);
+  int rc = WDMG_OK;
+  for (int q = 0; q < nrhs; ++q) {
+    st[q].converged = bn2[q] == 0.0 || rn2[q] <= tol2[q];
+    st[q].true_res = bn2[q] > 0.0 ? std::sqrt(rn2[q] / bn2[q]) : 0.0;
+    if (!st[q].converged) rc = WDMG_NOT_CONVERGED;
+  }
+  (void)total;
   check_flags(c);
-  return st.converged ? WDMG_OK : WDMG_NOT_CONVERGED;
+  return rc;
 }
 
 // ---------------------------------------------------------------------------
@@ -469,11 +560,13 @@ void free_hierarchy(Ctx& c) {
     dev_free(c, L.basisW);
     Level blank;
     if (l == 0) {
-      // level 0 work vectors are owned by the context's fine pool
+      // level 0 work vectors outlive the hierarchy (same geometry)
       for (int i = 0; i < kWork; ++i) {
         blank.w64[i] = L.w64[i];
         blank.w32[i] = L.w32[i];
       }
+      blank.cap64 = L.cap64;
+      blank.cap32 = L.cap32;
     }
     L = blank;
   }
@@ -584,47 +677,45 @@ void mg_setup(Ctx& c, const wdmg_mg_params& p) {
     else
       coarse_buildC(c, F, C);
     convert<float, double>(c, C.Dc32, C.Dc64, dcn);
-    for (int i = 0; i < kWork; ++i) {
-      C.w64[i] = static_cast<cx<double>*>(dev_alloc(c, C.n * sizeof(cx<double>)));
-      C.w32[i] = static_cast<cx<float>*>(dev_alloc(c, C.n * sizeof(cx<float>)));
-    }
   }
-  // coarsest GCR basis
+  // coarse-level GCR blocks: every right-hand side active
   {
-    Level& L = c.lev[p.n_levels - 1];
-    L.basisZ = static_cast<cx<double>*>(dev_alloc(c, (size_t)p.coarse_restart * L.n * sizeof(cx<double>)));
-    L.basisW = static_cast<cx<double>*>(dev_alloc(c, (size_t)p.coarse_restart * L.n * sizeof(cx<double>)));
+    double ones[kMaxRhs];
+    for (int q = 0; q < kMaxRhs; ++q) ones[q] = 1.0;
+    for (int l = 1; l < p.n_levels; ++l) set_active(c, l, ones, kMaxRhs);
   }
-  ensure_fine_work(c);
   WDMG_HIP(hipStreamSynchronize(c.stream));
   check_flags(c);
   c.have_mg = true;
 }
 
 void ensure_fine_work(Ctx& c) {
-  Level& L = c.lev[0];
-  if (L.w64[0]) return;
-  const size_t n = (size_t)c.g0.vpad * 12;
-  for (int i = 0; i < kWork; ++i) {
-    L.w64[i] = static_cast<cx<double>*>(dev_alloc(c, n * sizeof(cx<double>)));
-    L.w32[i] = static_cast<cx<float>*>(dev_alloc(c, n * sizeof(cx<float>)));
-  }
+  ensure_work<double>(c, 0, 1);
+  ensure_work<float>(c, 0, 1);
 }
 
-void ensure_outer(Ctx& c, int k, bool need32) {
+void ensure_outer(Ctx& c, int k, int nrhs, bool need32) {
   const size_t n = (size_t)c.g0.vpad * 12;
-  if (k > c.outer_k) {
+  if (k > c.outer_k || nrhs > c.outer_cap) {
     WDMG_HIP(hipStreamSynchronize(c.stream));
     dev_free(c, c.outer_Z);
     dev_free(c, c.outer_W);
-    c.outer_Z = static_cast<cx<double>*>(dev_alloc(c, (size_t)k * n * sizeof(cx<double>)));
-    c.outer_W = static_cast<cx<double>*>(dev_alloc(c, (size_t)k * n * sizeof(cx<double>)));
-    c.outer_k = k;
+    dev_free(c, c.outer_r);
+    const int kk = k > c.outer_k ? k : c.outer_k;
+    const int cc = nrhs > c.outer_cap ? nrhs : c.outer_cap;
+    c.outer_Z = static_cast<cx<double>*>(dev_alloc(c, (size_t)kk * cc * n * sizeof(cx<double>)));
+    c.outer_W = static_cast<cx<double>*>(dev_alloc(c, (size_t)kk * cc * n * sizeof(cx<double>)));
+    c.outer_r = static_cast<cx<double>*>(dev_alloc(c, (size_t)cc * n * sizeof(cx<double>)));
+    c.outer_k = kk;
+    c.outer_cap = cc;
   }
-  if (!c.outer_r) c.outer_r = static_cast<cx<double>*>(dev_alloc(c, n * sizeof(cx<double>)));
-  if (need32 && !c.outer_r32) {
-    c.outer_r32 = static_cast<cx<float>*>(dev_alloc(c, n * sizeof(cx<float>)));
-    c.outer_z32 = static_cast<cx<float>*>(dev_alloc(c, n * sizeof(cx<float>)));
+  if (need32 && nrhs > c.outer_cap32) {
+    WDMG_HIP(hipStreamSynchronize(c.stream));
+    dev_free(c, c.outer_r32);
+    dev_free(c, c.outer_z32);
+    c.outer_r32 = static_cast<cx<float>*>(dev_alloc(c, (size_t)nrhs * n * sizeof(cx<float>)));
+    c.outer_z32 = static_cast<cx<float>*>(dev_alloc(c, (size_t)nrhs * n * sizeof(cx<float>)));
+    c.outer_cap32 = nrhs;
   }
 }
 
