@@ -57,11 +57,13 @@ def parse():
     ap.add_argument("--L", type=int, default=16, help="lattice extent (L^4)")
     ap.add_argument("--eps", type=float, default=0.3)
     ap.add_argument("--delta", type=float, default=0.01, help="m - m_crit")
+    ap.add_argument("--mass", type=float, default=None,
+                    help="use this bare mass instead of m_crit + delta (no m_crit lookup)")
     ap.add_argument("--nv", type=int, default=20)
     ap.add_argument("--setup-iters", type=int, default=100)
     ap.add_argument("--nrhs", type=int, default=1)
     ap.add_argument("--mg-prec", default="f64", choices=["f64", "f32"])
-    ap.add_argument("--coarse-tol", type=float, default=1e-2)
+    ap.add_argument("--coarse-tol", type=float, default=0.1)
     ap.add_argument("--no-alpha", action="store_true",
                     help="skip the minimal-residual step after prolongation (alpha = 1)")
     ap.add_argument("--big-L", type=int, default=32, help="lattice for the out-of-cache Dslash figure (0: skip)")
@@ -174,7 +176,11 @@ def main():
     i_eps = {0.2: 0, 0.3: 1, 0.45: 2}.get(a.eps, 9)
     cfg = 1 if L == 8 else 2  # workload numbering of the seeds: 8^4 -> 1, 16^4 -> 2
     gseed = synthetic.gauge_seed(cfg, i_eps)
-    m = load_mcrit(dims, a.eps, gseed) + a.delta
+    if a.mass is not None:
+        m = a.mass
+        a.delta = float("nan")
+    else:
+        m = load_mcrit(dims, a.eps, gseed) + a.delta
     u = synthetic.gauge_field(dims, a.eps, gseed)
     ctx = wdmg.Context(dims, dev)
     ctx.set_gauge(torch.from_numpy(u).to(dev), t_bc=-1)

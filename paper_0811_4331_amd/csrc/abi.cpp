@@ -178,7 +178,7 @@ void wdmg_default_mg_params(wdmg_mg_params* p) {
   p->nu_pre = 2;
   p->nu_post = 2;
   p->coarse_cycles = 4;
-  p->coarse_tol = 1e-2;
+  p->coarse_tol = 1e-1;
   p->coarse_maxit = 200;
   p->coarse_restart = 32;
   p->use_alpha = 1;

@@ -742,7 +742,26 @@ struct XmyNormBOp {
 };
 
 template <class Op>
+__global__ __launch_bounds__(TPB1) void k_reduce_b_one(Op op, size_t n) {
+  constexpr int K = Op::K;
+  __shared__ double lds[K * (TPB1 / 64)];
+  const int y = blockIdx.x;
+  double v[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = 0.0;
+  for (size_t i = threadIdx.x; i < n; i += TPB1) op.acc(i, y, v);
+  block_sum<K>(v, lds);
+  if (threadIdx.x == 0) op.fin(v, y);
+}
+
+template <class Op>
 void run_reduce_b(Ctx& c, const Op& op, size_t n, int nb) {
+  if (n <= kSingleBlockMax / 4) {
+    // one workgroup per right-hand side, no second launch
+    hipLaunchKernelGGL((k_reduce_b_one<Op>), dim3(nb), dim3(TPB1), 0, c.stream, op, n);
+    WDMG_HIP(hipGetLastError());
+    return;
+  }
   unsigned nblk = reduce_blocks(n);
   if (nblk * nb > 8192) nblk = 8192 / nb;
   if (nblk < 1) nblk = 1;

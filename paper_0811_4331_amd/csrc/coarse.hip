@@ -18,6 +18,8 @@
 namespace wdmg {
 namespace {
 
+constexpr int kMfmaMinRhs = 2;  // batches of at least this many rhs use the matrix cores
+
 struct AggGeom {
   Geom g;       // geometry of the finer level
   int b[4];     // aggregate extents
@@ -308,6 +310,130 @@ __global__ __launch_bounds__(576) void k_coarse_apply(Geom g, int n2, const cx<R
   }
 }
 
+// ---- batched application on the matrix cores ---------------------------------
+// For a block of right-hand sides the coarse operator at one site is a
+// complex GEMM, y = [X | Y_{+x} | ... | Y_{-t}] [c(x); c(x+x); ...; c(x-t)],
+// (2Nv x 9*2Nv) x (9*2Nv x nrhs).  It runs as the equivalent real GEMM with
+// re/im-interleaved rows and columns: the complex entry a of row i, column j
+// becomes the 2x2 block [[Re a, -Im a], [Im a, Re a]], and the right-hand
+// sides enter as (Re, Im) row pairs.  The flop count equals the complex one.
+// One workgroup per (site, rhs tile); wave t owns a tile of real rows; the
+// right-hand-side operand of one direction is staged in LDS at a time.
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+// real-row r, real-col k of the complex block stored column-major (col j, row i)
+template <typename R>
+__device__ __forceinline__ R real_entry(const cx<R>* __restrict__ blk, int n2, int r, int k) {
+  const int i = r >> 1, j = k >> 1;
+  if (i >= n2) return (R)0;
+  const cx<R> a = blk[(size_t)j * n2 + i];
+  const int pr = r & 1, pk = k & 1;
+  return pr == 0 ? (pk == 0 ? a.re : -a.im) : (pk == 0 ? a.im : a.re);
+}
+
+// FP64: v_mfma_f64_16x16x4f64; tile = 16 real rows x 16 rhs.
+// Operand lanes: A[i][k] at lane i + 16k, B[k][j] at lane j + 16k;
+// result D[i][j] in lane j + 16 (i % 4), register i / 4.
+__global__ __launch_bounds__(512) void k_coarse_apply_mfma64(Geom g, int n2, int nrhs,
+                                                             const cx<double>* __restrict__ Dc,
+                                                             const cx<double>* __restrict__ in,
+                                                             cx<double>* __restrict__ out,
+                                                             cx<double>* __restrict__ copy) {
+  __shared__ double Bs[128][17];
+  extern __shared__ cx<double> As64[];  // the block of the current direction, column-major
+  const int s = blockIdx.x, q0 = blockIdx.y * 16;
+  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const size_t nsite = g.vol, fs = nsite * n2;
+  const int kr = 2 * n2;  // real columns per direction
+  int c[4];
+  coords_of(g, s, c);
+  doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int d = 0; d < 9; ++d) {
+    const int nb = d == 8 ? s : ((d & 1) ? nbr_bwd(g, s, c, d >> 1) : nbr_fwd(g, s, c, d >> 1));
+    __syncthreads();
+    for (int w = threadIdx.x; w < 16 * n2; w += blockDim.x) {
+      const int q = w / n2, j = w % n2;
+      cx<double> v = mk(0.0, 0.0);
+      if (q0 + q < nrhs) v = in[(size_t)(q0 + q) * fs + (size_t)nb * n2 + j];
+      Bs[2 * j][q] = v.re;
+      Bs[2 * j + 1][q] = v.im;
+      if (d == 8 && copy && q0 + q < nrhs) copy[(size_t)(q0 + q) * fs + (size_t)s * n2 + j] = v;
+    }
+    const cx<double>* blk = Dc + ((size_t)s * 9 + d) * n2 * n2;
+    for (int w = threadIdx.x; w < n2 * n2; w += blockDim.x) As64[w] = blk[w];
+    __syncthreads();
+    const int r = wave * 16 + (l & 15);
+    for (int k0 = 0; k0 < kr; k0 += 4) {
+      const int k = k0 + (l >> 4);
+      const double a = real_entry(As64, n2, r, k);
+      const double b = Bs[k][l & 15];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+  }
+  const int q = q0 + (l & 15);
+  if (q < nrhs) {
+    double* o = reinterpret_cast<double*>(out + (size_t)q * fs + (size_t)s * n2);
+#pragma unroll
+    for (int reg = 0; reg < 4; ++reg) {
+      const int r = wave * 16 + 4 * reg + (l >> 4);
+      if ((r >> 1) < n2) o[r] = acc[reg];  // real row r = 2 i + part is element r of the site's (re, im) pairs
+    }
+  }
+}
+
+// FP32: v_mfma_f32_32x32x2f32; tile = 32 real rows x 32 rhs.
+// Operand lanes: A[i][k] at lane i + 32k, B[k][j] at lane j + 32k; result
+// D[i][j] in lane j + 32 ((i / 4) % 2), register 4 (i / 8) + i % 4.
+__global__ __launch_bounds__(256) void k_coarse_apply_mfma32(Geom g, int n2, int nrhs,
+                                                             const cx<float>* __restrict__ Dc,
+                                                             const cx<float>* __restrict__ in,
+                                                             cx<float>* __restrict__ out,
+                                                             cx<float>* __restrict__ copy) {
+  __shared__ float Bs[128][33];
+  extern __shared__ cx<float> As32[];
+  const int s = blockIdx.x, q0 = blockIdx.y * 32;
+  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const size_t nsite = g.vol, fs = nsite * n2;
+  const int kr = 2 * n2;
+  int c[4];
+  coords_of(g, s, c);
+  floatx16 acc;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) acc[e] = 0.f;
+  for (int d = 0; d < 9; ++d) {
+    const int nb = d == 8 ? s : ((d & 1) ? nbr_bwd(g, s, c, d >> 1) : nbr_fwd(g, s, c, d >> 1));
+    __syncthreads();
+    for (int w = threadIdx.x; w < 32 * n2; w += blockDim.x) {
+      const int q = w / n2, j = w % n2;
+      cx<float> v = mk(0.f, 0.f);
+      if (q0 + q < nrhs) v = in[(size_t)(q0 + q) * fs + (size_t)nb * n2 + j];
+      Bs[2 * j][q] = v.re;
+      Bs[2 * j + 1][q] = v.im;
+      if (d == 8 && copy && q0 + q < nrhs) copy[(size_t)(q0 + q) * fs + (size_t)s * n2 + j] = v;
+    }
+    const cx<float>* blk = Dc + ((size_t)s * 9 + d) * n2 * n2;
+    for (int w = threadIdx.x; w < n2 * n2; w += blockDim.x) As32[w] = blk[w];
+    __syncthreads();
+    const int r = wave * 32 + (l & 31);
+    for (int k0 = 0; k0 < kr; k0 += 2) {
+      const int k = k0 + (l >> 5);
+      const float a = real_entry(As32, n2, r, k);
+      const float b = Bs[k][l & 31];
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+    }
+  }
+  const int q = q0 + (l & 31);
+  if (q < nrhs) {
+    float* o = reinterpret_cast<float*>(out + (size_t)q * fs + (size_t)s * n2);
+#pragma unroll
+    for (int reg = 0; reg < 16; ++reg) {
+      const int r = wave * 32 + 8 * (reg >> 2) + 4 * (l >> 5) + (reg & 3);
+      if ((r >> 1) < n2) o[r] = acc[reg];
+    }
+  }
+}
+
 template <typename R>
 __global__ void k_coarse_shift(cx<R>* Dc, int nsite, int n2, double dm) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -348,6 +474,32 @@ void coarse_buildC(Ctx& c, const Level& f, Level& cl) {
 
 template <typename R>
 void coarse_apply(Ctx& c, const Level& cl, const cx<R>* Dc, cx<R>* out, const cx<R>* in, int nrhs, cx<R>* copy) {
+  const int n2 = cl.dof;
+  if (nrhs >= kMfmaMinRhs && n2 <= 64) {
+    // matrix-core path for a batch of right-hand sides
+    if constexpr (sizeof(R) == 8) {
+      ProfScope ps(c, WDMG_K_DC_MFMA_F64, (long long)cl.nsite * nrhs);
+      const int waves = (2 * n2 + 15) / 16;
+      const size_t lds = (size_t)n2 * n2 * sizeof(cx<double>);
+      static bool attr = false;
+      if (!attr) {
+        WDMG_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_coarse_apply_mfma64),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 64 * sizeof(cx<double>)));
+        attr = true;
+      }
+      hipLaunchKernelGGL(k_coarse_apply_mfma64, dim3(cl.nsite, (nrhs + 15) / 16), dim3(64 * waves), lds, c.stream,
+                         cl.g, n2, nrhs, Dc, in, out, copy);
+    } else {
+      ProfScope ps(c, WDMG_K_DC_MFMA_F32, (long long)cl.nsite * nrhs);
+      const int waves = (2 * n2 + 31) / 32;
+      const size_t lds = (size_t)n2 * n2 * sizeof(cx<float>);
+      hipLaunchKernelGGL(k_coarse_apply_mfma32, dim3(cl.nsite, (nrhs + 31) / 32), dim3(64 * waves), lds, c.stream,
+                         cl.g, n2, nrhs, Dc, in, out, copy);
+    }
+    WDMG_HIP(hipGetLastError());
+    c.n_Dc[cl.l] += nrhs;
+    return;
+  }
   ProfScope ps(c, sizeof(R) == 8 ? WDMG_K_DC_F64 : WDMG_K_DC_F32, (long long)cl.nsite * nrhs);
   hipLaunchKernelGGL((k_coarse_apply<R>), dim3(cl.nsite, nrhs), dim3(576), 0, c.stream, cl.g, cl.dof, Dc, in, out,
                      copy);

@@ -28,7 +28,7 @@ ERRORS = {-1: "WDMG_ERR_ARG", -2: "WDMG_ERR_DIMS", -3: "WDMG_ERR_OOM", -4: "WDMG
           -5: "WDMG_ERR_NOT_SETUP", -6: "WDMG_ERR_NAN", -7: "WDMG_ERR_RANK_DEFICIENT"}
 PREC = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
 KERNELS = ["dslash_f64", "dslash_f32", "dc_f64", "dc_f32", "restrict_f64", "restrict_f32",
-           "prolong_f64", "prolong_f32", "dc_build", "block_qr"]
+           "prolong_f64", "prolong_f32", "dc_build", "block_qr", "dc_mfma_f64", "dc_mfma_f32"]
 MAX_LEVELS = 4
 
 
@@ -225,7 +225,7 @@ class Context:
         return out
 
     def mg_setup(self, levels, *, omega=0.8, nu_pre=2, nu_post=2, coarse_cycles=4,
-                 coarse_tol=1e-2, coarse_maxit=200, coarse_restart=32, use_alpha=True):
+                 coarse_tol=1e-1, coarse_maxit=200, coarse_restart=32, use_alpha=True):
         """``levels``: list of dicts ``{block, nv, setup_iters, vectors}`` per coarsening;
         ``vectors`` is a complex128 device tensor ``[nv, <level l field shape>]``."""
         p = MgParams()
