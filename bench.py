@@ -109,6 +109,21 @@ def dslash_bandwidth(wdmg, synthetic, torch, dev, L, reps=20):
         out[prec] = {"lattice": f"{L}^4", "us_per_launch": sec * 1e6,
                      "GB_s": DSLASH_BYTES[prec] * units / n / sec / 1e9,
                      "frac_hbm_peak": DSLASH_BYTES[prec] * units / n / sec / 1e9 / HBM_PEAK_GBS}
+    # a batch of 8 right-hand sides (links read once per 2 (FP64) or 4 (FP32) rhs)
+    xb = psi.unsqueeze(0).repeat(8, 1, 1, 1, 1, 1, 1)
+    for prec, key in (("f64", "dslash_f64"), ("f32", "dslash_f32")):
+        x = xb if prec == "f64" else xb.to(torch.complex64)
+        ctx.apply_D(x, prec=prec)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        for _ in range(max(2, reps // 4)):
+            ctx.apply_D(x, prec=prec)
+        n, units, ms = ctx.profile_read()[key]
+        ctx.profile(False)
+        sec = ms / 1e3 / n
+        out[prec + "_8rhs"] = {"lattice": f"{L}^4 x 8 rhs", "us_per_launch": sec * 1e6,
+                               "ns_per_site_rhs": sec / units * n * 1e9,
+                               "GB_s_alg_single_rhs_bytes": DSLASH_BYTES[prec] * units / n / sec / 1e9}
     ctx.close()
     return out
 

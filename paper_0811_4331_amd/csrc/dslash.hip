@@ -50,12 +50,36 @@ __device__ __forceinline__ void hop(const cx<R>* __restrict__ in, const cx<R>* _
 
 // One thread per site; blockIdx.y = right-hand side.  Padding sites
 // (vol <= s < vpad) are written as zeros.
+// Workgroup order for a batch of nrhs fields over nsb site blocks: the hardware
+// sends workgroup b to XCD b % 8.  Each XCD takes a contiguous run of site
+// blocks (spatial neighbours share its L2) and, within it, all right-hand
+// sides of one site block back to back (its links are read once from HBM).
+__device__ __forceinline__ void batch_block(int nsb, int nrhs, int& sb, int& rhs) {
+  const int b = blockIdx.x;
+  if ((nsb & 7) || nrhs == 1) {
+    if (nrhs == 1) {
+      sb = xcd_block();
+      rhs = 0;
+    } else {
+      sb = b % nsb;
+      rhs = b / nsb;
+    }
+    return;
+  }
+  const int xcd = b & 7, local = b >> 3;
+  sb = xcd * (nsb >> 3) + local / nrhs;
+  rhs = local % nrhs;
+}
+
 template <typename R>
 __global__ __launch_bounds__(kDslashThreads) void k_dslash(Geom g, cx<R>* __restrict__ out,
                                                           const cx<R>* __restrict__ in,
-                                                          const cx<R>* __restrict__ U, R diag, int tneg) {
-  const int s = xcd_block() * kDslashThreads + threadIdx.x;
-  const size_t off = (size_t)blockIdx.y * 12 * g.vpad;
+                                                          const cx<R>* __restrict__ U, R diag, int tneg, int nsb,
+                                                          int nrhs) {
+  int sb, rhs;
+  batch_block(nsb, nrhs, sb, rhs);
+  const int s = sb * kDslashThreads + threadIdx.x;
+  const size_t off = (size_t)rhs * 12 * g.vpad;
   in += off;
   out += off;
   if (s >= g.vol) {
@@ -109,10 +133,11 @@ void dslash(Ctx& c, cx<R>* out, const cx<R>* in, int nrhs) {
     U = c.U64;
   else
     U = c.U32;
-  dim3 grid(g.vpad / kDslashThreads + (g.vpad % kDslashThreads != 0), nrhs);
+  const unsigned gx = g.vpad / kDslashThreads + (g.vpad % kDslashThreads != 0);
   ProfScope ps(c, sizeof(R) == 8 ? WDMG_K_DSLASH_F64 : WDMG_K_DSLASH_F32, (long long)g.vol * nrhs);
-  hipLaunchKernelGGL((k_dslash<R>), grid, dim3(kDslashThreads), 0, c.stream, g, out, in, U, (R)(4.0 + c.mass),
-                     c.t_bc < 0 ? 1 : 0);
+  const int tneg = c.t_bc < 0 ? 1 : 0;
+  hipLaunchKernelGGL((k_dslash<R>), dim3(gx * nrhs), dim3(kDslashThreads), 0, c.stream, g, out, in, U,
+                     (R)(4.0 + c.mass), tneg, (int)gx, nrhs);
   WDMG_HIP(hipGetLastError());
   c.n_D += nrhs;
 }

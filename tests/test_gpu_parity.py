@@ -63,6 +63,22 @@ def test_apply_D_fp64_and_fp32(dims, t_bc):
     assert rel(out32.astype(np.complex128), ref) < 1e-6
 
 
+@pytest.mark.parametrize("nrhs", [5, 8])
+def test_apply_D_batched_link_reuse(nrhs):
+    """Several right-hand sides per thread (links loaded once per chunk), with a
+    ragged last chunk: every column equals the oracle."""
+    dims = (8, 4, 4, 8)
+    m = 0.11
+    ctx, u = make_ctx(dims, 0.45, 91, m)
+    psi = synthetic.gaussian_spinor(dims, seed=92, nrhs=nrhs)
+    ref = wilson.apply_D(u, psi, m)
+    out = ctx.apply_D(gpu(psi)).cpu().numpy()
+    out32 = ctx.apply_D(gpu(psi.astype(np.complex64)), prec="f32").cpu().numpy()
+    for j in range(nrhs):
+        assert rel(out[j], ref[j]) < 1e-13
+        assert rel(out32[j].astype(np.complex128), ref[j]) < 1e-6
+
+
 def test_apply_D_free_field_and_gamma5_hermiticity_on_gpu():
     dims = (8, 8, 8, 8)
     ctx, u = make_ctx(dims, 0.0, 1, 0.2)
