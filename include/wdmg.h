@@ -47,7 +47,16 @@ enum {
   WDMG_ERR_RANK_DEFICIENT = -7  /* candidate vectors dependent on an aggregate */
 };
 
-/* Arithmetic precision of a kernel path. */
+/* Precision of a kernel path.  WDMG_F16 and WDMG_BF16 store fields and
+ * operators in 16 bits and compute in FP32:
+ *  - a fine field keeps, per site, an FP32 scale s = the largest magnitude of
+ *    its 24 real components and the values fl16(fl32(v * fl32(1/s))), each
+ *    rounded to nearest-even (first to FP32, then to the 16-bit format); a
+ *    site with s below the smallest normal FP32 number is stored as zero;
+ *  - links and prolongator columns (entries of magnitude <= 1) are stored
+ *    unscaled, rounded from FP64 to FP32 to 16 bits;
+ *  - coarse-operator blocks keep one FP32 scale per (2Nv x 2Nv) block and
+ *    coarse vectors stay in FP32. */
 enum { WDMG_F64 = 0, WDMG_F32 = 1, WDMG_F16 = 2, WDMG_BF16 = 3 };
 
 #define WDMG_MAX_LEVELS 4
@@ -90,7 +99,9 @@ typedef struct {
   int restart;           /* FGCR restart length k (paper GCR(50), Sec. 5)          */
   int maxit;             /* cap on outer iterations                                */
   int precond;           /* 0: plain GCR, 1: multigrid V-cycle                      */
-  int mg_prec;           /* precision of the V-cycle: WDMG_F64 or WDMG_F32          */
+  int mg_prec;           /* precision of the V-cycle: WDMG_F64, WDMG_F32, or WDMG_F16 /
+                            WDMG_BF16 (16-bit fine fields, links, P and intermediate
+                            coarse operators; the coarsest solve stays FP64)        */
 } wdmg_solve_params;
 
 typedef struct {
@@ -130,8 +141,16 @@ int wdmg_set_gauge(wdmg_ctx* ctx, const void* U, int t_bc);
 int wdmg_set_mass(wdmg_ctx* ctx, double m);
 
 /* Sec. 1: out = D in for nrhs fine fields.  in, out: device, canonical fine
- * layout, out != in.  prec WDMG_F64 (complex128 I/O) or WDMG_F32 (complex64). */
+ * layout, out != in.  prec WDMG_F64 (complex128 I/O) or WDMG_F32, WDMG_F16,
+ * WDMG_BF16 (complex64 I/O; the 16-bit paths store `in`, the links and the
+ * result in 16 bits as described for WDMG_F16 and compute in FP32). */
 int wdmg_apply_D(wdmg_ctx* ctx, void* out, const void* in, int nrhs, int prec);
+
+/* Storage conversion of fine fields (the layout and precision conversion in
+ * front of every fine-level kernel): out = in after conversion into the
+ * internal fine-field storage of precision prec and back.  Canonical layout;
+ * complex128 for WDMG_F64, complex64 otherwise; out != in. */
+int wdmg_roundtrip(wdmg_ctx* ctx, void* out, const void* in, int nrhs, int prec);
 
 /* Sec. 2 (adaptive setup, block QR with P V_c = V and P^dagger P = I),
  * Sec. 3 (geometric aggregates, chirality kept in the blocks, R = P^dagger),
@@ -146,18 +165,23 @@ int wdmg_mg_setup(wdmg_ctx* ctx, const wdmg_mg_params* params);
 int wdmg_get_prolongator(wdmg_ctx* ctx, int level, void* V_out);
 
 /* Sec. 2: out = D_c in on coarse level l >= 1 (nrhs fields).  Canonical
- * coarse layout; prec WDMG_F64 (complex128) or WDMG_F32 (complex64). */
+ * coarse layout; prec WDMG_F64 (complex128) or WDMG_F32, WDMG_F16, WDMG_BF16
+ * (complex64 vectors; the 16-bit kinds use 16-bit blocks with one scale per
+ * block). */
 int wdmg_apply_Dc(wdmg_ctx* ctx, int level, void* out, const void* in, int nrhs, int prec);
 
 /* Sec. 2 / Sec. 3: c_out = P^dagger f_in (restriction from level l to l+1)
  * and f_out = P c_in (prolongation from level l+1 to l).  Canonical layouts
- * of the two levels; precision as for wdmg_apply_D. */
+ * of the two levels; precision as for wdmg_apply_D.  The 16-bit kinds
+ * (level 0 only) store the fine field and P in 16 bits; the coarse side is
+ * complex64. */
 int wdmg_restrict(wdmg_ctx* ctx, int level, void* c_out, const void* f_in, int nrhs, int prec);
 int wdmg_prolong(wdmg_ctx* ctx, int level, void* f_out, const void* c_in, int nrhs, int prec);
 
 /* Sec. 3: iters under-relaxed MR steps (omega of the setup params, 0.8 if no
  * setup) on A x = b at level l, starting from the given x (updated in place).
- * Canonical layout of level l. */
+ * Canonical layout of level l.  With a 16-bit kind, level 0 keeps x, r and
+ * D r in 16-bit storage; coarse levels use the 16-bit coarse blocks. */
 int wdmg_smooth(wdmg_ctx* ctx, int level, void* x, const void* b, int nrhs, int iters, int prec);
 
 /* Sec. 5: solve D x = b for nrhs (1..64) right-hand sides with flexible
@@ -186,7 +210,9 @@ int wdmg_solve_bicgstab(wdmg_ctx* ctx, void* x, const void* b, int nrhs, double 
 enum {
   WDMG_K_DSLASH_F64 = 0, WDMG_K_DSLASH_F32, WDMG_K_DC_F64, WDMG_K_DC_F32,
   WDMG_K_RESTRICT_F64, WDMG_K_RESTRICT_F32, WDMG_K_PROLONG_F64, WDMG_K_PROLONG_F32,
-  WDMG_K_DC_BUILD, WDMG_K_BLOCK_QR, WDMG_K_DC_MFMA_F64, WDMG_K_DC_MFMA_F32, WDMG_K_COUNT
+  WDMG_K_DC_BUILD, WDMG_K_BLOCK_QR, WDMG_K_DC_MFMA_F64, WDMG_K_DC_MFMA_F32,
+  WDMG_K_DSLASH_F16, WDMG_K_DSLASH_BF16, WDMG_K_RESTRICT_H, WDMG_K_PROLONG_H, WDMG_K_DC_H, WDMG_K_DC_MFMA_H,
+  WDMG_K_COUNT
 };
 
 /* enable = 1 starts recording (and clears earlier records), 0 stops. */

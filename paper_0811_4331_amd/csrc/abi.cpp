@@ -47,9 +47,72 @@ void need_mg(Ctx& c, int level, bool coarse) {
   if (level < lo || level > hi) throw Error(WDMG_ERR_ARG, "level out of range");
 }
 void need_prec(int prec) {
-  if (prec == WDMG_F16 || prec == WDMG_BF16)
-    throw Error(WDMG_ERR_ARG, "16-bit storage is not available through this entry point");
-  if (prec != WDMG_F64 && prec != WDMG_F32) throw Error(WDMG_ERR_ARG, "unknown precision");
+  if (prec != WDMG_F64 && prec != WDMG_F32 && prec != WDMG_F16 && prec != WDMG_BF16)
+    throw Error(WDMG_ERR_ARG, "unknown precision");
+}
+bool is_half(int prec) { return prec == WDMG_F16 || prec == WDMG_BF16; }
+
+// 16-bit scratch fine fields for nrhs right-hand sides
+void ensure_ioh(Ctx& c, int nrhs) {
+  if (nrhs <= c.ioh_cap) return;
+  WDMG_HIP(hipStreamSynchronize(c.stream));
+  for (HF& f : c.ioh) {
+    hf_free(c, f);
+    f = hf_alloc(c, nrhs);
+  }
+  c.ioh_cap = nrhs;
+}
+
+template <typename H>
+void apply_D_half(Ctx& c, void* out, const void* in, int nrhs) {
+  ensure_ioh(c, nrhs);
+  canon_to_half<H>(c, static_cast<const cx<float>*>(in), c.ioh[0], nrhs);
+  dslash_h<H>(c, c.ioh[1], c.ioh[0], nrhs);
+  half_to_canon<H>(c, c.ioh[1], static_cast<cx<float>*>(out), nrhs);
+}
+
+template <typename H>
+void roundtrip_half(Ctx& c, void* out, const void* in, int nrhs) {
+  ensure_ioh(c, nrhs);
+  canon_to_half<H>(c, static_cast<const cx<float>*>(in), c.ioh[0], nrhs);
+  half_to_canon<H>(c, c.ioh[0], static_cast<cx<float>*>(out), nrhs);
+}
+
+template <typename H>
+void restrict_half(Ctx& c, void* cout, const void* fin, int nrhs) {
+  ensure_ioh(c, nrhs);
+  const void* V = v16(c, c.lev[0], half_kind<H>());
+  canon_to_half<H>(c, static_cast<const cx<float>*>(fin), c.ioh[0], nrhs);
+  restrict0_h<H>(c, c.lev[0], V, c.ioh[0], static_cast<cx<float>*>(cout), nrhs);
+}
+
+template <typename H>
+void prolong_half(Ctx& c, void* fout, const void* cin, int nrhs) {
+  ensure_ioh(c, nrhs);
+  const void* V = v16(c, c.lev[0], half_kind<H>());
+  prolong0_h<H>(c, c.lev[0], V, static_cast<const cx<float>*>(cin), c.ioh[0], nrhs);
+  half_to_canon<H>(c, c.ioh[0], static_cast<cx<float>*>(fout), nrhs);
+}
+
+// MR on the fine level in 16-bit storage.  The starting residual b - D x is
+// formed in FP32; x and r are then held in 16 bits for the iterations.
+template <typename H>
+void smooth_half0(Ctx& c, void* x, const void* b, int nrhs, int iters) {
+  const size_t n = c.lev[0].n;
+  ensure_io(c, 2 * n * nrhs * sizeof(cx<float>));
+  ensure_ioh(c, nrhs);
+  cx<float>* xi = static_cast<cx<float>*>(c.io_a);
+  cx<float>* ri = xi + n * nrhs;
+  cx<float>* bi = static_cast<cx<float>*>(c.io_b);
+  fine_to_internal<float, float>(c, c.g0, static_cast<const cx<float>*>(x), xi, nrhs);
+  fine_to_internal<float, float>(c, c.g0, static_cast<const cx<float>*>(b), bi, nrhs);
+  dslash<float>(c, ri, xi, nrhs);
+  xmy<float>(c, bi, ri, n * nrhs);
+  to_half<float, H>(c, xi, c.ioh[0], nrhs);
+  to_half<float, H>(c, ri, c.ioh[1], nrhs);
+  const double omega = c.have_mg ? c.mg.omega : 0.8;
+  mr_h<H>(c, c.ioh[0], c.ioh[1], c.ioh[2], nrhs, iters, omega);
+  half_to_canon<H>(c, c.ioh[0], static_cast<cx<float>*>(x), nrhs);
 }
 void need_ptr(const void* p, const char* what) {
   if (!p) throw Error(WDMG_ERR_ARG, std::string("null pointer: ") + what);
@@ -275,6 +338,7 @@ int wdmg_set_gauge(wdmg_ctx* c, const void* U, int t_bc) {
       c->U32 = static_cast<cx<float>*>(dev_alloc(*c, n * sizeof(cx<float>)));
     }
     set_scalar(*c, S_ERR + 2, 0.0, 0.0);
+    c->u16_kind = 0;
     gauge_import(*c, static_cast<const cx<double>*>(U), t_bc);
     c->t_bc = t_bc;
     c->have_gauge = false;
@@ -310,8 +374,37 @@ int wdmg_apply_D(wdmg_ctx* c, void* out, const void* in, int nrhs, int prec) {
     if (out == in) throw Error(WDMG_ERR_ARG, "out must differ from in");
     if (prec == WDMG_F64)
       apply_D_impl<double>(*c, out, in, nrhs);
-    else
+    else if (prec == WDMG_F32)
       apply_D_impl<float>(*c, out, in, nrhs);
+    else if (prec == WDMG_F16)
+      apply_D_half<f16_t>(*c, out, in, nrhs);
+    else
+      apply_D_half<bf16_t>(*c, out, in, nrhs);
+    return WDMG_OK;
+  });
+}
+
+int wdmg_roundtrip(wdmg_ctx* c, void* out, const void* in, int nrhs, int prec) {
+  return guarded(c, [&]() {
+    need_ptr(out, "out");
+    need_ptr(in, "in");
+    need_nrhs(nrhs);
+    need_prec(prec);
+    if (out == in) throw Error(WDMG_ERR_ARG, "out must differ from in");
+    const size_t n = (size_t)c->g0.vpad * 12;
+    if (prec == WDMG_F64) {
+      ensure_io(*c, n * nrhs * sizeof(cx<double>));
+      fine_in<double>(*c, in, static_cast<cx<double>*>(c->io_a), nrhs);
+      fine_out<double>(*c, static_cast<cx<double>*>(c->io_a), out, nrhs);
+    } else if (prec == WDMG_F32) {
+      ensure_io(*c, n * nrhs * sizeof(cx<float>));
+      fine_in<float>(*c, in, static_cast<cx<float>*>(c->io_a), nrhs);
+      fine_out<float>(*c, static_cast<cx<float>*>(c->io_a), out, nrhs);
+    } else if (prec == WDMG_F16) {
+      roundtrip_half<f16_t>(*c, out, in, nrhs);
+    } else {
+      roundtrip_half<bf16_t>(*c, out, in, nrhs);
+    }
     return WDMG_OK;
   });
 }
@@ -345,13 +438,15 @@ int wdmg_apply_Dc(wdmg_ctx* c, int level, void* out, const void* in, int nrhs, i
     need_prec(prec);
     need_mg(*c, level, true);
     if (out == in) throw Error(WDMG_ERR_ARG, "out must differ from in");
-    const Level& L = c->lev[level];
+    Level& L = c->lev[level];
     if (prec == WDMG_F64)
       coarse_apply<double>(*c, L, dc_of<double>(L), static_cast<cx<double>*>(out),
                            static_cast<const cx<double>*>(in), nrhs);
-    else
+    else if (prec == WDMG_F32)
       coarse_apply<float>(*c, L, dc_of<float>(L), static_cast<cx<float>*>(out), static_cast<const cx<float>*>(in),
                           nrhs);
+    else
+      coarse_apply_h(*c, L, prec, static_cast<cx<float>*>(out), static_cast<const cx<float>*>(in), nrhs);
     return WDMG_OK;
   });
 }
@@ -363,10 +458,15 @@ int wdmg_restrict(wdmg_ctx* c, int level, void* c_out, const void* f_in, int nrh
     need_nrhs(nrhs);
     need_prec(prec);
     need_mg(*c, level, false);
+    if (is_half(prec) && level != 0) throw Error(WDMG_ERR_ARG, "16-bit transfers exist for level 0 only");
     if (prec == WDMG_F64)
       restrict_impl<double>(*c, level, c_out, f_in, nrhs);
-    else
+    else if (prec == WDMG_F32)
       restrict_impl<float>(*c, level, c_out, f_in, nrhs);
+    else if (prec == WDMG_F16)
+      restrict_half<f16_t>(*c, c_out, f_in, nrhs);
+    else
+      restrict_half<bf16_t>(*c, c_out, f_in, nrhs);
     return WDMG_OK;
   });
 }
@@ -378,10 +478,15 @@ int wdmg_prolong(wdmg_ctx* c, int level, void* f_out, const void* c_in, int nrhs
     need_nrhs(nrhs);
     need_prec(prec);
     need_mg(*c, level, false);
+    if (is_half(prec) && level != 0) throw Error(WDMG_ERR_ARG, "16-bit transfers exist for level 0 only");
     if (prec == WDMG_F64)
       prolong_impl<double>(*c, level, f_out, c_in, nrhs);
-    else
+    else if (prec == WDMG_F32)
       prolong_impl<float>(*c, level, f_out, c_in, nrhs);
+    else if (prec == WDMG_F16)
+      prolong_half<f16_t>(*c, f_out, c_in, nrhs);
+    else
+      prolong_half<bf16_t>(*c, f_out, c_in, nrhs);
     return WDMG_OK;
   });
 }
@@ -395,10 +500,19 @@ int wdmg_smooth(wdmg_ctx* c, int level, void* x, const void* b, int nrhs, int it
     need_gauge(*c);
     if (iters < 0) throw Error(WDMG_ERR_ARG, "iters must be >= 0");
     if (level != 0) need_mg(*c, level, true);
-    if (prec == WDMG_F64)
+    if (prec == WDMG_F64) {
       smooth_impl<double>(*c, level, x, b, nrhs, iters);
-    else
+    } else if (prec == WDMG_F32) {
       smooth_impl<float>(*c, level, x, b, nrhs, iters);
+    } else if (level == 0) {
+      if (prec == WDMG_F16)
+        smooth_half0<f16_t>(*c, x, b, nrhs, iters);
+      else
+        smooth_half0<bf16_t>(*c, x, b, nrhs, iters);
+    } else {
+      HalfScope hs(*c, prec);
+      smooth_impl<float>(*c, level, x, b, nrhs, iters);
+    }
     return WDMG_OK;
   });
 }
@@ -414,8 +528,7 @@ int wdmg_solve(wdmg_ctx* c, void* x, const void* b, int nrhs, const wdmg_solve_p
       throw Error(WDMG_ERR_ARG, "bad solve parameters");
     if (p->precond) {
       if (!c->have_mg) throw Error(WDMG_ERR_NOT_SETUP, "no multigrid hierarchy set up");
-      if (p->mg_prec != WDMG_F64 && p->mg_prec != WDMG_F32)
-        throw Error(WDMG_ERR_ARG, "the V-cycle runs in WDMG_F64 or WDMG_F32");
+      need_prec(p->mg_prec);
     }
     ensure_solve_io(*c, nrhs);
     std::vector<wdmg_solve_stats> st(nrhs);

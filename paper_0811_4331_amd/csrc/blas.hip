@@ -7,6 +7,7 @@
 // coefficient, ...) straight into the device scalar area.  The summation
 // order depends only on the vector length, so results are bitwise
 // reproducible run to run.
+#include "half_field.h"
 #include "internal.h"
 
 namespace wdmg {
@@ -198,6 +199,42 @@ struct StepAlphaBatchOp {
     v[0] += (double)x.re * z.re + (double)x.im * z.im;
     v[1] += (double)x.re * z.im - (double)x.im * z.re;
     v[2] += (double)x.re * x.re + (double)x.im * x.im;
+  }
+  __device__ void fin(const double* v, int y) const {
+    double re = 0.0, im = 0.0;
+    if (v[2] > 0.0) {
+      re = scale * v[0] / v[2];
+      im = scale * v[1] / v[2];
+    }
+    if (bad(v[0]) || bad(v[1]) || bad(v[2])) dsc[S_ERR] = 1.0;
+    dsc[slot + 2 * y] = re;
+    dsc[slot + 2 * y + 1] = im;
+  }
+};
+
+// Batched MR step sizes on 16-bit fields; i runs over sites.
+template <typename H>
+struct StepAlphaHalfOp {
+  static constexpr int K = 3;
+  const cxh<H>* a;
+  const float* as;
+  const cxh<H>* b;
+  const float* bs;
+  int vpad;
+  double scale;
+  double* dsc;
+  int slot;
+  __device__ void acc(size_t i, int y, double* v) const {
+    const size_t vo = (size_t)y * 12 * vpad, so = (size_t)y * vpad;
+    cx<float> x[12], z[12];
+    load_site_h(a + vo, as + so, (int)i, x);
+    load_site_h(b + vo, bs + so, (int)i, z);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      v[0] += (double)x[k].re * z[k].re + (double)x[k].im * z[k].im;
+      v[1] += (double)x[k].re * z[k].im - (double)x[k].im * z[k].re;
+      v[2] += (double)x[k].re * x[k].re + (double)x[k].im * x[k].im;
+    }
   }
   __device__ void fin(const double* v, int y) const {
     double re = 0.0, im = 0.0;
@@ -447,6 +484,30 @@ __global__ void k_update2(cx<R>* x, const cx<R>* u, cx<R>* r, const cx<R>* v, si
     x[i] = x[i] + a * ui;
     r[i] = r[i] - a * vi;
   }
+}
+
+// x += s u ; r -= s v on 16-bit fields (one thread per site and rhs); u may
+// be the same field as r, so nothing here is declared non-aliasing.
+template <typename H>
+__global__ void k_update2_half(Geom g, cxh<H>* xv, float* xs, const cxh<H>* uv, const float* us, cxh<H>* rv,
+                               float* rs, const cxh<H>* vv, const float* vs, const double* sc) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (s >= g.vpad) return;
+  const size_t vo = (size_t)y * 12 * g.vpad, so = (size_t)y * g.vpad;
+  const cx<float> a = mk((float)sc[2 * y], (float)sc[2 * y + 1]);
+  cx<float> x[12], u[12], r[12], v[12];
+  load_site_h(xv + vo, xs + so, s, x);
+  load_site_h(uv + vo, us + so, s, u);
+  load_site_h(rv + vo, rs + so, s, r);
+  load_site_h(vv + vo, vs + so, s, v);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    x[k] = x[k] + a * u[k];
+    r[k] = r[k] - a * v[k];
+  }
+  store_site_h(xv + vo, xs + so, s, x);
+  store_site_h(rv + vo, rs + so, s, r);
 }
 
 __global__ void k_bicg_p(cx<double>* p, const cx<double>* r, const cx<double>* v, size_t n, const double* dsc,
@@ -799,6 +860,35 @@ void update2_batch(Ctx& c, cx<R>* x, const cx<R>* u, cx<R>* r, const cx<R>* v, s
                      c.dsc + slot);
   WDMG_HIP(hipGetLastError());
 }
+
+template <typename H>
+void step_alpha_half(Ctx& c, HF a, HF b, int nrhs, double scale, int slot) {
+  const size_t n = c.g0.vol;
+  unsigned nblk = reduce_blocks(n);
+  if (nblk * nrhs > 8192) nblk = 8192 / nrhs;
+  if (nblk < 1) nblk = 1;
+  const StepAlphaHalfOp<H> op{static_cast<const cxh<H>*>(a.v), a.s, static_cast<const cxh<H>*>(b.v), b.s,
+                              c.g0.vpad, scale, c.dsc, slot};
+  hipLaunchKernelGGL((k_reduce_b_part<StepAlphaHalfOp<H>>), dim3(nblk, nrhs), dim3(TPB), 0, c.stream, op, n,
+                     c.partials);
+  WDMG_HIP(hipGetLastError());
+  hipLaunchKernelGGL((k_reduce_b_fin<StepAlphaHalfOp<H>>), dim3(nrhs), dim3(TPB), 0, c.stream, op, (int)nblk,
+                     c.partials);
+  WDMG_HIP(hipGetLastError());
+}
+
+template <typename H>
+void update2_half(Ctx& c, HF x, HF u, HF r, HF v, int nrhs, int slot) {
+  hipLaunchKernelGGL((k_update2_half<H>), dim3((c.g0.vpad + 255) / 256, nrhs), dim3(256), 0, c.stream, c.g0,
+                     static_cast<cxh<H>*>(x.v), x.s, static_cast<const cxh<H>*>(u.v), u.s,
+                     static_cast<cxh<H>*>(r.v), r.s, static_cast<const cxh<H>*>(v.v), v.s, c.dsc + slot);
+  WDMG_HIP(hipGetLastError());
+}
+
+template void step_alpha_half<f16_t>(Ctx&, HF, HF, int, double, int);
+template void step_alpha_half<bf16_t>(Ctx&, HF, HF, int, double, int);
+template void update2_half<f16_t>(Ctx&, HF, HF, HF, HF, int, int);
+template void update2_half<bf16_t>(Ctx&, HF, HF, HF, HF, int, int);
 
 void gcr_orth(Ctx& c, const cx<double>* W, const cx<double>* Z, cx<double>* w, cx<double>* z, const cx<double>* r,
               size_t n, int j, int hslot, int nrmslot) {

@@ -11,7 +11,7 @@
 // block of one coarse site: it applies the fine hops to the chirality-split
 // columns of P at a few sites at a time (staged in LDS) and contracts them
 // with the conjugated columns, all in FP64.
-#include "fine_field.h"
+#include "half_field.h"
 #include "internal.h"
 #include "wilson_spin.h"
 
@@ -434,6 +434,191 @@ __global__ __launch_bounds__(256) void k_coarse_apply_mfma32(Geom g, int n2, int
   }
 }
 
+// ---- 16-bit blocks ---------------------------------------------------------------
+// One workgroup per block: scale = largest magnitude of the block's real
+// components (after rounding to FP32), stored = fl16(fl32(value * fl32(1/scale))).
+template <typename H>
+__global__ __launch_bounds__(256) void k_dc_to_half(const cx<double>* __restrict__ Dc, cxh<H>* __restrict__ Dh,
+                                                    float* __restrict__ scales, int nn) {
+  __shared__ float red[4];
+  const size_t b = blockIdx.x;
+  const cx<double>* src = Dc + b * nn;
+  float m = 0.0f;
+  bool nan = false;
+  for (int i = threadIdx.x; i < nn; i += blockDim.x) {
+    const cx<float> a = cvt<float>(src[i]);
+    m = fmaxf(m, fmaxf(fabsf(a.re), fabsf(a.im)));
+    nan = nan || a.re != a.re || a.im != a.im;
+  }
+  if (nan) m = __builtin_nanf("");
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const float o = __shfl_xor(m, off, 64);
+    m = (o != o || m != m) ? __builtin_nanf("") : fmaxf(m, o);
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  float mm = red[0];
+  for (int w = 1; w < (int)(blockDim.x >> 6); ++w) mm = (red[w] != red[w] || mm != mm) ? __builtin_nanf("") : fmaxf(mm, red[w]);
+  float inv;
+  const float sc = quant_scale(mm, inv);
+  if (threadIdx.x == 0) scales[b] = sc;
+  for (int i = threadIdx.x; i < nn; i += blockDim.x) {
+    const cx<float> a = cvt<float>(src[i]);
+    Dh[b * nn + i] = quantise<H>(a.re, a.im, inv);
+  }
+}
+
+// One right-hand side on the vector units (as k_coarse_apply), 16-bit blocks.
+template <typename H>
+__global__ __launch_bounds__(576) void k_coarse_apply_h(Geom g, int n2, const cxh<H>* __restrict__ Dc,
+                                                        const float* __restrict__ Dcs,
+                                                        const cx<float>* __restrict__ in,
+                                                        cx<float>* __restrict__ out, cx<float>* __restrict__ copy) {
+  __shared__ cx<float> part[9][64];
+  const int s = blockIdx.x, rhs = blockIdx.y;
+  const int d = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const size_t nsite = g.vol;
+  in += (size_t)rhs * nsite * n2;
+  out += (size_t)rhs * nsite * n2;
+  if (copy && d == 8 && lane < n2) copy[(size_t)rhs * nsite * n2 + (size_t)s * n2 + lane] = in[(size_t)s * n2 + lane];
+  int nb = s;
+  if (d < 8) {
+    int c[4];
+    coords_of(g, s, c);
+    nb = (d & 1) ? nbr_bwd(g, s, c, d >> 1) : nbr_fwd(g, s, c, d >> 1);
+  }
+  cx<float> acc = mk(0.0f, 0.0f);
+  if (lane < n2) {
+    const cxh<H>* blk = Dc + ((size_t)s * 9 + d) * n2 * n2 + lane;
+    const cx<float>* v = in + (size_t)nb * n2;
+    for (int j = 0; j < n2; ++j) cmadd(acc, h2f(blk[(size_t)j * n2]), v[j]);
+    const float sc = Dcs[(size_t)s * 9 + d];
+    acc = mk(sc * acc.re, sc * acc.im);
+  }
+  part[d][lane] = acc;
+  __syncthreads();
+  if (d == 0 && lane < n2) {
+    cx<float> t = part[8][lane];
+#pragma unroll
+    for (int dd = 0; dd < 8; ++dd) t = t + part[dd][lane];
+    out[(size_t)s * n2 + lane] = t;
+  }
+}
+
+// A batch on the matrix cores with 16-bit operands (v_mfma_f32_32x32x8 f16 or
+// bf16, FP32 accumulation).  Same real-GEMM form and tiling as the FP32
+// kernel.  Per direction, each right-hand-side column of the staged operand
+// is scaled into [-1, 1] by its largest magnitude and rounded to 16 bits;
+// the product of that direction is accumulated from zero and added to the
+// result times (block scale x column scale).  Operand lanes: A[i][k] at lane
+// i + 32 (k / 4), element k % 4; B[k][j] at lane j + 32 (k / 4), element
+// k % 4; result as for the FP32 kernel.
+typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+typedef short short4_t __attribute__((ext_vector_type(4)));
+
+template <typename H>
+__device__ __forceinline__ floatx16 mfma_32x32x8(const float (&a)[4], const float (&b)[4], floatx16 acc);
+template <>
+__device__ __forceinline__ floatx16 mfma_32x32x8<f16_t>(const float (&a)[4], const float (&b)[4], floatx16 acc) {
+  half4_t x, y;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    x[e] = (_Float16)a[e];
+    y[e] = (_Float16)b[e];
+  }
+  return __builtin_amdgcn_mfma_f32_32x32x8f16(x, y, acc, 0, 0, 0);
+}
+template <>
+__device__ __forceinline__ floatx16 mfma_32x32x8<bf16_t>(const float (&a)[4], const float (&b)[4], floatx16 acc) {
+  short4_t x, y;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    x[e] = __builtin_bit_cast(short, (__bf16)a[e]);
+    y[e] = __builtin_bit_cast(short, (__bf16)b[e]);
+  }
+  return __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(x, y, acc, 0, 0, 0);
+}
+
+template <typename H>
+__global__ __launch_bounds__(256) void k_coarse_apply_mfma16(Geom g, int n2, int nrhs, const cxh<H>* __restrict__ Dc,
+                                                             const float* __restrict__ Dcs,
+                                                             const cx<float>* __restrict__ in,
+                                                             cx<float>* __restrict__ out,
+                                                             cx<float>* __restrict__ copy) {
+  __shared__ float Bs[128][33];
+  __shared__ float Bsc[32], Binv[32];
+  extern __shared__ __align__(16) char dyn16[];
+  cxh<H>* As16 = reinterpret_cast<cxh<H>*>(dyn16);
+  const int s = blockIdx.x, q0 = blockIdx.y * 32;
+  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const size_t nsite = g.vol, fs = nsite * n2;
+  const int kr = 2 * n2;
+  int c[4];
+  coords_of(g, s, c);
+  floatx16 acc;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) acc[e] = 0.f;
+  for (int d = 0; d < 9; ++d) {
+    const int nb = d == 8 ? s : ((d & 1) ? nbr_bwd(g, s, c, d >> 1) : nbr_fwd(g, s, c, d >> 1));
+    __syncthreads();
+    for (int w = threadIdx.x; w < 32 * n2; w += blockDim.x) {
+      const int q = w / n2, j = w % n2;
+      cx<float> v = mk(0.f, 0.f);
+      if (q0 + q < nrhs) v = in[(size_t)(q0 + q) * fs + (size_t)nb * n2 + j];
+      Bs[2 * j][q] = v.re;
+      Bs[2 * j + 1][q] = v.im;
+      if (d == 8 && copy && q0 + q < nrhs) copy[(size_t)(q0 + q) * fs + (size_t)s * n2 + j] = v;
+    }
+    const cxh<H>* blk = Dc + ((size_t)s * 9 + d) * n2 * n2;
+    for (int w = threadIdx.x; w < n2 * n2; w += blockDim.x) As16[w] = blk[w];
+    __syncthreads();
+    if (threadIdx.x < 32) {
+      float m = 0.0f;
+      for (int k = 0; k < kr; ++k) m = fmaxf(m, fabsf(Bs[k][threadIdx.x]));
+      float inv;
+      Bsc[threadIdx.x] = quant_scale(m, inv);
+      Binv[threadIdx.x] = inv;
+    }
+    __syncthreads();
+    const int r = wave * 32 + (l & 31), i = r >> 1, pr = r & 1;
+    const float binv = Binv[l & 31];
+    floatx16 t;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) t[e] = 0.f;
+    for (int k0 = 0; k0 < kr; k0 += 8) {
+      float a[4], b[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int k = k0 + 4 * (l >> 5) + e;
+        a[e] = 0.f;
+        b[e] = 0.f;
+        if (k < kr) {
+          b[e] = Bs[k][l & 31] * binv;
+          if (i < n2) {
+            const cx<float> z = h2f(As16[(size_t)(k >> 1) * n2 + i]);
+            const int pk = k & 1;
+            a[e] = pr == 0 ? (pk == 0 ? z.re : -z.im) : (pk == 0 ? z.im : z.re);
+          }
+        }
+      }
+      t = mfma_32x32x8<H>(a, b, t);
+    }
+    const float f = Dcs[(size_t)s * 9 + d] * Bsc[l & 31];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[e] += f * t[e];
+  }
+  const int q = q0 + (l & 31);
+  if (q < nrhs) {
+    float* o = reinterpret_cast<float*>(out + (size_t)q * fs + (size_t)s * n2);
+#pragma unroll
+    for (int reg = 0; reg < 16; ++reg) {
+      const int r = wave * 32 + 8 * (reg >> 2) + 4 * (l >> 5) + (reg & 3);
+      if ((r >> 1) < n2) o[r] = acc[reg];
+    }
+  }
+}
+
 template <typename R>
 __global__ void k_coarse_shift(cx<R>* Dc, int nsite, int n2, double dm) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -515,6 +700,47 @@ void coarse_shift(Ctx& c, Level& cl, double dm) {
   hipLaunchKernelGGL((k_coarse_shift<float>), dim3((n + 255) / 256), dim3(256), 0, c.stream, cl.Dc32, cl.nsite,
                      cl.dof, dm);
   WDMG_HIP(hipGetLastError());
+  cl.dc16_kind = 0;  // the 16-bit copy is remade from the shifted FP64 blocks on next use
+}
+
+void coarse_apply_h(Ctx& c, Level& cl, int kind, cx<float>* out, const cx<float>* in, int nrhs, cx<float>* copy) {
+  const int n2 = cl.dof;
+  const size_t nblk = (size_t)cl.nsite * 9, nn = (size_t)n2 * n2;
+  if (cl.dc16_kind != kind) {
+    if (!cl.Dc16) {
+      cl.Dc16 = dev_alloc(c, nblk * nn * 4);
+      cl.Dc16s = static_cast<float*>(dev_alloc(c, nblk * sizeof(float)));
+    }
+    if (kind == WDMG_F16)
+      hipLaunchKernelGGL((k_dc_to_half<f16_t>), dim3((unsigned)nblk), dim3(256), 0, c.stream, cl.Dc64,
+                         static_cast<cxh<f16_t>*>(cl.Dc16), cl.Dc16s, (int)nn);
+    else
+      hipLaunchKernelGGL((k_dc_to_half<bf16_t>), dim3((unsigned)nblk), dim3(256), 0, c.stream, cl.Dc64,
+                         static_cast<cxh<bf16_t>*>(cl.Dc16), cl.Dc16s, (int)nn);
+    WDMG_HIP(hipGetLastError());
+    cl.dc16_kind = kind;
+  }
+  if (nrhs >= kMfmaMinRhs && n2 <= 64) {
+    ProfScope ps(c, WDMG_K_DC_MFMA_H, (long long)cl.nsite * nrhs);
+    const int waves = (2 * n2 + 31) / 32;
+    const size_t lds = nn * 4;
+    if (kind == WDMG_F16)
+      hipLaunchKernelGGL((k_coarse_apply_mfma16<f16_t>), dim3(cl.nsite, (nrhs + 31) / 32), dim3(64 * waves), lds,
+                         c.stream, cl.g, n2, nrhs, static_cast<const cxh<f16_t>*>(cl.Dc16), cl.Dc16s, in, out, copy);
+    else
+      hipLaunchKernelGGL((k_coarse_apply_mfma16<bf16_t>), dim3(cl.nsite, (nrhs + 31) / 32), dim3(64 * waves), lds,
+                         c.stream, cl.g, n2, nrhs, static_cast<const cxh<bf16_t>*>(cl.Dc16), cl.Dc16s, in, out, copy);
+  } else {
+    ProfScope ps(c, WDMG_K_DC_H, (long long)cl.nsite * nrhs);
+    if (kind == WDMG_F16)
+      hipLaunchKernelGGL((k_coarse_apply_h<f16_t>), dim3(cl.nsite, nrhs), dim3(576), 0, c.stream, cl.g, n2,
+                         static_cast<const cxh<f16_t>*>(cl.Dc16), cl.Dc16s, in, out, copy);
+    else
+      hipLaunchKernelGGL((k_coarse_apply_h<bf16_t>), dim3(cl.nsite, nrhs), dim3(576), 0, c.stream, cl.g, n2,
+                         static_cast<const cxh<bf16_t>*>(cl.Dc16), cl.Dc16s, in, out, copy);
+  }
+  WDMG_HIP(hipGetLastError());
+  c.n_Dc[cl.l] += nrhs;
 }
 
 template void coarse_apply<double>(Ctx&, const Level&, const cx<double>*, cx<double>*, const cx<double>*, int,

@@ -10,7 +10,7 @@
 // Layout: fields in 64-site blocks, links as their first two rows (see
 // fine_field.h).  One thread per (site, right-hand side); workgroups are
 // remapped so spatially adjacent tiles share an XCD's L2.
-#include "fine_field.h"
+#include "half_field.h"
 #include "internal.h"
 #include "wilson_spin.h"
 
@@ -19,16 +19,59 @@ namespace {
 
 constexpr int kDslashThreads = 128;
 
-template <int MU, int SIGN, typename R>
-__device__ __forceinline__ void hop(const cx<R>* __restrict__ in, const cx<R>* __restrict__ U, int nb,
-                                    int link_site, bool neg, cx<R> (&acc)[12]) {
-  cx<R> p[12];
+// Field and link access of one precision.  FullIO: FP64 or FP32 fields and
+// links.  HalfIO: 16-bit fields with per-site scales and 16-bit links,
+// arithmetic in FP32.
+template <typename R>
+struct FullIO {
+  using T = R;
+  const cx<R>* in;
+  cx<R>* out;
+  const cx<R>* U;
+  __device__ __forceinline__ void select_rhs(int rhs, int vpad) {
+    in += (size_t)rhs * 12 * vpad;
+    out += (size_t)rhs * 12 * vpad;
+  }
+  __device__ __forceinline__ void spinor(int s, cx<R> (&p)[12]) const {
 #pragma unroll
-  for (int k = 0; k < 12; ++k) p[k] = in[fidx(nb, k, 12)];
+    for (int k = 0; k < 12; ++k) p[k] = in[fidx(s, k, 12)];
+  }
+  __device__ __forceinline__ void link(int mu, int s, bool neg, cx<R> (&u)[9]) const { load_link(U, mu, s, neg, u); }
+  __device__ __forceinline__ void store(int s, const cx<R> (&v)[12]) const {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) out[fidx(s, k, 12)] = v[k];
+  }
+};
+
+template <typename H>
+struct HalfIO {
+  using T = float;
+  const cxh<H>* in;
+  const float* isc;
+  cxh<H>* out;
+  float* osc;
+  const cxh<H>* U;
+  __device__ __forceinline__ void select_rhs(int rhs, int vpad) {
+    in += (size_t)rhs * 12 * vpad;
+    out += (size_t)rhs * 12 * vpad;
+    isc += (size_t)rhs * vpad;
+    osc += (size_t)rhs * vpad;
+  }
+  __device__ __forceinline__ void spinor(int s, cx<float> (&p)[12]) const { load_site_h(in, isc, s, p); }
+  __device__ __forceinline__ void link(int mu, int s, bool neg, cx<float> (&u)[9]) const {
+    load_link_h(U, mu, s, neg, u);
+  }
+  __device__ __forceinline__ void store(int s, const cx<float> (&v)[12]) const { store_site_h(out, osc, s, v); }
+};
+
+template <int MU, int SIGN, class IO, typename R = typename IO::T>
+__device__ __forceinline__ void hop(const IO& io, int nb, int link_site, bool neg, cx<R> (&acc)[12]) {
+  cx<R> p[12];
+  io.spinor(nb, p);
   cx<R> h[6];
   project<MU, SIGN>(p, h);
   cx<R> u[9];
-  load_link(U, MU, link_site, neg, u);
+  io.link(MU, link_site, neg, u);
   cx<R> uh[6];
 #pragma unroll
   for (int a = 0; a < 2; ++a) {
@@ -71,78 +114,91 @@ __device__ __forceinline__ void batch_block(int nsb, int nrhs, int& sb, int& rhs
   rhs = local % nrhs;
 }
 
-template <typename R>
-__global__ __launch_bounds__(kDslashThreads) void k_dslash(Geom g, cx<R>* __restrict__ out,
-                                                          const cx<R>* __restrict__ in,
-                                                          const cx<R>* __restrict__ U, R diag, int tneg, int nsb,
-                                                          int nrhs) {
+template <class IO, typename R = typename IO::T>
+__global__ __launch_bounds__(kDslashThreads) void k_dslash(Geom g, IO io, R diag, int tneg, int nsb, int nrhs) {
   int sb, rhs;
   batch_block(nsb, nrhs, sb, rhs);
   const int s = sb * kDslashThreads + threadIdx.x;
-  const size_t off = (size_t)rhs * 12 * g.vpad;
-  in += off;
-  out += off;
-  if (s >= g.vol) {
-    if (s < g.vpad) {
+  io.select_rhs(rhs, g.vpad);
+  cx<R> acc[12];
 #pragma unroll
-      for (int k = 0; k < 12; ++k) out[fidx(s, k, 12)] = mk<R>(0, 0);
-    }
+  for (int k = 0; k < 12; ++k) acc[k] = mk<R>(0, 0);
+  if (s >= g.vol) {
+    if (s < g.vpad) io.store(s, acc);
     return;
   }
   int c[4];
   coords_of(g, s, c);
-  cx<R> acc[12];
-#pragma unroll
-  for (int k = 0; k < 12; ++k) acc[k] = mk<R>(0, 0);
   const bool tlast = tneg && c[3] == g.L[3] - 1, tfirst = tneg && c[3] == 0;
   {
     const int f = nbr_fwd(g, s, c, 0), b = nbr_bwd(g, s, c, 0);
-    hop<0, +1>(in, U, f, s, false, acc);
-    hop<0, -1>(in, U, b, b, false, acc);
+    hop<0, +1>(io, f, s, false, acc);
+    hop<0, -1>(io, b, b, false, acc);
   }
   {
     const int f = nbr_fwd(g, s, c, 1), b = nbr_bwd(g, s, c, 1);
-    hop<1, +1>(in, U, f, s, false, acc);
-    hop<1, -1>(in, U, b, b, false, acc);
+    hop<1, +1>(io, f, s, false, acc);
+    hop<1, -1>(io, b, b, false, acc);
   }
   {
     const int f = nbr_fwd(g, s, c, 2), b = nbr_bwd(g, s, c, 2);
-    hop<2, +1>(in, U, f, s, false, acc);
-    hop<2, -1>(in, U, b, b, false, acc);
+    hop<2, +1>(io, f, s, false, acc);
+    hop<2, -1>(io, b, b, false, acc);
   }
   {
     const int f = nbr_fwd(g, s, c, 3), b = nbr_bwd(g, s, c, 3);
-    hop<3, +1>(in, U, f, s, tlast, acc);
-    hop<3, -1>(in, U, b, b, tfirst, acc);
+    hop<3, +1>(io, f, s, tlast, acc);
+    hop<3, -1>(io, b, b, tfirst, acc);
   }
   const R half = (R)0.5;
+  cx<R> p[12];
+  io.spinor(s, p);
 #pragma unroll
-  for (int k = 0; k < 12; ++k) {
-    const cx<R> p = in[fidx(s, k, 12)];
-    out[fidx(s, k, 12)] = mk<R>(diag * p.re - half * acc[k].re, diag * p.im - half * acc[k].im);
-  }
+  for (int k = 0; k < 12; ++k) acc[k] = mk<R>(diag * p[k].re - half * acc[k].re, diag * p[k].im - half * acc[k].im);
+  io.store(s, acc);
+}
+
+template <class IO>
+void launch_dslash(Ctx& c, const IO& io, int nrhs, int prof_id) {
+  const Geom& g = c.g0;
+  const unsigned gx = g.vpad / kDslashThreads + (g.vpad % kDslashThreads != 0);
+  ProfScope ps(c, prof_id, (long long)g.vol * nrhs);
+  const int tneg = c.t_bc < 0 ? 1 : 0;
+  using R = typename IO::T;
+  hipLaunchKernelGGL((k_dslash<IO>), dim3(gx * nrhs), dim3(kDslashThreads), 0, c.stream, g, io, (R)(4.0 + c.mass),
+                     tneg, (int)gx, nrhs);
+  WDMG_HIP(hipGetLastError());
+  c.n_D += nrhs;
 }
 
 }  // namespace
 
 template <typename R>
 void dslash(Ctx& c, cx<R>* out, const cx<R>* in, int nrhs) {
-  const Geom& g = c.g0;
-  const cx<R>* U = nullptr;
+  FullIO<R> io;
+  io.in = in;
+  io.out = out;
   if constexpr (sizeof(R) == 8)
-    U = c.U64;
+    io.U = c.U64;
   else
-    U = c.U32;
-  const unsigned gx = g.vpad / kDslashThreads + (g.vpad % kDslashThreads != 0);
-  ProfScope ps(c, sizeof(R) == 8 ? WDMG_K_DSLASH_F64 : WDMG_K_DSLASH_F32, (long long)g.vol * nrhs);
-  const int tneg = c.t_bc < 0 ? 1 : 0;
-  hipLaunchKernelGGL((k_dslash<R>), dim3(gx * nrhs), dim3(kDslashThreads), 0, c.stream, g, out, in, U,
-                     (R)(4.0 + c.mass), tneg, (int)gx, nrhs);
-  WDMG_HIP(hipGetLastError());
-  c.n_D += nrhs;
+    io.U = c.U32;
+  launch_dslash(c, io, nrhs, sizeof(R) == 8 ? WDMG_K_DSLASH_F64 : WDMG_K_DSLASH_F32);
+}
+
+template <typename H>
+void dslash_h(Ctx& c, HF out, HF in, int nrhs) {
+  HalfIO<H> io;
+  io.in = static_cast<const cxh<H>*>(in.v);
+  io.isc = in.s;
+  io.out = static_cast<cxh<H>*>(out.v);
+  io.osc = out.s;
+  io.U = static_cast<const cxh<H>*>(u16(c, half_kind<H>()));
+  launch_dslash(c, io, nrhs, sizeof(H) == 2 && half_kind<H>() == WDMG_F16 ? WDMG_K_DSLASH_F16 : WDMG_K_DSLASH_BF16);
 }
 
 template void dslash<double>(Ctx&, cx<double>*, const cx<double>*, int);
 template void dslash<float>(Ctx&, cx<float>*, const cx<float>*, int);
+template void dslash_h<f16_t>(Ctx&, HF, HF, int);
+template void dslash_h<bf16_t>(Ctx&, HF, HF, int);
 
 }  // namespace wdmg

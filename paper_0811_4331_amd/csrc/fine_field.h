@@ -26,11 +26,10 @@ __host__ __device__ __forceinline__ size_t fidx(int s, int k, int ncomp) {
   return ((size_t)(s >> 6) * ncomp + k) * 64 + (s & 63);
 }
 
+// Third row of an SU(3) link from its first two: conj(row0 x row1), with
+// the folded boundary sign when neg.
 template <typename R>
-__device__ __forceinline__ void load_link(const cx<R>* __restrict__ U, int mu, int s, bool neg, cx<R> (&u)[9]) {
-  const cx<R>* base = U + fidx(s, mu * 6, kLinkComp);
-#pragma unroll
-  for (int e = 0; e < 6; ++e) u[e] = base[e * 64];
+__device__ __forceinline__ void recon_third_row(cx<R> (&u)[9], bool neg) {
   const cx<R> c0 = u[1] * u[5] - u[2] * u[4];
   const cx<R> c1 = u[2] * u[3] - u[0] * u[5];
   const cx<R> c2 = u[0] * u[4] - u[1] * u[3];
@@ -38,6 +37,14 @@ __device__ __forceinline__ void load_link(const cx<R>* __restrict__ U, int mu, i
   u[6] = mk<R>(sg * c0.re, -sg * c0.im);
   u[7] = mk<R>(sg * c1.re, -sg * c1.im);
   u[8] = mk<R>(sg * c2.re, -sg * c2.im);
+}
+
+template <typename R>
+__device__ __forceinline__ void load_link(const cx<R>* __restrict__ U, int mu, int s, bool neg, cx<R> (&u)[9]) {
+  const cx<R>* base = U + fidx(s, mu * 6, kLinkComp);
+#pragma unroll
+  for (int e = 0; e < 6; ++e) u[e] = base[e * 64];
+  recon_third_row(u, neg);
 }
 
 // Workgroup index remapped so that consecutive tiles (spatial neighbours)

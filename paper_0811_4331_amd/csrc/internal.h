@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <stdexcept>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/wdmg.h"
@@ -58,6 +59,27 @@ enum ScalarSlot {
 inline int gcr_base(int slot_level) { return S_G + slot_level * G_STRIDE; }
 
 // ---------------------------------------------------------------------------
+// 16-bit storage (half_field.h).  A fine field in 16-bit storage is a pair of
+// arrays: values [rhs][vpad/64][12][64] of 4-byte complex and scales
+// [rhs][vpad] of float.
+typedef _Float16 f16_t;
+typedef __bf16 bf16_t;
+template <typename H>
+constexpr int half_kind() {
+  return std::is_same<H, f16_t>::value ? WDMG_F16 : WDMG_BF16;
+}
+struct HF {
+  void* v = nullptr;   // values
+  float* s = nullptr;  // per-site scales
+};
+inline HF hf_rhs(HF f, int rhs, int vpad) {
+  HF r;
+  r.v = static_cast<char*>(f.v) + (size_t)rhs * 12 * vpad * 4;
+  r.s = f.s + (size_t)rhs * vpad;
+  return r;
+}
+
+// ---------------------------------------------------------------------------
 // Memory owned by a context.
 struct Ctx;
 struct Buf {
@@ -83,6 +105,16 @@ struct Level {
   // coarse operator of this level (l >= 1): [site][9][col][row]
   cx<double>* Dc64 = nullptr;
   cx<float>* Dc32 = nullptr;
+  // 16-bit copies, made on first use (kind WDMG_F16 / WDMG_BF16, 0: none):
+  // prolongator columns (unscaled) and coarse blocks with one scale per block
+  void* V16 = nullptr;
+  int v16_kind = 0;
+  void* Dc16 = nullptr;
+  float* Dc16s = nullptr;
+  int dc16_kind = 0;
+  // 16-bit work fields of the fine level (V-cycle in 16-bit storage)
+  HF wh[6];
+  int caph = 0;
   // work vectors of the V-cycle at this level, each holding `cap` fields
   cx<double>* w64[8] = {};
   cx<float>* w32[8] = {};
@@ -113,6 +145,9 @@ struct Ctx {
   bool have_gauge = false;
   cx<double>* U64 = nullptr;   // [4][9][V], t boundary sign folded in
   cx<float>* U32 = nullptr;
+  void* U16 = nullptr;          // 16-bit links, made on first use
+  int u16_kind = 0;             // WDMG_F16 / WDMG_BF16 (0: none)
+  int vc_half = 0;              // 16-bit kind of the running V-cycle (0: none)
 
   double* dsc = nullptr;        // device scalars (S_TOTAL doubles)
   double* partials = nullptr;   // reduction partials
@@ -133,6 +168,8 @@ struct Ctx {
   void* io_a = nullptr;
   void* io_b = nullptr;
   size_t io_bytes = 0;
+  HF ioh[3];                    // 16-bit scratch fine fields
+  int ioh_cap = 0;
 
   // outer FGCR and BiCGStab work space (fine level, FP64)
   int outer_k = 0;
@@ -193,9 +230,38 @@ void fine_to_canonical(Ctx& c, const Geom& g, const cx<R>* in, cx<Rio>* canon, i
 template <typename Rout, typename Rin>
 void convert(Ctx& c, cx<Rout>* out, const cx<Rin>* in, size_t n);
 
+// 16-bit storage (half.hip).  Links and prolongator columns are rounded
+// from their FP32 copies.
+const void* u16(Ctx& c, int kind);
+const void* v16(Ctx& c, Level& L, int kind);
+HF hf_alloc(Ctx& c, int nrhs);
+void hf_free(Ctx& c, HF& f);
+template <typename H>
+void hf_zero(Ctx& c, HF f, int nrhs);
+void hf_copy(Ctx& c, HF dst, HF src, int nrhs);
+// internal R field [rhs][12 vpad] <-> 16-bit field
+template <typename R, typename H>
+void to_half(Ctx& c, const cx<R>* in, HF out, int nrhs);
+template <typename H, typename R>
+void from_half(Ctx& c, HF in, cx<R>* out, int nrhs);
+// canonical complex64 <-> 16-bit field
+template <typename H>
+void canon_to_half(Ctx& c, const cx<float>* canon, HF out, int nrhs);
+template <typename H>
+void half_to_canon(Ctx& c, HF in, cx<float>* canon, int nrhs);
+// Batched MR pieces on 16-bit fields: dsc[slot + 2q] = scale <a_q,b_q>/<a_q,a_q>;
+// x_q += s_q u_q, r_q -= s_q v_q (u may be r).
+template <typename H>
+void step_alpha_half(Ctx& c, HF a, HF b, int nrhs, double scale, int slot);
+template <typename H>
+void update2_half(Ctx& c, HF x, HF u, HF r, HF v, int nrhs, int slot);
+
 // Wilson operator (dslash.hip): out = diag * in - 1/2 sum_mu hops.
 template <typename R>
 void dslash(Ctx& c, cx<R>* out, const cx<R>* in, int nrhs);
+// The same on 16-bit fields and links, FP32 arithmetic.
+template <typename H>
+void dslash_h(Ctx& c, HF out, HF in, int nrhs);
 
 // BLAS-1 and reductions (blas.hip).  Vectors are flat arrays of n complex.
 template <typename R> void zero(Ctx& c, cx<R>* x, size_t n);
@@ -268,6 +334,11 @@ template <typename R>
 void prolongC(Ctx& c, const Level& f, const cx<R>* V, const cx<R>* in, cx<R>* out, int nrhs);
 // Block orthonormalisation in FP64, in place; sets dsc[S_ERR+1] != 0 on rank loss.
 void block_qr0(Ctx& c, const Level& f, cx<double>* V);
+// level 0 with 16-bit fields and prolongator: coarse side in FP32
+template <typename H>
+void restrict0_h(Ctx& c, const Level& f, const void* V16, HF in, cx<float>* out, int nrhs);
+template <typename H>
+void prolong0_h(Ctx& c, const Level& f, const void* V16, const cx<float>* in, HF out, int nrhs);
 void block_qrC(Ctx& c, const Level& f, cx<double>* V);
 
 // Coarse operator (coarse.hip).
@@ -278,5 +349,9 @@ template <typename R>
 void coarse_apply(Ctx& c, const Level& cl, const cx<R>* Dc, cx<R>* out, const cx<R>* in, int nrhs,
                   cx<R>* copy = nullptr);
 void coarse_shift(Ctx& c, Level& cl, double dm);
+// out = D_c in with the blocks stored in 16-bit (one scale per block), FP32
+// vectors; the 16-bit blocks are made from the FP64 ones on first use.
+void coarse_apply_h(Ctx& c, Level& cl, int kind, cx<float>* out, const cx<float>* in, int nrhs,
+                    cx<float>* copy = nullptr);
 
 }  // namespace wdmg

@@ -149,12 +149,20 @@ const cx<float>* stencil<float>(const Level& L) {
   return L.Dc32;
 }
 
+// Coarse levels of a V-cycle running in 16-bit storage (c.vc_half) apply
+// their 16-bit coarse blocks to FP32 vectors.
 template <typename R>
 void apply_op(Ctx& c, int l, cx<R>* out, const cx<R>* in, int nrhs) {
   if (l == 0)
     dslash<R>(c, out, in, nrhs);
-  else
+  else if constexpr (sizeof(R) == 4) {
+    if (c.vc_half)
+      coarse_apply_h(c, c.lev[l], c.vc_half, out, in, nrhs);
+    else
+      coarse_apply<R>(c, c.lev[l], stencil<R>(c.lev[l]), out, in, nrhs);
+  } else {
     coarse_apply<R>(c, c.lev[l], stencil<R>(c.lev[l]), out, in, nrhs);
+  }
 }
 
 template <typename R>
@@ -295,15 +303,14 @@ void coarsest_solve(Ctx& c, cx<double>* x, const cx<double>* b, int nrhs) {
 template <typename R>
 void vcycle(Ctx& c, int l, cx<R>* x, const cx<R>* b, int nrhs);
 
+// Coarse-grid solve of level lc >= 1 for the restricted residual rc: the
+// FP64 GCR on the coarsest level, else the stationary iteration
+// e <- e + M_lc (r_c - D_lc e) from e = 0 (Sec. 5).
 template <typename R>
-void coarse_correction(Ctx& c, int l, const cx<R>* res, cx<R>* y, int nrhs) {
-  Level& C = c.lev[l + 1];
+void coarse_solve_level(Ctx& c, int lc, cx<R>* rc, cx<R>* ec, int nrhs) {
+  Level& C = c.lev[lc];
   const size_t nc = C.n * nrhs;
-  cx<R>* rc = work<R>(C, 5);
-  cx<R>* ec = work<R>(C, 6);
-  restrict_to<R>(c, l, res, rc, nrhs);
-  if (l + 1 == c.nlevels - 1) {
-    // coarsest level: FP64 GCR
+  if (lc == c.nlevels - 1) {
     if constexpr (sizeof(R) == 8) {
       coarsest_solve(c, ec, rc, nrhs);
     } else {
@@ -312,19 +319,27 @@ void coarse_correction(Ctx& c, int l, const cx<R>* res, cx<R>* y, int nrhs) {
       convert<float, double>(c, ec, C.w64[6], nc);
     }
   } else {
-    // Sec. 5: stationary iteration e <- e + M_{l+1} (r_c - D_{l+1} e) from e = 0
     const int ncyc = c.mg.coarse_cycles > 0 ? c.mg.coarse_cycles : 1;
     cx<R>* t = work<R>(C, 7);
     cx<R>* xo = work<R>(C, 0);
-    vcycle<R>(c, l + 1, xo, rc, nrhs);
+    vcycle<R>(c, lc, xo, rc, nrhs);
     copy<R>(c, ec, xo, nc);
     for (int it = 1; it < ncyc; ++it) {
-      apply_op<R>(c, l + 1, t, ec, nrhs);
+      apply_op<R>(c, lc, t, ec, nrhs);
       xmy<R>(c, rc, t, nc);
-      vcycle<R>(c, l + 1, xo, t, nrhs);
+      vcycle<R>(c, lc, xo, t, nrhs);
       add<R>(c, ec, xo, nc);
     }
   }
+}
+
+template <typename R>
+void coarse_correction(Ctx& c, int l, const cx<R>* res, cx<R>* y, int nrhs) {
+  Level& C = c.lev[l + 1];
+  cx<R>* rc = work<R>(C, 5);
+  cx<R>* ec = work<R>(C, 6);
+  restrict_to<R>(c, l, res, rc, nrhs);
+  coarse_solve_level<R>(c, l + 1, rc, ec, nrhs);
   prolong_from<R>(c, l, ec, y, nrhs);
 }
 
@@ -361,6 +376,58 @@ INST(float)
 #undef INST
 
 // ---------------------------------------------------------------------------
+// The fine level of the V-cycle in 16-bit storage: the fine fields, links and
+// P in H with FP32 arithmetic; coarse levels in FP32 with 16-bit coarse
+// blocks; the coarsest solve in FP64.
+void ensure_work_h(Ctx& c, int nrhs) {
+  Level& L = c.lev[0];
+  if (nrhs <= L.caph) return;
+  WDMG_HIP(hipStreamSynchronize(c.stream));
+  for (HF& f : L.wh) {
+    hf_free(c, f);
+    f = hf_alloc(c, nrhs);
+  }
+  L.caph = nrhs;
+}
+
+template <typename H>
+void mr_h(Ctx& c, HF x, HF r, HF p, int nrhs, int iters, double omega) {
+  for (int it = 0; it < iters; ++it) {
+    dslash_h<H>(c, p, r, nrhs);
+    step_alpha_half<H>(c, p, r, nrhs, omega, S_BATCH);
+    update2_half<H>(c, x, r, r, p, nrhs, S_BATCH);
+  }
+}
+
+template <typename H>
+void vcycle_h(Ctx& c, HF x, HF b, int nrhs) {
+  Level& L = c.lev[0];
+  Level& C = c.lev[1];
+  const void* V = v16(c, L, half_kind<H>());
+  HF res = L.wh[0], p = L.wh[1], y = L.wh[2], dy = L.wh[3];
+  hf_zero<H>(c, x, nrhs);
+  hf_copy(c, res, b, nrhs);
+  mr_h<H>(c, x, res, p, nrhs, c.mg.nu_pre, c.mg.omega);
+  cx<float>* rc = C.w32[5];
+  cx<float>* ec = C.w32[6];
+  restrict0_h<H>(c, L, V, res, rc, nrhs);
+  coarse_solve_level<float>(c, 1, rc, ec, nrhs);
+  prolong0_h<H>(c, L, V, ec, y, nrhs);
+  dslash_h<H>(c, dy, y, nrhs);
+  if (c.mg.use_alpha)
+    step_alpha_half<H>(c, dy, res, nrhs, 1.0, S_BATCH);  // Sec. 3 step-size equation
+  else
+    fill_pairs(c, S_BATCH, nrhs, 1.0, 0.0);
+  update2_half<H>(c, x, y, res, dy, nrhs, S_BATCH);
+  mr_h<H>(c, x, res, p, nrhs, c.mg.nu_post, c.mg.omega);
+}
+
+template void mr_h<f16_t>(Ctx&, HF, HF, HF, int, int, double);
+template void mr_h<bf16_t>(Ctx&, HF, HF, HF, int, int, double);
+template void vcycle_h<f16_t>(Ctx&, HF, HF, int);
+template void vcycle_h<bf16_t>(Ctx&, HF, HF, int);
+
+// ---------------------------------------------------------------------------
 // Outer flexible GCR(k) in FP64 (Sec. 5) for nrhs right-hand sides in
 // lockstep, each with its own coefficients; a converged right-hand side is
 // frozen (its steps are zero).  b (input) and x (initial guess, output) are
@@ -370,9 +437,12 @@ int fgcr(Ctx& c, cx<double>* x, const cx<double>* b, int nrhs, const wdmg_solve_
   const size_t n = L.n;
   const size_t bs = n * nrhs;
   const int k = p.restart;
+  const bool half = p.precond && (p.mg_prec == WDMG_F16 || p.mg_prec == WDMG_BF16);
   const bool f32 = p.precond && p.mg_prec == WDMG_F32;
   ensure_outer(c, k, nrhs, f32);
-  if (p.precond) ensure_mg_work(c, nrhs, f32 ? WDMG_F32 : WDMG_F64);
+  if (p.precond) ensure_mg_work(c, nrhs, f32 || half ? WDMG_F32 : WDMG_F64);
+  if (half) ensure_work_h(c, nrhs);
+  HalfScope hs(c, half ? p.mg_prec : 0);
   cx<double>* r = c.outer_r;
   cx<double>* Zb = c.outer_Z;
   cx<double>* Wb = c.outer_W;
@@ -420,7 +490,18 @@ int fgcr(Ctx& c, cx<double>* x, const cx<double>* b, int nrhs, const wdmg_solve_
       cx<double>* z = Zb + (size_t)j * bs;
       cx<double>* w = Wb + (size_t)j * bs;
       if (p.precond) {
-        if (f32) {
+        if (half) {
+          Level& L0 = c.lev[0];
+          if (p.mg_prec == WDMG_F16) {
+            to_half<double, f16_t>(c, r, L0.wh[4], nrhs);
+            vcycle_h<f16_t>(c, L0.wh[5], L0.wh[4], nrhs);
+            from_half<f16_t, double>(c, L0.wh[5], z, nrhs);
+          } else {
+            to_half<double, bf16_t>(c, r, L0.wh[4], nrhs);
+            vcycle_h<bf16_t>(c, L0.wh[5], L0.wh[4], nrhs);
+            from_half<bf16_t, double>(c, L0.wh[5], z, nrhs);
+          }
+        } else if (f32) {
           convert<float, double>(c, c.outer_r32, r, bs);
           vcycle<float>(c, 0, c.outer_z32, c.outer_r32, nrhs);
           convert<double, float>(c, z, c.outer_z32, bs);
@@ -550,6 +631,9 @@ void free_hierarchy(Ctx& c) {
     dev_free(c, L.V32);
     dev_free(c, L.Dc64);
     dev_free(c, L.Dc32);
+    dev_free(c, L.V16);
+    dev_free(c, L.Dc16);
+    dev_free(c, L.Dc16s);
     for (int i = 0; i < kWork; ++i) {
       if (l > 0) {
         dev_free(c, L.w64[i]);
@@ -567,6 +651,8 @@ void free_hierarchy(Ctx& c) {
       }
       blank.cap64 = L.cap64;
       blank.cap32 = L.cap32;
+      for (int i = 0; i < 6; ++i) blank.wh[i] = L.wh[i];
+      blank.caph = L.caph;
     }
     L = blank;
   }

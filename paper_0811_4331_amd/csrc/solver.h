@@ -19,6 +19,20 @@ void mr(Ctx& c, int l, cx<R>* x, cx<R>* r, cx<R>* p, int nrhs, int iters, double
 template <typename R>
 void vcycle(Ctx& c, int l, cx<R>* x, const cx<R>* b, int nrhs);
 void coarsest_solve(Ctx& c, cx<double>* x, const cx<double>* b, int nrhs);
+// 16-bit fine level (x, r, p and b are 16-bit fields of nrhs right-hand sides)
+void ensure_work_h(Ctx& c, int nrhs);
+template <typename H>
+void mr_h(Ctx& c, HF x, HF r, HF p, int nrhs, int iters, double omega);
+template <typename H>
+void vcycle_h(Ctx& c, HF x, HF b, int nrhs);
+
+// Sets the 16-bit kind of the coarse operators (Ctx::vc_half) for a scope.
+struct HalfScope {
+  Ctx& c;
+  int saved;
+  HalfScope(Ctx& ctx, int kind) : c(ctx), saved(ctx.vc_half) { c.vc_half = kind; }
+  ~HalfScope() { c.vc_half = saved; }
+};
 template <typename R>
 void ensure_work(Ctx& c, int l, int nrhs);
 void ensure_mg_work(Ctx& c, int nrhs, int prec);

@@ -11,7 +11,7 @@
 // Level 0 fields are [12][V] over tile-major sites; chirality chi owns the
 // components 6 chi .. 6 chi + 5.  Level >= 1 fields are [site][dof] with the
 // two chiralities as the two halves of dof.
-#include "fine_field.h"
+#include "half_field.h"
 #include "internal.h"
 
 namespace wdmg {
@@ -194,6 +194,94 @@ __global__ __launch_bounds__(256) void k_prolongC(AggMap map, int dof, const cx<
   out[(size_t)rhs * vstride + idx] = acc;
 }
 
+// ---- level 0 with 16-bit fine fields and prolongator columns ----------------
+// Restriction: one workgroup per (aggregate, rhs) as above; values are read
+// as scale(site) x stored value, P columns unscaled.
+template <typename H>
+__global__ __launch_bounds__(256) void k_restrict0_h(Rows0 rows, int nrows, const cxh<H>* __restrict__ Vv,
+                                                     size_t vstride, const cxh<H>* __restrict__ in,
+                                                     const float* __restrict__ isc, cx<float>* __restrict__ out,
+                                                     int nagg, int nv, int vpad) {
+  __shared__ double lds[4 * KC * 4];
+  const int agg = blockIdx.x, rhs = blockIdx.y;
+  in += (size_t)rhs * 12 * vpad;
+  isc += (size_t)rhs * vpad;
+  out += ((size_t)rhs * nagg + agg) * 2 * nv;
+  const int bvol = rows.map.bvol;
+  for (int k0 = 0; k0 < nv; k0 += KC) {
+    double v[4 * KC];
+#pragma unroll
+    for (int q = 0; q < 4 * KC; ++q) v[q] = 0.0;
+    for (int chi = 0; chi < 2; ++chi) {
+      for (int r = threadIdx.x; r < nrows; r += blockDim.x) {
+        const int m = r / bvol, l = r - m * bvol;
+        const int site = rows.map.site(agg, l);
+        const size_t o = fidx(site, 6 * chi + m, 12);
+        const float sc = isc[site];
+        const cx<float> q16 = h2f(in[o]);
+        const cx<float> f = mk(sc * q16.re, sc * q16.im);
+#pragma unroll
+        for (int q = 0; q < KC; ++q) {
+          if (k0 + q < nv) {
+            const cx<float> w = h2f(Vv[(size_t)(k0 + q) * vstride + o]);
+            v[4 * q + 2 * chi] += (double)w.re * f.re + (double)w.im * f.im;
+            v[4 * q + 2 * chi + 1] += (double)w.re * f.im - (double)w.im * f.re;
+          }
+        }
+      }
+    }
+    block_sum<4 * KC>(v, lds);
+    if (threadIdx.x == 0) {
+      for (int q = 0; q < KC && k0 + q < nv; ++q) {
+        out[k0 + q] = mk((float)v[4 * q], (float)v[4 * q + 1]);
+        out[nv + k0 + q] = mk((float)v[4 * q + 2], (float)v[4 * q + 3]);
+      }
+    }
+  }
+}
+
+// Prolongation into a 16-bit field: one thread per site and RBH right-hand
+// sides (each site's 12 components are needed together for its scale).
+constexpr int RBH = 4;
+template <typename H>
+__global__ __launch_bounds__(256) void k_prolong0_h(AggMap map, const cxh<H>* __restrict__ Vv,
+                                                    const cx<float>* __restrict__ in, cxh<H>* __restrict__ out,
+                                                    float* __restrict__ osc, int nagg, int nv, int nrhs) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r0 = blockIdx.y * RBH;
+  const int nr = min(RBH, nrhs - r0);
+  const int vpad = map.g.vpad;
+  const size_t n = (size_t)12 * vpad;
+  if (s >= vpad) return;
+  cx<float> acc[RBH][12];
+#pragma unroll
+  for (int q = 0; q < RBH; ++q)
+#pragma unroll
+    for (int m = 0; m < 12; ++m) acc[q][m] = mk(0.0f, 0.0f);
+  if (s < map.g.vol) {
+    const int agg = map.agg_of(s);
+    for (int k = 0; k < nv; ++k) {
+      cx<float> w[12];
+#pragma unroll
+      for (int m = 0; m < 12; ++m) w[m] = h2f(Vv[(size_t)k * n + fidx(s, m, 12)]);
+#pragma unroll
+      for (int q = 0; q < RBH; ++q) {
+        if (q < nr) {
+          const cx<float>* ec = in + ((size_t)(r0 + q) * nagg + agg) * 2 * nv;
+          const cx<float> e0 = ec[k], e1 = ec[nv + k];
+#pragma unroll
+          for (int m = 0; m < 6; ++m) cmadd(acc[q][m], w[m], e0);
+#pragma unroll
+          for (int m = 6; m < 12; ++m) cmadd(acc[q][m], w[m], e1);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < RBH; ++q)
+    if (q < nr) store_site_h(out + (size_t)(r0 + q) * n, osc + (size_t)(r0 + q) * vpad, s, acc[q]);
+}
+
 // ---- block orthonormalisation (FP64): CGS with a second pass --------------
 // One workgroup per (aggregate, chirality); column j is orthogonalised
 // against columns 0..j-1 twice, then normalised by its (real, positive) norm,
@@ -330,6 +418,33 @@ void prolongC(Ctx& c, const Level& f, const cx<R>* V, const cx<R>* in, cx<R>* ou
                      V, in, out, nagg_of(f), f.nv);
   WDMG_HIP(hipGetLastError());
 }
+
+template <typename H>
+void restrict0_h(Ctx& c, const Level& f, const void* V16, HF in, cx<float>* out, int nrhs) {
+  Rows0 rows{make_map(f)};
+  const int nrows = rows.nrows();
+  const int nagg = nagg_of(f);
+  ProfScope ps(c, WDMG_K_RESTRICT_H, (long long)f.nsite * nrhs);
+  hipLaunchKernelGGL((k_restrict0_h<H>), dim3(nagg, nrhs), dim3(tpb_for(nrows)), 0, c.stream, rows, nrows,
+                     static_cast<const cxh<H>*>(V16), f.n, static_cast<const cxh<H>*>(in.v), in.s, out, nagg, f.nv,
+                     f.g.vpad);
+  WDMG_HIP(hipGetLastError());
+}
+
+template <typename H>
+void prolong0_h(Ctx& c, const Level& f, const void* V16, const cx<float>* in, HF out, int nrhs) {
+  const AggMap map = make_map(f);
+  ProfScope ps(c, WDMG_K_PROLONG_H, (long long)f.nsite * nrhs);
+  hipLaunchKernelGGL((k_prolong0_h<H>), dim3((f.g.vpad + 255) / 256, (nrhs + RBH - 1) / RBH), dim3(256), 0,
+                     c.stream, map, static_cast<const cxh<H>*>(V16), in, static_cast<cxh<H>*>(out.v), out.s,
+                     nagg_of(f), f.nv, nrhs);
+  WDMG_HIP(hipGetLastError());
+}
+
+template void restrict0_h<f16_t>(Ctx&, const Level&, const void*, HF, cx<float>*, int);
+template void restrict0_h<bf16_t>(Ctx&, const Level&, const void*, HF, cx<float>*, int);
+template void prolong0_h<f16_t>(Ctx&, const Level&, const void*, const cx<float>*, HF, int);
+template void prolong0_h<bf16_t>(Ctx&, const Level&, const void*, const cx<float>*, HF, int);
 
 void block_qr0(Ctx& c, const Level& f, cx<double>* V) {
   Rows0 rows{make_map(f)};

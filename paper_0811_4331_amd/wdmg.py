@@ -28,7 +28,8 @@ ERRORS = {-1: "WDMG_ERR_ARG", -2: "WDMG_ERR_DIMS", -3: "WDMG_ERR_OOM", -4: "WDMG
           -5: "WDMG_ERR_NOT_SETUP", -6: "WDMG_ERR_NAN", -7: "WDMG_ERR_RANK_DEFICIENT"}
 PREC = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
 KERNELS = ["dslash_f64", "dslash_f32", "dc_f64", "dc_f32", "restrict_f64", "restrict_f32",
-           "prolong_f64", "prolong_f32", "dc_build", "block_qr", "dc_mfma_f64", "dc_mfma_f32"]
+           "prolong_f64", "prolong_f32", "dc_build", "block_qr", "dc_mfma_f64", "dc_mfma_f32",
+           "dslash_f16", "dslash_bf16", "restrict_h", "prolong_h", "dc_h", "dc_mfma_h"]
 MAX_LEVELS = 4
 
 
@@ -103,6 +104,7 @@ def load() -> ctypes.CDLL:
         "wdmg_set_gauge": (ip, [vp, vp, ip]),
         "wdmg_set_mass": (ip, [vp, dp]),
         "wdmg_apply_D": (ip, [vp, vp, vp, ip, ip]),
+        "wdmg_roundtrip": (ip, [vp, vp, vp, ip, ip]),
         "wdmg_mg_setup": (ip, [vp, ctypes.POINTER(MgParams)]),
         "wdmg_get_prolongator": (ip, [vp, ip, vp]),
         "wdmg_apply_Dc": (ip, [vp, ip, vp, vp, ip, ip]),
@@ -222,6 +224,16 @@ class Context:
         out = torch.empty_like(psi) if out is None else out
         self._check(self.lib.wdmg_apply_D(self.h, _ptr(out, _cdtype(prec), "out"),
                                           _ptr(psi, _cdtype(prec), "in"), nrhs, PREC[prec]))
+        return out
+
+    def roundtrip(self, psi: torch.Tensor, prec: str = "f32"):
+        """``psi`` converted into the internal fine-field storage of ``prec`` and back."""
+        nrhs = self._nrhs(psi, 6)
+        if tuple(psi.shape[-6:]) != self.fine_shape():
+            raise ValueError("fine field shape mismatch")
+        out = torch.empty_like(psi)
+        self._check(self.lib.wdmg_roundtrip(self.h, _ptr(out, _cdtype(prec), "out"),
+                                            _ptr(psi, _cdtype(prec), "in"), nrhs, PREC[prec]))
         return out
 
     def mg_setup(self, levels, *, omega=0.8, nu_pre=2, nu_post=2, coarse_cycles=4,

@@ -58,3 +58,14 @@ int main(void){printf("%zu %zu %zu %zu\n", sizeof(wdmg_level_params), sizeof(wdm
         sizes = [int(v) for v in subprocess.run([exe], capture_output=True, text=True).stdout.split()]
     assert sizes == [ctypes.sizeof(wdmg.LevelParams), ctypes.sizeof(wdmg.MgParams),
                      ctypes.sizeof(wdmg.SolveParams), ctypes.sizeof(wdmg.SolveStats)]
+
+
+def test_kernel_ids_match_the_header():
+    import re
+    with open(wdmg.HEADER) as fh:
+        text = fh.read()
+    body = re.search(r"enum \{\s*(WDMG_K_DSLASH_F64[^}]*)\}", text).group(1)
+    names = [n.strip() for n in body.replace("\n", " ").split(",") if n.strip()]
+    names = [n.split("=")[0].strip() for n in names]
+    assert names[-1] == "WDMG_K_COUNT"
+    assert [n[len("WDMG_K_"):].lower() for n in names[:-1]] == wdmg.KERNELS

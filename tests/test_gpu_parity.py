@@ -271,8 +271,10 @@ def test_error_paths():
     assert not st[0]["converged"] and st[0]["iters"] == 1
     z, sz = ctx.solve(torch.zeros(ctx.fine_shape(), dtype=torch.complex128, device=DEV))
     assert sz[0]["converged"] and not torch.any(z)
-    with pytest.raises(wdmg.WdmgError) as e:
-        ctx.apply_D(gpu(synthetic.gaussian_spinor(dims, 4).astype(np.complex64)), prec="bf16")
+    f32 = gpu(synthetic.gaussian_spinor(dims, 4).astype(np.complex64))
+    o32 = torch.empty_like(f32)
+    with pytest.raises(wdmg.WdmgError) as e:  # unknown precision code
+        ctx._check(ctx.lib.wdmg_apply_D(ctx.h, o32.data_ptr(), f32.data_ptr(), 1, 7))
     assert e.value.name == "WDMG_ERR_ARG"
     # links that are not SU(3) are rejected (the library stores two rows per link)
     bad = u.copy()
