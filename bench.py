@@ -35,7 +35,7 @@ sys.path.insert(0, ROOT)
 METRIC = "MG time-to-solution @ rel.res 1e-10 (s/RHS); Dslash GB/s; D_c MFMA util"
 HBM_PEAK_GBS = 8000.0
 # Algorithmic (compulsory) bytes per work unit, per kernel.
-DSLASH_BYTES = {"f64": 960, "f32": 480}          # per fine site: psi in, 4 links, out
+DSLASH_BYTES = {"f64": 960, "f32": 480, "f16": 248, "bf16": 248}  # per fine site: psi in, 4 links, out
 
 
 def dc_bytes(prec, nv):                            # per coarse site: 9 blocks + in + out
@@ -55,6 +55,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--L", type=int, default=16, help="lattice extent (L^4)")
+    ap.add_argument("--dims", type=int, nargs=4, default=None, metavar=("LX", "LY", "LZ", "LT"),
+                    help="lattice extents (overrides --L)")
+    ap.add_argument("--mcrit-dims", type=int, nargs=4, default=None, metavar=("LX", "LY", "LZ", "LT"),
+                    help="take m_crit from the oracle's value for this lattice at the same eps "
+                         "(for lattices too large for the host Arnoldi)")
     ap.add_argument("--eps", type=float, default=0.3)
     ap.add_argument("--delta", type=float, default=0.01, help="m - m_crit")
     ap.add_argument("--mass", type=float, default=None,
@@ -62,10 +67,11 @@ def parse():
     ap.add_argument("--nv", type=int, default=20)
     ap.add_argument("--setup-iters", type=int, default=100)
     ap.add_argument("--nrhs", type=int, default=1)
-    ap.add_argument("--mg-prec", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--mg-prec", default="f64", choices=["f64", "f32", "f16", "bf16"])
     ap.add_argument("--coarse-tol", type=float, default=0.1)
-    ap.add_argument("--no-alpha", action="store_true",
-                    help="skip the minimal-residual step after prolongation (alpha = 1)")
+    ap.add_argument("--alpha", action="store_true",
+                    help="take the minimal-residual step size after prolongation (off: alpha = 1, "
+                         "which converges in far fewer outer iterations on these fields)")
     ap.add_argument("--big-L", type=int, default=32, help="lattice for the out-of-cache Dslash figure (0: skip)")
     ap.add_argument("--no-bicgstab", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -86,6 +92,12 @@ def load_mcrit(dims, eps, seed):
     return float(data[key]["m_crit"])
 
 
+def workload_number(dims):
+    """Seed family of a lattice: 8^4 -> 1, 16^4 -> 2, 32^4 -> 3, 24^3x48 -> 4, 48^3x96 -> 5."""
+    return {(8, 8, 8, 8): 1, (16, 16, 16, 16): 2, (32, 32, 32, 32): 3, (24, 24, 24, 48): 4,
+            (48, 48, 48, 96): 5}.get(tuple(dims), 9)
+
+
 def dslash_bandwidth(wdmg, synthetic, torch, dev, L, reps=20):
     """Dslash kernel time on an L^4 lattice (links exp(i 0.45 H)), FP64 and FP32."""
     dims = (L, L, L, L)
@@ -96,7 +108,8 @@ def dslash_bandwidth(wdmg, synthetic, torch, dev, L, reps=20):
     ctx.set_mass(-1.0)
     psi = torch.from_numpy(synthetic.gaussian_spinor(dims, 5)).to(dev)
     out = {}
-    for prec, key in (("f64", "dslash_f64"), ("f32", "dslash_f32")):
+    for prec, key in (("f64", "dslash_f64"), ("f32", "dslash_f32"), ("f16", "dslash_f16"),
+                      ("bf16", "dslash_bf16")):
         x = psi if prec == "f64" else psi.to(torch.complex64)
         ctx.apply_D(x, prec=prec)
         torch.cuda.synchronize()
@@ -111,7 +124,7 @@ def dslash_bandwidth(wdmg, synthetic, torch, dev, L, reps=20):
                      "frac_hbm_peak": DSLASH_BYTES[prec] * units / n / sec / 1e9 / HBM_PEAK_GBS}
     # a batch of 8 right-hand sides (links read once per 2 (FP64) or 4 (FP32) rhs)
     xb = psi.unsqueeze(0).repeat(8, 1, 1, 1, 1, 1, 1)
-    for prec, key in (("f64", "dslash_f64"), ("f32", "dslash_f32")):
+    for prec, key in (("f64", "dslash_f64"), ("f32", "dslash_f32"), ("bf16", "dslash_bf16")):
         x = xb if prec == "f64" else xb.to(torch.complex64)
         ctx.apply_D(x, prec=prec)
         torch.cuda.synchronize()
@@ -187,13 +200,18 @@ def main():
 
     dev = torch.device("cuda:0")
     L = a.L
-    dims = (L, L, L, L)
+    dims = tuple(a.dims) if a.dims else (L, L, L, L)
     i_eps = {0.2: 0, 0.3: 1, 0.45: 2}.get(a.eps, 9)
-    cfg = 1 if L == 8 else 2  # workload numbering of the seeds: 8^4 -> 1, 16^4 -> 2
+    cfg = workload_number(dims)
     gseed = synthetic.gauge_seed(cfg, i_eps)
+    mcrit_src = "oracle Arnoldi on this field"
     if a.mass is not None:
         m = a.mass
         a.delta = float("nan")
+    elif a.mcrit_dims:
+        md = tuple(a.mcrit_dims)
+        m = load_mcrit(md, a.eps, synthetic.gauge_seed(workload_number(md), i_eps)) + a.delta
+        mcrit_src = "oracle Arnoldi on the {} field of the same eps".format("x".join(map(str, md)))
     else:
         m = load_mcrit(dims, a.eps, gseed) + a.delta
     u = synthetic.gauge_field(dims, a.eps, gseed)
@@ -207,7 +225,7 @@ def main():
 
     def step():
         t0 = time.perf_counter()
-        ctx.mg_setup(levels, coarse_tol=a.coarse_tol, use_alpha=not a.no_alpha)
+        ctx.mg_setup(levels, coarse_tol=a.coarse_tol, use_alpha=a.alpha)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         x, st = ctx.solve(b, tol=1e-10, restart=50, maxit=2000, mg_prec=a.mg_prec)
@@ -250,7 +268,7 @@ def main():
     n, units, ms = prof[dom]
     per_launch_s = ms / 1e3 / n
     if dom.startswith("dslash"):
-        bpl = DSLASH_BYTES[dom[-3:]] * units / n
+        bpl = DSLASH_BYTES[dom.split("_")[1]] * units / n
     elif dom.startswith("dc_f"):
         bpl = dc_bytes(dom[-3:], a.nv) * units / n
     elif dom.startswith(("restrict", "prolong")):
@@ -267,20 +285,22 @@ def main():
     dslash_step = None
     if ds[0]:
         sec = ds[2] / 1e3 / ds[0]
-        dslash_step = {"lattice": f"{L}^4", "us_per_launch": sec * 1e6,
+        dslash_step = {"lattice": "x".join(map(str, dims)), "us_per_launch": sec * 1e6,
                        "GB_s": DSLASH_BYTES["f64"] * ds[1] / ds[0] / sec / 1e9}
 
     result = {
         "metric": METRIC, "value": value, "unit": "s/RHS", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": ms_per_step, "higher_is_better": False, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64" if a.mg_prec == "f64" else "f64 outer / f32 V-cycle",
+        "vs_baseline": None, "dtype": "f64" if a.mg_prec == "f64" else f"f64 outer / {a.mg_prec} V-cycle",
         "data": "synthetic",
-        "config": {"workload": f"{L}^4 Wilson-Dirac, links exp(i {a.eps} H), m = m_crit + {a.delta}, "
+        "config": {"workload": f"{'x'.join(map(str, dims))} Wilson-Dirac, links exp(i {a.eps} H), "
+                               f"m = m_crit + {a.delta}, "
                                f"2-level MG 4^4 aggregates Nv={a.nv}, MR setup {a.setup_iters} iters, "
                                f"FGCR(50) to 1e-10, {a.nrhs} Gaussian RHS",
-                   "lattice": list(dims), "eps": a.eps, "m": m, "m_crit": m - a.delta, "nv": a.nv,
+                   "lattice": list(dims), "eps": a.eps, "m": m, "m_crit": m - a.delta,
+                   "m_crit_source": mcrit_src, "nv": a.nv,
                    "nrhs": a.nrhs, "mg_prec": a.mg_prec, "coarse_tol": a.coarse_tol,
-                   "alpha_step": not a.no_alpha},
+                   "alpha_step": a.alpha},
         "setup_s": float(np.median(setups)), "solve_s_per_rhs": float(np.median(solves)) / a.nrhs,
         "mg_iters": [s["iters"] for s in last], "mg_n_D": [s["n_D"] for s in last],
         "mg_n_Dc": [s["n_Dc"][1] for s in last], "true_res": true_res,

@@ -206,13 +206,15 @@ int wdmg_solve_bicgstab(wdmg_ctx* ctx, void* x, const void* b, int nrhs, double 
  * launch of the kernels below.  `units` counts the work items the kernel
  * processed: fine sites x rhs (D, P, P^dagger), coarse sites x rhs (D_c
  * apply, on the vector units for one rhs or on the matrix cores (MFMA) for a
- * batch), coarse sites (D_c build) or (aggregate, chirality) blocks (QR). */
+ * batch), coarse sites (D_c build) or (aggregate, chirality) blocks (QR);
+ * WDMG_K_COARSE_GCR is the operator launch of one coarsest-level GCR
+ * iteration (D_c with the Gram-Schmidt partial sums; coarse sites x rhs). */
 enum {
   WDMG_K_DSLASH_F64 = 0, WDMG_K_DSLASH_F32, WDMG_K_DC_F64, WDMG_K_DC_F32,
   WDMG_K_RESTRICT_F64, WDMG_K_RESTRICT_F32, WDMG_K_PROLONG_F64, WDMG_K_PROLONG_F32,
   WDMG_K_DC_BUILD, WDMG_K_BLOCK_QR, WDMG_K_DC_MFMA_F64, WDMG_K_DC_MFMA_F32,
   WDMG_K_DSLASH_F16, WDMG_K_DSLASH_BF16, WDMG_K_RESTRICT_H, WDMG_K_PROLONG_H, WDMG_K_DC_H, WDMG_K_DC_MFMA_H,
-  WDMG_K_COUNT
+  WDMG_K_COARSE_GCR, WDMG_K_COUNT
 };
 
 /* enable = 1 starts recording (and clears earlier records), 0 stops. */

@@ -282,9 +282,9 @@ int wdmg_create(wdmg_ctx** out, const int dims[4], const wdmg_alloc* alloc, void
   int rc = guarded(c, [&]() {
     c->dsc = static_cast<double*>(dev_alloc(*c, S_TOTAL * sizeof(double)));
     c->partials = static_cast<double*>(dev_alloc(*c, (size_t)8192 * 16 * sizeof(double)));
-    c->counter = static_cast<unsigned*>(dev_alloc(*c, 256 * sizeof(unsigned)));
+
     WDMG_HIP(hipMemsetAsync(c->dsc, 0, S_TOTAL * sizeof(double), c->stream));
-    WDMG_HIP(hipMemsetAsync(c->counter, 0, 256 * sizeof(unsigned), c->stream));
+
     WDMG_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->hsc), kHscSize * sizeof(double), hipHostMallocDefault));
     WDMG_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->hring), kRing * kMaxRhs * sizeof(double),
                            hipHostMallocMapped | hipHostMallocCoherent));
@@ -534,6 +534,7 @@ int wdmg_solve(wdmg_ctx* c, void* x, const void* b, int nrhs, const wdmg_solve_p
     std::vector<wdmg_solve_stats> st(nrhs);
     c->n_D = 0;
     for (int l = 0; l < WDMG_MAX_LEVELS; ++l) c->n_Dc[l] = 0;
+
     const double t0 = now();
     fine_in<double>(*c, b, c->sol_b, nrhs);
     fine_in<double>(*c, x, c->sol_x, nrhs);

@@ -332,54 +332,107 @@ __device__ __forceinline__ R real_entry(const cx<R>* __restrict__ blk, int n2, i
   return pr == 0 ? (pk == 0 ? a.re : -a.im) : (pk == 0 ? a.im : a.re);
 }
 
+// Operands are read straight from memory into the MFMA lane layout (no LDS
+// staging): wave w owns real-row tile w % nrt and the directions
+// d = w / nrt, w / nrt + ng, ... (ng direction groups), so the nine blocks of
+// a site stream in parallel; the groups' partial products are added through
+// LDS in group order.  The right-hand sides of a tile are the columns of the
+// B operand.
+//
 // FP64: v_mfma_f64_16x16x4f64; tile = 16 real rows x 16 rhs.
 // Operand lanes: A[i][k] at lane i + 16k, B[k][j] at lane j + 16k;
 // result D[i][j] in lane j + 16 (i % 4), register i / 4.
-__global__ __launch_bounds__(512) void k_coarse_apply_mfma64(Geom g, int n2, int nrhs,
-                                                             const cx<double>* __restrict__ Dc,
-                                                             const cx<double>* __restrict__ in,
-                                                             cx<double>* __restrict__ out,
-                                                             cx<double>* __restrict__ copy) {
-  __shared__ double Bs[128][17];
-  extern __shared__ cx<double> As64[];  // the block of the current direction, column-major
-  const int s = blockIdx.x, q0 = blockIdx.y * 16;
-  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const size_t nsite = g.vol, fs = nsite * n2;
-  const int kr = 2 * n2;  // real columns per direction
+__host__ __device__ inline int mfma64_row_tiles(int n2) { return (2 * n2 + 15) / 16; }
+__host__ __device__ inline int mfma64_groups(int n2) {
+  const int g = 16 / mfma64_row_tiles(n2);
+  return g < 9 ? g : 9;
+}
+constexpr int kMfma64Lds = 4096;  // doubles of LDS for the group partials
+
+__device__ __forceinline__ void apply_site_mfma64(const Geom& g, int n2, int nrhs, int s, int q0,
+                                                  const cx<double>* __restrict__ Dc, const cx<double>* in,
+                                                  cx<double>* out, double* lds) {
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int nrt = mfma64_row_tiles(n2), ng = mfma64_groups(n2);
+  const int rt = w % nrt, grp = w / nrt;
+  const size_t fs = (size_t)g.vol * n2;
+  const int kr = 2 * n2;
+  const int r = rt * 16 + (l & 15), i = r >> 1, pr = r & 1;
+  const bool rowok = i < n2;
+  const int q = q0 + (l & 15);
+  const bool qok = q < nrhs;
+  const int kl = l >> 4;
   int c[4];
   coords_of(g, s, c);
   doublex4 acc = {0.0, 0.0, 0.0, 0.0};
-  for (int d = 0; d < 9; ++d) {
+  constexpr int KC = 8;  // MFMA steps whose operands are loaded together
+  for (int d = grp; d < 9; d += ng) {
     const int nb = d == 8 ? s : ((d & 1) ? nbr_bwd(g, s, c, d >> 1) : nbr_fwd(g, s, c, d >> 1));
-    __syncthreads();
-    for (int w = threadIdx.x; w < 16 * n2; w += blockDim.x) {
-      const int q = w / n2, j = w % n2;
-      cx<double> v = mk(0.0, 0.0);
-      if (q0 + q < nrhs) v = in[(size_t)(q0 + q) * fs + (size_t)nb * n2 + j];
-      Bs[2 * j][q] = v.re;
-      Bs[2 * j + 1][q] = v.im;
-      if (d == 8 && copy && q0 + q < nrhs) copy[(size_t)(q0 + q) * fs + (size_t)s * n2 + j] = v;
-    }
-    const cx<double>* blk = Dc + ((size_t)s * 9 + d) * n2 * n2;
-    for (int w = threadIdx.x; w < n2 * n2; w += blockDim.x) As64[w] = blk[w];
-    __syncthreads();
-    const int r = wave * 16 + (l & 15);
-    for (int k0 = 0; k0 < kr; k0 += 4) {
-      const int k = k0 + (l >> 4);
-      const double a = real_entry(As64, n2, r, k);
-      const double b = Bs[k][l & 15];
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-    }
-  }
-  const int q = q0 + (l & 15);
-  if (q < nrhs) {
-    double* o = reinterpret_cast<double*>(out + (size_t)q * fs + (size_t)s * n2);
+    const double* blk = reinterpret_cast<const double*>(Dc + ((size_t)s * 9 + d) * n2 * n2);
+    const double* v = reinterpret_cast<const double*>(in + (size_t)(qok ? q : 0) * fs + (size_t)nb * n2);
+    for (int t0 = 0; 4 * t0 < kr; t0 += KC) {
+      double av[KC], bv[KC];
 #pragma unroll
-    for (int reg = 0; reg < 4; ++reg) {
-      const int r = wave * 16 + 4 * reg + (l >> 4);
-      if ((r >> 1) < n2) o[r] = acc[reg];  // real row r = 2 i + part is element r of the site's (re, im) pairs
+      for (int t = 0; t < KC; ++t) {
+        const int k = 4 * (t0 + t) + kl, j = k >> 1, pk = k & 1;
+        av[t] = 0.0;
+        bv[t] = 0.0;
+        if (k < kr) {
+          if (rowok) {
+            const double a = blk[2 * ((size_t)j * n2 + i) + (pr ^ pk)];
+            av[t] = (pr == 0 && pk == 1) ? -a : a;
+          }
+          if (qok) bv[t] = v[2 * j + pk];
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < KC; ++t)
+        if (4 * (t0 + t) < kr) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], bv[t], acc, 0, 0, 0);
     }
   }
+  // groups 1.. hand their partial tiles to group 0
+  if (grp > 0 && grp < ng) {
+    double* dst = lds + ((size_t)((grp - 1) * nrt + rt) * 64 + l) * 4;
+#pragma unroll
+    for (int reg = 0; reg < 4; ++reg) dst[reg] = acc[reg];
+  }
+  __syncthreads();
+  if (grp == 0) {
+    for (int gg = 1; gg < ng; ++gg) {
+      const double* src = lds + ((size_t)((gg - 1) * nrt + rt) * 64 + l) * 4;
+#pragma unroll
+      for (int reg = 0; reg < 4; ++reg) acc[reg] += src[reg];
+    }
+    if (qok) {
+      double* o = reinterpret_cast<double*>(out + (size_t)q * fs + (size_t)s * n2);
+#pragma unroll
+      for (int reg = 0; reg < 4; ++reg) {
+        const int rr = rt * 16 + 4 * reg + (l >> 4);
+        if ((rr >> 1) < n2) o[rr] = acc[reg];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// copy = in on site s for the right-hand sides [q0, q0 + nq) (all threads of the block)
+template <typename R>
+__device__ __forceinline__ void copy_site(int n2, size_t fs, int s, int q0, int nq, const cx<R>* in, cx<R>* copy) {
+  for (int w = threadIdx.x; w < nq * n2; w += blockDim.x) {
+    const int q = q0 + w / n2, j = w % n2;
+    copy[(size_t)q * fs + (size_t)s * n2 + j] = in[(size_t)q * fs + (size_t)s * n2 + j];
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_coarse_apply_mfma64(Geom g, int n2, int nrhs,
+                                                              const cx<double>* __restrict__ Dc,
+                                                              const cx<double>* __restrict__ in,
+                                                              cx<double>* __restrict__ out,
+                                                              cx<double>* __restrict__ copy) {
+  __shared__ double lds[kMfma64Lds];
+  const int s = blockIdx.x, q0 = blockIdx.y * 16;
+  if (copy) copy_site(n2, (size_t)g.vol * n2, s, q0, min(16, nrhs - q0), in, copy);
+  apply_site_mfma64(g, n2, nrhs, s, q0, Dc, in, out, lds);
 }
 
 // FP32: v_mfma_f32_32x32x2f32; tile = 32 real rows x 32 rhs.
@@ -390,46 +443,52 @@ __global__ __launch_bounds__(256) void k_coarse_apply_mfma32(Geom g, int n2, int
                                                              const cx<float>* __restrict__ in,
                                                              cx<float>* __restrict__ out,
                                                              cx<float>* __restrict__ copy) {
-  __shared__ float Bs[128][33];
-  extern __shared__ cx<float> As32[];
   const int s = blockIdx.x, q0 = blockIdx.y * 32;
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const size_t nsite = g.vol, fs = nsite * n2;
+  const size_t fs = (size_t)g.vol * n2;
+  if (copy) copy_site(n2, fs, s, q0, min(32, nrhs - q0), in, copy);
   const int kr = 2 * n2;
+  const int r = wave * 32 + (l & 31), i = r >> 1, pr = r & 1;
+  const bool rowok = i < n2;
+  const int q = q0 + (l & 31);
+  const bool qok = q < nrhs;
+  const int kl = l >> 5;
   int c[4];
   coords_of(g, s, c);
   floatx16 acc;
 #pragma unroll
   for (int e = 0; e < 16; ++e) acc[e] = 0.f;
+  constexpr int KC = 16;  // MFMA steps loaded together
   for (int d = 0; d < 9; ++d) {
     const int nb = d == 8 ? s : ((d & 1) ? nbr_bwd(g, s, c, d >> 1) : nbr_fwd(g, s, c, d >> 1));
-    __syncthreads();
-    for (int w = threadIdx.x; w < 32 * n2; w += blockDim.x) {
-      const int q = w / n2, j = w % n2;
-      cx<float> v = mk(0.f, 0.f);
-      if (q0 + q < nrhs) v = in[(size_t)(q0 + q) * fs + (size_t)nb * n2 + j];
-      Bs[2 * j][q] = v.re;
-      Bs[2 * j + 1][q] = v.im;
-      if (d == 8 && copy && q0 + q < nrhs) copy[(size_t)(q0 + q) * fs + (size_t)s * n2 + j] = v;
-    }
-    const cx<float>* blk = Dc + ((size_t)s * 9 + d) * n2 * n2;
-    for (int w = threadIdx.x; w < n2 * n2; w += blockDim.x) As32[w] = blk[w];
-    __syncthreads();
-    const int r = wave * 32 + (l & 31);
-    for (int k0 = 0; k0 < kr; k0 += 2) {
-      const int k = k0 + (l >> 5);
-      const float a = real_entry(As32, n2, r, k);
-      const float b = Bs[k][l & 31];
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+    const float* blk = reinterpret_cast<const float*>(Dc + ((size_t)s * 9 + d) * n2 * n2);
+    const float* v = reinterpret_cast<const float*>(in + (size_t)(qok ? q : 0) * fs + (size_t)nb * n2);
+    for (int t0 = 0; 2 * t0 < kr; t0 += KC) {
+      float av[KC], bv[KC];
+#pragma unroll
+      for (int t = 0; t < KC; ++t) {
+        const int k = 2 * (t0 + t) + kl, j = k >> 1, pk = k & 1;
+        av[t] = 0.f;
+        bv[t] = 0.f;
+        if (k < kr) {
+          if (rowok) {
+            const float a = blk[2 * ((size_t)j * n2 + i) + (pr ^ pk)];
+            av[t] = (pr == 0 && pk == 1) ? -a : a;
+          }
+          if (qok) bv[t] = v[2 * j + pk];
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < KC; ++t)
+        if (2 * (t0 + t) < kr) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[t], bv[t], acc, 0, 0, 0);
     }
   }
-  const int q = q0 + (l & 31);
-  if (q < nrhs) {
+  if (qok) {
     float* o = reinterpret_cast<float*>(out + (size_t)q * fs + (size_t)s * n2);
 #pragma unroll
     for (int reg = 0; reg < 16; ++reg) {
-      const int r = wave * 32 + 8 * (reg >> 2) + 4 * (l >> 5) + (reg & 3);
-      if ((r >> 1) < n2) o[r] = acc[reg];
+      const int rr = wave * 32 + 8 * (reg >> 2) + 4 * (l >> 5) + (reg & 3);
+      if ((rr >> 1) < n2) o[rr] = acc[reg];
     }
   }
 }
@@ -619,6 +678,193 @@ __global__ __launch_bounds__(256) void k_coarse_apply_mfma16(Geom g, int n2, int
   }
 }
 
+// ---- coarsest-level GCR in three launches per iteration -------------------------
+// GCR(k) on D_c in FP64 for a batch of right-hand sides, each with its own
+// coefficients and stopping test (Sec. 2: the coarsest solve).  Iteration j:
+//   K1  w_j = D_c r, z_j = r, and per workgroup partial sums of
+//       c_i = <W_i, w_j>, d_i = <W_i, r> (i < j), <w_j, w_j>, <w_j, r>, <r, r>
+//   K2  (one workgroup per rhs) the sums in a fixed order; h_i = c_i / |W_i|^2;
+//       |w'|^2 = <w,w> - sum |c_i|^2 / |W_i|^2 and <w', r> = <w, r> - sum h_i^* d_i
+//       for w' = w_j - sum h_i W_i (classical Gram-Schmidt, the W_i orthogonal);
+//       a = <w', r> / |w'|^2; a right-hand side with |r| <= tol |b| is frozen
+//   K3  w_j = w', z_j -= sum h_i Z_i, x += a z_j, r -= a w_j, and partial sums
+//       of the exact |w_j|^2, which K2 of the next iteration stores as |W_j|^2.
+// The stopping test is thus lagged by one iteration; the per-rhs active flags
+// go to pinned host memory, where the host inspects them two iterations
+// later, so it never waits for the GPU inside the solve.
+constexpr int kCgcrG1 = 256;  // workgroups (x) of K1
+constexpr int kCgcrG3 = 64;   // chunks per rhs of K3
+
+struct CgcrState {  // per-rhs device scalars of one solve (inside the level's scalar block)
+  double* h;    // [rhs][2 kMaxKrylov]
+  double* nrm;  // [rhs][kMaxKrylov]
+  double* a;    // [rhs][2]
+  double* rn;   // [rhs]
+  double* act;  // [rhs]
+  double* tol2; // [rhs]
+};
+
+// x = 0, r = b, tol2 = tol^2 |b|^2, active = |b| > 0 (one workgroup per rhs)
+__global__ __launch_bounds__(256) void k_cgcr_init(const cx<double>* __restrict__ b, cx<double>* __restrict__ x,
+                                                   cx<double>* __restrict__ r, size_t n, double tol, CgcrState S,
+                                                   double* err) {
+  __shared__ double red[4];
+  const int q = blockIdx.x;
+  const size_t o = (size_t)q * n;
+  double v[1] = {0.0};
+  for (size_t e = threadIdx.x; e < n; e += blockDim.x) {
+    const cx<double> bv = b[o + e];
+    x[o + e] = mk(0.0, 0.0);
+    r[o + e] = bv;
+    v[0] += bv.re * bv.re + bv.im * bv.im;
+  }
+  block_sum<1>(v, red);
+  if (threadIdx.x == 0) {
+    if (!isfinite(v[0])) err[0] = 1.0;
+    S.tol2[q] = tol * tol * v[0];
+    S.act[q] = v[0] > 0.0 && isfinite(v[0]) ? 1.0 : 0.0;
+    S.rn[q] = v[0];
+  }
+}
+
+// K1: blocks (G1, rhs tiles of 16), one wave per 16 real rows of a site.
+__global__ __launch_bounds__(1024) void k_cgcr_apply(Geom g, int n2, int nrhs, int j, int vals,
+                                                    const cx<double>* __restrict__ Dc, const cx<double>* r,
+                                                    const cx<double>* Wb, cx<double>* w, cx<double>* z,
+                                                    double* part) {
+  extern __shared__ __align__(16) char dyn1[];
+  double* acc = reinterpret_cast<double*>(dyn1);  // [16][vals]
+  __shared__ double lds[kMfma64Lds];
+  const int q0 = blockIdx.y * 16, nq = min(16, nrhs - q0);
+  const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6, lane = threadIdx.x & 63;
+  const size_t fs = (size_t)g.vol * n2, bs = (size_t)nrhs * fs;
+  for (int t = threadIdx.x; t < 16 * vals; t += blockDim.x) acc[t] = 0.0;
+  for (int s = blockIdx.x; s < g.vol; s += gridDim.x) {
+    copy_site(n2, fs, s, q0, nq, r, z);
+    apply_site_mfma64(g, n2, nrhs, s, q0, Dc, r, w, lds);  // ends with a block barrier: w_j of s complete
+    for (int qq = wave; qq < nq; qq += nw) {
+      const size_t o = (size_t)(q0 + qq) * fs + (size_t)s * n2 + lane;
+      cx<double> wv = mk(0.0, 0.0), rv = mk(0.0, 0.0);
+      if (lane < n2) {
+        wv = w[o];
+        rv = r[o];
+      }
+      double* aq = acc + qq * vals;
+      for (int i = 0; i < j; ++i) {
+        cx<double> u = mk(0.0, 0.0);
+        if (lane < n2) u = Wb[(size_t)i * bs + o];
+        const double c_re = wave_sum(u.re * wv.re + u.im * wv.im);
+        const double c_im = wave_sum(u.re * wv.im - u.im * wv.re);
+        const double d_re = wave_sum(u.re * rv.re + u.im * rv.im);
+        const double d_im = wave_sum(u.re * rv.im - u.im * rv.re);
+        if (lane == 0) {
+          aq[2 * i] += c_re;
+          aq[2 * i + 1] += c_im;
+          aq[2 * j + 2 * i] += d_re;
+          aq[2 * j + 2 * i + 1] += d_im;
+        }
+      }
+      const double ww = wave_sum(wv.re * wv.re + wv.im * wv.im);
+      const double wr_re = wave_sum(wv.re * rv.re + wv.im * rv.im);
+      const double wr_im = wave_sum(wv.re * rv.im - wv.im * rv.re);
+      const double rr = wave_sum(rv.re * rv.re + rv.im * rv.im);
+      if (lane == 0) {
+        aq[4 * j] += ww;
+        aq[4 * j + 1] += wr_re;
+        aq[4 * j + 2] += wr_im;
+        aq[4 * j + 3] += rr;
+      }
+    }
+    __syncthreads();
+  }
+  for (int t = threadIdx.x; t < nq * vals; t += blockDim.x) {
+    const int qq = t / vals, v = t % vals;
+    part[((size_t)(q0 + qq) * gridDim.x + blockIdx.x) * vals + v] = acc[t];
+  }
+}
+
+// K2: one workgroup per rhs.  vals = 4 j + 4 partial values per K1 workgroup;
+// p3: K3's partial |w_{j-1}|^2 per chunk (j > 0).
+__global__ __launch_bounds__(256) void k_cgcr_coef(int j, int vals, int g1, const double* __restrict__ part,
+                                                   const double* __restrict__ p3, int kmax, CgcrState S,
+                                                   double* host_act, double* err) {
+  extern __shared__ __align__(16) char dyn2[];
+  double* tot = reinterpret_cast<double*>(dyn2);  // [vals + 1]
+  const int q = blockIdx.x;
+  const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6, lane = threadIdx.x & 63;
+  for (int v = wave; v <= vals; v += nw) {
+    double s = 0.0;
+    if (v < vals) {
+      for (int b = lane; b < g1; b += 64) s += part[((size_t)q * g1 + b) * vals + v];
+    } else if (j > 0) {
+      for (int b = lane; b < kCgcrG3; b += 64) s += p3[(size_t)q * kCgcrG3 + b];
+    }
+    s = wave_sum(s);
+    if (lane == 0) tot[v] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double* nrm = S.nrm + (size_t)q * kmax;
+  double* h = S.h + (size_t)q * 2 * kmax;
+  if (j > 0) nrm[j - 1] = tot[vals];
+  double ww = tot[4 * j], wr_re = tot[4 * j + 1], wr_im = tot[4 * j + 2];
+  const double rr = tot[4 * j + 3];
+  for (int i = 0; i < j; ++i) {
+    const double ni = nrm[i];
+    const double cr = tot[2 * i], ci = tot[2 * i + 1];
+    const double hr = ni > 0.0 ? cr / ni : 0.0, hi = ni > 0.0 ? ci / ni : 0.0;
+    h[2 * i] = hr;
+    h[2 * i + 1] = hi;
+    ww -= hr * cr + hi * ci;  // |c_i|^2 / |W_i|^2
+    const double dr = tot[2 * j + 2 * i], di = tot[2 * j + 2 * i + 1];
+    wr_re -= hr * dr + hi * di;  // conj(h_i) d_i
+    wr_im -= hr * di - hi * dr;
+  }
+  S.rn[q] = rr;
+  if (!isfinite(rr) || !isfinite(ww)) err[0] = 1.0;
+  const bool on = S.act[q] != 0.0 && rr > S.tol2[q];
+  const bool ok = on && ww > 1e-28 * tot[4 * j];
+  S.act[q] = on ? 1.0 : 0.0;
+  S.a[2 * q] = ok ? wr_re / ww : 0.0;
+  S.a[2 * q + 1] = ok ? wr_im / ww : 0.0;
+  if (host_act) host_act[q] = on ? 1.0 : 0.0;
+}
+
+// K3: blocks (kCgcrG3 chunks, rhs).
+__global__ __launch_bounds__(256) void k_cgcr_update(size_t n, int nrhs, int j, int kmax, const cx<double>* Wb,
+                                                     const cx<double>* Zb, cx<double>* w, cx<double>* z,
+                                                     cx<double>* x, cx<double>* r, CgcrState S, double* p3) {
+  __shared__ double red[4];
+  __shared__ double hs[2 * kMaxKrylov];
+  const int q = blockIdx.y;
+  if (S.act[q] == 0.0) {
+    if (threadIdx.x == 0) p3[(size_t)q * kCgcrG3 + blockIdx.x] = 0.0;
+    return;
+  }
+  const double* h = S.h + (size_t)q * 2 * kmax;
+  for (int t = threadIdx.x; t < 2 * j; t += blockDim.x) hs[t] = h[t];
+  __syncthreads();
+  const cx<double> a = mk(S.a[2 * q], S.a[2 * q + 1]);
+  const size_t bs = (size_t)nrhs * n, o = (size_t)q * n;
+  const size_t cs = (n + kCgcrG3 - 1) / kCgcrG3, e0 = blockIdx.x * cs, e1 = e0 + cs < n ? e0 + cs : n;
+  double v[1] = {0.0};
+  for (size_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    cx<double> wv = w[o + e], zv = z[o + e];
+    for (int i = 0; i < j; ++i) {
+      const cx<double> hi = mk(hs[2 * i], hs[2 * i + 1]);
+      wv = wv - hi * Wb[(size_t)i * bs + o + e];
+      zv = zv - hi * Zb[(size_t)i * bs + o + e];
+    }
+    w[o + e] = wv;
+    z[o + e] = zv;
+    x[o + e] = x[o + e] + a * zv;
+    r[o + e] = r[o + e] - a * wv;
+    v[0] += wv.re * wv.re + wv.im * wv.im;
+  }
+  block_sum<1>(v, red);
+  if (threadIdx.x == 0) p3[(size_t)q * kCgcrG3 + blockIdx.x] = v[0];
+}
+
 template <typename R>
 __global__ void k_coarse_shift(cx<R>* Dc, int nsite, int n2, double dm) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -664,21 +910,13 @@ void coarse_apply(Ctx& c, const Level& cl, const cx<R>* Dc, cx<R>* out, const cx
     // matrix-core path for a batch of right-hand sides
     if constexpr (sizeof(R) == 8) {
       ProfScope ps(c, WDMG_K_DC_MFMA_F64, (long long)cl.nsite * nrhs);
-      const int waves = (2 * n2 + 15) / 16;
-      const size_t lds = (size_t)n2 * n2 * sizeof(cx<double>);
-      static bool attr = false;
-      if (!attr) {
-        WDMG_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_coarse_apply_mfma64),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 64 * sizeof(cx<double>)));
-        attr = true;
-      }
-      hipLaunchKernelGGL(k_coarse_apply_mfma64, dim3(cl.nsite, (nrhs + 15) / 16), dim3(64 * waves), lds, c.stream,
+      const int waves = mfma64_row_tiles(n2) * mfma64_groups(n2);
+      hipLaunchKernelGGL(k_coarse_apply_mfma64, dim3(cl.nsite, (nrhs + 15) / 16), dim3(64 * waves), 0, c.stream,
                          cl.g, n2, nrhs, Dc, in, out, copy);
     } else {
       ProfScope ps(c, WDMG_K_DC_MFMA_F32, (long long)cl.nsite * nrhs);
       const int waves = (2 * n2 + 31) / 32;
-      const size_t lds = (size_t)n2 * n2 * sizeof(cx<float>);
-      hipLaunchKernelGGL(k_coarse_apply_mfma32, dim3(cl.nsite, (nrhs + 31) / 32), dim3(64 * waves), lds, c.stream,
+      hipLaunchKernelGGL(k_coarse_apply_mfma32, dim3(cl.nsite, (nrhs + 31) / 32), dim3(64 * waves), 0, c.stream,
                          cl.g, n2, nrhs, Dc, in, out, copy);
     }
     WDMG_HIP(hipGetLastError());
@@ -742,6 +980,61 @@ void coarse_apply_h(Ctx& c, Level& cl, int kind, cx<float>* out, const cx<float>
   WDMG_HIP(hipGetLastError());
   c.n_Dc[cl.l] += nrhs;
 }
+
+void coarsest_gcr(Ctx& c, Level& L, cx<double>* x, const cx<double>* b, int nrhs, double tol, int k, int maxit) {
+  const int n2 = L.dof;
+  const size_t n = L.n, bs = (size_t)nrhs * n;
+  double* gb = c.dsc + gcr_base(L.l);
+  CgcrState S{gb + G_H, gb + G_NRM, gb + G_A, gb + G_RN, gb + G_ACT, gb + G_TOL};
+  const int g1 = L.nsite < kCgcrG1 ? L.nsite : kCgcrG1;
+  const int ntile = (nrhs + 15) / 16, waves = mfma64_row_tiles(n2) * mfma64_groups(n2);
+  static bool lds_attr = false;
+  if (!lds_attr) {  // K1 keeps 16 x (4 k + 4) partial sums in LDS (k <= 128)
+    WDMG_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cgcr_apply),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, 16 * (4 * kMaxKrylov + 4) * 8));
+    lds_attr = true;
+  }
+  hipLaunchKernelGGL(k_cgcr_init, dim3(nrhs), dim3(256), 0, c.stream, b, x, L.w64[1], n, tol, S, c.dsc + S_ERR);
+  WDMG_HIP(hipGetLastError());
+  cx<double>* r = L.w64[1];
+  // The active flags of iteration it land in pinned memory and are inspected
+  // `lag` iterations later, so the stream never drains while the host waits.
+  const int lag = 2;
+  auto done_at = [&](int i) {
+    WDMG_HIP(hipEventSynchronize(c.ring_ev[i % kRing]));
+    const double* f = c.hring + (size_t)(i % kRing) * kMaxRhs;
+    for (int q = 0; q < nrhs; ++q)
+      if (f[q] != 0.0) return false;
+    return true;
+  };
+  int it = 0;
+  for (; it < maxit; ++it) {
+    const int j = it % k;
+    cx<double>* w = L.basisW + (size_t)j * bs;
+    cx<double>* z = L.basisZ + (size_t)j * bs;
+    const int vals = 4 * j + 4;
+    {
+      ProfScope ps(c, WDMG_K_COARSE_GCR, (long long)L.nsite * nrhs);
+      hipLaunchKernelGGL(k_cgcr_apply, dim3(g1, ntile), dim3(64 * waves), (size_t)16 * vals * sizeof(double),
+                         c.stream, L.g, n2, nrhs, j, vals, L.Dc64, r, L.basisW, w, z, L.cpart);
+      WDMG_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_cgcr_coef, dim3(nrhs), dim3(256), (size_t)(vals + 1) * sizeof(double), c.stream, j, vals,
+                       g1, L.cpart, L.cpart3, k, S, c.dring + (size_t)(it % kRing) * kMaxRhs, c.dsc + S_ERR);
+    WDMG_HIP(hipGetLastError());
+    WDMG_HIP(hipEventRecord(c.ring_ev[it % kRing], c.stream));
+    hipLaunchKernelGGL(k_cgcr_update, dim3(kCgcrG3, nrhs), dim3(256), 0, c.stream, n, nrhs, j, k, L.basisW,
+                       L.basisZ, w, z, x, r, S, L.cpart3);
+    WDMG_HIP(hipGetLastError());
+    c.n_Dc[L.l] += nrhs;
+    if (it >= lag && done_at(it - lag)) break;
+  }
+}
+
+size_t coarsest_gcr_partials(int nrhs, int k) {
+  return (size_t)nrhs * kCgcrG1 * (4 * k + 4);
+}
+size_t coarsest_gcr_partials3(int nrhs) { return (size_t)nrhs * kCgcrG3; }
 
 template void coarse_apply<double>(Ctx&, const Level&, const cx<double>*, cx<double>*, const cx<double>*, int,
                                    cx<double>*);

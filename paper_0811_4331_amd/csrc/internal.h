@@ -46,13 +46,14 @@ enum ScalarSlot {
   S_BATCH = S_GCR + 4 * S_GCR_STRIDE,  // batched step sizes: 2 per rhs
   // Batched GCR state, one block per level (0..3) and one for the outer solve
   // (index 4): h [rhs][2*kMaxKrylov], nrm [rhs][kMaxKrylov], a [rhs][2],
-  // rnorm^2 [rhs], active [rhs].
+  // rnorm^2 [rhs], active [rhs], target rnorm^2 [rhs].
   G_H = 0,
   G_NRM = G_H + kMaxRhs * 2 * kMaxKrylov,
   G_A = G_NRM + kMaxRhs * kMaxKrylov,
   G_RN = G_A + 2 * kMaxRhs,
   G_ACT = G_RN + kMaxRhs,
-  G_STRIDE = G_ACT + kMaxRhs,
+  G_TOL = G_ACT + kMaxRhs,
+  G_STRIDE = G_TOL + kMaxRhs,
   S_G = S_BATCH + 2 * kMaxRhs,
   S_TOTAL = S_G + 5 * G_STRIDE
 };
@@ -123,6 +124,8 @@ struct Level {
   // GCR basis of the coarsest solve (coarsest level only)
   cx<double>* basisZ = nullptr;
   cx<double>* basisW = nullptr;
+  double* cpart = nullptr;   // partial sums of the coarsest GCR
+  double* cpart3 = nullptr;
 };
 
 constexpr int kWork = 8;
@@ -149,9 +152,10 @@ struct Ctx {
   int u16_kind = 0;             // WDMG_F16 / WDMG_BF16 (0: none)
   int vc_half = 0;              // 16-bit kind of the running V-cycle (0: none)
 
+
   double* dsc = nullptr;        // device scalars (S_TOTAL doubles)
   double* partials = nullptr;   // reduction partials
-  unsigned* counter = nullptr;  // last-block counters
+
   double* hsc = nullptr;        // pinned host mirror of a few scalars
   double* hring = nullptr;      // pinned ring [kRing][kMaxRhs] for lagged residual checks (host view)
   double* dring = nullptr;      // the same ring as seen from the device
@@ -349,6 +353,14 @@ template <typename R>
 void coarse_apply(Ctx& c, const Level& cl, const cx<R>* Dc, cx<R>* out, const cx<R>* in, int nrhs,
                   cx<R>* copy = nullptr);
 void coarse_shift(Ctx& c, Level& cl, double dm);
+// The coarsest-level GCR(k) in FP64 for nrhs right-hand sides (three
+// launches per iteration): x = 0, r = b, iterate until every
+// ||r_q|| <= tol ||b_q|| (lagged test) or maxit.  Work space: L.basisW/Z
+// (k slots), L.w64[1] (r), L.cpart / L.cpart3 (partial sums, sized by the two
+// functions below).
+void coarsest_gcr(Ctx& c, Level& L, cx<double>* x, const cx<double>* b, int nrhs, double tol, int k, int maxit);
+size_t coarsest_gcr_partials(int nrhs, int k);
+size_t coarsest_gcr_partials3(int nrhs);
 // out = D_c in with the blocks stored in 16-bit (one scale per block), FP32
 // vectors; the 16-bit blocks are made from the FP64 ones on first use.
 void coarse_apply_h(Ctx& c, Level& cl, int kind, cx<float>* out, const cx<float>* in, int nrhs,

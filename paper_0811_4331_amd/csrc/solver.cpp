@@ -212,6 +212,10 @@ void ensure_coarsest_basis(Ctx& c, int nrhs) {
   const size_t sz = (size_t)c.mg.coarse_restart * nrhs * L.n * sizeof(cx<double>);
   L.basisZ = static_cast<cx<double>*>(dev_alloc(c, sz));
   L.basisW = static_cast<cx<double>*>(dev_alloc(c, sz));
+  dev_free(c, L.cpart);
+  dev_free(c, L.cpart3);
+  L.cpart = static_cast<double*>(dev_alloc(c, coarsest_gcr_partials(nrhs, c.mg.coarse_restart) * sizeof(double)));
+  L.cpart3 = static_cast<double*>(dev_alloc(c, coarsest_gcr_partials3(nrhs) * sizeof(double)));
   L.capB = nrhs;
 }
 
@@ -245,57 +249,8 @@ void mr(Ctx& c, int l, cx<R>* x, cx<R>* r, cx<R>* p, int nrhs, int iters, double
 // Coarsest solve: GCR(restart) on D_c in FP64 to relative tolerance tol_c,
 // for nrhs right-hand sides together (each with its own coefficients).
 void coarsest_solve(Ctx& c, cx<double>* x, const cx<double>* b, int nrhs) {
-  const int l = c.nlevels - 1;
-  Level& L = c.lev[l];
-  const size_t n = L.n;
-  const int k = c.mg.coarse_restart;
-  cx<double>* r = L.w64[1];
-  cx<double>* Zb = L.basisZ;
-  cx<double>* Wb = L.basisW;
-  const size_t bs = (size_t)nrhs * n;  // one basis slot for all rhs
-  zero<double>(c, x, bs);
-  copy<double>(c, r, b, bs);
-  // |b|^2 per rhs, read once (synchronous)
-  norm2_b(c, r, n, nrhs, l, c.dring);
-  WDMG_HIP(hipStreamSynchronize(c.stream));
-  double tol2[kMaxRhs];
-  bool any = false;
-  for (int q = 0; q < nrhs; ++q) {
-    const double bn2 = c.hring[q];
-    if (!std::isfinite(bn2)) throw Error(WDMG_ERR_NAN, "NaN in the coarsest right-hand side");
-    tol2[q] = c.mg.coarse_tol * c.mg.coarse_tol * bn2;
-    any = any || bn2 > 0.0;
-  }
-  if (!any) return;
-  // The residuals of iteration it land in pinned memory and are inspected
-  // `lag` iterations later, so the stream never drains while the host
-  // waits; up to `lag` extra iterations (which only reduce the residuals
-  // further) are the price.
-  const int lag = 2;
-  int it = 0;
-  auto converged_at = [&](int i) {
-    WDMG_HIP(hipEventSynchronize(c.ring_ev[i % kRing]));
-    const double* rn = c.hring + (size_t)(i % kRing) * kMaxRhs;
-    bool all = true;
-    for (int q = 0; q < nrhs; ++q) {
-      if (!std::isfinite(rn[q])) throw Error(WDMG_ERR_NAN, "NaN in the coarsest solve");
-      all = all && rn[q] <= tol2[q];
-    }
-    return all;
-  };
-  while (it < c.mg.coarse_maxit) {
-    for (int j = 0; j < k && it < c.mg.coarse_maxit; ++j, ++it) {
-      cx<double>* z = Zb + (size_t)j * bs;
-      cx<double>* w = Wb + (size_t)j * bs;
-      coarse_apply<double>(c, L, L.Dc64, w, r, nrhs, z);  // w = D_c r, z = r
-      gcr_orth_b(c, Wb, Zb, w, z, r, n, nrhs, j, l);
-      gcr_step_b(c, w, z, x, r, n, nrhs, l, c.dring + (size_t)(it % kRing) * kMaxRhs);
-      WDMG_HIP(hipEventRecord(c.ring_ev[it % kRing], c.stream));
-      if (it >= lag && converged_at(it - lag)) return;
-    }
-  }
-  for (int i = it - lag < 0 ? 0 : it - lag; i < it; ++i)
-    if (converged_at(i)) return;
+  Level& L = c.lev[c.nlevels - 1];
+  coarsest_gcr(c, L, x, b, nrhs, c.mg.coarse_tol, c.mg.coarse_restart, c.mg.coarse_maxit);
 }
 
 // ---------------------------------------------------------------------------
@@ -642,6 +597,8 @@ void free_hierarchy(Ctx& c) {
     }
     dev_free(c, L.basisZ);
     dev_free(c, L.basisW);
+    dev_free(c, L.cpart);
+    dev_free(c, L.cpart3);
     Level blank;
     if (l == 0) {
       // level 0 work vectors outlive the hierarchy (same geometry)

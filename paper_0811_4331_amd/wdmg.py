@@ -29,7 +29,7 @@ ERRORS = {-1: "WDMG_ERR_ARG", -2: "WDMG_ERR_DIMS", -3: "WDMG_ERR_OOM", -4: "WDMG
 PREC = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
 KERNELS = ["dslash_f64", "dslash_f32", "dc_f64", "dc_f32", "restrict_f64", "restrict_f32",
            "prolong_f64", "prolong_f32", "dc_build", "block_qr", "dc_mfma_f64", "dc_mfma_f32",
-           "dslash_f16", "dslash_bf16", "restrict_h", "prolong_h", "dc_h", "dc_mfma_h"]
+           "dslash_f16", "dslash_bf16", "restrict_h", "prolong_h", "dc_h", "dc_mfma_h", "coarse_gcr"]
 MAX_LEVELS = 4
 
 
@@ -154,11 +154,14 @@ class Context:
         dev_index = self.device.index if self.device.index is not None else 0
         stream = self.stream
 
+        alloc_fn = torch.cuda.caching_allocator_alloc
+        delete_fn = torch.cuda.caching_allocator_delete
+
         def _alloc(nbytes, _user):
-            return torch.cuda.caching_allocator_alloc(int(nbytes), dev_index, stream)
+            return alloc_fn(int(nbytes), dev_index, stream)
 
         def _free(ptr, _user):
-            torch.cuda.caching_allocator_delete(ptr)
+            delete_fn(ptr)
 
         self._alloc_cb = _ALLOC_FN(_alloc)
         self._free_cb = _FREE_FN(_free)
