@@ -72,6 +72,8 @@ def parse():
     ap.add_argument("--alpha", action="store_true",
                     help="take the minimal-residual step size after prolongation (off: alpha = 1, "
                          "which converges in far fewer outer iterations on these fields)")
+    ap.add_argument("--graph", action="store_true",
+                    help="capture the V-cycle in a HIP graph after its first application and replay it")
     ap.add_argument("--big-L", type=int, default=32, help="lattice for the out-of-cache Dslash figure (0: skip)")
     ap.add_argument("--no-bicgstab", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -108,8 +110,27 @@ def dslash_bandwidth(wdmg, synthetic, torch, dev, L, reps=20):
     ctx.set_mass(-1.0)
     psi = torch.from_numpy(synthetic.gaussian_spinor(dims, 5)).to(dev)
     out = {}
-    for prec, key in (("f64", "dslash_f64"), ("f32", "dslash_f32"), ("f16", "dslash_f16"),
-                      ("bf16", "dslash_bf16")):
+    precs = (("f64", "dslash_f64"), ("f32", "dslash_f32"), ("f16", "dslash_f16"), ("bf16", "dslash_bf16"))
+    # both kernel forms forced, then the autotuner's pick
+    forms = {}
+    for form in (0, 1):
+        ctx.set_tuning("dslash", form)
+        for prec, key in precs:
+            x = psi if prec == "f64" else psi.to(torch.complex64)
+            ctx.apply_D(x, prec=prec)
+            torch.cuda.synchronize()
+            ctx.profile(True)
+            for _ in range(reps):
+                ctx.apply_D(x, prec=prec)
+            n, units, ms = ctx.profile_read()[key]
+            ctx.profile(False)
+            sec = ms / 1e3 / n
+            forms[f"{prec}_form{form}"] = {"us_per_launch": sec * 1e6,
+                                           "GB_s": DSLASH_BYTES[prec] * units / n / sec / 1e9}
+    ctx.set_tuning("dslash", None)
+    out["forms"] = {"lattice": f"{L}^4", "form0": "one thread per site", "form1": "one wave per direction",
+                    **forms}
+    for prec, key in precs:
         x = psi if prec == "f64" else psi.to(torch.complex64)
         ctx.apply_D(x, prec=prec)
         torch.cuda.synchronize()
@@ -121,7 +142,8 @@ def dslash_bandwidth(wdmg, synthetic, torch, dev, L, reps=20):
         sec = ms / 1e3 / n
         out[prec] = {"lattice": f"{L}^4", "us_per_launch": sec * 1e6,
                      "GB_s": DSLASH_BYTES[prec] * units / n / sec / 1e9,
-                     "frac_hbm_peak": DSLASH_BYTES[prec] * units / n / sec / 1e9 / HBM_PEAK_GBS}
+                     "frac_hbm_peak": DSLASH_BYTES[prec] * units / n / sec / 1e9 / HBM_PEAK_GBS,
+                     "form": ctx.get_tuning("dslash", prec, 1)}
     # a batch of 8 right-hand sides (links read once per 2 (FP64) or 4 (FP32) rhs)
     xb = psi.unsqueeze(0).repeat(8, 1, 1, 1, 1, 1, 1)
     for prec, key in (("f64", "dslash_f64"), ("f32", "dslash_f32"), ("bf16", "dslash_bf16")):
@@ -228,7 +250,7 @@ def main():
         ctx.mg_setup(levels, coarse_tol=a.coarse_tol, use_alpha=a.alpha)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        x, st = ctx.solve(b, tol=1e-10, restart=50, maxit=2000, mg_prec=a.mg_prec)
+        x, st = ctx.solve(b, tol=1e-10, restart=50, maxit=2000, mg_prec=a.mg_prec, graph=a.graph)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         return x, st, t1 - t0, t2 - t1
@@ -300,7 +322,7 @@ def main():
                    "lattice": list(dims), "eps": a.eps, "m": m, "m_crit": m - a.delta,
                    "m_crit_source": mcrit_src, "nv": a.nv,
                    "nrhs": a.nrhs, "mg_prec": a.mg_prec, "coarse_tol": a.coarse_tol,
-                   "alpha_step": a.alpha},
+                   "alpha_step": a.alpha, "graph": a.graph},
         "setup_s": float(np.median(setups)), "solve_s_per_rhs": float(np.median(solves)) / a.nrhs,
         "mg_iters": [s["iters"] for s in last], "mg_n_D": [s["n_D"] for s in last],
         "mg_n_Dc": [s["n_Dc"][1] for s in last], "true_res": true_res,

@@ -102,6 +102,12 @@ typedef struct {
   int mg_prec;           /* precision of the V-cycle: WDMG_F64, WDMG_F32, or WDMG_F16 /
                             WDMG_BF16 (16-bit fine fields, links, P and intermediate
                             coarse operators; the coarsest solve stays FP64)        */
+  int use_graph;         /* 1: the first V-cycle of a solve runs as usual; it is then
+                            captured once in a HIP graph that later iterations replay.
+                            Inside the graph the coarsest GCR runs a fixed number of
+                            iterations, 1.5x (rounded up, plus one) the count the first
+                            V-cycle needed, at most coarse_maxit; right-hand sides that
+                            reach coarse_tol earlier are frozen on the device.      */
 } wdmg_solve_params;
 
 typedef struct {
@@ -200,6 +206,20 @@ int wdmg_solve(wdmg_ctx* ctx, void* x, const void* b, int nrhs,
  * true-residual criterion.  Same layouts as wdmg_solve. */
 int wdmg_solve_bicgstab(wdmg_ctx* ctx, void* x, const void* b, int nrhs, double tol,
                         int maxit, wdmg_solve_stats* stats);
+
+/* ---- kernel variants and the autotuner ------------------------------------
+ * Some kernels exist in more than one form with the same result (up to the
+ * order of floating-point additions).  With value WDMG_TUNE_AUTO (the
+ * default) the library times the forms on first use for each precision and
+ * batch size (HIP events, a few launches each, on the context's stream) and
+ * keeps the fastest for the context's lifetime; a fixed value forces a form.
+ *   WDMG_TUNE_DSLASH: 0 one thread per site, 1 one wave per direction with
+ *                     the four partial sums added in LDS. */
+enum { WDMG_TUNE_AUTO = -1, WDMG_TUNE_DSLASH = 0, WDMG_TUNE_COUNT };
+int wdmg_set_tuning(wdmg_ctx* ctx, int key, int value);
+/* Current choice for key (WDMG_TUNE_AUTO until tuned) for precision prec
+ * and batch size nrhs. */
+int wdmg_get_tuning(wdmg_ctx* ctx, int key, int prec, int nrhs, int* value);
 
 /* ---- instrumentation (not part of the method) ----------------------------
  * Kernel timing with HIP events recorded on the context's stream around each

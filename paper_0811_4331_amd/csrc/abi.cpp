@@ -254,6 +254,7 @@ void wdmg_default_solve_params(wdmg_solve_params* p) {
   p->maxit = 1000;
   p->precond = 1;
   p->mg_prec = WDMG_F64;
+  p->use_graph = 0;
 }
 
 int wdmg_create(wdmg_ctx** out, const int dims[4], const wdmg_alloc* alloc, void* hip_stream) {
@@ -268,6 +269,8 @@ int wdmg_create(wdmg_ctx** out, const int dims[4], const wdmg_alloc* alloc, void
   wdmg_ctx* c = new (std::nothrow) wdmg_ctx();
   if (!c) return WDMG_ERR_OOM;
   std::memcpy(c->dims, dims, sizeof(c->dims));
+  std::memset(c->tune_dslash, -1, sizeof(c->tune_dslash));
+  for (int k = 0; k < WDMG_TUNE_COUNT; ++k) c->tune_force[k] = WDMG_TUNE_AUTO;
   int B[4];
   for (int mu = 0; mu < 4; ++mu) B[mu] = dims[mu] % 4 == 0 ? 4 : (dims[mu] % 2 == 0 ? 2 : 1);
   c->g0 = make_geom(dims, B);
@@ -313,6 +316,7 @@ void wdmg_destroy(wdmg_ctx* c) {
     else
       (void)hipFree(p);
   }
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->hsc) (void)hipHostFree(c->hsc);
   if (c->hring) (void)hipHostFree(c->hring);
   for (int i = 0; i < kRing; ++i)
@@ -578,6 +582,27 @@ int wdmg_solve_bicgstab(wdmg_ctx* c, void* x, const void* b, int nrhs, double to
       if (rc != WDMG_OK) worst = rc;
     }
     return worst;
+  });
+}
+
+int wdmg_set_tuning(wdmg_ctx* c, int key, int value) {
+  return guarded(c, [&]() {
+    if (key != WDMG_TUNE_DSLASH) throw Error(WDMG_ERR_ARG, "unknown tuning key");
+    if (value != WDMG_TUNE_AUTO && value != 0 && value != 1) throw Error(WDMG_ERR_ARG, "bad tuning value");
+    c->tune_force[key] = value;
+    return WDMG_OK;
+  });
+}
+
+int wdmg_get_tuning(wdmg_ctx* c, int key, int prec, int nrhs, int* value) {
+  return guarded(c, [&]() {
+    need_ptr(value, "value");
+    if (key != WDMG_TUNE_DSLASH) throw Error(WDMG_ERR_ARG, "unknown tuning key");
+    need_prec(prec);
+    need_nrhs(nrhs);
+    *value = c->tune_force[key] >= 0 ? c->tune_force[key]
+                                     : (int)c->tune_dslash[prec][nrhs < kMaxRhs ? nrhs : kMaxRhs];
+    return WDMG_OK;
   });
 }
 

@@ -415,6 +415,38 @@ __device__ __forceinline__ void apply_site_mfma64(const Geom& g, int n2, int nrh
   __syncthreads();
 }
 
+// One right-hand side on the vector units: wave d (of nine) applies block d
+// of site s with lane = row; the nine partial rows are added in order.
+// Needs blockDim.x >= 576; ends with a block barrier.
+__device__ __forceinline__ void apply_site_valu1(const Geom& g, int n2, int s, const cx<double>* __restrict__ Dc,
+                                                 const cx<double>* in, cx<double>* out, double* lds) {
+  const int d = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  cx<double> acc = mk(0.0, 0.0);
+  if (d < 9 && lane < n2) {
+    int nb = s;
+    if (d < 8) {
+      int c[4];
+      coords_of(g, s, c);
+      nb = (d & 1) ? nbr_bwd(g, s, c, d >> 1) : nbr_fwd(g, s, c, d >> 1);
+    }
+    const cx<double>* blk = Dc + ((size_t)s * 9 + d) * n2 * n2 + lane;
+    const cx<double>* v = in + (size_t)nb * n2;
+    for (int jj = 0; jj < n2; ++jj) cmadd(acc, blk[(size_t)jj * n2], v[jj]);
+  }
+  if (d < 9) {
+    lds[2 * (d * 64 + lane)] = acc.re;
+    lds[2 * (d * 64 + lane) + 1] = acc.im;
+  }
+  __syncthreads();
+  if (d == 0 && lane < n2) {
+    cx<double> t = mk(lds[2 * (8 * 64 + lane)], lds[2 * (8 * 64 + lane) + 1]);
+#pragma unroll
+    for (int dd = 0; dd < 8; ++dd) t = t + mk(lds[2 * (dd * 64 + lane)], lds[2 * (dd * 64 + lane) + 1]);
+    out[(size_t)s * n2 + lane] = t;
+  }
+  __syncthreads();
+}
+
 // copy = in on site s for the right-hand sides [q0, q0 + nq) (all threads of the block)
 template <typename R>
 __device__ __forceinline__ void copy_site(int n2, size_t fs, int s, int q0, int nq, const cx<R>* in, cx<R>* copy) {
@@ -728,6 +760,7 @@ __global__ __launch_bounds__(256) void k_cgcr_init(const cx<double>* __restrict_
 }
 
 // K1: blocks (G1, rhs tiles of 16), one wave per 16 real rows of a site.
+template <bool VALU>
 __global__ __launch_bounds__(1024) void k_cgcr_apply(Geom g, int n2, int nrhs, int j, int vals,
                                                     const cx<double>* __restrict__ Dc, const cx<double>* r,
                                                     const cx<double>* Wb, cx<double>* w, cx<double>* z,
@@ -741,7 +774,11 @@ __global__ __launch_bounds__(1024) void k_cgcr_apply(Geom g, int n2, int nrhs, i
   for (int t = threadIdx.x; t < 16 * vals; t += blockDim.x) acc[t] = 0.0;
   for (int s = blockIdx.x; s < g.vol; s += gridDim.x) {
     copy_site(n2, fs, s, q0, nq, r, z);
-    apply_site_mfma64(g, n2, nrhs, s, q0, Dc, r, w, lds);  // ends with a block barrier: w_j of s complete
+    // both end with a block barrier: w_j of site s is then complete
+    if (VALU)
+      apply_site_valu1(g, n2, s, Dc, r, w, lds);
+    else
+      apply_site_mfma64(g, n2, nrhs, s, q0, Dc, r, w, lds);
     for (int qq = wave; qq < nq; qq += nw) {
       const size_t o = (size_t)(q0 + qq) * fs + (size_t)s * n2 + lane;
       cx<double> wv = mk(0.0, 0.0), rv = mk(0.0, 0.0);
@@ -990,7 +1027,9 @@ void coarsest_gcr(Ctx& c, Level& L, cx<double>* x, const cx<double>* b, int nrhs
   const int ntile = (nrhs + 15) / 16, waves = mfma64_row_tiles(n2) * mfma64_groups(n2);
   static bool lds_attr = false;
   if (!lds_attr) {  // K1 keeps 16 x (4 k + 4) partial sums in LDS (k <= 128)
-    WDMG_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cgcr_apply),
+    WDMG_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cgcr_apply<false>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, 16 * (4 * kMaxKrylov + 4) * 8));
+    WDMG_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cgcr_apply<true>),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, 16 * (4 * kMaxKrylov + 4) * 8));
     lds_attr = true;
   }
@@ -1007,28 +1046,38 @@ void coarsest_gcr(Ctx& c, Level& L, cx<double>* x, const cx<double>* b, int nrhs
       if (f[q] != 0.0) return false;
     return true;
   };
+  const int fixed = c.capturing ? (c.coarse_fixed_iters < maxit ? c.coarse_fixed_iters : maxit) : 0;
   int it = 0;
-  for (; it < maxit; ++it) {
+  for (; it < (c.capturing ? fixed : maxit); ++it) {
     const int j = it % k;
     cx<double>* w = L.basisW + (size_t)j * bs;
     cx<double>* z = L.basisZ + (size_t)j * bs;
     const int vals = 4 * j + 4;
     {
       ProfScope ps(c, WDMG_K_COARSE_GCR, (long long)L.nsite * nrhs);
-      hipLaunchKernelGGL(k_cgcr_apply, dim3(g1, ntile), dim3(64 * waves), (size_t)16 * vals * sizeof(double),
-                         c.stream, L.g, n2, nrhs, j, vals, L.Dc64, r, L.basisW, w, z, L.cpart);
+      if (nrhs == 1)
+        hipLaunchKernelGGL(k_cgcr_apply<true>, dim3(g1, 1), dim3(576), (size_t)16 * vals * sizeof(double), c.stream,
+                           L.g, n2, nrhs, j, vals, L.Dc64, r, L.basisW, w, z, L.cpart);
+      else
+        hipLaunchKernelGGL(k_cgcr_apply<false>, dim3(g1, ntile), dim3(64 * waves), (size_t)16 * vals * sizeof(double),
+                           c.stream, L.g, n2, nrhs, j, vals, L.Dc64, r, L.basisW, w, z, L.cpart);
       WDMG_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(k_cgcr_coef, dim3(nrhs), dim3(256), (size_t)(vals + 1) * sizeof(double), c.stream, j, vals,
-                       g1, L.cpart, L.cpart3, k, S, c.dring + (size_t)(it % kRing) * kMaxRhs, c.dsc + S_ERR);
+                       g1, L.cpart, L.cpart3, k, S, c.capturing ? nullptr : c.dring + (size_t)(it % kRing) * kMaxRhs,
+                       c.dsc + S_ERR);
     WDMG_HIP(hipGetLastError());
-    WDMG_HIP(hipEventRecord(c.ring_ev[it % kRing], c.stream));
+    if (!c.capturing) WDMG_HIP(hipEventRecord(c.ring_ev[it % kRing], c.stream));
     hipLaunchKernelGGL(k_cgcr_update, dim3(kCgcrG3, nrhs), dim3(256), 0, c.stream, n, nrhs, j, k, L.basisW,
                        L.basisZ, w, z, x, r, S, L.cpart3);
     WDMG_HIP(hipGetLastError());
     c.n_Dc[L.l] += nrhs;
-    if (it >= lag && done_at(it - lag)) break;
+    if (!c.capturing && it >= lag && done_at(it - lag)) {
+      ++it;
+      break;
+    }
   }
+  if (it > c.last_coarse_iters) c.last_coarse_iters = it;
 }
 
 size_t coarsest_gcr_partials(int nrhs, int k) {

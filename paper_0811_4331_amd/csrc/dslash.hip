@@ -158,16 +158,112 @@ __global__ __launch_bounds__(kDslashThreads) void k_dslash(Geom g, IO io, R diag
   io.store(s, acc);
 }
 
+// Direction-split form: a workgroup of four waves covers one 64-site block;
+// wave mu computes the two hops along mu (forward and backward) for the 64
+// sites, the partial sums meet in LDS, and wave 0 adds them in direction
+// order, applies the mass term and stores.  Four times as many waves as the
+// one-thread-per-site kernel, each with a quarter of the hops and of the
+// registers, so loads of many more sites are in flight.
+template <int MU, class IO, typename R>
+__device__ __forceinline__ void hops_mu(const IO& io, const Geom& g, int s, const int (&c)[4], bool tneg,
+                                        cx<R> (&acc)[12]) {
+  const bool last = MU == 3 && tneg && c[3] == g.L[3] - 1, first = MU == 3 && tneg && c[3] == 0;
+  const int f = nbr_fwd(g, s, c, MU), b = nbr_bwd(g, s, c, MU);
+  hop<MU, +1>(io, f, s, last, acc);
+  hop<MU, -1>(io, b, b, first, acc);
+}
+
+constexpr int kDs4Sites = 64;
+
+template <class IO, typename R = typename IO::T>
+__global__ __launch_bounds__(256) void k_dslash4(Geom g, IO io, R diag, int tneg, int nsb, int nrhs) {
+  __shared__ cx<R> part[3][12][kDs4Sites];
+  int sb, rhs;
+  batch_block(nsb, nrhs, sb, rhs);
+  const int lane = threadIdx.x & 63, mu = threadIdx.x >> 6;
+  const int s = sb * kDs4Sites + lane;
+  io.select_rhs(rhs, g.vpad);
+  cx<R> acc[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[k] = mk<R>(0, 0);
+  const bool live = s < g.vol;
+  if (live) {
+    int c[4];
+    coords_of(g, s, c);
+    switch (mu) {
+      case 0: hops_mu<0>(io, g, s, c, tneg, acc); break;
+      case 1: hops_mu<1>(io, g, s, c, tneg, acc); break;
+      case 2: hops_mu<2>(io, g, s, c, tneg, acc); break;
+      default: hops_mu<3>(io, g, s, c, tneg, acc); break;
+    }
+  }
+  if (mu > 0) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) part[mu - 1][k][lane] = acc[k];
+  }
+  __syncthreads();
+  if (mu != 0 || s >= g.vpad) return;
+  if (!live) {
+    io.store(s, acc);  // padding site: zeros
+    return;
+  }
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[k] = acc[k] + part[0][k][lane] + part[1][k][lane] + part[2][k][lane];
+  const R half = (R)0.5;
+  cx<R> p[12];
+  io.spinor(s, p);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[k] = mk<R>(diag * p[k].re - half * acc[k].re, diag * p[k].im - half * acc[k].im);
+  io.store(s, acc);
+}
+
 template <class IO>
-void launch_dslash(Ctx& c, const IO& io, int nrhs, int prof_id) {
+void run_dslash(Ctx& c, const IO& io, int nrhs, int variant) {
   const Geom& g = c.g0;
-  const unsigned gx = g.vpad / kDslashThreads + (g.vpad % kDslashThreads != 0);
-  ProfScope ps(c, prof_id, (long long)g.vol * nrhs);
   const int tneg = c.t_bc < 0 ? 1 : 0;
   using R = typename IO::T;
-  hipLaunchKernelGGL((k_dslash<IO>), dim3(gx * nrhs), dim3(kDslashThreads), 0, c.stream, g, io, (R)(4.0 + c.mass),
-                     tneg, (int)gx, nrhs);
+  if (variant == 1) {
+    const unsigned gx = g.vpad / kDs4Sites;
+    hipLaunchKernelGGL((k_dslash4<IO>), dim3(gx * nrhs), dim3(256), 0, c.stream, g, io, (R)(4.0 + c.mass), tneg,
+                       (int)gx, nrhs);
+  } else {
+    const unsigned gx = g.vpad / kDslashThreads + (g.vpad % kDslashThreads != 0);
+    hipLaunchKernelGGL((k_dslash<IO>), dim3(gx * nrhs), dim3(kDslashThreads), 0, c.stream, g, io,
+                       (R)(4.0 + c.mass), tneg, (int)gx, nrhs);
+  }
   WDMG_HIP(hipGetLastError());
+}
+
+// Autotuner: times both forms (HIP events, 3 launches each after one warm-up
+// launch) on the caller's buffers -- the operator has no side effects
+// besides writing `out` -- and returns the faster.
+template <class IO>
+int tune_dslash(Ctx& c, const IO& io, int nrhs) {
+  hipEvent_t ev[3];
+  for (auto& e : ev) WDMG_HIP(hipEventCreate(&e));
+  float ms[2] = {0.f, 0.f};
+  for (int v = 0; v < 2; ++v) {
+    run_dslash(c, io, nrhs, v);
+    WDMG_HIP(hipEventRecord(ev[0], c.stream));
+    for (int i = 0; i < 3; ++i) run_dslash(c, io, nrhs, v);
+    WDMG_HIP(hipEventRecord(ev[1], c.stream));
+    WDMG_HIP(hipEventSynchronize(ev[1]));
+    WDMG_HIP(hipEventElapsedTime(&ms[v], ev[0], ev[1]));
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  return ms[1] <= ms[0] ? 1 : 0;
+}
+
+template <class IO>
+void launch_dslash(Ctx& c, const IO& io, int nrhs, int prof_id, int prec_index) {
+  int v = c.tune_force[WDMG_TUNE_DSLASH];
+  if (v < 0) {
+    signed char& slot = c.tune_dslash[prec_index][nrhs < kMaxRhs ? nrhs : kMaxRhs];
+    if (slot < 0 && !c.capturing) slot = (signed char)tune_dslash(c, io, nrhs);
+    v = slot < 0 ? 1 : slot;
+  }
+  ProfScope ps(c, prof_id, (long long)c.g0.vol * nrhs);
+  run_dslash(c, io, nrhs, v);
   c.n_D += nrhs;
 }
 
@@ -182,7 +278,8 @@ void dslash(Ctx& c, cx<R>* out, const cx<R>* in, int nrhs) {
     io.U = c.U64;
   else
     io.U = c.U32;
-  launch_dslash(c, io, nrhs, sizeof(R) == 8 ? WDMG_K_DSLASH_F64 : WDMG_K_DSLASH_F32);
+  launch_dslash(c, io, nrhs, sizeof(R) == 8 ? WDMG_K_DSLASH_F64 : WDMG_K_DSLASH_F32,
+                sizeof(R) == 8 ? WDMG_F64 : WDMG_F32);
 }
 
 template <typename H>
@@ -193,7 +290,7 @@ void dslash_h(Ctx& c, HF out, HF in, int nrhs) {
   io.out = static_cast<cxh<H>*>(out.v);
   io.osc = out.s;
   io.U = static_cast<const cxh<H>*>(u16(c, half_kind<H>()));
-  launch_dslash(c, io, nrhs, sizeof(H) == 2 && half_kind<H>() == WDMG_F16 ? WDMG_K_DSLASH_F16 : WDMG_K_DSLASH_BF16);
+  launch_dslash(c, io, nrhs, half_kind<H>() == WDMG_F16 ? WDMG_K_DSLASH_F16 : WDMG_K_DSLASH_BF16, half_kind<H>());
 }
 
 template void dslash<double>(Ctx&, cx<double>*, const cx<double>*, int);

@@ -151,6 +151,18 @@ struct Ctx {
   void* U16 = nullptr;          // 16-bit links, made on first use
   int u16_kind = 0;             // WDMG_F16 / WDMG_BF16 (0: none)
   int vc_half = 0;              // 16-bit kind of the running V-cycle (0: none)
+  // kernel variants: forced choice per tuning key (-1: autotune) and the
+  // autotuner's choices per (precision, batch size)
+  int tune_force[WDMG_TUNE_COUNT] = {-1};
+  signed char tune_dslash[4][kMaxRhs + 1];
+  // HIP-graph capture of a V-cycle: while capturing, the coarsest GCR runs
+  // exactly coarse_fixed_iters iterations with no host interaction
+  bool capturing = false;
+  int coarse_fixed_iters = 0;
+  int last_coarse_iters = 0;    // most iterations of one coarsest solve since reset
+  hipStream_t cap_stream = nullptr;
+  cx<double>* outer_zf = nullptr;  // fixed output of a captured V-cycle
+  int outer_zf_cap = 0;
 
 
   double* dsc = nullptr;        // device scalars (S_TOTAL doubles)

@@ -398,10 +398,53 @@ int fgcr(Ctx& c, cx<double>* x, const cx<double>* b, int nrhs, const wdmg_solve_
   if (p.precond) ensure_mg_work(c, nrhs, f32 || half ? WDMG_F32 : WDMG_F64);
   if (half) ensure_work_h(c, nrhs);
   HalfScope hs(c, half ? p.mg_prec : 0);
+  const bool graph = p.precond && p.use_graph;
+  if (graph) {
+    if (!c.cap_stream) WDMG_HIP(hipStreamCreateWithFlags(&c.cap_stream, hipStreamNonBlocking));
+    if (nrhs > c.outer_zf_cap) {
+      WDMG_HIP(hipStreamSynchronize(c.stream));
+      dev_free(c, c.outer_zf);
+      c.outer_zf = static_cast<cx<double>*>(dev_alloc(c, (size_t)nrhs * n * sizeof(cx<double>)));
+      c.outer_zf_cap = nrhs;
+    }
+  }
+  struct GraphHolder {
+    hipStream_t s;
+    hipGraphExec_t e = nullptr;
+    ~GraphHolder() {
+      if (e) {
+        (void)hipStreamSynchronize(s);
+        (void)hipGraphExecDestroy(e);
+      }
+    }
+  } gh{c.stream};
+  hipGraphExec_t& gexec = gh.e;
+  long long g_nd = 0, g_ndc[WDMG_MAX_LEVELS] = {0, 0, 0, 0};
   cx<double>* r = c.outer_r;
   cx<double>* Zb = c.outer_Z;
   cx<double>* Wb = c.outer_W;
   const int G = 4;  // scalar block of the outer solve
+  // preconditioner application z = M r (Sec. 2 V-cycle) in the chosen precision
+  auto apply_M = [&](cx<double>* zdst) {
+    if (half) {
+      Level& L0 = c.lev[0];
+      if (p.mg_prec == WDMG_F16) {
+        to_half<double, f16_t>(c, r, L0.wh[4], nrhs);
+        vcycle_h<f16_t>(c, L0.wh[5], L0.wh[4], nrhs);
+        from_half<f16_t, double>(c, L0.wh[5], zdst, nrhs);
+      } else {
+        to_half<double, bf16_t>(c, r, L0.wh[4], nrhs);
+        vcycle_h<bf16_t>(c, L0.wh[5], L0.wh[4], nrhs);
+        from_half<bf16_t, double>(c, L0.wh[5], zdst, nrhs);
+      }
+    } else if (f32) {
+      convert<float, double>(c, c.outer_r32, r, bs);
+      vcycle<float>(c, 0, c.outer_z32, c.outer_r32, nrhs);
+      convert<double, float>(c, zdst, c.outer_z32, bs);
+    } else {
+      vcycle<double>(c, 0, zdst, r, nrhs);
+    }
+  };
   set_scalar(c, S_ERR, 0.0, 0.0);
   norm2_b(c, b, n, nrhs, G, c.dring);
   WDMG_HIP(hipStreamSynchronize(c.stream));
@@ -445,23 +488,55 @@ int fgcr(Ctx& c, cx<double>* x, const cx<double>* b, int nrhs, const wdmg_solve_
       cx<double>* z = Zb + (size_t)j * bs;
       cx<double>* w = Wb + (size_t)j * bs;
       if (p.precond) {
-        if (half) {
-          Level& L0 = c.lev[0];
-          if (p.mg_prec == WDMG_F16) {
-            to_half<double, f16_t>(c, r, L0.wh[4], nrhs);
-            vcycle_h<f16_t>(c, L0.wh[5], L0.wh[4], nrhs);
-            from_half<f16_t, double>(c, L0.wh[5], z, nrhs);
-          } else {
-            to_half<double, bf16_t>(c, r, L0.wh[4], nrhs);
-            vcycle_h<bf16_t>(c, L0.wh[5], L0.wh[4], nrhs);
-            from_half<bf16_t, double>(c, L0.wh[5], z, nrhs);
+        if (!graph) {
+          apply_M(z);
+        } else if (!gexec) {
+          // first application: eager; it also measures the coarsest iterations
+          c.last_coarse_iters = 0;
+          apply_M(c.outer_zf);
+          copy<double>(c, z, c.outer_zf, bs);
+          const int fixed = (3 * c.last_coarse_iters + 1) / 2 + 1;
+          // capture the V-cycle on a side stream, then replay it on c.stream
+          hipStream_t main_stream = c.stream;
+          const bool prof = c.prof_on;
+          c.prof_on = false;
+          c.capturing = true;
+          c.coarse_fixed_iters = fixed;
+          c.stream = c.cap_stream;
+          const long long nd1 = c.n_D;
+          long long ndc1[WDMG_MAX_LEVELS];
+          for (int l = 0; l < WDMG_MAX_LEVELS; ++l) ndc1[l] = c.n_Dc[l];
+          hipGraph_t graph_def = nullptr;
+          hipError_t e = hipStreamBeginCapture(c.cap_stream, hipStreamCaptureModeRelaxed);
+          if (e == hipSuccess) {
+            try {
+              apply_M(c.outer_zf);
+            } catch (...) {
+              (void)hipStreamEndCapture(c.cap_stream, &graph_def);
+              if (graph_def) (void)hipGraphDestroy(graph_def);
+              c.stream = main_stream;
+              c.capturing = false;
+              c.prof_on = prof;
+              throw;
+            }
+            e = hipStreamEndCapture(c.cap_stream, &graph_def);
           }
-        } else if (f32) {
-          convert<float, double>(c, c.outer_r32, r, bs);
-          vcycle<float>(c, 0, c.outer_z32, c.outer_r32, nrhs);
-          convert<double, float>(c, z, c.outer_z32, bs);
+          c.stream = main_stream;
+          c.capturing = false;
+          c.prof_on = prof;
+          if (e == hipSuccess) e = hipGraphInstantiate(&gexec, graph_def, nullptr, nullptr, 0);
+          if (graph_def) (void)hipGraphDestroy(graph_def);
+          WDMG_HIP(e);
+          g_nd = c.n_D - nd1;
+          for (int l = 0; l < WDMG_MAX_LEVELS; ++l) g_ndc[l] = c.n_Dc[l] - ndc1[l];
+          // the capture itself executed nothing
+          c.n_D = nd1;
+          for (int l = 0; l < WDMG_MAX_LEVELS; ++l) c.n_Dc[l] = ndc1[l];
         } else {
-          vcycle<double>(c, 0, z, r, nrhs);
+          WDMG_HIP(hipGraphLaunch(gexec, c.stream));
+          c.n_D += g_nd;
+          for (int l = 0; l < WDMG_MAX_LEVELS; ++l) c.n_Dc[l] += g_ndc[l];
+          copy<double>(c, z, c.outer_zf, bs);
         }
       } else {
         copy<double>(c, z, r, bs);

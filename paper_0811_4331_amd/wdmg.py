@@ -55,7 +55,7 @@ class MgParams(ctypes.Structure):
 
 class SolveParams(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("maxit", ctypes.c_int),
-                ("precond", ctypes.c_int), ("mg_prec", ctypes.c_int)]
+                ("precond", ctypes.c_int), ("mg_prec", ctypes.c_int), ("use_graph", ctypes.c_int)]
 
 
 class SolveStats(ctypes.Structure):
@@ -114,6 +114,8 @@ def load() -> ctypes.CDLL:
         "wdmg_solve": (ip, [vp, vp, vp, ip, ctypes.POINTER(SolveParams), ctypes.POINTER(SolveStats)]),
         "wdmg_solve_bicgstab": (ip, [vp, vp, vp, ip, dp, ip, ctypes.POINTER(SolveStats)]),
         "wdmg_profile": (ip, [vp, ip]),
+        "wdmg_set_tuning": (ip, [vp, ip, ip]),
+        "wdmg_get_tuning": (ip, [vp, ip, ip, ip, ctypes.POINTER(ctypes.c_int)]),
         "wdmg_profile_read": (ip, [vp, ip, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong),
                                    ctypes.POINTER(ctypes.c_double)]),
     }
@@ -311,15 +313,27 @@ class Context:
         return x
 
     def solve(self, b: torch.Tensor, x0: torch.Tensor | None = None, *, tol=1e-10, restart=50,
-              maxit=1000, precond=True, mg_prec="f64"):
+              maxit=1000, precond=True, mg_prec="f64", graph=False):
         nrhs = self._nrhs(b, 6)
         x = torch.zeros_like(b) if x0 is None else x0.clone()
-        p = SolveParams(float(tol), int(restart), int(maxit), 1 if precond else 0, PREC[mg_prec])
+        p = SolveParams(float(tol), int(restart), int(maxit), 1 if precond else 0, PREC[mg_prec],
+                        1 if graph else 0)
         stats = (SolveStats * nrhs)()
         rc = self.lib.wdmg_solve(self.h, _ptr(x, torch.complex128, "x"), _ptr(b, torch.complex128, "b"),
                                  nrhs, ctypes.byref(p), stats)
         self._check(rc, allow_not_converged=True)
         return x, [s.as_dict() for s in stats]
+
+    TUNE = {"dslash": 0}
+
+    def set_tuning(self, key: str, value: int | None):
+        """Force a kernel form (0, 1, ...) or let the autotuner pick (None)."""
+        self._check(self.lib.wdmg_set_tuning(self.h, self.TUNE[key], -1 if value is None else int(value)))
+
+    def get_tuning(self, key: str, prec: str = "f64", nrhs: int = 1):
+        v = ctypes.c_int()
+        self._check(self.lib.wdmg_get_tuning(self.h, self.TUNE[key], PREC[prec], int(nrhs), ctypes.byref(v)))
+        return None if v.value < 0 else v.value
 
     def profile(self, enable: bool):
         """Start (clearing earlier records) or stop HIP-event timing of the main kernels."""

@@ -303,3 +303,48 @@ def test_batched_coarse_operator_on_matrix_cores(nv, nrhs):
     out32 = ctx.apply_Dc(1, gpu(c.astype(np.complex64)), prec="f32").cpu().numpy()
     for j in range(nrhs):
         assert rel(out32[j].astype(np.complex128), ref[j]) < 1e-5, j
+
+
+@pytest.mark.parametrize("prec,nrhs", [("f64", 1), ("f32", 3), ("bf16", 4)])
+def test_solve_with_graph_captured_vcycle(prec, nrhs):
+    """The V-cycle captured once in a HIP graph and replayed for every later
+    outer iteration: each replay must act as the eager V-cycle, so the solve
+    reaches the same true residual with a similar iteration count."""
+    dims = (8, 8, 8, 8)
+    seed = synthetic.gauge_seed(1, 1)
+    m = MCRIT[f"8x8x8x8_eps0.3_seed{seed}"]["m_crit"] + 0.05
+    ctx, u = make_ctx(dims, 0.3, seed, m)
+    nv = 12
+    v0 = synthetic.gaussian_vectors((nv,) + ctx.fine_shape(), synthetic.null_seed(1))
+    ctx.mg_setup([{"block": (4, 4, 4, 4), "nv": nv, "setup_iters": 50, "vectors": gpu(v0)}], coarse_tol=1e-1)
+    b = synthetic.gaussian_spinor(dims, seed=synthetic.rhs_seed(1), nrhs=nrhs)
+    bb = gpu(b if nrhs > 1 else b[0])
+    xe, se = ctx.solve(bb, tol=1e-10, restart=20, maxit=300, mg_prec=prec)
+    for rep in range(2):  # two solves: two captures, many replays each
+        xg, sg = ctx.solve(bb, tol=1e-10, restart=20, maxit=300, mg_prec=prec, graph=True)
+        xgh = xg.cpu().numpy().reshape((nrhs,) + b.shape[1:])
+        for j in range(nrhs):
+            res = resid(b[j], wilson.apply_D(u, xgh[j], m))
+            assert sg[j]["converged"] and res <= 1e-10, (rep, j, res, sg[j])
+            assert sg[j]["iters"] <= se[j]["iters"] + 3, (sg[j]["iters"], se[j]["iters"])
+
+
+@pytest.mark.parametrize("form", [0, 1])
+@pytest.mark.parametrize("dims,nrhs", [((8, 8, 8, 8), 1), ((6, 4, 2, 10), 3), ((2, 2, 2, 2), 2)])
+def test_both_dslash_forms_match_oracle(form, dims, nrhs):
+    """The one-thread-per-site and the one-wave-per-direction Wilson kernels
+    (the autotuner's candidates) each agree with the oracle."""
+    m = -0.41
+    ctx, u = make_ctx(dims, 0.35, 400 + sum(dims), m)
+    ctx.set_tuning("dslash", form)
+    psi = synthetic.gaussian_spinor(dims, seed=17, nrhs=nrhs)
+    ref = wilson.apply_D(u, psi, m, -1.0)
+    out = ctx.apply_D(gpu(psi)).cpu().numpy()
+    out32 = ctx.apply_D(gpu(psi.astype(np.complex64)), prec="f32").cpu().numpy()
+    for j in range(nrhs):
+        assert rel(out[j], ref[j]) < 1e-13
+        assert rel(out32[j].astype(np.complex128), ref[j]) < 1e-6
+    assert ctx.get_tuning("dslash", "f64", nrhs) == form
+    ctx.set_tuning("dslash", None)
+    ctx.apply_D(gpu(psi))  # autotuned
+    assert ctx.get_tuning("dslash", "f64", nrhs) in (0, 1)
