@@ -67,6 +67,8 @@ def parse():
     ap.add_argument("--nv", type=int, default=20)
     ap.add_argument("--setup-iters", type=int, default=100)
     ap.add_argument("--nrhs", type=int, default=1)
+    ap.add_argument("--setup-prec", default="f64", choices=["f64", "f32"],
+                    help="arithmetic of the setup relaxation (the block QR is FP64 either way)")
     ap.add_argument("--mg-prec", default="f64", choices=["f64", "f32", "f16", "bf16"])
     ap.add_argument("--coarse-tol", type=float, default=0.1)
     ap.add_argument("--alpha", action="store_true",
@@ -243,7 +245,8 @@ def main():
     v0 = torch.from_numpy(synthetic.gaussian_vectors((a.nv,) + ctx.fine_shape(), synthetic.null_seed(cfg))).to(dev)
     bh = np.stack([synthetic.gaussian_spinor(dims, synthetic.rhs_seed(cfg, j)) for j in range(a.nrhs)])
     b = torch.from_numpy(bh).to(dev)
-    levels = [{"block": (4, 4, 4, 4), "nv": a.nv, "setup_iters": a.setup_iters, "vectors": v0}]
+    levels = [{"block": (4, 4, 4, 4), "nv": a.nv, "setup_iters": a.setup_iters, "vectors": v0,
+               "setup_prec": a.setup_prec}]
 
     def step():
         t0 = time.perf_counter()
@@ -321,7 +324,7 @@ def main():
                                f"FGCR(50) to 1e-10, {a.nrhs} Gaussian RHS",
                    "lattice": list(dims), "eps": a.eps, "m": m, "m_crit": m - a.delta,
                    "m_crit_source": mcrit_src, "nv": a.nv,
-                   "nrhs": a.nrhs, "mg_prec": a.mg_prec, "coarse_tol": a.coarse_tol,
+                   "nrhs": a.nrhs, "mg_prec": a.mg_prec, "setup_prec": a.setup_prec, "coarse_tol": a.coarse_tol,
                    "alpha_step": a.alpha, "graph": a.graph},
         "setup_s": float(np.median(setups)), "solve_s_per_rhs": float(np.median(solves)) / a.nrhs,
         "mg_iters": [s["iters"] for s in last], "mg_n_D": [s["n_D"] for s in last],

@@ -79,6 +79,8 @@ typedef struct {
   int setup_iters;       /* MR relaxation steps on D v = 0 (0: take the vectors as given) */
   const void* vectors;   /* device: nv starting vectors, canonical complex128 layout of
                             level l ([nv][sites][dof]); required */
+  int setup_prec;        /* arithmetic of the relaxation: WDMG_F64 or WDMG_F32 (the
+                            block orthonormalisation is FP64 either way)            */
 } wdmg_level_params;
 
 typedef struct {

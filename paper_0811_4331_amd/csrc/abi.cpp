@@ -236,6 +236,7 @@ void wdmg_default_mg_params(wdmg_mg_params* p) {
     p->level[l].nv = 20;
     p->level[l].setup_iters = 100;
     p->level[l].vectors = nullptr;
+    p->level[l].setup_prec = WDMG_F64;
   }
   p->omega = 0.8;
   p->nu_pre = 2;

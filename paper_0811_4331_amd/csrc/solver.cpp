@@ -703,28 +703,47 @@ void init_level0(Ctx& c) {
   L.n = (size_t)c.g0.vpad * 12;
 }
 
-static void relax(Ctx& c, int l, const wdmg_level_params& lp, double omega) {
+// Sec. 2 setup relaxation: setup_iters MR steps on A v = 0 for all Nv
+// vectors at once (each its own step size), in precision R, in place on X.
+// The batch is cut only when the work fields would exceed a 16 GB budget.
+template <typename R>
+static void relax_batch(Ctx& c, int l, cx<R>* V, int nv, int iters, double omega) {
   Level& F = c.lev[l];
   const size_t n = F.n;
-  const int nv = lp.nv;
-  const int kb = nv < 8 ? nv : 8;
-  cx<double>* R = static_cast<cx<double>*>(dev_alloc(c, (size_t)kb * n * sizeof(cx<double>)));
-  cx<double>* P = static_cast<cx<double>*>(dev_alloc(c, (size_t)kb * n * sizeof(cx<double>)));
-  for (int k0 = 0; k0 < nv; k0 += kb) {
-    const int nb = (nv - k0) < kb ? (nv - k0) : kb;
-    cx<double>* X = F.V64 + (size_t)k0 * n;
+  const size_t field = n * sizeof(cx<R>);
+  size_t kb = ((size_t)16 << 30) / (2 * field);
+  if (kb < 1) kb = 1;
+  if (kb > (size_t)nv) kb = nv;
+  if (kb > (size_t)kMaxRhs) kb = kMaxRhs;
+  cx<R>* Rb = static_cast<cx<R>*>(dev_alloc(c, kb * field));
+  cx<R>* Pb = static_cast<cx<R>*>(dev_alloc(c, kb * field));
+  for (int k0 = 0; k0 < nv; k0 += (int)kb) {
+    const int nb = (nv - k0) < (int)kb ? (nv - k0) : (int)kb;
+    cx<R>* X = V + (size_t)k0 * n;
     // r = 0 - A x
-    apply_op<double>(c, l, R, X, nb);
-    for (int q = 0; q < nb; ++q) neg<double>(c, R + (size_t)q * n, n);
-    for (int it = 0; it < lp.setup_iters; ++it) {
-      apply_op<double>(c, l, P, R, nb);
-      step_alpha_batch<double>(c, P, R, n, n, nb, omega, S_BATCH);
-      update2_batch<double>(c, X, R, R, P, n, n, nb, S_BATCH);
+    apply_op<R>(c, l, Rb, X, nb);
+    neg<R>(c, Rb, (size_t)nb * n);
+    for (int it = 0; it < iters; ++it) {
+      apply_op<R>(c, l, Pb, Rb, nb);
+      step_alpha_batch<R>(c, Pb, Rb, n, n, nb, omega, S_BATCH);
+      update2_batch<R>(c, X, Rb, Rb, Pb, n, n, nb, S_BATCH);
     }
   }
   WDMG_HIP(hipStreamSynchronize(c.stream));
-  dev_free(c, R);
-  dev_free(c, P);
+  dev_free(c, Rb);
+  dev_free(c, Pb);
+}
+
+static void relax(Ctx& c, int l, const wdmg_level_params& lp, double omega) {
+  Level& F = c.lev[l];
+  if (lp.setup_prec == WDMG_F32) {
+    const size_t nn = (size_t)lp.nv * F.n;
+    convert<float, double>(c, F.V32, F.V64, nn);
+    relax_batch<float>(c, l, F.V32, lp.nv, lp.setup_iters, omega);
+    convert<double, float>(c, F.V64, F.V32, nn);
+  } else {
+    relax_batch<double>(c, l, F.V64, lp.nv, lp.setup_iters, omega);
+  }
 }
 
 void mg_setup(Ctx& c, const wdmg_mg_params& p) {
@@ -742,6 +761,8 @@ void mg_setup(Ctx& c, const wdmg_mg_params& p) {
     const wdmg_level_params& lp = p.level[l];
     if (lp.nv < 1 || lp.nv > 32) throw Error(WDMG_ERR_ARG, "nv must be in 1..32");
     if (lp.setup_iters < 0) throw Error(WDMG_ERR_ARG, "setup_iters must be >= 0");
+    if (lp.setup_prec != WDMG_F64 && lp.setup_prec != WDMG_F32)
+      throw Error(WDMG_ERR_ARG, "setup_prec must be WDMG_F64 or WDMG_F32");
     if (!lp.vectors) throw Error(WDMG_ERR_ARG, "starting vectors are required for every level");
     int bvol = 1;
     for (int mu = 0; mu < 4; ++mu) {
