@@ -74,6 +74,9 @@ def parse():
     ap.add_argument("--alpha", action="store_true",
                     help="take the minimal-residual step size after prolongation (off: alpha = 1, "
                          "which converges in far fewer outer iterations on these fields)")
+    ap.add_argument("--restart", type=int, default=50, help="FGCR restart length (paper: 50)")
+    ap.add_argument("--precision-report", action="store_true",
+                    help="relative error of every reduced-precision operator against its FP64 form")
     ap.add_argument("--graph", action="store_true",
                     help="capture the V-cycle in a HIP graph after its first application and replay it")
     ap.add_argument("--big-L", type=int, default=32, help="lattice for the out-of-cache Dslash figure (0: skip)")
@@ -186,6 +189,27 @@ def only_dslash(L, reps=10):
     print(json.dumps(res), flush=True)
 
 
+def precision_report(ctx, torch, synthetic, dims, nv):
+    """||A_prec v - A_f64 v|| / ||A_f64 v|| for D (level 0), P^dagger, P and D_c
+    (level 1) on Gaussian vectors, per reduced precision.  The FP64 forms are
+    those the parity tests pin to the oracle."""
+    def rel(a, b):
+        return float(torch.linalg.vector_norm(a.to(torch.complex128) - b) / torch.linalg.vector_norm(b))
+    dev = ctx.device
+    f = torch.from_numpy(synthetic.gaussian_spinor(dims, 777)).to(dev)
+    cshape = ctx.coarse_shape(1)
+    c = torch.from_numpy(synthetic.gaussian_vectors(cshape, 778)).to(dev)
+    ref = {"D": ctx.apply_D(f), "P_dagger": ctx.restrict(0, f), "P": ctx.prolong(0, c), "D_c": ctx.apply_Dc(1, c)}
+    out = {}
+    for prec in ("f32", "f16", "bf16"):
+        f32, c32 = f.to(torch.complex64), c.to(torch.complex64)
+        out[prec] = {"level0_D": rel(ctx.apply_D(f32, prec=prec), ref["D"]),
+                     "level0_P_dagger": rel(ctx.restrict(0, f32, prec=prec), ref["P_dagger"]),
+                     "level0_P": rel(ctx.prolong(0, c32, prec=prec), ref["P"]),
+                     "level1_D_c": rel(ctx.apply_Dc(1, c32, prec=prec), ref["D_c"])}
+    return out
+
+
 def cpu_baseline(u, b, m, n_d_per_step, nrhs, seconds):
     """The FP64 oracle's Wilson operator timed on the host (bounded sample)."""
     from oracle import wilson
@@ -253,7 +277,7 @@ def main():
         ctx.mg_setup(levels, coarse_tol=a.coarse_tol, use_alpha=a.alpha)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        x, st = ctx.solve(b, tol=1e-10, restart=50, maxit=2000, mg_prec=a.mg_prec, graph=a.graph)
+        x, st = ctx.solve(b, tol=1e-10, restart=a.restart, maxit=2000, mg_prec=a.mg_prec, graph=a.graph)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         return x, st, t1 - t0, t2 - t1
@@ -321,7 +345,7 @@ def main():
         "config": {"workload": f"{'x'.join(map(str, dims))} Wilson-Dirac, links exp(i {a.eps} H), "
                                f"m = m_crit + {a.delta}, "
                                f"2-level MG 4^4 aggregates Nv={a.nv}, MR setup {a.setup_iters} iters, "
-                               f"FGCR(50) to 1e-10, {a.nrhs} Gaussian RHS",
+                               f"FGCR({a.restart}) to 1e-10, {a.nrhs} Gaussian RHS",
                    "lattice": list(dims), "eps": a.eps, "m": m, "m_crit": m - a.delta,
                    "m_crit_source": mcrit_src, "nv": a.nv,
                    "nrhs": a.nrhs, "mg_prec": a.mg_prec, "setup_prec": a.setup_prec, "coarse_tol": a.coarse_tol,
@@ -331,6 +355,8 @@ def main():
         "mg_n_Dc": [s["n_Dc"][1] for s in last], "true_res": true_res,
         "roofline": roofline, "kernels": kinfo, "dslash_in_step": dslash_step,
     }
+    if a.precision_report:
+        result["precision_error"] = precision_report(ctx, torch, synthetic, dims, a.nv)
     if not a.no_bicgstab:
         t0 = time.perf_counter()
         xb, sb = ctx.solve_bicgstab(b, tol=1e-10, maxit=100000)

@@ -349,70 +349,89 @@ __host__ __device__ inline int mfma64_groups(int n2) {
 }
 constexpr int kMfma64Lds = 4096;  // doubles of LDS for the group partials
 
-__device__ __forceinline__ void apply_site_mfma64(const Geom& g, int n2, int nrhs, int s, int q0,
+// All right-hand sides of the batch (up to kMaxRhs = 4 tiles of 16) are
+// done by one workgroup, so each operand chunk of A is loaded once and
+// multiplied into every tile's accumulator.
+constexpr int kMaxTiles = kMaxRhs / 16;
+__device__ __forceinline__ void apply_site_mfma64(const Geom& g, int n2, int nrhs, int s,
                                                   const cx<double>* __restrict__ Dc, const cx<double>* in,
                                                   cx<double>* out, double* lds) {
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int nrt = mfma64_row_tiles(n2), ng = mfma64_groups(n2);
   const int rt = w % nrt, grp = w / nrt;
+  const int ntile = (nrhs + 15) / 16;
   const size_t fs = (size_t)g.vol * n2;
   const int kr = 2 * n2;
   const int r = rt * 16 + (l & 15), i = r >> 1, pr = r & 1;
   const bool rowok = i < n2;
-  const int q = q0 + (l & 15);
-  const bool qok = q < nrhs;
   const int kl = l >> 4;
   int c[4];
   coords_of(g, s, c);
-  doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+  doublex4 acc[kMaxTiles];
+#pragma unroll
+  for (int t = 0; t < kMaxTiles; ++t) acc[t] = doublex4{0.0, 0.0, 0.0, 0.0};
   constexpr int KC = 8;  // MFMA steps whose operands are loaded together
   for (int d = grp; d < 9; d += ng) {
     const int nb = d == 8 ? s : ((d & 1) ? nbr_bwd(g, s, c, d >> 1) : nbr_fwd(g, s, c, d >> 1));
     const double* blk = reinterpret_cast<const double*>(Dc + ((size_t)s * 9 + d) * n2 * n2);
-    const double* v = reinterpret_cast<const double*>(in + (size_t)(qok ? q : 0) * fs + (size_t)nb * n2);
     for (int t0 = 0; 4 * t0 < kr; t0 += KC) {
-      double av[KC], bv[KC];
+      double av[KC];
 #pragma unroll
       for (int t = 0; t < KC; ++t) {
         const int k = 4 * (t0 + t) + kl, j = k >> 1, pk = k & 1;
         av[t] = 0.0;
-        bv[t] = 0.0;
-        if (k < kr) {
-          if (rowok) {
-            const double a = blk[2 * ((size_t)j * n2 + i) + (pr ^ pk)];
-            av[t] = (pr == 0 && pk == 1) ? -a : a;
-          }
-          if (qok) bv[t] = v[2 * j + pk];
+        if (k < kr && rowok) {
+          const double a = blk[2 * ((size_t)j * n2 + i) + (pr ^ pk)];
+          av[t] = (pr == 0 && pk == 1) ? -a : a;
         }
       }
 #pragma unroll
-      for (int t = 0; t < KC; ++t)
-        if (4 * (t0 + t) < kr) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], bv[t], acc, 0, 0, 0);
-    }
-  }
-  // groups 1.. hand their partial tiles to group 0
-  if (grp > 0 && grp < ng) {
-    double* dst = lds + ((size_t)((grp - 1) * nrt + rt) * 64 + l) * 4;
+      for (int tt = 0; tt < kMaxTiles; ++tt) {
+        if (tt >= ntile) break;
+        const int q = tt * 16 + (l & 15);
+        const bool qok = q < nrhs;
+        const double* v = reinterpret_cast<const double*>(in + (size_t)(qok ? q : 0) * fs + (size_t)nb * n2);
+        double bv[KC];
 #pragma unroll
-    for (int reg = 0; reg < 4; ++reg) dst[reg] = acc[reg];
-  }
-  __syncthreads();
-  if (grp == 0) {
-    for (int gg = 1; gg < ng; ++gg) {
-      const double* src = lds + ((size_t)((gg - 1) * nrt + rt) * 64 + l) * 4;
+        for (int t = 0; t < KC; ++t) {
+          const int k = 4 * (t0 + t) + kl, j = k >> 1, pk = k & 1;
+          bv[t] = (qok && k < kr) ? v[2 * j + pk] : 0.0;
+        }
 #pragma unroll
-      for (int reg = 0; reg < 4; ++reg) acc[reg] += src[reg];
-    }
-    if (qok) {
-      double* o = reinterpret_cast<double*>(out + (size_t)q * fs + (size_t)s * n2);
-#pragma unroll
-      for (int reg = 0; reg < 4; ++reg) {
-        const int rr = rt * 16 + 4 * reg + (l >> 4);
-        if ((rr >> 1) < n2) o[rr] = acc[reg];
+        for (int t = 0; t < KC; ++t)
+          if (4 * (t0 + t) < kr) acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], bv[t], acc[tt], 0, 0, 0);
       }
     }
   }
-  __syncthreads();
+  // groups 1.. hand their partial tiles to group 0, one rhs tile at a time
+#pragma unroll
+  for (int tt = 0; tt < kMaxTiles; ++tt) {
+    if (tt >= ntile) break;
+    if (grp > 0 && grp < ng) {
+      double* dst = lds + ((size_t)((grp - 1) * nrt + rt) * 64 + l) * 4;
+#pragma unroll
+      for (int reg = 0; reg < 4; ++reg) dst[reg] = acc[tt][reg];
+    }
+    __syncthreads();
+    if (grp == 0) {
+      doublex4 a = acc[tt];
+      for (int gg = 1; gg < ng; ++gg) {
+        const double* src = lds + ((size_t)((gg - 1) * nrt + rt) * 64 + l) * 4;
+#pragma unroll
+        for (int reg = 0; reg < 4; ++reg) a[reg] += src[reg];
+      }
+      const int q = tt * 16 + (l & 15);
+      if (q < nrhs) {
+        double* o = reinterpret_cast<double*>(out + (size_t)q * fs + (size_t)s * n2);
+#pragma unroll
+        for (int reg = 0; reg < 4; ++reg) {
+          const int rr = rt * 16 + 4 * reg + (l >> 4);
+          if ((rr >> 1) < n2) o[rr] = a[reg];
+        }
+      }
+    }
+    __syncthreads();
+  }
 }
 
 // One right-hand side on the vector units: wave d (of nine) applies block d
@@ -462,9 +481,9 @@ __global__ __launch_bounds__(1024) void k_coarse_apply_mfma64(Geom g, int n2, in
                                                               cx<double>* __restrict__ out,
                                                               cx<double>* __restrict__ copy) {
   __shared__ double lds[kMfma64Lds];
-  const int s = blockIdx.x, q0 = blockIdx.y * 16;
-  if (copy) copy_site(n2, (size_t)g.vol * n2, s, q0, min(16, nrhs - q0), in, copy);
-  apply_site_mfma64(g, n2, nrhs, s, q0, Dc, in, out, lds);
+  const int s = blockIdx.x;
+  if (copy) copy_site(n2, (size_t)g.vol * n2, s, 0, nrhs, in, copy);
+  apply_site_mfma64(g, n2, nrhs, s, Dc, in, out, lds);
 }
 
 // FP32: v_mfma_f32_32x32x2f32; tile = 32 real rows x 32 rhs.
@@ -724,7 +743,7 @@ __global__ __launch_bounds__(256) void k_coarse_apply_mfma16(Geom g, int n2, int
 // The stopping test is thus lagged by one iteration; the per-rhs active flags
 // go to pinned host memory, where the host inspects them two iterations
 // later, so it never waits for the GPU inside the solve.
-constexpr int kCgcrG1 = 256;  // workgroups (x) of K1
+constexpr int kCgcrG1 = 4096;  // workgroups of K1 (one coarse site each up to this many sites)
 constexpr int kCgcrG3 = 64;   // chunks per rhs of K3
 
 struct CgcrState {  // per-rhs device scalars of one solve (inside the level's scalar block)
@@ -766,19 +785,19 @@ __global__ __launch_bounds__(1024) void k_cgcr_apply(Geom g, int n2, int nrhs, i
                                                     const cx<double>* Wb, cx<double>* w, cx<double>* z,
                                                     double* part) {
   extern __shared__ __align__(16) char dyn1[];
-  double* acc = reinterpret_cast<double*>(dyn1);  // [16][vals]
+  double* acc = reinterpret_cast<double*>(dyn1);  // [nrhs][vals]
   __shared__ double lds[kMfma64Lds];
-  const int q0 = blockIdx.y * 16, nq = min(16, nrhs - q0);
+  const int q0 = 0, nq = nrhs;
   const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6, lane = threadIdx.x & 63;
   const size_t fs = (size_t)g.vol * n2, bs = (size_t)nrhs * fs;
-  for (int t = threadIdx.x; t < 16 * vals; t += blockDim.x) acc[t] = 0.0;
+  for (int t = threadIdx.x; t < nq * vals; t += blockDim.x) acc[t] = 0.0;
   for (int s = blockIdx.x; s < g.vol; s += gridDim.x) {
     copy_site(n2, fs, s, q0, nq, r, z);
     // both end with a block barrier: w_j of site s is then complete
     if (VALU)
       apply_site_valu1(g, n2, s, Dc, r, w, lds);
     else
-      apply_site_mfma64(g, n2, nrhs, s, q0, Dc, r, w, lds);
+      apply_site_mfma64(g, n2, nrhs, s, Dc, r, w, lds);
     for (int qq = wave; qq < nq; qq += nw) {
       const size_t o = (size_t)(q0 + qq) * fs + (size_t)s * n2 + lane;
       cx<double> wv = mk(0.0, 0.0), rv = mk(0.0, 0.0);
@@ -822,7 +841,7 @@ __global__ __launch_bounds__(1024) void k_cgcr_apply(Geom g, int n2, int nrhs, i
 
 // K2: one workgroup per rhs.  vals = 4 j + 4 partial values per K1 workgroup;
 // p3: K3's partial |w_{j-1}|^2 per chunk (j > 0).
-__global__ __launch_bounds__(256) void k_cgcr_coef(int j, int vals, int g1, const double* __restrict__ part,
+__global__ __launch_bounds__(1024) void k_cgcr_coef(int j, int vals, int g1, const double* __restrict__ part,
                                                    const double* __restrict__ p3, int kmax, CgcrState S,
                                                    double* host_act, double* err) {
   extern __shared__ __align__(16) char dyn2[];
@@ -948,7 +967,7 @@ void coarse_apply(Ctx& c, const Level& cl, const cx<R>* Dc, cx<R>* out, const cx
     if constexpr (sizeof(R) == 8) {
       ProfScope ps(c, WDMG_K_DC_MFMA_F64, (long long)cl.nsite * nrhs);
       const int waves = mfma64_row_tiles(n2) * mfma64_groups(n2);
-      hipLaunchKernelGGL(k_coarse_apply_mfma64, dim3(cl.nsite, (nrhs + 15) / 16), dim3(64 * waves), 0, c.stream,
+      hipLaunchKernelGGL(k_coarse_apply_mfma64, dim3(cl.nsite), dim3(64 * waves), 0, c.stream,
                          cl.g, n2, nrhs, Dc, in, out, copy);
     } else {
       ProfScope ps(c, WDMG_K_DC_MFMA_F32, (long long)cl.nsite * nrhs);
@@ -1024,13 +1043,15 @@ void coarsest_gcr(Ctx& c, Level& L, cx<double>* x, const cx<double>* b, int nrhs
   double* gb = c.dsc + gcr_base(L.l);
   CgcrState S{gb + G_H, gb + G_NRM, gb + G_A, gb + G_RN, gb + G_ACT, gb + G_TOL};
   const int g1 = L.nsite < kCgcrG1 ? L.nsite : kCgcrG1;
-  const int ntile = (nrhs + 15) / 16, waves = mfma64_row_tiles(n2) * mfma64_groups(n2);
+  const int waves = mfma64_row_tiles(n2) * mfma64_groups(n2);
+  if ((size_t)nrhs * (4 * k + 4) * sizeof(double) > 96 * 1024)
+    throw Error(WDMG_ERR_ARG, "coarse_restart too long for this many right-hand sides (LDS)");
   static bool lds_attr = false;
-  if (!lds_attr) {  // K1 keeps 16 x (4 k + 4) partial sums in LDS (k <= 128)
+  if (!lds_attr) {  // K1 keeps nrhs x (4 j + 4) partial sums in LDS
     WDMG_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cgcr_apply<false>),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, 16 * (4 * kMaxKrylov + 4) * 8));
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024));
     WDMG_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cgcr_apply<true>),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, 16 * (4 * kMaxKrylov + 4) * 8));
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024));
     lds_attr = true;
   }
   hipLaunchKernelGGL(k_cgcr_init, dim3(nrhs), dim3(256), 0, c.stream, b, x, L.w64[1], n, tol, S, c.dsc + S_ERR);
@@ -1056,14 +1077,14 @@ void coarsest_gcr(Ctx& c, Level& L, cx<double>* x, const cx<double>* b, int nrhs
     {
       ProfScope ps(c, WDMG_K_COARSE_GCR, (long long)L.nsite * nrhs);
       if (nrhs == 1)
-        hipLaunchKernelGGL(k_cgcr_apply<true>, dim3(g1, 1), dim3(576), (size_t)16 * vals * sizeof(double), c.stream,
-                           L.g, n2, nrhs, j, vals, L.Dc64, r, L.basisW, w, z, L.cpart);
+        hipLaunchKernelGGL(k_cgcr_apply<true>, dim3(g1), dim3(576), (size_t)vals * sizeof(double), c.stream, L.g, n2,
+                           nrhs, j, vals, L.Dc64, r, L.basisW, w, z, L.cpart);
       else
-        hipLaunchKernelGGL(k_cgcr_apply<false>, dim3(g1, ntile), dim3(64 * waves), (size_t)16 * vals * sizeof(double),
+        hipLaunchKernelGGL(k_cgcr_apply<false>, dim3(g1), dim3(64 * waves), (size_t)nrhs * vals * sizeof(double),
                            c.stream, L.g, n2, nrhs, j, vals, L.Dc64, r, L.basisW, w, z, L.cpart);
       WDMG_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_cgcr_coef, dim3(nrhs), dim3(256), (size_t)(vals + 1) * sizeof(double), c.stream, j, vals,
+    hipLaunchKernelGGL(k_cgcr_coef, dim3(nrhs), dim3(1024), (size_t)(vals + 1) * sizeof(double), c.stream, j, vals,
                        g1, L.cpart, L.cpart3, k, S, c.capturing ? nullptr : c.dring + (size_t)(it % kRing) * kMaxRhs,
                        c.dsc + S_ERR);
     WDMG_HIP(hipGetLastError());

@@ -79,13 +79,31 @@ struct RowsC {  // level >= 1: r = d * bvol + l, d in 0..half-1
   }
 };
 
+// Workgroup -> (aggregate, rhs) for a one-dimensional grid of nagg * nrhs
+// workgroups.  The hardware sends workgroup b to XCD b % 8; the mapping gives
+// every XCD a contiguous run of aggregates and runs all right-hand sides of
+// an aggregate back to back there, so its P columns come from HBM once and
+// are re-read from that XCD's L2.
+__device__ __forceinline__ void agg_rhs_block(int nagg, int nrhs, int& agg, int& rhs) {
+  const int b = blockIdx.x;
+  if (nrhs == 1 || (nagg & 7)) {
+    agg = b % nagg;
+    rhs = b / nagg;
+    return;
+  }
+  const int xcd = b & 7, local = b >> 3;
+  agg = xcd * (nagg >> 3) + local / nrhs;
+  rhs = local % nrhs;
+}
+
 // ---- restriction: one workgroup per (aggregate, rhs) ----------------------
 template <typename R, class Rows>
 __global__ __launch_bounds__(256) void k_restrict(Rows rows, int nrows, const cx<R>* __restrict__ Vv, size_t vstride,
                                                   const cx<R>* __restrict__ in, size_t fstride, cx<R>* __restrict__ out,
                                                   int nagg, int nv) {
   __shared__ double lds[4 * KC * 4];
-  const int agg = blockIdx.x, rhs = blockIdx.y;
+  int agg, rhs;
+  agg_rhs_block(nagg, gridDim.x / nagg, agg, rhs);
   in += (size_t)rhs * fstride;
   out += ((size_t)rhs * nagg + agg) * 2 * nv;
   for (int k0 = 0; k0 < nv; k0 += KC) {
@@ -122,9 +140,11 @@ constexpr int RB = 8;  // right-hand sides per workgroup in the batched prolonga
 template <typename R>
 __global__ __launch_bounds__(256) void k_prolong0_b(AggMap map, const cx<R>* __restrict__ Vv,
                                                     const cx<R>* __restrict__ in, cx<R>* __restrict__ out, int nagg,
-                                                    int nv, int nrhs) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  const int r0 = blockIdx.y * RB;
+                                                    int nv, int nrhs, int nsb) {
+  int sb, grp;
+  agg_rhs_block(nsb, gridDim.x / nsb, sb, grp);
+  const int s = sb * blockDim.x + threadIdx.x;
+  const int r0 = grp * RB;
   const int nr = min(RB, nrhs - r0);
   const size_t n = (size_t)12 * map.g.vpad;
   if (s >= map.g.vpad) return;
@@ -203,7 +223,8 @@ __global__ __launch_bounds__(256) void k_restrict0_h(Rows0 rows, int nrows, cons
                                                      const float* __restrict__ isc, cx<float>* __restrict__ out,
                                                      int nagg, int nv, int vpad) {
   __shared__ double lds[4 * KC * 4];
-  const int agg = blockIdx.x, rhs = blockIdx.y;
+  int agg, rhs;
+  agg_rhs_block(nagg, gridDim.x / nagg, agg, rhs);
   in += (size_t)rhs * 12 * vpad;
   isc += (size_t)rhs * vpad;
   out += ((size_t)rhs * nagg + agg) * 2 * nv;
@@ -246,9 +267,11 @@ constexpr int RBH = 4;
 template <typename H>
 __global__ __launch_bounds__(256) void k_prolong0_h(AggMap map, const cxh<H>* __restrict__ Vv,
                                                     const cx<float>* __restrict__ in, cxh<H>* __restrict__ out,
-                                                    float* __restrict__ osc, int nagg, int nv, int nrhs) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  const int r0 = blockIdx.y * RBH;
+                                                    float* __restrict__ osc, int nagg, int nv, int nrhs, int nsb) {
+  int sb, grp;
+  agg_rhs_block(nsb, gridDim.x / nsb, sb, grp);
+  const int s = sb * blockDim.x + threadIdx.x;
+  const int r0 = grp * RBH;
   const int nr = min(RBH, nrhs - r0);
   const int vpad = map.g.vpad;
   const size_t n = (size_t)12 * vpad;
@@ -280,6 +303,105 @@ __global__ __launch_bounds__(256) void k_prolong0_h(AggMap map, const cxh<H>* __
 #pragma unroll
   for (int q = 0; q < RBH; ++q)
     if (q < nr) store_site_h(out + (size_t)(r0 + q) * n, osc + (size_t)(r0 + q) * vpad, s, acc[q]);
+}
+
+// ---- batched restriction on the matrix cores (FP32 arithmetic) ----------------
+// For a batch of right-hand sides P^dagger is, per (aggregate, chirality), the
+// complex GEMM out[k][q] = sum_row conj(V[row][k]) f[row][q]; it runs as the
+// real GEMM with rows (k, re|im) and the contraction over (row, re|im):
+//   A[(k,0)][(r,0)] = Re v, A[(k,0)][(r,1)] = Im v, A[(k,1)][(r,0)] = -Im v,
+//   A[(k,1)][(r,1)] = Re v;  B[(r,0)][q] = Re f, B[(r,1)][q] = Im f.
+// Workgroup = one aggregate and up to 32 right-hand sides; wave w handles
+// chirality w / 2 and output row tile w % 2 (32 real rows, 2 Nv <= 64).
+// Chunks of 64 rows (one spin-colour component on 64 aggregate sites) of V
+// and of the fields are staged in LDS with coalesced loads, then fed to
+// v_mfma_f32_32x32x2f32 (lanes as in the coarse-operator kernel).
+struct FieldF32 {  // plain FP32 fine fields [rhs][12 vpad]
+  const cx<float>* f;
+  int vpad;
+  __device__ __forceinline__ cx<float> get(int q, int site, int comp) const {
+    return f[(size_t)q * 12 * vpad + fidx(site, comp, 12)];
+  }
+};
+template <typename H>
+struct FieldH {  // 16-bit fine fields with per-site scales
+  const cxh<H>* v;
+  const float* sc;
+  int vpad;
+  __device__ __forceinline__ cx<float> get(int q, int site, int comp) const {
+    const float s = sc[(size_t)q * vpad + site];
+    const cx<float> x = h2f(v[(size_t)q * 12 * vpad + fidx(site, comp, 12)]);
+    return mk(s * x.re, s * x.im);
+  }
+};
+struct VF32 {
+  const cx<float>* v;
+  size_t stride;
+  __device__ __forceinline__ cx<float> get(int k, size_t off) const { return v[(size_t)k * stride + off]; }
+};
+template <typename H>
+struct VH {
+  const cxh<H>* v;
+  size_t stride;
+  __device__ __forceinline__ cx<float> get(int k, size_t off) const { return h2f(v[(size_t)k * stride + off]); }
+};
+
+typedef float floatx16_t __attribute__((ext_vector_type(16)));
+
+template <class VL, class FL>
+__global__ __launch_bounds__(256) void k_restrict0_mfma(AggMap map, VL V, FL F, cx<float>* __restrict__ out,
+                                                        int nagg, int nv, int nrhs) {
+  __shared__ cx<float> Vs[2][64][33];
+  __shared__ cx<float> Fs[2][64][33];
+  int agg, tile;
+  agg_rhs_block(nagg, gridDim.x / nagg, agg, tile);
+  const int q0 = tile * 32, nq = min(32, nrhs - q0);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int chi = w >> 1, rt = w & 1;
+  const int i = rt * 32 + (l & 31), kidx = i >> 1, part = i & 1;
+  const int q = l & 31;
+  floatx16_t acc;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) acc[e] = 0.f;
+  const int per = map.bvol / 64;
+  for (int c = 0; c < 6 * per; ++c) {
+    const int m = c / per, l0 = (c % per) * 64;
+    __syncthreads();
+    // stage: thread t loads site l0 + (t & 63) for several k / q
+    {
+      const int ll = threadIdx.x & 63, grp = threadIdx.x >> 6;
+      const int site = map.site(agg, l0 + ll);
+      for (int ch = 0; ch < 2; ++ch) {
+        const size_t off = fidx(site, 6 * ch + m, 12);
+        for (int k = grp; k < nv; k += 4) Vs[ch][ll][k] = V.get(k, off);
+        for (int qq = grp; qq < nq; qq += 4) Fs[ch][ll][qq] = F.get(q0 + qq, site, 6 * ch + m);
+      }
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < 128; kk += 2) {
+      const int kr = kk + (l >> 5), r = kr >> 1, pk = kr & 1;
+      float a = 0.f, b = 0.f;
+      if (kidx < nv) {
+        const cx<float> v = Vs[chi][r][kidx];
+        a = part == 0 ? (pk == 0 ? v.re : v.im) : (pk == 0 ? -v.im : v.re);
+      }
+      if (q < nq) {
+        const cx<float> fv = Fs[chi][r][q];
+        b = pk == 0 ? fv.re : fv.im;
+      }
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+    }
+  }
+  // D[i][q] in lane q + 32 ((i / 4) % 2), register 4 (i / 8) + i % 4
+  if (q < nq) {
+    float* o = reinterpret_cast<float*>(out + ((size_t)(q0 + q) * nagg + agg) * 2 * nv + chi * nv);
+#pragma unroll
+    for (int reg = 0; reg < 16; ++reg) {
+      const int ii = rt * 32 + 8 * (reg >> 2) + 4 * (l >> 5) + (reg & 3);
+      if ((ii >> 1) < nv) o[ii] = acc[reg];
+    }
+  }
 }
 
 // ---- block orthonormalisation (FP64): CGS with a second pass --------------
@@ -373,13 +495,24 @@ inline int tpb_for(int nrows) {
 
 template <typename R>
 void restrict0(Ctx& c, const Level& f, const cx<R>* V, const cx<R>* in, cx<R>* out, int nrhs) {
+  if constexpr (sizeof(R) == 4) {
+    const AggMap map = make_map(f);
+    if (nrhs >= 2 && map.bvol % 64 == 0 && f.nv <= 32) {
+      const int nagg = nagg_of(f);
+      ProfScope ps(c, WDMG_K_RESTRICT_F32, (long long)f.nsite * nrhs);
+      hipLaunchKernelGGL((k_restrict0_mfma<VF32, FieldF32>), dim3(nagg * ((nrhs + 31) / 32)), dim3(256), 0,
+                         c.stream, map, VF32{V, f.n}, FieldF32{in, f.g.vpad}, out, nagg, f.nv, nrhs);
+      WDMG_HIP(hipGetLastError());
+      return;
+    }
+  }
   Rows0 rows{make_map(f)};
   const int nrows = rows.nrows();
   const int nagg = nagg_of(f);
   // (one workgroup per (aggregate, rhs): measured faster than reading V once
   // per rhs chunk, because the chunked form re-reads the fine fields per column)
   ProfScope ps(c, sizeof(R) == 8 ? WDMG_K_RESTRICT_F64 : WDMG_K_RESTRICT_F32, (long long)f.nsite * nrhs);
-  hipLaunchKernelGGL((k_restrict<R, Rows0>), dim3(nagg, nrhs), dim3(tpb_for(nrows)), 0, c.stream, rows, nrows, V,
+  hipLaunchKernelGGL((k_restrict<R, Rows0>), dim3(nagg * nrhs), dim3(tpb_for(nrows)), 0, c.stream, rows, nrows, V,
                      f.n, in, f.n, out, nagg, f.nv);
   WDMG_HIP(hipGetLastError());
 }
@@ -390,7 +523,7 @@ void restrictC(Ctx& c, const Level& f, const cx<R>* V, const cx<R>* in, cx<R>* o
   const int nrows = rows.nrows();
   const int nagg = nagg_of(f);
 
-  hipLaunchKernelGGL((k_restrict<R, RowsC>), dim3(nagg, nrhs), dim3(tpb_for(nrows)), 0, c.stream, rows, nrows, V,
+  hipLaunchKernelGGL((k_restrict<R, RowsC>), dim3(nagg * nrhs), dim3(tpb_for(nrows)), 0, c.stream, rows, nrows, V,
                      f.n, in, f.n, out, nagg, f.nv);
   WDMG_HIP(hipGetLastError());
 }
@@ -400,8 +533,9 @@ void prolong0(Ctx& c, const Level& f, const cx<R>* V, const cx<R>* in, cx<R>* ou
   const AggMap map = make_map(f);
   if (nrhs > 1) {
     ProfScope ps(c, sizeof(R) == 8 ? WDMG_K_PROLONG_F64 : WDMG_K_PROLONG_F32, (long long)f.nsite * nrhs);
-    hipLaunchKernelGGL((k_prolong0_b<R>), dim3((f.g.vpad + 255) / 256, (nrhs + RB - 1) / RB), dim3(256), 0,
-                       c.stream, map, V, in, out, nagg_of(f), f.nv, nrhs);
+    const int nsb = (f.g.vpad + 255) / 256;
+    hipLaunchKernelGGL((k_prolong0_b<R>), dim3(nsb * ((nrhs + RB - 1) / RB)), dim3(256), 0, c.stream, map, V, in,
+                       out, nagg_of(f), f.nv, nrhs, nsb);
     WDMG_HIP(hipGetLastError());
     return;
   }
@@ -421,11 +555,23 @@ void prolongC(Ctx& c, const Level& f, const cx<R>* V, const cx<R>* in, cx<R>* ou
 
 template <typename H>
 void restrict0_h(Ctx& c, const Level& f, const void* V16, HF in, cx<float>* out, int nrhs) {
+  {
+    const AggMap map = make_map(f);
+    if (nrhs >= 2 && map.bvol % 64 == 0 && f.nv <= 32) {
+      const int nagg = nagg_of(f);
+      ProfScope ps(c, WDMG_K_RESTRICT_H, (long long)f.nsite * nrhs);
+      hipLaunchKernelGGL((k_restrict0_mfma<VH<H>, FieldH<H>>), dim3(nagg * ((nrhs + 31) / 32)), dim3(256), 0,
+                         c.stream, map, VH<H>{static_cast<const cxh<H>*>(V16), f.n},
+                         FieldH<H>{static_cast<const cxh<H>*>(in.v), in.s, f.g.vpad}, out, nagg, f.nv, nrhs);
+      WDMG_HIP(hipGetLastError());
+      return;
+    }
+  }
   Rows0 rows{make_map(f)};
   const int nrows = rows.nrows();
   const int nagg = nagg_of(f);
   ProfScope ps(c, WDMG_K_RESTRICT_H, (long long)f.nsite * nrhs);
-  hipLaunchKernelGGL((k_restrict0_h<H>), dim3(nagg, nrhs), dim3(tpb_for(nrows)), 0, c.stream, rows, nrows,
+  hipLaunchKernelGGL((k_restrict0_h<H>), dim3(nagg * nrhs), dim3(tpb_for(nrows)), 0, c.stream, rows, nrows,
                      static_cast<const cxh<H>*>(V16), f.n, static_cast<const cxh<H>*>(in.v), in.s, out, nagg, f.nv,
                      f.g.vpad);
   WDMG_HIP(hipGetLastError());
@@ -435,9 +581,10 @@ template <typename H>
 void prolong0_h(Ctx& c, const Level& f, const void* V16, const cx<float>* in, HF out, int nrhs) {
   const AggMap map = make_map(f);
   ProfScope ps(c, WDMG_K_PROLONG_H, (long long)f.nsite * nrhs);
-  hipLaunchKernelGGL((k_prolong0_h<H>), dim3((f.g.vpad + 255) / 256, (nrhs + RBH - 1) / RBH), dim3(256), 0,
-                     c.stream, map, static_cast<const cxh<H>*>(V16), in, static_cast<cxh<H>*>(out.v), out.s,
-                     nagg_of(f), f.nv, nrhs);
+  const int nsb = (f.g.vpad + 255) / 256;
+  hipLaunchKernelGGL((k_prolong0_h<H>), dim3(nsb * ((nrhs + RBH - 1) / RBH)), dim3(256), 0, c.stream, map,
+                     static_cast<const cxh<H>*>(V16), in, static_cast<cxh<H>*>(out.v), out.s, nagg_of(f), f.nv, nrhs,
+                     nsb);
   WDMG_HIP(hipGetLastError());
 }
 

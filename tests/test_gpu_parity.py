@@ -348,3 +348,16 @@ def test_both_dslash_forms_match_oracle(form, dims, nrhs):
     ctx.set_tuning("dslash", None)
     ctx.apply_D(gpu(psi))  # autotuned
     assert ctx.get_tuning("dslash", "f64", nrhs) in (0, 1)
+
+
+@pytest.mark.parametrize("nrhs,nv", [(3, 12), (40, 8), (2, 32)])
+def test_batched_restriction_on_matrix_cores(nrhs, nv):
+    """A batch of right-hand sides restricts through the MFMA GEMM form of
+    P^dagger (FP32 arithmetic); every column equals the oracle's P^dagger."""
+    dims, blk = (8, 8, 8, 8), (4, 4, 4, 4)
+    ctx, u, q, lev = _setup_imported(dims, blk, nv, seed=83)
+    f = synthetic.gaussian_spinor(dims, seed=84, nrhs=nrhs)
+    got = ctx.restrict(0, gpu(f.astype(np.complex64)), prec="f32").cpu().numpy().astype(np.complex128)
+    for j in range(nrhs):
+        ref = transfer.restrict(q, transfer.as_chiral(f[j]), blk)
+        assert rel(got[j], ref) < 2e-6, j
