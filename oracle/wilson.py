@@ -155,3 +155,30 @@ def gauge_transform(u: np.ndarray, omega: np.ndarray) -> np.ndarray:
 
 def colour_rotate(omega: np.ndarray, psi: np.ndarray) -> np.ndarray:
     return np.einsum("...ab,...sb->...sa", omega, psi)
+
+
+def apply_D_at(u: np.ndarray, psi: np.ndarray, m: float, sites, t_bc: float = -1.0) -> np.ndarray:
+    """``(D psi)(x)`` at the listed sites only, each from its nine terms (Sec. 1
+    operator, reading above): ``sites`` is a sequence of ``(x, y, z, t)``;
+    returns ``[len(sites), 4, 3]``.  For sampled checks on lattices too large
+    for the whole-lattice form; written out term by term like ``dense_D``."""
+    lx, ly, lz, lt = dims_of(u)
+    ext = (lx, ly, lz, lt)
+    out = np.zeros((len(sites), 4, 3), dtype=np.complex128)
+    for n, here in enumerate(sites):
+        x, y, z, t = here
+        acc = (4.0 + m) * psi[t, z, y, x]
+        for mu in range(4):
+            up = list(here)
+            up[mu] = (up[mu] + 1) % ext[mu]
+            s_up = t_bc if (mu == 3 and t == lt - 1) else 1.0
+            f_up = psi[up[3], up[2], up[1], up[0]]
+            acc = acc - 0.5 * s_up * (ID4 - GAMMA[mu]) @ (f_up @ u[t, z, y, x, mu].T)
+            dn = list(here)
+            dn[mu] = (dn[mu] - 1) % ext[mu]
+            s_dn = t_bc if (mu == 3 and t == 0) else 1.0
+            f_dn = psi[dn[3], dn[2], dn[1], dn[0]]
+            link_dn = u[dn[3], dn[2], dn[1], dn[0], mu]
+            acc = acc - 0.5 * s_dn * (ID4 + GAMMA[mu]) @ (f_dn @ np.conj(link_dn))
+        out[n] = acc
+    return out

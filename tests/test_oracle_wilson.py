@@ -125,3 +125,24 @@ def test_batched_apply_matches_single():
     out = wilson.apply_D(u, psi, 0.1)
     for j in range(3):
         assert rel(out[j], wilson.apply_D(u, psi[j], 0.1)) < 1e-15
+
+
+def test_per_site_operator_matches_whole_lattice_forms():
+    """apply_D_at (term by term at chosen sites) against apply_D and dense_D."""
+    dims = (4, 6, 2, 8)
+    u = synthetic.gauge_field(dims, 0.4, 5)
+    psi = synthetic.gaussian_spinor(dims, 6)
+    full = wilson.apply_D(u, psi, -0.3, -1.0)
+    sites = [(0, 0, 0, 0), (3, 5, 1, 7), (2, 3, 0, 0), (1, 1, 1, 7), (3, 0, 1, 3)]
+    pt = wilson.apply_D_at(u, psi, -0.3, sites, -1.0)
+    for n, (x, y, z, t) in enumerate(sites):
+        assert np.abs(pt[n] - full[t, z, y, x]).max() < 1e-14
+    small = (2, 2, 2, 4)
+    u2 = synthetic.gauge_field(small, 0.4, 7)
+    p2 = synthetic.gaussian_spinor(small, 8)
+    dense = wilson.dense_D(u2, 0.2, 1.0) @ p2.reshape(-1)
+    sites2 = [(1, 0, 1, 3), (0, 1, 0, 0)]
+    pt2 = wilson.apply_D_at(u2, p2, 0.2, sites2, 1.0)
+    for n, (x, y, z, t) in enumerate(sites2):
+        i = x + 2 * (y + 2 * (z + 2 * t))
+        assert np.abs(pt2[n].reshape(-1) - dense[12 * i:12 * i + 12]).max() < 1e-14
