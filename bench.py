@@ -65,6 +65,9 @@ def parse():
     ap.add_argument("--mass", type=float, default=None,
                     help="use this bare mass instead of m_crit + delta (no m_crit lookup)")
     ap.add_argument("--nv", type=int, default=20)
+    ap.add_argument("--levels", type=int, default=2, choices=[2, 3],
+                    help="3: a second coarsening with 2^4 aggregates (Sec. 5 three-level cycle)")
+    ap.add_argument("--nv2", type=int, default=32, help="near-null vectors of the second coarsening")
     ap.add_argument("--setup-iters", type=int, default=100)
     ap.add_argument("--nrhs", type=int, default=1)
     ap.add_argument("--setup-prec", default="f64", choices=["f64", "f32"],
@@ -271,6 +274,12 @@ def main():
     b = torch.from_numpy(bh).to(dev)
     levels = [{"block": (4, 4, 4, 4), "nv": a.nv, "setup_iters": a.setup_iters, "vectors": v0,
                "setup_prec": a.setup_prec}]
+    if a.levels == 3:
+        cdims = tuple(d // 4 for d in dims)
+        v1 = torch.from_numpy(synthetic.gaussian_vectors(
+            (a.nv2, cdims[3], cdims[2], cdims[1], cdims[0], 2, a.nv), synthetic.null_seed(cfg) + 500)).to(dev)
+        levels.append({"block": (2, 2, 2, 2), "nv": a.nv2, "setup_iters": a.setup_iters, "vectors": v1,
+                       "setup_prec": a.setup_prec})
 
     def step():
         t0 = time.perf_counter()
@@ -344,10 +353,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{'x'.join(map(str, dims))} Wilson-Dirac, links exp(i {a.eps} H), "
                                f"m = m_crit + {a.delta}, "
-                               f"2-level MG 4^4 aggregates Nv={a.nv}, MR setup {a.setup_iters} iters, "
+                               + (f"2-level MG 4^4 aggregates Nv={a.nv}, " if a.levels == 2 else
+                                  f"3-level MG 4^4 then 2^4 aggregates Nv={a.nv} then {a.nv2}, ")
+                               + f"MR setup {a.setup_iters} iters, "
                                f"FGCR({a.restart}) to 1e-10, {a.nrhs} Gaussian RHS",
                    "lattice": list(dims), "eps": a.eps, "m": m, "m_crit": m - a.delta,
-                   "m_crit_source": mcrit_src, "nv": a.nv,
+                   "m_crit_source": mcrit_src, "levels": a.levels, "nv": a.nv,
+                   "nv2": a.nv2 if a.levels == 3 else None,
                    "nrhs": a.nrhs, "mg_prec": a.mg_prec, "setup_prec": a.setup_prec, "coarse_tol": a.coarse_tol,
                    "alpha_step": a.alpha, "graph": a.graph},
         "setup_s": float(np.median(setups)), "solve_s_per_rhs": float(np.median(solves)) / a.nrhs,
