@@ -44,6 +44,31 @@ def dc_bytes(prec, nv):                            # per coarse site: 9 blocks +
     return 9 * n2 * n2 * b + 2 * n2 * b
 
 
+def coarse_gcr_bytes(nsite, n2, units):           # one coarsest GCR operator launch (FP64 D_c)
+    """D_c read once per launch (9 blocks per coarse site), r read, w_j and z_j written."""
+    return nsite * 9 * n2 * n2 * 16 + units * 3 * n2 * 16
+
+
+def counter_traffic(kernel, dims, bytes_per_launch):
+    """HBM bytes per launch from the committed PMC measurement of this kernel on
+    this lattice (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's reading), or
+    None when there is none or the kernel's sources changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    h = hashlib.sha256()
+    for f in t["source_files"]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != t["source_hash"]:
+        return None
+    e = t["entries"].get(kernel + "@" + "x".join(map(str, dims)))
+    return None if e is None else e["measured_over_algorithmic"] * bytes_per_launch
+
+
 def transfer_bytes(prec, nv):                      # per fine site: Nv columns (12 cplx) + fine + coarse share
     b = 16 if prec == "f64" else 8
     return 12 * nv * b + 12 * b
@@ -331,13 +356,18 @@ def main():
         bpl = dc_bytes(dom[-3:], a.nv) * units / n
     elif dom.startswith(("restrict", "prolong")):
         bpl = transfer_bytes(dom[-3:], a.nv) * units / n
+    elif dom == "coarse_gcr":
+        vol = int(np.prod(dims))
+        csite, n2 = (vol // 256, 2 * a.nv) if a.levels == 2 else (vol // 4096, 2 * a.nv2)
+        bpl = coarse_gcr_bytes(csite, n2, units / n)
     else:
         bpl = None
     roofline = None
     if bpl is not None:
         ach = bpl / per_launch_s / 1e9
+        traffic = counter_traffic(dom, dims, bpl)
         roofline = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                    "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
                     "bytes_per_launch": bpl, "us_per_launch": per_launch_s * 1e6}
     ds = prof["dslash_f64"]
     dslash_step = None

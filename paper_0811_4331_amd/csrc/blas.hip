@@ -689,15 +689,21 @@ __global__ __launch_bounds__(TPB) void k_gcr_dots_b(const cx<double>* __restrict
   }
 }
 
+// One wave per coefficient: lanes add the workgroup partials in a strided
+// order, then a fixed shuffle tree (deterministic).
 __global__ __launch_bounds__(TPB) void k_gcr_dots_b_fin(int j, int gx, int gy, const double* partials, double* g) {
   const int rhs = blockIdx.x;
-  for (int t = threadIdx.x; t < 2 * j; t += TPB) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = TPB / 64;
+  for (int t = wave; t < 2 * j; t += nw) {
     const int i = t >> 1, part = t & 1;
     const int yy = i / GCR_G, q = i % GCR_G;
     double s = 0.0;
-    for (int bx = 0; bx < gx; ++bx) s += partials[(((size_t)rhs * gy + yy) * gx + bx) * 2 * GCR_G + 2 * q + part];
-    const double nrm = g[G_NRM + rhs * kMaxKrylov + i];
-    g[G_H + rhs * 2 * kMaxKrylov + t] = nrm > 0.0 ? s / nrm : 0.0;
+    for (int bx = lane; bx < gx; bx += 64) s += partials[(((size_t)rhs * gy + yy) * gx + bx) * 2 * GCR_G + 2 * q + part];
+    s = wave_sum(s);
+    if (lane == 0) {
+      const double nrm = g[G_NRM + rhs * kMaxKrylov + i];
+      g[G_H + rhs * 2 * kMaxKrylov + t] = nrm > 0.0 ? s / nrm : 0.0;
+    }
   }
 }
 
