@@ -49,6 +49,30 @@ def coarse_gcr_bytes(nsite, n2, units):           # one coarsest GCR operator la
     return nsite * 9 * n2 * n2 * 16 + units * 3 * n2 * 16
 
 
+# Dense matrix-core peaks of MI355X (TFLOP/s) by the dtype the contraction runs in.
+MFMA_PEAK_TFS = {"f64": 78.6, "f32": 157.3, "h": 2500.0}
+
+
+def dc_mfma_util(kinfo, nrhs, n2_mid, n2_coarsest):
+    """Achieved FLOP/s of the coarse-operator launches that run on matrix cores,
+    against the dense peak of their dtype.  A unit is one (coarse site, rhs);
+    one unit costs 9 (2Nv)^2 complex multiply-adds = 72 (2Nv)^2 real flops.
+    The intermediate-level kernels use Nv of the first coarsening; the
+    coarsest GCR's operator launch (FP64 matrix cores once nrhs > 1) uses the
+    coarsest level's Nv."""
+    out = {}
+    for name, dt, n2 in (("dc_mfma_f64", "f64", n2_mid), ("dc_mfma_f32", "f32", n2_mid),
+                         ("dc_mfma_h", "h", n2_mid), ("coarse_gcr", "f64", n2_coarsest)):
+        k = kinfo.get(name)
+        if k is None or (name == "coarse_gcr" and nrhs < 2):
+            continue
+        flops = 72.0 * n2 * n2 * k["units"]
+        tfs = flops / (k["ms_total"] / 1e3) / 1e12
+        out[name] = {"dtype": dt, "achieved_tflops": tfs, "peak_tflops": MFMA_PEAK_TFS[dt],
+                     "util": tfs / MFMA_PEAK_TFS[dt]}
+    return out or None
+
+
 def counter_traffic(kernel, dims, bytes_per_launch):
     """HBM bytes per launch from the committed PMC measurement of this kernel on
     this lattice (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's reading), or
@@ -369,6 +393,7 @@ def main():
         roofline = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
                     "bytes_per_launch": bpl, "us_per_launch": per_launch_s * 1e6}
+    dc_mfma = dc_mfma_util(kinfo, a.nrhs, 2 * a.nv, 2 * a.nv2 if a.levels == 3 else 2 * a.nv)
     ds = prof["dslash_f64"]
     dslash_step = None
     if ds[0]:
@@ -395,7 +420,7 @@ def main():
         "setup_s": float(np.median(setups)), "solve_s_per_rhs": float(np.median(solves)) / a.nrhs,
         "mg_iters": [s["iters"] for s in last], "mg_n_D": [s["n_D"] for s in last],
         "mg_n_Dc": [s["n_Dc"][1] for s in last], "true_res": true_res,
-        "roofline": roofline, "kernels": kinfo, "dslash_in_step": dslash_step,
+        "roofline": roofline, "kernels": kinfo, "dslash_in_step": dslash_step, "dc_mfma": dc_mfma,
     }
     if a.precision_report:
         result["precision_error"] = precision_report(ctx, torch, synthetic, dims, a.nv)
