@@ -117,7 +117,9 @@ def parse():
     ap.add_argument("--levels", type=int, default=2, choices=[2, 3],
                     help="3: a second coarsening with 2^4 aggregates (Sec. 5 three-level cycle)")
     ap.add_argument("--nv2", type=int, default=32, help="near-null vectors of the second coarsening")
-    ap.add_argument("--setup-iters", type=int, default=100)
+    ap.add_argument("--setup-iters", type=int, default=None,
+                    help="MR relaxation steps per near-null vector (default 50 for fewer than 8 rhs, "
+                         "100 for larger batches, whose setup cost is shared)")
     ap.add_argument("--nrhs", type=int, default=1)
     ap.add_argument("--setup-prec", default="f64", choices=["f64", "f32"],
                     help="arithmetic of the setup relaxation (the block QR is FP64 either way)")
@@ -138,7 +140,10 @@ def parse():
     ap.add_argument("--only-dslash", type=int, default=0, metavar="L",
                     help="only time Dslash (FP64, FP32) on L^4 plus a plain 1 GiB device copy "
                          "(the reference for hardware byte counters), then exit")
-    return ap.parse_args()
+    a = ap.parse_args()
+    if a.setup_iters is None:
+        a.setup_iters = 50 if a.nrhs < 8 else 100
+    return a
 
 
 def load_mcrit(dims, eps, seed):
@@ -170,7 +175,7 @@ def dslash_bandwidth(wdmg, synthetic, torch, dev, L, reps=20):
     precs = (("f64", "dslash_f64"), ("f32", "dslash_f32"), ("f16", "dslash_f16"), ("bf16", "dslash_bf16"))
     # both kernel forms forced, then the autotuner's pick
     forms = {}
-    for form in (0, 1):
+    for form in (0, 1, 2):
         ctx.set_tuning("dslash", form)
         for prec, key in precs:
             x = psi if prec == "f64" else psi.to(torch.complex64)
@@ -186,6 +191,7 @@ def dslash_bandwidth(wdmg, synthetic, torch, dev, L, reps=20):
                                            "GB_s": DSLASH_BYTES[prec] * units / n / sec / 1e9}
     ctx.set_tuning("dslash", None)
     out["forms"] = {"lattice": f"{L}^4", "form0": "one thread per site", "form1": "one wave per direction",
+                    "form2": "one wave per direction, registers capped for 4 waves per SIMD",
                     **forms}
     for prec, key in precs:
         x = psi if prec == "f64" else psi.to(torch.complex64)

@@ -216,7 +216,8 @@ int wdmg_solve_bicgstab(wdmg_ctx* ctx, void* x, const void* b, int nrhs, double 
  * batch size (HIP events, a few launches each, on the context's stream) and
  * keeps the fastest for the context's lifetime; a fixed value forces a form.
  *   WDMG_TUNE_DSLASH: 0 one thread per site, 1 one wave per direction with
- *                     the four partial sums added in LDS. */
+ *                     the four partial sums added in LDS, 2 form 1 with its
+ *                     registers capped so that four waves fit per SIMD. */
 enum { WDMG_TUNE_AUTO = -1, WDMG_TUNE_DSLASH = 0, WDMG_TUNE_COUNT };
 int wdmg_set_tuning(wdmg_ctx* ctx, int key, int value);
 /* Current choice for key (WDMG_TUNE_AUTO until tuned) for precision prec

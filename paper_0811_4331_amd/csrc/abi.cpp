@@ -589,7 +589,7 @@ int wdmg_solve_bicgstab(wdmg_ctx* c, void* x, const void* b, int nrhs, double to
 int wdmg_set_tuning(wdmg_ctx* c, int key, int value) {
   return guarded(c, [&]() {
     if (key != WDMG_TUNE_DSLASH) throw Error(WDMG_ERR_ARG, "unknown tuning key");
-    if (value != WDMG_TUNE_AUTO && value != 0 && value != 1) throw Error(WDMG_ERR_ARG, "bad tuning value");
+    if (value != WDMG_TUNE_AUTO && (value < 0 || value > 2)) throw Error(WDMG_ERR_ARG, "bad tuning value");
     c->tune_force[key] = value;
     return WDMG_OK;
   });

@@ -867,6 +867,13 @@ void update2_batch(Ctx& c, cx<R>* x, const cx<R>* u, cx<R>* r, const cx<R>* v, s
   WDMG_HIP(hipGetLastError());
 }
 
+void step_alpha_fin(Ctx& c, const double* parts, int nparts, int nrhs, double scale, int slot) {
+  const StepAlphaBatchOp<double> op{nullptr, nullptr, 0, scale, c.dsc, slot};
+  hipLaunchKernelGGL((k_reduce_b_fin<StepAlphaBatchOp<double>>), dim3(nrhs), dim3(TPB), 0, c.stream, op, nparts,
+                     parts);
+  WDMG_HIP(hipGetLastError());
+}
+
 template <typename H>
 void step_alpha_half(Ctx& c, HF a, HF b, int nrhs, double scale, int slot) {
   const size_t n = c.g0.vol;

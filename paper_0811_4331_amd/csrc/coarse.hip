@@ -277,6 +277,24 @@ __global__ __launch_bounds__(256) void k_coarse_build(Side side, AggGeom a, cons
 // ---- application ----------------------------------------------------------------
 // One workgroup of nine waves per (coarse site, rhs); wave d applies block d
 // (lane = row), and the nine partial rows are summed in a fixed order.
+// acc += sum_j blk[j n2] v[j]: one row of a column-major block times a
+// vector, in column order, with the loads of 8 columns issued together.
+template <typename R>
+__device__ __forceinline__ void block_row_madd(const cx<R>* __restrict__ blk, int n2, const cx<R>* v, cx<R>& acc) {
+  int jj = 0;
+  for (; jj + 8 <= n2; jj += 8) {
+    cx<R> a[8], b[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      a[u] = blk[(size_t)(jj + u) * n2];
+      b[u] = v[jj + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) cmadd(acc, a[u], b[u]);
+  }
+  for (; jj < n2; ++jj) cmadd(acc, blk[(size_t)jj * n2], v[jj]);
+}
+
 template <typename R>
 __global__ __launch_bounds__(576) void k_coarse_apply(Geom g, int n2, const cx<R>* __restrict__ Dc,
                                                       const cx<R>* __restrict__ in, cx<R>* __restrict__ out,
@@ -296,9 +314,7 @@ __global__ __launch_bounds__(576) void k_coarse_apply(Geom g, int n2, const cx<R
   }
   cx<R> acc = mk<R>(0, 0);
   if (lane < n2) {
-    const cx<R>* blk = Dc + ((size_t)s * 9 + d) * n2 * n2 + lane;
-    const cx<R>* v = in + (size_t)nb * n2;
-    for (int j = 0; j < n2; ++j) cmadd(acc, blk[(size_t)j * n2], v[j]);
+    block_row_madd(Dc + ((size_t)s * 9 + d) * n2 * n2 + lane, n2, in + (size_t)nb * n2, acc);
   }
   part[d][lane] = acc;
   __syncthreads();
@@ -351,8 +367,11 @@ constexpr int kMfma64Lds = 4096;  // doubles of LDS for the group partials
 
 // All right-hand sides of the batch (up to kMaxRhs = 4 tiles of 16) are
 // done by one workgroup, so each operand chunk of A is loaded once and
-// multiplied into every tile's accumulator.
+// multiplied into every tile's accumulator.  NT >= ceil(nrhs / 16) tiles are
+// held in registers; instantiating the smallest NT keeps the unused
+// accumulators out of the register budget.
 constexpr int kMaxTiles = kMaxRhs / 16;
+template <int NT>
 __device__ __forceinline__ void apply_site_mfma64(const Geom& g, int n2, int nrhs, int s,
                                                   const cx<double>* __restrict__ Dc, const cx<double>* in,
                                                   cx<double>* out, double* lds) {
@@ -367,10 +386,12 @@ __device__ __forceinline__ void apply_site_mfma64(const Geom& g, int n2, int nrh
   const int kl = l >> 4;
   int c[4];
   coords_of(g, s, c);
-  doublex4 acc[kMaxTiles];
+  doublex4 acc[NT];
 #pragma unroll
-  for (int t = 0; t < kMaxTiles; ++t) acc[t] = doublex4{0.0, 0.0, 0.0, 0.0};
-  constexpr int KC = 8;  // MFMA steps whose operands are loaded together
+  for (int t = 0; t < NT; ++t) acc[t] = doublex4{0.0, 0.0, 0.0, 0.0};
+  // MFMA steps whose operands are loaded together (fewer when more tiles
+  // hold accumulators, to stay within the register budget)
+  constexpr int KC = NT == 1 ? 8 : 4;
   for (int d = grp; d < 9; d += ng) {
     const int nb = d == 8 ? s : ((d & 1) ? nbr_bwd(g, s, c, d >> 1) : nbr_fwd(g, s, c, d >> 1));
     const double* blk = reinterpret_cast<const double*>(Dc + ((size_t)s * 9 + d) * n2 * n2);
@@ -386,7 +407,7 @@ __device__ __forceinline__ void apply_site_mfma64(const Geom& g, int n2, int nrh
         }
       }
 #pragma unroll
-      for (int tt = 0; tt < kMaxTiles; ++tt) {
+      for (int tt = 0; tt < NT; ++tt) {
         if (tt >= ntile) break;
         const int q = tt * 16 + (l & 15);
         const bool qok = q < nrhs;
@@ -405,7 +426,7 @@ __device__ __forceinline__ void apply_site_mfma64(const Geom& g, int n2, int nrh
   }
   // groups 1.. hand their partial tiles to group 0, one rhs tile at a time
 #pragma unroll
-  for (int tt = 0; tt < kMaxTiles; ++tt) {
+  for (int tt = 0; tt < NT; ++tt) {
     if (tt >= ntile) break;
     if (grp > 0 && grp < ng) {
       double* dst = lds + ((size_t)((grp - 1) * nrt + rt) * 64 + l) * 4;
@@ -448,9 +469,7 @@ __device__ __forceinline__ void apply_site_valu1(const Geom& g, int n2, int s, c
       coords_of(g, s, c);
       nb = (d & 1) ? nbr_bwd(g, s, c, d >> 1) : nbr_fwd(g, s, c, d >> 1);
     }
-    const cx<double>* blk = Dc + ((size_t)s * 9 + d) * n2 * n2 + lane;
-    const cx<double>* v = in + (size_t)nb * n2;
-    for (int jj = 0; jj < n2; ++jj) cmadd(acc, blk[(size_t)jj * n2], v[jj]);
+    block_row_madd(Dc + ((size_t)s * 9 + d) * n2 * n2 + lane, n2, in + (size_t)nb * n2, acc);
   }
   if (d < 9) {
     lds[2 * (d * 64 + lane)] = acc.re;
@@ -475,6 +494,7 @@ __device__ __forceinline__ void copy_site(int n2, size_t fs, int s, int q0, int 
   }
 }
 
+template <int NT>
 __global__ __launch_bounds__(1024) void k_coarse_apply_mfma64(Geom g, int n2, int nrhs,
                                                               const cx<double>* __restrict__ Dc,
                                                               const cx<double>* __restrict__ in,
@@ -483,7 +503,7 @@ __global__ __launch_bounds__(1024) void k_coarse_apply_mfma64(Geom g, int n2, in
   __shared__ double lds[kMfma64Lds];
   const int s = blockIdx.x;
   if (copy) copy_site(n2, (size_t)g.vol * n2, s, 0, nrhs, in, copy);
-  apply_site_mfma64(g, n2, nrhs, s, Dc, in, out, lds);
+  apply_site_mfma64<NT>(g, n2, nrhs, s, Dc, in, out, lds);
 }
 
 // FP32: v_mfma_f32_32x32x2f32; tile = 32 real rows x 32 rhs.
@@ -779,7 +799,7 @@ __global__ __launch_bounds__(256) void k_cgcr_init(const cx<double>* __restrict_
 }
 
 // K1: blocks (G1, rhs tiles of 16), one wave per 16 real rows of a site.
-template <bool VALU>
+template <bool VALU, int NT>
 __global__ __launch_bounds__(1024) void k_cgcr_apply(Geom g, int n2, int nrhs, int j, int vals,
                                                     const cx<double>* __restrict__ Dc, const cx<double>* r,
                                                     const cx<double>* Wb, cx<double>* w, cx<double>* z,
@@ -797,8 +817,13 @@ __global__ __launch_bounds__(1024) void k_cgcr_apply(Geom g, int n2, int nrhs, i
     if (VALU)
       apply_site_valu1(g, n2, s, Dc, r, w, lds);
     else
-      apply_site_mfma64(g, n2, nrhs, s, Dc, r, w, lds);
-    for (int qq = wave; qq < nq; qq += nw) {
+      apply_site_mfma64<NT>(g, n2, nrhs, s, Dc, r, w, lds);
+    // Dot-product tasks (rhs qq, basis vector i < j) and (qq, the four
+    // norms) spread over the waves; a task keeps its wave for every site of
+    // the loop, so each accumulator has a single writer.
+    const int per = j + 1;
+    for (int t = wave; t < nq * per; t += nw) {
+      const int qq = t / per, i = t % per;
       const size_t o = (size_t)(q0 + qq) * fs + (size_t)s * n2 + lane;
       cx<double> wv = mk(0.0, 0.0), rv = mk(0.0, 0.0);
       if (lane < n2) {
@@ -806,7 +831,7 @@ __global__ __launch_bounds__(1024) void k_cgcr_apply(Geom g, int n2, int nrhs, i
         rv = r[o];
       }
       double* aq = acc + qq * vals;
-      for (int i = 0; i < j; ++i) {
+      if (i < j) {
         cx<double> u = mk(0.0, 0.0);
         if (lane < n2) u = Wb[(size_t)i * bs + o];
         const double c_re = wave_sum(u.re * wv.re + u.im * wv.im);
@@ -819,16 +844,17 @@ __global__ __launch_bounds__(1024) void k_cgcr_apply(Geom g, int n2, int nrhs, i
           aq[2 * j + 2 * i] += d_re;
           aq[2 * j + 2 * i + 1] += d_im;
         }
-      }
-      const double ww = wave_sum(wv.re * wv.re + wv.im * wv.im);
-      const double wr_re = wave_sum(wv.re * rv.re + wv.im * rv.im);
-      const double wr_im = wave_sum(wv.re * rv.im - wv.im * rv.re);
-      const double rr = wave_sum(rv.re * rv.re + rv.im * rv.im);
-      if (lane == 0) {
-        aq[4 * j] += ww;
-        aq[4 * j + 1] += wr_re;
-        aq[4 * j + 2] += wr_im;
-        aq[4 * j + 3] += rr;
+      } else {
+        const double ww = wave_sum(wv.re * wv.re + wv.im * wv.im);
+        const double wr_re = wave_sum(wv.re * rv.re + wv.im * rv.im);
+        const double wr_im = wave_sum(wv.re * rv.im - wv.im * rv.re);
+        const double rr = wave_sum(rv.re * rv.re + rv.im * rv.im);
+        if (lane == 0) {
+          aq[4 * j] += ww;
+          aq[4 * j + 1] += wr_re;
+          aq[4 * j + 2] += wr_im;
+          aq[4 * j + 3] += rr;
+        }
       }
     }
     __syncthreads();
@@ -967,8 +993,13 @@ void coarse_apply(Ctx& c, const Level& cl, const cx<R>* Dc, cx<R>* out, const cx
     if constexpr (sizeof(R) == 8) {
       ProfScope ps(c, WDMG_K_DC_MFMA_F64, (long long)cl.nsite * nrhs);
       const int waves = mfma64_row_tiles(n2) * mfma64_groups(n2);
-      hipLaunchKernelGGL(k_coarse_apply_mfma64, dim3(cl.nsite), dim3(64 * waves), 0, c.stream,
-                         cl.g, n2, nrhs, Dc, in, out, copy);
+      const dim3 grid(cl.nsite), block(64 * waves);
+      switch ((nrhs + 15) / 16) {
+        case 1: hipLaunchKernelGGL(k_coarse_apply_mfma64<1>, grid, block, 0, c.stream, cl.g, n2, nrhs, Dc, in, out, copy); break;
+        case 2: hipLaunchKernelGGL(k_coarse_apply_mfma64<2>, grid, block, 0, c.stream, cl.g, n2, nrhs, Dc, in, out, copy); break;
+        case 3: hipLaunchKernelGGL(k_coarse_apply_mfma64<3>, grid, block, 0, c.stream, cl.g, n2, nrhs, Dc, in, out, copy); break;
+        default: hipLaunchKernelGGL(k_coarse_apply_mfma64<kMaxTiles>, grid, block, 0, c.stream, cl.g, n2, nrhs, Dc, in, out, copy); break;
+      }
     } else {
       ProfScope ps(c, WDMG_K_DC_MFMA_F32, (long long)cl.nsite * nrhs);
       const int waves = (2 * n2 + 31) / 32;
@@ -1048,10 +1079,12 @@ void coarsest_gcr(Ctx& c, Level& L, cx<double>* x, const cx<double>* b, int nrhs
     throw Error(WDMG_ERR_ARG, "coarse_restart too long for this many right-hand sides (LDS)");
   static bool lds_attr = false;
   if (!lds_attr) {  // K1 keeps nrhs x (4 j + 4) partial sums in LDS
-    WDMG_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cgcr_apply<false>),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024));
-    WDMG_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cgcr_apply<true>),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024));
+    const void* fns[] = {reinterpret_cast<const void*>(&k_cgcr_apply<true, 1>),
+                         reinterpret_cast<const void*>(&k_cgcr_apply<false, 1>),
+                         reinterpret_cast<const void*>(&k_cgcr_apply<false, 2>),
+                         reinterpret_cast<const void*>(&k_cgcr_apply<false, 3>),
+                         reinterpret_cast<const void*>(&k_cgcr_apply<false, kMaxTiles>)};
+    for (const void* f : fns) WDMG_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024));
     lds_attr = true;
   }
   hipLaunchKernelGGL(k_cgcr_init, dim3(nrhs), dim3(256), 0, c.stream, b, x, L.w64[1], n, tol, S, c.dsc + S_ERR);
@@ -1076,12 +1109,21 @@ void coarsest_gcr(Ctx& c, Level& L, cx<double>* x, const cx<double>* b, int nrhs
     const int vals = 4 * j + 4;
     {
       ProfScope ps(c, WDMG_K_COARSE_GCR, (long long)L.nsite * nrhs);
-      if (nrhs == 1)
-        hipLaunchKernelGGL(k_cgcr_apply<true>, dim3(g1), dim3(576), (size_t)vals * sizeof(double), c.stream, L.g, n2,
-                           nrhs, j, vals, L.Dc64, r, L.basisW, w, z, L.cpart);
-      else
-        hipLaunchKernelGGL(k_cgcr_apply<false>, dim3(g1), dim3(64 * waves), (size_t)nrhs * vals * sizeof(double),
-                           c.stream, L.g, n2, nrhs, j, vals, L.Dc64, r, L.basisW, w, z, L.cpart);
+      const size_t lds = (size_t)nrhs * vals * sizeof(double);
+#define WDMG_K1(VALU, NT, THREADS)                                                                              \
+  hipLaunchKernelGGL((k_cgcr_apply<VALU, NT>), dim3(g1), dim3(THREADS), lds, c.stream, L.g, n2, nrhs, j, vals, \
+                     L.Dc64, r, L.basisW, w, z, L.cpart)
+      if (nrhs == 1) {
+        WDMG_K1(true, 1, 576);
+      } else {
+        switch ((nrhs + 15) / 16) {
+          case 1: WDMG_K1(false, 1, 64 * waves); break;
+          case 2: WDMG_K1(false, 2, 64 * waves); break;
+          case 3: WDMG_K1(false, 3, 64 * waves); break;
+          default: WDMG_K1(false, kMaxTiles, 64 * waves); break;
+        }
+      }
+#undef WDMG_K1
       WDMG_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(k_cgcr_coef, dim3(nrhs), dim3(1024), (size_t)(vals + 1) * sizeof(double), c.stream, j, vals,

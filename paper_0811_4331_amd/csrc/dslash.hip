@@ -8,8 +8,10 @@
 // links U_t(x) at t = Lt-1, so it reaches both hop directions.
 //
 // Layout: fields in 64-site blocks, links as their first two rows (see
-// fine_field.h).  One thread per (site, right-hand side); workgroups are
-// remapped so spatially adjacent tiles share an XCD's L2.
+// fine_field.h).  Three forms with the same result: one thread per (site,
+// right-hand side); one wave per direction; the latter with its registers
+// capped for a fourth wave per SIMD.  Workgroups are remapped so spatially
+// adjacent tiles share an XCD's L2.
 #include "half_field.h"
 #include "internal.h"
 #include "wilson_spin.h"
@@ -114,8 +116,38 @@ __device__ __forceinline__ void batch_block(int nsb, int nrhs, int& sb, int& rhs
   rhs = local % nrhs;
 }
 
-template <class IO, typename R = typename IO::T>
-__global__ __launch_bounds__(kDslashThreads) void k_dslash(Geom g, IO io, R diag, int tneg, int nsb, int nrhs) {
+// MR step-size partial sums of one wave (Sec. 3 smoother): Re and Im of
+// <out, in> and |out|^2 over the wave's sites, where `in` is the operator's
+// input at the site itself (already loaded for the mass term).  Lanes of
+// sites outside the lattice pass live = false.  Lane 0 writes the three sums
+// to dots[(rhs * nparts + part) * 3 + k]; the fixed slot per wave keeps the
+// result independent of scheduling.
+template <typename R>
+__device__ __forceinline__ void wave_dots(bool live, const cx<R> (&out)[12], const cx<R> (&in)[12], double* dots,
+                                          size_t slot) {
+  double d0 = 0.0, d1 = 0.0, d2 = 0.0;
+  if (live) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      const double ore = out[k].re, oim = out[k].im, ire = in[k].re, iim = in[k].im;
+      d0 += ore * ire + oim * iim;
+      d1 += ore * iim - oim * ire;
+      d2 += ore * ore + oim * oim;
+    }
+  }
+  d0 = wave_sum(d0);
+  d1 = wave_sum(d1);
+  d2 = wave_sum(d2);
+  if ((threadIdx.x & 63) == 0) {
+    dots[slot * 3 + 0] = d0;
+    dots[slot * 3 + 1] = d1;
+    dots[slot * 3 + 2] = d2;
+  }
+}
+
+template <class IO, bool DOTS, typename R = typename IO::T>
+__global__ __launch_bounds__(kDslashThreads) void k_dslash(Geom g, IO io, R diag, int tneg, int nsb, int nrhs,
+                                                           double* dots) {
   int sb, rhs;
   batch_block(nsb, nrhs, sb, rhs);
   const int s = sb * kDslashThreads + threadIdx.x;
@@ -123,39 +155,41 @@ __global__ __launch_bounds__(kDslashThreads) void k_dslash(Geom g, IO io, R diag
   cx<R> acc[12];
 #pragma unroll
   for (int k = 0; k < 12; ++k) acc[k] = mk<R>(0, 0);
-  if (s >= g.vol) {
-    if (s < g.vpad) io.store(s, acc);
-    return;
-  }
-  int c[4];
-  coords_of(g, s, c);
-  const bool tlast = tneg && c[3] == g.L[3] - 1, tfirst = tneg && c[3] == 0;
-  {
-    const int f = nbr_fwd(g, s, c, 0), b = nbr_bwd(g, s, c, 0);
-    hop<0, +1>(io, f, s, false, acc);
-    hop<0, -1>(io, b, b, false, acc);
-  }
-  {
-    const int f = nbr_fwd(g, s, c, 1), b = nbr_bwd(g, s, c, 1);
-    hop<1, +1>(io, f, s, false, acc);
-    hop<1, -1>(io, b, b, false, acc);
-  }
-  {
-    const int f = nbr_fwd(g, s, c, 2), b = nbr_bwd(g, s, c, 2);
-    hop<2, +1>(io, f, s, false, acc);
-    hop<2, -1>(io, b, b, false, acc);
-  }
-  {
-    const int f = nbr_fwd(g, s, c, 3), b = nbr_bwd(g, s, c, 3);
-    hop<3, +1>(io, f, s, tlast, acc);
-    hop<3, -1>(io, b, b, tfirst, acc);
-  }
-  const R half = (R)0.5;
+  const bool live = s < g.vol;
   cx<R> p[12];
-  io.spinor(s, p);
+  if (live) {
+    int c[4];
+    coords_of(g, s, c);
+    const bool tlast = tneg && c[3] == g.L[3] - 1, tfirst = tneg && c[3] == 0;
+    {
+      const int f = nbr_fwd(g, s, c, 0), b = nbr_bwd(g, s, c, 0);
+      hop<0, +1>(io, f, s, false, acc);
+      hop<0, -1>(io, b, b, false, acc);
+    }
+    {
+      const int f = nbr_fwd(g, s, c, 1), b = nbr_bwd(g, s, c, 1);
+      hop<1, +1>(io, f, s, false, acc);
+      hop<1, -1>(io, b, b, false, acc);
+    }
+    {
+      const int f = nbr_fwd(g, s, c, 2), b = nbr_bwd(g, s, c, 2);
+      hop<2, +1>(io, f, s, false, acc);
+      hop<2, -1>(io, b, b, false, acc);
+    }
+    {
+      const int f = nbr_fwd(g, s, c, 3), b = nbr_bwd(g, s, c, 3);
+      hop<3, +1>(io, f, s, tlast, acc);
+      hop<3, -1>(io, b, b, tfirst, acc);
+    }
+    const R half = (R)0.5;
+    io.spinor(s, p);
 #pragma unroll
-  for (int k = 0; k < 12; ++k) acc[k] = mk<R>(diag * p[k].re - half * acc[k].re, diag * p[k].im - half * acc[k].im);
-  io.store(s, acc);
+    for (int k = 0; k < 12; ++k) acc[k] = mk<R>(diag * p[k].re - half * acc[k].re, diag * p[k].im - half * acc[k].im);
+  }
+  if (s < g.vpad) io.store(s, acc);  // padding sites: zeros
+  if constexpr (DOTS)
+    wave_dots(live, acc, p, dots,
+              (size_t)rhs * nsb * (kDslashThreads / 64) + (size_t)sb * (kDslashThreads / 64) + (threadIdx.x >> 6));
 }
 
 // Direction-split form: a workgroup of four waves covers one 64-site block;
@@ -175,8 +209,13 @@ __device__ __forceinline__ void hops_mu(const IO& io, const Geom& g, int s, cons
 
 constexpr int kDs4Sites = 64;
 
-template <class IO, typename R = typename IO::T>
-__global__ __launch_bounds__(256) void k_dslash4(Geom g, IO io, R diag, int tneg, int nsb, int nrhs) {
+// MINW: the fewest waves per SIMD the register allocation must allow (1: no
+// limit).  FP64 needs 132 registers unconstrained (3 waves per SIMD); with
+// MINW = 4 it fits in 128 with one spilled register.
+template <class IO, bool DOTS, int MINW, typename R = typename IO::T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MINW))) void k_dslash4(Geom g, IO io, R diag,
+                                                                                            int tneg, int nsb,
+                                                                                            int nrhs, double* dots) {
   __shared__ cx<R> part[3][12][kDs4Sites];
   int sb, rhs;
   batch_block(nsb, nrhs, sb, rhs);
@@ -202,47 +241,70 @@ __global__ __launch_bounds__(256) void k_dslash4(Geom g, IO io, R diag, int tneg
     for (int k = 0; k < 12; ++k) part[mu - 1][k][lane] = acc[k];
   }
   __syncthreads();
+  // the grid covers vpad sites in whole 64-site blocks, so the test below is
+  // uniform over the wave
   if (mu != 0 || s >= g.vpad) return;
-  if (!live) {
-    io.store(s, acc);  // padding site: zeros
-    return;
-  }
-#pragma unroll
-  for (int k = 0; k < 12; ++k) acc[k] = acc[k] + part[0][k][lane] + part[1][k][lane] + part[2][k][lane];
-  const R half = (R)0.5;
   cx<R> p[12];
-  io.spinor(s, p);
+  if (live) {
 #pragma unroll
-  for (int k = 0; k < 12; ++k) acc[k] = mk<R>(diag * p[k].re - half * acc[k].re, diag * p[k].im - half * acc[k].im);
-  io.store(s, acc);
+    for (int k = 0; k < 12; ++k) acc[k] = acc[k] + part[0][k][lane] + part[1][k][lane] + part[2][k][lane];
+    const R half = (R)0.5;
+    io.spinor(s, p);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = mk<R>(diag * p[k].re - half * acc[k].re, diag * p[k].im - half * acc[k].im);
+  }
+  io.store(s, acc);  // padding sites: zeros
+  if constexpr (DOTS) wave_dots(live, acc, p, dots, (size_t)rhs * nsb + sb);
+}
+
+// Slots of MR partial sums per right-hand side written by a fused launch.
+int dslash_parts(const Geom& g, int variant) {
+  return variant != 0 ? g.vpad / kDs4Sites : (g.vpad / kDslashThreads + (g.vpad % kDslashThreads != 0)) * (kDslashThreads / 64);
 }
 
 template <class IO>
-void run_dslash(Ctx& c, const IO& io, int nrhs, int variant) {
+void run_dslash(Ctx& c, const IO& io, int nrhs, int variant, double* dots = nullptr) {
   const Geom& g = c.g0;
   const int tneg = c.t_bc < 0 ? 1 : 0;
   using R = typename IO::T;
-  if (variant == 1) {
+  if (variant == 1 || variant == 2) {
     const unsigned gx = g.vpad / kDs4Sites;
-    hipLaunchKernelGGL((k_dslash4<IO>), dim3(gx * nrhs), dim3(256), 0, c.stream, g, io, (R)(4.0 + c.mass), tneg,
-                       (int)gx, nrhs);
+    const dim3 grid(gx * nrhs), block(256);
+    const R diag = (R)(4.0 + c.mass);
+    if (variant == 1) {
+      if (dots)
+        hipLaunchKernelGGL((k_dslash4<IO, true, 1>), grid, block, 0, c.stream, g, io, diag, tneg, (int)gx, nrhs, dots);
+      else
+        hipLaunchKernelGGL((k_dslash4<IO, false, 1>), grid, block, 0, c.stream, g, io, diag, tneg, (int)gx, nrhs, dots);
+    } else {
+      if (dots)
+        hipLaunchKernelGGL((k_dslash4<IO, true, 4>), grid, block, 0, c.stream, g, io, diag, tneg, (int)gx, nrhs, dots);
+      else
+        hipLaunchKernelGGL((k_dslash4<IO, false, 4>), grid, block, 0, c.stream, g, io, diag, tneg, (int)gx, nrhs, dots);
+    }
   } else {
     const unsigned gx = g.vpad / kDslashThreads + (g.vpad % kDslashThreads != 0);
-    hipLaunchKernelGGL((k_dslash<IO>), dim3(gx * nrhs), dim3(kDslashThreads), 0, c.stream, g, io,
-                       (R)(4.0 + c.mass), tneg, (int)gx, nrhs);
+    if (dots)
+      hipLaunchKernelGGL((k_dslash<IO, true>), dim3(gx * nrhs), dim3(kDslashThreads), 0, c.stream, g, io,
+                         (R)(4.0 + c.mass), tneg, (int)gx, nrhs, dots);
+    else
+      hipLaunchKernelGGL((k_dslash<IO, false>), dim3(gx * nrhs), dim3(kDslashThreads), 0, c.stream, g, io,
+                         (R)(4.0 + c.mass), tneg, (int)gx, nrhs, dots);
   }
   WDMG_HIP(hipGetLastError());
 }
 
-// Autotuner: times both forms (HIP events, 3 launches each after one warm-up
-// launch) on the caller's buffers -- the operator has no side effects
-// besides writing `out` -- and returns the faster.
+// Autotuner: times the three forms (HIP events, 3 launches each after one
+// warm-up launch) on the caller's buffers -- the operator has no side effects
+// besides writing `out` -- and returns the fastest (form 1 on ties).
+constexpr int kDslashForms = 3;
+
 template <class IO>
 int tune_dslash(Ctx& c, const IO& io, int nrhs) {
   hipEvent_t ev[3];
   for (auto& e : ev) WDMG_HIP(hipEventCreate(&e));
-  float ms[2] = {0.f, 0.f};
-  for (int v = 0; v < 2; ++v) {
+  float ms[kDslashForms] = {};
+  for (int v = 0; v < kDslashForms; ++v) {
     run_dslash(c, io, nrhs, v);
     WDMG_HIP(hipEventRecord(ev[0], c.stream));
     for (int i = 0; i < 3; ++i) run_dslash(c, io, nrhs, v);
@@ -251,11 +313,16 @@ int tune_dslash(Ctx& c, const IO& io, int nrhs) {
     WDMG_HIP(hipEventElapsedTime(&ms[v], ev[0], ev[1]));
   }
   for (auto& e : ev) (void)hipEventDestroy(e);
-  return ms[1] <= ms[0] ? 1 : 0;
+  int best = 1;
+  for (int v = 0; v < kDslashForms; ++v)
+    if (ms[v] < ms[best]) best = v;
+  return best;
 }
 
+// Runs the operator in the tuned form; with `dots` the launch also writes the
+// MR partial sums and the return value is the number of slots per rhs.
 template <class IO>
-void launch_dslash(Ctx& c, const IO& io, int nrhs, int prof_id, int prec_index) {
+int launch_dslash(Ctx& c, const IO& io, int nrhs, int prof_id, int prec_index, double* dots = nullptr) {
   int v = c.tune_force[WDMG_TUNE_DSLASH];
   if (v < 0) {
     signed char& slot = c.tune_dslash[prec_index][nrhs < kMaxRhs ? nrhs : kMaxRhs];
@@ -263,8 +330,9 @@ void launch_dslash(Ctx& c, const IO& io, int nrhs, int prof_id, int prec_index) 
     v = slot < 0 ? 1 : slot;
   }
   ProfScope ps(c, prof_id, (long long)c.g0.vol * nrhs);
-  run_dslash(c, io, nrhs, v);
+  run_dslash(c, io, nrhs, v, dots);
   c.n_D += nrhs;
+  return dslash_parts(c.g0, v);
 }
 
 }  // namespace
@@ -293,9 +361,54 @@ void dslash_h(Ctx& c, HF out, HF in, int nrhs) {
   launch_dslash(c, io, nrhs, half_kind<H>() == WDMG_F16 ? WDMG_K_DSLASH_F16 : WDMG_K_DSLASH_BF16, half_kind<H>());
 }
 
+double* dots_buffer(Ctx& c, int nrhs) {
+  const size_t need = ((size_t)c.g0.vpad / 64 + 2) * 3 * (size_t)nrhs;
+  if (need > c.dots_cap) {
+    if (c.capturing) throw Error(WDMG_ERR_ARG, "MR partial-sum buffer too small inside a graph capture");
+    WDMG_HIP(hipStreamSynchronize(c.stream));
+    dev_free(c, c.dots);
+    c.dots = static_cast<double*>(dev_alloc(c, need * sizeof(double)));
+    c.dots_cap = need;
+  }
+  return c.dots;
+}
+
+template <typename R>
+void dslash_mr(Ctx& c, cx<R>* out, const cx<R>* in, int nrhs, double scale, int slot) {
+  FullIO<R> io;
+  io.in = in;
+  io.out = out;
+  if constexpr (sizeof(R) == 8)
+    io.U = c.U64;
+  else
+    io.U = c.U32;
+  double* d = dots_buffer(c, nrhs);
+  const int nparts = launch_dslash(c, io, nrhs, sizeof(R) == 8 ? WDMG_K_DSLASH_F64 : WDMG_K_DSLASH_F32,
+                                   sizeof(R) == 8 ? WDMG_F64 : WDMG_F32, d);
+  step_alpha_fin(c, d, nparts, nrhs, scale, slot);
+}
+
+template <typename H>
+void dslash_h_mr(Ctx& c, HF out, HF in, int nrhs, double scale, int slot) {
+  HalfIO<H> io;
+  io.in = static_cast<const cxh<H>*>(in.v);
+  io.isc = in.s;
+  io.out = static_cast<cxh<H>*>(out.v);
+  io.osc = out.s;
+  io.U = static_cast<const cxh<H>*>(u16(c, half_kind<H>()));
+  double* d = dots_buffer(c, nrhs);
+  const int nparts = launch_dslash(c, io, nrhs, half_kind<H>() == WDMG_F16 ? WDMG_K_DSLASH_F16 : WDMG_K_DSLASH_BF16,
+                                   half_kind<H>(), d);
+  step_alpha_fin(c, d, nparts, nrhs, scale, slot);
+}
+
 template void dslash<double>(Ctx&, cx<double>*, const cx<double>*, int);
 template void dslash<float>(Ctx&, cx<float>*, const cx<float>*, int);
 template void dslash_h<f16_t>(Ctx&, HF, HF, int);
 template void dslash_h<bf16_t>(Ctx&, HF, HF, int);
+template void dslash_mr<double>(Ctx&, cx<double>*, const cx<double>*, int, double, int);
+template void dslash_mr<float>(Ctx&, cx<float>*, const cx<float>*, int, double, int);
+template void dslash_h_mr<f16_t>(Ctx&, HF, HF, int, double, int);
+template void dslash_h_mr<bf16_t>(Ctx&, HF, HF, int, double, int);
 
 }  // namespace wdmg

@@ -167,6 +167,8 @@ struct Ctx {
 
   double* dsc = nullptr;        // device scalars (S_TOTAL doubles)
   double* partials = nullptr;   // reduction partials
+  double* dots = nullptr;       // MR partial sums written by the fused Wilson operator
+  size_t dots_cap = 0;          // its capacity in doubles
 
   double* hsc = nullptr;        // pinned host mirror of a few scalars
   double* hring = nullptr;      // pinned ring [kRing][kMaxRhs] for lagged residual checks (host view)
@@ -278,6 +280,19 @@ void dslash(Ctx& c, cx<R>* out, const cx<R>* in, int nrhs);
 // The same on 16-bit fields and links, FP32 arithmetic.
 template <typename H>
 void dslash_h(Ctx& c, HF out, HF in, int nrhs);
+// Fused MR step (Sec. 3): out = D in, and for every rhs q
+// dsc[slot + 2q] = scale <out_q, in_q> / <out_q, out_q> (0 if the norm is 0),
+// from partial sums the operator launch writes per wave.
+template <typename R>
+void dslash_mr(Ctx& c, cx<R>* out, const cx<R>* in, int nrhs, double scale, int slot);
+template <typename H>
+void dslash_h_mr(Ctx& c, HF out, HF in, int nrhs, double scale, int slot);
+// The partial-sum buffer of the fused operator, grown to nrhs right-hand
+// sides (never inside a graph capture).
+double* dots_buffer(Ctx& c, int nrhs);
+// dsc[slot + 2q] = scale (p0 + i p1) / p2 from nparts triples per rhs q
+// (parts[(q * nparts + j) * 3 + k]), summed in a fixed order.
+void step_alpha_fin(Ctx& c, const double* parts, int nparts, int nrhs, double scale, int slot);
 
 // BLAS-1 and reductions (blas.hip).  Vectors are flat arrays of n complex.
 template <typename R> void zero(Ctx& c, cx<R>* x, size_t n);

@@ -230,6 +230,7 @@ void ensure_mg_work(Ctx& c, int nrhs, int prec) {
   // the coarsest solve runs in FP64 whatever the V-cycle precision
   ensure_work<double>(c, c.nlevels - 1, nrhs);
   ensure_coarsest_basis(c, nrhs);
+  dots_buffer(c, nrhs);
 }
 
 // ---------------------------------------------------------------------------
@@ -239,8 +240,12 @@ template <typename R>
 void mr(Ctx& c, int l, cx<R>* x, cx<R>* r, cx<R>* p, int nrhs, int iters, double omega) {
   const size_t n = c.lev[l].n;
   for (int it = 0; it < iters; ++it) {
-    apply_op<R>(c, l, p, r, nrhs);
-    step_alpha_batch<R>(c, p, r, n, n, nrhs, omega, S_BATCH);
+    if (l == 0) {
+      dslash_mr<R>(c, p, r, nrhs, omega, S_BATCH);
+    } else {
+      apply_op<R>(c, l, p, r, nrhs);
+      step_alpha_batch<R>(c, p, r, n, n, nrhs, omega, S_BATCH);
+    }
     update2_batch<R>(c, x, r, r, p, n, n, nrhs, S_BATCH);
   }
 }
@@ -348,8 +353,7 @@ void ensure_work_h(Ctx& c, int nrhs) {
 template <typename H>
 void mr_h(Ctx& c, HF x, HF r, HF p, int nrhs, int iters, double omega) {
   for (int it = 0; it < iters; ++it) {
-    dslash_h<H>(c, p, r, nrhs);
-    step_alpha_half<H>(c, p, r, nrhs, omega, S_BATCH);
+    dslash_h_mr<H>(c, p, r, nrhs, omega, S_BATCH);
     update2_half<H>(c, x, r, r, p, nrhs, S_BATCH);
   }
 }
@@ -717,6 +721,7 @@ static void relax_batch(Ctx& c, int l, cx<R>* V, int nv, int iters, double omega
   if (kb > (size_t)kMaxRhs) kb = kMaxRhs;
   cx<R>* Rb = static_cast<cx<R>*>(dev_alloc(c, kb * field));
   cx<R>* Pb = static_cast<cx<R>*>(dev_alloc(c, kb * field));
+  if (l == 0) dots_buffer(c, (int)kb);
   for (int k0 = 0; k0 < nv; k0 += (int)kb) {
     const int nb = (nv - k0) < (int)kb ? (nv - k0) : (int)kb;
     cx<R>* X = V + (size_t)k0 * n;
@@ -724,8 +729,12 @@ static void relax_batch(Ctx& c, int l, cx<R>* V, int nv, int iters, double omega
     apply_op<R>(c, l, Rb, X, nb);
     neg<R>(c, Rb, (size_t)nb * n);
     for (int it = 0; it < iters; ++it) {
-      apply_op<R>(c, l, Pb, Rb, nb);
-      step_alpha_batch<R>(c, Pb, Rb, n, n, nb, omega, S_BATCH);
+      if (l == 0) {
+        dslash_mr<R>(c, Pb, Rb, nb, omega, S_BATCH);
+      } else {
+        apply_op<R>(c, l, Pb, Rb, nb);
+        step_alpha_batch<R>(c, Pb, Rb, n, n, nb, omega, S_BATCH);
+      }
       update2_batch<R>(c, X, Rb, Rb, Pb, n, n, nb, S_BATCH);
     }
   }

@@ -86,7 +86,7 @@ struct RowsC {  // level >= 1: r = d * bvol + l, d in 0..half-1
 // are re-read from that XCD's L2.
 __device__ __forceinline__ void agg_rhs_block(int nagg, int nrhs, int& agg, int& rhs) {
   const int b = blockIdx.x;
-  if (nrhs == 1 || (nagg & 7)) {
+  if (nagg & 7) {
     agg = b % nagg;
     rhs = b / nagg;
     return;
@@ -96,17 +96,23 @@ __device__ __forceinline__ void agg_rhs_block(int nagg, int nrhs, int& agg, int&
   rhs = local % nrhs;
 }
 
-// ---- restriction: one workgroup per (aggregate, rhs) ----------------------
+// ---- restriction: one workgroup per (aggregate, rhs, column range) ---------
+// The nv columns of an aggregate are split into nsplit ranges of kper columns
+// so that a single right-hand side still fills the chip; the ranges of one
+// (aggregate, rhs) run back to back on one XCD and re-read the fine field
+// from its L2.
 template <typename R, class Rows>
 __global__ __launch_bounds__(256) void k_restrict(Rows rows, int nrows, const cx<R>* __restrict__ Vv, size_t vstride,
                                                   const cx<R>* __restrict__ in, size_t fstride, cx<R>* __restrict__ out,
-                                                  int nagg, int nv) {
+                                                  int nagg, int nv, int nsplit, int kper) {
   __shared__ double lds[4 * KC * 4];
-  int agg, rhs;
-  agg_rhs_block(nagg, gridDim.x / nagg, agg, rhs);
+  int agg, item;
+  agg_rhs_block(nagg, gridDim.x / nagg, agg, item);
+  const int rhs = item / nsplit, split = item % nsplit;
+  const int kbeg = split * kper, kend = min(nv, kbeg + kper);
   in += (size_t)rhs * fstride;
   out += ((size_t)rhs * nagg + agg) * 2 * nv;
-  for (int k0 = 0; k0 < nv; k0 += KC) {
+  for (int k0 = kbeg; k0 < kend; k0 += KC) {
     double v[4 * KC];
 #pragma unroll
     for (int q = 0; q < 4 * KC; ++q) v[q] = 0.0;
@@ -116,7 +122,7 @@ __global__ __launch_bounds__(256) void k_restrict(Rows rows, int nrows, const cx
         const cx<R> f = in[o];
 #pragma unroll
         for (int q = 0; q < KC; ++q) {
-          if (k0 + q < nv) {
+          if (k0 + q < kend) {
             const cx<R> w = Vv[(size_t)(k0 + q) * vstride + o];
             v[4 * q + 2 * chi] += (double)w.re * f.re + (double)w.im * f.im;
             v[4 * q + 2 * chi + 1] += (double)w.re * f.im - (double)w.im * f.re;
@@ -126,7 +132,7 @@ __global__ __launch_bounds__(256) void k_restrict(Rows rows, int nrows, const cx
     }
     block_sum<4 * KC>(v, lds);
     if (threadIdx.x == 0) {
-      for (int q = 0; q < KC && k0 + q < nv; ++q) {
+      for (int q = 0; q < KC && k0 + q < kend; ++q) {
         out[k0 + q] = mk<R>((R)v[4 * q], (R)v[4 * q + 1]);
         out[nv + k0 + q] = mk<R>((R)v[4 * q + 2], (R)v[4 * q + 3]);
       }
@@ -491,6 +497,20 @@ inline int tpb_for(int nrows) {
   return t > 256 ? 256 : t;
 }
 
+// Column ranges per (aggregate, rhs) of k_restrict: enough workgroups to
+// fill the chip (about 2048), ranges of at least one column.
+struct RestrictSplit {
+  int nsplit, kper;
+};
+inline RestrictSplit restrict_split(int nagg, int nrhs, int nv) {
+  const long long have = (long long)nagg * nrhs;
+  int want = (int)((2048 + have - 1) / have);
+  if (want > nv) want = nv;
+  if (want < 1) want = 1;
+  const int kper = (nv + want - 1) / want;
+  return {(nv + kper - 1) / kper, kper};
+}
+
 }  // namespace
 
 template <typename R>
@@ -512,8 +532,9 @@ void restrict0(Ctx& c, const Level& f, const cx<R>* V, const cx<R>* in, cx<R>* o
   // (one workgroup per (aggregate, rhs): measured faster than reading V once
   // per rhs chunk, because the chunked form re-reads the fine fields per column)
   ProfScope ps(c, sizeof(R) == 8 ? WDMG_K_RESTRICT_F64 : WDMG_K_RESTRICT_F32, (long long)f.nsite * nrhs);
-  hipLaunchKernelGGL((k_restrict<R, Rows0>), dim3(nagg * nrhs), dim3(tpb_for(nrows)), 0, c.stream, rows, nrows, V,
-                     f.n, in, f.n, out, nagg, f.nv);
+  const RestrictSplit sp = restrict_split(nagg, nrhs, f.nv);
+  hipLaunchKernelGGL((k_restrict<R, Rows0>), dim3(nagg * nrhs * sp.nsplit), dim3(tpb_for(nrows)), 0, c.stream, rows,
+                     nrows, V, f.n, in, f.n, out, nagg, f.nv, sp.nsplit, sp.kper);
   WDMG_HIP(hipGetLastError());
 }
 
@@ -523,8 +544,9 @@ void restrictC(Ctx& c, const Level& f, const cx<R>* V, const cx<R>* in, cx<R>* o
   const int nrows = rows.nrows();
   const int nagg = nagg_of(f);
 
-  hipLaunchKernelGGL((k_restrict<R, RowsC>), dim3(nagg * nrhs), dim3(tpb_for(nrows)), 0, c.stream, rows, nrows, V,
-                     f.n, in, f.n, out, nagg, f.nv);
+  const RestrictSplit sp = restrict_split(nagg, nrhs, f.nv);
+  hipLaunchKernelGGL((k_restrict<R, RowsC>), dim3(nagg * nrhs * sp.nsplit), dim3(tpb_for(nrows)), 0, c.stream, rows,
+                     nrows, V, f.n, in, f.n, out, nagg, f.nv, sp.nsplit, sp.kper);
   WDMG_HIP(hipGetLastError());
 }
 
