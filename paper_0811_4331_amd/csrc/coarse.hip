@@ -371,15 +371,29 @@ constexpr int kMfma64Lds = 4096;  // doubles of LDS for the group partials
 // held in registers; instantiating the smallest NT keeps the unused
 // accumulators out of the register budget.
 constexpr int kMaxTiles = kMaxRhs / 16;
-template <int NT>
+
+// Coarse vector layouts: element (rhs q, site, row) of nrhs vectors.
+struct RhsMajor {  // [rhs][site][row], the canonical coarse layout
+  size_t fs;       // site count x rows
+  __device__ __forceinline__ size_t at(int q, int site, int row, int n2) const {
+    return (size_t)q * fs + (size_t)site * n2 + row;
+  }
+};
+struct RhsFast {  // [site][row][rhs]: the rhs of one row are adjacent
+  int nrhs;
+  __device__ __forceinline__ size_t at(int q, int site, int row, int n2) const {
+    return ((size_t)site * n2 + row) * nrhs + q;
+  }
+};
+
+template <int NT, class Lay>
 __device__ __forceinline__ void apply_site_mfma64(const Geom& g, int n2, int nrhs, int s,
                                                   const cx<double>* __restrict__ Dc, const cx<double>* in,
-                                                  cx<double>* out, double* lds) {
+                                                  cx<double>* out, double* lds, Lay lay) {
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int nrt = mfma64_row_tiles(n2), ng = mfma64_groups(n2);
   const int rt = w % nrt, grp = w / nrt;
   const int ntile = (nrhs + 15) / 16;
-  const size_t fs = (size_t)g.vol * n2;
   const int kr = 2 * n2;
   const int r = rt * 16 + (l & 15), i = r >> 1, pr = r & 1;
   const bool rowok = i < n2;
@@ -411,12 +425,11 @@ __device__ __forceinline__ void apply_site_mfma64(const Geom& g, int n2, int nrh
         if (tt >= ntile) break;
         const int q = tt * 16 + (l & 15);
         const bool qok = q < nrhs;
-        const double* v = reinterpret_cast<const double*>(in + (size_t)(qok ? q : 0) * fs + (size_t)nb * n2);
         double bv[KC];
 #pragma unroll
         for (int t = 0; t < KC; ++t) {
           const int k = 4 * (t0 + t) + kl, j = k >> 1, pk = k & 1;
-          bv[t] = (qok && k < kr) ? v[2 * j + pk] : 0.0;
+          bv[t] = (qok && k < kr) ? reinterpret_cast<const double*>(in + lay.at(q, nb, j, n2))[pk] : 0.0;
         }
 #pragma unroll
         for (int t = 0; t < KC; ++t)
@@ -443,11 +456,10 @@ __device__ __forceinline__ void apply_site_mfma64(const Geom& g, int n2, int nrh
       }
       const int q = tt * 16 + (l & 15);
       if (q < nrhs) {
-        double* o = reinterpret_cast<double*>(out + (size_t)q * fs + (size_t)s * n2);
 #pragma unroll
         for (int reg = 0; reg < 4; ++reg) {
           const int rr = rt * 16 + 4 * reg + (l >> 4);
-          if ((rr >> 1) < n2) o[rr] = a[reg];
+          if ((rr >> 1) < n2) reinterpret_cast<double*>(out + lay.at(q, s, rr >> 1, n2))[rr & 1] = a[reg];
         }
       }
     }
@@ -503,7 +515,7 @@ __global__ __launch_bounds__(1024) void k_coarse_apply_mfma64(Geom g, int n2, in
   __shared__ double lds[kMfma64Lds];
   const int s = blockIdx.x;
   if (copy) copy_site(n2, (size_t)g.vol * n2, s, 0, nrhs, in, copy);
-  apply_site_mfma64<NT>(g, n2, nrhs, s, Dc, in, out, lds);
+  apply_site_mfma64<NT>(g, n2, nrhs, s, Dc, in, out, lds, RhsMajor{(size_t)g.vol * n2});
 }
 
 // FP32: v_mfma_f32_32x32x2f32; tile = 32 real rows x 32 rhs.
@@ -798,8 +810,8 @@ __global__ __launch_bounds__(256) void k_cgcr_init(const cx<double>* __restrict_
   }
 }
 
-// K1: blocks (G1, rhs tiles of 16), one wave per 16 real rows of a site.
-template <bool VALU, int NT>
+// K1 of a single rhs: grid-stride over sites, nine waves (one per block of
+// the stencil), then the dot products of w_j with the basis and r.
 __global__ __launch_bounds__(1024) void k_cgcr_apply(Geom g, int n2, int nrhs, int j, int vals,
                                                     const cx<double>* __restrict__ Dc, const cx<double>* r,
                                                     const cx<double>* Wb, cx<double>* w, cx<double>* z,
@@ -813,11 +825,8 @@ __global__ __launch_bounds__(1024) void k_cgcr_apply(Geom g, int n2, int nrhs, i
   for (int t = threadIdx.x; t < nq * vals; t += blockDim.x) acc[t] = 0.0;
   for (int s = blockIdx.x; s < g.vol; s += gridDim.x) {
     copy_site(n2, fs, s, q0, nq, r, z);
-    // both end with a block barrier: w_j of site s is then complete
-    if (VALU)
-      apply_site_valu1(g, n2, s, Dc, r, w, lds);
-    else
-      apply_site_mfma64<NT>(g, n2, nrhs, s, Dc, r, w, lds);
+    // ends with a block barrier: w_j of site s is then complete
+    apply_site_valu1(g, n2, s, Dc, r, w, lds);
     // Dot-product tasks (rhs qq, basis vector i < j) and (qq, the four
     // norms) spread over the waves; a task keeps its wave for every site of
     // the loop, so each accumulator has a single writer.
@@ -866,9 +875,9 @@ __global__ __launch_bounds__(1024) void k_cgcr_apply(Geom g, int n2, int nrhs, i
 }
 
 // K2: one workgroup per rhs.  vals = 4 j + 4 partial values per K1 workgroup;
-// p3: K3's partial |w_{j-1}|^2 per chunk (j > 0).
+// p3: K3's g3 partial |w_{j-1}|^2 per rhs (j > 0).
 __global__ __launch_bounds__(1024) void k_cgcr_coef(int j, int vals, int g1, const double* __restrict__ part,
-                                                   const double* __restrict__ p3, int kmax, CgcrState S,
+                                                   const double* __restrict__ p3, int g3, int kmax, CgcrState S,
                                                    double* host_act, double* err) {
   extern __shared__ __align__(16) char dyn2[];
   double* tot = reinterpret_cast<double*>(dyn2);  // [vals + 1]
@@ -879,7 +888,7 @@ __global__ __launch_bounds__(1024) void k_cgcr_coef(int j, int vals, int g1, con
     if (v < vals) {
       for (int b = lane; b < g1; b += 64) s += part[((size_t)q * g1 + b) * vals + v];
     } else if (j > 0) {
-      for (int b = lane; b < kCgcrG3; b += 64) s += p3[(size_t)q * kCgcrG3 + b];
+      for (int b = lane; b < g3; b += 64) s += p3[(size_t)q * g3 + b];
     }
     s = wave_sum(s);
     if (lane == 0) tot[v] = s;
@@ -945,6 +954,182 @@ __global__ __launch_bounds__(256) void k_cgcr_update(size_t n, int nrhs, int j, 
   }
   block_sum<1>(v, red);
   if (threadIdx.x == 0) p3[(size_t)q * kCgcrG3 + blockIdx.x] = v[0];
+}
+
+// ---- the same solve for a batch of rhs in the rhs-fast layout ---------------
+// Vectors of the batch are stored [site][row][rhs] for the whole solve, so the
+// matrix-core operand of one row and 16 rhs is one contiguous 256-byte run.
+// Threads of a workgroup form a (rows x nrhs) grid, thread t handling rhs
+// t % nrhs at positions (site, row) t / nrhs, t / nrhs + R, ... of the
+// workgroup's chunk; sums over those positions meet in LDS, per rhs.
+constexpr int kCgcrG3T = 256;    // workgroups (chunks) of the rhs-fast update
+constexpr int kCgcrDotIG = 4;    // basis vectors per pass of the dot kernel
+
+// Sums v over the threads of each rhs column; thread q < nrhs receives its total.
+__device__ __forceinline__ double rhs_column_sum(double v, int nrhs, int rows, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  double sum = 0.0;
+  if ((int)threadIdx.x < nrhs)
+    for (int rr = 0; rr < rows; ++rr) sum += red[rr * nrhs + threadIdx.x];
+  __syncthreads();
+  return sum;
+}
+
+// r = b and x = 0 in the rhs-fast layout; partial |b_q|^2 per workgroup.
+__global__ __launch_bounds__(256) void k_cgcrT_init(size_t npos, int nrhs, const cx<double>* __restrict__ b,
+                                                    cx<double>* __restrict__ xT, cx<double>* __restrict__ rT,
+                                                    double* p3) {
+  __shared__ double red[256];
+  const int rows = 256 / nrhs, q = threadIdx.x % nrhs, rho = threadIdx.x / nrhs;
+  const size_t cs = (npos + gridDim.x - 1) / gridDim.x, p0 = blockIdx.x * cs, p1 = p0 + cs < npos ? p0 + cs : npos;
+  double v = 0.0;
+  if (rho < rows) {
+    for (size_t p = p0 + rho; p < p1; p += rows) {
+      const cx<double> bv = b[(size_t)q * npos + p];
+      rT[p * nrhs + q] = bv;
+      xT[p * nrhs + q] = mk(0.0, 0.0);
+      v += bv.re * bv.re + bv.im * bv.im;
+    }
+  }
+  const double sum = rhs_column_sum(v, nrhs, rows, red);
+  if ((int)threadIdx.x < nrhs) p3[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = sum;
+}
+
+// tol2 = tol^2 |b|^2, active = |b| > 0, from the init partials (one thread per rhs).
+__global__ void k_cgcrT_init_fin(int nrhs, int g, const double* __restrict__ p3, double tol, CgcrState S,
+                                 double* err) {
+  const int q = threadIdx.x;
+  if (q >= nrhs) return;
+  double v = 0.0;
+  for (int b = 0; b < g; ++b) v += p3[(size_t)q * g + b];
+  if (!isfinite(v)) err[0] = 1.0;
+  S.tol2[q] = tol * tol * v;
+  S.act[q] = v > 0.0 && isfinite(v) ? 1.0 : 0.0;
+  S.rn[q] = v;
+}
+
+// x (canonical) = xT.
+__global__ __launch_bounds__(256) void k_cgcrT_out(size_t npos, int nrhs, const cx<double>* __restrict__ xT,
+                                                   cx<double>* __restrict__ x) {
+  const size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (e >= npos * nrhs) return;
+  const size_t p = e / nrhs;
+  const int q = (int)(e % nrhs);
+  x[(size_t)q * npos + p] = xT[e];
+}
+
+// K1 (rhs-fast): w_j = D_c r and z_j = r at one site per workgroup.
+template <int NT>
+__global__ __launch_bounds__(1024) void k_cgcrT_apply(Geom g, int n2, int nrhs, const cx<double>* __restrict__ Dc,
+                                                     const cx<double>* __restrict__ r, cx<double>* __restrict__ w,
+                                                     cx<double>* __restrict__ z) {
+  __shared__ double lds[kMfma64Lds];
+  const int s = blockIdx.x;
+  const size_t o = (size_t)s * n2 * nrhs;
+  for (int e = threadIdx.x; e < n2 * nrhs; e += blockDim.x) z[o + e] = r[o + e];
+  apply_site_mfma64<NT>(g, n2, nrhs, s, Dc, r, w, lds, RhsFast{nrhs});
+}
+
+// Dots (rhs-fast): partial c_i = <W_i, w>, d_i = <W_i, r> (i < j) and
+// |w|^2, <w, r>, |r|^2 of one chunk of positions, stored in the value order of
+// k_cgcr_coef.  Basis vectors are taken kCgcrDotIG per pass over the chunk.
+__global__ __launch_bounds__(256) void k_cgcrT_dots(size_t npos, int nrhs, int j, int vals,
+                                                    const cx<double>* __restrict__ Wb,
+                                                    const cx<double>* __restrict__ w,
+                                                    const cx<double>* __restrict__ r, double* part) {
+  __shared__ double red[256];
+  const int rows = 256 / nrhs, q = threadIdx.x % nrhs, rho = threadIdx.x / nrhs;
+  const bool on = rho < rows;
+  const size_t bs = npos * nrhs;
+  const size_t cs = (npos + gridDim.x - 1) / gridDim.x, p0 = blockIdx.x * cs, p1 = p0 + cs < npos ? p0 + cs : npos;
+  double* out = part + ((size_t)threadIdx.x * gridDim.x + blockIdx.x) * vals;  // used by threads < nrhs
+  for (int i0 = 0; i0 == 0 || i0 < j; i0 += kCgcrDotIG) {
+    const int ni = j - i0 < kCgcrDotIG ? j - i0 : kCgcrDotIG;
+    double a[kCgcrDotIG][4] = {}, nv[4] = {};
+    if (on) {
+      for (size_t p = p0 + rho; p < p1; p += rows) {
+        const size_t e = p * nrhs + q;
+        const cx<double> wv = w[e], rv = r[e];
+        if (i0 == 0) {
+          nv[0] += wv.re * wv.re + wv.im * wv.im;
+          nv[1] += wv.re * rv.re + wv.im * rv.im;
+          nv[2] += wv.re * rv.im - wv.im * rv.re;
+          nv[3] += rv.re * rv.re + rv.im * rv.im;
+        }
+#pragma unroll
+        for (int u = 0; u < kCgcrDotIG; ++u) {
+          if (u < ni) {
+            const cx<double> bv = Wb[(size_t)(i0 + u) * bs + e];
+            a[u][0] += bv.re * wv.re + bv.im * wv.im;
+            a[u][1] += bv.re * wv.im - bv.im * wv.re;
+            a[u][2] += bv.re * rv.re + bv.im * rv.im;
+            a[u][3] += bv.re * rv.im - bv.im * rv.re;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kCgcrDotIG; ++u) {
+      if (u < ni) {
+        const int i = i0 + u;
+        const double s0 = rhs_column_sum(a[u][0], nrhs, rows, red);
+        const double s1 = rhs_column_sum(a[u][1], nrhs, rows, red);
+        const double s2 = rhs_column_sum(a[u][2], nrhs, rows, red);
+        const double s3 = rhs_column_sum(a[u][3], nrhs, rows, red);
+        if ((int)threadIdx.x < nrhs) {
+          out[2 * i] = s0;
+          out[2 * i + 1] = s1;
+          out[2 * j + 2 * i] = s2;
+          out[2 * j + 2 * i + 1] = s3;
+        }
+      }
+    }
+    if (i0 == 0) {
+      double t[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) t[k] = rhs_column_sum(nv[k], nrhs, rows, red);
+      if ((int)threadIdx.x < nrhs) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) out[4 * j + k] = t[k];
+      }
+    }
+  }
+}
+
+// K3 (rhs-fast): w' = w - sum h_i W_i, z' = z - sum h_i Z_i, x += a z',
+// r -= a w', partial |w'|^2 per rhs; frozen rhs are left unchanged.
+__global__ __launch_bounds__(256) void k_cgcrT_update(size_t npos, int nrhs, int j, int kmax,
+                                                      const cx<double>* __restrict__ Wb,
+                                                      const cx<double>* __restrict__ Zb, cx<double>* __restrict__ w,
+                                                      cx<double>* __restrict__ z, cx<double>* __restrict__ x,
+                                                      cx<double>* __restrict__ r, CgcrState S, double* p3) {
+  __shared__ double red[256];
+  const int rows = 256 / nrhs, q = threadIdx.x % nrhs, rho = threadIdx.x / nrhs;
+  const bool on = rho < rows && S.act[q] != 0.0;
+  const size_t bs = npos * nrhs;
+  const size_t cs = (npos + gridDim.x - 1) / gridDim.x, p0 = blockIdx.x * cs, p1 = p0 + cs < npos ? p0 + cs : npos;
+  double v = 0.0;
+  if (on) {
+    const double* h = S.h + (size_t)q * 2 * kmax;
+    const cx<double> a = mk(S.a[2 * q], S.a[2 * q + 1]);
+    for (size_t p = p0 + rho; p < p1; p += rows) {
+      const size_t e = p * nrhs + q;
+      cx<double> wv = w[e], zv = z[e];
+      for (int i = 0; i < j; ++i) {
+        const cx<double> hi = mk(h[2 * i], h[2 * i + 1]);
+        wv = wv - hi * Wb[(size_t)i * bs + e];
+        zv = zv - hi * Zb[(size_t)i * bs + e];
+      }
+      w[e] = wv;
+      z[e] = zv;
+      x[e] = x[e] + a * zv;
+      r[e] = r[e] - a * wv;
+      v += wv.re * wv.re + wv.im * wv.im;
+    }
+  }
+  const double sum = rhs_column_sum(v, nrhs, rows, red);
+  if ((int)threadIdx.x < nrhs) p3[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = sum;
 }
 
 template <typename R>
@@ -1075,21 +1260,30 @@ void coarsest_gcr(Ctx& c, Level& L, cx<double>* x, const cx<double>* b, int nrhs
   CgcrState S{gb + G_H, gb + G_NRM, gb + G_A, gb + G_RN, gb + G_ACT, gb + G_TOL};
   const int g1 = L.nsite < kCgcrG1 ? L.nsite : kCgcrG1;
   const int waves = mfma64_row_tiles(n2) * mfma64_groups(n2);
-  if ((size_t)nrhs * (4 * k + 4) * sizeof(double) > 96 * 1024)
-    throw Error(WDMG_ERR_ARG, "coarse_restart too long for this many right-hand sides (LDS)");
+  if (nrhs == 1 && (size_t)(4 * k + 4) * sizeof(double) > 96 * 1024)
+    throw Error(WDMG_ERR_ARG, "coarse_restart too long (LDS)");
   static bool lds_attr = false;
-  if (!lds_attr) {  // K1 keeps nrhs x (4 j + 4) partial sums in LDS
-    const void* fns[] = {reinterpret_cast<const void*>(&k_cgcr_apply<true, 1>),
-                         reinterpret_cast<const void*>(&k_cgcr_apply<false, 1>),
-                         reinterpret_cast<const void*>(&k_cgcr_apply<false, 2>),
-                         reinterpret_cast<const void*>(&k_cgcr_apply<false, 3>),
-                         reinterpret_cast<const void*>(&k_cgcr_apply<false, kMaxTiles>)};
-    for (const void* f : fns) WDMG_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024));
+  if (!lds_attr) {  // the single-rhs K1 keeps 4 j + 4 partial sums in LDS
+    WDMG_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cgcr_apply),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024));
     lds_attr = true;
   }
-  hipLaunchKernelGGL(k_cgcr_init, dim3(nrhs), dim3(256), 0, c.stream, b, x, L.w64[1], n, tol, S, c.dsc + S_ERR);
-  WDMG_HIP(hipGetLastError());
+  // a batch keeps its vectors rhs-fast for the whole solve (x in L.xT)
+  const bool fast = nrhs >= 2;
+  const size_t npos = (size_t)L.nsite * n2;
+  long long g1t = ((long long)npos * nrhs + 511) / 512;
+  if (g1t > 1024) g1t = 1024;
+  const int g1f = (int)g1t;
   cx<double>* r = L.w64[1];
+  if (fast) {
+    hipLaunchKernelGGL(k_cgcrT_init, dim3(kCgcrG3T), dim3(256), 0, c.stream, npos, nrhs, b, L.xT, r, L.cpart3);
+    WDMG_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_cgcrT_init_fin, dim3(1), dim3(64), 0, c.stream, nrhs, kCgcrG3T, L.cpart3, tol, S,
+                       c.dsc + S_ERR);
+  } else {
+    hipLaunchKernelGGL(k_cgcr_init, dim3(nrhs), dim3(256), 0, c.stream, b, x, r, n, tol, S, c.dsc + S_ERR);
+  }
+  WDMG_HIP(hipGetLastError());
   // The active flags of iteration it land in pinned memory and are inspected
   // `lag` iterations later, so the stream never drains while the host waits.
   const int lag = 2;
@@ -1107,28 +1301,45 @@ void coarsest_gcr(Ctx& c, Level& L, cx<double>* x, const cx<double>* b, int nrhs
     cx<double>* w = L.basisW + (size_t)j * bs;
     cx<double>* z = L.basisZ + (size_t)j * bs;
     const int vals = 4 * j + 4;
+    if (fast) {
+      {
+        ProfScope ps(c, WDMG_K_COARSE_GCR, (long long)L.nsite * nrhs);
+        const dim3 grid(L.nsite), block(64 * waves);
+        switch ((nrhs + 15) / 16) {
+          case 1: hipLaunchKernelGGL(k_cgcrT_apply<1>, grid, block, 0, c.stream, L.g, n2, nrhs, L.Dc64, r, w, z); break;
+          case 2: hipLaunchKernelGGL(k_cgcrT_apply<2>, grid, block, 0, c.stream, L.g, n2, nrhs, L.Dc64, r, w, z); break;
+          case 3: hipLaunchKernelGGL(k_cgcrT_apply<3>, grid, block, 0, c.stream, L.g, n2, nrhs, L.Dc64, r, w, z); break;
+          default: hipLaunchKernelGGL(k_cgcrT_apply<kMaxTiles>, grid, block, 0, c.stream, L.g, n2, nrhs, L.Dc64, r, w, z); break;
+        }
+        WDMG_HIP(hipGetLastError());
+      }
+      hipLaunchKernelGGL(k_cgcrT_dots, dim3(g1f), dim3(256), 0, c.stream, npos, nrhs, j, vals, L.basisW, w, r,
+                         L.cpart);
+      WDMG_HIP(hipGetLastError());
+      hipLaunchKernelGGL(k_cgcr_coef, dim3(nrhs), dim3(1024), (size_t)(vals + 1) * sizeof(double), c.stream, j, vals,
+                         g1f, L.cpart, L.cpart3, kCgcrG3T, k, S,
+                         c.capturing ? nullptr : c.dring + (size_t)(it % kRing) * kMaxRhs, c.dsc + S_ERR);
+      WDMG_HIP(hipGetLastError());
+      if (!c.capturing) WDMG_HIP(hipEventRecord(c.ring_ev[it % kRing], c.stream));
+      hipLaunchKernelGGL(k_cgcrT_update, dim3(kCgcrG3T), dim3(256), 0, c.stream, npos, nrhs, j, k, L.basisW,
+                         L.basisZ, w, z, L.xT, r, S, L.cpart3);
+      WDMG_HIP(hipGetLastError());
+      c.n_Dc[L.l] += nrhs;
+      if (!c.capturing && it >= lag && done_at(it - lag)) {
+        ++it;
+        break;
+      }
+      continue;
+    }
     {
       ProfScope ps(c, WDMG_K_COARSE_GCR, (long long)L.nsite * nrhs);
-      const size_t lds = (size_t)nrhs * vals * sizeof(double);
-#define WDMG_K1(VALU, NT, THREADS)                                                                              \
-  hipLaunchKernelGGL((k_cgcr_apply<VALU, NT>), dim3(g1), dim3(THREADS), lds, c.stream, L.g, n2, nrhs, j, vals, \
-                     L.Dc64, r, L.basisW, w, z, L.cpart)
-      if (nrhs == 1) {
-        WDMG_K1(true, 1, 576);
-      } else {
-        switch ((nrhs + 15) / 16) {
-          case 1: WDMG_K1(false, 1, 64 * waves); break;
-          case 2: WDMG_K1(false, 2, 64 * waves); break;
-          case 3: WDMG_K1(false, 3, 64 * waves); break;
-          default: WDMG_K1(false, kMaxTiles, 64 * waves); break;
-        }
-      }
-#undef WDMG_K1
+      hipLaunchKernelGGL(k_cgcr_apply, dim3(g1), dim3(576), (size_t)vals * sizeof(double), c.stream, L.g, n2, nrhs,
+                         j, vals, L.Dc64, r, L.basisW, w, z, L.cpart);
       WDMG_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(k_cgcr_coef, dim3(nrhs), dim3(1024), (size_t)(vals + 1) * sizeof(double), c.stream, j, vals,
-                       g1, L.cpart, L.cpart3, k, S, c.capturing ? nullptr : c.dring + (size_t)(it % kRing) * kMaxRhs,
-                       c.dsc + S_ERR);
+                       g1, L.cpart, L.cpart3, kCgcrG3, k, S,
+                       c.capturing ? nullptr : c.dring + (size_t)(it % kRing) * kMaxRhs, c.dsc + S_ERR);
     WDMG_HIP(hipGetLastError());
     if (!c.capturing) WDMG_HIP(hipEventRecord(c.ring_ev[it % kRing], c.stream));
     hipLaunchKernelGGL(k_cgcr_update, dim3(kCgcrG3, nrhs), dim3(256), 0, c.stream, n, nrhs, j, k, L.basisW,
@@ -1140,13 +1351,18 @@ void coarsest_gcr(Ctx& c, Level& L, cx<double>* x, const cx<double>* b, int nrhs
       break;
     }
   }
+  if (fast) {
+    hipLaunchKernelGGL(k_cgcrT_out, dim3((unsigned)((npos * nrhs + 255) / 256)), dim3(256), 0, c.stream, npos, nrhs,
+                       L.xT, x);
+    WDMG_HIP(hipGetLastError());
+  }
   if (it > c.last_coarse_iters) c.last_coarse_iters = it;
 }
 
 size_t coarsest_gcr_partials(int nrhs, int k) {
   return (size_t)nrhs * kCgcrG1 * (4 * k + 4);
 }
-size_t coarsest_gcr_partials3(int nrhs) { return (size_t)nrhs * kCgcrG3; }
+size_t coarsest_gcr_partials3(int nrhs) { return (size_t)nrhs * (kCgcrG3T > kCgcrG3 ? kCgcrG3T : kCgcrG3); }
 
 template void coarse_apply<double>(Ctx&, const Level&, const cx<double>*, cx<double>*, const cx<double>*, int,
                                    cx<double>*);

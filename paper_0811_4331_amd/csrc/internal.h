@@ -124,6 +124,7 @@ struct Level {
   // GCR basis of the coarsest solve (coarsest level only)
   cx<double>* basisZ = nullptr;
   cx<double>* basisW = nullptr;
+  cx<double>* xT = nullptr;  // solution of a batched coarsest solve in the rhs-fast layout
   double* cpart = nullptr;   // partial sums of the coarsest GCR
   double* cpart3 = nullptr;
 };
@@ -380,11 +381,12 @@ template <typename R>
 void coarse_apply(Ctx& c, const Level& cl, const cx<R>* Dc, cx<R>* out, const cx<R>* in, int nrhs,
                   cx<R>* copy = nullptr);
 void coarse_shift(Ctx& c, Level& cl, double dm);
-// The coarsest-level GCR(k) in FP64 for nrhs right-hand sides (three
-// launches per iteration): x = 0, r = b, iterate until every
-// ||r_q|| <= tol ||b_q|| (lagged test) or maxit.  Work space: L.basisW/Z
-// (k slots), L.w64[1] (r), L.cpart / L.cpart3 (partial sums, sized by the two
-// functions below).
+// The coarsest-level GCR(k) in FP64 for nrhs right-hand sides: x = 0, r = b,
+// iterate until every ||r_q|| <= tol ||b_q|| (lagged test) or maxit.  One rhs:
+// three launches per iteration on the canonical layout; a batch: four, on
+// vectors kept rhs-fast for the whole solve.  Work space: L.basisW/Z (k slots),
+// L.w64[1] (r), L.xT (batched x), L.cpart / L.cpart3 (partial sums, sized by
+// the two functions below).
 void coarsest_gcr(Ctx& c, Level& L, cx<double>* x, const cx<double>* b, int nrhs, double tol, int k, int maxit);
 size_t coarsest_gcr_partials(int nrhs, int k);
 size_t coarsest_gcr_partials3(int nrhs);

@@ -209,9 +209,11 @@ void ensure_coarsest_basis(Ctx& c, int nrhs) {
   WDMG_HIP(hipStreamSynchronize(c.stream));
   dev_free(c, L.basisZ);
   dev_free(c, L.basisW);
+  dev_free(c, L.xT);
   const size_t sz = (size_t)c.mg.coarse_restart * nrhs * L.n * sizeof(cx<double>);
   L.basisZ = static_cast<cx<double>*>(dev_alloc(c, sz));
   L.basisW = static_cast<cx<double>*>(dev_alloc(c, sz));
+  L.xT = static_cast<cx<double>*>(dev_alloc(c, (size_t)nrhs * L.n * sizeof(cx<double>)));
   dev_free(c, L.cpart);
   dev_free(c, L.cpart3);
   L.cpart = static_cast<double*>(dev_alloc(c, coarsest_gcr_partials(nrhs, c.mg.coarse_restart) * sizeof(double)));
@@ -676,6 +678,7 @@ void free_hierarchy(Ctx& c) {
     }
     dev_free(c, L.basisZ);
     dev_free(c, L.basisW);
+    dev_free(c, L.xT);
     dev_free(c, L.cpart);
     dev_free(c, L.cpart3);
     Level blank;
