@@ -660,22 +660,25 @@ void dot(Ctx& c, const cx<R>* a, const cx<R>* b, size_t n, int slot) {
 }
 
 // ---- batched GCR ------------------------------------------------------------
-__global__ __launch_bounds__(TPB) void k_gcr_dots_b(const cx<double>* __restrict__ W, const cx<double>* __restrict__ w,
+// B: storage type of the basis and of w (double, or float for a reduced-
+// precision outer basis); sums are formed in double.
+template <typename B>
+__global__ __launch_bounds__(TPB) void k_gcr_dots_b(const cx<B>* __restrict__ W, const cx<B>* __restrict__ w,
                                                     size_t n, int nb, int j, int gx, int gy, double* partials) {
   __shared__ double lds[2 * GCR_G * (TPB / 64)];
   const int rhs = blockIdx.z;
   const int i0 = blockIdx.y * GCR_G;
   const int ni = min(GCR_G, j - i0);
-  const cx<double>* wr = w + (size_t)rhs * n;
+  const cx<B>* wr = w + (size_t)rhs * n;
   double v[2 * GCR_G];
 #pragma unroll
   for (int k = 0; k < 2 * GCR_G; ++k) v[k] = 0.0;
   for (size_t e = blockIdx.x * (size_t)TPB + threadIdx.x; e < n; e += (size_t)gridDim.x * TPB) {
-    const cx<double> y = wr[e];
+    const cx<double> y = cvt<double>(wr[e]);
 #pragma unroll
     for (int q = 0; q < GCR_G; ++q) {
       if (q < ni) {
-        const cx<double> x = W[((size_t)(i0 + q) * nb + rhs) * n + e];
+        const cx<double> x = cvt<double>(W[((size_t)(i0 + q) * nb + rhs) * n + e]);
         v[2 * q] += x.re * y.re + x.im * y.im;
         v[2 * q + 1] += x.re * y.im - x.im * y.re;
       }
@@ -707,12 +710,15 @@ __global__ __launch_bounds__(TPB) void k_gcr_dots_b_fin(int j, int gx, int gy, c
   }
 }
 
+// w -= sum h_i W_i, z -= sum h_i Z_i in double, stored as B; |w|^2 and
+// <w, r> of the stored w.
+template <typename B>
 struct GcrAxpyCoefBOp {
   static constexpr int K = 3;
-  const cx<double>* W;
-  const cx<double>* Z;
-  cx<double>* w;
-  cx<double>* z;
+  const cx<B>* W;
+  const cx<B>* Z;
+  cx<B>* w;
+  cx<B>* z;
   const cx<double>* r;
   double* g;
   double* dsc;
@@ -720,17 +726,19 @@ struct GcrAxpyCoefBOp {
   int nb, j;
   __device__ void acc(size_t e, int rhs, double* v) const {
     const size_t o = (size_t)rhs * n + e;
-    cx<double> a = w[o], b = z[o];
+    cx<double> a = cvt<double>(w[o]), b = cvt<double>(z[o]);
     const double* h = g + G_H + rhs * 2 * kMaxKrylov;
     for (int i = 0; i < j; ++i) {
       const cx<double> hi = mk(h[2 * i], h[2 * i + 1]);
       const size_t oi = ((size_t)i * nb + rhs) * n + e;
-      a = a - hi * W[oi];
-      b = b - hi * Z[oi];
+      a = a - hi * cvt<double>(W[oi]);
+      b = b - hi * cvt<double>(Z[oi]);
     }
     if (j > 0) {
-      w[o] = a;
-      z[o] = b;
+      const cx<B> as = cvt<B>(a);
+      w[o] = as;
+      z[o] = cvt<B>(b);
+      a = cvt<double>(as);
     }
     const cx<double> y = r[o];
     v[0] += a.re * a.re + a.im * a.im;
@@ -746,10 +754,11 @@ struct GcrAxpyCoefBOp {
   }
 };
 
+template <typename B>
 struct GcrUpdateBOp {
   static constexpr int K = 1;
-  const cx<double>* w;
-  const cx<double>* z;
+  const cx<B>* w;
+  const cx<B>* z;
   cx<double>* x;
   cx<double>* r;
   double* g;
@@ -759,8 +768,8 @@ struct GcrUpdateBOp {
   __device__ void acc(size_t e, int rhs, double* v) const {
     const size_t o = (size_t)rhs * n + e;
     const cx<double> s = mk(g[G_A + 2 * rhs], g[G_A + 2 * rhs + 1]);
-    x[o] = x[o] + s * z[o];
-    const cx<double> ri = r[o] - s * w[o];
+    x[o] = x[o] + s * cvt<double>(z[o]);
+    const cx<double> ri = r[o] - s * cvt<double>(w[o]);
     r[o] = ri;
     v[0] += ri.re * ri.re + ri.im * ri.im;
   }
@@ -923,26 +932,38 @@ void gcr_step(Ctx& c, const cx<double>* w, const cx<double>* z, cx<double>* x, c
   run_reduce(c, GcrUpdateOp{w, z, x, r, c.dsc + S_TMP, c.dsc, rslot, host}, n);
 }
 
-void gcr_orth_b(Ctx& c, const cx<double>* W, const cx<double>* Z, cx<double>* w, cx<double>* z,
-                const cx<double>* r, size_t n, int nb, int j, int gl) {
+template <typename B>
+void gcr_orth_b(Ctx& c, const cx<B>* W, const cx<B>* Z, cx<B>* w, cx<B>* z, const cx<double>* r, size_t n, int nb,
+                int j, int gl) {
   double* g = c.dsc + gcr_base(gl);
   if (j > 0) {
     const int gy = (j + GCR_G - 1) / GCR_G;
     int gx = (int)reduce_blocks(n);
     if ((size_t)gx * gy * nb > 8192) gx = 8192 / (gy * nb);
     if (gx < 1) gx = 1;
-    hipLaunchKernelGGL(k_gcr_dots_b, dim3(gx, gy, nb), dim3(TPB), 0, c.stream, W, w, n, nb, j, gx, gy, c.partials);
+    hipLaunchKernelGGL(k_gcr_dots_b<B>, dim3(gx, gy, nb), dim3(TPB), 0, c.stream, W, w, n, nb, j, gx, gy,
+                       c.partials);
     WDMG_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_gcr_dots_b_fin, dim3(nb), dim3(TPB), 0, c.stream, j, gx, gy, c.partials, g);
     WDMG_HIP(hipGetLastError());
   }
-  run_reduce_b(c, GcrAxpyCoefBOp{W, Z, w, z, r, g, c.dsc, n, nb, j}, n, nb);
+  run_reduce_b(c, GcrAxpyCoefBOp<B>{W, Z, w, z, r, g, c.dsc, n, nb, j}, n, nb);
 }
 
-void gcr_step_b(Ctx& c, const cx<double>* w, const cx<double>* z, cx<double>* x, cx<double>* r, size_t n, int nb,
-                int gl, double* host) {
-  run_reduce_b(c, GcrUpdateBOp{w, z, x, r, c.dsc + gcr_base(gl), c.dsc, host, n}, n, nb);
+template <typename B>
+void gcr_step_b(Ctx& c, const cx<B>* w, const cx<B>* z, cx<double>* x, cx<double>* r, size_t n, int nb, int gl,
+                double* host) {
+  run_reduce_b(c, GcrUpdateBOp<B>{w, z, x, r, c.dsc + gcr_base(gl), c.dsc, host, n}, n, nb);
 }
+
+template void gcr_orth_b<double>(Ctx&, const cx<double>*, const cx<double>*, cx<double>*, cx<double>*,
+                                 const cx<double>*, size_t, int, int, int);
+template void gcr_orth_b<float>(Ctx&, const cx<float>*, const cx<float>*, cx<float>*, cx<float>*, const cx<double>*,
+                                size_t, int, int, int);
+template void gcr_step_b<double>(Ctx&, const cx<double>*, const cx<double>*, cx<double>*, cx<double>*, size_t, int,
+                                 int, double*);
+template void gcr_step_b<float>(Ctx&, const cx<float>*, const cx<float>*, cx<double>*, cx<double>*, size_t, int, int,
+                                double*);
 
 void norm2_b(Ctx& c, const cx<double>* a, size_t n, int nb, int gl, double* host) {
   run_reduce_b(c, Norm2BOp{a, c.dsc + gcr_base(gl), c.dsc, host, n}, n, nb);

@@ -197,11 +197,15 @@ struct Ctx {
   cx<double>* outer_r = nullptr;
   cx<float>* outer_r32 = nullptr;
   cx<float>* outer_z32 = nullptr;
+  cx<float>* outer_Z32 = nullptr;  // FP32 outer basis (reduced-precision V-cycle)
+  cx<float>* outer_W32 = nullptr;
+  int outer_k32 = 0, outer_capB32 = 0;
   cx<double>* bicg[6] = {};
   cx<double>* sol_x = nullptr;   // internal x, b of a solve
   cx<double>* sol_b = nullptr;
   int sol_cap = 0;
-  int outer_cap = 0;             // rhs capacity of the outer basis
+  int outer_cap = 0;             // rhs capacity of outer_r
+  int outer_capB = 0;            // rhs capacity of the FP64 outer basis
   int outer_cap32 = 0;
 
   // kernel timing (instrumentation)
@@ -316,12 +320,16 @@ void update2_batch(Ctx& c, cx<R>* x, const cx<R>* u, cx<R>* r, const cx<R>* v, s
 // Batched GCR over nb right-hand sides.  Fields of one rhs are n long and
 // consecutive (batch stride n); basis vector i of all rhs is W + i*nb*n.
 // State in the block gcr_base(g): h, nrm, a, rnorm^2, active (see ScalarSlot).
-void gcr_orth_b(Ctx& c, const cx<double>* W, const cx<double>* Z, cx<double>* w, cx<double>* z,
-                const cx<double>* r, size_t n, int nb, int j, int g);
+// B is the storage type of the basis W, Z and of w, z (double or float);
+// r and x are double and every sum is formed in double.
+template <typename B>
+void gcr_orth_b(Ctx& c, const cx<B>* W, const cx<B>* Z, cx<B>* w, cx<B>* z, const cx<double>* r, size_t n, int nb,
+                int j, int g);
 // x += a z; r -= a w per rhs (a = 0 for inactive rhs); rnorm^2 per rhs, also
 // to host (device-visible pinned address, nb doubles) when given.
-void gcr_step_b(Ctx& c, const cx<double>* w, const cx<double>* z, cx<double>* x, cx<double>* r, size_t n, int nb,
-                int g, double* host = nullptr);
+template <typename B>
+void gcr_step_b(Ctx& c, const cx<B>* w, const cx<B>* z, cx<double>* x, cx<double>* r, size_t n, int nb, int g,
+                double* host = nullptr);
 // rnorm^2 of nb fields into the block g (and host when given).
 void norm2_b(Ctx& c, const cx<double>* a, size_t n, int nb, int g, double* host = nullptr);
 // y = b - y per rhs, with rnorm^2 into block g.

@@ -400,14 +400,18 @@ int fgcr(Ctx& c, cx<double>* x, const cx<double>* b, int nrhs, const wdmg_solve_
   const int k = p.restart;
   const bool half = p.precond && (p.mg_prec == WDMG_F16 || p.mg_prec == WDMG_BF16);
   const bool f32 = p.precond && p.mg_prec == WDMG_F32;
-  ensure_outer(c, k, nrhs, f32);
+  // With a reduced-precision V-cycle the outer basis z_j, w_j = D z_j is kept
+  // in FP32 (z_j comes out of the V-cycle in FP32 or 16 bits anyway); x, r and
+  // every restart's true residual stay FP64.
+  const bool basis32 = f32 || half;
+  ensure_outer(c, k, nrhs, basis32, basis32);
   if (p.precond) ensure_mg_work(c, nrhs, f32 || half ? WDMG_F32 : WDMG_F64);
   if (half) ensure_work_h(c, nrhs);
   HalfScope hs(c, half ? p.mg_prec : 0);
   const bool graph = p.precond && p.use_graph;
   if (graph) {
     if (!c.cap_stream) WDMG_HIP(hipStreamCreateWithFlags(&c.cap_stream, hipStreamNonBlocking));
-    if (nrhs > c.outer_zf_cap) {
+    if (!basis32 && nrhs > c.outer_zf_cap) {
       WDMG_HIP(hipStreamSynchronize(c.stream));
       dev_free(c, c.outer_zf);
       c.outer_zf = static_cast<cx<double>*>(dev_alloc(c, (size_t)nrhs * n * sizeof(cx<double>)));
@@ -427,30 +431,42 @@ int fgcr(Ctx& c, cx<double>* x, const cx<double>* b, int nrhs, const wdmg_solve_
   hipGraphExec_t& gexec = gh.e;
   long long g_nd = 0, g_ndc[WDMG_MAX_LEVELS] = {0, 0, 0, 0};
   cx<double>* r = c.outer_r;
-  cx<double>* Zb = c.outer_Z;
-  cx<double>* Wb = c.outer_W;
   const int G = 4;  // scalar block of the outer solve
-  // preconditioner application z = M r (Sec. 2 V-cycle) in the chosen precision
-  auto apply_M = [&](cx<double>* zdst) {
+  // preconditioner application z = M r (Sec. 2 V-cycle) in the chosen
+  // precision; zdst is FP32 when basis32, else FP64
+  auto apply_M = [&](void* zdst) {
     if (half) {
       Level& L0 = c.lev[0];
       if (p.mg_prec == WDMG_F16) {
         to_half<double, f16_t>(c, r, L0.wh[4], nrhs);
         vcycle_h<f16_t>(c, L0.wh[5], L0.wh[4], nrhs);
-        from_half<f16_t, double>(c, L0.wh[5], zdst, nrhs);
+        from_half<f16_t, float>(c, L0.wh[5], static_cast<cx<float>*>(zdst), nrhs);
       } else {
         to_half<double, bf16_t>(c, r, L0.wh[4], nrhs);
         vcycle_h<bf16_t>(c, L0.wh[5], L0.wh[4], nrhs);
-        from_half<bf16_t, double>(c, L0.wh[5], zdst, nrhs);
+        from_half<bf16_t, float>(c, L0.wh[5], static_cast<cx<float>*>(zdst), nrhs);
       }
     } else if (f32) {
       convert<float, double>(c, c.outer_r32, r, bs);
-      vcycle<float>(c, 0, c.outer_z32, c.outer_r32, nrhs);
-      convert<double, float>(c, zdst, c.outer_z32, bs);
+      vcycle<float>(c, 0, static_cast<cx<float>*>(zdst), c.outer_r32, nrhs);
     } else {
-      vcycle<double>(c, 0, zdst, r, nrhs);
+      vcycle<double>(c, 0, static_cast<cx<double>*>(zdst), r, nrhs);
     }
   };
+  // output of a graph-captured V-cycle (a fixed address), and its copy into a
+  // basis slot
+  void* zfix = basis32 ? static_cast<void*>(c.outer_z32) : static_cast<void*>(c.outer_zf);
+  auto copy_z = [&](void* dst, const void* src) {
+    if (basis32)
+      copy<float>(c, static_cast<cx<float>*>(dst), static_cast<const cx<float>*>(src), bs);
+    else
+      copy<double>(c, static_cast<cx<double>*>(dst), static_cast<const cx<double>*>(src), bs);
+  };
+  // Reliable update: with an FP32 basis one cycle cannot bring the true
+  // residual much below 1e-7 of its starting value, so a cycle also ends once
+  // every active rhs has reduced its recursive residual by kReliable^2 in norm^2.
+  constexpr double kReliable = 1e-5;
+  double rstart2[kMaxRhs];
   set_scalar(c, S_ERR, 0.0, 0.0);
   norm2_b(c, b, n, nrhs, G, c.dring);
   WDMG_HIP(hipStreamSynchronize(c.stream));
@@ -490,17 +506,18 @@ int fgcr(Ctx& c, cx<double>* x, const cx<double>* b, int nrhs, const wdmg_solve_
   while (true) {
     update_active();
     if (nact == 0) break;
+    for (int q = 0; q < nrhs; ++q) rstart2[q] = rn2[q];
     for (int j = 0; j < k && nact > 0; ++j) {
-      cx<double>* z = Zb + (size_t)j * bs;
-      cx<double>* w = Wb + (size_t)j * bs;
+      void* z = basis32 ? static_cast<void*>(c.outer_Z32 + (size_t)j * bs) : static_cast<void*>(c.outer_Z + (size_t)j * bs);
+      void* w = basis32 ? static_cast<void*>(c.outer_W32 + (size_t)j * bs) : static_cast<void*>(c.outer_W + (size_t)j * bs);
       if (p.precond) {
         if (!graph) {
           apply_M(z);
         } else if (!gexec) {
           // first application: eager; it also measures the coarsest iterations
           c.last_coarse_iters = 0;
-          apply_M(c.outer_zf);
-          copy<double>(c, z, c.outer_zf, bs);
+          apply_M(zfix);
+          copy_z(z, zfix);
           const int fixed = (3 * c.last_coarse_iters + 1) / 2 + 1;
           // capture the V-cycle on a side stream, then replay it on c.stream
           hipStream_t main_stream = c.stream;
@@ -516,7 +533,7 @@ int fgcr(Ctx& c, cx<double>* x, const cx<double>* b, int nrhs, const wdmg_solve_
           hipError_t e = hipStreamBeginCapture(c.cap_stream, hipStreamCaptureModeRelaxed);
           if (e == hipSuccess) {
             try {
-              apply_M(c.outer_zf);
+              apply_M(zfix);
             } catch (...) {
               (void)hipStreamEndCapture(c.cap_stream, &graph_def);
               if (graph_def) (void)hipGraphDestroy(graph_def);
@@ -542,20 +559,36 @@ int fgcr(Ctx& c, cx<double>* x, const cx<double>* b, int nrhs, const wdmg_solve_
           WDMG_HIP(hipGraphLaunch(gexec, c.stream));
           c.n_D += g_nd;
           for (int l = 0; l < WDMG_MAX_LEVELS; ++l) c.n_Dc[l] += g_ndc[l];
-          copy<double>(c, z, c.outer_zf, bs);
+          copy_z(z, zfix);
         }
+      } else if (basis32) {
+        convert<float, double>(c, static_cast<cx<float>*>(z), r, bs);
       } else {
-        copy<double>(c, z, r, bs);
+        copy<double>(c, static_cast<cx<double>*>(z), r, bs);
       }
-      dslash<double>(c, w, z, nrhs);
-      gcr_orth_b(c, Wb, Zb, w, z, r, n, nrhs, j, G);
-      gcr_step_b(c, w, z, x, r, n, nrhs, G);
+      if (basis32) {
+        cx<float>* w32 = static_cast<cx<float>*>(w);
+        cx<float>* z32 = static_cast<cx<float>*>(z);
+        dslash<float>(c, w32, z32, nrhs);
+        gcr_orth_b<float>(c, c.outer_W32, c.outer_Z32, w32, z32, r, n, nrhs, j, G);
+        gcr_step_b<float>(c, w32, z32, x, r, n, nrhs, G);
+      } else {
+        cx<double>* w64 = static_cast<cx<double>*>(w);
+        cx<double>* z64 = static_cast<cx<double>*>(z);
+        dslash<double>(c, w64, z64, nrhs);
+        gcr_orth_b<double>(c, c.outer_W, c.outer_Z, w64, z64, r, n, nrhs, j, G);
+        gcr_step_b<double>(c, w64, z64, x, r, n, nrhs, G);
+      }
       for (int q = 0; q < nrhs; ++q) st[q].iters += act[q] != 0.0;
       ++total;
       read_rn(rn2);
-      bool changed = false;
-      for (int q = 0; q < nrhs; ++q)
-        if (act[q] != 0.0 && (rn2[q] <= tol2[q] || st[q].iters >= p.maxit)) changed = true;
+      bool changed = false, reliable = basis32;
+      for (int q = 0; q < nrhs; ++q) {
+        if (act[q] == 0.0) continue;
+        if (rn2[q] <= tol2[q] || st[q].iters >= p.maxit) changed = true;
+        if (rn2[q] > kReliable * kReliable * rstart2[q] && rn2[q] > tol2[q]) reliable = false;
+      }
+      if (reliable) break;  // recompute the true residual now
       if (changed) update_active();
     }
     // restart (or claimed convergence): recompute the true residual in FP64
@@ -845,20 +878,35 @@ void ensure_fine_work(Ctx& c) {
   ensure_work<float>(c, 0, 1);
 }
 
-void ensure_outer(Ctx& c, int k, int nrhs, bool need32) {
+void ensure_outer(Ctx& c, int k, int nrhs, bool need32, bool basis32) {
   const size_t n = (size_t)c.g0.vpad * 12;
-  if (k > c.outer_k || nrhs > c.outer_cap) {
+  if (nrhs > c.outer_cap) {
+    WDMG_HIP(hipStreamSynchronize(c.stream));
+    dev_free(c, c.outer_r);
+    c.outer_r = static_cast<cx<double>*>(dev_alloc(c, (size_t)nrhs * n * sizeof(cx<double>)));
+    c.outer_cap = nrhs;
+  }
+  if (!basis32 && (k > c.outer_k || nrhs > c.outer_capB)) {
     WDMG_HIP(hipStreamSynchronize(c.stream));
     dev_free(c, c.outer_Z);
     dev_free(c, c.outer_W);
-    dev_free(c, c.outer_r);
     const int kk = k > c.outer_k ? k : c.outer_k;
-    const int cc = nrhs > c.outer_cap ? nrhs : c.outer_cap;
+    const int cc = nrhs > c.outer_capB ? nrhs : c.outer_capB;
     c.outer_Z = static_cast<cx<double>*>(dev_alloc(c, (size_t)kk * cc * n * sizeof(cx<double>)));
     c.outer_W = static_cast<cx<double>*>(dev_alloc(c, (size_t)kk * cc * n * sizeof(cx<double>)));
-    c.outer_r = static_cast<cx<double>*>(dev_alloc(c, (size_t)cc * n * sizeof(cx<double>)));
     c.outer_k = kk;
-    c.outer_cap = cc;
+    c.outer_capB = cc;
+  }
+  if (basis32 && (k > c.outer_k32 || nrhs > c.outer_capB32)) {
+    WDMG_HIP(hipStreamSynchronize(c.stream));
+    dev_free(c, c.outer_Z32);
+    dev_free(c, c.outer_W32);
+    const int kk = k > c.outer_k32 ? k : c.outer_k32;
+    const int cc = nrhs > c.outer_capB32 ? nrhs : c.outer_capB32;
+    c.outer_Z32 = static_cast<cx<float>*>(dev_alloc(c, (size_t)kk * cc * n * sizeof(cx<float>)));
+    c.outer_W32 = static_cast<cx<float>*>(dev_alloc(c, (size_t)kk * cc * n * sizeof(cx<float>)));
+    c.outer_k32 = kk;
+    c.outer_capB32 = cc;
   }
   if (need32 && nrhs > c.outer_cap32) {
     WDMG_HIP(hipStreamSynchronize(c.stream));

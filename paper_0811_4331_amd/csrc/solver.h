@@ -44,7 +44,7 @@ void mg_setup(Ctx& c, const wdmg_mg_params& p);
 void free_hierarchy(Ctx& c);
 void init_level0(Ctx& c);
 void ensure_fine_work(Ctx& c);
-void ensure_outer(Ctx& c, int k, int nrhs, bool need32);
+void ensure_outer(Ctx& c, int k, int nrhs, bool need32, bool basis32);
 void ensure_bicg(Ctx& c);
 
 }  // namespace wdmg
