@@ -221,7 +221,9 @@ def dslash_bandwidth(wdmg, synthetic, torch, dev, L, reps=20):
         sec = ms / 1e3 / n
         out[prec + "_8rhs"] = {"lattice": f"{L}^4 x 8 rhs", "us_per_launch": sec * 1e6,
                                "ns_per_site_rhs": sec / units * n * 1e9,
-                               "GB_s_alg_single_rhs_bytes": DSLASH_BYTES[prec] * units / n / sec / 1e9}
+                               "GB_s_alg_single_rhs_bytes": DSLASH_BYTES[prec] * units / n / sec / 1e9,
+                               "form": ctx.get_tuning("dslash", prec, 8),
+                               "rhs_group": ctx.get_tuning("dslash_group", prec, 8)}
     ctx.close()
     return out
 

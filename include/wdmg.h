@@ -103,7 +103,12 @@ typedef struct {
   int precond;           /* 0: plain GCR, 1: multigrid V-cycle                      */
   int mg_prec;           /* precision of the V-cycle: WDMG_F64, WDMG_F32, or WDMG_F16 /
                             WDMG_BF16 (16-bit fine fields, links, P and intermediate
-                            coarse operators; the coarsest solve stays FP64)        */
+                            coarse operators; the coarsest solve stays FP64).  Below
+                            FP64 the outer basis z_j, w_j = D z_j is stored and
+                            applied in FP32 (sums in FP64; x, r and the true
+                            residual of every restart stay FP64), and a cycle
+                            restarts from the true residual once its recursive
+                            residual has fallen by 1e-5.                          */
   int use_graph;         /* 1: the first V-cycle of a solve runs as usual; it is then
                             captured once in a HIP graph that later iterations replay.
                             Inside the graph the coarsest GCR runs a fixed number of
@@ -217,8 +222,14 @@ int wdmg_solve_bicgstab(wdmg_ctx* ctx, void* x, const void* b, int nrhs, double 
  * keeps the fastest for the context's lifetime; a fixed value forces a form.
  *   WDMG_TUNE_DSLASH: 0 one thread per site, 1 one wave per direction with
  *                     the four partial sums added in LDS, 2 form 1 with its
- *                     registers capped so that four waves fit per SIMD. */
-enum { WDMG_TUNE_AUTO = -1, WDMG_TUNE_DSLASH = 0, WDMG_TUNE_COUNT };
+ *                     registers capped so that four waves fit per SIMD.
+ *   WDMG_TUNE_DSLASH_GROUP: right-hand sides per group (1..64) in the
+ *                     workgroup order of a batched Wilson launch: each XCD
+ *                     sweeps its lattice region once per group, with the
+ *                     group's rhs of one site block back to back (a value
+ *                     above the batch size means the whole batch).  Tuned
+ *                     after the form. */
+enum { WDMG_TUNE_AUTO = -1, WDMG_TUNE_DSLASH = 0, WDMG_TUNE_DSLASH_GROUP = 1, WDMG_TUNE_COUNT };
 int wdmg_set_tuning(wdmg_ctx* ctx, int key, int value);
 /* Current choice for key (WDMG_TUNE_AUTO until tuned) for precision prec
  * and batch size nrhs. */

@@ -271,6 +271,7 @@ int wdmg_create(wdmg_ctx** out, const int dims[4], const wdmg_alloc* alloc, void
   if (!c) return WDMG_ERR_OOM;
   std::memcpy(c->dims, dims, sizeof(c->dims));
   std::memset(c->tune_dslash, -1, sizeof(c->tune_dslash));
+  std::memset(c->tune_group, -1, sizeof(c->tune_group));
   for (int k = 0; k < WDMG_TUNE_COUNT; ++k) c->tune_force[k] = WDMG_TUNE_AUTO;
   int B[4];
   for (int mu = 0; mu < 4; ++mu) B[mu] = dims[mu] % 4 == 0 ? 4 : (dims[mu] % 2 == 0 ? 2 : 1);
@@ -588,8 +589,9 @@ int wdmg_solve_bicgstab(wdmg_ctx* c, void* x, const void* b, int nrhs, double to
 
 int wdmg_set_tuning(wdmg_ctx* c, int key, int value) {
   return guarded(c, [&]() {
-    if (key != WDMG_TUNE_DSLASH) throw Error(WDMG_ERR_ARG, "unknown tuning key");
-    if (value != WDMG_TUNE_AUTO && (value < 0 || value > 2)) throw Error(WDMG_ERR_ARG, "bad tuning value");
+    if (key != WDMG_TUNE_DSLASH && key != WDMG_TUNE_DSLASH_GROUP) throw Error(WDMG_ERR_ARG, "unknown tuning key");
+    const int hi = key == WDMG_TUNE_DSLASH ? 2 : kMaxRhs, lo = key == WDMG_TUNE_DSLASH ? 0 : 1;
+    if (value != WDMG_TUNE_AUTO && (value < lo || value > hi)) throw Error(WDMG_ERR_ARG, "bad tuning value");
     c->tune_force[key] = value;
     return WDMG_OK;
   });
@@ -598,11 +600,13 @@ int wdmg_set_tuning(wdmg_ctx* c, int key, int value) {
 int wdmg_get_tuning(wdmg_ctx* c, int key, int prec, int nrhs, int* value) {
   return guarded(c, [&]() {
     need_ptr(value, "value");
-    if (key != WDMG_TUNE_DSLASH) throw Error(WDMG_ERR_ARG, "unknown tuning key");
+    if (key != WDMG_TUNE_DSLASH && key != WDMG_TUNE_DSLASH_GROUP) throw Error(WDMG_ERR_ARG, "unknown tuning key");
     need_prec(prec);
     need_nrhs(nrhs);
-    *value = c->tune_force[key] >= 0 ? c->tune_force[key]
-                                     : (int)c->tune_dslash[prec][nrhs < kMaxRhs ? nrhs : kMaxRhs];
+    const int slot = nrhs < kMaxRhs ? nrhs : kMaxRhs;
+    *value = c->tune_force[key] >= 0           ? c->tune_force[key]
+             : key == WDMG_TUNE_DSLASH ? (int)c->tune_dslash[prec][slot]
+                                       : (int)c->tune_group[prec][slot];
     return WDMG_OK;
   });
 }

@@ -97,9 +97,11 @@ __device__ __forceinline__ void hop(const IO& io, int nb, int link_site, bool ne
 // (vol <= s < vpad) are written as zeros.
 // Workgroup order for a batch of nrhs fields over nsb site blocks: the hardware
 // sends workgroup b to XCD b % 8.  Each XCD takes a contiguous run of site
-// blocks (spatial neighbours share its L2) and, within it, all right-hand
-// sides of one site block back to back (its links are read once from HBM).
-__device__ __forceinline__ void batch_block(int nsb, int nrhs, int& sb, int& rhs) {
+// blocks (spatial neighbours share its L2) and sweeps it once per group of rg
+// right-hand sides, the rhs of a group back to back on each site block (its
+// links come from HBM once per group).  Small groups keep more site blocks in
+// flight (neighbour spinors stay in L2); large ones share links more.
+__device__ __forceinline__ void batch_block(int nsb, int nrhs, int rg, int& sb, int& rhs) {
   const int b = blockIdx.x;
   if ((nsb & 7) || nrhs == 1) {
     if (nrhs == 1) {
@@ -111,9 +113,13 @@ __device__ __forceinline__ void batch_block(int nsb, int nrhs, int& sb, int& rhs
     }
     return;
   }
-  const int xcd = b & 7, local = b >> 3;
-  sb = xcd * (nsb >> 3) + local / nrhs;
-  rhs = local % nrhs;
+  const int xcd = b & 7, local = b >> 3, nsb8 = nsb >> 3;
+  if (rg < 1 || rg > nrhs) rg = nrhs;
+  const int g = local / (nsb8 * rg);
+  const int size = min(rg, nrhs - g * rg);
+  const int off = local - g * nsb8 * rg;
+  sb = xcd * nsb8 + off / size;
+  rhs = g * rg + off % size;
 }
 
 // MR step-size partial sums of one wave (Sec. 3 smoother): Re and Im of
@@ -147,9 +153,9 @@ __device__ __forceinline__ void wave_dots(bool live, const cx<R> (&out)[12], con
 
 template <class IO, bool DOTS, typename R = typename IO::T>
 __global__ __launch_bounds__(kDslashThreads) void k_dslash(Geom g, IO io, R diag, int tneg, int nsb, int nrhs,
-                                                           double* dots) {
+                                                           int rg, double* dots) {
   int sb, rhs;
-  batch_block(nsb, nrhs, sb, rhs);
+  batch_block(nsb, nrhs, rg, sb, rhs);
   const int s = sb * kDslashThreads + threadIdx.x;
   io.select_rhs(rhs, g.vpad);
   cx<R> acc[12];
@@ -215,10 +221,11 @@ constexpr int kDs4Sites = 64;
 template <class IO, bool DOTS, int MINW, typename R = typename IO::T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MINW))) void k_dslash4(Geom g, IO io, R diag,
                                                                                             int tneg, int nsb,
-                                                                                            int nrhs, double* dots) {
+                                                                                            int nrhs, int rg,
+                                                                                            double* dots) {
   __shared__ cx<R> part[3][12][kDs4Sites];
   int sb, rhs;
-  batch_block(nsb, nrhs, sb, rhs);
+  batch_block(nsb, nrhs, rg, sb, rhs);
   const int lane = threadIdx.x & 63, mu = threadIdx.x >> 6;
   const int s = sb * kDs4Sites + lane;
   io.select_rhs(rhs, g.vpad);
@@ -263,7 +270,7 @@ int dslash_parts(const Geom& g, int variant) {
 }
 
 template <class IO>
-void run_dslash(Ctx& c, const IO& io, int nrhs, int variant, double* dots = nullptr) {
+void run_dslash(Ctx& c, const IO& io, int nrhs, int variant, int rg, double* dots = nullptr) {
   const Geom& g = c.g0;
   const int tneg = c.t_bc < 0 ? 1 : 0;
   using R = typename IO::T;
@@ -273,23 +280,23 @@ void run_dslash(Ctx& c, const IO& io, int nrhs, int variant, double* dots = null
     const R diag = (R)(4.0 + c.mass);
     if (variant == 1) {
       if (dots)
-        hipLaunchKernelGGL((k_dslash4<IO, true, 1>), grid, block, 0, c.stream, g, io, diag, tneg, (int)gx, nrhs, dots);
+        hipLaunchKernelGGL((k_dslash4<IO, true, 1>), grid, block, 0, c.stream, g, io, diag, tneg, (int)gx, nrhs, rg, dots);
       else
-        hipLaunchKernelGGL((k_dslash4<IO, false, 1>), grid, block, 0, c.stream, g, io, diag, tneg, (int)gx, nrhs, dots);
+        hipLaunchKernelGGL((k_dslash4<IO, false, 1>), grid, block, 0, c.stream, g, io, diag, tneg, (int)gx, nrhs, rg, dots);
     } else {
       if (dots)
-        hipLaunchKernelGGL((k_dslash4<IO, true, 4>), grid, block, 0, c.stream, g, io, diag, tneg, (int)gx, nrhs, dots);
+        hipLaunchKernelGGL((k_dslash4<IO, true, 4>), grid, block, 0, c.stream, g, io, diag, tneg, (int)gx, nrhs, rg, dots);
       else
-        hipLaunchKernelGGL((k_dslash4<IO, false, 4>), grid, block, 0, c.stream, g, io, diag, tneg, (int)gx, nrhs, dots);
+        hipLaunchKernelGGL((k_dslash4<IO, false, 4>), grid, block, 0, c.stream, g, io, diag, tneg, (int)gx, nrhs, rg, dots);
     }
   } else {
     const unsigned gx = g.vpad / kDslashThreads + (g.vpad % kDslashThreads != 0);
     if (dots)
       hipLaunchKernelGGL((k_dslash<IO, true>), dim3(gx * nrhs), dim3(kDslashThreads), 0, c.stream, g, io,
-                         (R)(4.0 + c.mass), tneg, (int)gx, nrhs, dots);
+                         (R)(4.0 + c.mass), tneg, (int)gx, nrhs, rg, dots);
     else
       hipLaunchKernelGGL((k_dslash<IO, false>), dim3(gx * nrhs), dim3(kDslashThreads), 0, c.stream, g, io,
-                         (R)(4.0 + c.mass), tneg, (int)gx, nrhs, dots);
+                         (R)(4.0 + c.mass), tneg, (int)gx, nrhs, rg, dots);
   }
   WDMG_HIP(hipGetLastError());
 }
@@ -300,37 +307,65 @@ void run_dslash(Ctx& c, const IO& io, int nrhs, int variant, double* dots = null
 constexpr int kDslashForms = 3;
 
 template <class IO>
-int tune_dslash(Ctx& c, const IO& io, int nrhs) {
-  hipEvent_t ev[3];
+float time_dslash(Ctx& c, const IO& io, int nrhs, int v, int rg, hipEvent_t (&ev)[2]) {
+  run_dslash(c, io, nrhs, v, rg);
+  WDMG_HIP(hipEventRecord(ev[0], c.stream));
+  for (int i = 0; i < 3; ++i) run_dslash(c, io, nrhs, v, rg);
+  WDMG_HIP(hipEventRecord(ev[1], c.stream));
+  WDMG_HIP(hipEventSynchronize(ev[1]));
+  float ms = 0.f;
+  WDMG_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+  return ms;
+}
+
+// Picks the form (rhs groups of the whole batch), then, for a batch, the rhs
+// group size among 1, 2, 4, ... and nrhs with that form.  Forced values
+// (wdmg_set_tuning) are kept and not timed.
+template <class IO>
+void tune_dslash(Ctx& c, const IO& io, int nrhs, int& form, int& rg) {
+  hipEvent_t ev[2];
   for (auto& e : ev) WDMG_HIP(hipEventCreate(&e));
-  float ms[kDslashForms] = {};
-  for (int v = 0; v < kDslashForms; ++v) {
-    run_dslash(c, io, nrhs, v);
-    WDMG_HIP(hipEventRecord(ev[0], c.stream));
-    for (int i = 0; i < 3; ++i) run_dslash(c, io, nrhs, v);
-    WDMG_HIP(hipEventRecord(ev[1], c.stream));
-    WDMG_HIP(hipEventSynchronize(ev[1]));
-    WDMG_HIP(hipEventElapsedTime(&ms[v], ev[0], ev[1]));
+  if (form < 0) {
+    float ms[kDslashForms] = {};
+    for (int v = 0; v < kDslashForms; ++v) ms[v] = time_dslash(c, io, nrhs, v, rg < 0 ? nrhs : rg, ev);
+    form = 1;
+    for (int v = 0; v < kDslashForms; ++v)
+      if (ms[v] < ms[form]) form = v;
+  }
+  if (rg < 0) {
+    rg = nrhs;
+    if (nrhs > 1) {
+      float best = time_dslash(c, io, nrhs, form, nrhs, ev);
+      for (int cand = 1; cand < nrhs; cand *= 2) {
+        const float t = time_dslash(c, io, nrhs, form, cand, ev);
+        if (t < best) {
+          best = t;
+          rg = cand;
+        }
+      }
+    }
   }
   for (auto& e : ev) (void)hipEventDestroy(e);
-  int best = 1;
-  for (int v = 0; v < kDslashForms; ++v)
-    if (ms[v] < ms[best]) best = v;
-  return best;
 }
 
 // Runs the operator in the tuned form; with `dots` the launch also writes the
 // MR partial sums and the return value is the number of slots per rhs.
 template <class IO>
 int launch_dslash(Ctx& c, const IO& io, int nrhs, int prof_id, int prec_index, double* dots = nullptr) {
-  int v = c.tune_force[WDMG_TUNE_DSLASH];
-  if (v < 0) {
-    signed char& slot = c.tune_dslash[prec_index][nrhs < kMaxRhs ? nrhs : kMaxRhs];
-    if (slot < 0 && !c.capturing) slot = (signed char)tune_dslash(c, io, nrhs);
-    v = slot < 0 ? 1 : slot;
+  const int key = nrhs < kMaxRhs ? nrhs : kMaxRhs;
+  signed char& fslot = c.tune_dslash[prec_index][key];
+  signed char& gslot = c.tune_group[prec_index][key];
+  int v = c.tune_force[WDMG_TUNE_DSLASH] >= 0 ? c.tune_force[WDMG_TUNE_DSLASH] : fslot;
+  int rg = c.tune_force[WDMG_TUNE_DSLASH_GROUP] >= 0 ? c.tune_force[WDMG_TUNE_DSLASH_GROUP] : gslot;
+  if ((v < 0 || rg < 0) && !c.capturing) {
+    tune_dslash(c, io, nrhs, v, rg);
+    if (c.tune_force[WDMG_TUNE_DSLASH] < 0) fslot = (signed char)v;
+    if (c.tune_force[WDMG_TUNE_DSLASH_GROUP] < 0) gslot = (signed char)rg;
   }
+  if (v < 0) v = 1;
+  if (rg < 0) rg = nrhs;
   ProfScope ps(c, prof_id, (long long)c.g0.vol * nrhs);
-  run_dslash(c, io, nrhs, v, dots);
+  run_dslash(c, io, nrhs, v, rg, dots);
   c.n_D += nrhs;
   return dslash_parts(c.g0, v);
 }

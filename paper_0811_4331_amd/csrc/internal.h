@@ -156,6 +156,7 @@ struct Ctx {
   // autotuner's choices per (precision, batch size)
   int tune_force[WDMG_TUNE_COUNT] = {-1};
   signed char tune_dslash[4][kMaxRhs + 1];
+  signed char tune_group[4][kMaxRhs + 1];  // rhs group size of batched Wilson launches
   // HIP-graph capture of a V-cycle: while capturing, the coarsest GCR runs
   // exactly coarse_fixed_iters iterations with no host interaction
   bool capturing = false;

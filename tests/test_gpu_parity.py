@@ -358,6 +358,30 @@ def test_solve_with_graph_captured_vcycle(prec, nrhs):
             assert sg[j]["iters"] <= se[j]["iters"] + 3, (sg[j]["iters"], se[j]["iters"])
 
 
+@pytest.mark.parametrize("form", [0, 1])
+@pytest.mark.parametrize("group", [1, 2, 3, 7, 64])
+def test_batched_dslash_rhs_groups_match_oracle(form, group):
+    """Every rhs group size of the batched workgroup order (groups of 1, 2,
+    uneven 3 of 7, the whole batch, more than the batch) gives the oracle's
+    operator on every right-hand side."""
+    dims, nrhs, m = (8, 8, 8, 8), 7, -0.37
+    ctx, u = make_ctx(dims, 0.35, 404, m)
+    ctx.set_tuning("dslash", form)
+    ctx.set_tuning("dslash_group", group)
+    psi = synthetic.gaussian_spinor(dims, seed=23, nrhs=nrhs)
+    ref = wilson.apply_D(u, psi, m, -1.0)
+    out = ctx.apply_D(gpu(psi)).cpu().numpy()
+    for j in range(nrhs):
+        assert rel(out[j], ref[j]) < 1e-13, j
+    assert ctx.get_tuning("dslash_group", "f64", nrhs) == group
+    ctx.set_tuning("dslash_group", None)
+    ctx.set_tuning("dslash", None)
+    out2 = ctx.apply_D(gpu(psi)).cpu().numpy()  # autotuned form and group
+    for j in range(nrhs):
+        assert rel(out2[j], ref[j]) < 1e-13, j
+    assert 1 <= ctx.get_tuning("dslash_group", "f64", nrhs) <= nrhs
+
+
 @pytest.mark.parametrize("form", [0, 1, 2])
 @pytest.mark.parametrize("dims,nrhs", [((8, 8, 8, 8), 1), ((6, 4, 2, 10), 3), ((2, 2, 2, 2), 2)])
 def test_both_dslash_forms_match_oracle(form, dims, nrhs):
