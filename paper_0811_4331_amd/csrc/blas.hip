@@ -697,7 +697,8 @@ __global__ __launch_bounds__(TPB) void k_gcr_dots_b(const cx<B>* __restrict__ W,
 __global__ __launch_bounds__(TPB) void k_gcr_dots_b_fin(int j, int gx, int gy, const double* partials, double* g) {
   const int rhs = blockIdx.x;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = TPB / 64;
-  for (int t = wave; t < 2 * j; t += nw) {
+  // blockIdx.y selects nw coefficients, one per wave
+  for (int t = blockIdx.y * nw + wave; t < 2 * j; t += nw * gridDim.y) {
     const int i = t >> 1, part = t & 1;
     const int yy = i / GCR_G, q = i % GCR_G;
     double s = 0.0;
@@ -944,7 +945,8 @@ void gcr_orth_b(Ctx& c, const cx<B>* W, const cx<B>* Z, cx<B>* w, cx<B>* z, cons
     hipLaunchKernelGGL(k_gcr_dots_b<B>, dim3(gx, gy, nb), dim3(TPB), 0, c.stream, W, w, n, nb, j, gx, gy,
                        c.partials);
     WDMG_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_gcr_dots_b_fin, dim3(nb), dim3(TPB), 0, c.stream, j, gx, gy, c.partials, g);
+    hipLaunchKernelGGL(k_gcr_dots_b_fin, dim3(nb, (2 * j + TPB / 64 - 1) / (TPB / 64)), dim3(TPB), 0, c.stream, j, gx,
+                       gy, c.partials, g);
     WDMG_HIP(hipGetLastError());
   }
   run_reduce_b(c, GcrAxpyCoefBOp<B>{W, Z, w, z, r, g, c.dsc, n, nb, j}, n, nb);

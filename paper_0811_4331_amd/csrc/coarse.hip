@@ -976,6 +976,23 @@ __device__ __forceinline__ double rhs_column_sum(double v, int nrhs, int rows, d
   return sum;
 }
 
+// The same for K values per thread at once (red holds K x 256 doubles): value
+// k of rhs q is summed by thread k * nrhs + q (looping when K * nrhs > 256)
+// and handed to put(k, q, sum).
+template <int K, class Put>
+__device__ __forceinline__ void rhs_column_sums(const double (&v)[K], int nrhs, int rows, double* red, Put put) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) red[k * 256 + threadIdx.x] = v[k];
+  __syncthreads();
+  for (int u = threadIdx.x; u < K * nrhs; u += 256) {
+    const int k = u / nrhs, q = u % nrhs;
+    double sum = 0.0;
+    for (int rr = 0; rr < rows; ++rr) sum += red[k * 256 + rr * nrhs + q];
+    put(k, q, sum);
+  }
+  __syncthreads();
+}
+
 // r = b and x = 0 in the rhs-fast layout; partial |b_q|^2 per workgroup.
 __global__ __launch_bounds__(256) void k_cgcrT_init(size_t npos, int nrhs, const cx<double>* __restrict__ b,
                                                     cx<double>* __restrict__ xT, cx<double>* __restrict__ rT,
@@ -1038,12 +1055,12 @@ __global__ __launch_bounds__(256) void k_cgcrT_dots(size_t npos, int nrhs, int j
                                                     const cx<double>* __restrict__ Wb,
                                                     const cx<double>* __restrict__ w,
                                                     const cx<double>* __restrict__ r, double* part) {
-  __shared__ double red[256];
+  __shared__ double red[4 * kCgcrDotIG * 256];
   const int rows = 256 / nrhs, q = threadIdx.x % nrhs, rho = threadIdx.x / nrhs;
   const bool on = rho < rows;
   const size_t bs = npos * nrhs;
   const size_t cs = (npos + gridDim.x - 1) / gridDim.x, p0 = blockIdx.x * cs, p1 = p0 + cs < npos ? p0 + cs : npos;
-  double* out = part + ((size_t)threadIdx.x * gridDim.x + blockIdx.x) * vals;  // used by threads < nrhs
+  auto out = [&](int qq) { return part + ((size_t)qq * gridDim.x + blockIdx.x) * vals; };
   for (int i0 = 0; i0 == 0 || i0 < j; i0 += kCgcrDotIG) {
     const int ni = j - i0 < kCgcrDotIG ? j - i0 : kCgcrDotIG;
     double a[kCgcrDotIG][4] = {}, nv[4] = {};
@@ -1069,31 +1086,18 @@ __global__ __launch_bounds__(256) void k_cgcrT_dots(size_t npos, int nrhs, int j
         }
       }
     }
+    // value k = 4 u + c of this pass: c = 0, 1 -> c_i (re, im), 2, 3 -> d_i
+    double flat[4 * kCgcrDotIG];
 #pragma unroll
-    for (int u = 0; u < kCgcrDotIG; ++u) {
-      if (u < ni) {
-        const int i = i0 + u;
-        const double s0 = rhs_column_sum(a[u][0], nrhs, rows, red);
-        const double s1 = rhs_column_sum(a[u][1], nrhs, rows, red);
-        const double s2 = rhs_column_sum(a[u][2], nrhs, rows, red);
-        const double s3 = rhs_column_sum(a[u][3], nrhs, rows, red);
-        if ((int)threadIdx.x < nrhs) {
-          out[2 * i] = s0;
-          out[2 * i + 1] = s1;
-          out[2 * j + 2 * i] = s2;
-          out[2 * j + 2 * i + 1] = s3;
-        }
-      }
-    }
-    if (i0 == 0) {
-      double t[4];
+    for (int u = 0; u < kCgcrDotIG; ++u)
 #pragma unroll
-      for (int k = 0; k < 4; ++k) t[k] = rhs_column_sum(nv[k], nrhs, rows, red);
-      if ((int)threadIdx.x < nrhs) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) out[4 * j + k] = t[k];
-      }
-    }
+      for (int cc = 0; cc < 4; ++cc) flat[4 * u + cc] = a[u][cc];
+    rhs_column_sums<4 * kCgcrDotIG>(flat, nrhs, rows, red, [&](int k, int qq, double sum) {
+      const int u = k >> 2, cc = k & 3, i = i0 + u;
+      if (u < ni) out(qq)[cc < 2 ? 2 * i + cc : 2 * j + 2 * i + (cc - 2)] = sum;
+    });
+    if (i0 == 0)
+      rhs_column_sums<4>(nv, nrhs, rows, red, [&](int k, int qq, double sum) { out(qq)[4 * j + k] = sum; });
   }
 }
 

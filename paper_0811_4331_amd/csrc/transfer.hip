@@ -322,34 +322,49 @@ __global__ __launch_bounds__(256) void k_prolong0_h(AggMap map, const cxh<H>* __
 // Chunks of 64 rows (one spin-colour component on 64 aggregate sites) of V
 // and of the fields are staged in LDS with coalesced loads, then fed to
 // v_mfma_f32_32x32x2f32 (lanes as in the coarse-operator kernel).
+// Operand loaders of the batched restriction: raw() issues the load, conv()
+// turns its result into FP32 (kept apart so a load can be in flight while
+// matrix-core work runs, and converted only when it is stored to LDS).
 struct FieldF32 {  // plain FP32 fine fields [rhs][12 vpad]
   const cx<float>* f;
   int vpad;
-  __device__ __forceinline__ cx<float> get(int q, int site, int comp) const {
+  using Raw = cx<float>;
+  __device__ __forceinline__ Raw raw(int q, int site, int comp) const {
     return f[(size_t)q * 12 * vpad + fidx(site, comp, 12)];
   }
+  __device__ __forceinline__ static cx<float> conv(Raw r) { return r; }
 };
 template <typename H>
 struct FieldH {  // 16-bit fine fields with per-site scales
   const cxh<H>* v;
   const float* sc;
   int vpad;
-  __device__ __forceinline__ cx<float> get(int q, int site, int comp) const {
-    const float s = sc[(size_t)q * vpad + site];
-    const cx<float> x = h2f(v[(size_t)q * 12 * vpad + fidx(site, comp, 12)]);
-    return mk(s * x.re, s * x.im);
+  struct Raw {
+    cxh<H> x;
+    float s;
+  };
+  __device__ __forceinline__ Raw raw(int q, int site, int comp) const {
+    return {v[(size_t)q * 12 * vpad + fidx(site, comp, 12)], sc[(size_t)q * vpad + site]};
+  }
+  __device__ __forceinline__ static cx<float> conv(Raw r) {
+    const cx<float> x = h2f(r.x);
+    return mk(r.s * x.re, r.s * x.im);
   }
 };
 struct VF32 {
   const cx<float>* v;
   size_t stride;
-  __device__ __forceinline__ cx<float> get(int k, size_t off) const { return v[(size_t)k * stride + off]; }
+  using Raw = cx<float>;
+  __device__ __forceinline__ Raw raw(int k, size_t off) const { return v[(size_t)k * stride + off]; }
+  __device__ __forceinline__ static cx<float> conv(Raw r) { return r; }
 };
 template <typename H>
 struct VH {
   const cxh<H>* v;
   size_t stride;
-  __device__ __forceinline__ cx<float> get(int k, size_t off) const { return h2f(v[(size_t)k * stride + off]); }
+  using Raw = cxh<H>;
+  __device__ __forceinline__ Raw raw(int k, size_t off) const { return v[(size_t)k * stride + off]; }
+  __device__ __forceinline__ static cx<float> conv(Raw r) { return h2f(r); }
 };
 
 typedef float floatx16_t __attribute__((ext_vector_type(16)));
@@ -370,20 +385,39 @@ __global__ __launch_bounds__(256) void k_restrict0_mfma(AggMap map, VL V, FL F, 
 #pragma unroll
   for (int e = 0; e < 16; ++e) acc[e] = 0.f;
   const int per = map.bvol / 64;
-  for (int c = 0; c < 6 * per; ++c) {
+  // Staging: for chunk c (component pair m, 64 sites from l0) thread t loads
+  // site l0 + (t & 63), columns k = t / 64 + 4u and rhs q0 + t / 64 + 4u
+  // (nv, nq <= 32: u < 8).  The loads of chunk c + 1 are issued before the
+  // matrix-core work of chunk c and stored to LDS after it.
+  const int ll = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  typename VL::Raw vr[2][8];
+  typename FL::Raw fr[2][8];
+  auto load = [&](int c) {
     const int m = c / per, l0 = (c % per) * 64;
+    const int site = map.site(agg, l0 + ll);
+#pragma unroll
+    for (int ch = 0; ch < 2; ++ch) {
+      const size_t off = fidx(site, 6 * ch + m, 12);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (grp + 4 * u < nv) vr[ch][u] = V.raw(grp + 4 * u, off);
+        if (grp + 4 * u < nq) fr[ch][u] = F.raw(q0 + grp + 4 * u, site, 6 * ch + m);
+      }
+    }
+  };
+  load(0);
+  for (int c = 0; c < 6 * per; ++c) {
     __syncthreads();
-    // stage: thread t loads site l0 + (t & 63) for several k / q
-    {
-      const int ll = threadIdx.x & 63, grp = threadIdx.x >> 6;
-      const int site = map.site(agg, l0 + ll);
-      for (int ch = 0; ch < 2; ++ch) {
-        const size_t off = fidx(site, 6 * ch + m, 12);
-        for (int k = grp; k < nv; k += 4) Vs[ch][ll][k] = V.get(k, off);
-        for (int qq = grp; qq < nq; qq += 4) Fs[ch][ll][qq] = F.get(q0 + qq, site, 6 * ch + m);
+#pragma unroll
+    for (int ch = 0; ch < 2; ++ch) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (grp + 4 * u < nv) Vs[ch][ll][grp + 4 * u] = VL::conv(vr[ch][u]);
+        if (grp + 4 * u < nq) Fs[ch][ll][grp + 4 * u] = FL::conv(fr[ch][u]);
       }
     }
     __syncthreads();
+    if (c + 1 < 6 * per) load(c + 1);
 #pragma unroll 4
     for (int kk = 0; kk < 128; kk += 2) {
       const int kr = kk + (l >> 5), r = kr >> 1, pk = kr & 1;
