@@ -248,90 +248,6 @@ struct StepAlphaHalfOp {
   }
 };
 
-// GCR: nrm_j = <w,w>, a = <w,r>/nrm_j.
-struct GcrCoefOp {
-  static constexpr int K = 3;
-  const cx<double>* w;
-  const cx<double>* r;
-  double* dsc;
-  int nrmslot, aslot;
-  __device__ void acc(size_t i, double* v) const {
-    const cx<double> x = w[i], y = r[i];
-    v[0] += x.re * x.re + x.im * x.im;
-    v[1] += x.re * y.re + x.im * y.im;
-    v[2] += x.re * y.im - x.im * y.re;
-  }
-  __device__ void fin(const double* v) const {
-    if (bad(v[0]) || bad(v[1]) || bad(v[2])) dsc[S_ERR] = 1.0;
-    dsc[nrmslot] = v[0];
-    dsc[aslot] = v[0] > 0.0 ? v[1] / v[0] : 0.0;
-    dsc[aslot + 1] = v[0] > 0.0 ? v[2] / v[0] : 0.0;
-  }
-};
-
-// w -= sum_i h_i W_i ; z -= sum_i h_i Z_i  (i < j), then nrm_j = <w,w> and
-// a = <w, r> / nrm_j, in one pass.
-struct GcrAxpyCoefOp {
-  static constexpr int K = 3;
-  const cx<double>* W;
-  const cx<double>* Z;
-  cx<double>* w;
-  cx<double>* z;
-  const cx<double>* r;
-  const double* h;
-  size_t n;
-  int j;
-  double* dsc;
-  int nrmslot, aslot;
-  __device__ void acc(size_t e, double* v) const {
-    cx<double> a = w[e], b = z[e];
-    for (int i = 0; i < j; ++i) {
-      const cx<double> hi = mk(h[2 * i], h[2 * i + 1]);
-      a = a - hi * W[(size_t)i * n + e];
-      b = b - hi * Z[(size_t)i * n + e];
-    }
-    if (j > 0) {
-      w[e] = a;
-      z[e] = b;
-    }
-    const cx<double> y = r[e];
-    v[0] += a.re * a.re + a.im * a.im;
-    v[1] += a.re * y.re + a.im * y.im;
-    v[2] += a.re * y.im - a.im * y.re;
-  }
-  __device__ void fin(const double* v) const {
-    if (bad(v[0]) || bad(v[1]) || bad(v[2])) dsc[S_ERR] = 1.0;
-    dsc[nrmslot] = v[0];
-    dsc[aslot] = v[0] > 0.0 ? v[1] / v[0] : 0.0;
-    dsc[aslot + 1] = v[0] > 0.0 ? v[2] / v[0] : 0.0;
-  }
-};
-
-// x += a z; r -= a w; ||r||^2 (also to a host-visible slot when given).
-struct GcrUpdateOp {
-  static constexpr int K = 1;
-  const cx<double>* w;
-  const cx<double>* z;
-  cx<double>* x;
-  cx<double>* r;
-  const double* a;
-  double* dsc;
-  int rslot;
-  double* host;
-  __device__ void acc(size_t i, double* v) const {
-    const cx<double> s = mk(a[0], a[1]);
-    x[i] = x[i] + s * z[i];
-    const cx<double> ri = r[i] - s * w[i];
-    r[i] = ri;
-    v[0] += ri.re * ri.re + ri.im * ri.im;
-  }
-  __device__ void fin(const double* v) const {
-    if (bad(v[0])) dsc[S_ERR] = 1.0;
-    dsc[rslot] = v[0];
-    if (host) host[0] = v[0];
-  }
-};
-
 struct XmyNormOp {
   static constexpr int K = 1;
   const cx<double>* b;
@@ -538,60 +454,6 @@ __global__ void k_bicg_s(cx<double>* s, const cx<double>* r, const cx<double>* v
 // vectors per workgroup row (blockIdx.y), then one workgroup finalises all
 // coefficients h_i = <W_i, w> / nrm_i.
 constexpr int GCR_G = 8;
-__global__ __launch_bounds__(TPB) void k_gcr_dots(const cx<double>* __restrict__ W, const cx<double>* __restrict__ w,
-                                                  size_t n, int j, double* partials) {
-  __shared__ double lds[2 * GCR_G * (TPB / 64)];
-  const int i0 = blockIdx.y * GCR_G;
-  const int ni = min(GCR_G, j - i0);
-  double v[2 * GCR_G];
-#pragma unroll
-  for (int k = 0; k < 2 * GCR_G; ++k) v[k] = 0.0;
-  for (size_t e = blockIdx.x * (size_t)TPB + threadIdx.x; e < n; e += (size_t)gridDim.x * TPB) {
-    const cx<double> y = w[e];
-#pragma unroll
-    for (int q = 0; q < GCR_G; ++q) {
-      if (q < ni) {
-        const cx<double> x = W[(size_t)(i0 + q) * n + e];
-        v[2 * q] += x.re * y.re + x.im * y.im;
-        v[2 * q + 1] += x.re * y.im - x.im * y.re;
-      }
-    }
-  }
-  block_sum<2 * GCR_G>(v, lds);
-  if (threadIdx.x == 0) {
-    const size_t myblk = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
-#pragma unroll
-    for (int k = 0; k < 2 * GCR_G; ++k) partials[myblk * 2 * GCR_G + k] = v[k];
-  }
-}
-
-__global__ __launch_bounds__(TPB) void k_gcr_dots_fin(int j, int gx, const double* partials, double* dsc, int hslot,
-                                                      int nrmslot) {
-  // thread t finalises value t = (basis vector, re/im); workgroups summed in order
-  for (int t = threadIdx.x; t < 2 * j; t += TPB) {
-    const int i = t >> 1, part = t & 1;
-    const int gy = i / GCR_G, q = i % GCR_G;
-    double s = 0.0;
-    for (int bx = 0; bx < gx; ++bx) s += partials[((size_t)gy * gx + bx) * 2 * GCR_G + 2 * q + part];
-    const double nrm = dsc[nrmslot + i];
-    dsc[hslot + t] = nrm > 0.0 ? s / nrm : 0.0;
-  }
-}
-
-__global__ void k_gcr_axpy(const cx<double>* __restrict__ W, const cx<double>* __restrict__ Z, cx<double>* w,
-                           cx<double>* z, size_t n, int j, const double* h) {
-  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
-    cx<double> a = w[e], b = z[e];
-    for (int i = 0; i < j; ++i) {
-      const cx<double> hi = mk(h[2 * i], h[2 * i + 1]);
-      a = a - hi * W[(size_t)i * n + e];
-      b = b - hi * Z[(size_t)i * n + e];
-    }
-    w[e] = a;
-    z[e] = b;
-  }
-}
-
 __global__ void k_fill_pairs(double* dsc, int slot, int count, double re, double im) {
   const int i = threadIdx.x;
   if (i < count) {
@@ -711,15 +573,14 @@ __global__ __launch_bounds__(TPB) void k_gcr_dots_b_fin(int j, int gx, int gy, c
   }
 }
 
-// w -= sum h_i W_i, z -= sum h_i Z_i in double, stored as B; |w|^2 and
-// <w, r> of the stored w.
+// w -= sum h_i W_i in double, stored as B; |w|^2 and <w, r> of the stored w.
+// (The matching combination of the search directions z is deferred to the
+// end of the cycle: see k_gcr_combine.)
 template <typename B>
 struct GcrAxpyCoefBOp {
   static constexpr int K = 3;
   const cx<B>* W;
-  const cx<B>* Z;
   cx<B>* w;
-  cx<B>* z;
   const cx<double>* r;
   double* g;
   double* dsc;
@@ -727,18 +588,15 @@ struct GcrAxpyCoefBOp {
   int nb, j;
   __device__ void acc(size_t e, int rhs, double* v) const {
     const size_t o = (size_t)rhs * n + e;
-    cx<double> a = cvt<double>(w[o]), b = cvt<double>(z[o]);
+    cx<double> a = cvt<double>(w[o]);
     const double* h = g + G_H + rhs * 2 * kMaxKrylov;
     for (int i = 0; i < j; ++i) {
       const cx<double> hi = mk(h[2 * i], h[2 * i + 1]);
-      const size_t oi = ((size_t)i * nb + rhs) * n + e;
-      a = a - hi * cvt<double>(W[oi]);
-      b = b - hi * cvt<double>(Z[oi]);
+      a = a - hi * cvt<double>(W[((size_t)i * nb + rhs) * n + e]);
     }
     if (j > 0) {
       const cx<B> as = cvt<B>(a);
       w[o] = as;
-      z[o] = cvt<B>(b);
       a = cvt<double>(as);
     }
     const cx<double> y = r[o];
@@ -755,12 +613,11 @@ struct GcrAxpyCoefBOp {
   }
 };
 
+// r -= a w per rhs, rnorm^2 per rhs.
 template <typename B>
 struct GcrUpdateBOp {
   static constexpr int K = 1;
   const cx<B>* w;
-  const cx<B>* z;
-  cx<double>* x;
   cx<double>* r;
   double* g;
   double* dsc;
@@ -769,7 +626,6 @@ struct GcrUpdateBOp {
   __device__ void acc(size_t e, int rhs, double* v) const {
     const size_t o = (size_t)rhs * n + e;
     const cx<double> s = mk(g[G_A + 2 * rhs], g[G_A + 2 * rhs + 1]);
-    x[o] = x[o] + s * cvt<double>(z[o]);
     const cx<double> ri = r[o] - s * cvt<double>(w[o]);
     r[o] = ri;
     v[0] += ri.re * ri.re + ri.im * ri.im;
@@ -780,6 +636,48 @@ struct GcrUpdateBOp {
     if (host) host[rhs] = v[0];
   }
 };
+
+// Records iteration j of every rhs: hist[q][i][j] = h_i (i < j), av[q][j] = a.
+__global__ void k_gcr_record(const double* __restrict__ g, cx<double>* __restrict__ hist, cx<double>* __restrict__ av,
+                             int nb, int j, int k) {
+  const int q = blockIdx.x;
+  if (q >= nb) return;
+  for (int i = threadIdx.x; i < j; i += blockDim.x)
+    hist[((size_t)q * k + i) * k + j] = mk(g[G_H + q * 2 * kMaxKrylov + 2 * i], g[G_H + q * 2 * kMaxKrylov + 2 * i + 1]);
+  if (threadIdx.x == 0) av[(size_t)q * k + j] = mk(g[G_A + 2 * q], g[G_A + 2 * q + 1]);
+}
+
+// Coefficients of the unorthogonalised directions: with z_j = zt_j -
+// sum_{i<j} h_ij z_i, sum_j a_j z_j = sum_j y_j zt_j where
+// y_j = a_j - sum_{m>j} h_jm y_m (one thread per rhs).
+__global__ void k_gcr_backsolve(const cx<double>* __restrict__ hist, const cx<double>* __restrict__ av,
+                                cx<double>* __restrict__ y, int nb, int jn, int k) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nb) return;
+  const cx<double>* hq = hist + (size_t)q * k * k;
+  cx<double>* yq = y + (size_t)q * k;
+  for (int jj = jn - 1; jj >= 0; --jj) {
+    cx<double> t = av[(size_t)q * k + jj];
+    for (int m = jj + 1; m < jn; ++m) t = t - hq[(size_t)jj * k + m] * yq[m];
+    yq[jj] = t;
+  }
+}
+
+// x += sum_{i < jn} y_i Zt_i per rhs.
+template <typename B>
+__global__ __launch_bounds__(256) void k_gcr_combine(cx<double>* __restrict__ x, const cx<B>* __restrict__ Z,
+                                                     const cx<double>* __restrict__ y, size_t n, int nb, int jn,
+                                                     int k) {
+  const int q = blockIdx.y;
+  __shared__ cx<double> ys[kMaxKrylov];
+  for (int i = threadIdx.x; i < jn; i += blockDim.x) ys[i] = y[(size_t)q * k + i];
+  __syncthreads();
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    cx<double> a = x[(size_t)q * n + e];
+    for (int i = 0; i < jn; ++i) a = a + ys[i] * cvt<double>(Z[((size_t)i * nb + q) * n + e]);
+    x[(size_t)q * n + e] = a;
+  }
+}
 
 struct Norm2BOp {
   static constexpr int K = 1;
@@ -913,29 +811,8 @@ template void step_alpha_half<bf16_t>(Ctx&, HF, HF, int, double, int);
 template void update2_half<f16_t>(Ctx&, HF, HF, HF, HF, int, int);
 template void update2_half<bf16_t>(Ctx&, HF, HF, HF, HF, int, int);
 
-void gcr_orth(Ctx& c, const cx<double>* W, const cx<double>* Z, cx<double>* w, cx<double>* z, const cx<double>* r,
-              size_t n, int j, int hslot, int nrmslot) {
-  if (j > 0) {
-    const unsigned gy = (unsigned)((j + GCR_G - 1) / GCR_G);
-    unsigned gx = reduce_blocks(n);
-    if (gx * gy > (unsigned)kMaxReduceBlocks * 2) gx = (kMaxReduceBlocks * 2) / gy;
-    hipLaunchKernelGGL(k_gcr_dots, dim3(gx, gy), dim3(TPB), 0, c.stream, W, w, n, j, c.partials);
-    WDMG_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_gcr_dots_fin, dim3(1), dim3(TPB), 0, c.stream, j, (int)gx, c.partials, c.dsc, hslot,
-                       nrmslot);
-    WDMG_HIP(hipGetLastError());
-  }
-  run_reduce(c, GcrAxpyCoefOp{W, Z, w, z, r, c.dsc + hslot, n, j, c.dsc, nrmslot + j, S_TMP}, n);
-}
-
-void gcr_step(Ctx& c, const cx<double>* w, const cx<double>* z, cx<double>* x, cx<double>* r, size_t n, int rslot,
-              double* host) {
-  run_reduce(c, GcrUpdateOp{w, z, x, r, c.dsc + S_TMP, c.dsc, rslot, host}, n);
-}
-
 template <typename B>
-void gcr_orth_b(Ctx& c, const cx<B>* W, const cx<B>* Z, cx<B>* w, cx<B>* z, const cx<double>* r, size_t n, int nb,
-                int j, int gl) {
+void gcr_orth_b(Ctx& c, const cx<B>* W, cx<B>* w, const cx<double>* r, size_t n, int nb, int j, int gl) {
   double* g = c.dsc + gcr_base(gl);
   if (j > 0) {
     const int gy = (j + GCR_G - 1) / GCR_G;
@@ -949,23 +826,39 @@ void gcr_orth_b(Ctx& c, const cx<B>* W, const cx<B>* Z, cx<B>* w, cx<B>* z, cons
                        gy, c.partials, g);
     WDMG_HIP(hipGetLastError());
   }
-  run_reduce_b(c, GcrAxpyCoefBOp<B>{W, Z, w, z, r, g, c.dsc, n, nb, j}, n, nb);
+  run_reduce_b(c, GcrAxpyCoefBOp<B>{W, w, r, g, c.dsc, n, nb, j}, n, nb);
 }
 
 template <typename B>
-void gcr_step_b(Ctx& c, const cx<B>* w, const cx<B>* z, cx<double>* x, cx<double>* r, size_t n, int nb, int gl,
-                double* host) {
-  run_reduce_b(c, GcrUpdateBOp<B>{w, z, x, r, c.dsc + gcr_base(gl), c.dsc, host, n}, n, nb);
+void gcr_step_b(Ctx& c, const cx<B>* w, cx<double>* r, size_t n, int nb, int gl, double* host) {
+  run_reduce_b(c, GcrUpdateBOp<B>{w, r, c.dsc + gcr_base(gl), c.dsc, host, n}, n, nb);
 }
 
-template void gcr_orth_b<double>(Ctx&, const cx<double>*, const cx<double>*, cx<double>*, cx<double>*,
-                                 const cx<double>*, size_t, int, int, int);
-template void gcr_orth_b<float>(Ctx&, const cx<float>*, const cx<float>*, cx<float>*, cx<float>*, const cx<double>*,
-                                size_t, int, int, int);
-template void gcr_step_b<double>(Ctx&, const cx<double>*, const cx<double>*, cx<double>*, cx<double>*, size_t, int,
-                                 int, double*);
-template void gcr_step_b<float>(Ctx&, const cx<float>*, const cx<float>*, cx<double>*, cx<double>*, size_t, int, int,
-                                double*);
+void gcr_record(Ctx& c, cx<double>* hist, cx<double>* av, int nb, int j, int k, int gl) {
+  hipLaunchKernelGGL(k_gcr_record, dim3(nb), dim3(64), 0, c.stream, c.dsc + gcr_base(gl), hist, av, nb, j, k);
+  WDMG_HIP(hipGetLastError());
+}
+
+template <typename B>
+void gcr_combine(Ctx& c, cx<double>* x, const cx<B>* Z, const cx<double>* hist, const cx<double>* av, cx<double>* y,
+                 size_t n, int nb, int jn, int k) {
+  if (jn == 0) return;
+  hipLaunchKernelGGL(k_gcr_backsolve, dim3(1), dim3(kMaxRhs), 0, c.stream, hist, av, y, nb, jn, k);
+  WDMG_HIP(hipGetLastError());
+  unsigned gx = ew_blocks(n);
+  if (gx * nb > 8192) gx = (8192 + nb - 1) / nb;
+  hipLaunchKernelGGL(k_gcr_combine<B>, dim3(gx, nb), dim3(256), 0, c.stream, x, Z, y, n, nb, jn, k);
+  WDMG_HIP(hipGetLastError());
+}
+
+template void gcr_orth_b<double>(Ctx&, const cx<double>*, cx<double>*, const cx<double>*, size_t, int, int, int);
+template void gcr_orth_b<float>(Ctx&, const cx<float>*, cx<float>*, const cx<double>*, size_t, int, int, int);
+template void gcr_step_b<double>(Ctx&, const cx<double>*, cx<double>*, size_t, int, int, double*);
+template void gcr_step_b<float>(Ctx&, const cx<float>*, cx<double>*, size_t, int, int, double*);
+template void gcr_combine<double>(Ctx&, cx<double>*, const cx<double>*, const cx<double>*, const cx<double>*,
+                                  cx<double>*, size_t, int, int, int);
+template void gcr_combine<float>(Ctx&, cx<double>*, const cx<float>*, const cx<double>*, const cx<double>*,
+                                 cx<double>*, size_t, int, int, int);
 
 void norm2_b(Ctx& c, const cx<double>* a, size_t n, int nb, int gl, double* host) {
   run_reduce_b(c, Norm2BOp{a, c.dsc + gcr_base(gl), c.dsc, host, n}, n, nb);

@@ -198,6 +198,10 @@ struct Ctx {
   cx<double>* outer_r = nullptr;
   cx<float>* outer_r32 = nullptr;
   cx<float>* outer_z32 = nullptr;
+  cx<double>* outer_hist = nullptr;  // [rhs][k][k] orthogonalisation coefficients of a cycle
+  cx<double>* outer_av = nullptr;    // [rhs][k] step sizes of a cycle
+  cx<double>* outer_y = nullptr;     // [rhs][k] combination coefficients
+  int outer_histk = 0, outer_histcap = 0;
   cx<float>* outer_Z32 = nullptr;  // FP32 outer basis (reduced-precision V-cycle)
   cx<float>* outer_W32 = nullptr;
   int outer_k32 = 0, outer_capB32 = 0;
@@ -323,14 +327,22 @@ void update2_batch(Ctx& c, cx<R>* x, const cx<R>* u, cx<R>* r, const cx<R>* v, s
 // State in the block gcr_base(g): h, nrm, a, rnorm^2, active (see ScalarSlot).
 // B is the storage type of the basis W, Z and of w, z (double or float);
 // r and x are double and every sum is formed in double.
+// Classical Gram-Schmidt of w against the j earlier directions W: h_i =
+// <W_i, w> / nrm_i, w -= sum h_i W_i, nrm_j = |w|^2, step a = <w, r> / nrm_j.
 template <typename B>
-void gcr_orth_b(Ctx& c, const cx<B>* W, const cx<B>* Z, cx<B>* w, cx<B>* z, const cx<double>* r, size_t n, int nb,
-                int j, int g);
-// x += a z; r -= a w per rhs (a = 0 for inactive rhs); rnorm^2 per rhs, also
-// to host (device-visible pinned address, nb doubles) when given.
+void gcr_orth_b(Ctx& c, const cx<B>* W, cx<B>* w, const cx<double>* r, size_t n, int nb, int j, int g);
+// r -= a w per rhs (a = 0 for inactive rhs); rnorm^2 per rhs, also to host
+// (device-visible pinned address, nb doubles) when given.
 template <typename B>
-void gcr_step_b(Ctx& c, const cx<B>* w, const cx<B>* z, cx<double>* x, cx<double>* r, size_t n, int nb, int g,
-                double* host = nullptr);
+void gcr_step_b(Ctx& c, const cx<B>* w, cx<double>* r, size_t n, int nb, int g, double* host = nullptr);
+// Search directions are kept as the preconditioner returned them (zt_j) and
+// combined once per cycle: gcr_record stores iteration j's h_i and a of every
+// rhs (hist [rhs][k][k], av [rhs][k]); gcr_combine solves y_j = a_j -
+// sum_{m>j} h_jm y_m and adds sum_{j < jn} y_j zt_j to x.
+void gcr_record(Ctx& c, cx<double>* hist, cx<double>* av, int nb, int j, int k, int g);
+template <typename B>
+void gcr_combine(Ctx& c, cx<double>* x, const cx<B>* Z, const cx<double>* hist, const cx<double>* av, cx<double>* y,
+                 size_t n, int nb, int jn, int k);
 // rnorm^2 of nb fields into the block g (and host when given).
 void norm2_b(Ctx& c, const cx<double>* a, size_t n, int nb, int g, double* host = nullptr);
 // y = b - y per rhs, with rnorm^2 into block g.
@@ -341,16 +353,6 @@ void set_active(Ctx& c, int g, const double* host_flags, int nb);
 template <typename R> void norm2(Ctx& c, const cx<R>* a, size_t n, int slot);
 // dsc[slot] = <a, b>
 template <typename R> void dot(Ctx& c, const cx<R>* a, const cx<R>* b, size_t n, int slot);
-// GCR orthogonalisation (classical Gram-Schmidt against the j earlier
-// directions): h_i = <W_i, w> / nrm_i into dsc[hslot + 2 i]; w -= sum h_i W_i,
-// z -= sum h_i Z_i; then nrm_j = <w,w> -> dsc[nrmslot + j] and the step
-// a = <w, r> / nrm_j -> dsc[S_TMP].  W, Z: j contiguous vectors of n.
-void gcr_orth(Ctx& c, const cx<double>* W, const cx<double>* Z, cx<double>* w, cx<double>* z, const cx<double>* r,
-              size_t n, int j, int hslot, int nrmslot);
-// GCR step: x += a z; r -= a w; dsc[rslot] = ||r||^2 (and *host when given,
-// a device-visible pinned host address).
-void gcr_step(Ctx& c, const cx<double>* w, const cx<double>* z, cx<double>* x, cx<double>* r, size_t n, int rslot,
-              double* host = nullptr);
 // y = b - y (residual from an operator application); dsc[slot] = ||y||^2.
 void xmy_norm(Ctx& c, const cx<double>* b, cx<double>* y, size_t n, int slot);
 // BiCGStab kernels (FP64).

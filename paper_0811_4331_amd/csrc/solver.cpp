@@ -507,6 +507,7 @@ int fgcr(Ctx& c, cx<double>* x, const cx<double>* b, int nrhs, const wdmg_solve_
     update_active();
     if (nact == 0) break;
     for (int q = 0; q < nrhs; ++q) rstart2[q] = rn2[q];
+    int jn = 0;  // directions of this cycle (x is formed from them at its end)
     for (int j = 0; j < k && nact > 0; ++j) {
       void* z = basis32 ? static_cast<void*>(c.outer_Z32 + (size_t)j * bs) : static_cast<void*>(c.outer_Z + (size_t)j * bs);
       void* w = basis32 ? static_cast<void*>(c.outer_W32 + (size_t)j * bs) : static_cast<void*>(c.outer_W + (size_t)j * bs);
@@ -568,17 +569,18 @@ int fgcr(Ctx& c, cx<double>* x, const cx<double>* b, int nrhs, const wdmg_solve_
       }
       if (basis32) {
         cx<float>* w32 = static_cast<cx<float>*>(w);
-        cx<float>* z32 = static_cast<cx<float>*>(z);
-        dslash<float>(c, w32, z32, nrhs);
-        gcr_orth_b<float>(c, c.outer_W32, c.outer_Z32, w32, z32, r, n, nrhs, j, G);
-        gcr_step_b<float>(c, w32, z32, x, r, n, nrhs, G);
+        dslash<float>(c, w32, static_cast<cx<float>*>(z), nrhs);
+        gcr_orth_b<float>(c, c.outer_W32, w32, r, n, nrhs, j, G);
+        gcr_record(c, c.outer_hist, c.outer_av, nrhs, j, k, G);
+        gcr_step_b<float>(c, w32, r, n, nrhs, G);
       } else {
         cx<double>* w64 = static_cast<cx<double>*>(w);
-        cx<double>* z64 = static_cast<cx<double>*>(z);
-        dslash<double>(c, w64, z64, nrhs);
-        gcr_orth_b<double>(c, c.outer_W, c.outer_Z, w64, z64, r, n, nrhs, j, G);
-        gcr_step_b<double>(c, w64, z64, x, r, n, nrhs, G);
+        dslash<double>(c, w64, static_cast<cx<double>*>(z), nrhs);
+        gcr_orth_b<double>(c, c.outer_W, w64, r, n, nrhs, j, G);
+        gcr_record(c, c.outer_hist, c.outer_av, nrhs, j, k, G);
+        gcr_step_b<double>(c, w64, r, n, nrhs, G);
       }
+      jn = j + 1;
       for (int q = 0; q < nrhs; ++q) st[q].iters += act[q] != 0.0;
       ++total;
       read_rn(rn2);
@@ -591,7 +593,11 @@ int fgcr(Ctx& c, cx<double>* x, const cx<double>* b, int nrhs, const wdmg_solve_
       if (reliable) break;  // recompute the true residual now
       if (changed) update_active();
     }
-    // restart (or claimed convergence): recompute the true residual in FP64
+    // end of the cycle: x += sum_j y_j zt_j, then the true residual in FP64
+    if (basis32)
+      gcr_combine<float>(c, x, c.outer_Z32, c.outer_hist, c.outer_av, c.outer_y, n, nrhs, jn, k);
+    else
+      gcr_combine<double>(c, x, c.outer_Z, c.outer_hist, c.outer_av, c.outer_y, n, nrhs, jn, k);
     dslash<double>(c, r, x, nrhs);
     xmy_norm_b(c, b, r, n, nrhs, G);
     read_rn(rn2);
@@ -896,6 +902,19 @@ void ensure_outer(Ctx& c, int k, int nrhs, bool need32, bool basis32) {
     c.outer_W = static_cast<cx<double>*>(dev_alloc(c, (size_t)kk * cc * n * sizeof(cx<double>)));
     c.outer_k = kk;
     c.outer_capB = cc;
+  }
+  if (k > c.outer_histk || nrhs > c.outer_histcap) {
+    WDMG_HIP(hipStreamSynchronize(c.stream));
+    dev_free(c, c.outer_hist);
+    dev_free(c, c.outer_av);
+    dev_free(c, c.outer_y);
+    const int kk = k > c.outer_histk ? k : c.outer_histk;
+    const int cc = nrhs > c.outer_histcap ? nrhs : c.outer_histcap;
+    c.outer_hist = static_cast<cx<double>*>(dev_alloc(c, (size_t)cc * kk * kk * sizeof(cx<double>)));
+    c.outer_av = static_cast<cx<double>*>(dev_alloc(c, (size_t)cc * kk * sizeof(cx<double>)));
+    c.outer_y = static_cast<cx<double>*>(dev_alloc(c, (size_t)cc * kk * sizeof(cx<double>)));
+    c.outer_histk = kk;
+    c.outer_histcap = cc;
   }
   if (basis32 && (k > c.outer_k32 || nrhs > c.outer_capB32)) {
     WDMG_HIP(hipStreamSynchronize(c.stream));
