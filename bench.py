@@ -120,6 +120,9 @@ def parse():
     ap.add_argument("--setup-iters", type=int, default=None,
                     help="MR relaxation steps per near-null vector (default 50 for fewer than 8 rhs, "
                          "100 for larger batches, whose setup cost is shared)")
+    ap.add_argument("--adapt-iters", type=int, default=0,
+                    help="adaptive augmentation (Sec. 2): two-level iterations refining each candidate "
+                         "after the first (0: relaxation only)")
     ap.add_argument("--nrhs", type=int, default=1)
     ap.add_argument("--setup-prec", default="f64", choices=["f64", "f32"],
                     help="arithmetic of the setup relaxation (the block QR is FP64 either way)")
@@ -329,7 +332,8 @@ def main():
     v0 = torch.from_numpy(synthetic.gaussian_vectors((a.nv,) + ctx.fine_shape(), synthetic.null_seed(cfg))).to(dev)
     bh = np.stack([synthetic.gaussian_spinor(dims, synthetic.rhs_seed(cfg, j)) for j in range(a.nrhs)])
     b = torch.from_numpy(bh).to(dev)
-    levels = [{"block": (4, 4, 4, 4), "nv": a.nv, "setup_iters": a.setup_iters, "vectors": v0,
+    levels = [{"block": (4, 4, 4, 4), "nv": a.nv, "setup_iters": a.setup_iters, "adapt_iters": a.adapt_iters,
+               "vectors": v0,
                "setup_prec": a.setup_prec}]
     if a.levels == 3:
         cdims = tuple(d // 4 for d in dims)
@@ -419,11 +423,13 @@ def main():
                                + (f"2-level MG 4^4 aggregates Nv={a.nv}, " if a.levels == 2 else
                                   f"3-level MG 4^4 then 2^4 aggregates Nv={a.nv} then {a.nv2}, ")
                                + f"MR setup {a.setup_iters} iters, "
-                               f"FGCR({a.restart}) to 1e-10, {a.nrhs} Gaussian RHS",
+                               + (f"adaptive {a.adapt_iters} two-level iters per candidate, " if a.adapt_iters else "")
+                               + f"FGCR({a.restart}) to 1e-10, {a.nrhs} Gaussian RHS",
                    "lattice": list(dims), "eps": a.eps, "m": m, "m_crit": m - a.delta,
                    "m_crit_source": mcrit_src, "levels": a.levels, "nv": a.nv,
                    "nv2": a.nv2 if a.levels == 3 else None,
                    "nrhs": a.nrhs, "mg_prec": a.mg_prec, "setup_prec": a.setup_prec, "coarse_tol": a.coarse_tol,
+                   "adapt_iters": a.adapt_iters,
                    "alpha_step": a.alpha, "graph": a.graph},
         "setup_s": float(np.median(setups)), "solve_s_per_rhs": float(np.median(solves)) / a.nrhs,
         "mg_iters": [s["iters"] for s in last], "mg_n_D": [s["n_D"] for s in last],

@@ -81,6 +81,12 @@ typedef struct {
                             level l ([nv][sites][dof]); required */
   int setup_prec;        /* arithmetic of the relaxation: WDMG_F64 or WDMG_F32 (the
                             block orthonormalisation is FP64 either way)            */
+  int adapt_iters;       /* adaptive augmentation (Sec. 2): after the relaxation,
+                            candidate k = 2..nv is refined by this many stationary
+                            iterations x <- x - M A x of the two-level multigrid
+                            built from candidates 1..k-1 (FP64, this level and its
+                            coarse level, the coarse level solved as the coarsest);
+                            0: relaxation only                                      */
 } wdmg_level_params;
 
 typedef struct {

@@ -10,7 +10,9 @@ Paper passages followed:
   3-level cycle with 4 next-coarser V-cycles between fine restriction and
   prolongation: Sec. 5.
 * adaptive setup: relax ``A x = 0`` from random ``x_0`` for ``l`` iterations,
-  then block QR: Sec. 2 (the alpha-SA procedure).
+  then block QR: Sec. 2 (the alpha-SA procedure); the augmentation in which
+  the current multigrid, applied to ``A x = 0``, refines each next candidate:
+  Sec. 2 (the paragraph after the three steps).
 * flexible GCR(k) outer solver: Sec. 5; BiCGstab as the unpreconditioned
   comparator: Sec. 5.
 
@@ -24,6 +26,9 @@ Readings (the paper is silent):
 * the coarsest solve is GCR (restart 32) to a relative tolerance.
 * the outer FGCR orthogonalises with modified Gram-Schmidt, starts from
   ``x = 0`` and declares convergence only on the true residual.
+* the augmentation relaxes every starting vector first and then refines
+  candidates 2..Nv with a fixed number of stationary two-level iterations
+  ``x <- x - M A x`` (the paper gives no count and no stopping test).
 """
 from __future__ import annotations
 
@@ -236,6 +241,31 @@ def relax_null_vectors(apply, v0, iters, omega=0.8):
         x, _ = mr(apply, x, r, iters, omega)
         out[k] = x / norm(x)
     return out
+
+
+def adaptive_null_vectors(op, v0, blk, iters, adapt_iters, omega=0.8, **hier_kw):
+    """Sec. 2 adaptive augmentation (alpha-SA): the current multigrid solver is
+    applied to ``A x = 0`` to produce each next candidate.
+
+    Every starting vector is first relaxed (``iters`` MR steps, as in
+    ``relax_null_vectors``).  Then, for k = 2, ..., Nv, the two-level
+    multigrid built from candidates 1..k-1 (block QR, Galerkin operator) is
+    applied ``adapt_iters`` times to candidate k as the stationary iteration
+    ``x <- x - M A x``.  Candidates are returned with unit norm; the block QR of
+    all of them defines P (``P V_c = V``, ``P^dagger P = I``).  ``hier_kw`` go to
+    the ``Hierarchy`` of each step (smoothing, alpha, coarsest tolerance).
+    """
+    vecs = relax_null_vectors(op.apply, v0, iters, omega)
+    for k in range(1, vecs.shape[0]):
+        if adapt_iters == 0:
+            break
+        q, _ = transfer.block_orthonormalize(vecs[:k], blk)
+        h = Hierarchy([op, coarse.build_stencil(op, q, blk)], [q], [blk], omega=omega, **hier_kw)
+        x = vecs[k]
+        for _ in range(adapt_iters):
+            x = x - h.vcycle(0, op.apply(x))
+        vecs[k] = x / norm(x)
+    return vecs
 
 
 def build_hierarchy(u, m, t_bc, blocks, nvs, *, seeds=None, setup_iters=100,

@@ -797,6 +797,56 @@ static void relax(Ctx& c, int l, const wdmg_level_params& lp, double omega) {
   }
 }
 
+// Sec. 2 adaptive augmentation of the candidates of level l (already relaxed
+// in F.V64): for k = 1..nv-1 the two-level multigrid of the first k candidates
+// (block QR in place, Galerkin D_c with 2k coarse dof, level l+1 solved as the
+// coarsest) is applied `iters` times to candidate k as x <- x - M A x, in FP64.
+// The QR of the first k columns leaves earlier, already orthonormal columns
+// unchanged (Q is unique with diag(R) > 0), so it is redone in place each step.
+// Work space of level l+1 and the coarsest basis are sized for the final nv.
+static void adapt_candidates(Ctx& c, int l, int iters) {
+  Level& F = c.lev[l];
+  Level& C = c.lev[l + 1];
+  const int nv = F.nv;
+  const int saved_levels = c.nlevels;
+  c.nlevels = l + 2;
+  C.dof = 2 * nv;
+  C.n = (size_t)C.nsite * C.dof;
+  ensure_work<double>(c, l, 1);
+  ensure_work<double>(c, l + 1, 1);
+  ensure_coarsest_basis(c, 1);
+  cx<double>* ax = static_cast<cx<double>*>(dev_alloc(c, F.n * sizeof(cx<double>)));
+  cx<double>* mx = static_cast<cx<double>*>(dev_alloc(c, F.n * sizeof(cx<double>)));
+  for (int k = 1; k < nv; ++k) {
+    F.nv = k;
+    if (l == 0)
+      block_qr0(c, F, F.V64);
+    else
+      block_qrC(c, F, F.V64);
+    C.dof = 2 * k;
+    C.n = (size_t)C.nsite * C.dof;
+    if (l == 0)
+      coarse_build0(c, F, C);
+    else
+      coarse_buildC(c, F, C);
+    cx<double>* x = F.V64 + (size_t)k * F.n;
+    for (int it = 0; it < iters; ++it) {
+      apply_op<double>(c, l, ax, x, 1);
+      vcycle<double>(c, l, mx, ax, 1);
+      xmy<double>(c, x, mx, F.n);  // mx = x - M A x
+      copy<double>(c, x, mx, F.n);
+    }
+    check_flags(c);
+  }
+  WDMG_HIP(hipStreamSynchronize(c.stream));
+  dev_free(c, ax);
+  dev_free(c, mx);
+  F.nv = nv;
+  C.dof = 2 * nv;
+  C.n = (size_t)C.nsite * C.dof;
+  c.nlevels = saved_levels;
+}
+
 void mg_setup(Ctx& c, const wdmg_mg_params& p) {
   if (!c.have_gauge) throw Error(WDMG_ERR_NOT_SETUP, "set the gauge field before the multigrid setup");
   if (p.n_levels < 2 || p.n_levels > WDMG_MAX_LEVELS - 1)
@@ -814,6 +864,7 @@ void mg_setup(Ctx& c, const wdmg_mg_params& p) {
     if (lp.setup_iters < 0) throw Error(WDMG_ERR_ARG, "setup_iters must be >= 0");
     if (lp.setup_prec != WDMG_F64 && lp.setup_prec != WDMG_F32)
       throw Error(WDMG_ERR_ARG, "setup_prec must be WDMG_F64 or WDMG_F32");
+    if (lp.adapt_iters < 0) throw Error(WDMG_ERR_ARG, "adapt_iters must be >= 0");
     if (!lp.vectors) throw Error(WDMG_ERR_ARG, "starting vectors are required for every level");
     int bvol = 1;
     for (int mu = 0; mu < 4; ++mu) {
@@ -845,12 +896,6 @@ void mg_setup(Ctx& c, const wdmg_mg_params& p) {
     else
       copy<double>(c, F.V64, src, (size_t)lp.nv * F.n);
     if (lp.setup_iters > 0) relax(c, l, lp, p.omega);
-    if (l == 0)
-      block_qr0(c, F, F.V64);
-    else
-      block_qrC(c, F, F.V64);
-    check_flags(c);
-    convert<float, double>(c, F.V32, F.V64, (size_t)lp.nv * F.n);
     // coarse level geometry
     C.l = l + 1;
     int one[4] = {1, 1, 1, 1};
@@ -862,6 +907,13 @@ void mg_setup(Ctx& c, const wdmg_mg_params& p) {
     const size_t dcn = (size_t)C.nsite * 9 * C.dof * C.dof;
     C.Dc64 = static_cast<cx<double>*>(dev_alloc(c, dcn * sizeof(cx<double>)));
     C.Dc32 = static_cast<cx<float>*>(dev_alloc(c, dcn * sizeof(cx<float>)));
+    if (lp.adapt_iters > 0 && lp.nv > 1) adapt_candidates(c, l, lp.adapt_iters);
+    if (l == 0)
+      block_qr0(c, F, F.V64);
+    else
+      block_qrC(c, F, F.V64);
+    check_flags(c);
+    convert<float, double>(c, F.V32, F.V64, (size_t)lp.nv * F.n);
     if (l == 0)
       coarse_build0(c, F, C);
     else

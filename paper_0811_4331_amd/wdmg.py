@@ -42,7 +42,7 @@ class WdmgError(RuntimeError):
 
 class LevelParams(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int * 4), ("nv", ctypes.c_int), ("setup_iters", ctypes.c_int),
-                ("vectors", ctypes.c_void_p), ("setup_prec", ctypes.c_int)]
+                ("vectors", ctypes.c_void_p), ("setup_prec", ctypes.c_int), ("adapt_iters", ctypes.c_int)]
 
 
 class MgParams(ctypes.Structure):
@@ -243,7 +243,7 @@ class Context:
 
     def mg_setup(self, levels, *, omega=0.8, nu_pre=2, nu_post=2, coarse_cycles=4,
                  coarse_tol=1e-1, coarse_maxit=200, coarse_restart=32, use_alpha=True):
-        """``levels``: list of dicts ``{block, nv, setup_iters, vectors[, setup_prec]}`` per coarsening;
+        """``levels``: list of dicts ``{block, nv, setup_iters, vectors[, setup_prec, adapt_iters]}`` per coarsening;
         ``vectors`` is a complex128 device tensor ``[nv, <level l field shape>]``."""
         p = MgParams()
         self.lib.wdmg_default_mg_params(ctypes.byref(p))
@@ -262,6 +262,7 @@ class Context:
             p.level[i].nv = nv
             p.level[i].setup_iters = int(lv.get("setup_iters", 0))
             p.level[i].setup_prec = PREC[lv.get("setup_prec", "f64")]
+            p.level[i].adapt_iters = int(lv.get("adapt_iters", 0))
             p.level[i].vectors = _ptr(vec, torch.complex128, f"level {i} vectors")
             lt, lz, ly, lx = shape
             shape = (lt // blk[3], lz // blk[2], ly // blk[1], lx // blk[0])

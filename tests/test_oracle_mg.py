@@ -128,3 +128,51 @@ def test_three_level_cycle_runs_and_reduces_residual():
     b = transfer.as_chiral(synthetic.gaussian_spinor(dims, seed=24))
     x = h.vcycle(0, b)
     assert np.linalg.norm(b - h.ops[0].apply(x)) < 0.9 * np.linalg.norm(b)
+
+
+def _wilson_op(dims, eps, seed, m):
+    u = synthetic.gauge_field(dims, eps, seed)
+    return coarse.WilsonLevel(u, m, -1.0)
+
+
+def test_adaptive_step_is_the_complementary_galerkin_projection():
+    """With no smoothing, alpha = 1 and an (essentially) exact coarsest solve,
+    one refinement step maps x to x - P D_c^{-1} P^dagger A x; since
+    D_c = P^dagger A P this leaves P^dagger A x_new = 0 (Sec. 2)."""
+    dims, blk = (4, 4, 4, 4), (2, 2, 2, 2)
+    op = _wilson_op(dims, 0.3, 41, -0.3)
+    v0 = transfer.as_chiral(synthetic.gaussian_vectors((3,) + dims + (4, 3), 42))
+    kw = dict(nu_pre=0, nu_post=0, use_alpha=False, coarse_tol=1e-13, coarse_maxit=4000)
+    vecs = mg.adaptive_null_vectors(op, v0, blk, iters=2, adapt_iters=1, **kw)
+    relaxed = mg.relax_null_vectors(op.apply, v0, 2)
+    for k in (1, 2):
+        q, _ = transfer.block_orthonormalize(vecs[:k], blk)
+        before = np.linalg.norm(transfer.restrict(q, op.apply(relaxed[k]), blk))
+        after = np.linalg.norm(transfer.restrict(q, op.apply(vecs[k]), blk))
+        assert after <= 1e-9 * before, (k, after, before)
+        # the first k candidates are those of the previous steps, unchanged
+        assert np.array_equal(vecs[:1], relaxed[:1])
+
+
+def test_adaptive_candidates_are_smoother_and_span_p():
+    """Refined candidates have a smaller residual ||A v|| / ||v|| than their
+    relaxed starting points (the two-level iteration damps the smooth error
+    slower than the rough), adapt_iters = 0 is plain relaxation, and the block
+    QR of the candidates satisfies P^dagger P = I and P P^dagger v_k = v_k."""
+    dims, blk, nv = (4, 4, 4, 4), (2, 2, 2, 2), 4
+    op = _wilson_op(dims, 0.3, 43, -0.3)
+    v0 = transfer.as_chiral(synthetic.gaussian_vectors((nv,) + dims + (4, 3), 44))
+    relaxed = mg.relax_null_vectors(op.apply, v0, 3)
+    assert np.array_equal(mg.adaptive_null_vectors(op, v0, blk, 3, 0), relaxed)
+    vecs = mg.adaptive_null_vectors(op, v0, blk, 3, 3, coarse_tol=1e-12, coarse_maxit=4000)
+    for k in range(1, nv):
+        ratio_before = np.linalg.norm(op.apply(relaxed[k]))
+        ratio_after = np.linalg.norm(op.apply(vecs[k]))
+        assert ratio_after < ratio_before, (k, ratio_after, ratio_before)
+        assert abs(np.linalg.norm(vecs[k]) - 1.0) < 1e-13
+    q, _ = transfer.block_orthonormalize(vecs, blk)
+    c = synthetic.gaussian_vectors((2, 2, 2, 2, 2, nv), 45)
+    assert np.allclose(transfer.restrict(q, transfer.prolong(q, c, blk), blk), c, atol=1e-13)
+    for k in range(nv):
+        back = transfer.prolong(q, transfer.restrict(q, vecs[k], blk), blk)
+        assert np.allclose(back, vecs[k], atol=1e-12)
