@@ -132,6 +132,9 @@ def parse():
                     help="take the minimal-residual step size after prolongation (off: alpha = 1, "
                          "which converges in far fewer outer iterations on these fields)")
     ap.add_argument("--restart", type=int, default=50, help="FGCR restart length (paper: 50)")
+    ap.add_argument("--outer", default="fgcr", choices=["fgcr", "bicgstab"],
+                    help="outer Krylov method: flexible GCR (Sec. 5) or BiCGStab with the V-cycle as right "
+                         "preconditioner (Sec. 4)")
     ap.add_argument("--precision-report", action="store_true",
                     help="relative error of every reduced-precision operator against its FP64 form")
     ap.add_argument("--graph", action="store_true",
@@ -347,7 +350,8 @@ def main():
         ctx.mg_setup(levels, coarse_tol=a.coarse_tol, use_alpha=a.alpha)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        x, st = ctx.solve(b, tol=1e-10, restart=a.restart, maxit=2000, mg_prec=a.mg_prec, graph=a.graph)
+        x, st = ctx.solve(b, tol=1e-10, restart=a.restart, maxit=2000, mg_prec=a.mg_prec, graph=a.graph,
+                          outer=a.outer)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         return x, st, t1 - t0, t2 - t1
@@ -424,12 +428,13 @@ def main():
                                   f"3-level MG 4^4 then 2^4 aggregates Nv={a.nv} then {a.nv2}, ")
                                + f"MR setup {a.setup_iters} iters, "
                                + (f"adaptive {a.adapt_iters} two-level iters per candidate, " if a.adapt_iters else "")
-                               + f"FGCR({a.restart}) to 1e-10, {a.nrhs} Gaussian RHS",
+                               + (f"FGCR({a.restart})" if a.outer == "fgcr" else "MG-BiCGStab")
+                               + f" to 1e-10, {a.nrhs} Gaussian RHS",
                    "lattice": list(dims), "eps": a.eps, "m": m, "m_crit": m - a.delta,
                    "m_crit_source": mcrit_src, "levels": a.levels, "nv": a.nv,
                    "nv2": a.nv2 if a.levels == 3 else None,
                    "nrhs": a.nrhs, "mg_prec": a.mg_prec, "setup_prec": a.setup_prec, "coarse_tol": a.coarse_tol,
-                   "adapt_iters": a.adapt_iters,
+                   "adapt_iters": a.adapt_iters, "outer": a.outer,
                    "alpha_step": a.alpha, "graph": a.graph},
         "setup_s": float(np.median(setups)), "solve_s_per_rhs": float(np.median(solves)) / a.nrhs,
         "mg_iters": [s["iters"] for s in last], "mg_n_D": [s["n_D"] for s in last],

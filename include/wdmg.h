@@ -121,6 +121,11 @@ typedef struct {
                             iterations, 1.5x (rounded up, plus one) the count the first
                             V-cycle needed, at most coarse_maxit; right-hand sides that
                             reach coarse_tol earlier are frozen on the device.      */
+  int outer;             /* outer Krylov method: 0 flexible GCR(restart) (Sec. 5); 1
+                            BiCGStab with the V-cycle as right preconditioner (the
+                            MG-BiCGstab of Sec. 4), one rhs after another, from x = 0
+                            (x on input is ignored), restarting from the true residual
+                            after a breakdown; use_graph does not apply to it        */
 } wdmg_solve_params;
 
 typedef struct {

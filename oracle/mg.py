@@ -14,7 +14,8 @@ Paper passages followed:
   the current multigrid, applied to ``A x = 0``, refines each next candidate:
   Sec. 2 (the paragraph after the three steps).
 * flexible GCR(k) outer solver: Sec. 5; BiCGstab as the unpreconditioned
-  comparator: Sec. 5.
+  comparator: Sec. 5, and with the V-cycle as right preconditioner (the
+  MG-BiCGstab of the 2d study): Sec. 4.
 
 Readings (the paper is silent):
 
@@ -113,12 +114,16 @@ def gcr(apply, b, tol, restart=32, maxit=1000, precond=None, x0=None, true_apply
         info["restarts"] += 1
 
 
-def bicgstab(apply, b, tol, maxit=100000):
-    """Unpreconditioned BiCGstab (van der Vorst 1992), ``x_0 = 0``.
+def bicgstab(apply, b, tol, maxit=100000, precond=None):
+    """BiCGstab (van der Vorst 1992), ``x_0 = 0``; with ``precond`` (a map M)
+    preconditioned on the right: the directions p and s enter A and the
+    solution update as ``M p`` and ``M s`` (the MG-preconditioned BiCGstab of
+    Sec. 4).  Without it, unpreconditioned (the Sec. 5 comparator).
 
     A breakdown (``rho = 0``) restarts from the true residual.  Returns
     ``(x, info)`` with ``iters`` (each costs two applications of ``A``).
     """
+    m = precond if precond is not None else (lambda f: f)
     bn = norm(b)
     x = np.zeros_like(b)
     info = {"iters": 0, "converged": False, "true_res": 1.0, "restarts": 0}
@@ -137,13 +142,15 @@ def bicgstab(apply, b, tol, maxit=100000):
                 break
             beta = (rho_new / rho) * (alpha / omega)
             p = r + beta * (p - omega * v)
-            v = apply(p)
+            ph = m(p)
+            v = apply(ph)
             alpha = rho_new / dot(rhat, v)
             s = r - alpha * v
-            t = apply(s)
+            sh = m(s)
+            t = apply(sh)
             tt = dot(t, t).real
             omega = dot(t, s) / tt if tt != 0 else 0.0
-            x = x + alpha * p + omega * s
+            x = x + alpha * ph + omega * sh
             r = s - omega * t
             rho = rho_new
             info["iters"] += 1

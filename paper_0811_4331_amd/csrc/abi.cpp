@@ -256,6 +256,7 @@ void wdmg_default_solve_params(wdmg_solve_params* p) {
   p->precond = 1;
   p->mg_prec = WDMG_F64;
   p->use_graph = 0;
+  p->outer = 0;
 }
 
 int wdmg_create(wdmg_ctx** out, const int dims[4], const wdmg_alloc* alloc, void* hip_stream) {
@@ -535,6 +536,29 @@ int wdmg_solve(wdmg_ctx* c, void* x, const void* b, int nrhs, const wdmg_solve_p
     if (p->precond) {
       if (!c->have_mg) throw Error(WDMG_ERR_NOT_SETUP, "no multigrid hierarchy set up");
       need_prec(p->mg_prec);
+    }
+    if (p->outer != 0 && p->outer != 1) throw Error(WDMG_ERR_ARG, "outer must be 0 (FGCR) or 1 (BiCGStab)");
+    if (p->outer == 1) {
+      // MG-preconditioned BiCGStab, one right-hand side after another
+      ensure_solve_io(*c, 1);
+      const size_t nc = (size_t)c->g0.vol * 12;  // canonical stride per rhs
+      int worst = WDMG_OK;
+      for (int k = 0; k < nrhs; ++k) {
+        wdmg_solve_stats st{};
+        c->n_D = 0;
+        for (int l = 0; l < WDMG_MAX_LEVELS; ++l) c->n_Dc[l] = 0;
+        const double t0 = now();
+        fine_in<double>(*c, static_cast<const cx<double>*>(b) + k * nc, c->sol_b, 1);
+        const int rc = bicgstab(*c, c->sol_x, c->sol_b, p->tol, p->maxit, st, p->precond ? p : nullptr);
+        fine_out<double>(*c, c->sol_x, static_cast<cx<double>*>(x) + k * nc, 1);
+        WDMG_HIP(hipStreamSynchronize(c->stream));
+        st.seconds = now() - t0;
+        st.n_D = c->n_D;
+        for (int l = 0; l < WDMG_MAX_LEVELS; ++l) st.n_Dc[l] = c->n_Dc[l];
+        if (stats) stats[k] = st;
+        if (rc != WDMG_OK) worst = rc;
+      }
+      return worst;
     }
     ensure_solve_io(*c, nrhs);
     std::vector<wdmg_solve_stats> st(nrhs);

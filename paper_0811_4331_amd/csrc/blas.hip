@@ -315,12 +315,15 @@ struct BicgOmegaOp {  // omega = <t, s> / <t, t>
   }
 };
 
-struct BicgXrOp {  // x += alpha p + omega s ; r = s - omega t ; rho_new = <rhat, r>, ||r||^2
+// x += alpha p + omega sx ; r = s - omega t ; rho_new = <rhat, r>, ||r||^2
+// (sx = s, or M s with a right preconditioner M, when p is M p too)
+struct BicgXrOp {
   static constexpr int K = 3;
   cx<double>* x;
   cx<double>* r;
   const cx<double>* p;
   const cx<double>* s;
+  const cx<double>* sx;
   const cx<double>* t;
   const cx<double>* rhat;
   double* dsc;
@@ -328,7 +331,7 @@ struct BicgXrOp {  // x += alpha p + omega s ; r = s - omega t ; rho_new = <rhat
     const double* b = dsc + S_BICG;
     const cx<double> al = mk(b[B_ALPHA], b[B_ALPHA + 1]), om = mk(b[B_OMEGA], b[B_OMEGA + 1]);
     const cx<double> si = s[i];
-    x[i] = x[i] + al * p[i] + om * si;
+    x[i] = x[i] + al * p[i] + om * sx[i];
     const cx<double> ri = si - om * t[i];
     r[i] = ri;
     const cx<double> h = rhat[i];
@@ -896,9 +899,9 @@ void bicg_s(Ctx& c, cx<double>* s, const cx<double>* r, const cx<double>* v, siz
 void bicg_omega(Ctx& c, const cx<double>* t, const cx<double>* s, size_t n) {
   run_reduce(c, BicgOmegaOp{t, s, c.dsc}, n);
 }
-void bicg_xr(Ctx& c, cx<double>* x, cx<double>* r, const cx<double>* p, const cx<double>* s, const cx<double>* t,
-             const cx<double>* rhat, size_t n) {
-  run_reduce(c, BicgXrOp{x, r, p, s, t, rhat, c.dsc}, n);
+void bicg_xr(Ctx& c, cx<double>* x, cx<double>* r, const cx<double>* p, const cx<double>* s, const cx<double>* sx,
+             const cx<double>* t, const cx<double>* rhat, size_t n) {
+  run_reduce(c, BicgXrOp{x, r, p, s, sx, t, rhat, c.dsc}, n);
 }
 void fill_pairs(Ctx& c, int slot, int count, double re, double im) {
   hipLaunchKernelGGL(k_fill_pairs, dim3(1), dim3(kMaxRhs), 0, c.stream, c.dsc, slot, count, re, im);

@@ -205,7 +205,7 @@ struct Ctx {
   cx<float>* outer_Z32 = nullptr;  // FP32 outer basis (reduced-precision V-cycle)
   cx<float>* outer_W32 = nullptr;
   int outer_k32 = 0, outer_capB32 = 0;
-  cx<double>* bicg[6] = {};
+  cx<double>* bicg[8] = {};
   cx<double>* sol_x = nullptr;   // internal x, b of a solve
   cx<double>* sol_b = nullptr;
   int sol_cap = 0;
@@ -360,7 +360,8 @@ void bicg_p(Ctx& c, cx<double>* p, const cx<double>* r, const cx<double>* v, siz
 void bicg_alpha(Ctx& c, const cx<double>* rhat, const cx<double>* v, size_t n);
 void bicg_s(Ctx& c, cx<double>* s, const cx<double>* r, const cx<double>* v, size_t n);
 void bicg_omega(Ctx& c, const cx<double>* t, const cx<double>* s, size_t n);
-void bicg_xr(Ctx& c, cx<double>* x, cx<double>* r, const cx<double>* p, const cx<double>* s,
+// x += alpha p + omega sx; r = s - omega t (sx = s unpreconditioned)
+void bicg_xr(Ctx& c, cx<double>* x, cx<double>* r, const cx<double>* p, const cx<double>* s, const cx<double>* sx,
              const cx<double>* t, const cx<double>* rhat, size_t n);
 void set_scalar(Ctx& c, int slot, double re, double im);
 // dsc[slot + 2 i] = re, dsc[slot + 2 i + 1] = im for i < count (count <= kMaxRhs)

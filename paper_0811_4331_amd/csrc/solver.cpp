@@ -623,7 +623,29 @@ int fgcr(Ctx& c, cx<double>* x, const cx<double>* b, int nrhs, const wdmg_solve_
 
 // ---------------------------------------------------------------------------
 // BiCGStab (van der Vorst 1992), FP64, x = 0 start (Sec. 5 comparator).
-int bicgstab(Ctx& c, cx<double>* x, const cx<double>* b, double tol, int maxit, wdmg_solve_stats& st) {
+// z = M r for one rhs: the V-cycle in the precision of pc (FP64 in and out).
+static void precond_apply1(Ctx& c, const wdmg_solve_params& pc, const cx<double>* r, cx<double>* z) {
+  const size_t n = c.lev[0].n;
+  Level& L0 = c.lev[0];
+  if (pc.mg_prec == WDMG_F16) {
+    to_half<double, f16_t>(c, r, L0.wh[4], 1);
+    vcycle_h<f16_t>(c, L0.wh[5], L0.wh[4], 1);
+    from_half<f16_t, double>(c, L0.wh[5], z, 1);
+  } else if (pc.mg_prec == WDMG_BF16) {
+    to_half<double, bf16_t>(c, r, L0.wh[4], 1);
+    vcycle_h<bf16_t>(c, L0.wh[5], L0.wh[4], 1);
+    from_half<bf16_t, double>(c, L0.wh[5], z, 1);
+  } else if (pc.mg_prec == WDMG_F32) {
+    convert<float, double>(c, c.outer_r32, r, n);
+    vcycle<float>(c, 0, c.outer_z32, c.outer_r32, 1);
+    convert<double, float>(c, z, c.outer_z32, n);
+  } else {
+    vcycle<double>(c, 0, z, r, 1);
+  }
+}
+
+int bicgstab(Ctx& c, cx<double>* x, const cx<double>* b, double tol, int maxit, wdmg_solve_stats& st,
+             const wdmg_solve_params* pc) {
   const size_t n = c.lev[0].n;
   ensure_bicg(c);
   cx<double>* r = c.bicg[0];
@@ -632,6 +654,16 @@ int bicgstab(Ctx& c, cx<double>* x, const cx<double>* b, double tol, int maxit, 
   cx<double>* v = c.bicg[3];
   cx<double>* s = c.bicg[4];
   cx<double>* t = c.bicg[5];
+  cx<double>* ph = c.bicg[6];  // M p
+  cx<double>* sh = c.bicg[7];  // M s
+  const bool half = pc && (pc->mg_prec == WDMG_F16 || pc->mg_prec == WDMG_BF16);
+  if (pc) {
+    const bool low = pc->mg_prec != WDMG_F64;
+    ensure_outer(c, 1, 1, low, true);
+    ensure_mg_work(c, 1, low ? WDMG_F32 : WDMG_F64);
+    if (half) ensure_work_h(c, 1);
+  }
+  HalfScope hs(c, half ? pc->mg_prec : 0);
   set_scalar(c, S_ERR, 0.0, 0.0);
   norm2<double>(c, b, n, S_TMP + 4);
   const double bn2 = read_scalar(c, S_TMP + 4);
@@ -659,12 +691,22 @@ int bicgstab(Ctx& c, cx<double>* x, const cx<double>* b, double tol, int maxit, 
     while (st.iters < maxit) {
       bicg_p(c, p, r, v, n, first);
       first = false;
-      dslash<double>(c, v, p, 1);
+      const cx<double>* pp = p;
+      if (pc) {
+        precond_apply1(c, *pc, p, ph);
+        pp = ph;
+      }
+      dslash<double>(c, v, pp, 1);
       bicg_alpha(c, rhat, v, n);
       bicg_s(c, s, r, v, n);
-      dslash<double>(c, t, s, 1);
+      const cx<double>* ss = s;
+      if (pc) {
+        precond_apply1(c, *pc, s, sh);
+        ss = sh;
+      }
+      dslash<double>(c, t, ss, 1);
       bicg_omega(c, t, s, n);
-      bicg_xr(c, x, r, p, s, t, rhat, n);
+      bicg_xr(c, x, r, pp, s, ss, t, rhat, n);
       ++st.iters;
       if (++since >= check_every || st.iters >= maxit) {
         since = 0;
@@ -992,7 +1034,7 @@ void ensure_outer(Ctx& c, int k, int nrhs, bool need32, bool basis32) {
 void ensure_bicg(Ctx& c) {
   if (c.bicg[0]) return;
   const size_t n = (size_t)c.g0.vpad * 12;
-  for (int i = 0; i < 6; ++i) c.bicg[i] = static_cast<cx<double>*>(dev_alloc(c, n * sizeof(cx<double>)));
+  for (cx<double>*& f : c.bicg) f = static_cast<cx<double>*>(dev_alloc(c, n * sizeof(cx<double>)));
 }
 
 }  // namespace wdmg

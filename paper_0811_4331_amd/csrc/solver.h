@@ -38,7 +38,10 @@ void ensure_work(Ctx& c, int l, int nrhs);
 void ensure_mg_work(Ctx& c, int nrhs, int prec);
 
 int fgcr(Ctx& c, cx<double>* x, const cx<double>* b, int nrhs, const wdmg_solve_params& p, wdmg_solve_stats* st);
-int bicgstab(Ctx& c, cx<double>* x, const cx<double>* b, double tol, int maxit, wdmg_solve_stats& st);
+// BiCGStab from x = 0; with pc (precond set) the V-cycle of pc's precision is
+// the right preconditioner.
+int bicgstab(Ctx& c, cx<double>* x, const cx<double>* b, double tol, int maxit, wdmg_solve_stats& st,
+             const wdmg_solve_params* pc = nullptr);
 
 void mg_setup(Ctx& c, const wdmg_mg_params& p);
 void free_hierarchy(Ctx& c);

@@ -55,7 +55,8 @@ class MgParams(ctypes.Structure):
 
 class SolveParams(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("maxit", ctypes.c_int),
-                ("precond", ctypes.c_int), ("mg_prec", ctypes.c_int), ("use_graph", ctypes.c_int)]
+                ("precond", ctypes.c_int), ("mg_prec", ctypes.c_int), ("use_graph", ctypes.c_int),
+                ("outer", ctypes.c_int)]
 
 
 class SolveStats(ctypes.Structure):
@@ -315,11 +316,13 @@ class Context:
         return x
 
     def solve(self, b: torch.Tensor, x0: torch.Tensor | None = None, *, tol=1e-10, restart=50,
-              maxit=1000, precond=True, mg_prec="f64", graph=False):
+              maxit=1000, precond=True, mg_prec="f64", graph=False, outer="fgcr"):
+        """MG-preconditioned solve; ``outer`` is "fgcr" (flexible GCR(restart)) or
+        "bicgstab" (BiCGStab with the V-cycle as right preconditioner, x0 = 0)."""
         nrhs = self._nrhs(b, 6)
         x = torch.zeros_like(b) if x0 is None else x0.clone()
         p = SolveParams(float(tol), int(restart), int(maxit), 1 if precond else 0, PREC[mg_prec],
-                        1 if graph else 0)
+                        1 if graph else 0, {"fgcr": 0, "bicgstab": 1}[outer])
         stats = (SolveStats * nrhs)()
         rc = self.lib.wdmg_solve(self.h, _ptr(x, torch.complex128, "x"), _ptr(b, torch.complex128, "b"),
                                  nrhs, ctypes.byref(p), stats)
