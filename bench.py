@@ -124,6 +124,8 @@ def parse():
                     help="adaptive augmentation (Sec. 2): two-level iterations refining each candidate "
                          "after the first (0: relaxation only)")
     ap.add_argument("--nrhs", type=int, default=1)
+    ap.add_argument("--coarse-apply", type=int, default=None, choices=[0, 1],
+                    help="force a form of the batched coarsest-level operator (default: library choice)")
     ap.add_argument("--setup-prec", default="f64", choices=["f64", "f32"],
                     help="arithmetic of the setup relaxation (the block QR is FP64 either way)")
     ap.add_argument("--mg-prec", default="f64", choices=["f64", "f32", "f16", "bf16"])
@@ -332,6 +334,7 @@ def main():
     ctx = wdmg.Context(dims, dev)
     ctx.set_gauge(torch.from_numpy(u).to(dev), t_bc=-1)
     ctx.set_mass(m)
+    ctx.set_tuning("coarse_apply", a.coarse_apply)
     v0 = torch.from_numpy(synthetic.gaussian_vectors((a.nv,) + ctx.fine_shape(), synthetic.null_seed(cfg))).to(dev)
     bh = np.stack([synthetic.gaussian_spinor(dims, synthetic.rhs_seed(cfg, j)) for j in range(a.nrhs)])
     b = torch.from_numpy(bh).to(dev)

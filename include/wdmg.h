@@ -239,8 +239,23 @@ int wdmg_solve_bicgstab(wdmg_ctx* ctx, void* x, const void* b, int nrhs, double 
  *                     sweeps its lattice region once per group, with the
  *                     group's rhs of one site block back to back (a value
  *                     above the batch size means the whole batch).  Tuned
- *                     after the form. */
-enum { WDMG_TUNE_AUTO = -1, WDMG_TUNE_DSLASH = 0, WDMG_TUNE_DSLASH_GROUP = 1, WDMG_TUNE_COUNT };
+ *                     after the form.
+ *   WDMG_TUNE_COARSE_APPLY: the batched coarsest-level operator (nrhs >= 2)
+ *                     on the FP64 matrix cores; 0 waves split over
+ *                     directions with operands read straight from memory,
+ *                     1 operator block and neighbour rows staged through
+ *                     LDS one direction at a time, the next one loading
+ *                     during the products (needs 2Nv % 8 == 0 and at most
+ *                     16 waves for 16 rhs x 16 rows tiles, else form 0).
+ *                     AUTO means form 1 where it applies (not timed);
+ *                     wdmg_get_tuning reports only a forced value. */
+enum {
+  WDMG_TUNE_AUTO = -1,
+  WDMG_TUNE_DSLASH = 0,
+  WDMG_TUNE_DSLASH_GROUP = 1,
+  WDMG_TUNE_COARSE_APPLY = 2,
+  WDMG_TUNE_COUNT
+};
 int wdmg_set_tuning(wdmg_ctx* ctx, int key, int value);
 /* Current choice for key (WDMG_TUNE_AUTO until tuned) for precision prec
  * and batch size nrhs. */

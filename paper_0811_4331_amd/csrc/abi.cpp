@@ -613,8 +613,9 @@ int wdmg_solve_bicgstab(wdmg_ctx* c, void* x, const void* b, int nrhs, double to
 
 int wdmg_set_tuning(wdmg_ctx* c, int key, int value) {
   return guarded(c, [&]() {
-    if (key != WDMG_TUNE_DSLASH && key != WDMG_TUNE_DSLASH_GROUP) throw Error(WDMG_ERR_ARG, "unknown tuning key");
-    const int hi = key == WDMG_TUNE_DSLASH ? 2 : kMaxRhs, lo = key == WDMG_TUNE_DSLASH ? 0 : 1;
+    if (key < 0 || key >= WDMG_TUNE_COUNT) throw Error(WDMG_ERR_ARG, "unknown tuning key");
+    const int hi = key == WDMG_TUNE_DSLASH ? 2 : key == WDMG_TUNE_COARSE_APPLY ? 1 : kMaxRhs;
+    const int lo = key == WDMG_TUNE_DSLASH_GROUP ? 1 : 0;
     if (value != WDMG_TUNE_AUTO && (value < lo || value > hi)) throw Error(WDMG_ERR_ARG, "bad tuning value");
     c->tune_force[key] = value;
     return WDMG_OK;
@@ -624,13 +625,14 @@ int wdmg_set_tuning(wdmg_ctx* c, int key, int value) {
 int wdmg_get_tuning(wdmg_ctx* c, int key, int prec, int nrhs, int* value) {
   return guarded(c, [&]() {
     need_ptr(value, "value");
-    if (key != WDMG_TUNE_DSLASH && key != WDMG_TUNE_DSLASH_GROUP) throw Error(WDMG_ERR_ARG, "unknown tuning key");
+    if (key < 0 || key >= WDMG_TUNE_COUNT) throw Error(WDMG_ERR_ARG, "unknown tuning key");
     need_prec(prec);
     need_nrhs(nrhs);
     const int slot = nrhs < kMaxRhs ? nrhs : kMaxRhs;
-    *value = c->tune_force[key] >= 0           ? c->tune_force[key]
-             : key == WDMG_TUNE_DSLASH ? (int)c->tune_dslash[prec][slot]
-                                       : (int)c->tune_group[prec][slot];
+    *value = c->tune_force[key] >= 0                 ? c->tune_force[key]
+             : key == WDMG_TUNE_DSLASH               ? (int)c->tune_dslash[prec][slot]
+             : key == WDMG_TUNE_DSLASH_GROUP         ? (int)c->tune_group[prec][slot]
+                                                     : WDMG_TUNE_AUTO;
     return WDMG_OK;
   });
 }

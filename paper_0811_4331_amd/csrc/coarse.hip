@@ -1048,6 +1048,162 @@ __global__ __launch_bounds__(1024) void k_cgcrT_apply(Geom g, int n2, int nrhs, 
   apply_site_mfma64<NT>(g, n2, nrhs, s, Dc, r, w, lds, RhsFast{nrhs});
 }
 
+// K1 (rhs-fast) with both operands staged through LDS: one workgroup per
+// site, split into ng direction groups of nrt x ntile waves; wave (rt, tt) of
+// group g owns real rows 16 rt.. and rhs 16 tt.. of w for the directions
+// g, g + ng, ...  Each group fetches the block of its next direction and the
+// neighbour's n2 x nrhs rows (contiguous in the rhs-fast layout) into
+// registers with 16-byte loads while the matrix cores work on its current
+// direction from LDS, so the product loop issues no global loads.  The
+// groups' partial tiles are added through LDS at the end (one group: none).
+// Block columns are padded to ldc = 8 (mod 16) complex so the two columns one
+// MFMA operand fetch touches fall in disjoint bank halves.  Needs n2 % 8 == 0.
+// Staging registers hold complex numbers as a clang vector of two doubles: an
+// array of HIP's double2 class is not promoted to registers (it lands in
+// scratch memory, whose stores wait for the loads and serialise the prefetch).
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+constexpr int kStageA = 8;  // most complex of a block staged per thread (n2 <= 64)
+constexpr int kStageB = 2;  // complex of the rhs rows staged per thread
+__host__ __device__ inline int cgcr_ldc(int n2) {
+  int l = n2;
+  while ((l & 15) != 8) ++l;
+  return l;
+}
+// LDS of one direction group's operands, and of the whole workgroup
+__host__ __device__ inline size_t cgcr_group_bytes(int n2, int nrhs) {
+  return ((size_t)n2 * cgcr_ldc(n2) + (size_t)n2 * nrhs) * 16;
+}
+__host__ __device__ inline size_t cgcr_lds_bytes(int n2, int nrhs, int ng) {
+  const size_t waves = (size_t)mfma64_row_tiles(n2) * ((nrhs + 15) / 16);
+  const size_t ops = ng * cgcr_group_bytes(n2, nrhs), part = (ng - 1) * waves * 64 * 4 * sizeof(double);
+  return ops > part ? ops : part;
+}
+// (the smaller stagings keep to 80 registers so that two 12-wave workgroups
+// share a compute unit)
+template <int SA>  // complex of the block staged per thread (n2^2 <= SA x group threads)
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(SA <= 4 ? 6 : 4))) void k_cgcrT_apply_lds(Geom g, int n2, int nrhs, int ng,
+                                                         const cx<double>* __restrict__ Dc,
+                                                         const cx<double>* __restrict__ r, cx<double>* __restrict__ w,
+                                                         cx<double>* __restrict__ z) {
+  extern __shared__ __align__(16) char dyn4[];
+  const int ldc = cgcr_ldc(n2), nrt = mfma64_row_tiles(n2);
+  const int wg = nrt * ((nrhs + 15) / 16);  // waves per group
+  const int nthr = 64 * wg;                 // threads per group
+  const int l = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int grp = wave / wg, wv = wave % wg, tid = threadIdx.x - grp * nthr;
+  const int rt = wv % nrt, tt = wv / nrt;
+  dbl2* al = reinterpret_cast<dbl2*>(dyn4 + grp * cgcr_group_bytes(n2, nrhs));  // [n2 cols][ldc]
+  dbl2* bl = al + (size_t)n2 * ldc;                                              // [n2 rows][nrhs]
+  const int s = blockIdx.x;
+  const int nblk = n2 * n2, nb2 = n2 * nrhs;
+  const size_t o = (size_t)s * nb2;
+  for (int e = threadIdx.x; e < nb2; e += blockDim.x) z[o + e] = r[o + e];
+  int c[4];
+  coords_of(g, s, c);
+  // staging slots: block element e = tid + u nthr (column-major) goes to
+  // column e / n2, row e % n2; loads past the end re-read the last element
+  dbl2 sa[SA], sb[kStageB];
+  auto fetch = [&](int d) {
+    const int nb = d == 8 ? s : ((d & 1) ? nbr_bwd(g, s, c, d >> 1) : nbr_fwd(g, s, c, d >> 1));
+    const dbl2* blk = reinterpret_cast<const dbl2*>(Dc + ((size_t)s * 9 + d) * nblk);
+    const dbl2* rows = reinterpret_cast<const dbl2*>(r + (size_t)nb * nb2);
+#pragma unroll
+    for (int u = 0; u < SA; ++u) sa[u] = blk[min(tid + u * nthr, nblk - 1)];
+#pragma unroll
+    for (int u = 0; u < kStageB; ++u) sb[u] = rows[min(tid + u * nthr, nb2 - 1)];
+  };
+  auto stage = [&]() {
+#pragma unroll
+    for (int u = 0; u < SA; ++u) {
+      const int e = tid + u * nthr, col = e / n2;
+      if (e < nblk) al[col * ldc + (e - col * n2)] = sa[u];
+    }
+#pragma unroll
+    for (int u = 0; u < kStageB; ++u)
+      if (tid + u * nthr < nb2) bl[tid + u * nthr] = sb[u];
+  };
+  // lane roles of the 16x16x4 product: A row rr, B column q, k = 4 t + kl
+  const int rr = rt * 16 + (l & 15), kl = l >> 4;
+  const int i = min(rr >> 1, n2 - 1), pr = rr & 1, pk = kl & 1, jl = kl >> 1;
+  const int q = tt * 16 + (l & 15), qc = min(q, nrhs - 1);
+  // real entry (rr, k) of the complex block: Re or Im of element (i, j), the
+  // sign bit flipped for row pr = 0, column pk = 1 (-Im)
+  const unsigned long long sgn = (pr == 0 && pk == 1) ? 0x8000000000000000ull : 0ull;
+  const double* pa = reinterpret_cast<const double*>(al) + 2 * (jl * ldc + i) + (pr ^ pk);
+  const double* pb = reinterpret_cast<const double*>(bl) + 2 * (jl * nrhs + qc) + pk;
+  const int sa4 = 4 * ldc, sb4 = 4 * nrhs;  // doubles per step of t (j += 2)
+  const int nk = n2 / 2;
+  doublex4 acc = doublex4{0.0, 0.0, 0.0, 0.0};
+  const int rounds = (9 + ng - 1) / ng;
+  if (grp < 9) {
+    fetch(grp);
+    stage();
+  }
+  __syncthreads();
+  for (int k = 0; k < rounds; ++k) {
+    const int d = grp + k * ng, dn = d + ng;
+    if (dn < 9) fetch(dn);
+    if (d < 9) {
+      for (int t = 0; t < nk; t += 4) {
+        double av[4], bv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          av[u] = __longlong_as_double(__double_as_longlong(pa[(t + u) * sa4]) ^ sgn);
+          bv[u] = pb[(t + u) * sb4];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
+      }
+    }
+    if (k + 1 < rounds) {
+      __syncthreads();  // every wave of the group is done with direction d
+      if (dn < 9) stage();
+      __syncthreads();
+    }
+  }
+  if (ng > 1) {  // groups 1.. hand their tiles to group 0 (in group order)
+    double* part = reinterpret_cast<double*>(dyn4);
+    __syncthreads();
+    if (grp > 0) {
+      double* dst = part + ((size_t)((grp - 1) * wg + wv) * 64 + l) * 4;
+#pragma unroll
+      for (int reg = 0; reg < 4; ++reg) dst[reg] = acc[reg];
+    }
+    __syncthreads();
+    if (grp == 0) {
+      for (int gg = 1; gg < ng; ++gg) {
+        const double* src = part + ((size_t)((gg - 1) * wg + wv) * 64 + l) * 4;
+#pragma unroll
+        for (int reg = 0; reg < 4; ++reg) acc[reg] += src[reg];
+      }
+    }
+  }
+  if (grp == 0 && q < nrhs) {
+#pragma unroll
+    for (int reg = 0; reg < 4; ++reg) {
+      const int row = rt * 16 + 4 * reg + (l >> 4);
+      if ((row >> 1) < n2) reinterpret_cast<double*>(w + ((size_t)s * n2 + (row >> 1)) * nrhs + q)[row & 1] = acc[reg];
+    }
+  }
+}
+
+// The staged K1 needs n2 % 8 == 0 and a group's block and waves within the
+// staging registers.  Direction groups: one when the grid has several sites
+// per compute unit (workgroups then overlap each other's loads), else the
+// most of 3, 2 that fit 16 waves and the LDS limit.
+constexpr int kCgcrStagedMinSites = 1024;
+constexpr size_t kCgcrStagedLds = 128 * 1024;
+inline int cgcr_staged_groups(int n2, int nrhs, long long nsite) {
+  const int wg = mfma64_row_tiles(n2) * ((nrhs + 15) / 16);
+  if (n2 % 8 != 0 || n2 > 64 || wg > 16 || n2 * n2 > kStageA * 64 * wg || n2 * nrhs > kStageB * 64 * wg ||
+      cgcr_lds_bytes(n2, nrhs, 1) > kCgcrStagedLds)
+    return 0;
+  if (nsite < kCgcrStagedMinSites)
+    for (int ng = 3; ng >= 2; --ng)
+      if (ng * wg <= 16 && cgcr_lds_bytes(n2, nrhs, ng) <= kCgcrStagedLds) return ng;
+  return 1;
+}
+
 // Dots (rhs-fast): partial c_i = <W_i, w>, d_i = <W_i, r> (i < j) and
 // |w|^2, <w, r>, |r|^2 of one chunk of positions, stored in the value order of
 // k_cgcr_coef.  Basis vectors are taken kCgcrDotIG per pass over the chunk.
@@ -1264,12 +1420,18 @@ void coarsest_gcr(Ctx& c, Level& L, cx<double>* x, const cx<double>* b, int nrhs
   CgcrState S{gb + G_H, gb + G_NRM, gb + G_A, gb + G_RN, gb + G_ACT, gb + G_TOL};
   const int g1 = L.nsite < kCgcrG1 ? L.nsite : kCgcrG1;
   const int waves = mfma64_row_tiles(n2) * mfma64_groups(n2);
+  const int form = c.tune_force[WDMG_TUNE_COARSE_APPLY];
+  const int sgroups = nrhs >= 2 && form != 0 ? cgcr_staged_groups(n2, nrhs, L.nsite) : 0;
   if (nrhs == 1 && (size_t)(4 * k + 4) * sizeof(double) > 96 * 1024)
     throw Error(WDMG_ERR_ARG, "coarse_restart too long (LDS)");
   static bool lds_attr = false;
-  if (!lds_attr) {  // the single-rhs K1 keeps 4 j + 4 partial sums in LDS
+  if (!lds_attr) {  // the single-rhs K1 keeps 4 j + 4 partial sums in LDS, the staged one a block
     WDMG_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cgcr_apply),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024));
+    for (const void* f : {reinterpret_cast<const void*>(&k_cgcrT_apply_lds<2>),
+                          reinterpret_cast<const void*>(&k_cgcrT_apply_lds<4>),
+                          reinterpret_cast<const void*>(&k_cgcrT_apply_lds<kStageA>)})
+      WDMG_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kCgcrStagedLds));
     lds_attr = true;
   }
   // a batch keeps its vectors rhs-fast for the whole solve (x in L.xT)
@@ -1308,12 +1470,30 @@ void coarsest_gcr(Ctx& c, Level& L, cx<double>* x, const cx<double>* b, int nrhs
     if (fast) {
       {
         ProfScope ps(c, WDMG_K_COARSE_GCR, (long long)L.nsite * nrhs);
-        const dim3 grid(L.nsite), block(64 * waves);
-        switch ((nrhs + 15) / 16) {
-          case 1: hipLaunchKernelGGL(k_cgcrT_apply<1>, grid, block, 0, c.stream, L.g, n2, nrhs, L.Dc64, r, w, z); break;
-          case 2: hipLaunchKernelGGL(k_cgcrT_apply<2>, grid, block, 0, c.stream, L.g, n2, nrhs, L.Dc64, r, w, z); break;
-          case 3: hipLaunchKernelGGL(k_cgcrT_apply<3>, grid, block, 0, c.stream, L.g, n2, nrhs, L.Dc64, r, w, z); break;
-          default: hipLaunchKernelGGL(k_cgcrT_apply<kMaxTiles>, grid, block, 0, c.stream, L.g, n2, nrhs, L.Dc64, r, w, z); break;
+        const dim3 grid(L.nsite);
+        if (sgroups) {
+          const int nthr = 64 * mfma64_row_tiles(n2) * ((nrhs + 15) / 16);
+          const size_t lb = cgcr_lds_bytes(n2, nrhs, sgroups);
+          const dim3 block(nthr * sgroups);
+          if (n2 * n2 <= 2 * nthr)
+            hipLaunchKernelGGL(k_cgcrT_apply_lds<2>, grid, block, lb, c.stream, L.g, n2, nrhs, sgroups, L.Dc64, r, w,
+                               z);
+          else if (n2 * n2 <= 4 * nthr)
+            hipLaunchKernelGGL(k_cgcrT_apply_lds<4>, grid, block, lb, c.stream, L.g, n2, nrhs, sgroups, L.Dc64, r, w,
+                               z);
+          else
+            hipLaunchKernelGGL(k_cgcrT_apply_lds<kStageA>, grid, block, lb, c.stream, L.g, n2, nrhs, sgroups, L.Dc64,
+                               r, w, z);
+        } else {
+          const dim3 block(64 * waves);
+          switch ((nrhs + 15) / 16) {
+            case 1: hipLaunchKernelGGL(k_cgcrT_apply<1>, grid, block, 0, c.stream, L.g, n2, nrhs, L.Dc64, r, w, z); break;
+            case 2: hipLaunchKernelGGL(k_cgcrT_apply<2>, grid, block, 0, c.stream, L.g, n2, nrhs, L.Dc64, r, w, z); break;
+            case 3: hipLaunchKernelGGL(k_cgcrT_apply<3>, grid, block, 0, c.stream, L.g, n2, nrhs, L.Dc64, r, w, z); break;
+            default:
+              hipLaunchKernelGGL(k_cgcrT_apply<kMaxTiles>, grid, block, 0, c.stream, L.g, n2, nrhs, L.Dc64, r, w, z);
+              break;
+          }
         }
         WDMG_HIP(hipGetLastError());
       }

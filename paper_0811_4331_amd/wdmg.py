@@ -329,7 +329,7 @@ class Context:
         self._check(rc, allow_not_converged=True)
         return x, [s.as_dict() for s in stats]
 
-    TUNE = {"dslash": 0, "dslash_group": 1}
+    TUNE = {"dslash": 0, "dslash_group": 1, "coarse_apply": 2}
 
     def set_tuning(self, key: str, value: int | None):
         """Force a kernel form (0, 1, ...) or let the autotuner pick (None)."""

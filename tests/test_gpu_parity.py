@@ -235,6 +235,42 @@ def test_batched_coarsest_solve_matches_single_solves(dims, blk, nv, nrhs):
         assert rel(xh[j], xj.cpu().numpy()) < 1e-8, j
 
 
+@pytest.mark.parametrize("dims,blk,nv,nrhs", [
+    ((4, 4, 4, 8), (2, 2, 2, 2), 8, 17),     # 2Nv = 16, two rhs tiles, three direction groups
+    ((8, 8, 8, 8), (4, 4, 4, 4), 20, 16),    # 2Nv = 40, one tile, three direction groups (the 16^4 shape)
+    ((8, 8, 8, 8), (4, 4, 4, 4), 20, 20),    # 2Nv = 40, ragged second tile, one group
+    ((8, 8, 8, 8), (4, 4, 4, 4), 24, 32),    # 2Nv = 48, two full tiles (the 24^3 x 48 workload's shape)
+    ((8, 8, 8, 8), (4, 4, 4, 4), 32, 5),     # 2Nv = 64, one ragged tile
+    ((8, 8, 16, 16), (2, 2, 2, 2), 8, 9),    # 1024 coarse sites: the staged form by default
+    ((4, 4, 4, 8), (2, 2, 2, 2), 6, 17),     # 2Nv = 12 is not staged: form 1 falls back to form 0
+])
+def test_batched_coarse_operator_forms_agree(dims, blk, nv, nrhs):
+    """Both forms of the batched coarsest-level operator (direction-split waves
+    reading operands from memory, and LDS-staged operands one direction per
+    wave group at a time) give solutions that reach the true
+    residual 1e-10 with the oracle's D and agree with each other to rounding,
+    with the same iteration counts to within one."""
+    m = -0.5
+    ctx, u, q, lev = _setup_imported(dims, blk, nv, m=m)
+    b = synthetic.gaussian_spinor(dims, seed=140 + nrhs, nrhs=nrhs)
+    out = {}
+    for form in (0, 1, None):
+        ctx.set_tuning("coarse_apply", form)
+        assert ctx.get_tuning("coarse_apply", "f64", nrhs) == form
+        x, st = ctx.solve(gpu(b), tol=1e-10, restart=20, maxit=300)
+        xh = x.cpu().numpy()
+        for j in range(nrhs):
+            assert st[j]["converged"], (form, j, st[j])
+        for j in sorted({0, nrhs // 2, nrhs - 1}):
+            assert resid(b[j], wilson.apply_D(u, xh[j], m)) <= 1e-10, (form, j)
+        out[form] = (xh, [s_["iters"] for s_ in st])
+    for form in (1, None):
+        assert rel(out[form][0], out[0][0]) < 1e-8, form
+        assert max(abs(a - c) for a, c in zip(out[form][1], out[0][1])) <= 1, form
+    with pytest.raises(wdmg.WdmgError):
+        ctx.set_tuning("coarse_apply", 2)
+
+
 def test_three_level_coarse_operator_and_solve():
     dims = (8, 8, 8, 8)
     m = -0.5
