@@ -876,9 +876,11 @@ __global__ __launch_bounds__(1024) void k_cgcr_apply(Geom g, int n2, int nrhs, i
 
 // K2: one workgroup per rhs.  vals = 4 j + 4 partial values per K1 workgroup;
 // p3: K3's g3 partial |w_{j-1}|^2 per rhs (j > 0).
+// hist (batched solves, else null): per rhs and iteration j, the h_i of
+// iteration j at [2 i], a_j at [2 kmax]; stride 2 kmax + 4 doubles per j.
 __global__ __launch_bounds__(1024) void k_cgcr_coef(int j, int vals, int g1, const double* __restrict__ part,
                                                    const double* __restrict__ p3, int g3, int kmax, CgcrState S,
-                                                   double* host_act, double* err) {
+                                                   double* host_act, double* err, double* hist) {
   extern __shared__ __align__(16) char dyn2[];
   double* tot = reinterpret_cast<double*>(dyn2);  // [vals + 1]
   const int q = blockIdx.x;
@@ -906,6 +908,10 @@ __global__ __launch_bounds__(1024) void k_cgcr_coef(int j, int vals, int g1, con
     const double hr = ni > 0.0 ? cr / ni : 0.0, hi = ni > 0.0 ? ci / ni : 0.0;
     h[2 * i] = hr;
     h[2 * i + 1] = hi;
+    if (hist) {
+      hist[((size_t)q * kmax + j) * (2 * kmax + 4) + 2 * i] = hr;
+      hist[((size_t)q * kmax + j) * (2 * kmax + 4) + 2 * i + 1] = hi;
+    }
     ww -= hr * cr + hi * ci;  // |c_i|^2 / |W_i|^2
     const double dr = tot[2 * j + 2 * i], di = tot[2 * j + 2 * i + 1];
     wr_re -= hr * dr + hi * di;  // conj(h_i) d_i
@@ -918,6 +924,10 @@ __global__ __launch_bounds__(1024) void k_cgcr_coef(int j, int vals, int g1, con
   S.act[q] = on ? 1.0 : 0.0;
   S.a[2 * q] = ok ? wr_re / ww : 0.0;
   S.a[2 * q + 1] = ok ? wr_im / ww : 0.0;
+  if (hist) {
+    hist[((size_t)q * kmax + j) * (2 * kmax + 4) + 2 * kmax] = S.a[2 * q];
+    hist[((size_t)q * kmax + j) * (2 * kmax + 4) + 2 * kmax + 1] = S.a[2 * q + 1];
+  }
   if (host_act) host_act[q] = on ? 1.0 : 0.0;
 }
 
@@ -962,7 +972,7 @@ __global__ __launch_bounds__(256) void k_cgcr_update(size_t n, int nrhs, int j, 
 // Threads of a workgroup form a (rows x nrhs) grid, thread t handling rhs
 // t % nrhs at positions (site, row) t / nrhs, t / nrhs + R, ... of the
 // workgroup's chunk; sums over those positions meet in LDS, per rhs.
-constexpr int kCgcrG3T = 256;    // workgroups (chunks) of the rhs-fast update
+constexpr int kCgcrG3T = 1024;   // workgroups (chunks) of the rhs-fast update: four per CU
 constexpr int kCgcrDotIG = 4;    // basis vectors per pass of the dot kernel
 
 // Sums v over the threads of each rhs column; thread q < nrhs receives its total.
@@ -1013,13 +1023,15 @@ __global__ __launch_bounds__(256) void k_cgcrT_init(size_t npos, int nrhs, const
   if ((int)threadIdx.x < nrhs) p3[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = sum;
 }
 
-// tol2 = tol^2 |b|^2, active = |b| > 0, from the init partials (one thread per rhs).
-__global__ void k_cgcrT_init_fin(int nrhs, int g, const double* __restrict__ p3, double tol, CgcrState S,
-                                 double* err) {
-  const int q = threadIdx.x;
-  if (q >= nrhs) return;
+// tol2 = tol^2 |b|^2, active = |b| > 0, from the init partials.
+// One wave per rhs sums the g partials.
+__global__ __launch_bounds__(64) void k_cgcrT_init_fin(int nrhs, int g, const double* __restrict__ p3, double tol,
+                                                       CgcrState S, double* err) {
+  const int q = blockIdx.x;
   double v = 0.0;
-  for (int b = 0; b < g; ++b) v += p3[(size_t)q * g + b];
+  for (int b = threadIdx.x; b < g; b += 64) v += p3[(size_t)q * g + b];
+  v = wave_sum(v);
+  if (threadIdx.x != 0) return;
   if (!isfinite(v)) err[0] = 1.0;
   S.tol2[q] = tol * tol * v;
   S.act[q] = v > 0.0 && isfinite(v) ? 1.0 : 0.0;
@@ -1259,10 +1271,12 @@ __global__ __launch_bounds__(256) void k_cgcrT_dots(size_t npos, int nrhs, int j
 
 // K3 (rhs-fast): w' = w - sum h_i W_i, z' = z - sum h_i Z_i, x += a z',
 // r -= a w', partial |w'|^2 per rhs; frozen rhs are left unchanged.
+// K3 (rhs-fast): w_j -= sum_i h_i W_i (kept, with |w_j|^2 for the next
+// iteration) and r -= a w_j.  The search directions stay unorthogonalised
+// (z_j = r_j as K1 copied it) and x is formed once per cycle by
+// k_cgcrT_backsolve + k_cgcrT_combine from the recorded h and a.
 __global__ __launch_bounds__(256) void k_cgcrT_update(size_t npos, int nrhs, int j, int kmax,
-                                                      const cx<double>* __restrict__ Wb,
-                                                      const cx<double>* __restrict__ Zb, cx<double>* __restrict__ w,
-                                                      cx<double>* __restrict__ z, cx<double>* __restrict__ x,
+                                                      const cx<double>* __restrict__ Wb, cx<double>* __restrict__ w,
                                                       cx<double>* __restrict__ r, CgcrState S, double* p3) {
   __shared__ double red[256];
   const int rows = 256 / nrhs, q = threadIdx.x % nrhs, rho = threadIdx.x / nrhs;
@@ -1275,21 +1289,48 @@ __global__ __launch_bounds__(256) void k_cgcrT_update(size_t npos, int nrhs, int
     const cx<double> a = mk(S.a[2 * q], S.a[2 * q + 1]);
     for (size_t p = p0 + rho; p < p1; p += rows) {
       const size_t e = p * nrhs + q;
-      cx<double> wv = w[e], zv = z[e];
-      for (int i = 0; i < j; ++i) {
-        const cx<double> hi = mk(h[2 * i], h[2 * i + 1]);
-        wv = wv - hi * Wb[(size_t)i * bs + e];
-        zv = zv - hi * Zb[(size_t)i * bs + e];
-      }
+      cx<double> wv = w[e];
+#pragma unroll 4
+      for (int i = 0; i < j; ++i) wv = wv - mk(h[2 * i], h[2 * i + 1]) * Wb[(size_t)i * bs + e];
       w[e] = wv;
-      z[e] = zv;
-      x[e] = x[e] + a * zv;
       r[e] = r[e] - a * wv;
       v += wv.re * wv.re + wv.im * wv.im;
     }
   }
   const double sum = rhs_column_sum(v, nrhs, rows, red);
   if ((int)threadIdx.x < nrhs) p3[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = sum;
+}
+
+// With orthogonalised directions z_m = z~_m - sum_{i<m} h_{m,i} z_i, the
+// cycle's update sum_m a_m z_m equals sum_m y_m z~_m for
+// y_m = a_m - sum_{i>m} y_i h_{i,m}, taken from the last direction down.
+// One thread per rhs; y_m lands at [2 kmax + 2] of row m of the history.
+__global__ __launch_bounds__(64) void k_cgcrT_backsolve(int nrhs, int J, int kmax, double* __restrict__ hist) {
+  const int q = threadIdx.x;
+  if (q >= nrhs) return;
+  const size_t st = 2 * (size_t)kmax + 4;
+  double* hq = hist + (size_t)q * kmax * st;
+  for (int m = J - 1; m >= 0; --m) {
+    cx<double> y = mk(hq[m * st + 2 * kmax], hq[m * st + 2 * kmax + 1]);
+    for (int i = m + 1; i < J; ++i)
+      y = y - mk(hq[i * st + 2 * kmax + 2], hq[i * st + 2 * kmax + 3]) * mk(hq[i * st + 2 * m], hq[i * st + 2 * m + 1]);
+    hq[m * st + 2 * kmax + 2] = y.re;
+    hq[m * st + 2 * kmax + 3] = y.im;
+  }
+}
+
+// x += sum_{m<J} y_m z~_m (rhs-fast vectors, element e belongs to rhs e % nrhs).
+__global__ __launch_bounds__(256) void k_cgcrT_combine(size_t npos, int nrhs, int J, int kmax,
+                                                       const cx<double>* __restrict__ Zb,
+                                                       const double* __restrict__ hist, cx<double>* __restrict__ x) {
+  const size_t bs = npos * nrhs;
+  const size_t st = 2 * (size_t)kmax + 4;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < bs; e += (size_t)gridDim.x * blockDim.x) {
+    const double* yq = hist + (size_t)(e % nrhs) * kmax * st + 2 * kmax + 2;
+    cx<double> xv = x[e];
+    for (int m = 0; m < J; ++m) xv = xv + mk(yq[m * st], yq[m * st + 1]) * Zb[(size_t)m * bs + e];
+    x[e] = xv;
+  }
 }
 
 template <typename R>
@@ -1444,7 +1485,7 @@ void coarsest_gcr(Ctx& c, Level& L, cx<double>* x, const cx<double>* b, int nrhs
   if (fast) {
     hipLaunchKernelGGL(k_cgcrT_init, dim3(kCgcrG3T), dim3(256), 0, c.stream, npos, nrhs, b, L.xT, r, L.cpart3);
     WDMG_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_cgcrT_init_fin, dim3(1), dim3(64), 0, c.stream, nrhs, kCgcrG3T, L.cpart3, tol, S,
+    hipLaunchKernelGGL(k_cgcrT_init_fin, dim3(nrhs), dim3(64), 0, c.stream, nrhs, kCgcrG3T, L.cpart3, tol, S,
                        c.dsc + S_ERR);
   } else {
     hipLaunchKernelGGL(k_cgcr_init, dim3(nrhs), dim3(256), 0, c.stream, b, x, r, n, tol, S, c.dsc + S_ERR);
@@ -1459,6 +1500,15 @@ void coarsest_gcr(Ctx& c, Level& L, cx<double>* x, const cx<double>* b, int nrhs
     for (int q = 0; q < nrhs; ++q)
       if (f[q] != 0.0) return false;
     return true;
+  };
+  // batch: x += sum_m y_m z~_m over the J directions of the cycle just ended
+  auto combine = [&](int J) {
+    hipLaunchKernelGGL(k_cgcrT_backsolve, dim3(1), dim3(64), 0, c.stream, nrhs, J, k, L.chist);
+    WDMG_HIP(hipGetLastError());
+    const size_t nb = (npos * nrhs + 255) / 256;
+    hipLaunchKernelGGL(k_cgcrT_combine, dim3((unsigned)(nb < 4096 ? nb : 4096)), dim3(256), 0, c.stream, npos, nrhs,
+                       J, k, L.basisZ, L.chist, L.xT);
+    WDMG_HIP(hipGetLastError());
   };
   const int fixed = c.capturing ? (c.coarse_fixed_iters < maxit ? c.coarse_fixed_iters : maxit) : 0;
   int it = 0;
@@ -1502,12 +1552,13 @@ void coarsest_gcr(Ctx& c, Level& L, cx<double>* x, const cx<double>* b, int nrhs
       WDMG_HIP(hipGetLastError());
       hipLaunchKernelGGL(k_cgcr_coef, dim3(nrhs), dim3(1024), (size_t)(vals + 1) * sizeof(double), c.stream, j, vals,
                          g1f, L.cpart, L.cpart3, kCgcrG3T, k, S,
-                         c.capturing ? nullptr : c.dring + (size_t)(it % kRing) * kMaxRhs, c.dsc + S_ERR);
+                         c.capturing ? nullptr : c.dring + (size_t)(it % kRing) * kMaxRhs, c.dsc + S_ERR, L.chist);
       WDMG_HIP(hipGetLastError());
       if (!c.capturing) WDMG_HIP(hipEventRecord(c.ring_ev[it % kRing], c.stream));
-      hipLaunchKernelGGL(k_cgcrT_update, dim3(kCgcrG3T), dim3(256), 0, c.stream, npos, nrhs, j, k, L.basisW,
-                         L.basisZ, w, z, L.xT, r, S, L.cpart3);
+      hipLaunchKernelGGL(k_cgcrT_update, dim3(kCgcrG3T), dim3(256), 0, c.stream, npos, nrhs, j, k, L.basisW, w, r, S,
+                         L.cpart3);
       WDMG_HIP(hipGetLastError());
+      if (j == k - 1) combine(k);
       c.n_Dc[L.l] += nrhs;
       if (!c.capturing && it >= lag && done_at(it - lag)) {
         ++it;
@@ -1523,7 +1574,7 @@ void coarsest_gcr(Ctx& c, Level& L, cx<double>* x, const cx<double>* b, int nrhs
     }
     hipLaunchKernelGGL(k_cgcr_coef, dim3(nrhs), dim3(1024), (size_t)(vals + 1) * sizeof(double), c.stream, j, vals,
                        g1, L.cpart, L.cpart3, kCgcrG3, k, S,
-                       c.capturing ? nullptr : c.dring + (size_t)(it % kRing) * kMaxRhs, c.dsc + S_ERR);
+                       c.capturing ? nullptr : c.dring + (size_t)(it % kRing) * kMaxRhs, c.dsc + S_ERR, nullptr);
     WDMG_HIP(hipGetLastError());
     if (!c.capturing) WDMG_HIP(hipEventRecord(c.ring_ev[it % kRing], c.stream));
     hipLaunchKernelGGL(k_cgcr_update, dim3(kCgcrG3, nrhs), dim3(256), 0, c.stream, n, nrhs, j, k, L.basisW,
@@ -1536,6 +1587,7 @@ void coarsest_gcr(Ctx& c, Level& L, cx<double>* x, const cx<double>* b, int nrhs
     }
   }
   if (fast) {
+    if (it > 0 && (it - 1) % k != k - 1) combine((it - 1) % k + 1);
     hipLaunchKernelGGL(k_cgcrT_out, dim3((unsigned)((npos * nrhs + 255) / 256)), dim3(256), 0, c.stream, npos, nrhs,
                        L.xT, x);
     WDMG_HIP(hipGetLastError());
@@ -1546,6 +1598,7 @@ void coarsest_gcr(Ctx& c, Level& L, cx<double>* x, const cx<double>* b, int nrhs
 size_t coarsest_gcr_partials(int nrhs, int k) {
   return (size_t)nrhs * kCgcrG1 * (4 * k + 4);
 }
+size_t coarsest_gcr_history(int nrhs, int k) { return (size_t)nrhs * k * (2 * (size_t)k + 4); }
 size_t coarsest_gcr_partials3(int nrhs) { return (size_t)nrhs * (kCgcrG3T > kCgcrG3 ? kCgcrG3T : kCgcrG3); }
 
 template void coarse_apply<double>(Ctx&, const Level&, const cx<double>*, cx<double>*, const cx<double>*, int,

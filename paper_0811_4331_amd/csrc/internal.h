@@ -127,6 +127,7 @@ struct Level {
   cx<double>* xT = nullptr;  // solution of a batched coarsest solve in the rhs-fast layout
   double* cpart = nullptr;   // partial sums of the coarsest GCR
   double* cpart3 = nullptr;
+  double* chist = nullptr;   // per-rhs coefficient history of a batched coarsest GCR cycle
 };
 
 constexpr int kWork = 8;
@@ -402,6 +403,7 @@ void coarse_shift(Ctx& c, Level& cl, double dm);
 void coarsest_gcr(Ctx& c, Level& L, cx<double>* x, const cx<double>* b, int nrhs, double tol, int k, int maxit);
 size_t coarsest_gcr_partials(int nrhs, int k);
 size_t coarsest_gcr_partials3(int nrhs);
+size_t coarsest_gcr_history(int nrhs, int k);
 // out = D_c in with the blocks stored in 16-bit (one scale per block), FP32
 // vectors; the 16-bit blocks are made from the FP64 ones on first use.
 void coarse_apply_h(Ctx& c, Level& cl, int kind, cx<float>* out, const cx<float>* in, int nrhs,

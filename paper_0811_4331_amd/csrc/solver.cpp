@@ -216,8 +216,10 @@ void ensure_coarsest_basis(Ctx& c, int nrhs) {
   L.xT = static_cast<cx<double>*>(dev_alloc(c, (size_t)nrhs * L.n * sizeof(cx<double>)));
   dev_free(c, L.cpart);
   dev_free(c, L.cpart3);
+  dev_free(c, L.chist);
   L.cpart = static_cast<double*>(dev_alloc(c, coarsest_gcr_partials(nrhs, c.mg.coarse_restart) * sizeof(double)));
   L.cpart3 = static_cast<double*>(dev_alloc(c, coarsest_gcr_partials3(nrhs) * sizeof(double)));
+  L.chist = static_cast<double*>(dev_alloc(c, coarsest_gcr_history(nrhs, c.mg.coarse_restart) * sizeof(double)));
   L.capB = nrhs;
 }
 
@@ -762,6 +764,7 @@ void free_hierarchy(Ctx& c) {
     dev_free(c, L.xT);
     dev_free(c, L.cpart);
     dev_free(c, L.cpart3);
+    dev_free(c, L.chist);
     Level blank;
     if (l == 0) {
       // level 0 work vectors outlive the hierarchy (same geometry)
