@@ -126,6 +126,12 @@ def test_prolongator_transfer_and_coarse_operator(dims, blk, nv):
     pe = ctx.prolong(0, gpu(ec)).cpu().numpy()
     pe_ref = transfer.as_spinor(transfer.prolong(q, ec, blk))
     assert rel(pe, pe_ref) < 1e-12
+    # chirality is kept ([gamma5, P] = 0, Sec. 3): gamma5 P c = P gamma5_c c and
+    # P^dagger gamma5 P = gamma5_c = diag(+1, -1) over the two chirality blocks
+    g5c = np.array([1.0, -1.0])[:, None]
+    assert rel(np.stack([wilson.apply_gamma5(x) for x in pe]), ctx.prolong(0, gpu(g5c * ec)).cpu().numpy()) < 1e-12
+    back = ctx.restrict(0, gpu(np.stack([wilson.apply_gamma5(x) for x in pe]))).cpu().numpy()
+    assert rel(back, g5c * ec) < 1e-12
     # coarse operator: GPU stencil vs the oracle's, which is pinned to P^dagger D P
     st = coarse.build_stencil(lev, q, blk)
     dc = ctx.apply_Dc(1, gpu(ec)).cpu().numpy()
