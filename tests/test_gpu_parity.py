@@ -400,6 +400,34 @@ def test_solve_with_graph_captured_vcycle(prec, nrhs):
             assert sg[j]["iters"] <= se[j]["iters"] + 3, (sg[j]["iters"], se[j]["iters"])
 
 
+def test_batched_coarsest_gcr_across_short_restarts():
+    """A coarsest GCR(3) runs many restart cycles; the batch forms x from its
+    unorthogonalised directions once per cycle, the single-rhs path updates x
+    every iteration.  Eager and graph-captured batched solves reach the true
+    residual with the oracle's D, and their columns equal single-rhs solves."""
+    dims = (8, 8, 8, 8)
+    seed = synthetic.gauge_seed(1, 1)
+    m = MCRIT[f"8x8x8x8_eps0.3_seed{seed}"]["m_crit"] + 0.05
+    ctx, u = make_ctx(dims, 0.3, seed, m)
+    nv = 8
+    v0 = synthetic.gaussian_vectors((nv,) + ctx.fine_shape(), synthetic.null_seed(1))
+    ctx.mg_setup([{"block": (4, 4, 4, 4), "nv": nv, "setup_iters": 20, "vectors": gpu(v0)}], coarse_tol=1e-6,
+                 coarse_restart=3, coarse_maxit=400)
+    nrhs = 5
+    b = synthetic.gaussian_spinor(dims, seed=77, nrhs=nrhs)
+    for graph in (False, True):
+        x, st = ctx.solve(gpu(b), tol=1e-10, restart=20, maxit=300, graph=graph)
+        xh = x.cpu().numpy()
+        for j in range(nrhs):
+            assert st[j]["converged"], (graph, j, st[j])
+            assert resid(b[j], wilson.apply_D(u, xh[j], m)) <= 1e-10, (graph, j)
+        if not graph:
+            for j in (0, nrhs - 1):
+                xj, sj = ctx.solve(gpu(b[j]), tol=1e-10, restart=20, maxit=300)
+                assert abs(sj[0]["iters"] - st[j]["iters"]) <= 1, (j, sj[0]["iters"], st[j]["iters"])
+                assert rel(xh[j], xj.cpu().numpy()) < 1e-8, j
+
+
 @pytest.mark.parametrize("form", [0, 1])
 @pytest.mark.parametrize("group", [1, 2, 3, 7, 64])
 def test_batched_dslash_rhs_groups_match_oracle(form, group):
