@@ -63,8 +63,12 @@ enum { WDMG_F64 = 0, WDMG_F32 = 1, WDMG_F16 = 2, WDMG_BF16 = 3 };
 
 typedef struct wdmg_ctx wdmg_ctx;
 
-/* Device-memory provider.  alloc(bytes, user) returns device memory or NULL;
- * free(ptr, user) releases it.  Pass NULL to wdmg_create for hipMalloc/hipFree. */
+/* Device-memory provider.  alloc(bytes, user) returns device memory aligned
+ * to 256 bytes, or NULL when it has none (the call then fails with
+ * WDMG_ERR_OOM; a misaligned pointer is rejected the same way); free(ptr,
+ * user) releases it.  Neither may unwind through the library (a callback
+ * written in another language must catch its own errors).  Pass NULL to
+ * wdmg_create for hipMalloc/hipFree. */
 typedef struct {
   void* (*alloc)(size_t bytes, void* user);
   void (*free)(void* ptr, void* user);

@@ -29,6 +29,9 @@ void* dev_alloc(Ctx& c, size_t bytes) {
   if (c.alloc.alloc) {
     p = c.alloc.alloc(bytes, c.alloc.user);
     if (!p) throw Error(WDMG_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    if (reinterpret_cast<uintptr_t>(p) & 255)  // not an allocation: never hand it to a kernel
+      throw Error(WDMG_ERR_OOM, "device allocation of " + std::to_string(bytes) +
+                                    " bytes returned a misaligned pointer");
   } else {
     if (hipMalloc(&p, bytes) != hipSuccess || !p) {
       (void)hipGetLastError();
@@ -224,8 +227,10 @@ void ensure_coarsest_basis(Ctx& c, int nrhs) {
 }
 
 // Work space of a whole V-cycle solve with nrhs right-hand sides in precision prec.
-void ensure_mg_work(Ctx& c, int nrhs, int prec) {
-  for (int l = 0; l < c.nlevels; ++l) {
+// A V-cycle in 16-bit storage works on the 16-bit fields of level 0
+// (ensure_work_h), so its FP32 work vectors start at level 1 (first = 1).
+void ensure_mg_work(Ctx& c, int nrhs, int prec, int first) {
+  for (int l = first; l < c.nlevels; ++l) {
     if (prec == WDMG_F32)
       ensure_work<float>(c, l, nrhs);
     else
@@ -407,7 +412,7 @@ int fgcr(Ctx& c, cx<double>* x, const cx<double>* b, int nrhs, const wdmg_solve_
   // every restart's true residual stay FP64.
   const bool basis32 = f32 || half;
   ensure_outer(c, k, nrhs, basis32, basis32);
-  if (p.precond) ensure_mg_work(c, nrhs, f32 || half ? WDMG_F32 : WDMG_F64);
+  if (p.precond) ensure_mg_work(c, nrhs, f32 || half ? WDMG_F32 : WDMG_F64, half ? 1 : 0);
   if (half) ensure_work_h(c, nrhs);
   HalfScope hs(c, half ? p.mg_prec : 0);
   const bool graph = p.precond && p.use_graph;
@@ -662,7 +667,7 @@ int bicgstab(Ctx& c, cx<double>* x, const cx<double>* b, double tol, int maxit, 
   if (pc) {
     const bool low = pc->mg_prec != WDMG_F64;
     ensure_outer(c, 1, 1, low, true);
-    ensure_mg_work(c, 1, low ? WDMG_F32 : WDMG_F64);
+    ensure_mg_work(c, 1, low ? WDMG_F32 : WDMG_F64, half ? 1 : 0);
     if (half) ensure_work_h(c, 1);
   }
   HalfScope hs(c, half ? pc->mg_prec : 0);

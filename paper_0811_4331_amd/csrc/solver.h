@@ -35,7 +35,7 @@ struct HalfScope {
 };
 template <typename R>
 void ensure_work(Ctx& c, int l, int nrhs);
-void ensure_mg_work(Ctx& c, int nrhs, int prec);
+void ensure_mg_work(Ctx& c, int nrhs, int prec, int first = 0);
 
 int fgcr(Ctx& c, cx<double>* x, const cx<double>* b, int nrhs, const wdmg_solve_params& p, wdmg_solve_stats* st);
 // BiCGStab from x = 0; with pc (precond set) the V-cycle of pc's precision is

@@ -14,6 +14,7 @@ from __future__ import annotations
 import ctypes
 import os
 import re
+import sys
 from typing import Sequence
 
 import torch
@@ -76,6 +77,28 @@ _FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
 class AllocStruct(ctypes.Structure):
     _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("user", ctypes.c_void_p)]
+
+
+def _torch_allocator(alloc_fn, delete_fn, dev_index, stream):
+    """The library's device-memory callbacks on torch's caching allocator.
+
+    An exception must not leave a ctypes callback: ctypes would print it and
+    hand the library an undefined pointer.  A failed allocation returns None
+    (NULL), which the library reports as WDMG_ERR_OOM; a failed release is
+    reported on stderr and otherwise ignored."""
+    def _alloc(nbytes, _user):
+        try:
+            return alloc_fn(int(nbytes), dev_index, stream)
+        except Exception:  # out of memory, or any allocator error
+            return None
+
+    def _free(ptr, _user):
+        try:
+            delete_fn(ptr)
+        except Exception as e:  # never unwind into the library
+            print(f"wdmg: releasing device memory at {ptr:#x} failed: {e}", file=sys.stderr)
+
+    return _alloc, _free
 
 
 _LIB = None
@@ -157,15 +180,8 @@ class Context:
         dev_index = self.device.index if self.device.index is not None else 0
         stream = self.stream
 
-        alloc_fn = torch.cuda.caching_allocator_alloc
-        delete_fn = torch.cuda.caching_allocator_delete
-
-        def _alloc(nbytes, _user):
-            return alloc_fn(int(nbytes), dev_index, stream)
-
-        def _free(ptr, _user):
-            delete_fn(ptr)
-
+        _alloc, _free = _torch_allocator(torch.cuda.caching_allocator_alloc, torch.cuda.caching_allocator_delete,
+                                         dev_index, stream)
         self._alloc_cb = _ALLOC_FN(_alloc)
         self._free_cb = _FREE_FN(_free)
         self._alloc = AllocStruct(self._alloc_cb, self._free_cb, None)

@@ -69,3 +69,23 @@ def test_kernel_ids_match_the_header():
     names = [n.split("=")[0].strip() for n in names]
     assert names[-1] == "WDMG_K_COUNT"
     assert [n[len("WDMG_K_"):].lower() for n in names[:-1]] == wdmg.KERNELS
+
+
+def test_allocator_callbacks_never_raise_into_the_library():
+    """A raising torch allocator must reach the library as NULL (reported as
+    WDMG_ERR_OOM), never as an undefined pointer; a raising release is
+    swallowed.  Called through the C function pointers ctypes builds."""
+
+    def boom(*_a):
+        raise RuntimeError("out of memory")
+
+    alloc, free = wdmg._torch_allocator(boom, boom, 0, None)
+    a_cb, f_cb = wdmg._ALLOC_FN(alloc), wdmg._FREE_FN(free)
+    a_c = wdmg._ALLOC_FN(ctypes.cast(a_cb, ctypes.c_void_p).value)
+    f_c = wdmg._FREE_FN(ctypes.cast(f_cb, ctypes.c_void_p).value)
+    for _ in range(100):
+        assert a_c(1 << 40, None) is None
+    f_c(4096, None)
+    ok, _ = wdmg._torch_allocator(lambda n, d, s: 4096 * n, boom, 0, None)
+    ok_c = wdmg._ALLOC_FN(ok)
+    assert wdmg._ALLOC_FN(ctypes.cast(ok_c, ctypes.c_void_p).value)(3, None) == 3 * 4096
