@@ -124,6 +124,9 @@ def parse():
                     help="adaptive augmentation (Sec. 2): two-level iterations refining each candidate "
                          "after the first (0: relaxation only)")
     ap.add_argument("--nrhs", type=int, default=1)
+    ap.add_argument("--nullvec-source", default="host", choices=["host", "device"],
+                    help="first-level null-vector starts: numpy on the host, kept on the device (default), or "
+                         "torch's seeded device generator inside each step, released after the setup (large lattices)")
     ap.add_argument("--coarse-apply", type=int, default=None, choices=[0, 1],
                     help="force a form of the batched coarsest-level operator (default: library choice)")
     ap.add_argument("--setup-prec", default="f64", choices=["f64", "f32"],
@@ -335,7 +338,16 @@ def main():
     ctx.set_gauge(torch.from_numpy(u).to(dev), t_bc=-1)
     ctx.set_mass(m)
     ctx.set_tuning("coarse_apply", a.coarse_apply)
-    v0 = torch.from_numpy(synthetic.gaussian_vectors((a.nv,) + ctx.fine_shape(), synthetic.null_seed(cfg))).to(dev)
+    v0_shape = (a.nv,) + ctx.fine_shape()
+    if a.nullvec_source == "host":
+        v0 = torch.from_numpy(synthetic.gaussian_vectors(v0_shape, synthetic.null_seed(cfg))).to(dev)
+    else:
+        v0 = None  # drawn on the device inside each step
+
+    def device_v0():
+        g = torch.Generator(device=dev)
+        g.manual_seed(synthetic.null_seed(cfg))
+        return torch.randn(v0_shape, dtype=torch.complex128, device=dev, generator=g)
     bh = np.stack([synthetic.gaussian_spinor(dims, synthetic.rhs_seed(cfg, j)) for j in range(a.nrhs)])
     b = torch.from_numpy(bh).to(dev)
     levels = [{"block": (4, 4, 4, 4), "nv": a.nv, "setup_iters": a.setup_iters, "adapt_iters": a.adapt_iters,
@@ -349,10 +361,15 @@ def main():
                        "setup_prec": a.setup_prec})
 
     def step():
+        if v0 is None:
+            levels[0]["vectors"] = device_v0()
+            torch.cuda.synchronize()
         t0 = time.perf_counter()
         ctx.mg_setup(levels, coarse_tol=a.coarse_tol, use_alpha=a.alpha)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
+        if v0 is None:
+            levels[0]["vectors"] = None  # the setup copied them; the solve gets the memory
         x, st = ctx.solve(b, tol=1e-10, restart=a.restart, maxit=2000, mg_prec=a.mg_prec, graph=a.graph,
                           outer=a.outer)
         torch.cuda.synchronize()
@@ -438,7 +455,7 @@ def main():
                    "nv2": a.nv2 if a.levels == 3 else None,
                    "nrhs": a.nrhs, "mg_prec": a.mg_prec, "setup_prec": a.setup_prec, "coarse_tol": a.coarse_tol,
                    "adapt_iters": a.adapt_iters, "outer": a.outer,
-                   "alpha_step": a.alpha, "graph": a.graph},
+                   "alpha_step": a.alpha, "graph": a.graph, "nullvec_source": a.nullvec_source},
         "setup_s": float(np.median(setups)), "solve_s_per_rhs": float(np.median(solves)) / a.nrhs,
         "mg_iters": [s["iters"] for s in last], "mg_n_D": [s["n_D"] for s in last],
         "mg_n_Dc": [s["n_Dc"][1] for s in last], "true_res": true_res,

@@ -981,11 +981,6 @@ void mg_setup(Ctx& c, const wdmg_mg_params& p) {
   c.have_mg = true;
 }
 
-void ensure_fine_work(Ctx& c) {
-  ensure_work<double>(c, 0, 1);
-  ensure_work<float>(c, 0, 1);
-}
-
 void ensure_outer(Ctx& c, int k, int nrhs, bool need32, bool basis32) {
   const size_t n = (size_t)c.g0.vpad * 12;
   if (nrhs > c.outer_cap) {

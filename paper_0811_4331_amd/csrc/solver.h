@@ -46,7 +46,6 @@ int bicgstab(Ctx& c, cx<double>* x, const cx<double>* b, double tol, int maxit, 
 void mg_setup(Ctx& c, const wdmg_mg_params& p);
 void free_hierarchy(Ctx& c);
 void init_level0(Ctx& c);
-void ensure_fine_work(Ctx& c);
 void ensure_outer(Ctx& c, int k, int nrhs, bool need32, bool basis32);
 void ensure_bicg(Ctx& c);
 
