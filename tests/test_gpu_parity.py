@@ -248,6 +248,8 @@ def test_batched_coarsest_solve_matches_single_solves(dims, blk, nv, nrhs):
     ((8, 8, 8, 8), (4, 4, 4, 4), 24, 32),    # 2Nv = 48, two full tiles (the 24^3 x 48 workload's shape)
     ((8, 8, 8, 8), (4, 4, 4, 4), 32, 5),     # 2Nv = 64, one ragged tile
     ((8, 8, 16, 16), (2, 2, 2, 2), 8, 9),    # 1024 coarse sites: the staged form by default
+    ((4, 4, 4, 8), (2, 2, 2, 2), 8, 64),     # the batch limit: four rhs tiles, two direction groups
+    ((8, 8, 8, 8), (4, 4, 4, 4), 16, 2),     # the smallest batch, 2Nv = 32, three direction groups
     ((4, 4, 4, 8), (2, 2, 2, 2), 6, 17),     # 2Nv = 12 is not staged: form 1 falls back to form 0
 ])
 def test_batched_coarse_operator_forms_agree(dims, blk, nv, nrhs):
