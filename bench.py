@@ -73,10 +73,11 @@ def dc_mfma_util(kinfo, nrhs, n2_mid, n2_coarsest):
     return out or None
 
 
-def counter_traffic(kernel, dims, bytes_per_launch):
+def counter_traffic(kernel, dims, bytes_per_launch, tuning=None):
     """HBM bytes per launch from the committed PMC measurement of this kernel on
     this lattice (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's reading), or
-    None when there is none or the kernel's sources changed since."""
+    None when there is none, the kernel's sources changed since, or this run's
+    Wilson forms and rhs groups differ from the ones the counters were taken with."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
@@ -90,7 +91,9 @@ def counter_traffic(kernel, dims, bytes_per_launch):
     if h.hexdigest()[:16] != t["source_hash"]:
         return None
     e = t["entries"].get(kernel + "@" + "x".join(map(str, dims)))
-    return None if e is None else e["measured_over_algorithmic"] * bytes_per_launch
+    if e is None or e.get("wilson_tuning") != tuning:
+        return None
+    return e["measured_over_algorithmic"] * bytes_per_launch
 
 
 def transfer_bytes(prec, nv):                      # per fine site: Nv columns (12 cplx) + fine + coarse share
@@ -127,6 +130,9 @@ def parse():
     ap.add_argument("--nullvec-source", default="host", choices=["host", "device"],
                     help="first-level null-vector starts: numpy on the host, kept on the device (default), or "
                          "torch's seeded device generator inside each step, released after the setup (large lattices)")
+    ap.add_argument("--wilson-tuning", default=None, metavar="F1,FB,GB",
+                    help="force the Wilson form of one-rhs launches (F1), and the form (FB) and rhs group (GB) "
+                         "of the setup's batched launches, instead of the autotuner (one-rhs solves only)")
     ap.add_argument("--coarse-apply", type=int, default=None, choices=[0, 1],
                     help="force a form of the batched coarsest-level operator (default: library choice)")
     ap.add_argument("--setup-prec", default="f64", choices=["f64", "f32"],
@@ -360,7 +366,19 @@ def main():
         levels.append({"block": (2, 2, 2, 2), "nv": a.nv2, "setup_iters": a.setup_iters, "vectors": v1,
                        "setup_prec": a.setup_prec})
 
+    # the setup relaxes its vectors in batches of at most 64 that fit a 16 GiB work budget
+    setup_field = int(np.prod(dims)) * 12 * (16 if a.setup_prec == "f64" else 8)
+    setup_batch = max(1, min(a.nv, 64, (16 << 30) // (2 * setup_field)))
+    forced = None
+    if a.wilson_tuning:
+        if a.nrhs != 1:
+            raise SystemExit("--wilson-tuning is for one-rhs solves")
+        forced = [int(v) for v in a.wilson_tuning.split(",")]
+
     def step():
+        if forced:
+            ctx.set_tuning("dslash", forced[1])
+            ctx.set_tuning("dslash_group", forced[2])
         if v0 is None:
             levels[0]["vectors"] = device_v0()
             torch.cuda.synchronize()
@@ -370,6 +388,9 @@ def main():
         t1 = time.perf_counter()
         if v0 is None:
             levels[0]["vectors"] = None  # the setup copied them; the solve gets the memory
+        if forced:
+            ctx.set_tuning("dslash", forced[0])
+            ctx.set_tuning("dslash_group", None)
         x, st = ctx.solve(b, tol=1e-10, restart=a.restart, maxit=2000, mg_prec=a.mg_prec, graph=a.graph,
                           outer=a.outer)
         torch.cuda.synchronize()
@@ -389,6 +410,14 @@ def main():
         stats.append(st)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
+    # Wilson forms and rhs groups this run used: one-rhs launches (form),
+    # the setup's batched launches (form, group)
+    if forced:
+        wilson_tuning = list(forced)
+    else:
+        one = "f64" if a.mg_prec == "f64" else "f32"
+        wilson_tuning = [ctx.get_tuning("dslash", one, 1), ctx.get_tuning("dslash", a.setup_prec, setup_batch),
+                         ctx.get_tuning("dslash_group", a.setup_prec, setup_batch)]
     prof = ctx.profile_read()
     ctx.profile(False)
     last = stats[-1]
@@ -425,7 +454,7 @@ def main():
     roofline = None
     if bpl is not None:
         ach = bpl / per_launch_s / 1e9
-        traffic = counter_traffic(dom, dims, bpl)
+        traffic = counter_traffic(dom, dims, bpl, wilson_tuning)
         roofline = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
                     "bytes_per_launch": bpl, "us_per_launch": per_launch_s * 1e6}
@@ -460,6 +489,7 @@ def main():
         "mg_iters": [s["iters"] for s in last], "mg_n_D": [s["n_D"] for s in last],
         "mg_n_Dc": [s["n_Dc"][1] for s in last], "true_res": true_res,
         "roofline": roofline, "kernels": kinfo, "dslash_in_step": dslash_step, "dc_mfma": dc_mfma,
+        "wilson_tuning": wilson_tuning,
     }
     if a.precision_report:
         result["precision_error"] = precision_report(ctx, torch, synthetic, dims, a.nv)

@@ -307,15 +307,33 @@ void run_dslash(Ctx& c, const IO& io, int nrhs, int variant, int rg, double* dot
 constexpr int kDslashForms = 3;
 
 template <class IO>
-float time_dslash(Ctx& c, const IO& io, int nrhs, int v, int rg, hipEvent_t (&ev)[2]) {
+float time_dslash(Ctx& c, const IO& io, int nrhs, int v, int rg, hipEvent_t (&ev)[2], int reps = 3) {
   run_dslash(c, io, nrhs, v, rg);
   WDMG_HIP(hipEventRecord(ev[0], c.stream));
-  for (int i = 0; i < 3; ++i) run_dslash(c, io, nrhs, v, rg);
+  for (int i = 0; i < reps; ++i) run_dslash(c, io, nrhs, v, rg);
   WDMG_HIP(hipEventRecord(ev[1], c.stream));
   WDMG_HIP(hipEventSynchronize(ev[1]));
   float ms = 0.f;
   WDMG_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
-  return ms;
+  return ms / reps;
+}
+
+// Timing windows of the autotuner: launches shorter than 0.1 ms are timed in
+// windows of at least 0.3 ms (up to 20 launches), best of three interleaved
+// rounds, so a few microseconds of launch jitter cannot decide between forms
+// that differ by 10%; longer launches keep one window of three.
+struct TuneWindow {
+  int reps = 3, rounds = 1;
+};
+inline TuneWindow tune_window(float ms_per_launch) {
+  TuneWindow t;
+  if (ms_per_launch > 0.f && ms_per_launch < 0.1f) {
+    t.rounds = 3;
+    t.reps = (int)(0.3f / ms_per_launch) + 1;
+    if (t.reps < 3) t.reps = 3;
+    if (t.reps > 20) t.reps = 20;
+  }
+  return t;
 }
 
 // Picks the form (rhs groups of the whole batch), then, for a batch, the rhs
@@ -325,9 +343,22 @@ template <class IO>
 void tune_dslash(Ctx& c, const IO& io, int nrhs, int& form, int& rg) {
   hipEvent_t ev[2];
   for (auto& e : ev) WDMG_HIP(hipEventCreate(&e));
+  TuneWindow tw;
   if (form < 0) {
+    const int g = rg < 0 ? nrhs : rg;
     float ms[kDslashForms] = {};
-    for (int v = 0; v < kDslashForms; ++v) ms[v] = time_dslash(c, io, nrhs, v, rg < 0 ? nrhs : rg, ev);
+    for (int v = 0; v < kDslashForms; ++v) ms[v] = time_dslash(c, io, nrhs, v, g, ev);
+    float est = ms[0];
+    for (int v = 1; v < kDslashForms; ++v) est = ms[v] < est ? ms[v] : est;
+    tw = tune_window(est);
+    if (tw.rounds > 1) {
+      for (int v = 0; v < kDslashForms; ++v) ms[v] = 1e30f;
+      for (int r = 0; r < tw.rounds; ++r)
+        for (int v = 0; v < kDslashForms; ++v) {
+          const float t = time_dslash(c, io, nrhs, v, g, ev, tw.reps);
+          if (t < ms[v]) ms[v] = t;
+        }
+    }
     form = 1;
     for (int v = 0; v < kDslashForms; ++v)
       if (ms[v] < ms[form]) form = v;
@@ -335,14 +366,24 @@ void tune_dslash(Ctx& c, const IO& io, int nrhs, int& form, int& rg) {
   if (rg < 0) {
     rg = nrhs;
     if (nrhs > 1) {
-      float best = time_dslash(c, io, nrhs, form, nrhs, ev);
-      for (int cand = 1; cand < nrhs; cand *= 2) {
-        const float t = time_dslash(c, io, nrhs, form, cand, ev);
-        if (t < best) {
-          best = t;
-          rg = cand;
+      // candidates: the whole batch, then groups of 1, 2, 4, ...
+      int cands[8], nc = 0;
+      cands[nc++] = nrhs;
+      for (int cand = 1; cand < nrhs && nc < 8; cand *= 2) cands[nc++] = cand;
+      float ms[8];
+      for (int i = 0; i < nc; ++i) ms[i] = time_dslash(c, io, nrhs, form, cands[i], ev);
+      if (tw.rounds == 1) tw = tune_window(ms[0]);
+      for (int r = 1; r < tw.rounds; ++r)
+        for (int i = 0; i < nc; ++i) {
+          const float t = time_dslash(c, io, nrhs, form, cands[i], ev, tw.reps);
+          if (t < ms[i]) ms[i] = t;
         }
-      }
+      float best = ms[0];
+      for (int i = 1; i < nc; ++i)
+        if (ms[i] < best) {
+          best = ms[i];
+          rg = cands[i];
+        }
     }
   }
   for (auto& e : ev) (void)hipEventDestroy(e);
