@@ -133,6 +133,9 @@ def parse():
     ap.add_argument("--wilson-tuning", default=None, metavar="F1,FB,GB",
                     help="force the Wilson form of one-rhs launches (F1), and the form (FB) and rhs group (GB) "
                          "of the setup's batched launches, instead of the autotuner (one-rhs solves only)")
+    ap.add_argument("--release-unused", action="store_true",
+                    help="after each setup, free the FP64/FP32 copies of P and D_c that the 16-bit V-cycle "
+                         "does not read (room for larger batches)")
     ap.add_argument("--coarse-apply", type=int, default=None, choices=[0, 1],
                     help="force a form of the batched coarsest-level operator (default: library choice)")
     ap.add_argument("--setup-prec", default="f64", choices=["f64", "f32"],
@@ -388,6 +391,8 @@ def main():
         t1 = time.perf_counter()
         if v0 is None:
             levels[0]["vectors"] = None  # the setup copied them; the solve gets the memory
+        if a.release_unused:
+            ctx.release_unused(a.mg_prec)
         if forced:
             ctx.set_tuning("dslash", forced[0])
             ctx.set_tuning("dslash_group", None)
@@ -423,9 +428,14 @@ def main():
     last = stats[-1]
     if not all(s["converged"] and s["true_res"] <= 1e-10 for st in stats for s in st):
         raise SystemExit(f"solve did not reach 1e-10: {last}")
-    # independent check of the final residual with the library's FP64 D
-    r = b - ctx.apply_D(x)
-    true_res = float(torch.linalg.vector_norm(r) / torch.linalg.vector_norm(b))
+    # independent check of the final residual with the library's FP64 D, one
+    # rhs at a time (a batch-sized temporary may not fit beside the solver's memory)
+    rr = 0.0
+    for j in range(a.nrhs):
+        rj = b[j] - ctx.apply_D(x[j])
+        rr += float(torch.linalg.vector_norm(rj)) ** 2
+        del rj
+    true_res = rr ** 0.5 / float(torch.linalg.vector_norm(b))
 
     ms_per_step = elapsed / a.steps * 1e3
     value = elapsed / a.steps / a.nrhs
@@ -484,7 +494,8 @@ def main():
                    "nv2": a.nv2 if a.levels == 3 else None,
                    "nrhs": a.nrhs, "mg_prec": a.mg_prec, "setup_prec": a.setup_prec, "coarse_tol": a.coarse_tol,
                    "adapt_iters": a.adapt_iters, "outer": a.outer,
-                   "alpha_step": a.alpha, "graph": a.graph, "nullvec_source": a.nullvec_source},
+                   "alpha_step": a.alpha, "graph": a.graph, "nullvec_source": a.nullvec_source,
+                   "release_unused": a.release_unused},
         "setup_s": float(np.median(setups)), "solve_s_per_rhs": float(np.median(solves)) / a.nrhs,
         "mg_iters": [s["iters"] for s in last], "mg_n_D": [s["n_D"] for s in last],
         "mg_n_Dc": [s["n_Dc"][1] for s in last], "true_res": true_res,

@@ -188,6 +188,19 @@ int wdmg_roundtrip(wdmg_ctx* ctx, void* out, const void* in, int nrhs, int prec)
  * chirality) and the coarse stencil is built.  Synchronises. */
 int wdmg_mg_setup(wdmg_ctx* ctx, const wdmg_mg_params* params);
 
+/* Memory for large batches: after wdmg_mg_setup, frees what a V-cycle in
+ * 16-bit storage of mg_prec (WDMG_F16 or WDMG_BF16) does not read, after
+ * making the 16-bit copies it does.  Freed are the FP64 and FP32 columns of
+ * the first prolongator, and the FP64 and FP32 blocks of every coarse level
+ * but the coarsest (whose FP64 GCR keeps them).  Until the next
+ * wdmg_mg_setup, calls that would read a freed copy fail with WDMG_ERR_ARG
+ * before launching anything: solves with a V-cycle in another precision,
+ * wdmg_get_prolongator(0), wdmg_restrict / wdmg_prolong / wdmg_apply_Dc in
+ * FP64 or FP32 where they need it, and wdmg_set_mass.  Synchronises.
+ * Errors: WDMG_ERR_NOT_SETUP without a hierarchy, WDMG_ERR_ARG for another
+ * precision. */
+int wdmg_release_unused(wdmg_ctx* ctx, int mg_prec);
+
 /* The orthonormalised columns of P from level l to l+1: device output,
  * canonical complex128 layout of level l, [nv][sites][dof]. */
 int wdmg_get_prolongator(wdmg_ctx* ctx, int level, void* V_out);

@@ -144,10 +144,13 @@ void apply_D_impl(Ctx& c, void* out, const void* in, int nrhs) {
 
 template <typename R>
 const cx<R>* dc_of(const Level& L) {
+  const cx<R>* p;
   if constexpr (sizeof(R) == 8)
-    return L.Dc64;
+    p = L.Dc64;
   else
-    return L.Dc32;
+    p = L.Dc32;
+  if (!p) throw Error(WDMG_ERR_ARG, "coarse blocks released by wdmg_release_unused");
+  return p;
 }
 
 template <typename R>
@@ -358,9 +361,18 @@ int wdmg_set_gauge(wdmg_ctx* c, const void* U, int t_bc) {
   });
 }
 
+int wdmg_release_unused(wdmg_ctx* c, int mg_prec) {
+  return guarded(c, [&]() {
+    release_unused(*c, mg_prec);
+    return WDMG_OK;
+  });
+}
+
 int wdmg_set_mass(wdmg_ctx* c, double m) {
   return guarded(c, [&]() {
     if (!std::isfinite(m)) throw Error(WDMG_ERR_ARG, "mass must be finite");
+    if (c->have_mg && c->released)
+      throw Error(WDMG_ERR_ARG, "coarse blocks released by wdmg_release_unused: set up again to change the mass");
     c->mass = m;
     if (c->have_mg) {
       const double dm = m - c->setup_mass;
@@ -429,6 +441,7 @@ int wdmg_get_prolongator(wdmg_ctx* c, int level, void* V_out) {
     need_ptr(V_out, "V_out");
     need_mg(*c, level, false);
     Level& L = c->lev[level];
+    if (!L.V64) throw Error(WDMG_ERR_ARG, "prolongator released by wdmg_release_unused");
     if (level == 0)
       fine_to_canonical<double, double>(*c, c->g0, L.V64, static_cast<cx<double>*>(V_out), L.nv);
     else

@@ -1404,6 +1404,7 @@ void coarse_apply(Ctx& c, const Level& cl, const cx<R>* Dc, cx<R>* out, const cx
 }
 
 void coarse_shift(Ctx& c, Level& cl, double dm) {
+  if (!cl.Dc64 || !cl.Dc32) throw Error(WDMG_ERR_ARG, "coarse blocks released by wdmg_release_unused");
   const int n = cl.nsite * cl.dof;
   hipLaunchKernelGGL((k_coarse_shift<double>), dim3((n + 255) / 256), dim3(256), 0, c.stream, cl.Dc64, cl.nsite,
                      cl.dof, dm);
@@ -1414,10 +1415,11 @@ void coarse_shift(Ctx& c, Level& cl, double dm) {
   cl.dc16_kind = 0;  // the 16-bit copy is remade from the shifted FP64 blocks on next use
 }
 
-void coarse_apply_h(Ctx& c, Level& cl, int kind, cx<float>* out, const cx<float>* in, int nrhs, cx<float>* copy) {
+void ensure_dc16(Ctx& c, Level& cl, int kind) {
   const int n2 = cl.dof;
   const size_t nblk = (size_t)cl.nsite * 9, nn = (size_t)n2 * n2;
   if (cl.dc16_kind != kind) {
+    if (!cl.Dc64) throw Error(WDMG_ERR_ARG, "FP64 coarse blocks released by wdmg_release_unused");
     if (!cl.Dc16) {
       cl.Dc16 = dev_alloc(c, nblk * nn * 4);
       cl.Dc16s = static_cast<float*>(dev_alloc(c, nblk * sizeof(float)));
@@ -1431,6 +1433,12 @@ void coarse_apply_h(Ctx& c, Level& cl, int kind, cx<float>* out, const cx<float>
     WDMG_HIP(hipGetLastError());
     cl.dc16_kind = kind;
   }
+}
+
+void coarse_apply_h(Ctx& c, Level& cl, int kind, cx<float>* out, const cx<float>* in, int nrhs, cx<float>* copy) {
+  const int n2 = cl.dof;
+  const size_t nn = (size_t)n2 * n2;
+  ensure_dc16(c, cl, kind);
   if (nrhs >= kMfmaMinRhs && n2 <= 64) {
     ProfScope ps(c, WDMG_K_DC_MFMA_H, (long long)cl.nsite * nrhs);
     const int waves = (2 * n2 + 31) / 32;

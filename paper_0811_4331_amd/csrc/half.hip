@@ -129,6 +129,7 @@ const void* u16(Ctx& c, int kind) {
 const void* v16(Ctx& c, Level& L, int kind) {
   if (kind != WDMG_F16 && kind != WDMG_BF16) throw Error(WDMG_ERR_ARG, "not a 16-bit kind");
   if (L.v16_kind == kind) return L.V16;
+  if (!L.V32) throw Error(WDMG_ERR_ARG, "FP32 prolongator released by wdmg_release_unused");
   const size_t n = (size_t)L.nv * L.n;
   if (!L.V16) L.V16 = dev_alloc(c, n * 4);
   round_kind(c, kind, L.V32, L.V16, n);

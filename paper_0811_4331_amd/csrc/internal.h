@@ -180,6 +180,7 @@ struct Ctx {
 
   // multigrid
   bool have_mg = false;
+  bool released = false;  // wdmg_release_unused freed higher-precision copies of P / D_c
   wdmg_mg_params mg{};
   int nlevels = 0;
   Level lev[WDMG_MAX_LEVELS];
@@ -394,6 +395,13 @@ template <typename R>
 void coarse_apply(Ctx& c, const Level& cl, const cx<R>* Dc, cx<R>* out, const cx<R>* in, int nrhs,
                   cx<R>* copy = nullptr);
 void coarse_shift(Ctx& c, Level& cl, double dm);
+// The 16-bit blocks of kind (WDMG_F16 / WDMG_BF16) of coarse level cl, made
+// from its FP64 blocks unless already current.
+void ensure_dc16(Ctx& c, Level& cl, int kind);
+// Frees what a V-cycle in 16-bit storage of kind does not read (after making
+// the 16-bit copies it does): the FP64 and FP32 first prolongator and the FP64
+// and FP32 blocks of every coarse level but the coarsest.
+void release_unused(Ctx& c, int kind);
 // The coarsest-level GCR(k) in FP64 for nrhs right-hand sides: x = 0, r = b,
 // iterate until every ||r_q|| <= tol ||b_q|| (lagged test) or maxit.  One rhs:
 // three launches per iteration on the canonical layout; a batch: four, on

@@ -133,22 +133,27 @@ cx<float>* work<float>(Level& L, int i) {
 }
 template <typename R>
 const cx<R>* vecs(const Level& L);
+// The accessors refuse copies that wdmg_release_unused freed (before any launch).
 template <>
 const cx<double>* vecs<double>(const Level& L) {
+  if (!L.V64) throw Error(WDMG_ERR_ARG, "FP64 prolongator released by wdmg_release_unused");
   return L.V64;
 }
 template <>
 const cx<float>* vecs<float>(const Level& L) {
+  if (!L.V32) throw Error(WDMG_ERR_ARG, "FP32 prolongator released by wdmg_release_unused");
   return L.V32;
 }
 template <typename R>
 const cx<R>* stencil(const Level& L);
 template <>
 const cx<double>* stencil<double>(const Level& L) {
+  if (!L.Dc64) throw Error(WDMG_ERR_ARG, "FP64 coarse blocks released by wdmg_release_unused");
   return L.Dc64;
 }
 template <>
 const cx<float>* stencil<float>(const Level& L) {
+  if (!L.Dc32) throw Error(WDMG_ERR_ARG, "FP32 coarse blocks released by wdmg_release_unused");
   return L.Dc32;
 }
 
@@ -785,6 +790,7 @@ void free_hierarchy(Ctx& c) {
     L = blank;
   }
   c.have_mg = false;
+  c.released = false;
   c.nlevels = 0;
   init_level0(c);
 }
@@ -979,6 +985,27 @@ void mg_setup(Ctx& c, const wdmg_mg_params& p) {
   WDMG_HIP(hipStreamSynchronize(c.stream));
   check_flags(c);
   c.have_mg = true;
+}
+
+void release_unused(Ctx& c, int kind) {
+  if (!c.have_mg) throw Error(WDMG_ERR_NOT_SETUP, "no multigrid hierarchy set up");
+  if (kind != WDMG_F16 && kind != WDMG_BF16) throw Error(WDMG_ERR_ARG, "mg_prec must be WDMG_F16 or WDMG_BF16");
+  Level& L0 = c.lev[0];
+  v16(c, L0, kind);
+  for (int l = 1; l < c.nlevels - 1; ++l) ensure_dc16(c, c.lev[l], kind);
+  WDMG_HIP(hipStreamSynchronize(c.stream));
+  dev_free(c, L0.V64);
+  dev_free(c, L0.V32);
+  L0.V64 = nullptr;
+  L0.V32 = nullptr;
+  for (int l = 1; l < c.nlevels - 1; ++l) {
+    Level& C = c.lev[l];
+    dev_free(c, C.Dc64);
+    dev_free(c, C.Dc32);
+    C.Dc64 = nullptr;
+    C.Dc32 = nullptr;
+  }
+  c.released = true;
 }
 
 void ensure_outer(Ctx& c, int k, int nrhs, bool need32, bool basis32) {

@@ -131,6 +131,7 @@ def load() -> ctypes.CDLL:
         "wdmg_roundtrip": (ip, [vp, vp, vp, ip, ip]),
         "wdmg_mg_setup": (ip, [vp, ctypes.POINTER(MgParams)]),
         "wdmg_get_prolongator": (ip, [vp, ip, vp]),
+        "wdmg_release_unused": (ip, [vp, ip]),
         "wdmg_apply_Dc": (ip, [vp, ip, vp, vp, ip, ip]),
         "wdmg_restrict": (ip, [vp, ip, vp, vp, ip, ip]),
         "wdmg_prolong": (ip, [vp, ip, vp, vp, ip, ip]),
@@ -291,6 +292,11 @@ class Context:
         self._check(self.lib.wdmg_mg_setup(self.h, ctypes.byref(p)))
         self.levels = new_levels
         del keep
+
+    def release_unused(self, mg_prec: str):
+        """Free the FP64/FP32 copies of P and D_c that a V-cycle in 16-bit storage
+        (``mg_prec`` "f16" or "bf16") does not read, until the next mg_setup."""
+        self._check(self.lib.wdmg_release_unused(self.h, PREC[mg_prec]))
 
     def get_prolongator(self, level: int):
         nv = self.levels[level][1]

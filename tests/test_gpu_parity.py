@@ -402,6 +402,47 @@ def test_solve_with_graph_captured_vcycle(prec, nrhs):
             assert sg[j]["iters"] <= se[j]["iters"] + 3, (sg[j]["iters"], se[j]["iters"])
 
 
+def test_release_unused_keeps_the_16bit_solve_and_refuses_the_rest():
+    """wdmg_release_unused frees the FP64/FP32 first prolongator and the
+    intermediate coarse blocks: the bf16 solve is unchanged (same 16-bit copies),
+    every call that would read a freed copy fails on the host with
+    WDMG_ERR_ARG, the coarsest level still applies in FP64, and a new setup
+    restores everything."""
+    dims = (8, 8, 8, 8)
+    seed = synthetic.gauge_seed(1, 1)
+    m = MCRIT[f"8x8x8x8_eps0.3_seed{seed}"]["m_crit"] + 0.05
+    ctx, u = make_ctx(dims, 0.3, seed, m)
+    v1 = synthetic.gaussian_vectors((6, 8, 8, 8, 8, 4, 3), 62)
+    v2 = synthetic.gaussian_vectors((8, 4, 4, 4, 4, 2, 6), 63)
+    levels = [{"block": (2, 2, 2, 2), "nv": 6, "setup_iters": 10, "vectors": gpu(v1)},
+              {"block": (2, 2, 2, 2), "nv": 8, "setup_iters": 10, "vectors": gpu(v2)}]
+    b = synthetic.gaussian_spinor(dims, seed=88, nrhs=3)
+    ctx.mg_setup(levels, coarse_tol=1e-1)
+    x0, s0 = ctx.solve(gpu(b), tol=1e-10, restart=20, maxit=300, mg_prec="bf16")
+    ctx.mg_setup(levels, coarse_tol=1e-1)
+    ctx.release_unused("bf16")
+    x1, s1 = ctx.solve(gpu(b), tol=1e-10, restart=20, maxit=300, mg_prec="bf16")
+    assert all(abs(a["iters"] - c["iters"]) <= 1 for a, c in zip(s1, s0))
+    assert rel(x1.cpu().numpy(), x0.cpu().numpy()) < 1e-10
+    for j in range(3):
+        assert resid(b[j], wilson.apply_D(u, x1.cpu().numpy()[j], m)) <= 1e-10
+    c2 = gpu(synthetic.gaussian_vectors((2, 2, 2, 2, 2, 8), 64))
+    ctx.apply_Dc(2, c2)  # the coarsest level keeps its FP64 blocks
+    for call in (lambda: ctx.solve(gpu(b[0]), tol=1e-10, restart=20, maxit=300, mg_prec="f64"),
+                 lambda: ctx.solve(gpu(b[0]), tol=1e-10, restart=20, maxit=300, mg_prec="f16"),
+                 lambda: ctx.get_prolongator(0),
+                 lambda: ctx.apply_Dc(1, gpu(synthetic.gaussian_vectors((4, 4, 4, 4, 2, 6), 65))),
+                 lambda: ctx.set_mass(m + 0.01)):
+        with pytest.raises(wdmg.WdmgError) as e:
+            call()
+        assert e.value.name == "WDMG_ERR_ARG", e.value
+    with pytest.raises(wdmg.WdmgError):
+        ctx.release_unused("f32")
+    ctx.mg_setup(levels, coarse_tol=1e-1)
+    x2, s2 = ctx.solve(gpu(b[0]), tol=1e-10, restart=20, maxit=300, mg_prec="f64")
+    assert s2[0]["converged"]
+
+
 def test_batched_coarsest_gcr_across_short_restarts():
     """A coarsest GCR(3) runs many restart cycles; the batch forms x from its
     unorthogonalised directions once per cycle, the single-rhs path updates x
