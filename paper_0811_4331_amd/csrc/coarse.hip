@@ -682,6 +682,10 @@ __device__ __forceinline__ floatx16 mfma_32x32x8<bf16_t>(const float (&a)[4], co
   return __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(x, y, acc, 0, 0, 0);
 }
 
+// Per-thread staging of one direction (workgroup of 64 ceil(2 n2 / 32)
+// threads, n2 <= 64): the block's 16-byte chunks, n2^2 / 4 <= 4 per thread,
+// and the batch's rhs rows, 32 n2 <= 8 per thread.
+constexpr int kH16Chunks = 4, kH16Rows = 8;
 template <typename H>
 __global__ __launch_bounds__(256) void k_coarse_apply_mfma16(Geom g, int n2, int nrhs, const cxh<H>* __restrict__ Dc,
                                                              const float* __restrict__ Dcs,
@@ -701,19 +705,46 @@ __global__ __launch_bounds__(256) void k_coarse_apply_mfma16(Geom g, int n2, int
   floatx16 acc;
 #pragma unroll
   for (int e = 0; e < 16; ++e) acc[e] = 0.f;
+  // rhs columns beyond the batch stay zero for every direction
+  const int nq = nrhs - q0 < 32 ? nrhs - q0 : 32;
+  for (int w = threadIdx.x; w < (32 - nq) * kr; w += blockDim.x) Bs[w % kr][nq + w / kr] = 0.f;
+  const int nthr = blockDim.x;
+  const int nch = n2 * n2 / 4;  // 16-byte chunks of a block (n2 even)
   for (int d = 0; d < 9; ++d) {
     const int nb = d == 8 ? s : ((d & 1) ? nbr_bwd(g, s, c, d >> 1) : nbr_fwd(g, s, c, d >> 1));
-    __syncthreads();
-    for (int w = threadIdx.x; w < 32 * n2; w += blockDim.x) {
-      const int q = w / n2, j = w % n2;
-      cx<float> v = mk(0.f, 0.f);
-      if (q0 + q < nrhs) v = in[(size_t)(q0 + q) * fs + (size_t)nb * n2 + j];
-      Bs[2 * j][q] = v.re;
-      Bs[2 * j + 1][q] = v.im;
-      if (d == 8 && copy && q0 + q < nrhs) copy[(size_t)(q0 + q) * fs + (size_t)s * n2 + j] = v;
+    // every load of the direction is issued before the first store to LDS
+    typedef float f2v __attribute__((ext_vector_type(2)));
+    typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+    const u4v* blk = reinterpret_cast<const u4v*>(Dc + ((size_t)s * 9 + d) * n2 * n2);
+    u4v ra[kH16Chunks];
+#pragma unroll
+    for (int u = 0; u < kH16Chunks; ++u) {
+      const int e = threadIdx.x + u * nthr;
+      if (e < nch) ra[u] = blk[e];
     }
-    const cxh<H>* blk = Dc + ((size_t)s * 9 + d) * n2 * n2;
-    for (int w = threadIdx.x; w < n2 * n2; w += blockDim.x) As16[w] = blk[w];
+    f2v rb[kH16Rows];
+#pragma unroll
+    for (int u = 0; u < kH16Rows; ++u) {
+      const int w = threadIdx.x + u * nthr;
+      if (w < nq * n2)
+        rb[u] = *reinterpret_cast<const f2v*>(in + (size_t)(q0 + w / n2) * fs + (size_t)nb * n2 + w % n2);
+    }
+    __syncthreads();  // every wave is done with the previous direction's operands
+#pragma unroll
+    for (int u = 0; u < kH16Chunks; ++u) {
+      const int e = threadIdx.x + u * nthr;
+      if (e < nch) reinterpret_cast<u4v*>(As16)[e] = ra[u];
+    }
+#pragma unroll
+    for (int u = 0; u < kH16Rows; ++u) {
+      const int w = threadIdx.x + u * nthr;
+      if (w < nq * n2) {
+        const int q = w / n2, j = w % n2;
+        Bs[2 * j][q] = rb[u].x;
+        Bs[2 * j + 1][q] = rb[u].y;
+        if (d == 8 && copy) copy[(size_t)(q0 + q) * fs + (size_t)s * n2 + j] = mk(rb[u].x, rb[u].y);
+      }
+    }
     __syncthreads();
     if (threadIdx.x < 32) {
       float m = 0.0f;
