@@ -686,7 +686,7 @@ __device__ __forceinline__ floatx16 mfma_32x32x8<bf16_t>(const float (&a)[4], co
 // threads, n2 <= 64): the block's 16-byte chunks, n2^2 / 4 <= 4 per thread,
 // and the batch's rhs rows, 32 n2 <= 8 per thread.
 constexpr int kH16Chunks = 4, kH16Rows = 8;
-template <typename H>
+template <typename H, int CB = kH16Rows>  // CB: rhs rows staged per thread (>= 32 n2 / threads for the batch)
 __global__ __launch_bounds__(256) void k_coarse_apply_mfma16(Geom g, int n2, int nrhs, const cxh<H>* __restrict__ Dc,
                                                              const float* __restrict__ Dcs,
                                                              const cx<float>* __restrict__ in,
@@ -722,9 +722,9 @@ __global__ __launch_bounds__(256) void k_coarse_apply_mfma16(Geom g, int n2, int
       const int e = threadIdx.x + u * nthr;
       if (e < nch) ra[u] = blk[e];
     }
-    f2v rb[kH16Rows];
+    f2v rb[CB];
 #pragma unroll
-    for (int u = 0; u < kH16Rows; ++u) {
+    for (int u = 0; u < CB; ++u) {
       const int w = threadIdx.x + u * nthr;
       if (w < nq * n2)
         rb[u] = *reinterpret_cast<const f2v*>(in + (size_t)(q0 + w / n2) * fs + (size_t)nb * n2 + w % n2);
@@ -736,7 +736,7 @@ __global__ __launch_bounds__(256) void k_coarse_apply_mfma16(Geom g, int n2, int
       if (e < nch) reinterpret_cast<u4v*>(As16)[e] = ra[u];
     }
 #pragma unroll
-    for (int u = 0; u < kH16Rows; ++u) {
+    for (int u = 0; u < CB; ++u) {
       const int w = threadIdx.x + u * nthr;
       if (w < nq * n2) {
         const int q = w / n2, j = w % n2;
@@ -1474,12 +1474,26 @@ void coarse_apply_h(Ctx& c, Level& cl, int kind, cx<float>* out, const cx<float>
     ProfScope ps(c, WDMG_K_DC_MFMA_H, (long long)cl.nsite * nrhs);
     const int waves = (2 * n2 + 31) / 32;
     const size_t lds = nn * 4;
-    if (kind == WDMG_F16)
-      hipLaunchKernelGGL((k_coarse_apply_mfma16<f16_t>), dim3(cl.nsite, (nrhs + 31) / 32), dim3(64 * waves), lds,
-                         c.stream, cl.g, n2, nrhs, static_cast<const cxh<f16_t>*>(cl.Dc16), cl.Dc16s, in, out, copy);
-    else
-      hipLaunchKernelGGL((k_coarse_apply_mfma16<bf16_t>), dim3(cl.nsite, (nrhs + 31) / 32), dim3(64 * waves), lds,
-                         c.stream, cl.g, n2, nrhs, static_cast<const cxh<bf16_t>*>(cl.Dc16), cl.Dc16s, in, out, copy);
+    // small batches stage at most two rhs rows per thread (fewer registers)
+    const bool few = (nrhs < 32 ? nrhs : 32) * n2 <= 2 * 64 * waves;
+    const dim3 grid(cl.nsite, (nrhs + 31) / 32), block(64 * waves);
+    if (kind == WDMG_F16) {
+      const auto* d16 = static_cast<const cxh<f16_t>*>(cl.Dc16);
+      if (few)
+        hipLaunchKernelGGL((k_coarse_apply_mfma16<f16_t, 2>), grid, block, lds, c.stream, cl.g, n2, nrhs, d16,
+                           cl.Dc16s, in, out, copy);
+      else
+        hipLaunchKernelGGL((k_coarse_apply_mfma16<f16_t>), grid, block, lds, c.stream, cl.g, n2, nrhs, d16, cl.Dc16s,
+                           in, out, copy);
+    } else {
+      const auto* d16 = static_cast<const cxh<bf16_t>*>(cl.Dc16);
+      if (few)
+        hipLaunchKernelGGL((k_coarse_apply_mfma16<bf16_t, 2>), grid, block, lds, c.stream, cl.g, n2, nrhs, d16,
+                           cl.Dc16s, in, out, copy);
+      else
+        hipLaunchKernelGGL((k_coarse_apply_mfma16<bf16_t>), grid, block, lds, c.stream, cl.g, n2, nrhs, d16,
+                           cl.Dc16s, in, out, copy);
+    }
   } else {
     ProfScope ps(c, WDMG_K_DC_H, (long long)cl.nsite * nrhs);
     if (kind == WDMG_F16)
