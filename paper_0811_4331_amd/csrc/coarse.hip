@@ -710,26 +710,30 @@ __global__ __launch_bounds__(256) void k_coarse_apply_mfma16(Geom g, int n2, int
   for (int w = threadIdx.x; w < (32 - nq) * kr; w += blockDim.x) Bs[w % kr][nq + w / kr] = 0.f;
   const int nthr = blockDim.x;
   const int nch = n2 * n2 / 4;  // 16-byte chunks of a block (n2 even)
-  for (int d = 0; d < 9; ++d) {
+  typedef float f2v __attribute__((ext_vector_type(2)));
+  typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+  u4v ra[kH16Chunks];
+  f2v rb[CB];
+  float fsc = 0.f;  // block scale of the fetched direction
+  // Direction d + 1 is fetched into registers (every load issued before any
+  // use) while the matrix cores work on direction d from LDS.
+  auto fetch = [&](int d) {
     const int nb = d == 8 ? s : ((d & 1) ? nbr_bwd(g, s, c, d >> 1) : nbr_fwd(g, s, c, d >> 1));
-    // every load of the direction is issued before the first store to LDS
-    typedef float f2v __attribute__((ext_vector_type(2)));
-    typedef unsigned int u4v __attribute__((ext_vector_type(4)));
     const u4v* blk = reinterpret_cast<const u4v*>(Dc + ((size_t)s * 9 + d) * n2 * n2);
-    u4v ra[kH16Chunks];
 #pragma unroll
     for (int u = 0; u < kH16Chunks; ++u) {
       const int e = threadIdx.x + u * nthr;
       if (e < nch) ra[u] = blk[e];
     }
-    f2v rb[CB];
 #pragma unroll
     for (int u = 0; u < CB; ++u) {
       const int w = threadIdx.x + u * nthr;
       if (w < nq * n2)
         rb[u] = *reinterpret_cast<const f2v*>(in + (size_t)(q0 + w / n2) * fs + (size_t)nb * n2 + w % n2);
     }
-    __syncthreads();  // every wave is done with the previous direction's operands
+    fsc = Dcs[(size_t)s * 9 + d];
+  };
+  auto stage = [&](int d) {
 #pragma unroll
     for (int u = 0; u < kH16Chunks; ++u) {
       const int e = threadIdx.x + u * nthr;
@@ -745,6 +749,13 @@ __global__ __launch_bounds__(256) void k_coarse_apply_mfma16(Geom g, int n2, int
         if (d == 8 && copy) copy[(size_t)(q0 + q) * fs + (size_t)s * n2 + j] = mk(rb[u].x, rb[u].y);
       }
     }
+  };
+  fetch(0);
+  for (int d = 0; d < 9; ++d) {
+    __syncthreads();  // every wave is done with the previous direction's operands
+    stage(d);
+    const float fd = fsc;
+    if (d + 1 < 9) fetch(d + 1);
     __syncthreads();
     if (threadIdx.x < 32) {
       float m = 0.0f;
@@ -777,7 +788,7 @@ __global__ __launch_bounds__(256) void k_coarse_apply_mfma16(Geom g, int n2, int
       }
       t = mfma_32x32x8<H>(a, b, t);
     }
-    const float f = Dcs[(size_t)s * 9 + d] * Bsc[l & 31];
+    const float f = fd * Bsc[l & 31];
 #pragma unroll
     for (int e = 0; e < 16; ++e) acc[e] += f * t[e];
   }
