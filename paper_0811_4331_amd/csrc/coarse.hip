@@ -1135,10 +1135,9 @@ __host__ __device__ inline size_t cgcr_lds_bytes(int n2, int nrhs, int ng) {
 // (the smaller stagings keep to 80 registers so that two 12-wave workgroups
 // share a compute unit)
 template <int SA>  // complex of the block staged per thread (n2^2 <= SA x group threads)
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(SA <= 4 ? 6 : 4))) void k_cgcrT_apply_lds(Geom g, int n2, int nrhs, int ng,
-                                                         const cx<double>* __restrict__ Dc,
-                                                         const cx<double>* __restrict__ r, cx<double>* __restrict__ w,
-                                                         cx<double>* __restrict__ z) {
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(SA <= 4 ? 6 : 4))) void k_cgcrT_apply_lds(
+    Geom g, int n2, int nrhs, int ng, const cx<double>* __restrict__ Dc, const cx<double>* __restrict__ r,
+    cx<double>* __restrict__ w, cx<double>* __restrict__ z) {
   extern __shared__ __align__(16) char dyn4[];
   const int ldc = cgcr_ldc(n2), nrt = mfma64_row_tiles(n2);
   const int wg = nrt * ((nrhs + 15) / 16);  // waves per group
