@@ -188,7 +188,8 @@ int wdmg_roundtrip(wdmg_ctx* ctx, void* out, const void* in, int nrhs, int prec)
  * chirality) and the coarse stencil is built.  Synchronises. */
 int wdmg_mg_setup(wdmg_ctx* ctx, const wdmg_mg_params* params);
 
-/* Memory for large batches: after wdmg_mg_setup, frees what a V-cycle in
+/* Memory for large batches (memory management, not an operation of the
+ * paper): after wdmg_mg_setup, frees what a V-cycle in
  * 16-bit storage of mg_prec (WDMG_F16 or WDMG_BF16) does not read, after
  * making the 16-bit copies it does.  Freed are the FP64 and FP32 columns of
  * the first prolongator, and the FP64 and FP32 blocks of every coarse level
