@@ -71,6 +71,23 @@ def test_kernel_ids_match_the_header():
     assert [n[len("WDMG_K_"):].lower() for n in names[:-1]] == wdmg.KERNELS
 
 
+def test_tuning_keys_match_the_header():
+    import re
+    with open(wdmg.HEADER) as fh:
+        text = fh.read()
+    body = re.search(r"enum \{\s*(WDMG_TUNE_AUTO[^}]*)\}", text).group(1)
+    vals = {}
+    for item in body.replace("\n", " ").split(","):
+        item = item.strip()
+        if "=" in item:
+            k, v = (t.strip() for t in item.split("="))
+            vals[k] = int(v)
+    assert vals["WDMG_TUNE_AUTO"] == -1
+    keys = {k[len("WDMG_TUNE_"):].lower(): v for k, v in vals.items() if k not in ("WDMG_TUNE_AUTO",)}
+    assert keys == wdmg.Context.TUNE
+    assert "WDMG_TUNE_COUNT" in body and max(keys.values()) + 1 == len(keys)
+
+
 def test_allocator_callbacks_never_raise_into_the_library():
     """A raising torch allocator must reach the library as NULL (reported as
     WDMG_ERR_OOM), never as an undefined pointer; a raising release is
