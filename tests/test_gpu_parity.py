@@ -316,6 +316,35 @@ def test_three_level_coarse_operator_and_solve():
         assert resid(bb[j], wilson.apply_D(u, xb[j].cpu().numpy(), m)) <= 1e-10
 
 
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32", 1e-5)])
+def test_three_level_vcycle_parity_via_single_iteration_solve(prec, tol):
+    """The modified 3-level cycle of Sec. 5 (4 stationary cycles of the level-1
+    V-cycle between the fine restriction and prolongation, alpha at every
+    level) on identical P_1, P_2 and an exact coarsest solve: one FGCR
+    iteration returns a M b, equal to the oracle's.  The level-2 grid is 3^4,
+    so every +-mu neighbour is a distinct site."""
+    dims, blk, nv1, nv2, m = (12, 12, 12, 12), (2, 2, 2, 2), 4, 6, -0.5
+    ctx, u = make_ctx(dims, 0.3, 91, m)
+    v1 = synthetic.gaussian_vectors((nv1, 12, 12, 12, 12, 4, 3), 92)
+    v2 = synthetic.gaussian_vectors((nv2, 6, 6, 6, 6, 2, nv1), 93)
+    ctx.mg_setup([{"block": blk, "nv": nv1, "setup_iters": 0, "vectors": gpu(v1)},
+                  {"block": blk, "nv": nv2, "setup_iters": 0, "vectors": gpu(v2)}],
+                 coarse_tol=1e-12, coarse_maxit=500, coarse_cycles=4)
+    lev = coarse.WilsonLevel(u, m, -1.0)
+    q1, _ = transfer.block_orthonormalize(transfer.as_chiral(v1), blk)
+    st1 = coarse.build_stencil(lev, q1, blk)
+    q2, _ = transfer.block_orthonormalize(v2, blk)
+    st2 = coarse.build_stencil(st1, q2, blk)
+    h = mg.Hierarchy([lev, st1, st2], [q1, q2], [blk, blk], coarse_tol=1e-12, coarse_maxit=500)
+    assert h.coarse_cycles == [4, 1]
+    b = synthetic.gaussian_spinor(dims, seed=94)
+    xg, _ = ctx.solve(gpu(b), tol=1e-30, restart=1, maxit=1, precond=True, mg_prec=prec)
+    z = transfer.as_spinor(h.vcycle(0, transfer.as_chiral(b)))
+    w = wilson.apply_D(u, z, m)
+    a = np.vdot(w, b) / np.vdot(w, w)
+    assert rel(xg.cpu().numpy(), a * z) < tol
+
+
 def test_error_paths():
     dims = (8, 8, 8, 8)
     ctx, u = make_ctx(dims, 0.3, 71, -0.4)

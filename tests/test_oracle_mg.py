@@ -201,3 +201,108 @@ def test_right_preconditioned_bicgstab():
     _, i0 = mg.bicgstab(ap, b, 1e-10)
     assert im["converged"] and np.linalg.norm(xm - xs) / np.linalg.norm(xs) < 1e-8
     assert im["iters"] < i0["iters"], (im["iters"], i0["iters"])
+
+
+# --- The modified 3-level cycle of Sec. 5 ------------------------------------
+# Between the fine restriction and prolongation the correction runs 4 cycles of
+# the next level as the stationary iteration e <- e + M_1 (r_c - D_1 e) from
+# e = 0.  The three pins below fix it against exact results that do not reuse
+# the oracle's loop: a level-1 operator c I (every step of the cycle becomes a
+# scalar map, so the residual after k cycles has a closed form), a unitary
+# second prolongator (M_1 = D_1^{-1}, so the correction is the exact level-1
+# solve), and a cycle without smoothing or step size (M_1 D_1 is then a
+# projector and the correction is M_1 r_c, independent of the count).
+
+def _scaled_identity_level(site_shape, nv, c):
+    n2 = 2 * nv
+    x = np.broadcast_to(c * np.eye(n2, dtype=np.complex128), tuple(site_shape) + (n2, n2)).copy()
+    y = np.zeros((4, 2) + tuple(site_shape) + (n2, n2), dtype=np.complex128)
+    return coarse.StencilLevel(x, y, nv)
+
+
+@pytest.mark.parametrize("cycles,omega", [(4, 0.5), (3, 0.5), (4, 0.8), (2, 0.3)])
+def test_three_level_correction_closed_form_on_scaled_identity(cycles, omega):
+    """Level-1 operator D_1 = c I (complex c), exact coarsest solve, alpha on.
+
+    An MR step on c I maps r to (1 - omega) r with x += omega r / c.  The
+    level-2 correction is y = Pi res / c with Pi = P_2 P_2^dagger, so
+    D_1 y = Pi res and alpha = 1; the post-smoother then scales (1 - Pi) res.
+    One level-1 V(2,2) cycle therefore has residual map
+    T = (1 - omega)^4 (1 - Pi), and after k stationary cycles the residual is
+    T^k r_c = (1 - omega)^(4k) (1 - Pi) r_c, i.e.
+    e_k = [r_c - (1 - omega)^(4k) (1 - Pi) r_c] / c.  A cycle that never
+    updates its residual, a wrong cycle count or an exact level-1 solve in
+    place of the cycles all miss this by far more than rounding."""
+    dims, blk1, blk2, nv1, nv2 = (4, 4, 4, 8), (2, 2, 2, 2), (2, 2, 2, 2), 2, 3
+    c = 1.7 + 0.4j
+    lev0 = _wilson_level(dims, seed=71)
+    v1 = transfer.as_chiral(synthetic.gaussian_vectors((nv1,) + (8, 4, 4, 4) + (4, 3), 72))
+    q1, _ = transfer.block_orthonormalize(v1, blk1)
+    lev1 = _scaled_identity_level((4, 2, 2, 2), nv1, c)
+    v2 = synthetic.gaussian_vectors((nv2, 4, 2, 2, 2, 2, nv1), 73)
+    q2, _ = transfer.block_orthonormalize(v2, blk2)
+    lev2 = coarse.build_stencil(lev1, q2, blk2)
+    h = mg.Hierarchy([lev0, lev1, lev2], [q1, q2], [blk1, blk2], omega=omega,
+                     coarse_cycles=[cycles, 1], coarse_tol=1e-15, coarse_maxit=50)
+    r = transfer.as_chiral(synthetic.gaussian_spinor(dims, seed=74))
+    rc = transfer.restrict(q1, r, blk1)
+    pi_rc = transfer.prolong(q2, transfer.restrict(q2, rc, blk2), blk2)
+    ek = (rc - (1 - omega) ** (4 * cycles) * (rc - pi_rc)) / c
+    got = h.correction(0, r)
+    want = transfer.prolong(q1, ek, blk1)
+    assert np.linalg.norm(got - want) / np.linalg.norm(want) < 1e-13
+    # the level-1 residual left after the cycles is far above the tolerance,
+    # so one cycle more or less would show
+    assert np.linalg.norm(rc - c * ek) > 1e4 * 1e-13 * np.linalg.norm(rc)
+
+
+def test_three_level_correction_is_exact_with_unitary_second_prolongator():
+    """1^4 second-level aggregates with Nv_2 = Nv_1 make P_2 unitary; with an
+    exact coarsest solve the level-1 V-cycle is then D_1^{-1} (the Galerkin
+    D_2 = P_2^dagger D_1 P_2 is D_1 in another basis), every further cycle
+    adds nothing, and the correction equals P_1 D_1^{-1} P_1^dagger r with D_1
+    the dense Galerkin operator on a 3^4 level-1 grid (distinct +-mu
+    neighbours)."""
+    dims, blk1, blk2, nv1 = (6, 6, 6, 6), (2, 2, 2, 2), (1, 1, 1, 1), 3
+    lev0 = _wilson_level(dims, eps=0.3, m=-0.3, seed=75)
+    v1 = transfer.as_chiral(synthetic.gaussian_vectors((nv1,) + dims + (4, 3), 76))
+    q1, _ = transfer.block_orthonormalize(v1, blk1)
+    lev1 = coarse.build_stencil(lev0, q1, blk1)
+    cs = (3, 3, 3, 3, 2, nv1)
+    v2 = synthetic.gaussian_vectors((nv1,) + cs, 77)
+    q2, _ = transfer.block_orthonormalize(v2, blk2)
+    lev2 = coarse.build_stencil(lev1, q2, blk2)
+    h = mg.Hierarchy([lev0, lev1, lev2], [q1, q2], [blk1, blk2], coarse_tol=1e-14,
+                     coarse_maxit=5000)
+    assert h.coarse_cycles == [4, 1]
+    r = transfer.as_chiral(synthetic.gaussian_spinor(dims, seed=78))
+    d1 = coarse.dense_from_apply(lambda f: coarse.apply_galerkin(lev0, q1, blk1, f), cs)
+    rc = transfer.restrict(q1, r, blk1)
+    want = transfer.prolong(q1, np.linalg.solve(d1, rc.reshape(-1)).reshape(cs), blk1)
+    got = h.correction(0, r)
+    assert np.linalg.norm(got - want) / np.linalg.norm(want) < 1e-10
+
+
+def test_three_level_correction_without_smoothing_is_one_galerkin_solve():
+    """With no smoothing, no step size and an exact coarsest solve,
+    M_1 = P_2 D_2^{-1} P_2^dagger and (I - M_1 D_1) M_1 = 0, so the 4-cycle
+    correction is P_1 M_1 P_1^dagger r whatever the count; a cycle that does
+    not update its residual returns 4 times that."""
+    dims, blk1, blk2, nv1, nv2 = (8, 8, 8, 8), (2, 2, 2, 2), (2, 2, 2, 2), 2, 3
+    lev0 = _wilson_level(dims, eps=0.3, m=-0.3, seed=79)
+    v1 = transfer.as_chiral(synthetic.gaussian_vectors((nv1,) + dims + (4, 3), 80))
+    q1, _ = transfer.block_orthonormalize(v1, blk1)
+    lev1 = coarse.build_stencil(lev0, q1, blk1)
+    v2 = synthetic.gaussian_vectors((nv2, 4, 4, 4, 4, 2, nv1), 81)
+    q2, _ = transfer.block_orthonormalize(v2, blk2)
+    lev2 = coarse.build_stencil(lev1, q2, blk2)
+    h = mg.Hierarchy([lev0, lev1, lev2], [q1, q2], [blk1, blk2], nu_pre=0, nu_post=0,
+                     use_alpha=False, coarse_tol=1e-14, coarse_maxit=5000)
+    cs2 = (2, 2, 2, 2, 2, nv2)
+    d2 = coarse.dense_from_apply(lambda f: coarse.apply_galerkin(lev1, q2, blk2, f), cs2)
+    r = transfer.as_chiral(synthetic.gaussian_spinor(dims, seed=82))
+    rc2 = transfer.restrict(q2, transfer.restrict(q1, r, blk1), blk2)
+    e2 = np.linalg.solve(d2, rc2.reshape(-1)).reshape(cs2)
+    want = transfer.prolong(q1, transfer.prolong(q2, e2, blk2), blk1)
+    got = h.correction(0, r)
+    assert np.linalg.norm(got - want) / np.linalg.norm(want) < 1e-10
