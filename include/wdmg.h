@@ -251,7 +251,12 @@ int wdmg_solve_bicgstab(wdmg_ctx* ctx, void* x, const void* b, int nrhs, double 
  * keeps the fastest for the context's lifetime; a fixed value forces a form.
  *   WDMG_TUNE_DSLASH: 0 one thread per site, 1 one wave per direction with
  *                     the four partial sums added in LDS, 2 form 1 with its
- *                     registers capped so that four waves fit per SIMD.
+ *                     registers capped so that four waves fit per SIMD,
+ *                     3 and 4 form 1 with 2 or 4 right-hand sides per
+ *                     thread (each link loaded once for them, the
+ *                     direction sums meeting in LDS one rhs at a time);
+ *                     forms 3 and 4 apply to batches they divide (a forced
+ *                     value runs form 1 on other batch sizes).
  *   WDMG_TUNE_DSLASH_GROUP: right-hand sides per group (1..64) in the
  *                     workgroup order of a batched Wilson launch: each XCD
  *                     sweeps its lattice region once per group, with the

@@ -43,6 +43,17 @@ struct FullIO {
 #pragma unroll
     for (int k = 0; k < 12; ++k) out[fidx(s, k, 12)] = v[k];
   }
+  // right-hand side r of the selected chunk
+  __device__ __forceinline__ void spinor_r(int r, int vpad, int s, cx<R> (&p)[12]) const {
+    const cx<R>* b = in + (size_t)r * 12 * vpad;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) p[k] = b[fidx(s, k, 12)];
+  }
+  __device__ __forceinline__ void store_r(int r, int vpad, int s, const cx<R> (&v)[12]) const {
+    cx<R>* b = out + (size_t)r * 12 * vpad;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) b[fidx(s, k, 12)] = v[k];
+  }
 };
 
 template <typename H>
@@ -64,6 +75,12 @@ struct HalfIO {
     load_link_h(U, mu, s, neg, u);
   }
   __device__ __forceinline__ void store(int s, const cx<float> (&v)[12]) const { store_site_h(out, osc, s, v); }
+  __device__ __forceinline__ void spinor_r(int r, int vpad, int s, cx<float> (&p)[12]) const {
+    load_site_h(in + (size_t)r * 12 * vpad, isc + (size_t)r * vpad, s, p);
+  }
+  __device__ __forceinline__ void store_r(int r, int vpad, int s, const cx<float> (&v)[12]) const {
+    store_site_h(out + (size_t)r * 12 * vpad, osc + (size_t)r * vpad, s, v);
+  }
 };
 
 template <int MU, int SIGN, class IO, typename R = typename IO::T>
@@ -264,10 +281,115 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MINW))) voi
   if constexpr (DOTS) wave_dots(live, acc, p, dots, (size_t)rhs * nsb + sb);
 }
 
+// Register-blocked direction-split form for batches: the workgroup layout of
+// k_dslash4 (wave mu computes the two hops along mu for 64 sites) with RB
+// right-hand sides of one chunk per thread.  Each link is loaded (and its
+// third row rebuilt) once and applied to the RB neighbour spinors, so a batch
+// reads every link once per chunk instead of once per rhs, and each wave
+// keeps RB independent spinor loads in flight.  The partial sums of the four
+// directions meet in LDS one rhs at a time (two buffers, one barrier per rhs).
+// The batch size must be a multiple of RB; chunks are ordered like the rhs
+// of the other forms (batch_block with chunks in place of rhs).
+template <int MU, int SIGN, int RB, class IO, typename R = typename IO::T>
+__device__ __forceinline__ void hop_rb(const IO& io, int vpad, int nb, int link_site, bool neg,
+                                       cx<R> (&acc)[RB][12]) {
+  cx<R> u[9];
+  io.link(MU, link_site, neg, u);
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    cx<R> p[12];
+    io.spinor_r(r, vpad, nb, p);
+    cx<R> h[6];
+    project<MU, SIGN>(p, h);
+    cx<R> uh[6];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        cx<R> t = mk<R>(0, 0);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+          if (SIGN > 0)
+            cmadd(t, u[i * 3 + b], h[a * 3 + b]);   // U h
+          else
+            cmaddc(t, u[b * 3 + i], h[a * 3 + b]);  // U^+ h
+        }
+        uh[a * 3 + i] = t;
+      }
+    }
+    expand_add<MU, SIGN>(uh, acc[r]);
+  }
+}
+
+template <int MU, int RB, class IO, typename R>
+__device__ __forceinline__ void hops_mu_rb(const IO& io, const Geom& g, int s, const int (&c)[4], bool tneg,
+                                           cx<R> (&acc)[RB][12]) {
+  const bool last = MU == 3 && tneg && c[3] == g.L[3] - 1, first = MU == 3 && tneg && c[3] == 0;
+  const int f = nbr_fwd(g, s, c, MU), b = nbr_bwd(g, s, c, MU);
+  hop_rb<MU, +1, RB>(io, g.vpad, f, s, last, acc);
+  hop_rb<MU, -1, RB>(io, g.vpad, b, b, first, acc);
+}
+
+template <class IO, bool DOTS, int RB, typename R = typename IO::T>
+__global__ __launch_bounds__(256) void k_dslash4_rb(Geom g, IO io, R diag, int tneg, int nsb, int nchunk, int rg,
+                                                    double* dots) {
+  __shared__ cx<R> part[2][3][12][kDs4Sites];
+  int sb, ch;
+  batch_block(nsb, nchunk, rg, sb, ch);
+  const int lane = threadIdx.x & 63, mu = threadIdx.x >> 6;
+  const int s = sb * kDs4Sites + lane;
+  io.select_rhs(ch * RB, g.vpad);
+  cx<R> acc[RB][12];
+#pragma unroll
+  for (int r = 0; r < RB; ++r)
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[r][k] = mk<R>(0, 0);
+  const bool live = s < g.vol;
+  if (live) {
+    int c[4];
+    coords_of(g, s, c);
+    switch (mu) {
+      case 0: hops_mu_rb<0, RB>(io, g, s, c, tneg, acc); break;
+      case 1: hops_mu_rb<1, RB>(io, g, s, c, tneg, acc); break;
+      case 2: hops_mu_rb<2, RB>(io, g, s, c, tneg, acc); break;
+      default: hops_mu_rb<3, RB>(io, g, s, c, tneg, acc); break;
+    }
+  }
+  const R half = (R)0.5;
+  // the grid covers vpad sites in whole 64-site blocks: every lane's site is
+  // below vpad, and the barrier below is reached by all four waves
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    if (mu > 0) {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) part[r & 1][mu - 1][k][lane] = acc[r][k];
+    }
+    __syncthreads();
+    if (mu == 0) {
+      cx<R> p[12];
+      if (live) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k)
+          acc[r][k] = acc[r][k] + part[r & 1][0][k][lane] + part[r & 1][1][k][lane] + part[r & 1][2][k][lane];
+        io.spinor_r(r, g.vpad, s, p);
+#pragma unroll
+        for (int k = 0; k < 12; ++k)
+          acc[r][k] = mk<R>(diag * p[k].re - half * acc[r][k].re, diag * p[k].im - half * acc[r][k].im);
+      }
+      io.store_r(r, g.vpad, s, acc[r]);  // padding sites: zeros
+      if constexpr (DOTS) wave_dots(live, acc[r], p, dots, (size_t)(ch * RB + r) * nsb + sb);
+    }
+  }
+}
+
 // Slots of MR partial sums per right-hand side written by a fused launch.
 int dslash_parts(const Geom& g, int variant) {
-  return variant != 0 ? g.vpad / kDs4Sites : (g.vpad / kDslashThreads + (g.vpad % kDslashThreads != 0)) * (kDslashThreads / 64);
+  if (variant != 0) return g.vpad / kDs4Sites;
+  return (g.vpad / kDslashThreads + (g.vpad % kDslashThreads != 0)) * (kDslashThreads / 64);
 }
+
+// Right-hand sides per thread of a form (forms 3 and 4 are register-blocked).
+constexpr int rb_of(int variant) { return variant == 3 ? 2 : (variant == 4 ? 4 : 1); }
 
 template <class IO>
 void run_dslash(Ctx& c, const IO& io, int nrhs, int variant, int rg, double* dots = nullptr) {
@@ -289,6 +411,26 @@ void run_dslash(Ctx& c, const IO& io, int nrhs, int variant, int rg, double* dot
       else
         hipLaunchKernelGGL((k_dslash4<IO, false, 4>), grid, block, 0, c.stream, g, io, diag, tneg, (int)gx, nrhs, rg, dots);
     }
+  } else if (variant == 3 || variant == 4) {
+    const unsigned gx = g.vpad / kDs4Sites;
+    const R diag = (R)(4.0 + c.mass);
+    if (variant == 3) {
+      const int nch = nrhs / 2, rgc = rg >= 2 ? rg / 2 : 1;
+      if (dots)
+        hipLaunchKernelGGL((k_dslash4_rb<IO, true, 2>), dim3(gx * nch), dim3(256), 0, c.stream, g, io, diag, tneg,
+                           (int)gx, nch, rgc, dots);
+      else
+        hipLaunchKernelGGL((k_dslash4_rb<IO, false, 2>), dim3(gx * nch), dim3(256), 0, c.stream, g, io, diag, tneg,
+                           (int)gx, nch, rgc, dots);
+    } else {
+      const int nch = nrhs / 4, rgc = rg >= 4 ? rg / 4 : 1;
+      if (dots)
+        hipLaunchKernelGGL((k_dslash4_rb<IO, true, 4>), dim3(gx * nch), dim3(256), 0, c.stream, g, io, diag, tneg,
+                           (int)gx, nch, rgc, dots);
+      else
+        hipLaunchKernelGGL((k_dslash4_rb<IO, false, 4>), dim3(gx * nch), dim3(256), 0, c.stream, g, io, diag, tneg,
+                           (int)gx, nch, rgc, dots);
+    }
   } else {
     const unsigned gx = g.vpad / kDslashThreads + (g.vpad % kDslashThreads != 0);
     if (dots)
@@ -301,10 +443,14 @@ void run_dslash(Ctx& c, const IO& io, int nrhs, int variant, int rg, double* dot
   WDMG_HIP(hipGetLastError());
 }
 
-// Autotuner: times the three forms (HIP events, 3 launches each after one
-// warm-up launch) on the caller's buffers -- the operator has no side effects
-// besides writing `out` -- and returns the fastest (form 1 on ties).
-constexpr int kDslashForms = 3;
+// Autotuner: times the forms (HIP events, 3 launches each after one warm-up
+// launch) on the caller's buffers -- the operator has no side effects besides
+// writing `out` -- and returns the fastest (form 1 on ties).  The
+// register-blocked forms 3 and 4 take part when the batch is a multiple of
+// their 2 or 4 rhs per thread.
+constexpr int kDslashForms = 5;
+
+inline bool form_fits(int v, int nrhs) { return nrhs % rb_of(v) == 0; }
 
 template <class IO>
 float time_dslash(Ctx& c, const IO& io, int nrhs, int v, int rg, hipEvent_t (&ev)[2], int reps = 3) {
@@ -346,8 +492,8 @@ void tune_dslash(Ctx& c, const IO& io, int nrhs, int& form, int& rg) {
   TuneWindow tw;
   if (form < 0) {
     const int g = rg < 0 ? nrhs : rg;
-    float ms[kDslashForms] = {};
-    for (int v = 0; v < kDslashForms; ++v) ms[v] = time_dslash(c, io, nrhs, v, g, ev);
+    float ms[kDslashForms];
+    for (int v = 0; v < kDslashForms; ++v) ms[v] = form_fits(v, nrhs) ? time_dslash(c, io, nrhs, v, g, ev) : 1e30f;
     float est = ms[0];
     for (int v = 1; v < kDslashForms; ++v) est = ms[v] < est ? ms[v] : est;
     tw = tune_window(est);
@@ -355,6 +501,7 @@ void tune_dslash(Ctx& c, const IO& io, int nrhs, int& form, int& rg) {
       for (int v = 0; v < kDslashForms; ++v) ms[v] = 1e30f;
       for (int r = 0; r < tw.rounds; ++r)
         for (int v = 0; v < kDslashForms; ++v) {
+          if (!form_fits(v, nrhs)) continue;
           const float t = time_dslash(c, io, nrhs, v, g, ev, tw.reps);
           if (t < ms[v]) ms[v] = t;
         }
@@ -397,6 +544,7 @@ int launch_dslash(Ctx& c, const IO& io, int nrhs, int prof_id, int prec_index, d
   signed char& fslot = c.tune_dslash[prec_index][key];
   signed char& gslot = c.tune_group[prec_index][key];
   int v = c.tune_force[WDMG_TUNE_DSLASH] >= 0 ? c.tune_force[WDMG_TUNE_DSLASH] : fslot;
+  if (v >= 0 && !form_fits(v, nrhs)) v = 1;  // a forced register-blocked form on a batch it does not divide
   int rg = c.tune_force[WDMG_TUNE_DSLASH_GROUP] >= 0 ? c.tune_force[WDMG_TUNE_DSLASH_GROUP] : gslot;
   if ((v < 0 || rg < 0) && !c.capturing) {
     tune_dslash(c, io, nrhs, v, rg);
