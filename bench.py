@@ -4,20 +4,25 @@
 One step = one pass of the whole hot path over one batch of right-hand sides:
 the adaptive setup (MR relaxation of the Nv starting vectors on D v = 0,
 FP64 block orthonormalisation, Galerkin coarse operator) followed by the
-MG-preconditioned flexible GCR(50) solve of every right-hand side to true
+MG-preconditioned flexible GCR solve of every right-hand side to true
 relative residual 1e-10 (FP64).  `value` is the step's wall time per
 right-hand side, inputs resident in HBM before the timed region.
 
-Default workload: the 16^4 lattice with links exp(i 0.3 H), antiperiodic
-time, m = m_crit + 0.01 (m_crit from the oracle's Arnoldi, stored in
-tests/golden/mcrit.json), 2-level MG with 4^4 aggregates and Nv = 20, FP64
-throughout, one Gaussian right-hand side.  Unpreconditioned FP64 BiCGStab on
-the same GPU is timed beside it, outside the K steps.
+Default workload: the 24^3 x 48 lattice with links exp(i 0.45 H),
+antiperiodic time, m = m_crit + 0.005 with m_crit of this very field,
+32 Gaussian right-hand sides solved together: batched FP32 setup (Nv = 24,
+100 MR steps, 4^4 aggregates), V-cycle in BF16 storage with FP32
+arithmetic (coarse operator and P^dagger on matrix cores), FP64 coarsest
+GCR and FP64 outer flexible GCR(16) with an FP32 basis.
 
-The JSON line also carries the roofline of the dominant kernel (timed with
-HIP events on the library's stream during the timed steps), Dslash bandwidth
-on a lattice larger than the 256 MB Infinity Cache, and the FP64 oracle timed
-on the host as `cpu_baseline`.
+Beside the K timed steps, on the same GPU and field, the line carries the
+two comparators of the target: FP64 single-rhs MG (FP64 setup and V-cycle,
+FGCR(50)) and plain FP64 BiCGStab, each timed after a warm-up.  It also
+carries the roofline of the step's dominant kernel (HIP events on the
+library's stream during the timed steps), the Wilson operator's bandwidth
+on a 32^4 lattice (larger than the 256 MB Infinity Cache), the coarse
+operator's matrix-core utilisation, and the FP64 oracle's real MG solve of
+the 8^4 workload timed on the host as `cpu_baseline`.
 """
 from __future__ import annotations
 
@@ -34,89 +39,139 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MG time-to-solution @ rel.res 1e-10 (s/RHS); Dslash GB/s; D_c MFMA util"
 HBM_PEAK_GBS = 8000.0
-# Algorithmic (compulsory) bytes per work unit, per kernel.
-DSLASH_BYTES = {"f64": 960, "f32": 480, "f16": 248, "bf16": 248}  # per fine site: psi in, 4 links, out
+# Dense peaks of MI355X (TFLOP/s) by the dtype a kernel computes in.
+PEAK_TFS = {"f64": 78.6, "f32": 157.3, "h": 2500.0}
+
+# Algorithmic (compulsory) bytes of the Wilson operator per fine site with N
+# right-hand sides per launch: the four links of a site (as 18 reals each) once
+# per launch, psi in and out once per rhs.  One rhs: 960 / 480 / 248 B.
+WILSON_LINK_BYTES = {"f64": 576, "f32": 288, "f16": 144, "bf16": 144}
+WILSON_SPINOR_BYTES = {"f64": 384, "f32": 192, "f16": 104, "bf16": 104}
+WILSON_FLOPS = 1368  # per fine site and rhs: 8 spin-projected hops and the mass term
 
 
-def dc_bytes(prec, nv):                            # per coarse site: 9 blocks + in + out
-    b = 16 if prec == "f64" else 8
-    n2 = 2 * nv
-    return 9 * n2 * n2 * b + 2 * n2 * b
+def wilson_bytes(prec, vol, launches, units):
+    """Algorithmic bytes of `launches` Wilson launches on `vol` sites that
+    processed `units` (site, rhs) pairs in total: 576/N + 384 B per site and rhs
+    in FP64 (288/N + 192 FP32, 144/N + 104 16-bit)."""
+    return launches * vol * WILSON_LINK_BYTES[prec] + units * WILSON_SPINOR_BYTES[prec]
 
 
-def coarse_gcr_bytes(nsite, n2, units):           # one coarsest GCR operator launch (FP64 D_c)
-    """D_c read once per launch (9 blocks per coarse site), r read, w_j and z_j written."""
-    return nsite * 9 * n2 * n2 * 16 + units * 3 * n2 * 16
+def coarse_bytes(store, n2, nsite, launches, units, vec_bytes):
+    """Coarse operator: the 9 (2Nv)^2 blocks of every coarse site once per
+    launch (`store` bytes per complex entry), the input and output vectors
+    (`vec_bytes` per complex entry) once per (site, rhs)."""
+    return launches * nsite * 9 * n2 * n2 * store + units * 2 * n2 * vec_bytes
 
 
-# Dense matrix-core peaks of MI355X (TFLOP/s) by the dtype the contraction runs in.
-MFMA_PEAK_TFS = {"f64": 78.6, "f32": 157.3, "h": 2500.0}
+def transfer_bytes(store, nv, vol, launches, units, fine_bytes, coarse_vec_bytes, n2):
+    """P^dagger or P at the fine level: the Nv columns of P (12 complex per
+    fine site each) once per launch, the fine vector once per (site, rhs) and
+    the coarse vector's share (2Nv entries per 256 fine sites)."""
+    return launches * vol * 12 * nv * store + units * (fine_bytes + n2 * coarse_vec_bytes / 256.0)
 
 
-def dc_mfma_util(kinfo, nrhs, n2_mid, n2_coarsest):
+def kernel_model(name, launches, units, w):
+    """(bytes, flops, dtype) of the profiled launches of one library kernel.
+    `w` describes the workload: fine volume, Nv and 2Nv per level, coarse sites."""
+    vol, nv, n2m, n2c = w["vol"], w["nv"], w["n2_mid"], w["n2_coarsest"]
+    if name.startswith("dslash_"):
+        p = name.split("_")[1]
+        return wilson_bytes(p, vol, launches, units), WILSON_FLOPS * units, "f32" if p != "f64" else "f64"
+    if name in ("restrict_f64", "prolong_f64"):
+        return transfer_bytes(16, nv, vol, launches, units, 192, 16, 2 * nv), 96 * nv * units, "f64"
+    if name in ("restrict_f32", "prolong_f32"):
+        return transfer_bytes(8, nv, vol, launches, units, 96, 8, 2 * nv), 96 * nv * units, "f32"
+    if name in ("restrict_h", "prolong_h"):
+        return transfer_bytes(4, nv, vol, launches, units, 52, 8, 2 * nv), 96 * nv * units, "f32"
+    fl_mid, fl_c = 72 * n2m * n2m * units, 72 * n2c * n2c * units
+    if name in ("dc_f64", "dc_mfma_f64"):
+        return coarse_bytes(16, n2m, w["nsite_mid"], launches, units, 16), fl_mid, "f64"
+    if name in ("dc_f32", "dc_mfma_f32"):
+        return coarse_bytes(8, n2m, w["nsite_mid"], launches, units, 8), fl_mid, "f32"
+    if name == "dc_h":
+        return coarse_bytes(4, n2m, w["nsite_mid"], launches, units, 8), fl_mid, "f32"
+    if name == "dc_mfma_h":
+        return coarse_bytes(4, n2m, w["nsite_mid"], launches, units, 8), fl_mid, "h"
+    if name == "coarse_gcr":
+        # the coarsest GCR's operator launch: FP64 D_c once, r read, w_j and z_j written
+        return (launches * w["nsite_coarsest"] * 9 * n2c * n2c * 16 + units * 3 * n2c * 16), fl_c, "f64"
+    return None
+
+
+def roofline_of(name, k, w):
+    """Roofline record of one profiled kernel: the bound follows from its
+    arithmetic intensity against the ridge of its dtype."""
+    m = kernel_model(name, k["launches"], k["units"], w)
+    if m is None:
+        return None
+    nbytes, flops, dt = m
+    sec = k["ms_total"] / 1e3
+    ridge = PEAK_TFS[dt] * 1e12 / (HBM_PEAK_GBS * 1e9)
+    per = k["launches"]
+    rec = {"kernel": name, "us_per_launch": sec / per * 1e6, "launches": per,
+           "bytes_per_launch": nbytes / per, "flops_per_launch": flops / per,
+           "arithmetic_intensity": flops / nbytes, "dtype": dt}
+    if flops / nbytes > ridge:
+        ach = flops / sec / 1e12
+        rec.update(bound="mfma", achieved=ach, peak=PEAK_TFS[dt], unit="TFLOP/s", frac=ach / PEAK_TFS[dt])
+    else:
+        ach = nbytes / sec / 1e9
+        rec.update(bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS)
+    return rec
+
+
+def dc_mfma_util(kinfo, w, nrhs):
     """Achieved FLOP/s of the coarse-operator launches that run on matrix cores,
-    against the dense peak of their dtype.  A unit is one (coarse site, rhs);
-    one unit costs 9 (2Nv)^2 complex multiply-adds = 72 (2Nv)^2 real flops.
-    The intermediate-level kernels use Nv of the first coarsening; the
-    coarsest GCR's operator launch (FP64 matrix cores once nrhs > 1) uses the
-    coarsest level's Nv."""
+    against the dense peak of their dtype (one (site, rhs) unit = 72 (2Nv)^2
+    real flops).  The coarsest GCR's operator runs on FP64 matrix cores once
+    nrhs > 1."""
     out = {}
-    for name, dt, n2 in (("dc_mfma_f64", "f64", n2_mid), ("dc_mfma_f32", "f32", n2_mid),
-                         ("dc_mfma_h", "h", n2_mid), ("coarse_gcr", "f64", n2_coarsest)):
+    for name in ("dc_mfma_f64", "dc_mfma_f32", "dc_mfma_h", "coarse_gcr"):
         k = kinfo.get(name)
         if k is None or (name == "coarse_gcr" and nrhs < 2):
             continue
-        flops = 72.0 * n2 * n2 * k["units"]
+        _, flops, dt = kernel_model(name, k["launches"], k["units"], w)
         tfs = flops / (k["ms_total"] / 1e3) / 1e12
-        out[name] = {"dtype": dt, "achieved_tflops": tfs, "peak_tflops": MFMA_PEAK_TFS[dt],
-                     "util": tfs / MFMA_PEAK_TFS[dt]}
+        out[name] = {"dtype": dt, "achieved_tflops": tfs, "peak_tflops": PEAK_TFS[dt], "util": tfs / PEAK_TFS[dt]}
     return out or None
 
 
-def counter_traffic(kernel, dims, bytes_per_launch, tuning=None):
-    """HBM bytes per launch from the committed PMC measurement of this kernel on
-    this lattice (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's reading), or
-    None when there is none, the kernel's sources changed since, or this run's
-    Wilson forms and rhs groups differ from the ones the counters were taken with."""
+def counter_traffic(kernel, workload, bytes_per_launch, tuning=None):
+    """HBM bytes per launch from the committed PMC measurement of this kernel in
+    this workload (FETCH_SIZE + WRITE_SIZE, scaled by what the same counters read
+    for a plain copy), or None when there is none, the kernel's sources changed
+    since, or this run's kernel forms differ from the ones the counters were
+    taken with."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         t = json.load(fh)
-    h = hashlib.sha256()
-    for f in t["source_files"]:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
-    if h.hexdigest()[:16] != t["source_hash"]:
-        return None
-    for e in t["entries"].get(kernel + "@" + "x".join(map(str, dims)), []):
-        if e.get("wilson_tuning") == tuning:
+    for e in t["entries"].get(kernel + "@" + workload, []):
+        h = hashlib.sha256()
+        for f in e["source_files"]:
+            with open(os.path.join(ROOT, f), "rb") as fh:
+                h.update(fh.read())
+        if h.hexdigest()[:16] != e["source_hash"]:
+            continue
+        if e.get("tuning") == tuning:
             return e["measured_over_algorithmic"] * bytes_per_launch
     return None
 
 
-def transfer_bytes(prec, nv):                      # per fine site: Nv columns (12 cplx) + fine + coarse share
-    b = 16 if prec == "f64" else 8
-    return 12 * nv * b + 12 * b
-
-
-def parse():
+def parse(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--L", type=int, default=16, help="lattice extent (L^4)")
-    ap.add_argument("--dims", type=int, nargs=4, default=None, metavar=("LX", "LY", "LZ", "LT"),
-                    help="lattice extents (overrides --L)")
-    ap.add_argument("--mcrit-dims", type=int, nargs=4, default=None, metavar=("LX", "LY", "LZ", "LT"),
-                    help="take m_crit from the oracle's value for this lattice at the same eps "
-                         "(for lattices too large for the host Arnoldi)")
-    ap.add_argument("--eps", type=float, default=0.3)
-    ap.add_argument("--delta", type=float, default=0.01, help="m - m_crit")
+    ap.add_argument("--dims", type=int, nargs=4, default=(24, 24, 24, 48), metavar=("LX", "LY", "LZ", "LT"))
+    ap.add_argument("--eps", type=float, default=0.45)
+    ap.add_argument("--delta", type=float, default=0.005, help="m - m_crit")
     ap.add_argument("--mass", type=float, default=None,
                     help="use this bare mass instead of m_crit + delta (no m_crit lookup)")
-    ap.add_argument("--nv", type=int, default=20)
+    ap.add_argument("--nv", type=int, default=24)
     ap.add_argument("--levels", type=int, default=2, choices=[2, 3],
                     help="3: a second coarsening with 2^4 aggregates (Sec. 5 three-level cycle)")
     ap.add_argument("--nv2", type=int, default=32, help="near-null vectors of the second coarsening")
@@ -126,26 +181,26 @@ def parse():
     ap.add_argument("--adapt-iters", type=int, default=0,
                     help="adaptive augmentation (Sec. 2): two-level iterations refining each candidate "
                          "after the first (0: relaxation only)")
-    ap.add_argument("--nrhs", type=int, default=1)
+    ap.add_argument("--nrhs", type=int, default=32)
     ap.add_argument("--nullvec-source", default="host", choices=["host", "device"],
-                    help="first-level null-vector starts: numpy on the host, kept on the device (default), or "
+                    help="first-level null-vector starts: numpy on the host, kept on the device, or "
                          "torch's seeded device generator inside each step, released after the setup (large lattices)")
-    ap.add_argument("--wilson-tuning", default=None, metavar="F1,FB,GB",
+    ap.add_argument("--tuning", default=None, metavar="F1,FB,GB",
                     help="force the Wilson form of one-rhs launches (F1), and the form (FB) and rhs group (GB) "
-                         "of the setup's batched launches, instead of the autotuner (one-rhs solves only)")
+                         "of batched launches, instead of the autotuner")
     ap.add_argument("--release-unused", action="store_true",
                     help="after each setup, free the FP64/FP32 copies of P and D_c that the 16-bit V-cycle "
                          "does not read (room for larger batches)")
     ap.add_argument("--coarse-apply", type=int, default=None, choices=[0, 1],
                     help="force a form of the batched coarsest-level operator (default: library choice)")
-    ap.add_argument("--setup-prec", default="f64", choices=["f64", "f32"],
+    ap.add_argument("--setup-prec", default="f32", choices=["f64", "f32"],
                     help="arithmetic of the setup relaxation (the block QR is FP64 either way)")
-    ap.add_argument("--mg-prec", default="f64", choices=["f64", "f32", "f16", "bf16"])
+    ap.add_argument("--mg-prec", default="bf16", choices=["f64", "f32", "f16", "bf16"])
     ap.add_argument("--coarse-tol", type=float, default=0.1)
     ap.add_argument("--alpha", action="store_true",
                     help="take the minimal-residual step size after prolongation (off: alpha = 1, "
                          "which converges in far fewer outer iterations on these fields)")
-    ap.add_argument("--restart", type=int, default=50, help="FGCR restart length (paper: 50)")
+    ap.add_argument("--restart", type=int, default=16, help="FGCR restart length (paper: 50)")
     ap.add_argument("--outer", default="fgcr", choices=["fgcr", "bicgstab"],
                     help="outer Krylov method: flexible GCR (Sec. 5) or BiCGStab with the V-cycle as right "
                          "preconditioner (Sec. 4)")
@@ -155,25 +210,41 @@ def parse():
                     help="capture the V-cycle in a HIP graph after its first application and replay it")
     ap.add_argument("--big-L", type=int, default=32, help="lattice for the out-of-cache Dslash figure (0: skip)")
     ap.add_argument("--no-bicgstab", action="store_true")
+    ap.add_argument("--bicgstab-budget", type=float, default=60.0,
+                    help="seconds the BiCGStab comparator may run; its iteration cap follows from the "
+                         "measured time per iteration, and a capped run is reported as a lower bound")
+    ap.add_argument("--no-fp64-mg", action="store_true", help="skip the FP64 single-rhs MG comparator")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="start with a plain 1 GiB device copy (the reference for hardware byte counters)")
     ap.add_argument("--only-dslash", type=int, default=0, metavar="L",
-                    help="only time Dslash (FP64, FP32) on L^4 plus a plain 1 GiB device copy "
-                         "(the reference for hardware byte counters), then exit")
-    a = ap.parse_args()
+                    help="only time Dslash on L^4 plus a plain 1 GiB device copy, then exit")
+    a = ap.parse_args(argv)
     if a.setup_iters is None:
         a.setup_iters = 50 if a.nrhs < 8 else 100
     return a
 
 
 def load_mcrit(dims, eps, seed):
-    path = os.path.join(ROOT, "tests", "golden", "mcrit.json")
+    """m_crit of a field: the oracle's Arnoldi (tests/golden/mcrit.json) where the
+    host could run it, else the GPU Krylov-Schur of tests/inputs/mcrit_gpu.json
+    (library FP64 D validated against the oracle on that field).  Returns
+    (m_crit, source)."""
     key = "x".join(str(d) for d in dims) + f"_eps{eps}_seed{seed}"
-    with open(path) as fh:
+    gold = os.path.join(ROOT, "tests", "golden", "mcrit.json")
+    with open(gold) as fh:
         data = json.load(fh)
-    if key not in data:
-        raise SystemExit(f"no oracle m_crit for {key} in {path}; run tests/golden/make_mcrit.py")
-    return float(data[key]["m_crit"])
+    if key in data:
+        return float(data[key]["m_crit"]), "oracle Arnoldi on this field"
+    gpu = os.path.join(ROOT, "tests", "inputs", "mcrit_gpu.json")
+    if os.path.exists(gpu):
+        with open(gpu) as fh:
+            data = json.load(fh)
+        e = data.get(key)
+        if e is not None and e.get("accepted"):
+            return float(e["m_crit"]), (f"Krylov-Schur on this field with the library's FP64 D "
+                                        f"(residual {e['leftmost_explicit_residual']:.1e})")
+    raise SystemExit(f"no m_crit for {key}: run tests/golden/make_mcrit.py or tests/inputs/make_mcrit_gpu.py")
 
 
 def workload_number(dims):
@@ -182,81 +253,68 @@ def workload_number(dims):
             (48, 48, 48, 96): 5}.get(tuple(dims), 9)
 
 
+def timed_apply(ctx, x, prec, key, reps, sync):
+    """(launches, units, ms) of `reps` library Wilson launches, HIP events."""
+    ctx.apply_D(x, prec=prec)
+    sync()
+    ctx.profile(True)
+    for _ in range(reps):
+        ctx.apply_D(x, prec=prec)
+    n, units, ms = ctx.profile_read()[key]
+    ctx.profile(False)
+    return n, units, ms
+
+
 def dslash_bandwidth(wdmg, synthetic, torch, dev, L, reps=20):
-    """Dslash kernel time on an L^4 lattice (links exp(i 0.45 H)), FP64 and FP32."""
+    """Wilson operator on an L^4 lattice (links exp(i 0.45 H)): one rhs in every
+    form and precision, and a batch of 8 rhs, by the N-rhs byte model."""
     dims = (L, L, L, L)
+    vol = L ** 4
     u = synthetic.gauge_field(dims, 0.45, synthetic.gauge_seed(3, 2))
     ctx = wdmg.Context(dims, dev)
     ctx.set_gauge(torch.from_numpy(u).to(dev), t_bc=-1)
     del u
     ctx.set_mass(-1.0)
     psi = torch.from_numpy(synthetic.gaussian_spinor(dims, 5)).to(dev)
-    out = {}
+    sync = torch.cuda.synchronize
+    out = {"lattice": f"{L}^4", "bytes_model": "576/N + 384 B per site and rhs (FP64), 288/N + 192 (FP32), "
+                                                "144/N + 104 (16-bit + scale)"}
     precs = (("f64", "dslash_f64"), ("f32", "dslash_f32"), ("f16", "dslash_f16"), ("bf16", "dslash_bf16"))
-    # both kernel forms forced, then the autotuner's pick
+
+    def rec(prec, n, units, ms, form, group=None):
+        sec = ms / 1e3
+        gbs = wilson_bytes(prec, vol, n, units) / sec / 1e9
+        r = {"us_per_launch": sec / n * 1e6, "GB_s": gbs, "frac_hbm_peak": gbs / HBM_PEAK_GBS, "form": form}
+        if group is not None:
+            r["rhs_group"] = group
+        return r
+
     forms = {}
     for form in (0, 1, 2):
         ctx.set_tuning("dslash", form)
         for prec, key in precs:
             x = psi if prec == "f64" else psi.to(torch.complex64)
-            ctx.apply_D(x, prec=prec)
-            torch.cuda.synchronize()
-            ctx.profile(True)
-            for _ in range(reps):
-                ctx.apply_D(x, prec=prec)
-            n, units, ms = ctx.profile_read()[key]
-            ctx.profile(False)
-            sec = ms / 1e3 / n
-            forms[f"{prec}_form{form}"] = {"us_per_launch": sec * 1e6,
-                                           "GB_s": DSLASH_BYTES[prec] * units / n / sec / 1e9}
+            forms[f"{prec}_form{form}"] = rec(prec, *timed_apply(ctx, x, prec, key, reps, sync), form)
     ctx.set_tuning("dslash", None)
-    out["forms"] = {"lattice": f"{L}^4", "form0": "one thread per site", "form1": "one wave per direction",
-                    "form2": "one wave per direction, registers capped for 4 waves per SIMD",
-                    **forms}
+    out["forms"] = {"form0": "one thread per site", "form1": "one wave per direction",
+                    "form2": "one wave per direction, registers capped for 4 waves per SIMD", **forms}
     for prec, key in precs:
         x = psi if prec == "f64" else psi.to(torch.complex64)
-        ctx.apply_D(x, prec=prec)
-        torch.cuda.synchronize()
-        ctx.profile(True)
-        for _ in range(reps):
-            ctx.apply_D(x, prec=prec)
-        n, units, ms = ctx.profile_read()[key]
-        ctx.profile(False)
-        sec = ms / 1e3 / n
-        out[prec] = {"lattice": f"{L}^4", "us_per_launch": sec * 1e6,
-                     "GB_s": DSLASH_BYTES[prec] * units / n / sec / 1e9,
-                     "frac_hbm_peak": DSLASH_BYTES[prec] * units / n / sec / 1e9 / HBM_PEAK_GBS,
-                     "form": ctx.get_tuning("dslash", prec, 1)}
-    # a batch of 8 right-hand sides (links read once per 2 (FP64) or 4 (FP32) rhs)
+        out[prec] = rec(prec, *timed_apply(ctx, x, prec, key, reps, sync), ctx.get_tuning("dslash", prec, 1))
     xb = psi.unsqueeze(0).repeat(8, 1, 1, 1, 1, 1, 1)
     for prec, key in (("f64", "dslash_f64"), ("f32", "dslash_f32"), ("bf16", "dslash_bf16")):
         x = xb if prec == "f64" else xb.to(torch.complex64)
-        ctx.apply_D(x, prec=prec)
-        torch.cuda.synchronize()
-        ctx.profile(True)
-        for _ in range(max(2, reps // 4)):
-            ctx.apply_D(x, prec=prec)
-        n, units, ms = ctx.profile_read()[key]
-        ctx.profile(False)
-        sec = ms / 1e3 / n
-        out[prec + "_8rhs"] = {"lattice": f"{L}^4 x 8 rhs", "us_per_launch": sec * 1e6,
-                               "ns_per_site_rhs": sec / units * n * 1e9,
-                               "GB_s_alg_single_rhs_bytes": DSLASH_BYTES[prec] * units / n / sec / 1e9,
-                               "form": ctx.get_tuning("dslash", prec, 8),
-                               "rhs_group": ctx.get_tuning("dslash_group", prec, 8)}
+        n, units, ms = timed_apply(ctx, x, prec, key, max(2, reps // 4), sync)
+        r = rec(prec, n, units, ms, ctx.get_tuning("dslash", prec, 8), ctx.get_tuning("dslash_group", prec, 8))
+        r["ns_per_site_rhs"] = ms / 1e3 / units * 1e9
+        out[prec + "_8rhs"] = r
     ctx.close()
     return out
 
 
-def only_dslash(L, reps=10):
-    """Dslash on L^4 and a plain device copy of known size (counter calibration)."""
-    import torch
-
-    import synthetic
-    from paper_0811_4331_amd import wdmg
-    dev = torch.device("cuda:0")
-    res = {"dslash": dslash_bandwidth(wdmg, synthetic, torch, dev, L, reps=reps)}
-    src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)  # 1 GiB
+def copy_calibration(torch, dev):
+    """A plain 1 GiB device copy: the reference for FETCH_SIZE / WRITE_SIZE."""
+    src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -264,12 +322,24 @@ def only_dslash(L, reps=10):
         dst.copy_(src)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / 3
-    res["copy_1GiB"] = {"bytes_read": src.numel() * 8, "bytes_written": dst.numel() * 8,
-                        "GB_s_read_plus_write": 2 * src.numel() * 8 / dt / 1e9}
+    res = {"bytes_read": src.numel() * 8, "bytes_written": dst.numel() * 8,
+           "GB_s_read_plus_write": 2 * src.numel() * 8 / dt / 1e9}
+    del src, dst
+    return res
+
+
+def only_dslash(L, reps=10):
+    import torch
+
+    import synthetic
+    from paper_0811_4331_amd import wdmg
+    dev = torch.device("cuda:0")
+    res = {"copy_1GiB": copy_calibration(torch, dev),
+           "dslash": dslash_bandwidth(wdmg, synthetic, torch, dev, L, reps=reps)}
     print(json.dumps(res), flush=True)
 
 
-def precision_report(ctx, torch, synthetic, dims, nv):
+def precision_report(ctx, torch, synthetic, dims):
     """||A_prec v - A_f64 v|| / ||A_f64 v|| for D (level 0), P^dagger, P and D_c
     (level 1) on Gaussian vectors, per reduced precision.  The FP64 forms are
     those the parity tests pin to the oracle."""
@@ -277,8 +347,7 @@ def precision_report(ctx, torch, synthetic, dims, nv):
         return float(torch.linalg.vector_norm(a.to(torch.complex128) - b) / torch.linalg.vector_norm(b))
     dev = ctx.device
     f = torch.from_numpy(synthetic.gaussian_spinor(dims, 777)).to(dev)
-    cshape = ctx.coarse_shape(1)
-    c = torch.from_numpy(synthetic.gaussian_vectors(cshape, 778)).to(dev)
+    c = torch.from_numpy(synthetic.gaussian_vectors(ctx.coarse_shape(1), 778)).to(dev)
     ref = {"D": ctx.apply_D(f), "P_dagger": ctx.restrict(0, f), "P": ctx.prolong(0, c), "D_c": ctx.apply_Dc(1, c)}
     out = {}
     for prec in ("f32", "f16", "bf16"):
@@ -290,33 +359,101 @@ def precision_report(ctx, torch, synthetic, dims, nv):
     return out
 
 
-def cpu_baseline(u, b, m, n_d_per_step, nrhs, seconds):
-    """The FP64 oracle's Wilson operator timed on the host (bounded sample)."""
-    from oracle import wilson
-    reps = 0
+def progress(msg):
+    """Progress of the long comparator runs (stderr; stdout carries the one JSON line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def bicgstab_comparator(ctx, b1, budget_s, torch):
+    """Plain FP64 BiCGStab on one rhs after a short warm-up (20 iterations); the
+    iteration cap is the time budget over the warm-up's time per iteration.  A
+    run stopped by the cap is a lower bound (converged false)."""
     t0 = time.perf_counter()
-    while True:
-        wilson.apply_D(u, b, m, -1.0)
-        reps += 1
-        el = time.perf_counter() - t0
-        if el > seconds or reps >= 200:
-            break
-    t_apply = el / reps
-    return {
-        "value": t_apply * n_d_per_step / nrhs, "unit": "s/RHS", "cores": 1, "kind": "oracle",
-        "sample": (f"{reps} oracle FP64 Wilson applications on the same lattice ({t_apply:.3f} s each, "
-                   f"numpy, one thread), scaled by the {n_d_per_step} fine-operator applications of one "
-                   "GPU step; a lower bound for the oracle's MG step (coarse, QR and vector work "
-                   "excluded)"),
-        "host_cpus": os.cpu_count(),
-    }
+    ctx.solve_bicgstab(b1, tol=1e-10, maxit=20)
+    torch.cuda.synchronize()
+    t_it = (time.perf_counter() - t0) / 20
+    maxit = max(50, int(budget_s / t_it))
+    progress(f"BiCGStab comparator: {t_it * 1e3:.2f} ms per iteration, at most {maxit} iterations")
+    t0 = time.perf_counter()
+    _, sb = ctx.solve_bicgstab(b1, tol=1e-10, maxit=maxit)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    conv = all(s["converged"] for s in sb)
+    return {"s_per_rhs": dt, "iters": [s["iters"] for s in sb], "n_D": [s["n_D"] for s in sb],
+            "converged": conv, "true_res": [s["true_res"] for s in sb], "maxit": maxit,
+            "lower_bound": not conv, "what": "unpreconditioned FP64 BiCGStab, one rhs, same field and mass"}
 
 
-def main():
-    a = parse()
+def fp64_mg_comparator(ctx, b1, a, v0, torch):
+    """FP64 single-rhs MG on the same field: FP64 setup (l = 50 MR steps, the
+    single-rhs default) and V-cycle, FGCR(50); one untimed run, then one timed."""
+    levels = [{"block": (4, 4, 4, 4), "nv": a.nv, "setup_iters": 50, "vectors": v0, "setup_prec": "f64"}]
+
+    def once():
+        t0 = time.perf_counter()
+        ctx.mg_setup(levels, coarse_tol=a.coarse_tol, use_alpha=a.alpha)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, st = ctx.solve(b1, tol=1e-10, restart=50, maxit=3000, mg_prec="f64")
+        torch.cuda.synchronize()
+        return t1 - t0, time.perf_counter() - t1, st
+    progress("FP64 single-rhs MG comparator")
+    once()
+    ts, tv, st = once()
+    return {"s_per_rhs": ts + tv, "setup_s": ts, "solve_s": tv, "iters": [s["iters"] for s in st],
+            "n_D": [s["n_D"] for s in st], "converged": all(s["converged"] for s in st),
+            "true_res": [s["true_res"] for s in st],
+            "what": f"FP64 setup (l = 50) and V-cycle, Nv = {a.nv}, FGCR(50), one rhs"}
+
+
+def cpu_baseline_oracle(torch, dev, wdmg, synthetic):
+    """The FP64 oracle's real MG-FGCR solve of the 8^4 workload (eps 0.3,
+    m = m_crit + 0.05, 4^4 aggregates, Nv = 12, 50 MR setup steps, FGCR(50) to
+    1e-10), setup + solve, timed on the host; the GPU's time for the same
+    problem and inputs is reported beside it."""
+    from oracle import mg, transfer
+    from threadpoolctl import threadpool_info
+    dims = (8, 8, 8, 8)
+    seed = synthetic.gauge_seed(1, 1)
+    m = load_mcrit(dims, 0.3, seed)[0] + 0.05
+    u = synthetic.gauge_field(dims, 0.3, seed)
+    bh = synthetic.gaussian_spinor(dims, synthetic.rhs_seed(1))
+    t0 = time.perf_counter()
+    h = mg.build_hierarchy(u, m, -1.0, [(4, 4, 4, 4)], [12], seeds=[synthetic.null_seed(1)], setup_iters=50,
+                           coarse_tol=0.1, use_alpha=False)
+    _, info = h.solve(transfer.as_chiral(bh), tol=1e-10, restart=50)
+    t_cpu = time.perf_counter() - t0
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    # the same problem on the GPU (warm-up, then timed)
+    ctx = wdmg.Context(dims, dev)
+    ctx.set_gauge(torch.from_numpy(u).to(dev), t_bc=-1)
+    ctx.set_mass(m)
+    v0 = torch.from_numpy(synthetic.gaussian_vectors((12,) + ctx.fine_shape(), synthetic.null_seed(1))).to(dev)
+    b = torch.from_numpy(bh).to(dev)
+    lv = [{"block": (4, 4, 4, 4), "nv": 12, "setup_iters": 50, "vectors": v0}]
+    for _ in range(2):
+        t0 = time.perf_counter()
+        ctx.mg_setup(lv, coarse_tol=0.1, use_alpha=False)
+        _, st = ctx.solve(b, tol=1e-10, restart=50, maxit=1000)
+        torch.cuda.synchronize()
+        t_gpu = time.perf_counter() - t0
+    ctx.close()
+    return {"value": t_cpu, "unit": "s/RHS", "cores": threads, "kind": "oracle",
+            "sample": ("the oracle's full MG solve (numpy FP64: 50-step relaxation of 12 null vectors, block QR, "
+                       "Galerkin stencil, FGCR(50) with V(2,2) cycles to true residual 1e-10) of the 8^4 "
+                       "workload, one rhs, timed once; element-wise numpy runs on one core, BLAS calls "
+                       f"on up to {threads} threads.  The headline lattice is beyond the oracle's reach "
+                       "(one numpy Wilson apply there takes seconds); its oracle time is not extrapolated."),
+            "oracle_iters": info["iters"], "oracle_true_res": info["true_res"],
+            "gpu_same_sample_s_per_rhs": t_gpu, "gpu_same_sample_iters": st[0]["iters"],
+            "host_cpus": os.cpu_count()}
+
+
+def main(argv=None):
+    a = parse(argv)
     if a.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1",
-                          "n_gpus": a.gpus}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only (every path here is single-GPU); "
+                                   "--gpus must be 1", "n_gpus": a.gpus}), flush=True)
         sys.exit(2)
     if a.only_dslash:
         only_dslash(a.only_dslash)
@@ -327,24 +464,22 @@ def main():
     from paper_0811_4331_amd import wdmg
 
     dev = torch.device("cuda:0")
-    L = a.L
-    dims = tuple(a.dims) if a.dims else (L, L, L, L)
+    calib = copy_calibration(torch, dev) if a.copy_calibration else None
+    dims = tuple(a.dims)
+    vol = int(np.prod(dims))
     i_eps = {0.2: 0, 0.3: 1, 0.45: 2}.get(a.eps, 9)
     cfg = workload_number(dims)
     gseed = synthetic.gauge_seed(cfg, i_eps)
-    mcrit_src = "oracle Arnoldi on this field"
     if a.mass is not None:
-        m = a.mass
+        m, mc, mcrit_src = a.mass, float("nan"), "bare mass given"
         a.delta = float("nan")
-    elif a.mcrit_dims:
-        md = tuple(a.mcrit_dims)
-        m = load_mcrit(md, a.eps, synthetic.gauge_seed(workload_number(md), i_eps)) + a.delta
-        mcrit_src = "oracle Arnoldi on the {} field of the same eps".format("x".join(map(str, md)))
     else:
-        m = load_mcrit(dims, a.eps, gseed) + a.delta
+        mc, mcrit_src = load_mcrit(dims, a.eps, gseed)
+        m = mc + a.delta
     u = synthetic.gauge_field(dims, a.eps, gseed)
     ctx = wdmg.Context(dims, dev)
     ctx.set_gauge(torch.from_numpy(u).to(dev), t_bc=-1)
+    del u
     ctx.set_mass(m)
     ctx.set_tuning("coarse_apply", a.coarse_apply)
     v0_shape = (a.nv,) + ctx.fine_shape()
@@ -359,24 +494,16 @@ def main():
         return torch.randn(v0_shape, dtype=torch.complex128, device=dev, generator=g)
     bh = np.stack([synthetic.gaussian_spinor(dims, synthetic.rhs_seed(cfg, j)) for j in range(a.nrhs)])
     b = torch.from_numpy(bh).to(dev)
+    del bh
     levels = [{"block": (4, 4, 4, 4), "nv": a.nv, "setup_iters": a.setup_iters, "adapt_iters": a.adapt_iters,
-               "vectors": v0,
-               "setup_prec": a.setup_prec}]
+               "vectors": v0, "setup_prec": a.setup_prec}]
     if a.levels == 3:
         cdims = tuple(d // 4 for d in dims)
         v1 = torch.from_numpy(synthetic.gaussian_vectors(
             (a.nv2, cdims[3], cdims[2], cdims[1], cdims[0], 2, a.nv), synthetic.null_seed(cfg) + 500)).to(dev)
         levels.append({"block": (2, 2, 2, 2), "nv": a.nv2, "setup_iters": a.setup_iters, "vectors": v1,
                        "setup_prec": a.setup_prec})
-
-    # the setup relaxes its vectors in batches of at most 64 that fit a 16 GiB work budget
-    setup_field = int(np.prod(dims)) * 12 * (16 if a.setup_prec == "f64" else 8)
-    setup_batch = max(1, min(a.nv, 64, (16 << 30) // (2 * setup_field)))
-    forced = None
-    if a.wilson_tuning:
-        if a.nrhs != 1:
-            raise SystemExit("--wilson-tuning is for one-rhs solves")
-        forced = [int(v) for v in a.wilson_tuning.split(",")]
+    forced = [int(v) for v in a.tuning.split(",")] if a.tuning else None
 
     def step():
         if forced:
@@ -393,17 +520,17 @@ def main():
             levels[0]["vectors"] = None  # the setup copied them; the solve gets the memory
         if a.release_unused:
             ctx.release_unused(a.mg_prec)
-        if forced:
+        if forced and a.nrhs == 1:
             ctx.set_tuning("dslash", forced[0])
             ctx.set_tuning("dslash_group", None)
-        x, st = ctx.solve(b, tol=1e-10, restart=a.restart, maxit=2000, mg_prec=a.mg_prec, graph=a.graph,
+        x, st = ctx.solve(b, tol=1e-10, restart=a.restart, maxit=3000, mg_prec=a.mg_prec, graph=a.graph,
                           outer=a.outer)
         torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        return x, st, t1 - t0, t2 - t1
+        return x, st, t1 - t0, time.perf_counter() - t1
 
-    for _ in range(a.warmup):
+    for i in range(a.warmup):
         step()
+        progress(f"warm-up step {i + 1}/{a.warmup} done")
     torch.cuda.synchronize()
     ctx.profile(True)
     t_start = time.perf_counter()
@@ -415,16 +542,16 @@ def main():
         stats.append(st)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
-    # Wilson forms and rhs groups this run used: one-rhs launches (form),
-    # the setup's batched launches (form, group)
-    if forced:
-        wilson_tuning = list(forced)
-    else:
-        one = "f64" if a.mg_prec == "f64" else "f32"
-        wilson_tuning = [ctx.get_tuning("dslash", one, 1), ctx.get_tuning("dslash", a.setup_prec, setup_batch),
-                         ctx.get_tuning("dslash_group", a.setup_prec, setup_batch)]
     prof = ctx.profile_read()
     ctx.profile(False)
+    progress(f"{a.steps} timed steps done in {elapsed:.1f} s")
+    one = "f64" if a.mg_prec == "f64" else "f32"
+    setup_batch = max(1, min(a.nv, 64, (16 << 30) // (2 * vol * 12 * (16 if a.setup_prec == "f64" else 8))))
+    vprec = a.mg_prec if a.mg_prec in ("f16", "bf16") else one
+    tuning = forced or [ctx.get_tuning("dslash", one, 1), ctx.get_tuning("dslash", a.setup_prec, setup_batch),
+                        ctx.get_tuning("dslash_group", a.setup_prec, setup_batch),
+                        ctx.get_tuning("dslash", vprec, a.nrhs), ctx.get_tuning("dslash_group", vprec, a.nrhs),
+                        ctx.get_tuning("coarse_apply", "f64", a.nrhs)]
     last = stats[-1]
     if not all(s["converged"] and s["true_res"] <= 1e-10 for st in stats for s in st):
         raise SystemExit(f"solve did not reach 1e-10: {last}")
@@ -436,46 +563,30 @@ def main():
         rr += float(torch.linalg.vector_norm(rj)) ** 2
         del rj
     true_res = rr ** 0.5 / float(torch.linalg.vector_norm(b))
+    del x
 
     ms_per_step = elapsed / a.steps * 1e3
     value = elapsed / a.steps / a.nrhs
-
-    # dominant kernel of the step and its roofline
-    kinfo = {}
-    for name, (n, units, ms) in prof.items():
-        if n == 0:
-            continue
-        kinfo[name] = {"launches": n, "ms_total": ms, "us_per_launch": ms / n * 1e3, "units": units}
-    dom = max(kinfo, key=lambda k: kinfo[k]["ms_total"])
-    n, units, ms = prof[dom]
-    per_launch_s = ms / 1e3 / n
-    if dom.startswith("dslash"):
-        bpl = DSLASH_BYTES[dom.split("_")[1]] * units / n
-    elif dom.startswith("dc_f"):
-        bpl = dc_bytes(dom[-3:], a.nv) * units / n
-    elif dom.startswith(("restrict", "prolong")):
-        bpl = transfer_bytes(dom[-3:], a.nv) * units / n
-    elif dom == "coarse_gcr":
-        vol = int(np.prod(dims))
-        csite, n2 = (vol // 256, 2 * a.nv) if a.levels == 2 else (vol // 4096, 2 * a.nv2)
-        bpl = coarse_gcr_bytes(csite, n2, units / n)
-    else:
-        bpl = None
+    n2_mid = 2 * a.nv
+    n2_c = 2 * a.nv2 if a.levels == 3 else 2 * a.nv
+    w = {"vol": vol, "nv": a.nv, "n2_mid": n2_mid, "n2_coarsest": n2_c, "nsite_mid": vol // 256,
+         "nsite_coarsest": vol // 256 if a.levels == 2 else vol // 4096}
+    kinfo = {name: {"launches": n, "ms_total": ms, "us_per_launch": ms / n * 1e3, "units": units}
+             for name, (n, units, ms) in prof.items() if n}
+    roofs = {k: roofline_of(k, kinfo[k], w) for k in kinfo}
+    roofs = {k: r for k, r in roofs.items() if r is not None}
+    step_ms = sum(k["ms_total"] for k in kinfo.values())
+    dom = max(roofs, key=lambda k: kinfo[k]["ms_total"]) if roofs else None
     roofline = None
-    if bpl is not None:
-        ach = bpl / per_launch_s / 1e9
-        traffic = counter_traffic(dom, dims, bpl, wilson_tuning)
-        roofline = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
-                    "bytes_per_launch": bpl, "us_per_launch": per_launch_s * 1e6}
-    dc_mfma = dc_mfma_util(kinfo, a.nrhs, 2 * a.nv, 2 * a.nv2 if a.levels == 3 else 2 * a.nv)
-    ds = prof["dslash_f64"]
-    dslash_step = None
-    if ds[0]:
-        sec = ds[2] / 1e3 / ds[0]
-        dslash_step = {"lattice": "x".join(map(str, dims)), "us_per_launch": sec * 1e6,
-                       "GB_s": DSLASH_BYTES["f64"] * ds[1] / ds[0] / sec / 1e9}
-
+    if dom is not None:
+        r = roofs[dom]
+        wl = "x".join(map(str, dims)) + f"_{a.nrhs}rhs_{a.mg_prec}"
+        traffic = counter_traffic(dom, wl, r["bytes_per_launch"], tuning)
+        roofline = {"kernel": dom, "bound": r["bound"], "achieved": r["achieved"], "peak": r["peak"],
+                    "unit": r["unit"], "frac": r["frac"], "traffic": traffic,
+                    "bytes_per_launch": r["bytes_per_launch"], "flops_per_launch": r["flops_per_launch"],
+                    "us_per_launch": r["us_per_launch"], "launches": r["launches"],
+                    "share_of_profiled_time": kinfo[dom]["ms_total"] / step_ms}
     result = {
         "metric": METRIC, "value": value, "unit": "s/RHS", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": ms_per_step, "higher_is_better": False, "scaling": "weak",
@@ -485,38 +596,47 @@ def main():
                                f"m = m_crit + {a.delta}, "
                                + (f"2-level MG 4^4 aggregates Nv={a.nv}, " if a.levels == 2 else
                                   f"3-level MG 4^4 then 2^4 aggregates Nv={a.nv} then {a.nv2}, ")
-                               + f"MR setup {a.setup_iters} iters, "
+                               + f"{a.setup_prec} MR setup {a.setup_iters} iters, {a.mg_prec} V-cycle, "
                                + (f"adaptive {a.adapt_iters} two-level iters per candidate, " if a.adapt_iters else "")
                                + (f"FGCR({a.restart})" if a.outer == "fgcr" else "MG-BiCGStab")
-                               + f" to 1e-10, {a.nrhs} Gaussian RHS",
-                   "lattice": list(dims), "eps": a.eps, "m": m, "m_crit": m - a.delta,
+                               + f" to 1e-10, {a.nrhs} Gaussian RHS solved together",
+                   "lattice": list(dims), "eps": a.eps, "m": m, "m_crit": mc,
                    "m_crit_source": mcrit_src, "levels": a.levels, "nv": a.nv,
                    "nv2": a.nv2 if a.levels == 3 else None,
                    "nrhs": a.nrhs, "mg_prec": a.mg_prec, "setup_prec": a.setup_prec, "coarse_tol": a.coarse_tol,
-                   "adapt_iters": a.adapt_iters, "outer": a.outer,
-                   "alpha_step": a.alpha, "graph": a.graph, "nullvec_source": a.nullvec_source,
-                   "release_unused": a.release_unused},
+                   "setup_iters": a.setup_iters, "adapt_iters": a.adapt_iters, "outer": a.outer,
+                   "restart": a.restart, "alpha_step": a.alpha, "graph": a.graph,
+                   "nullvec_source": a.nullvec_source, "release_unused": a.release_unused},
         "setup_s": float(np.median(setups)), "solve_s_per_rhs": float(np.median(solves)) / a.nrhs,
         "mg_iters": [s["iters"] for s in last], "mg_n_D": [s["n_D"] for s in last],
         "mg_n_Dc": [s["n_Dc"][1] for s in last], "true_res": true_res,
-        "roofline": roofline, "kernels": kinfo, "dslash_in_step": dslash_step, "dc_mfma": dc_mfma,
-        "wilson_tuning": wilson_tuning,
+        "roofline": roofline, "rooflines": roofs, "kernels": kinfo, "dc_mfma": dc_mfma_util(kinfo, w, a.nrhs),
+        "tuning": tuning,
     }
+    if calib is not None:
+        result["copy_calibration"] = calib
     if a.precision_report:
-        result["precision_error"] = precision_report(ctx, torch, synthetic, dims, a.nv)
+        result["precision_error"] = precision_report(ctx, torch, synthetic, dims)
+    comps = {}
+    if not a.no_fp64_mg:
+        v64 = v0 if v0 is not None else device_v0()
+        comps["fp64_single_rhs_mg"] = fp64_mg_comparator(ctx, b[0].contiguous(), a, v64, torch)
+        del v64
     if not a.no_bicgstab:
-        t0 = time.perf_counter()
-        xb, sb = ctx.solve_bicgstab(b, tol=1e-10, maxit=100000)
-        torch.cuda.synchronize()
-        tb = time.perf_counter() - t0
-        result["bicgstab"] = {"s_per_rhs": tb / a.nrhs, "iters": [s["iters"] for s in sb],
-                              "n_D": [s["n_D"] for s in sb], "converged": all(s["converged"] for s in sb)}
+        comps["bicgstab"] = bicgstab_comparator(ctx, b[0].contiguous(), a.bicgstab_budget, torch)
+    if comps:
+        for c in comps.values():
+            c["ratio_to_value"] = c["s_per_rhs"] / value
+        result["comparators"] = comps
+    ctx.close()
+    del ctx, b, v0
+    torch.cuda.empty_cache()
     if a.big_L:
+        progress(f"Wilson operator bandwidth on {a.big_L}^4")
         result["dslash_out_of_cache"] = dslash_bandwidth(wdmg, synthetic, torch, dev, a.big_L)
     if not a.no_cpu_baseline:
-        n_d = int(np.sum([s["n_D"] for s in last])) + a.nv * (a.setup_iters + 1)
-        result["cpu_baseline"] = cpu_baseline(u, bh[0], m, n_d, a.nrhs, a.cpu_seconds)
-    ctx.close()
+        progress("oracle MG solve of the 8^4 workload on the host")
+        result["cpu_baseline"] = cpu_baseline_oracle(torch, dev, wdmg, synthetic)
     print(json.dumps(result), flush=True)
 
 

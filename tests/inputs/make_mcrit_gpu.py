@@ -43,6 +43,24 @@ OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "mcrit_gpu.json")
 GOLDEN = os.path.join(ROOT, "tests", "golden", "mcrit.json")
 
 
+def basis_dots(Vj, w, chunk=1 << 20):
+    """``Vj^H w`` for a basis Vj [k, n] on the GPU.  A plain matrix-vector
+    product reduces each of the k long rows in one workgroup; splitting n into
+    chunks that form a batch spreads the reduction over the whole device."""
+    import torch
+    k, n = Vj.shape
+    nb = n // chunk
+    c = torch.zeros(k, dtype=Vj.dtype, device=Vj.device)
+    wc = w.conj().resolve_conj()
+    if nb:
+        a = Vj[:, : nb * chunk].view(k, nb, chunk).transpose(0, 1)  # [nb, k, chunk], no copy
+        x = wc[: nb * chunk].view(nb, chunk, 1)
+        c += torch.bmm(a, x).sum(dim=0).squeeze(-1)
+    if nb * chunk < n:
+        c += torch.mv(Vj[:, nb * chunk:], wc[nb * chunk:])
+    return c.conj().resolve_conj()
+
+
 def krylov_schur_leftmost(matvec, n, dev, m, p, nev, tol, max_cycles, seed, log, time_limit):
     """Leftmost eigenvalues of a linear map on C^n by Krylov-Schur.
 
@@ -72,8 +90,7 @@ def krylov_schur_leftmost(matvec, n, dev, m, p, nev, tol, max_cycles, seed, log,
             h = np.zeros(j + 1, dtype=np.complex128)
             before = float(torch.linalg.vector_norm(w))
             for _ in range(2):
-                # c = V[:j+1]^H w without conjugating the basis: conj(V conj(w))
-                c = torch.mv(V[: j + 1], w.conj().resolve_conj()).conj().resolve_conj()
+                c = basis_dots(V[: j + 1], w)
                 w -= (c.unsqueeze(0) @ V[: j + 1]).squeeze(0)
                 h += c.cpu().numpy()
                 beta = float(torch.linalg.vector_norm(w))

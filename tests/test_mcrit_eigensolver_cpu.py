@@ -38,3 +38,12 @@ def test_krylov_schur_finds_the_leftmost_eigenvalues_of_D0():
     v = (torch.from_numpy(np.ascontiguousarray(C[:, 0])).unsqueeze(0) @ V[: C.shape[0]]).squeeze(0)
     r = matvec(v) - complex(theta[0]) * v
     assert float(torch.linalg.vector_norm(r) / torch.linalg.vector_norm(v)) < 1e-9
+
+
+def test_chunked_basis_dots_equal_the_plain_product():
+    g = torch.Generator().manual_seed(4)
+    V = torch.randn(7, 1000, dtype=torch.complex128, generator=g)
+    w = torch.randn(1000, dtype=torch.complex128, generator=g)
+    for chunk in (64, 100, 1000, 4096):
+        c = mk.basis_dots(V, w, chunk=chunk)
+        assert float((c - V.conj() @ w).abs().max()) < 1e-12, chunk
