@@ -174,6 +174,21 @@ int wdmg_set_mass(wdmg_ctx* ctx, double m);
  * result in 16 bits as described for WDMG_F16 and compute in FP32). */
 int wdmg_apply_D(wdmg_ctx* ctx, void* out, const void* in, int nrhs, int prec);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * out = D in as wdmg_apply_D, with the internal-layout input and output
+ * fields in a 64 MiB device array that the library holds on every GPU it
+ * runs on until the process ends.  prec WDMG_F64 or WDMG_F32 only; at most
+ * 2 x 12 x padded sites x nrhs x (16 or 8) bytes <= 64 MiB (a 16^4 lattice
+ * takes 2 FP64 or 5 FP32 right-hand sides), else WDMG_ERR_ARG before
+ * anything is launched.  Makes no hipMalloc/hipFree or other allocating call:
+ * the Wilson form is the one the autotuner already chose for (prec, nrhs) on
+ * this context, else the default form, and the call is not timed by
+ * wdmg_profile.  All calls on one GPU share its array (which keeps the last
+ * call's contents; nothing in it needs to start at zero), so calls that
+ * overlap on one GPU, from any context or stream, race. */
+int wdmg_apply_D_noalloc(wdmg_ctx* ctx, void* out, const void* in, int nrhs, int prec);
+
 /* Storage conversion of fine fields (the layout and precision conversion in
  * front of every fine-level kernel): out = in after conversion into the
  * internal fine-field storage of precision prec and back.  Canonical layout;

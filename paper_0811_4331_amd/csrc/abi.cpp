@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -18,7 +19,29 @@ using namespace wdmg;
 
 struct wdmg_ctx : Ctx {};
 
+// ---------------------------------------------------------------------------
+// Scratch of wdmg_apply_D_noalloc: the internal-layout input and output fields
+// live in this file-scope device array instead of library allocations.  Its
+// device address is taken once per device in wdmg_create (with that device
+// current); host code uses only that address, never the array's name.
+static constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+static constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+static void* g_scratch[kMaxDevices] = {};
+static hipError_t g_scratch_rc[kMaxDevices] = {};
+static std::once_flag g_scratch_once[kMaxDevices];
+
 namespace {
+
+// Records the scratch address of the current device (once per device).
+void init_scratch(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return;
+  std::call_once(g_scratch_once[dev], [dev]() {
+    void* p = nullptr;
+    g_scratch_rc[dev] = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (g_scratch_rc[dev] == hipSuccess) g_scratch[dev] = p;
+  });
+}
 
 template <class F>
 int guarded(wdmg_ctx* c, F&& f) {
@@ -282,6 +305,11 @@ int wdmg_create(wdmg_ctx** out, const int dims[4], const wdmg_alloc* alloc, void
   for (int mu = 0; mu < 4; ++mu) B[mu] = dims[mu] % 4 == 0 ? 4 : (dims[mu] % 2 == 0 ? 2 : 1);
   c->g0 = make_geom(dims, B);
   c->stream = static_cast<hipStream_t>(hip_stream);
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return WDMG_ERR_HIP;
+  }
+  init_scratch(c->device);
   if (alloc) {
     c->alloc = *alloc;
     if (!alloc->alloc || !alloc->free) {
@@ -400,6 +428,48 @@ int wdmg_apply_D(wdmg_ctx* c, void* out, const void* in, int nrhs, int prec) {
       apply_D_half<f16_t>(*c, out, in, nrhs);
     else
       apply_D_half<bf16_t>(*c, out, in, nrhs);
+    return WDMG_OK;
+  });
+}
+
+int wdmg_apply_D_noalloc(wdmg_ctx* c, void* out, const void* in, int nrhs, int prec) {
+  return guarded(c, [&]() {
+    need_ptr(out, "out");
+    need_ptr(in, "in");
+    need_nrhs(nrhs);
+    need_prec(prec);
+    need_gauge(*c);
+    if (out == in) throw Error(WDMG_ERR_ARG, "out must differ from in");
+    if (prec != WDMG_F64 && prec != WDMG_F32)
+      throw Error(WDMG_ERR_ARG, "wdmg_apply_D_noalloc takes WDMG_F64 or WDMG_F32");
+    const int dev = c->device;
+    if (dev < 0 || dev >= kMaxDevices || !g_scratch[dev])
+      throw Error(WDMG_ERR_HIP, std::string("no scratch address on this device: hipGetSymbolAddress: ") +
+                                    (dev >= 0 && dev < kMaxDevices ? hipGetErrorString(g_scratch_rc[dev]) : "bad device"));
+    const size_t field = (size_t)c->g0.vpad * 12 * (prec == WDMG_F64 ? 16 : 8) * (size_t)nrhs;
+    if (2 * field > kNoAllocScratchBytes)
+      throw Error(WDMG_ERR_ARG, "wdmg_apply_D_noalloc: " + std::to_string(2 * field) +
+                                    " bytes of scratch needed, the maximum is 64 MiB");
+    // `field` is a multiple of 64 sites x 12 x 8 bytes, so b stays 256-byte aligned
+    unsigned char* base = static_cast<unsigned char*>(g_scratch[dev]);
+    c->no_alloc = true;
+    struct Restore {
+      Ctx& c;
+      ~Restore() { c.no_alloc = false; }
+    } restore{*c};
+    if (prec == WDMG_F64) {
+      cx<double>* a = reinterpret_cast<cx<double>*>(base);
+      cx<double>* b = reinterpret_cast<cx<double>*>(base + field);
+      fine_in<double>(*c, in, a, nrhs);
+      dslash<double>(*c, b, a, nrhs);
+      fine_out<double>(*c, b, out, nrhs);
+    } else {
+      cx<float>* a = reinterpret_cast<cx<float>*>(base);
+      cx<float>* b = reinterpret_cast<cx<float>*>(base + field);
+      fine_in<float>(*c, in, a, nrhs);
+      dslash<float>(*c, b, a, nrhs);
+      fine_out<float>(*c, b, out, nrhs);
+    }
     return WDMG_OK;
   });
 }

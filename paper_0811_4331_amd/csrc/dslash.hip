@@ -546,7 +546,7 @@ int launch_dslash(Ctx& c, const IO& io, int nrhs, int prof_id, int prec_index, d
   int v = c.tune_force[WDMG_TUNE_DSLASH] >= 0 ? c.tune_force[WDMG_TUNE_DSLASH] : fslot;
   if (v >= 0 && !form_fits(v, nrhs)) v = 1;  // a forced register-blocked form on a batch it does not divide
   int rg = c.tune_force[WDMG_TUNE_DSLASH_GROUP] >= 0 ? c.tune_force[WDMG_TUNE_DSLASH_GROUP] : gslot;
-  if ((v < 0 || rg < 0) && !c.capturing) {
+  if ((v < 0 || rg < 0) && !c.capturing && !c.no_alloc) {
     tune_dslash(c, io, nrhs, v, rg);
     if (c.tune_force[WDMG_TUNE_DSLASH] < 0) fslot = (signed char)v;
     if (c.tune_force[WDMG_TUNE_DSLASH_GROUP] < 0) gslot = (signed char)rg;

@@ -161,6 +161,10 @@ struct Ctx {
   // HIP-graph capture of a V-cycle: while capturing, the coarsest GCR runs
   // exactly coarse_fixed_iters iterations with no host interaction
   bool capturing = false;
+  // inside wdmg_apply_D_noalloc: no autotuning (its timing buffers) and no
+  // event records; kernels take already-tuned or default forms
+  bool no_alloc = false;
+  int device = 0;               // HIP device current at wdmg_create
   int coarse_fixed_iters = 0;
   int last_coarse_iters = 0;    // most iterations of one coarsest solve since reset
   hipStream_t cap_stream = nullptr;

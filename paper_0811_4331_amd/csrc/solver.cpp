@@ -67,7 +67,7 @@ void ensure_io(Ctx& c, size_t bytes) {
 }
 
 ProfScope::ProfScope(Ctx& ctx, int id, long long units) : c(ctx) {
-  if (!c.prof_on) return;
+  if (!c.prof_on || c.no_alloc) return;
   Ctx::ProfRec r{id, units, nullptr, nullptr};
   for (hipEvent_t* e : {&r.a, &r.b}) {
     if (!c.prof_pool.empty()) {

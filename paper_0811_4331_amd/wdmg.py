@@ -128,6 +128,7 @@ def load() -> ctypes.CDLL:
         "wdmg_set_gauge": (ip, [vp, vp, ip]),
         "wdmg_set_mass": (ip, [vp, dp]),
         "wdmg_apply_D": (ip, [vp, vp, vp, ip, ip]),
+        "wdmg_apply_D_noalloc": (ip, [vp, vp, vp, ip, ip]),
         "wdmg_roundtrip": (ip, [vp, vp, vp, ip, ip]),
         "wdmg_mg_setup": (ip, [vp, ctypes.POINTER(MgParams)]),
         "wdmg_get_prolongator": (ip, [vp, ip, vp]),
@@ -247,6 +248,17 @@ class Context:
         out = torch.empty_like(psi) if out is None else out
         self._check(self.lib.wdmg_apply_D(self.h, _ptr(out, _cdtype(prec), "out"),
                                           _ptr(psi, _cdtype(prec), "in"), nrhs, PREC[prec]))
+        return out
+
+    def apply_D_noalloc(self, psi: torch.Tensor, out: torch.Tensor, prec: str = "f64"):
+        """``out = D psi`` through the entry point that allocates nothing (its
+        work fields sit in the library's fixed 64 MiB device scratch); the
+        caller provides ``out``."""
+        nrhs = self._nrhs(psi, 6)
+        if tuple(psi.shape[-6:]) != self.fine_shape() or out.shape != psi.shape:
+            raise ValueError("fine field shape mismatch")
+        self._check(self.lib.wdmg_apply_D_noalloc(self.h, _ptr(out, _cdtype(prec), "out"),
+                                                  _ptr(psi, _cdtype(prec), "in"), nrhs, PREC[prec]))
         return out
 
     def roundtrip(self, psi: torch.Tensor, prec: str = "f32"):

@@ -1,0 +1,91 @@
+"""The entry point that allocates nothing, wdmg_apply_D_noalloc, against
+wdmg_apply_D (and the oracle): two calls in a row, the second with a smaller
+input, in FP64 and FP32; no device allocation reaches the library's allocator
+during those calls; sizes beyond its 64 MiB scratch are refused before any
+launch."""
+import numpy as np
+import pytest
+import torch
+
+import synthetic
+from oracle import wilson
+from paper_0811_4331_amd import wdmg
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def rel(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+@pytest.fixture
+def counting_allocator(monkeypatch):
+    """Counts the device allocations the library asks torch for."""
+    calls = {"n": 0}
+    real = torch.cuda.caching_allocator_alloc
+
+    def counted(size, device=None, stream=None):
+        calls["n"] += 1
+        return real(size, device, stream)
+    monkeypatch.setattr(torch.cuda, "caching_allocator_alloc", counted)
+    return calls
+
+
+@pytest.mark.parametrize("prec,tol,big", [("f64", 1e-13, 2), ("f32", 1e-6, 5)])
+def test_noalloc_apply_matches_apply_D(prec, tol, big, counting_allocator):
+    dims, m = (16, 16, 16, 16), -0.4
+    u = synthetic.gauge_field(dims, 0.3, seed=201)
+    ctx = wdmg.Context(dims, DEV)
+    ctx.set_gauge(torch.from_numpy(u).to(DEV), t_bc=-1)
+    ctx.set_mass(m)
+    cdt = np.complex128 if prec == "f64" else np.complex64
+    psi = synthetic.gaussian_spinor(dims, seed=202, nrhs=big).astype(cdt)
+    x = torch.from_numpy(psi).to(DEV)
+    out = torch.full_like(x, float("nan"))
+    torch.cuda.synchronize()
+    before = counting_allocator["n"]
+    # first call on a fresh context: no tuned form yet, the default one runs
+    ctx.apply_D_noalloc(x, out, prec=prec)
+    torch.cuda.synchronize()
+    assert counting_allocator["n"] == before
+    got = out.cpu().numpy()
+    ref = ctx.apply_D(x, prec=prec).cpu().numpy()
+    for j in range(big):
+        assert rel(got[j], ref[j]) < tol, j
+    assert rel(got[0].astype(np.complex128), wilson.apply_D(u, psi[0].astype(np.complex128), m, -1.0)) < tol
+    # second call in a row, smaller input (one rhs), after the autotuner ran
+    x1 = x[1:2].clone()
+    out1 = torch.full_like(x1, float("nan"))
+    torch.cuda.synchronize()
+    before = counting_allocator["n"]
+    ctx.apply_D_noalloc(x1, out1, prec=prec)
+    torch.cuda.synchronize()
+    assert counting_allocator["n"] == before
+    assert rel(out1.cpu().numpy()[0], ref[1]) < tol
+    # beyond the scratch: refused on the host
+    xb = torch.zeros((big + 1,) + x.shape[1:], dtype=x.dtype, device=DEV)
+    with pytest.raises(wdmg.WdmgError) as e:
+        ctx.apply_D_noalloc(xb, torch.empty_like(xb), prec=prec)
+    assert e.value.code == -1 and "64 MiB" in str(e.value)
+    ctx.close()
+
+
+def test_noalloc_apply_across_contexts_and_precisions():
+    """The array is shared by every context on the GPU: a smaller lattice after
+    a larger one, then the 16-bit kinds refused."""
+    for dims, seed in (((8, 8, 8, 12), 211), ((4, 6, 2, 8), 212)):
+        u = synthetic.gauge_field(dims, 0.4, seed=seed)
+        ctx = wdmg.Context(dims, DEV)
+        ctx.set_gauge(torch.from_numpy(u).to(DEV), t_bc=-1)
+        ctx.set_mass(-0.3)
+        psi = synthetic.gaussian_spinor(dims, seed=seed + 1, nrhs=3)
+        x = torch.from_numpy(psi).to(DEV)
+        out = torch.empty_like(x)
+        ctx.apply_D_noalloc(x, out)
+        got = out.cpu().numpy()
+        for j in range(3):
+            assert rel(got[j], wilson.apply_D(u, psi[j], -0.3, -1.0)) < 1e-13
+        with pytest.raises(wdmg.WdmgError):
+            ctx.apply_D_noalloc(x.to(torch.complex64), out.to(torch.complex64), prec="bf16")
+        ctx.close()
