@@ -18,7 +18,10 @@ DEV = torch.device("cuda:0")
 
 
 def rel(a, b):
-    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+    """Error of a against b element by element: the largest |a_i - b_i| over the
+    largest |b_i| (or the ratio of 2-norms, if that is larger)."""
+    d, r = (a - b).ravel(), b.ravel()
+    return float(max(np.abs(d).max() / np.abs(r).max(), np.linalg.norm(d) / np.linalg.norm(r)))
 
 
 def gpu(x):
