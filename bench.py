@@ -11,9 +11,9 @@ right-hand side, inputs resident in HBM before the timed region.
 Default workload: the 24^3 x 48 lattice with links exp(i 0.45 H),
 antiperiodic time, m = m_crit + 0.005 with m_crit of this very field,
 32 Gaussian right-hand sides solved together: batched FP32 setup (Nv = 24,
-100 MR steps, 4^4 aggregates), V-cycle in BF16 storage with FP32
+250 MR steps, 4^4 aggregates), V-cycle in BF16 storage with FP32
 arithmetic (coarse operator and P^dagger on matrix cores), FP64 coarsest
-GCR and FP64 outer flexible GCR(16) with an FP32 basis.
+GCR and FP64 outer flexible GCR(12) with an FP32 basis.
 
 Beside the K timed steps, on the same GPU and field, the line carries the
 two comparators of the target: FP64 single-rhs MG (FP64 setup and V-cycle,
@@ -177,7 +177,7 @@ def parse(argv=None):
     ap.add_argument("--nv2", type=int, default=32, help="near-null vectors of the second coarsening")
     ap.add_argument("--setup-iters", type=int, default=None,
                     help="MR relaxation steps per near-null vector (default 50 for fewer than 8 rhs, "
-                         "100 for larger batches, whose setup cost is shared)")
+                         "100 for 8 to 15 and 250 for 16 or more, whose setup cost is shared)")
     ap.add_argument("--adapt-iters", type=int, default=0,
                     help="adaptive augmentation (Sec. 2): two-level iterations refining each candidate "
                          "after the first (0: relaxation only)")
@@ -200,7 +200,9 @@ def parse(argv=None):
     ap.add_argument("--alpha", action="store_true",
                     help="take the minimal-residual step size after prolongation (off: alpha = 1, "
                          "which converges in far fewer outer iterations on these fields)")
-    ap.add_argument("--restart", type=int, default=16, help="FGCR restart length (paper: 50)")
+    ap.add_argument("--restart", type=int, default=None,
+                    help="FGCR restart length (paper: 50; default 50 for fewer than 8 rhs, 12 for batches, "
+                         "whose outer basis is large)")
     ap.add_argument("--outer", default="fgcr", choices=["fgcr", "bicgstab"],
                     help="outer Krylov method: flexible GCR (Sec. 5) or BiCGStab with the V-cycle as right "
                          "preconditioner (Sec. 4)")
@@ -221,7 +223,9 @@ def parse(argv=None):
                     help="only time Dslash on L^4 plus a plain 1 GiB device copy, then exit")
     a = ap.parse_args(argv)
     if a.setup_iters is None:
-        a.setup_iters = 50 if a.nrhs < 8 else 100
+        a.setup_iters = 50 if a.nrhs < 8 else (100 if a.nrhs < 16 else 250)
+    if a.restart is None:
+        a.restart = 50 if a.nrhs < 8 else 12
     return a
 
 

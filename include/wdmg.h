@@ -271,7 +271,15 @@ int wdmg_solve_bicgstab(wdmg_ctx* ctx, void* x, const void* b, int nrhs, double 
  *                     thread (each link loaded once for them, the
  *                     direction sums meeting in LDS one rhs at a time);
  *                     forms 3 and 4 apply to batches they divide (a forced
- *                     value runs form 1 on other batch sizes).
+ *                     value runs form 1 on other batch sizes); 5 one wave per
+ *                     4x4x4 tile column walking a chunk of time layers, each
+ *                     spinor loaded once per chunk, the x, y, z hops exchanged
+ *                     between lanes (lattices cut into 4^4 tiles only, else
+ *                     form 1; the rhs-group value 4, 8 or 16 sets the chunk);
+ *                     6, 7, 8 forms 1, 2, 3 with the workgroups of each XCD
+ *                     walking a box of tile columns layer by layer (4^4
+ *                     tiles and tile columns that split into 8 boxes only,
+ *                     else form 1).
  *   WDMG_TUNE_DSLASH_GROUP: right-hand sides per group (1..64) in the
  *                     workgroup order of a batched Wilson launch: each XCD
  *                     sweeps its lattice region once per group, with the

@@ -379,7 +379,9 @@ __global__ void k_add(cx<R>* __restrict__ y, const cx<R>* __restrict__ x, size_t
     y[i] = y[i] + x[i];
 }
 
-template <typename R>
+// MODE 0: x += s u ; r -= s v.  MODE 1 (first MR step from x = 0 with
+// residual u): x = s u ; r = u - s v.  MODE 2 (last MR step): x += s u only.
+template <typename R, int MODE>
 __global__ void k_update2_batch(cx<R>* x, const cx<R>* u, cx<R>* r, const cx<R>* v, size_t n, size_t stride,
                                 const double* s) {
   const int y = blockIdx.y;
@@ -389,9 +391,14 @@ __global__ void k_update2_batch(cx<R>* x, const cx<R>* u, cx<R>* r, const cx<R>*
   r += y * stride;
   v += y * stride;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-    const cx<R> ui = u[i], vi = v[i];
-    x[i] = x[i] + a * ui;
-    r[i] = r[i] - a * vi;
+    const cx<R> ui = u[i];
+    if constexpr (MODE == 1) {
+      x[i] = a * ui;
+      r[i] = ui - a * v[i];
+    } else {
+      x[i] = x[i] + a * ui;
+      if constexpr (MODE == 0) r[i] = r[i] - a * v[i];
+    }
   }
 }
 
@@ -407,7 +414,10 @@ __global__ void k_update2(cx<R>* x, const cx<R>* u, cx<R>* r, const cx<R>* v, si
 
 // x += s u ; r -= s v on 16-bit fields (one thread per site and rhs); u may
 // be the same field as r, so nothing here is declared non-aliasing.
-template <typename H>
+// MODE 0: as written.  MODE 1 (first MR step of a cycle from x = 0 with
+// residual u): x = s u and r = u - s v, x not read.  MODE 2 (last MR step,
+// whose residual nobody reads): x += s u only.
+template <typename H, int MODE>
 __global__ void k_update2_half(Geom g, cxh<H>* xv, float* xs, const cxh<H>* uv, const float* us, cxh<H>* rv,
                                float* rs, const cxh<H>* vv, const float* vs, const double* sc) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -415,18 +425,30 @@ __global__ void k_update2_half(Geom g, cxh<H>* xv, float* xs, const cxh<H>* uv, 
   if (s >= g.vpad) return;
   const size_t vo = (size_t)y * 12 * g.vpad, so = (size_t)y * g.vpad;
   const cx<float> a = mk((float)sc[2 * y], (float)sc[2 * y + 1]);
-  cx<float> x[12], u[12], r[12], v[12];
-  load_site_h(xv + vo, xs + so, s, x);
+  cx<float> x[12], u[12];
   load_site_h(uv + vo, us + so, s, u);
-  load_site_h(rv + vo, rs + so, s, r);
-  load_site_h(vv + vo, vs + so, s, v);
+  if constexpr (MODE == 1) {
 #pragma unroll
-  for (int k = 0; k < 12; ++k) {
-    x[k] = x[k] + a * u[k];
-    r[k] = r[k] - a * v[k];
+    for (int k = 0; k < 12; ++k) x[k] = a * u[k];
+  } else {
+    load_site_h(xv + vo, xs + so, s, x);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) x[k] = x[k] + a * u[k];
   }
   store_site_h(xv + vo, xs + so, s, x);
-  store_site_h(rv + vo, rs + so, s, r);
+  if constexpr (MODE != 2) {
+    cx<float> r[12], v[12];
+    if constexpr (MODE == 1) {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) r[k] = u[k];
+    } else {
+      load_site_h(rv + vo, rs + so, s, r);
+    }
+    load_site_h(vv + vo, vs + so, s, v);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) r[k] = r[k] - a * v[k];
+    store_site_h(rv + vo, rs + so, s, r);
+  }
 }
 
 __global__ void k_bicg_p(cx<double>* p, const cx<double>* r, const cx<double>* v, size_t n, const double* dsc,
@@ -770,11 +792,18 @@ void step_alpha_batch(Ctx& c, const cx<R>* a, const cx<R>* b, size_t n, size_t s
 }
 template <typename R>
 void update2_batch(Ctx& c, cx<R>* x, const cx<R>* u, cx<R>* r, const cx<R>* v, size_t n, size_t stride, int nb,
-                   int slot) {
+                   int slot, int mode) {
   unsigned gx = ew_blocks(n);
   if (gx * nb > 8192) gx = (8192 + nb - 1) / nb;
-  hipLaunchKernelGGL((k_update2_batch<R>), dim3(gx, nb), dim3(256), 0, c.stream, x, u, r, v, n, stride,
-                     c.dsc + slot);
+  if (mode == 1)
+    hipLaunchKernelGGL((k_update2_batch<R, 1>), dim3(gx, nb), dim3(256), 0, c.stream, x, u, r, v, n, stride,
+                       c.dsc + slot);
+  else if (mode == 2)
+    hipLaunchKernelGGL((k_update2_batch<R, 2>), dim3(gx, nb), dim3(256), 0, c.stream, x, u, r, v, n, stride,
+                       c.dsc + slot);
+  else
+    hipLaunchKernelGGL((k_update2_batch<R, 0>), dim3(gx, nb), dim3(256), 0, c.stream, x, u, r, v, n, stride,
+                       c.dsc + slot);
   WDMG_HIP(hipGetLastError());
 }
 
@@ -802,17 +831,28 @@ void step_alpha_half(Ctx& c, HF a, HF b, int nrhs, double scale, int slot) {
 }
 
 template <typename H>
-void update2_half(Ctx& c, HF x, HF u, HF r, HF v, int nrhs, int slot) {
-  hipLaunchKernelGGL((k_update2_half<H>), dim3((c.g0.vpad + 255) / 256, nrhs), dim3(256), 0, c.stream, c.g0,
-                     static_cast<cxh<H>*>(x.v), x.s, static_cast<const cxh<H>*>(u.v), u.s,
-                     static_cast<cxh<H>*>(r.v), r.s, static_cast<const cxh<H>*>(v.v), v.s, c.dsc + slot);
+void update2_half(Ctx& c, HF x, HF u, HF r, HF v, int nrhs, int slot, int mode) {
+  const dim3 grid((c.g0.vpad + 255) / 256, nrhs);
+  auto* xv = static_cast<cxh<H>*>(x.v);
+  auto* uv = static_cast<const cxh<H>*>(u.v);
+  auto* rv = static_cast<cxh<H>*>(r.v);
+  auto* vv = static_cast<const cxh<H>*>(v.v);
+  if (mode == 1)
+    hipLaunchKernelGGL((k_update2_half<H, 1>), grid, dim3(256), 0, c.stream, c.g0, xv, x.s, uv, u.s, rv, r.s, vv, v.s,
+                       c.dsc + slot);
+  else if (mode == 2)
+    hipLaunchKernelGGL((k_update2_half<H, 2>), grid, dim3(256), 0, c.stream, c.g0, xv, x.s, uv, u.s, rv, r.s, vv, v.s,
+                       c.dsc + slot);
+  else
+    hipLaunchKernelGGL((k_update2_half<H, 0>), grid, dim3(256), 0, c.stream, c.g0, xv, x.s, uv, u.s, rv, r.s, vv, v.s,
+                       c.dsc + slot);
   WDMG_HIP(hipGetLastError());
 }
 
 template void step_alpha_half<f16_t>(Ctx&, HF, HF, int, double, int);
 template void step_alpha_half<bf16_t>(Ctx&, HF, HF, int, double, int);
-template void update2_half<f16_t>(Ctx&, HF, HF, HF, HF, int, int);
-template void update2_half<bf16_t>(Ctx&, HF, HF, HF, HF, int, int);
+template void update2_half<f16_t>(Ctx&, HF, HF, HF, HF, int, int, int);
+template void update2_half<bf16_t>(Ctx&, HF, HF, HF, HF, int, int, int);
 
 template <typename B>
 void gcr_orth_b(Ctx& c, const cx<B>* W, cx<B>* w, const cx<double>* r, size_t n, int nb, int j, int gl) {
@@ -924,7 +964,7 @@ void set_scalar(Ctx& c, int slot, double re, double im) {
   template void norm2<R>(Ctx&, const cx<R>*, size_t, int);                                 \
   template void dot<R>(Ctx&, const cx<R>*, const cx<R>*, size_t, int);                      \
   template void step_alpha_batch<R>(Ctx&, const cx<R>*, const cx<R>*, size_t, size_t, int, double, int); \
-  template void update2_batch<R>(Ctx&, cx<R>*, const cx<R>*, cx<R>*, const cx<R>*, size_t, size_t, int, int);
+  template void update2_batch<R>(Ctx&, cx<R>*, const cx<R>*, cx<R>*, const cx<R>*, size_t, size_t, int, int, int);
 INST(double)
 INST(float)
 #undef INST

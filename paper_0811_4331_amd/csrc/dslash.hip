@@ -139,6 +139,39 @@ __device__ __forceinline__ void batch_block(int nsb, int nrhs, int rg, int& sb, 
   rhs = g * rg + off % size;
 }
 
+// Tile-column box order (forms 6-8) for lattices cut into 4^4 tiles: XCD k
+// takes box k of the xyz tile columns (the boxes of the t-marching form) and
+// walks it layer by layer, t outermost within an rhs group: the blocks of
+// one time layer of the box, then of the next, so the time neighbours of a
+// layer are the blocks its XCD handled just before and just after.  `n`
+// counts rhs (or rhs chunks of the register-blocked form) and rg the group.
+struct BoxOrder {
+  int on;
+  int ncol, nT0, nT1, Lt;
+  int box[3], nbox[3];
+};
+
+__device__ __forceinline__ void box_block(const BoxOrder& o, int n, int rg, int& sb, int& rhs) {
+  const int b = blockIdx.x;
+  const int xcd = b & 7, local = b >> 3;
+  const int bs = o.box[0] * o.box[1] * o.box[2];
+  if (rg < 1 || rg > n) rg = n;
+  const int per = o.Lt * bs;  // blocks of one rhs in the box
+  const int g = local / (per * rg);
+  const int size = min(rg, n - g * rg);
+  const int off = local - g * per * rg;
+  const int t = off / (bs * size);
+  const int rem = off % (bs * size);
+  const int in = rem / size;
+  rhs = g * rg + rem % size;
+  const int bx = xcd % o.nbox[0], by = (xcd / o.nbox[0]) % o.nbox[1], bz = xcd / (o.nbox[0] * o.nbox[1]);
+  const int tx = bx * o.box[0] + in % o.box[0];
+  const int ty = by * o.box[1] + (in / o.box[0]) % o.box[1];
+  const int tz = bz * o.box[2] + in / (o.box[0] * o.box[1]);
+  const int col = tx + o.nT0 * (ty + o.nT1 * tz);
+  sb = ((col + o.ncol * (t >> 2)) << 2) + (t & 3);
+}
+
 // MR step-size partial sums of one wave (Sec. 3 smoother): Re and Im of
 // <out, in> and |out|^2 over the wave's sites, where `in` is the operator's
 // input at the site itself (already loaded for the mass term).  Lanes of
@@ -239,10 +272,14 @@ template <class IO, bool DOTS, int MINW, typename R = typename IO::T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MINW))) void k_dslash4(Geom g, IO io, R diag,
                                                                                             int tneg, int nsb,
                                                                                             int nrhs, int rg,
-                                                                                            double* dots) {
+                                                                                            double* dots,
+                                                                                            BoxOrder bo) {
   __shared__ cx<R> part[3][12][kDs4Sites];
   int sb, rhs;
-  batch_block(nsb, nrhs, rg, sb, rhs);
+  if (bo.on)
+    box_block(bo, nrhs, rg, sb, rhs);
+  else
+    batch_block(nsb, nrhs, rg, sb, rhs);
   const int lane = threadIdx.x & 63, mu = threadIdx.x >> 6;
   const int s = sb * kDs4Sites + lane;
   io.select_rhs(rhs, g.vpad);
@@ -332,10 +369,13 @@ __device__ __forceinline__ void hops_mu_rb(const IO& io, const Geom& g, int s, c
 
 template <class IO, bool DOTS, int RB, typename R = typename IO::T>
 __global__ __launch_bounds__(256) void k_dslash4_rb(Geom g, IO io, R diag, int tneg, int nsb, int nchunk, int rg,
-                                                    double* dots) {
+                                                    double* dots, BoxOrder bo) {
   __shared__ cx<R> part[2][3][12][kDs4Sites];
   int sb, ch;
-  batch_block(nsb, nchunk, rg, sb, ch);
+  if (bo.on)
+    box_block(bo, nchunk, rg, sb, ch);
+  else
+    batch_block(nsb, nchunk, rg, sb, ch);
   const int lane = threadIdx.x & 63, mu = threadIdx.x >> 6;
   const int s = sb * kDs4Sites + lane;
   io.select_rhs(ch * RB, g.vpad);
@@ -382,63 +422,298 @@ __global__ __launch_bounds__(256) void k_dslash4_rb(Geom g, IO io, R diag, int t
   }
 }
 
+// t-marching form for lattices cut into 4^4 tiles: one wave per (xyz tile
+// column, chunk of T time layers, rhs); lane = x + 4y + 16z of the 4x4x4 block
+// of one layer (the field layout's 64-site block).  The wave walks its chunk
+// layer by layer, so every spinor of the column is loaded once: psi(t+1) is
+// loaded as the forward time neighbour and becomes the centre of the next
+// step, and the backward time hop U_t(x-t)^+ (1+gamma_t) psi(x-t) is formed
+// one step earlier from the centre and its own link.  Inside the block the
+// x, y, z hops exchange half spinors between lanes (each lane sends
+// (1-gamma_mu) psi to x-mu and U_mu^+ (1+gamma_mu) psi to x+mu, both from its
+// own spinor and link); lanes on a tile face load the neighbouring tile's
+// spinor (and link) instead.  Work items are grouped per XCD in boxes of
+// adjacent tile columns, so neighbouring columns share an L2 while they walk
+// the same layers.
+struct TmMap {
+  int ncol;           // xyz tile columns
+  int nch, T;         // chunks of T layers per column
+  int nrhs;
+  int box[3];         // tile columns per XCD box (0: no XCD boxes)
+  int nbox[3];        // boxes per direction (product 8)
+};
+
+template <int SIGN, typename R>
+__device__ __forceinline__ void link_mul(const cx<R> (&u)[9], const cx<R> (&h)[6], cx<R> (&uh)[6]) {
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      cx<R> t = mk<R>(0, 0);
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        if (SIGN > 0)
+          cmadd(t, u[i * 3 + b], h[a * 3 + b]);   // U h
+        else
+          cmaddc(t, u[b * 3 + i], h[a * 3 + b]);  // U^+ h
+      }
+      uh[a * 3 + i] = t;
+    }
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void shfl6(const cx<R> (&in)[6], cx<R> (&out)[6], int src) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) out[k] = mk<R>(__shfl(in[k].re, src, 64), __shfl(in[k].im, src, 64));
+}
+
+// The x, y or z hops of one site with lane-exchanged half spinors.
+template <int MU, class IO, typename R = typename IO::T>
+__device__ __forceinline__ void tm_space_hops(const IO& io, const Geom& g, int s, const int (&c)[4], int lane,
+                                              const cx<R> (&psi)[12], cx<R> (&acc)[12]) {
+  constexpr int SL = MU == 0 ? 1 : (MU == 1 ? 4 : 16);
+  const int lc = (lane / SL) & 3;
+  cx<R> u[9];
+  io.link(MU, s, false, u);
+  // messages of this lane: (1-gamma) psi for x-mu, U^+ (1+gamma) psi for x+mu
+  cx<R> mf[6], mb[6], t6[6];
+  project<MU, +1>(psi, mf);
+  project<MU, -1>(psi, t6);
+  link_mul<-1>(u, t6, mb);
+  // forward hop: (1-gamma) psi(x+mu) from lane + SL, or from the next tile
+  cx<R> h[6];
+  shfl6(mf, h, lane + SL);
+  if (lc == 3) {
+    cx<R> p[12];
+    io.spinor(nbr_fwd(g, s, c, MU), p);
+    project<MU, +1>(p, h);
+  }
+  cx<R> uh[6];
+  link_mul<+1>(u, h, uh);
+  expand_add<MU, +1>(uh, acc);
+  // backward hop: U^+(x-mu) (1+gamma) psi(x-mu) from lane - SL, or computed
+  // here from the previous tile's spinor and link
+  shfl6(mb, uh, lane - SL);
+  if (lc == 0) {
+    const int b = nbr_bwd(g, s, c, MU);
+    cx<R> p[12], ub[9];
+    io.spinor(b, p);
+    io.link(MU, b, false, ub);
+    project<MU, -1>(p, t6);
+    link_mul<-1>(ub, t6, uh);
+  }
+  expand_add<MU, -1>(uh, acc);
+}
+
+__device__ __forceinline__ void tm_work(const TmMap& m, int w, int& col, int& ch, int& rhs, const Geom& g) {
+  int tx, ty, tz, local;
+  if (m.box[0]) {
+    const int xcd = w & 7;
+    local = w >> 3;
+    const int bs = m.box[0] * m.box[1] * m.box[2];
+    const int in = local % bs;
+    const int rest = local / bs;
+    rhs = rest % m.nrhs;
+    ch = rest / m.nrhs;
+    const int bx = xcd % m.nbox[0], by = (xcd / m.nbox[0]) % m.nbox[1], bz = xcd / (m.nbox[0] * m.nbox[1]);
+    tx = bx * m.box[0] + in % m.box[0];
+    ty = by * m.box[1] + (in / m.box[0]) % m.box[1];
+    tz = bz * m.box[2] + in / (m.box[0] * m.box[1]);
+    col = tx + g.nT[0] * (ty + g.nT[1] * tz);
+  } else {
+    col = w % m.ncol;
+    const int rest = w / m.ncol;
+    rhs = rest % m.nrhs;
+    ch = rest / m.nrhs;
+  }
+}
+
+template <class IO, bool DOTS, typename R = typename IO::T>
+__global__ __launch_bounds__(64) void k_dslash_tm(Geom g, IO io, R diag, int tneg, TmMap m, double* dots) {
+  int col, ch, rhs;
+  tm_work(m, blockIdx.x, col, ch, rhs, g);
+  io.select_rhs(rhs, g.vpad);
+  const int lane = threadIdx.x;
+  const int ncol = m.ncol, Lt = g.L[3];
+  auto site_at = [&](int t) { return ((col + ncol * (t >> 2)) << 8) + ((t & 3) << 6) + lane; };
+  const int t0 = ch * m.T;
+  int c[4];
+  coords_of(g, site_at(t0), c);
+  // backward time hop of the first layer, from layer t0 - 1
+  cx<R> bt[6];
+  {
+    const int tp = t0 == 0 ? Lt - 1 : t0 - 1;
+    const int sp = site_at(tp);
+    cx<R> p[12], u[9], h[6];
+    io.spinor(sp, p);
+    io.link(3, sp, tneg && tp == Lt - 1, u);
+    project<3, -1>(p, h);
+    link_mul<-1>(u, h, bt);
+  }
+  cx<R> psi[12];
+  io.spinor(site_at(t0), psi);
+  const R half = (R)0.5;
+  for (int t = t0; t < t0 + m.T; ++t) {
+    const int s = site_at(t);
+    c[3] = t;
+    const int tn = t == Lt - 1 ? 0 : t + 1;
+    cx<R> nxt[12];
+    io.spinor(site_at(tn), nxt);
+    cx<R> acc[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = mk<R>(0, 0);
+    tm_space_hops<0>(io, g, s, c, lane, psi, acc);
+    tm_space_hops<1>(io, g, s, c, lane, psi, acc);
+    tm_space_hops<2>(io, g, s, c, lane, psi, acc);
+    {
+      cx<R> u[9], h[6], uh[6];
+      const bool neg = tneg && t == Lt - 1;
+      io.link(3, s, neg, u);
+      project<3, +1>(nxt, h);  // forward time hop
+      link_mul<+1>(u, h, uh);
+      expand_add<3, +1>(uh, acc);
+      expand_add<3, -1>(bt, acc);  // backward time hop
+      project<3, -1>(psi, h);      // the next layer's backward hop
+      link_mul<-1>(u, h, bt);
+    }
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = mk<R>(diag * psi[k].re - half * acc[k].re, diag * psi[k].im - half * acc[k].im);
+    io.store(s, acc);
+    if constexpr (DOTS) wave_dots(true, acc, psi, dots, (size_t)rhs * (g.vpad / 64) + (s >> 6));
+#pragma unroll
+    for (int k = 0; k < 12; ++k) psi[k] = nxt[k];
+  }
+}
+
+// Work map of the t-marching form: tile columns split into 8 boxes when the
+// tile counts allow (one box per XCD), chunks of T layers.
+inline TmMap tm_map(const Geom& g, int nrhs, int T) {
+  TmMap m{};
+  m.ncol = g.nT[0] * g.nT[1] * g.nT[2];
+  m.T = T;
+  m.nch = g.L[3] / T;
+  m.nrhs = nrhs;
+  const int nb[3][3] = {{2, 2, 2}, {1, 2, 4}, {1, 1, 8}};
+  for (auto& split : nb) {
+    // try the split and its permutations along x, y, z
+    const int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    for (auto& pm : perm) {
+      bool ok = true;
+      for (int d = 0; d < 3; ++d) ok = ok && g.nT[d] % split[pm[d]] == 0;
+      if (!ok) continue;
+      for (int d = 0; d < 3; ++d) {
+        m.nbox[d] = split[pm[d]];
+        m.box[d] = g.nT[d] / split[pm[d]];
+      }
+      return m;
+    }
+  }
+  return m;
+}
+
+// Layers per chunk of the t-marching form: the rhs-group tuning value when it
+// is 4, 8 or 16 and divides Lt, else 8 (or 4).
+inline int tm_chunk(const Geom& g, int rg) {
+  for (int T : {rg, 8, 4})
+    if ((T == 4 || T == 8 || T == 16) && g.L[3] % T == 0) return T;
+  return 4;
+}
+
 // Slots of MR partial sums per right-hand side written by a fused launch.
 int dslash_parts(const Geom& g, int variant) {
-  if (variant != 0) return g.vpad / kDs4Sites;
+  if (variant != 0) return g.vpad / kDs4Sites;  // forms 1-5: one slot per 64-site block
   return (g.vpad / kDslashThreads + (g.vpad % kDslashThreads != 0)) * (kDslashThreads / 64);
 }
 
 // Right-hand sides per thread of a form (forms 3 and 4 are register-blocked).
-constexpr int rb_of(int variant) { return variant == 3 ? 2 : (variant == 4 ? 4 : 1); }
+constexpr int rb_of(int variant) { return (variant == 3 || variant == 8) ? 2 : (variant == 4 ? 4 : 1); }
+
+inline BoxOrder box_order(const Geom& g) {
+  const TmMap m = tm_map(g, 1, 4);
+  BoxOrder o{};
+  o.on = m.box[0] != 0;
+  o.ncol = m.ncol;
+  o.nT0 = g.nT[0];
+  o.nT1 = g.nT[1];
+  o.Lt = g.L[3];
+  for (int d = 0; d < 3; ++d) {
+    o.box[d] = m.box[d];
+    o.nbox[d] = m.nbox[d];
+  }
+  return o;
+}
+
+// Forms 3, 4 and 8 need a batch they divide; forms 5-8 need 4^4 tiles, and
+// 6-8 tile columns that split into one box per XCD.
+inline bool form_fits(const Geom& g, int v, int nrhs) {
+  const bool tiles = g.B[0] == 4 && g.B[1] == 4 && g.B[2] == 4 && g.B[3] == 4;
+  if (v >= 5 && !tiles) return false;
+  if (v >= 6 && !box_order(g).on) return false;
+  return nrhs % rb_of(v) == 0;
+}
 
 template <class IO>
 void run_dslash(Ctx& c, const IO& io, int nrhs, int variant, int rg, double* dots = nullptr) {
   const Geom& g = c.g0;
   const int tneg = c.t_bc < 0 ? 1 : 0;
   using R = typename IO::T;
-  if (variant == 1 || variant == 2) {
+  const R diag = (R)(4.0 + c.mass);
+  BoxOrder bo{};
+  if (variant >= 6) bo = box_order(g);  // forms 6-8: forms 1, 2, 3 in tile-column box order
+  const int base = variant == 6 ? 1 : (variant == 7 ? 2 : (variant == 8 ? 3 : variant));
+  if (base == 1 || base == 2) {
     const unsigned gx = g.vpad / kDs4Sites;
     const dim3 grid(gx * nrhs), block(256);
-    const R diag = (R)(4.0 + c.mass);
-    if (variant == 1) {
+    if (base == 1) {
       if (dots)
-        hipLaunchKernelGGL((k_dslash4<IO, true, 1>), grid, block, 0, c.stream, g, io, diag, tneg, (int)gx, nrhs, rg, dots);
+        hipLaunchKernelGGL((k_dslash4<IO, true, 1>), grid, block, 0, c.stream, g, io, diag, tneg, (int)gx, nrhs, rg,
+                           dots, bo);
       else
-        hipLaunchKernelGGL((k_dslash4<IO, false, 1>), grid, block, 0, c.stream, g, io, diag, tneg, (int)gx, nrhs, rg, dots);
+        hipLaunchKernelGGL((k_dslash4<IO, false, 1>), grid, block, 0, c.stream, g, io, diag, tneg, (int)gx, nrhs, rg,
+                           dots, bo);
     } else {
       if (dots)
-        hipLaunchKernelGGL((k_dslash4<IO, true, 4>), grid, block, 0, c.stream, g, io, diag, tneg, (int)gx, nrhs, rg, dots);
+        hipLaunchKernelGGL((k_dslash4<IO, true, 4>), grid, block, 0, c.stream, g, io, diag, tneg, (int)gx, nrhs, rg,
+                           dots, bo);
       else
-        hipLaunchKernelGGL((k_dslash4<IO, false, 4>), grid, block, 0, c.stream, g, io, diag, tneg, (int)gx, nrhs, rg, dots);
+        hipLaunchKernelGGL((k_dslash4<IO, false, 4>), grid, block, 0, c.stream, g, io, diag, tneg, (int)gx, nrhs, rg,
+                           dots, bo);
     }
-  } else if (variant == 3 || variant == 4) {
+  } else if (base == 5) {
+    const TmMap m = tm_map(g, nrhs, tm_chunk(g, rg));
+    const dim3 grid((unsigned)(m.ncol * m.nch * nrhs));
+    if (dots)
+      hipLaunchKernelGGL((k_dslash_tm<IO, true>), grid, dim3(64), 0, c.stream, g, io, diag, tneg, m, dots);
+    else
+      hipLaunchKernelGGL((k_dslash_tm<IO, false>), grid, dim3(64), 0, c.stream, g, io, diag, tneg, m, dots);
+  } else if (base == 3 || base == 4) {
     const unsigned gx = g.vpad / kDs4Sites;
-    const R diag = (R)(4.0 + c.mass);
-    if (variant == 3) {
+    if (base == 3) {
       const int nch = nrhs / 2, rgc = rg >= 2 ? rg / 2 : 1;
       if (dots)
         hipLaunchKernelGGL((k_dslash4_rb<IO, true, 2>), dim3(gx * nch), dim3(256), 0, c.stream, g, io, diag, tneg,
-                           (int)gx, nch, rgc, dots);
+                           (int)gx, nch, rgc, dots, bo);
       else
         hipLaunchKernelGGL((k_dslash4_rb<IO, false, 2>), dim3(gx * nch), dim3(256), 0, c.stream, g, io, diag, tneg,
-                           (int)gx, nch, rgc, dots);
+                           (int)gx, nch, rgc, dots, bo);
     } else {
       const int nch = nrhs / 4, rgc = rg >= 4 ? rg / 4 : 1;
       if (dots)
         hipLaunchKernelGGL((k_dslash4_rb<IO, true, 4>), dim3(gx * nch), dim3(256), 0, c.stream, g, io, diag, tneg,
-                           (int)gx, nch, rgc, dots);
+                           (int)gx, nch, rgc, dots, bo);
       else
         hipLaunchKernelGGL((k_dslash4_rb<IO, false, 4>), dim3(gx * nch), dim3(256), 0, c.stream, g, io, diag, tneg,
-                           (int)gx, nch, rgc, dots);
+                           (int)gx, nch, rgc, dots, bo);
     }
   } else {
     const unsigned gx = g.vpad / kDslashThreads + (g.vpad % kDslashThreads != 0);
     if (dots)
-      hipLaunchKernelGGL((k_dslash<IO, true>), dim3(gx * nrhs), dim3(kDslashThreads), 0, c.stream, g, io,
-                         (R)(4.0 + c.mass), tneg, (int)gx, nrhs, rg, dots);
+      hipLaunchKernelGGL((k_dslash<IO, true>), dim3(gx * nrhs), dim3(kDslashThreads), 0, c.stream, g, io, diag, tneg,
+                         (int)gx, nrhs, rg, dots);
     else
-      hipLaunchKernelGGL((k_dslash<IO, false>), dim3(gx * nrhs), dim3(kDslashThreads), 0, c.stream, g, io,
-                         (R)(4.0 + c.mass), tneg, (int)gx, nrhs, rg, dots);
+      hipLaunchKernelGGL((k_dslash<IO, false>), dim3(gx * nrhs), dim3(kDslashThreads), 0, c.stream, g, io, diag, tneg,
+                         (int)gx, nrhs, rg, dots);
   }
   WDMG_HIP(hipGetLastError());
 }
@@ -448,9 +723,7 @@ void run_dslash(Ctx& c, const IO& io, int nrhs, int variant, int rg, double* dot
 // writing `out` -- and returns the fastest (form 1 on ties).  The
 // register-blocked forms 3 and 4 take part when the batch is a multiple of
 // their 2 or 4 rhs per thread.
-constexpr int kDslashForms = 5;
-
-inline bool form_fits(int v, int nrhs) { return nrhs % rb_of(v) == 0; }
+constexpr int kDslashForms = 9;
 
 template <class IO>
 float time_dslash(Ctx& c, const IO& io, int nrhs, int v, int rg, hipEvent_t (&ev)[2], int reps = 3) {
@@ -493,7 +766,7 @@ void tune_dslash(Ctx& c, const IO& io, int nrhs, int& form, int& rg) {
   if (form < 0) {
     const int g = rg < 0 ? nrhs : rg;
     float ms[kDslashForms];
-    for (int v = 0; v < kDslashForms; ++v) ms[v] = form_fits(v, nrhs) ? time_dslash(c, io, nrhs, v, g, ev) : 1e30f;
+    for (int v = 0; v < kDslashForms; ++v) ms[v] = form_fits(c.g0, v, nrhs) ? time_dslash(c, io, nrhs, v, g, ev) : 1e30f;
     float est = ms[0];
     for (int v = 1; v < kDslashForms; ++v) est = ms[v] < est ? ms[v] : est;
     tw = tune_window(est);
@@ -501,7 +774,7 @@ void tune_dslash(Ctx& c, const IO& io, int nrhs, int& form, int& rg) {
       for (int v = 0; v < kDslashForms; ++v) ms[v] = 1e30f;
       for (int r = 0; r < tw.rounds; ++r)
         for (int v = 0; v < kDslashForms; ++v) {
-          if (!form_fits(v, nrhs)) continue;
+          if (!form_fits(c.g0, v, nrhs)) continue;
           const float t = time_dslash(c, io, nrhs, v, g, ev, tw.reps);
           if (t < ms[v]) ms[v] = t;
         }
@@ -544,7 +817,7 @@ int launch_dslash(Ctx& c, const IO& io, int nrhs, int prof_id, int prec_index, d
   signed char& fslot = c.tune_dslash[prec_index][key];
   signed char& gslot = c.tune_group[prec_index][key];
   int v = c.tune_force[WDMG_TUNE_DSLASH] >= 0 ? c.tune_force[WDMG_TUNE_DSLASH] : fslot;
-  if (v >= 0 && !form_fits(v, nrhs)) v = 1;  // a forced register-blocked form on a batch it does not divide
+  if (v >= 0 && !form_fits(c.g0, v, nrhs)) v = 1;  // a forced register-blocked form on a batch it does not divide
   int rg = c.tune_force[WDMG_TUNE_DSLASH_GROUP] >= 0 ? c.tune_force[WDMG_TUNE_DSLASH_GROUP] : gslot;
   if ((v < 0 || rg < 0) && !c.capturing && !c.no_alloc) {
     tune_dslash(c, io, nrhs, v, rg);

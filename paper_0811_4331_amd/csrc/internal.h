@@ -288,7 +288,9 @@ void half_to_canon(Ctx& c, HF in, cx<float>* canon, int nrhs);
 template <typename H>
 void step_alpha_half(Ctx& c, HF a, HF b, int nrhs, double scale, int slot);
 template <typename H>
-void update2_half(Ctx& c, HF x, HF u, HF r, HF v, int nrhs, int slot);
+// x += s u ; r -= s v (mode 0); x = s u ; r = u - s v (mode 1, x not read);
+// x += s u only (mode 2)
+void update2_half(Ctx& c, HF x, HF u, HF r, HF v, int nrhs, int slot, int mode = 0);
 
 // Wilson operator (dslash.hip): out = diag * in - 1/2 sum_mu hops.
 template <typename R>
@@ -327,7 +329,7 @@ void step_alpha_batch(Ctx& c, const cx<R>* a, const cx<R>* b, size_t n, size_t s
                       int slot);
 template <typename R>
 void update2_batch(Ctx& c, cx<R>* x, const cx<R>* u, cx<R>* r, const cx<R>* v, size_t n, size_t stride, int nb,
-                   int slot);
+                   int slot, int mode = 0);
 // Batched GCR over nb right-hand sides.  Fields of one rhs are n long and
 // consecutive (batch stride n); basis vector i of all rhs is W + i*nb*n.
 // State in the block gcr_base(g): h, nrm, a, rnorm^2, active (see ScalarSlot).

@@ -250,17 +250,22 @@ void ensure_mg_work(Ctx& c, int nrhs, int prec, int first) {
 // ---------------------------------------------------------------------------
 // MR smoother (Sec. 3): p = A r; alpha = omega <p,r>/<p,p>; x += alpha r;
 // r -= alpha p, with one step size per right-hand side.
+// With b0, the steps start from x = 0 and residual b0 (the first step reads
+// b0 and writes x and r); with last_x_only the last step updates x alone.
 template <typename R>
-void mr(Ctx& c, int l, cx<R>* x, cx<R>* r, cx<R>* p, int nrhs, int iters, double omega) {
+void mr(Ctx& c, int l, cx<R>* x, cx<R>* r, cx<R>* p, int nrhs, int iters, double omega, const cx<R>* b0,
+        bool last_x_only) {
   const size_t n = c.lev[l].n;
   for (int it = 0; it < iters; ++it) {
+    const bool first = it == 0 && b0;
+    const cx<R>* in = first ? b0 : r;
     if (l == 0) {
-      dslash_mr<R>(c, p, r, nrhs, omega, S_BATCH);
+      dslash_mr<R>(c, p, in, nrhs, omega, S_BATCH);
     } else {
-      apply_op<R>(c, l, p, r, nrhs);
-      step_alpha_batch<R>(c, p, r, n, n, nrhs, omega, S_BATCH);
+      apply_op<R>(c, l, p, in, nrhs);
+      step_alpha_batch<R>(c, p, in, n, n, nrhs, omega, S_BATCH);
     }
-    update2_batch<R>(c, x, r, r, p, n, n, nrhs, S_BATCH);
+    update2_batch<R>(c, x, in, r, p, n, n, nrhs, S_BATCH, first ? 1 : (last_x_only && it == iters - 1 ? 2 : 0));
   }
 }
 
@@ -325,17 +330,20 @@ void vcycle(Ctx& c, int l, cx<R>* x, const cx<R>* b, int nrhs) {
   cx<R>* p = work<R>(L, 2);
   cx<R>* y = work<R>(L, 3);
   cx<R>* dy = work<R>(L, 4);
-  zero<R>(c, x, n * nrhs);
-  copy<R>(c, res, b, n * nrhs);
-  mr<R>(c, l, x, res, p, nrhs, c.mg.nu_pre, c.mg.omega);
+  if (c.mg.nu_pre > 0) {
+    mr<R>(c, l, x, res, p, nrhs, c.mg.nu_pre, c.mg.omega, b, false);
+  } else {
+    zero<R>(c, x, n * nrhs);
+    copy<R>(c, res, b, n * nrhs);
+  }
   coarse_correction<R>(c, l, res, y, nrhs);
   apply_op<R>(c, l, dy, y, nrhs);
   if (c.mg.use_alpha)
     step_alpha_batch<R>(c, dy, res, n, n, nrhs, 1.0, S_BATCH);  // Sec. 3 step-size equation
   else
     fill_pairs(c, S_BATCH, nrhs, 1.0, 0.0);
-  update2_batch<R>(c, x, y, res, dy, n, n, nrhs, S_BATCH);
-  mr<R>(c, l, x, res, p, nrhs, c.mg.nu_post, c.mg.omega);
+  update2_batch<R>(c, x, y, res, dy, n, n, nrhs, S_BATCH, c.mg.nu_post > 0 ? 0 : 2);
+  mr<R>(c, l, x, res, p, nrhs, c.mg.nu_post, c.mg.omega, nullptr, true);
 }
 
 #define INST(R)                                                                \
@@ -343,7 +351,7 @@ void vcycle(Ctx& c, int l, cx<R>* x, const cx<R>* b, int nrhs) {
   template void apply_op<R>(Ctx&, int, cx<R>*, const cx<R>*, int);            \
   template void restrict_to<R>(Ctx&, int, const cx<R>*, cx<R>*, int);         \
   template void prolong_from<R>(Ctx&, int, const cx<R>*, cx<R>*, int);        \
-  template void mr<R>(Ctx&, int, cx<R>*, cx<R>*, cx<R>*, int, int, double);   \
+  template void mr<R>(Ctx&, int, cx<R>*, cx<R>*, cx<R>*, int, int, double, const cx<R>*, bool); \
   template void ensure_work<R>(Ctx&, int, int);
 INST(double)
 INST(float)
@@ -364,11 +372,17 @@ void ensure_work_h(Ctx& c, int nrhs) {
   L.caph = nrhs;
 }
 
+// With b0, the steps start from x = 0 and residual *b0 (the first step reads
+// b0 and writes x and r, no copy or zero fill); with last_x_only the last
+// step updates x alone (a V-cycle does not read the residual after its
+// post-smoothing).
 template <typename H>
-void mr_h(Ctx& c, HF x, HF r, HF p, int nrhs, int iters, double omega) {
+void mr_h(Ctx& c, HF x, HF r, HF p, int nrhs, int iters, double omega, const HF* b0, bool last_x_only) {
   for (int it = 0; it < iters; ++it) {
-    dslash_h_mr<H>(c, p, r, nrhs, omega, S_BATCH);
-    update2_half<H>(c, x, r, r, p, nrhs, S_BATCH);
+    const bool first = it == 0 && b0;
+    dslash_h_mr<H>(c, p, first ? *b0 : r, nrhs, omega, S_BATCH);
+    const int mode = first ? 1 : (last_x_only && it == iters - 1 ? 2 : 0);
+    update2_half<H>(c, x, first ? *b0 : r, r, p, nrhs, S_BATCH, mode);
   }
 }
 
@@ -378,9 +392,12 @@ void vcycle_h(Ctx& c, HF x, HF b, int nrhs) {
   Level& C = c.lev[1];
   const void* V = v16(c, L, half_kind<H>());
   HF res = L.wh[0], p = L.wh[1], y = L.wh[2], dy = L.wh[3];
-  hf_zero<H>(c, x, nrhs);
-  hf_copy(c, res, b, nrhs);
-  mr_h<H>(c, x, res, p, nrhs, c.mg.nu_pre, c.mg.omega);
+  if (c.mg.nu_pre > 0) {
+    mr_h<H>(c, x, res, p, nrhs, c.mg.nu_pre, c.mg.omega, &b, false);
+  } else {
+    hf_zero<H>(c, x, nrhs);
+    hf_copy(c, res, b, nrhs);
+  }
   cx<float>* rc = C.w32[5];
   cx<float>* ec = C.w32[6];
   restrict0_h<H>(c, L, V, res, rc, nrhs);
@@ -391,12 +408,12 @@ void vcycle_h(Ctx& c, HF x, HF b, int nrhs) {
     step_alpha_half<H>(c, dy, res, nrhs, 1.0, S_BATCH);  // Sec. 3 step-size equation
   else
     fill_pairs(c, S_BATCH, nrhs, 1.0, 0.0);
-  update2_half<H>(c, x, y, res, dy, nrhs, S_BATCH);
-  mr_h<H>(c, x, res, p, nrhs, c.mg.nu_post, c.mg.omega);
+  update2_half<H>(c, x, y, res, dy, nrhs, S_BATCH, c.mg.nu_post > 0 ? 0 : 2);
+  mr_h<H>(c, x, res, p, nrhs, c.mg.nu_post, c.mg.omega, nullptr, true);
 }
 
-template void mr_h<f16_t>(Ctx&, HF, HF, HF, int, int, double);
-template void mr_h<bf16_t>(Ctx&, HF, HF, HF, int, int, double);
+template void mr_h<f16_t>(Ctx&, HF, HF, HF, int, int, double, const HF*, bool);
+template void mr_h<bf16_t>(Ctx&, HF, HF, HF, int, int, double, const HF*, bool);
 template void vcycle_h<f16_t>(Ctx&, HF, HF, int);
 template void vcycle_h<bf16_t>(Ctx&, HF, HF, int);
 

@@ -15,14 +15,16 @@ void restrict_to(Ctx& c, int l, const cx<R>* fine, cx<R>* crs, int nrhs);
 template <typename R>
 void prolong_from(Ctx& c, int l, const cx<R>* crs, cx<R>* fine, int nrhs);
 template <typename R>
-void mr(Ctx& c, int l, cx<R>* x, cx<R>* r, cx<R>* p, int nrhs, int iters, double omega);
+void mr(Ctx& c, int l, cx<R>* x, cx<R>* r, cx<R>* p, int nrhs, int iters, double omega, const cx<R>* b0 = nullptr,
+        bool last_x_only = false);
 template <typename R>
 void vcycle(Ctx& c, int l, cx<R>* x, const cx<R>* b, int nrhs);
 void coarsest_solve(Ctx& c, cx<double>* x, const cx<double>* b, int nrhs);
 // 16-bit fine level (x, r, p and b are 16-bit fields of nrhs right-hand sides)
 void ensure_work_h(Ctx& c, int nrhs);
 template <typename H>
-void mr_h(Ctx& c, HF x, HF r, HF p, int nrhs, int iters, double omega);
+void mr_h(Ctx& c, HF x, HF r, HF p, int nrhs, int iters, double omega, const HF* b0 = nullptr,
+          bool last_x_only = false);
 template <typename H>
 void vcycle_h(Ctx& c, HF x, HF b, int nrhs);
 

@@ -95,7 +95,8 @@ def test_committed_traffic_entries_are_well_formed(bench):
 def test_default_workload_and_single_gpu(bench, capsys):
     a = bench.parse([])
     assert tuple(a.dims) == (24, 24, 24, 48) and a.nrhs == 32 and a.nv == 24
-    assert a.eps == 0.45 and a.delta == 0.005 and a.mg_prec == "bf16" and a.setup_iters == 100
+    assert a.eps == 0.45 and a.delta == 0.005 and a.mg_prec == "bf16" and a.setup_iters == 250
+    assert a.restart == 12 and bench.parse(["--nrhs", "1"]).restart == 50
     with pytest.raises(SystemExit) as e:
         bench.main(["--gpus", "2"])
     assert e.value.code == 2

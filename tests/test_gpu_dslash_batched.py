@@ -1,6 +1,7 @@
-"""The register-blocked batched forms of the Wilson kernel (forms 3 and 4:
-two or four right-hand sides per thread, each link loaded once for them,
-direction-split waves) against the oracle (Sec. 1 operator): FP64 within
+"""The batched forms of the Wilson kernel (forms 3 and 4: two or four
+right-hand sides per thread, each link loaded once for them, direction-split
+waves; form 5: one wave per tile column walking its time layers; forms 6-8:
+forms 1-3 in tile-column box order) against the oracle (Sec. 1 operator): FP64 within
 1e-13, FP32 within 1e-6, 16-bit storage within the storage bound, on
 ragged lattices and with rhs groups; their fused MR partial sums through
 batched smoother steps; a forced form on a batch it does not divide (the
@@ -40,13 +41,15 @@ def site_max(f):
     return np.maximum(np.abs(f.real), np.abs(f.imag)).max(axis=(-2, -1))
 
 
-@pytest.mark.parametrize("form", [3, 4])
+@pytest.mark.parametrize("form", [3, 4, 5, 6, 7, 8])
 @pytest.mark.parametrize("dims,nrhs,group", [
-    ((8, 8, 8, 8), 4, None),     # one chunk of four, or two of two
+    ((8, 8, 8, 8), 4, None),     # one chunk of four, or two of two; form 5: 8 tile columns, one per XCD box
     ((8, 8, 8, 8), 8, 2),        # groups of two rhs
-    ((6, 4, 2, 10), 12, 4),      # ragged tiles, partly padded last site block
+    ((6, 4, 2, 10), 12, 4),      # ragged tiles, partly padded last site block (form 5 runs form 1)
     ((2, 2, 2, 2), 4, None),     # one 64-site block, mostly padding
-    ((16, 8, 8, 8), 8, 8),       # the whole batch as one group
+    ((16, 8, 8, 8), 8, 8),       # the whole batch as one group; form 5: chunks of 8 layers
+    ((4, 8, 4, 16), 4, 16),      # form 5: 2 tile columns (no XCD boxes), one chunk of 16 layers
+    ((8, 8, 16, 12), 4, 4),      # form 5: boxes of 1 x 1 x 2 columns, chunks of 4 layers
 ])
 def test_register_blocked_forms_match_oracle(form, dims, nrhs, group):
     m = -0.37
@@ -84,7 +87,7 @@ def test_forced_register_blocked_form_on_a_batch_it_does_not_divide():
     ctx.close()
 
 
-@pytest.mark.parametrize("form", [1, 3, 4])
+@pytest.mark.parametrize("form", [1, 3, 4, 5, 6, 7, 8])
 def test_batched_mr_steps_with_each_form(form):
     """Three MR steps on four right-hand sides (one step size per rhs from the
     partial sums the Wilson launch writes) equal the oracle's MR, Sec. 3."""

@@ -47,3 +47,12 @@ def test_chunked_basis_dots_equal_the_plain_product():
     for chunk in (64, 100, 1000, 4096):
         c = mk.basis_dots(V, w, chunk=chunk)
         assert float((c - V.conj() @ w).abs().max()) < 1e-12, chunk
+
+
+def test_chunked_basis_combination_equals_the_plain_product():
+    g = torch.Generator().manual_seed(5)
+    V = torch.randn(6, 1000, dtype=torch.complex128, generator=g)
+    c = torch.randn(6, dtype=torch.complex128, generator=g)
+    for chunk in (64, 100, 1000, 4096):
+        out = mk.basis_combine(V, c, chunk=chunk)
+        assert float((out - c @ V).abs().max()) < 1e-12, chunk
