@@ -104,6 +104,13 @@ typedef struct {
   int coarse_maxit;              /* iteration cap of the coarsest solve                 */
   int coarse_restart;            /* restart length of the coarsest GCR                  */
   int use_alpha;                 /* 1: minimal-residual step after prolongation (Sec. 3) */
+  int normal;                    /* 1: also set up multigrid on the normal equations
+                                    (Sec. 3, first approach): the candidates are relaxed on
+                                    D^dagger D v = 0, and besides D_c the Galerkin operator
+                                    (D^dagger D)_c = P^dagger D^dagger D P is built (33 blocks
+                                    per coarse site, wdmg_apply_Nc), for MG-CG solves.  Two
+                                    levels, aggregates of extent >= 2 and coarse extents >= 3
+                                    only (else WDMG_ERR_ARG / WDMG_ERR_DIMS); FP64.         */
 } wdmg_mg_params;
 
 typedef struct {
@@ -129,7 +136,14 @@ typedef struct {
                             BiCGStab with the V-cycle as right preconditioner (the
                             MG-BiCGstab of Sec. 4), one rhs after another, from x = 0
                             (x on input is ignored), restarting from the true residual
-                            after a breakdown; use_graph does not apply to it        */
+                            after a breakdown; use_graph does not apply to it; 2 CG on
+                            the normal equations D^dagger D x = D^dagger b (the CG of
+                            Sec. 4 and 5; precond and mg_prec ignored); 3 MG-CG (Sec. 4):
+                            flexible CG on the normal equations preconditioned by the
+                            two-level V-cycle on D^dagger D of a normal-equation
+                            hierarchy (wdmg_mg_params.normal; coarse solve by CG to
+                            coarse_tol).  2 and 3 run in FP64, one rhs after another,
+                            from x = 0, and stop on the true residual of D x = b.      */
 } wdmg_solve_params;
 
 typedef struct {
@@ -226,6 +240,12 @@ int wdmg_get_prolongator(wdmg_ctx* ctx, int level, void* V_out);
  * (complex64 vectors; the 16-bit kinds use 16-bit blocks with one scale per
  * block). */
 int wdmg_apply_Dc(wdmg_ctx* ctx, int level, void* out, const void* in, int nrhs, int prec);
+
+/* Sec. 3 (normal equations): out = (D^dagger D)_c in = P^dagger D^dagger D P in
+ * on coarse level 1 of a hierarchy set up with wdmg_mg_params.normal = 1,
+ * as the 33-block stencil the setup built.  Canonical coarse layout,
+ * complex128; WDMG_ERR_NOT_SETUP without a normal-equation hierarchy. */
+int wdmg_apply_Nc(wdmg_ctx* ctx, int level, void* out, const void* in, int nrhs);
 
 /* Sec. 2 / Sec. 3: c_out = P^dagger f_in (restriction from level l to l+1)
  * and f_out = P c_in (prolongation from level l+1 to l).  Canonical layouts

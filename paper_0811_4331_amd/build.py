@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libwdmg.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["layout.hip", "half.hip", "dslash.hip", "blas.hip", "transfer.hip", "coarse.hip", "solver.cpp", "abi.cpp"]
+SOURCES = ["layout.hip", "half.hip", "dslash.hip", "blas.hip", "transfer.hip", "coarse.hip", "normal.hip", "solver.cpp",
+           "abi.cpp"]
 ARCH = "gfx950"
 
 

@@ -265,6 +265,7 @@ void wdmg_default_mg_params(wdmg_mg_params* p) {
     p->level[l].vectors = nullptr;
     p->level[l].setup_prec = WDMG_F64;
   }
+  p->normal = 0;
   p->omega = 0.8;
   p->nu_pre = 2;
   p->nu_post = 2;
@@ -407,6 +408,8 @@ int wdmg_set_mass(wdmg_ctx* c, double m) {
       const double dm = m - c->setup_mass;
       for (int l = 1; l < c->nlevels; ++l) coarse_shift(*c, c->lev[l], dm);
       c->setup_mass = m;
+      // (D^dagger D)_c is not a shift of itself: probe it again at the new mass
+      if (c->lev[1].Nc64) normal_build(*c, c->lev[0], c->lev[1]);
     }
     return WDMG_OK;
   });
@@ -542,6 +545,18 @@ int wdmg_apply_Dc(wdmg_ctx* c, int level, void* out, const void* in, int nrhs, i
   });
 }
 
+int wdmg_apply_Nc(wdmg_ctx* c, int level, void* out, const void* in, int nrhs) {
+  return guarded(c, [&]() {
+    need_ptr(out, "out");
+    need_ptr(in, "in");
+    need_nrhs(nrhs);
+    need_mg(*c, level, true);
+    if (out == in) throw Error(WDMG_ERR_ARG, "out must differ from in");
+    normal_apply_c(*c, c->lev[level], static_cast<cx<double>*>(out), static_cast<const cx<double>*>(in), nrhs);
+    return WDMG_OK;
+  });
+}
+
 int wdmg_restrict(wdmg_ctx* c, int level, void* c_out, const void* f_in, int nrhs, int prec) {
   return guarded(c, [&]() {
     need_ptr(c_out, "c_out");
@@ -621,7 +636,29 @@ int wdmg_solve(wdmg_ctx* c, void* x, const void* b, int nrhs, const wdmg_solve_p
       if (!c->have_mg) throw Error(WDMG_ERR_NOT_SETUP, "no multigrid hierarchy set up");
       need_prec(p->mg_prec);
     }
-    if (p->outer != 0 && p->outer != 1) throw Error(WDMG_ERR_ARG, "outer must be 0 (FGCR) or 1 (BiCGStab)");
+    if (p->outer < 0 || p->outer > 3) throw Error(WDMG_ERR_ARG, "outer must be 0 (FGCR), 1 (BiCGStab), 2 (CGNR) or 3 (MG-CG)");
+    if (p->outer == 2 || p->outer == 3) {
+      // CG on the normal equations, plain or preconditioned by the normal-equation V-cycle
+      ensure_solve_io(*c, 1);
+      const size_t nc = (size_t)c->g0.vol * 12;
+      int worst = WDMG_OK;
+      for (int k = 0; k < nrhs; ++k) {
+        wdmg_solve_stats st{};
+        c->n_D = 0;
+        for (int l = 0; l < WDMG_MAX_LEVELS; ++l) c->n_Dc[l] = 0;
+        const double t0 = now();
+        fine_in<double>(*c, static_cast<const cx<double>*>(b) + k * nc, c->sol_b, 1);
+        const int rc = normal_solve(*c, c->sol_x, c->sol_b, p->tol, p->maxit, p->outer == 3, st);
+        fine_out<double>(*c, c->sol_x, static_cast<cx<double>*>(x) + k * nc, 1);
+        WDMG_HIP(hipStreamSynchronize(c->stream));
+        st.seconds = now() - t0;
+        st.n_D = c->n_D;
+        for (int l = 0; l < WDMG_MAX_LEVELS; ++l) st.n_Dc[l] = c->n_Dc[l];
+        if (stats) stats[k] = st;
+        if (rc != WDMG_OK) worst = rc;
+      }
+      return worst;
+    }
     if (p->outer == 1) {
       // MG-preconditioned BiCGStab, one right-hand side after another
       ensure_solve_io(*c, 1);

@@ -106,6 +106,11 @@ struct Level {
   // coarse operator of this level (l >= 1): [site][9][col][row]
   cx<double>* Dc64 = nullptr;
   cx<float>* Dc32 = nullptr;
+  // normal-equation coarse operator (D^dagger D)_c of this level (l >= 1) when
+  // the hierarchy was set up for the normal equations: [site][33][col][row],
+  // and its offset table (33 int4 offsets, then 81 ints: offset index by code)
+  cx<double>* Nc64 = nullptr;
+  void* noff = nullptr;
   // 16-bit copies, made on first use (kind WDMG_F16 / WDMG_BF16, 0: none):
   // prolongator columns (unscaled) and coarse blocks with one scale per block
   void* V16 = nullptr;

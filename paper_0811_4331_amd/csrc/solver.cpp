@@ -780,6 +780,8 @@ void free_hierarchy(Ctx& c) {
     dev_free(c, L.V16);
     dev_free(c, L.Dc16);
     dev_free(c, L.Dc16s);
+    dev_free(c, L.Nc64);
+    dev_free(c, L.noff);
     for (int i = 0; i < kWork; ++i) {
       if (l > 0) {
         dev_free(c, L.w64[i]);
@@ -948,7 +950,16 @@ void mg_setup(Ctx& c, const wdmg_mg_params& p) {
     }
     const int dof = l == 0 ? 12 : 2 * p.level[l - 1].nv;
     if (bvol * dof / 2 < lp.nv) throw Error(WDMG_ERR_DIMS, "aggregate too small for nv vectors");
+    if (p.normal) {
+      for (int mu = 0; mu < 4; ++mu)
+        if (lp.block[mu] < 2 || dims[mu] < 3)
+          throw Error(WDMG_ERR_DIMS, "a normal-equation hierarchy needs aggregates of extent >= 2 and coarse "
+                                     "extents >= 3");
+    }
   }
+  if (p.normal && p.n_levels != 2) throw Error(WDMG_ERR_ARG, "a normal-equation hierarchy has 2 levels");
+  if (p.normal && p.level[0].adapt_iters > 0)
+    throw Error(WDMG_ERR_ARG, "the adaptive augmentation runs the direct V-cycle: not with normal = 1");
   free_hierarchy(c);
   set_scalar(c, S_ERR, 0.0, 0.0);
   c.mg = p;
@@ -968,7 +979,12 @@ void mg_setup(Ctx& c, const wdmg_mg_params& p) {
       fine_to_internal<double, double>(c, F.g, src, F.V64, lp.nv);
     else
       copy<double>(c, F.V64, src, (size_t)lp.nv * F.n);
-    if (lp.setup_iters > 0) relax(c, l, lp, p.omega);
+    if (lp.setup_iters > 0) {
+      if (p.normal)
+        normal_relax(c, F, lp.nv, lp.setup_iters, p.omega);  // candidates of D^dagger D v = 0
+      else
+        relax(c, l, lp, p.omega);
+    }
     // coarse level geometry
     C.l = l + 1;
     int one[4] = {1, 1, 1, 1};
@@ -992,6 +1008,7 @@ void mg_setup(Ctx& c, const wdmg_mg_params& p) {
     else
       coarse_buildC(c, F, C);
     convert<float, double>(c, C.Dc32, C.Dc64, dcn);
+    if (p.normal) normal_build(c, F, C);
   }
   // coarse-level GCR blocks: every right-hand side active
   {

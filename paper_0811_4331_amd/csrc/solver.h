@@ -46,6 +46,16 @@ int bicgstab(Ctx& c, cx<double>* x, const cx<double>* b, double tol, int maxit, 
              const wdmg_solve_params* pc = nullptr);
 
 void mg_setup(Ctx& c, const wdmg_mg_params& p);
+
+// Normal equations (normal.hip): A = D^dagger D on level 0, its Galerkin
+// coarse operator on level 1, CGNR and MG-CG for one right-hand side.
+void normal_apply0(Ctx& c, cx<double>* out, const cx<double>* in, cx<double>* tmp, int nrhs);
+void normal_check_geometry(const Level& f, const Level& cl);
+void normal_relax(Ctx& c, Level& f, int nv, int iters, double omega);
+void normal_build(Ctx& c, Level& f, Level& cl);
+void normal_apply_c(Ctx& c, const Level& cl, cx<double>* out, const cx<double>* in, int nrhs);
+int normal_solve(Ctx& c, cx<double>* x, const cx<double>* b, double tol, int maxit, bool precond,
+                 wdmg_solve_stats& st);
 void free_hierarchy(Ctx& c);
 void init_level0(Ctx& c);
 void ensure_outer(Ctx& c, int k, int nrhs, bool need32, bool basis32);

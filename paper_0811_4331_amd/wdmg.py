@@ -51,7 +51,7 @@ class MgParams(ctypes.Structure):
                 ("omega", ctypes.c_double), ("nu_pre", ctypes.c_int), ("nu_post", ctypes.c_int),
                 ("coarse_cycles", ctypes.c_int), ("coarse_tol", ctypes.c_double),
                 ("coarse_maxit", ctypes.c_int), ("coarse_restart", ctypes.c_int),
-                ("use_alpha", ctypes.c_int)]
+                ("use_alpha", ctypes.c_int), ("normal", ctypes.c_int)]
 
 
 class SolveParams(ctypes.Structure):
@@ -134,6 +134,7 @@ def load() -> ctypes.CDLL:
         "wdmg_get_prolongator": (ip, [vp, ip, vp]),
         "wdmg_release_unused": (ip, [vp, ip]),
         "wdmg_apply_Dc": (ip, [vp, ip, vp, vp, ip, ip]),
+        "wdmg_apply_Nc": (ip, [vp, ip, vp, vp, ip]),
         "wdmg_restrict": (ip, [vp, ip, vp, vp, ip, ip]),
         "wdmg_prolong": (ip, [vp, ip, vp, vp, ip, ip]),
         "wdmg_smooth": (ip, [vp, ip, vp, vp, ip, ip, ip]),
@@ -272,7 +273,7 @@ class Context:
         return out
 
     def mg_setup(self, levels, *, omega=0.8, nu_pre=2, nu_post=2, coarse_cycles=4,
-                 coarse_tol=1e-1, coarse_maxit=200, coarse_restart=32, use_alpha=True):
+                 coarse_tol=1e-1, coarse_maxit=200, coarse_restart=32, use_alpha=True, normal=False):
         """``levels``: list of dicts ``{block, nv, setup_iters, vectors[, setup_prec, adapt_iters]}`` per coarsening;
         ``vectors`` is a complex128 device tensor ``[nv, <level l field shape>]``."""
         p = MgParams()
@@ -301,6 +302,7 @@ class Context:
         p.coarse_cycles, p.coarse_tol = int(coarse_cycles), float(coarse_tol)
         p.coarse_maxit, p.coarse_restart = int(coarse_maxit), int(coarse_restart)
         p.use_alpha = 1 if use_alpha else 0
+        p.normal = 1 if normal else 0
         self._check(self.lib.wdmg_mg_setup(self.h, ctypes.byref(p)))
         self.levels = new_levels
         del keep
@@ -322,6 +324,15 @@ class Context:
         out = torch.empty_like(c)
         self._check(self.lib.wdmg_apply_Dc(self.h, int(level), _ptr(out, _cdtype(prec), "out"),
                                            _ptr(c, _cdtype(prec), "in"), nrhs, PREC[prec]))
+        return out
+
+    def apply_Nc(self, level: int, c: torch.Tensor):
+        """(D^dagger D)_c of a normal-equation hierarchy on coarse level ``level``."""
+        base = len(self.coarse_shape(level))
+        nrhs = self._nrhs(c, base)
+        out = torch.empty_like(c)
+        self._check(self.lib.wdmg_apply_Nc(self.h, int(level), _ptr(out, torch.complex128, "out"),
+                                           _ptr(c, torch.complex128, "in"), nrhs))
         return out
 
     def restrict(self, level: int, f: torch.Tensor, prec: str = "f64"):
@@ -351,12 +362,14 @@ class Context:
 
     def solve(self, b: torch.Tensor, x0: torch.Tensor | None = None, *, tol=1e-10, restart=50,
               maxit=1000, precond=True, mg_prec="f64", graph=False, outer="fgcr"):
-        """MG-preconditioned solve; ``outer`` is "fgcr" (flexible GCR(restart)) or
-        "bicgstab" (BiCGStab with the V-cycle as right preconditioner, x0 = 0)."""
+        """MG-preconditioned solve; ``outer`` is "fgcr" (flexible GCR(restart)),
+        "bicgstab" (BiCGStab with the V-cycle as right preconditioner, x0 = 0),
+        "cgnr" (CG on the normal equations) or "mgcg" (flexible CG on the normal
+        equations with the normal-equation V-cycle)."""
         nrhs = self._nrhs(b, 6)
         x = torch.zeros_like(b) if x0 is None else x0.clone()
         p = SolveParams(float(tol), int(restart), int(maxit), 1 if precond else 0, PREC[mg_prec],
-                        1 if graph else 0, {"fgcr": 0, "bicgstab": 1}[outer])
+                        1 if graph else 0, {"fgcr": 0, "bicgstab": 1, "cgnr": 2, "mgcg": 3}[outer])
         stats = (SolveStats * nrhs)()
         rc = self.lib.wdmg_solve(self.h, _ptr(x, torch.complex128, "x"), _ptr(b, torch.complex128, "b"),
                                  nrhs, ctypes.byref(p), stats)
