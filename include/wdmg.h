@@ -299,7 +299,11 @@ int wdmg_solve_bicgstab(wdmg_ctx* ctx, void* x, const void* b, int nrhs, double 
  *                     6, 7, 8 forms 1, 2, 3 with the workgroups of each XCD
  *                     walking a box of tile columns layer by layer (4^4
  *                     tiles and tile columns that split into 8 boxes only,
- *                     else form 1).
+ *                     else form 1); 9 form 5 with XCD k taking the k-th
+ *                     eighth of the time extent (every tile column of it)
+ *                     and the rhs of a group running each column back to
+ *                     back (4^4 tiles and Lt a multiple of 8 only, else
+ *                     form 1; the rhs-group value sets the group).
  *   WDMG_TUNE_DSLASH_GROUP: right-hand sides per group (1..64) in the
  *                     workgroup order of a batched Wilson launch: each XCD
  *                     sweeps its lattice region once per group, with the

@@ -735,7 +735,7 @@ int wdmg_solve_bicgstab(wdmg_ctx* c, void* x, const void* b, int nrhs, double to
 int wdmg_set_tuning(wdmg_ctx* c, int key, int value) {
   return guarded(c, [&]() {
     if (key < 0 || key >= WDMG_TUNE_COUNT) throw Error(WDMG_ERR_ARG, "unknown tuning key");
-    const int hi = key == WDMG_TUNE_DSLASH ? 8 : key == WDMG_TUNE_COARSE_APPLY ? 1 : kMaxRhs;
+    const int hi = key == WDMG_TUNE_DSLASH ? 9 : key == WDMG_TUNE_COARSE_APPLY ? 1 : kMaxRhs;
     const int lo = key == WDMG_TUNE_DSLASH_GROUP ? 1 : 0;
     if (value != WDMG_TUNE_AUTO && (value < lo || value > hi)) throw Error(WDMG_ERR_ARG, "bad tuning value");
     c->tune_force[key] = value;

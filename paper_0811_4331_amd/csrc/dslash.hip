@@ -434,13 +434,20 @@ __global__ __launch_bounds__(256) void k_dslash4_rb(Geom g, IO io, R diag, int t
 // own spinor and link); lanes on a tile face load the neighbouring tile's
 // spinor (and link) instead.  Work items are grouped per XCD in boxes of
 // adjacent tile columns, so neighbouring columns share an L2 while they walk
-// the same layers.
+// the same layers (form 5), or per XCD in time slabs (form 9): XCD k takes
+// every tile column of the k-th eighth of the time extent, so no x, y or z
+// face of a column lies on another XCD and only the two slab ends read time
+// neighbours from another XCD's layers; inside the slab the XCD runs the
+// columns of a group of G right-hand sides back to back, rhs fastest, so the
+// G waves of one column share its links in L2.
 struct TmMap {
   int ncol;           // xyz tile columns
   int nch, T;         // chunks of T layers per column
   int nrhs;
   int box[3];         // tile columns per XCD box (0: no XCD boxes)
   int nbox[3];        // boxes per direction (product 8)
+  int slab;           // 1: time slabs per XCD (nch a multiple of 8)
+  int G;              // rhs group of the slab order (divides nrhs)
 };
 
 template <int SIGN, typename R>
@@ -508,7 +515,17 @@ __device__ __forceinline__ void tm_space_hops(const IO& io, const Geom& g, int s
 
 __device__ __forceinline__ void tm_work(const TmMap& m, int w, int& col, int& ch, int& rhs, const Geom& g) {
   int tx, ty, tz, local;
-  if (m.box[0]) {
+  if (m.slab) {
+    const int xcd = w & 7;
+    local = w >> 3;
+    const int rin = local % m.G;
+    int rest = local / m.G;
+    col = rest % m.ncol;
+    rest /= m.ncol;
+    const int ngrp = m.nrhs / m.G;
+    rhs = (rest % ngrp) * m.G + rin;
+    ch = xcd * (m.nch >> 3) + rest / ngrp;
+  } else if (m.box[0]) {
     const int xcd = w & 7;
     local = w >> 3;
     const int bs = m.box[0] * m.box[1] * m.box[2];
@@ -612,6 +629,23 @@ inline TmMap tm_map(const Geom& g, int nrhs, int T) {
   return m;
 }
 
+// Time-slab map (form 9): chunks of T layers, T the largest divisor of Lt / 8
+// up to 8, so every XCD walks the same number of whole chunks; G = rg when it
+// divides the batch, else 1.
+inline TmMap tm_slab_map(const Geom& g, int nrhs, int rg) {
+  TmMap m{};
+  m.ncol = g.nT[0] * g.nT[1] * g.nT[2];
+  const int nl = g.L[3] / 8;
+  m.T = 1;
+  for (int T = 1; T <= 8 && T <= nl; ++T)
+    if (nl % T == 0) m.T = T;
+  m.nch = g.L[3] / m.T;
+  m.nrhs = nrhs;
+  m.slab = 1;
+  m.G = (rg >= 1 && nrhs % rg == 0) ? rg : 1;
+  return m;
+}
+
 // Layers per chunk of the t-marching form: the rhs-group tuning value when it
 // is 4, 8 or 16 and divides Lt, else 8 (or 4).
 inline int tm_chunk(const Geom& g, int rg) {
@@ -644,11 +678,13 @@ inline BoxOrder box_order(const Geom& g) {
   return o;
 }
 
-// Forms 3, 4 and 8 need a batch they divide; forms 5-8 need 4^4 tiles, and
-// 6-8 tile columns that split into one box per XCD.
+// Forms 3, 4 and 8 need a batch they divide; forms 5-9 need 4^4 tiles, 6-8
+// tile columns that split into one box per XCD, and 9 a time extent that
+// splits into 8 slabs.
 inline bool form_fits(const Geom& g, int v, int nrhs) {
   const bool tiles = g.B[0] == 4 && g.B[1] == 4 && g.B[2] == 4 && g.B[3] == 4;
   if (v >= 5 && !tiles) return false;
+  if (v == 9) return g.L[3] % 8 == 0;
   if (v >= 6 && !box_order(g).on) return false;
   return nrhs % rb_of(v) == 0;
 }
@@ -680,8 +716,8 @@ void run_dslash(Ctx& c, const IO& io, int nrhs, int variant, int rg, double* dot
         hipLaunchKernelGGL((k_dslash4<IO, false, 4>), grid, block, 0, c.stream, g, io, diag, tneg, (int)gx, nrhs, rg,
                            dots, bo);
     }
-  } else if (base == 5) {
-    const TmMap m = tm_map(g, nrhs, tm_chunk(g, rg));
+  } else if (base == 5 || base == 9) {
+    const TmMap m = base == 5 ? tm_map(g, nrhs, tm_chunk(g, rg)) : tm_slab_map(g, nrhs, rg);
     const dim3 grid((unsigned)(m.ncol * m.nch * nrhs));
     if (dots)
       hipLaunchKernelGGL((k_dslash_tm<IO, true>), grid, dim3(64), 0, c.stream, g, io, diag, tneg, m, dots);
@@ -723,7 +759,7 @@ void run_dslash(Ctx& c, const IO& io, int nrhs, int variant, int rg, double* dot
 // writing `out` -- and returns the fastest (form 1 on ties).  The
 // register-blocked forms 3 and 4 take part when the batch is a multiple of
 // their 2 or 4 rhs per thread.
-constexpr int kDslashForms = 9;
+constexpr int kDslashForms = 10;
 
 template <class IO>
 float time_dslash(Ctx& c, const IO& io, int nrhs, int v, int rg, hipEvent_t (&ev)[2], int reps = 3) {

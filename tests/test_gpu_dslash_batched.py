@@ -1,7 +1,7 @@
 """The batched forms of the Wilson kernel (forms 3 and 4: two or four
 right-hand sides per thread, each link loaded once for them, direction-split
 waves; form 5: one wave per tile column walking its time layers; forms 6-8:
-forms 1-3 in tile-column box order) against the oracle (Sec. 1 operator): FP64 within
+forms 1-3 in tile-column box order; form 9: form 5 in time slabs per XCD) against the oracle (Sec. 1 operator): FP64 within
 1e-13, FP32 within 1e-6, 16-bit storage within the storage bound, on
 ragged lattices and with rhs groups; their fused MR partial sums through
 batched smoother steps; a forced form on a batch it does not divide (the
@@ -41,7 +41,7 @@ def site_max(f):
     return np.maximum(np.abs(f.real), np.abs(f.imag)).max(axis=(-2, -1))
 
 
-@pytest.mark.parametrize("form", [3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("form", [3, 4, 5, 6, 7, 8, 9])
 @pytest.mark.parametrize("dims,nrhs,group", [
     ((8, 8, 8, 8), 4, None),     # one chunk of four, or two of two; form 5: 8 tile columns, one per XCD box
     ((8, 8, 8, 8), 8, 2),        # groups of two rhs
@@ -50,6 +50,7 @@ def site_max(f):
     ((16, 8, 8, 8), 8, 8),       # the whole batch as one group; form 5: chunks of 8 layers
     ((4, 8, 4, 16), 4, 16),      # form 5: 2 tile columns (no XCD boxes), one chunk of 16 layers
     ((8, 8, 16, 12), 4, 4),      # form 5: boxes of 1 x 1 x 2 columns, chunks of 4 layers
+    ((4, 8, 4, 48), 6, 3),       # form 9: slabs of 6 layers, groups of 3 rhs
 ])
 def test_register_blocked_forms_match_oracle(form, dims, nrhs, group):
     m = -0.37
@@ -87,7 +88,7 @@ def test_forced_register_blocked_form_on_a_batch_it_does_not_divide():
     ctx.close()
 
 
-@pytest.mark.parametrize("form", [1, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("form", [1, 3, 4, 5, 6, 7, 8, 9])
 def test_batched_mr_steps_with_each_form(form):
     """Three MR steps on four right-hand sides (one step size per rhs from the
     partial sums the Wilson launch writes) equal the oracle's MR, Sec. 3."""

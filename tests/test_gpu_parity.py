@@ -380,8 +380,8 @@ def test_error_paths():
     with pytest.raises(wdmg.WdmgError) as e:  # unknown precision code
         ctx._check(ctx.lib.wdmg_apply_D(ctx.h, o32.data_ptr(), f32.data_ptr(), 1, 7))
     assert e.value.name == "WDMG_ERR_ARG"
-    with pytest.raises(wdmg.WdmgError) as e:  # no Wilson-kernel form 9
-        ctx.set_tuning("dslash", 9)
+    with pytest.raises(wdmg.WdmgError) as e:  # no Wilson-kernel form 10
+        ctx.set_tuning("dslash", 10)
     assert e.value.name == "WDMG_ERR_ARG"
     # links that are not SU(3) are rejected (the library stores two rows per link)
     bad = u.copy()
@@ -529,14 +529,14 @@ def test_batched_dslash_rhs_groups_match_oracle(form, group):
     assert 1 <= ctx.get_tuning("dslash_group", "f64", nrhs) <= nrhs
 
 
-@pytest.mark.parametrize("form", [0, 1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("form", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9])
 @pytest.mark.parametrize("dims,nrhs", [((8, 8, 8, 8), 1), ((6, 4, 2, 10), 3), ((2, 2, 2, 2), 2),
                                        ((4, 4, 4, 4), 1), ((8, 12, 4, 12), 2)])
 def test_both_dslash_forms_match_oracle(form, dims, nrhs):
     """The forms of the Wilson kernel (the autotuner's candidates: one thread
     per site, one wave per direction, the latter with capped registers, the
     register-blocked batch forms, which run form 1 where they do not divide the
-    batch, and the t-marching form, which needs 4^4 tiles and runs form 1
+    batch, and the t-marching forms, which need 4^4 tiles and run form 1
     elsewhere) each agree with the oracle."""
     m = -0.41
     ctx, u = make_ctx(dims, 0.35, 400 + sum(dims), m)
@@ -551,7 +551,7 @@ def test_both_dslash_forms_match_oracle(form, dims, nrhs):
     assert ctx.get_tuning("dslash", "f64", nrhs) == form
     ctx.set_tuning("dslash", None)
     ctx.apply_D(gpu(psi))  # autotuned
-    assert ctx.get_tuning("dslash", "f64", nrhs) in range(9)
+    assert ctx.get_tuning("dslash", "f64", nrhs) in range(10)
 
 
 @pytest.mark.parametrize("nrhs,nv", [(3, 12), (40, 8), (2, 32)])
