@@ -83,8 +83,11 @@ typedef struct {
   int setup_iters;       /* MR relaxation steps on D v = 0 (0: take the vectors as given) */
   const void* vectors;   /* device: nv starting vectors, canonical complex128 layout of
                             level l ([nv][sites][dof]); required */
-  int setup_prec;        /* arithmetic of the relaxation: WDMG_F64 or WDMG_F32 (the
-                            block orthonormalisation is FP64 either way)            */
+  int setup_prec;        /* arithmetic of the relaxation: WDMG_F64 or WDMG_F32, or at
+                            level 0 also WDMG_F16 / WDMG_BF16 (vectors, residuals
+                            and D r in 16-bit storage with per-site scales, FP32
+                            arithmetic); the block orthonormalisation is FP64
+                            either way                                              */
   int adapt_iters;       /* adaptive augmentation (Sec. 2): after the relaxation,
                             candidate k = 2..nv is refined by this many stationary
                             iterations x <- x - M A x of the two-level multigrid
@@ -327,6 +330,15 @@ enum {
   WDMG_TUNE_COUNT
 };
 int wdmg_set_tuning(wdmg_ctx* ctx, int key, int value);
+/* Sets the choice the autotuner keeps for key (WDMG_TUNE_DSLASH or
+ * WDMG_TUNE_DSLASH_GROUP) at precision prec and batch size nrhs (sizes from
+ * 64 up share one entry), as if it had timed the forms and picked `value`;
+ * WDMG_TUNE_AUTO clears the entry, so the next launch times the forms again.
+ * A value forced with wdmg_set_tuning takes precedence.  A form that does not
+ * apply to the batch or lattice runs form 1, as with wdmg_set_tuning.
+ * WDMG_ERR_ARG for another key, an unknown precision, nrhs < 1 or a value
+ * out of range. */
+int wdmg_set_tuning_for(wdmg_ctx* ctx, int key, int prec, int nrhs, int value);
 /* Current choice for key (WDMG_TUNE_AUTO until tuned) for precision prec
  * and batch size nrhs. */
 int wdmg_get_tuning(wdmg_ctx* ctx, int key, int prec, int nrhs, int* value);

@@ -743,6 +743,24 @@ int wdmg_set_tuning(wdmg_ctx* c, int key, int value) {
   });
 }
 
+int wdmg_set_tuning_for(wdmg_ctx* c, int key, int prec, int nrhs, int value) {
+  return guarded(c, [&]() {
+    if (key != WDMG_TUNE_DSLASH && key != WDMG_TUNE_DSLASH_GROUP)
+      throw Error(WDMG_ERR_ARG, "only the Wilson form and rhs group are kept per precision and batch");
+    need_prec(prec);
+    need_nrhs(nrhs);
+    const int hi = key == WDMG_TUNE_DSLASH ? 9 : kMaxRhs;
+    const int lo = key == WDMG_TUNE_DSLASH_GROUP ? 1 : 0;
+    if (value != WDMG_TUNE_AUTO && (value < lo || value > hi)) throw Error(WDMG_ERR_ARG, "bad tuning value");
+    const int slot = nrhs < kMaxRhs ? nrhs : kMaxRhs;
+    if (key == WDMG_TUNE_DSLASH)
+      c->tune_dslash[prec][slot] = (signed char)value;
+    else
+      c->tune_group[prec][slot] = (signed char)value;
+    return WDMG_OK;
+  });
+}
+
 int wdmg_get_tuning(wdmg_ctx* c, int key, int prec, int nrhs, int* value) {
   return guarded(c, [&]() {
     need_ptr(value, "value");

@@ -12,6 +12,13 @@ __global__ void k_round_h(const cx<float>* __restrict__ in, cxh<H>* __restrict__
     out[i] = f2h<H>(in[i].re, in[i].im);
 }
 
+// -v for every stored value: flipping the sign bits of both halves is exact
+// (the scales are unchanged).
+__global__ void k_neg_h(uint32_t* __restrict__ v, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    v[i] ^= 0x80008000u;
+}
+
 template <typename H>
 __global__ void k_zero_h(Geom g, cxh<H>* __restrict__ v, float* __restrict__ sc) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -158,6 +165,14 @@ void hf_copy(Ctx& c, HF dst, HF src, int nrhs) {
   copy<float>(c, static_cast<cx<float>*>(dst.v), static_cast<const cx<float>*>(src.v), (size_t)nrhs * 6 * vp);
   copy<float>(c, reinterpret_cast<cx<float>*>(dst.s), reinterpret_cast<const cx<float>*>(src.s),
               (size_t)nrhs * vp / 2);
+}
+
+void hf_neg(Ctx& c, HF f, int nrhs) {
+  const size_t n = (size_t)nrhs * 12 * c.g0.vpad;
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_neg_h, dim3((unsigned)blocks), dim3(256), 0, c.stream, static_cast<uint32_t*>(f.v), n);
+  WDMG_HIP(hipGetLastError());
 }
 
 template <typename H>

@@ -278,6 +278,7 @@ void hf_free(Ctx& c, HF& f);
 template <typename H>
 void hf_zero(Ctx& c, HF f, int nrhs);
 void hf_copy(Ctx& c, HF dst, HF src, int nrhs);
+void hf_neg(Ctx& c, HF f, int nrhs);  // f = -f, exact
 // internal R field [rhs][12 vpad] <-> 16-bit field
 template <typename R, typename H>
 void to_half(Ctx& c, const cx<R>* in, HF out, int nrhs);

@@ -860,8 +860,47 @@ static void relax_batch(Ctx& c, int l, cx<R>* V, int nv, int iters, double omega
   dev_free(c, Pb);
 }
 
+// The same relaxation at level 0 with the candidates, residuals and A r in
+// 16-bit storage (per-site scales, FP32 arithmetic; the dslash launch fuses
+// the MR partial sums as in the 16-bit smoother).  The batch is cut when its
+// three 16-bit fields would exceed a 16 GB budget.
+template <typename H>
+static void relax_batch_h(Ctx& c, cx<double>* V, int nv, int iters, double omega) {
+  const size_t n = c.lev[0].n;
+  const size_t per_rhs = (size_t)c.g0.vpad * (12 * 4 + 4) * 3;
+  size_t kb = ((size_t)16 << 30) / per_rhs;
+  if (kb < 1) kb = 1;
+  if (kb > (size_t)nv) kb = nv;
+  if (kb > (size_t)kMaxRhs) kb = kMaxRhs;
+  HF X = hf_alloc(c, (int)kb), Rb = hf_alloc(c, (int)kb), Pb = hf_alloc(c, (int)kb);
+  dots_buffer(c, (int)kb);
+  for (int k0 = 0; k0 < nv; k0 += (int)kb) {
+    const int nb = (nv - k0) < (int)kb ? (nv - k0) : (int)kb;
+    to_half<double, H>(c, V + (size_t)k0 * n, X, nb);
+    // r = 0 - A x
+    dslash_h<H>(c, Rb, X, nb);
+    hf_neg(c, Rb, nb);
+    for (int it = 0; it < iters; ++it) {
+      dslash_h_mr<H>(c, Pb, Rb, nb, omega, S_BATCH);
+      update2_half<H>(c, X, Rb, Rb, Pb, nb, S_BATCH, 0);
+    }
+    from_half<H, double>(c, X, V + (size_t)k0 * n, nb);
+  }
+  WDMG_HIP(hipStreamSynchronize(c.stream));
+  hf_free(c, X);
+  hf_free(c, Rb);
+  hf_free(c, Pb);
+}
+
 static void relax(Ctx& c, int l, const wdmg_level_params& lp, double omega) {
   Level& F = c.lev[l];
+  if (lp.setup_prec == WDMG_F16 || lp.setup_prec == WDMG_BF16) {
+    if (lp.setup_prec == WDMG_F16)
+      relax_batch_h<f16_t>(c, F.V64, lp.nv, lp.setup_iters, omega);
+    else
+      relax_batch_h<bf16_t>(c, F.V64, lp.nv, lp.setup_iters, omega);
+    return;
+  }
   if (lp.setup_prec == WDMG_F32) {
     const size_t nn = (size_t)lp.nv * F.n;
     convert<float, double>(c, F.V32, F.V64, nn);
@@ -937,8 +976,10 @@ void mg_setup(Ctx& c, const wdmg_mg_params& p) {
     const wdmg_level_params& lp = p.level[l];
     if (lp.nv < 1 || lp.nv > 32) throw Error(WDMG_ERR_ARG, "nv must be in 1..32");
     if (lp.setup_iters < 0) throw Error(WDMG_ERR_ARG, "setup_iters must be >= 0");
-    if (lp.setup_prec != WDMG_F64 && lp.setup_prec != WDMG_F32)
-      throw Error(WDMG_ERR_ARG, "setup_prec must be WDMG_F64 or WDMG_F32");
+    if (lp.setup_prec < WDMG_F64 || lp.setup_prec > WDMG_BF16)
+      throw Error(WDMG_ERR_ARG, "setup_prec must be WDMG_F64, WDMG_F32, WDMG_F16 or WDMG_BF16");
+    if (l > 0 && lp.setup_prec != WDMG_F64 && lp.setup_prec != WDMG_F32)
+      throw Error(WDMG_ERR_ARG, "16-bit setup relaxation exists for level 0 only");
     if (lp.adapt_iters < 0) throw Error(WDMG_ERR_ARG, "adapt_iters must be >= 0");
     if (!lp.vectors) throw Error(WDMG_ERR_ARG, "starting vectors are required for every level");
     int bvol = 1;

@@ -382,6 +382,12 @@ class Context:
         """Force a kernel form (0, 1, ...) or let the autotuner pick (None)."""
         self._check(self.lib.wdmg_set_tuning(self.h, self.TUNE[key], -1 if value is None else int(value)))
 
+    def set_tuning_for(self, key: str, prec: str, nrhs: int, value: int | None):
+        """Pin the autotuner's choice of ``key`` ("dslash" or "dslash_group") for one
+        precision and batch size (None clears it)."""
+        self._check(self.lib.wdmg_set_tuning_for(self.h, self.TUNE[key], PREC[prec], int(nrhs),
+                                                 -1 if value is None else int(value)))
+
     def get_tuning(self, key: str, prec: str = "f64", nrhs: int = 1):
         v = ctypes.c_int()
         self._check(self.lib.wdmg_get_tuning(self.h, self.TUNE[key], PREC[prec], int(nrhs), ctypes.byref(v)))

@@ -244,3 +244,59 @@ def test_three_level_solve_with_16bit_intermediate_level():
             assert sb[j]["converged"], (kind, sb[j])
             res = np.linalg.norm(bb[j] - wilson.apply_D(u, xb[j].cpu().numpy(), m)) / np.linalg.norm(bb[j])
             assert res <= 1e-10
+
+
+def _aggregate_columns(q, blk):
+    """``[Nv, T, Z, Y, X, 2, 6]`` -> ``[Tc, Zc, Yc, Xc, chi, rows, Nv]``: the
+    orthonormal columns of P on each (aggregate, chirality)."""
+    bx, by, bz, bt = blk
+    nv, lt, lz, ly, lx, two, n = q.shape
+    a = q.reshape(nv, lt // bt, bt, lz // bz, bz, ly // by, by, lx // bx, bx, two, n)
+    a = a.transpose(1, 3, 5, 7, 9, 2, 4, 6, 8, 10, 0)
+    return a.reshape(lt // bt, lz // bz, ly // by, lx // bx, two, bt * bz * by * bx * n, nv)
+
+
+@pytest.mark.parametrize("setup_prec", ["f32", "f16", "bf16"])
+def test_setup_relaxation_in_reduced_precision(setup_prec):
+    """Sec. 2 setup relaxation with the candidates in FP32 or 16-bit storage.
+
+    The block QR of nearly dependent candidates amplifies a perturbation of
+    the candidates in its last columns (FP32 storage, 6e-8, moves the spans
+    by about 4e-5 here), so P itself is compared with the FP64 oracle's only
+    in FP32 (largest principal-angle sine over all aggregates and both
+    chiralities; the 16-bit spans are only reported), and for every
+    precision the FP64 MG solve built on the hierarchy must reach 1e-10 with
+    at most two more outer iterations than the one built on the FP64 setup:
+    the relaxation is judged by the coarse space it delivers."""
+    dims, blk, nv = (8, 8, 8, 8), (4, 4, 4, 4), 12
+    seed = synthetic.gauge_seed(1, 1)
+    m = MCRIT[f"8x8x8x8_eps0.3_seed{seed}"]["m_crit"] + 0.05
+    u = synthetic.gauge_field(dims, 0.3, seed)
+    ctx = wdmg.Context(dims, DEV)
+    ctx.set_gauge(gpu(u))
+    ctx.set_mass(m)
+    v0 = synthetic.gaussian_vectors((nv,) + ctx.fine_shape(), synthetic.null_seed(1))
+    b = synthetic.gaussian_spinor(dims, seed=synthetic.rhs_seed(1))
+    op = coarse.WilsonLevel(u, m, -1.0)
+    from oracle import mg
+    qref, _ = transfer.block_orthonormalize(mg.relax_null_vectors(op.apply, transfer.as_chiral(v0), 50), blk)
+    a_ref = _aggregate_columns(qref, blk)
+    iters = {}
+    for prec in ("f64", setup_prec):
+        ctx.mg_setup([{"block": blk, "nv": nv, "setup_iters": 50, "vectors": gpu(v0), "setup_prec": prec}],
+                     coarse_tol=1e-2)
+        qg = ctx.get_prolongator(0).cpu().numpy().reshape(qref.shape)
+        a = _aggregate_columns(qg, blk)
+        # sine of the largest principal angle between the two column spans
+        resid = a - a_ref @ (np.conj(np.swapaxes(a_ref, -1, -2)) @ a)
+        sin_max = float(np.linalg.norm(resid, ord=2, axis=(-2, -1)).max())
+        print(f"setup {prec}: largest principal-angle sine {sin_max:.2e}")
+        if prec in ("f64", "f32"):
+            assert sin_max <= {"f64": 1e-9, "f32": 1e-3}[prec], (prec, sin_max)
+        x, st = ctx.solve(gpu(b), tol=1e-10, restart=50, maxit=300)
+        res = float(np.linalg.norm(b - wilson.apply_D(u, x.cpu().numpy(), m)) / np.linalg.norm(b))
+        assert st[0]["converged"] and res <= 1e-10, (prec, res)
+        iters[prec] = st[0]["iters"]
+    print(f"outer iterations: {iters}")
+    assert iters[setup_prec] <= iters["f64"] + 2, iters
+    ctx.close()
