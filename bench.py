@@ -11,9 +11,11 @@ right-hand side, inputs resident in HBM before the timed region.
 Default workload: the 24^3 x 48 lattice with links exp(i 0.45 H),
 antiperiodic time, m = m_crit + 0.005 with m_crit of this very field,
 32 Gaussian right-hand sides solved together: batched FP32 setup (Nv = 24,
-250 MR steps, 4^4 aggregates), V-cycle in BF16 storage with FP32
-arithmetic (coarse operator and P^dagger on matrix cores), FP64 coarsest
-GCR and FP64 outer flexible GCR(12) with an FP32 basis.
+200 MR steps, 4^4 aggregates; then Nv = 16 on 2^4 aggregates of the coarse
+lattice, 25 steps), the Sec. 5 three-level cycle (four level-1 V-cycles per
+fine cycle) with the fine level in BF16 storage and FP32 arithmetic
+(coarse operators and P^dagger on matrix cores), FP64 coarsest GCR to 0.3
+and FP64 outer flexible GCR(12) with an FP32 basis.
 
 Beside the K timed steps, on the same GPU and field, the line carries the
 two comparators of the target: FP64 single-rhs MG (FP64 setup and V-cycle,
@@ -48,6 +50,21 @@ PEAK_TFS = {"f64": 78.6, "f32": 157.3, "h": 2500.0}
 WILSON_LINK_BYTES = {"f64": 576, "f32": 288, "f16": 144, "bf16": 144}
 WILSON_SPINOR_BYTES = {"f64": 384, "f32": 192, "f16": 104, "bf16": 104}
 WILSON_FLOPS = 1368  # per fine site and rhs: 8 spin-projected hops and the mass term
+
+# Wilson kernel form and rhs group pinned per (precision, rhs per launch) for
+# the default workload, from the form sweep on this lattice (24^3 x 48: form 5
+# fastest in FP32 at 24 and 32 rhs, form 2 in BF16 at 32 rhs); the FP32 setup
+# runs 24-rhs launches and the outer solve 32-rhs ones.  Pinning keeps the
+# step's kernels, and so the committed counter profile, the same from box to
+# box; elsewhere (or with --autotune) the library's autotuner decides.
+PINNED_TUNING = {((24, 24, 24, 48), 32): {("f32", 24): (5, 8), ("f32", 32): (5, 8), ("bf16", 32): (2, 2)}}
+# Sources of each profiled kernel family (a committed counter profile is
+# used only while these files are unchanged).
+KERNEL_SOURCES = {
+    "dslash": ["paper_0811_4331_amd/csrc/dslash.hip", "paper_0811_4331_amd/csrc/fine_field.h",
+               "paper_0811_4331_amd/csrc/half_field.h", "paper_0811_4331_amd/csrc/wilson_spin.h",
+               "paper_0811_4331_amd/csrc/common.h"],
+}
 
 
 def wilson_bytes(prec, vol, launches, units):
@@ -141,8 +158,8 @@ def counter_traffic(kernel, workload, bytes_per_launch, tuning=None):
     """HBM bytes per launch from the committed PMC measurement of this kernel in
     this workload (FETCH_SIZE + WRITE_SIZE, scaled by what the same counters read
     for a plain copy), or None when there is none, the kernel's sources changed
-    since, or this run's kernel forms differ from the ones the counters were
-    taken with."""
+    since, or this run's kernel forms (the entries of ``tuning`` the
+    measurement names) differ from the ones the counters were taken with."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
@@ -156,7 +173,12 @@ def counter_traffic(kernel, workload, bytes_per_launch, tuning=None):
                 h.update(fh.read())
         if h.hexdigest()[:16] != e["source_hash"]:
             continue
-        if e.get("tuning") == tuning:
+        want = e.get("tuning")
+        if isinstance(want, dict) and isinstance(tuning, dict):
+            same = all(tuning.get(k) == v for k, v in want.items())
+        else:
+            same = want == tuning
+        if same:
             return e["measured_over_algorithmic"] * bytes_per_launch
     return None
 
@@ -172,9 +194,12 @@ def parse(argv=None):
     ap.add_argument("--mass", type=float, default=None,
                     help="use this bare mass instead of m_crit + delta (no m_crit lookup)")
     ap.add_argument("--nv", type=int, default=24)
-    ap.add_argument("--levels", type=int, default=2, choices=[2, 3],
-                    help="3: a second coarsening with 2^4 aggregates (Sec. 5 three-level cycle)")
-    ap.add_argument("--nv2", type=int, default=32, help="near-null vectors of the second coarsening")
+    ap.add_argument("--levels", type=int, default=None, choices=[2, 3],
+                    help="3: a second coarsening with 2^4 aggregates (Sec. 5 three-level cycle); default 3 for "
+                         "batches of 16 or more on lattices whose extents are multiples of 8, else 2")
+    ap.add_argument("--nv2", type=int, default=16, help="near-null vectors of the second coarsening")
+    ap.add_argument("--setup-iters2", type=int, default=25,
+                    help="MR relaxation steps of the second coarsening's vectors")
     ap.add_argument("--setup-iters", type=int, default=None,
                     help="MR relaxation steps per near-null vector (default 50 for fewer than 8 rhs, "
                          "100 for 8 to 15 and 250 for 16 or more, whose setup cost is shared)")
@@ -185,18 +210,19 @@ def parse(argv=None):
     ap.add_argument("--nullvec-source", default="host", choices=["host", "device"],
                     help="first-level null-vector starts: numpy on the host, kept on the device, or "
                          "torch's seeded device generator inside each step, released after the setup (large lattices)")
-    ap.add_argument("--tuning", default=None, metavar="F1,FB,GB",
-                    help="force the Wilson form of one-rhs launches (F1), and the form (FB) and rhs group (GB) "
-                         "of batched launches, instead of the autotuner")
+    ap.add_argument("--autotune", action="store_true",
+                    help="let the library's autotuner pick every Wilson form (default: the forms pinned for the "
+                         "default workload)")
     ap.add_argument("--release-unused", action="store_true",
                     help="after each setup, free the FP64/FP32 copies of P and D_c that the 16-bit V-cycle "
                          "does not read (room for larger batches)")
     ap.add_argument("--coarse-apply", type=int, default=None, choices=[0, 1],
                     help="force a form of the batched coarsest-level operator (default: library choice)")
-    ap.add_argument("--setup-prec", default="f32", choices=["f64", "f32"],
-                    help="arithmetic of the setup relaxation (the block QR is FP64 either way)")
+    ap.add_argument("--setup-prec", default="f32", choices=["f64", "f32", "f16", "bf16"],
+                    help="arithmetic (storage, for 16 bits) of the setup relaxation; the block QR is FP64 either way")
     ap.add_argument("--mg-prec", default="bf16", choices=["f64", "f32", "f16", "bf16"])
-    ap.add_argument("--coarse-tol", type=float, default=0.1)
+    ap.add_argument("--coarse-tol", type=float, default=None,
+                    help="relative residual of the coarsest GCR (default 0.3 with 3 levels, 0.1 with 2)")
     ap.add_argument("--alpha", action="store_true",
                     help="take the minimal-residual step size after prolongation (off: alpha = 1, "
                          "which converges in far fewer outer iterations on these fields)")
@@ -221,9 +247,17 @@ def parse(argv=None):
                     help="start with a plain 1 GiB device copy (the reference for hardware byte counters)")
     ap.add_argument("--only-dslash", type=int, default=0, metavar="L",
                     help="only time Dslash on L^4 plus a plain 1 GiB device copy, then exit")
+    ap.add_argument("--traffic-entry", nargs=5, metavar=("FETCH_CSV", "WRITE_CSV", "BENCH_JSON", "KERNEL", "COMMAND"),
+                    help="no GPU work: turn two rocprofv3 --pmc runs of this benchmark (FETCH_SIZE, then "
+                         "WRITE_SIZE, each started with --copy-calibration) and the JSON line of the first into "
+                         "KERNEL's entry of profiles/traffic.json (KERNEL: the headline run's dominant kernel)")
     a = ap.parse_args(argv)
+    if a.levels is None:
+        a.levels = 3 if a.nrhs >= 16 and all(d % 8 == 0 for d in a.dims) else 2
+    if a.coarse_tol is None:
+        a.coarse_tol = 0.3 if a.levels == 3 else 0.1
     if a.setup_iters is None:
-        a.setup_iters = 50 if a.nrhs < 8 else (100 if a.nrhs < 16 else 250)
+        a.setup_iters = 50 if a.nrhs < 8 else (100 if a.nrhs < 16 else 200)
     if a.restart is None:
         a.restart = 50 if a.nrhs < 8 else 12
     return a
@@ -390,12 +424,15 @@ def bicgstab_comparator(ctx, b1, budget_s, torch):
 
 def fp64_mg_comparator(ctx, b1, a, v0, torch):
     """FP64 single-rhs MG on the same field: FP64 setup (l = 50 MR steps, the
-    single-rhs default) and V-cycle, FGCR(50); one untimed run, then one timed."""
+    single-rhs default) and V-cycle, 2 levels (4^4 aggregates, coarsest GCR to
+    0.1; faster for one rhs than the batch's 3-level shape: 1.43 against
+    1.58 s on the default workload), FGCR(50); one untimed run, then one
+    timed."""
     levels = [{"block": (4, 4, 4, 4), "nv": a.nv, "setup_iters": 50, "vectors": v0, "setup_prec": "f64"}]
 
     def once():
         t0 = time.perf_counter()
-        ctx.mg_setup(levels, coarse_tol=a.coarse_tol, use_alpha=a.alpha)
+        ctx.mg_setup(levels, coarse_tol=0.1, use_alpha=a.alpha)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         _, st = ctx.solve(b1, tol=1e-10, restart=50, maxit=3000, mg_prec="f64")
@@ -407,7 +444,7 @@ def fp64_mg_comparator(ctx, b1, a, v0, torch):
     return {"s_per_rhs": ts + tv, "setup_s": ts, "solve_s": tv, "iters": [s["iters"] for s in st],
             "n_D": [s["n_D"] for s in st], "converged": all(s["converged"] for s in st),
             "true_res": [s["true_res"] for s in st],
-            "what": f"FP64 setup (l = 50) and V-cycle, Nv = {a.nv}, FGCR(50), one rhs"}
+            "what": f"FP64 setup (l = 50) and V-cycle, 2 levels, Nv = {a.nv}, FGCR(50), one rhs"}
 
 
 def cpu_baseline_oracle(torch, dev, wdmg, synthetic):
@@ -453,8 +490,78 @@ def cpu_baseline_oracle(torch, dev, wdmg, synthetic):
             "host_cpus": os.cpu_count()}
 
 
+def kernel_family_names(kernel):
+    """Substrings of the HIP kernel names (demangled or mangled) of one profiled kernel id."""
+    fam, prec = kernel.split("_", 1)
+    io = {"f64": ["FullIO<double>", "FullIOIdE"], "f32": ["FullIO<float>", "FullIOIfE"],
+          "f16": ["HalfIO<_Float16>", "HalfIOIDF16_E"], "bf16": ["HalfIO<__bf16>", "HalfIOIDF16bE"]}[prec]
+    return ["k_dslash"], io
+
+
+def traffic_entry(fetch_csv, write_csv, bench_json, kernel, command):
+    """Entry of profiles/traffic.json for one profiled kernel of a bench run:
+    its FETCH_SIZE and WRITE_SIZE per launch (KiB per dispatch in the CSVs,
+    scaled by the counters' reading of the run's 1 GiB copy) over the
+    algorithmic bytes per launch of the same run."""
+    import csv
+    import hashlib
+    with open(bench_json) as fh:
+        line = [json.loads(x) for x in fh if x.startswith("{")][-1]
+    roof = line["rooflines"][kernel]
+    if not kernel.startswith("dslash_"):
+        raise SystemExit(f"no counter mapping for {kernel}")
+    must, io = kernel_family_names(kernel)
+
+    def per_dispatch(path, counter):
+        vals, copy = {}, []
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] != counter:
+                    continue
+                name, v = r["Kernel_Name"], float(r["Counter_Value"])
+                if "copyBuffer" in name:
+                    copy.append(v)
+                elif all(m in name for m in must) and any(t in name for t in io):
+                    vals[r["Dispatch_Id"]] = v  # repeated rows of one dispatch carry one value
+        return list(vals.values()), max(copy)
+
+    fetch, fcopy = per_dispatch(fetch_csv, "FETCH_SIZE")
+    write, wcopy = per_dispatch(write_csv, "WRITE_SIZE")
+    if len(fetch) != roof["launches"] or len(write) != roof["launches"]:
+        raise SystemExit(f"{len(fetch)} / {len(write)} profiled dispatches, {roof['launches']} launches in the line")
+    gib_kib = float(1 << 20)  # the 1 GiB copy read and written, in KiB
+    f_scale, w_scale = gib_kib / fcopy, gib_kib / wcopy
+    alg = roof["bytes_per_launch"]
+    fb = np.mean(fetch) * 1024 * f_scale / alg
+    wb = np.mean(write) * 1024 * w_scale / alg
+    fam = kernel.split("_")[0]
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[fam]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    prec = kernel.split("_", 1)[1]
+    tuning = {k: v for k, v in line["tuning"].items() if k.startswith(prec + "x")}
+    wl = "x".join(map(str, line["config"]["lattice"])) + f"_{line['config']['nrhs']}rhs_{line['config']['mg_prec']}"
+    entry = {"tuning": tuning, "measured_over_algorithmic": fb + wb, "fetch_bytes_over_alg": fb,
+             "write_bytes_over_alg": wb, "launches": roof["launches"], "alg_bytes_per_launch": alg,
+             "fetch_kib_per_dispatch": float(np.mean(fetch)), "write_kib_per_dispatch": float(np.mean(write)),
+             "copy_scale": {"FETCH_SIZE": f_scale, "WRITE_SIZE": w_scale},
+             "source_files": KERNEL_SOURCES[fam], "source_hash": h.hexdigest()[:16], "command": command}
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    with open(path) as fh:
+        t = json.load(fh)
+    t["entries"][f"{kernel}@{wl}"] = [entry]
+    with open(path, "w") as fh:
+        json.dump(t, fh, indent=1, sort_keys=True)
+        fh.write("\n")
+    print(json.dumps({f"{kernel}@{wl}": entry}))
+
+
 def main(argv=None):
     a = parse(argv)
+    if a.traffic_entry:
+        traffic_entry(*a.traffic_entry)
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only (every path here is single-GPU); "
                                    "--gpus must be 1", "n_gpus": a.gpus}), flush=True)
@@ -486,6 +593,10 @@ def main(argv=None):
     del u
     ctx.set_mass(m)
     ctx.set_tuning("coarse_apply", a.coarse_apply)
+    pinned = {} if a.autotune else PINNED_TUNING.get((dims, a.nrhs), {})
+    for (prec, n), (form, group) in pinned.items():
+        ctx.set_tuning_for("dslash", prec, n, form)
+        ctx.set_tuning_for("dslash_group", prec, n, group)
     v0_shape = (a.nv,) + ctx.fine_shape()
     if a.nullvec_source == "host":
         v0 = torch.from_numpy(synthetic.gaussian_vectors(v0_shape, synthetic.null_seed(cfg))).to(dev)
@@ -505,14 +616,9 @@ def main(argv=None):
         cdims = tuple(d // 4 for d in dims)
         v1 = torch.from_numpy(synthetic.gaussian_vectors(
             (a.nv2, cdims[3], cdims[2], cdims[1], cdims[0], 2, a.nv), synthetic.null_seed(cfg) + 500)).to(dev)
-        levels.append({"block": (2, 2, 2, 2), "nv": a.nv2, "setup_iters": a.setup_iters, "vectors": v1,
-                       "setup_prec": a.setup_prec})
-    forced = [int(v) for v in a.tuning.split(",")] if a.tuning else None
-
+        levels.append({"block": (2, 2, 2, 2), "nv": a.nv2, "vectors": v1, "setup_iters": a.setup_iters2,
+                       "setup_prec": a.setup_prec if a.setup_prec in ("f64", "f32") else "f32"})
     def step():
-        if forced:
-            ctx.set_tuning("dslash", forced[1])
-            ctx.set_tuning("dslash_group", forced[2])
         if v0 is None:
             levels[0]["vectors"] = device_v0()
             torch.cuda.synchronize()
@@ -524,9 +630,6 @@ def main(argv=None):
             levels[0]["vectors"] = None  # the setup copied them; the solve gets the memory
         if a.release_unused:
             ctx.release_unused(a.mg_prec)
-        if forced and a.nrhs == 1:
-            ctx.set_tuning("dslash", forced[0])
-            ctx.set_tuning("dslash_group", None)
         x, st = ctx.solve(b, tol=1e-10, restart=a.restart, maxit=3000, mg_prec=a.mg_prec, graph=a.graph,
                           outer=a.outer)
         torch.cuda.synchronize()
@@ -550,12 +653,14 @@ def main(argv=None):
     ctx.profile(False)
     progress(f"{a.steps} timed steps done in {elapsed:.1f} s")
     one = "f64" if a.mg_prec == "f64" else "f32"
-    setup_batch = max(1, min(a.nv, 64, (16 << 30) // (2 * vol * 12 * (16 if a.setup_prec == "f64" else 8))))
+    field_b = {"f64": 2 * 12 * 16, "f32": 2 * 12 * 8, "f16": 3 * 52, "bf16": 3 * 52}[a.setup_prec]
+    setup_batch = max(1, min(a.nv, 64, (16 << 30) // (vol * field_b)))  # the library's 16 GB relaxation budget
     vprec = a.mg_prec if a.mg_prec in ("f16", "bf16") else one
-    tuning = forced or [ctx.get_tuning("dslash", one, 1), ctx.get_tuning("dslash", a.setup_prec, setup_batch),
-                        ctx.get_tuning("dslash_group", a.setup_prec, setup_batch),
-                        ctx.get_tuning("dslash", vprec, a.nrhs), ctx.get_tuning("dslash_group", vprec, a.nrhs),
-                        ctx.get_tuning("coarse_apply", "f64", a.nrhs)]
+    # Wilson form and rhs group of every (precision, rhs per launch) the step runs
+    tuning = {f"{p}x{n}": [ctx.get_tuning("dslash", p, n), ctx.get_tuning("dslash_group", p, n)]
+              for p, n in ((a.setup_prec, setup_batch), (one, a.nrhs), (vprec, a.nrhs), ("f64", a.nrhs))}
+    tuning["coarse_apply"] = ctx.get_tuning("coarse_apply", "f64", a.nrhs)
+    tuning["pinned"] = bool(pinned)
     last = stats[-1]
     if not all(s["converged"] and s["true_res"] <= 1e-10 for st in stats for s in st):
         raise SystemExit(f"solve did not reach 1e-10: {last}")
@@ -599,7 +704,8 @@ def main(argv=None):
         "config": {"workload": f"{'x'.join(map(str, dims))} Wilson-Dirac, links exp(i {a.eps} H), "
                                f"m = m_crit + {a.delta}, "
                                + (f"2-level MG 4^4 aggregates Nv={a.nv}, " if a.levels == 2 else
-                                  f"3-level MG 4^4 then 2^4 aggregates Nv={a.nv} then {a.nv2}, ")
+                                  f"3-level MG 4^4 then 2^4 aggregates Nv={a.nv} then {a.nv2} "
+                                  f"({a.setup_iters2} MR setup iters), ")
                                + f"{a.setup_prec} MR setup {a.setup_iters} iters, {a.mg_prec} V-cycle, "
                                + (f"adaptive {a.adapt_iters} two-level iters per candidate, " if a.adapt_iters else "")
                                + (f"FGCR({a.restart})" if a.outer == "fgcr" else "MG-BiCGStab")
