@@ -11,6 +11,8 @@
 // block of one coarse site: it applies the fine hops to the chirality-split
 // columns of P at a few sites at a time (staged in LDS) and contracts them
 // with the conjugated columns, all in FP64.
+#include <type_traits>
+
 #include "half_field.h"
 #include "internal.h"
 #include "wilson_spin.h"
@@ -651,9 +653,11 @@ __global__ __launch_bounds__(576) void k_coarse_apply_h(Geom g, int n2, const cx
 // A batch on the matrix cores with 16-bit operands (v_mfma_f32_32x32x8 f16 or
 // bf16, FP32 accumulation).  Same real-GEMM form and tiling as the FP32
 // kernel.  Per direction, each right-hand-side column of the staged operand
-// is scaled into [-1, 1] by its largest magnitude and rounded to 16 bits;
-// the product of that direction is accumulated from zero and added to the
-// result times (block scale x column scale).  Operand lanes: A[i][k] at lane
+// is rounded to 16 bits: in FP16 after scaling it into [-1, 1] by its largest
+// magnitude (the format's range is narrow), in BF16 as it is (BF16 has the
+// range of FP32, so a scale would change no relative rounding error); the
+// product of that direction is accumulated from zero and added to the result
+// times the block scale (and the FP16 column scale).  Operand lanes: A[i][k] at lane
 // i + 32 (k / 4), element k % 4; B[k][j] at lane j + 32 (k / 4), element
 // k % 4; result as for the FP32 kernel.
 typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
@@ -757,16 +761,20 @@ __global__ __launch_bounds__(256) void k_coarse_apply_mfma16(Geom g, int n2, int
     const float fd = fsc;
     if (d + 1 < 9) fetch(d + 1);
     __syncthreads();
-    if (threadIdx.x < 32) {
-      float m = 0.0f;
-      for (int k = 0; k < kr; ++k) m = fmaxf(m, fabsf(Bs[k][threadIdx.x]));
-      float inv;
-      Bsc[threadIdx.x] = quant_scale(m, inv);
-      Binv[threadIdx.x] = inv;
+    float binv = 1.0f, bsc = 1.0f;
+    if constexpr (sizeof(H) == 2 && !std::is_same<H, bf16_t>::value) {
+      if (threadIdx.x < 32) {
+        float m = 0.0f;
+        for (int k = 0; k < kr; ++k) m = fmaxf(m, fabsf(Bs[k][threadIdx.x]));
+        float inv;
+        Bsc[threadIdx.x] = quant_scale(m, inv);
+        Binv[threadIdx.x] = inv;
+      }
+      __syncthreads();
+      binv = Binv[l & 31];
+      bsc = Bsc[l & 31];
     }
-    __syncthreads();
     const int r = wave * 32 + (l & 31), i = r >> 1, pr = r & 1;
-    const float binv = Binv[l & 31];
     floatx16 t;
 #pragma unroll
     for (int e = 0; e < 16; ++e) t[e] = 0.f;
@@ -788,7 +796,7 @@ __global__ __launch_bounds__(256) void k_coarse_apply_mfma16(Geom g, int n2, int
       }
       t = mfma_32x32x8<H>(a, b, t);
     }
-    const float f = fd * Bsc[l & 31];
+    const float f = fd * bsc;
 #pragma unroll
     for (int e = 0; e < 16; ++e) acc[e] += f * t[e];
   }
