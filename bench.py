@@ -15,7 +15,7 @@ antiperiodic time, m = m_crit + 0.005 with m_crit of this very field,
 lattice, 25 steps), the Sec. 5 three-level cycle (four level-1 V-cycles per
 fine cycle) with the fine level in BF16 storage and FP32 arithmetic
 (coarse operators and P^dagger on matrix cores), FP64 coarsest GCR to 0.3
-and FP64 outer flexible GCR(12) with an FP32 basis.
+and FP64 outer flexible GCR(6) with an FP32 basis.
 
 Beside the K timed steps, on the same GPU and field, the line carries the
 two comparators of the target: FP64 single-rhs MG (FP64 setup and V-cycle,
@@ -229,8 +229,9 @@ def parse(argv=None):
                     help="take the minimal-residual step size after prolongation (off: alpha = 1, "
                          "which converges in far fewer outer iterations on these fields)")
     ap.add_argument("--restart", type=int, default=None,
-                    help="FGCR restart length (paper: 50; default 50 for fewer than 8 rhs, 12 for batches, "
-                         "whose outer basis is large)")
+                    help="FGCR restart length (paper: 50; default 50 for fewer than 8 rhs, 12 for 8 to 15 and "
+                         "6 for 16 or more: with the FP32 basis a cycle ends at the reliable update anyway, and "
+                         "a short basis saves Gram-Schmidt passes)")
     ap.add_argument("--outer", default="fgcr", choices=["fgcr", "bicgstab"],
                     help="outer Krylov method: flexible GCR (Sec. 5) or BiCGStab with the V-cycle as right "
                          "preconditioner (Sec. 4)")
@@ -261,7 +262,7 @@ def parse(argv=None):
     if a.setup_iters is None:
         a.setup_iters = 50 if a.nrhs < 8 else (100 if a.nrhs < 16 else 200)
     if a.restart is None:
-        a.restart = 50 if a.nrhs < 8 else 12
+        a.restart = 50 if a.nrhs < 8 else (12 if a.nrhs < 16 else 6)
     return a
 
 

@@ -119,7 +119,7 @@ def test_default_workload_and_single_gpu(bench, capsys):
     assert tuple(a.dims) == (24, 24, 24, 48) and a.nrhs == 32 and a.nv == 24
     assert a.eps == 0.45 and a.delta == 0.005 and a.mg_prec == "bf16" and a.setup_iters == 200
     assert a.levels == 3 and a.nv2 == 16 and a.coarse_tol == 0.3 and a.setup_iters2 == 25
-    assert a.restart == 12 and bench.parse(["--nrhs", "1"]).restart == 50
+    assert a.restart == 6 and bench.parse(["--nrhs", "1"]).restart == 50 and bench.parse(["--nrhs", "8"]).restart == 12
     one = bench.parse(["--nrhs", "1", "--dims", "16", "16", "16", "16"])
     assert one.levels == 2 and one.coarse_tol == 0.1 and one.setup_iters == 50
     with pytest.raises(SystemExit) as e:
