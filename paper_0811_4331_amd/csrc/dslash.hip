@@ -27,6 +27,7 @@ constexpr int kDslashThreads = 128;
 template <typename R>
 struct FullIO {
   using T = R;
+  static constexpr bool kScaled = false;  // values are read as they are stored
   const cx<R>* in;
   cx<R>* out;
   const cx<R>* U;
@@ -59,6 +60,7 @@ struct FullIO {
 template <typename H>
 struct HalfIO {
   using T = float;
+  static constexpr bool kScaled = true;  // spinor_raw: stored values and the site scale apart
   const cxh<H>* in;
   const float* isc;
   cxh<H>* out;
@@ -71,12 +73,24 @@ struct HalfIO {
     osc += (size_t)rhs * vpad;
   }
   __device__ __forceinline__ void spinor(int s, cx<float> (&p)[12]) const { load_site_h(in, isc, s, p); }
+  // the stored values of site s (in [-1, 1]) and the scale they are multiplied by
+  __device__ __forceinline__ void spinor_raw(int s, cx<float> (&p)[12], float& sc) const {
+    sc = isc[s];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) p[k] = h2f(in[fidx(s, k, 12)]);
+  }
   __device__ __forceinline__ void link(int mu, int s, bool neg, cx<float> (&u)[9]) const {
     load_link_h(U, mu, s, neg, u);
   }
   __device__ __forceinline__ void store(int s, const cx<float> (&v)[12]) const { store_site_h(out, osc, s, v); }
   __device__ __forceinline__ void spinor_r(int r, int vpad, int s, cx<float> (&p)[12]) const {
     load_site_h(in + (size_t)r * 12 * vpad, isc + (size_t)r * vpad, s, p);
+  }
+  __device__ __forceinline__ void spinor_r_raw(int r, int vpad, int s, cx<float> (&p)[12], float& sc) const {
+    const cxh<H>* b = in + (size_t)r * 12 * vpad;
+    sc = isc[(size_t)r * vpad + s];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) p[k] = h2f(b[fidx(s, k, 12)]);
   }
   __device__ __forceinline__ void store_r(int r, int vpad, int s, const cx<float> (&v)[12]) const {
     store_site_h(out + (size_t)r * 12 * vpad, osc + (size_t)r * vpad, s, v);
@@ -86,7 +100,11 @@ struct HalfIO {
 template <int MU, int SIGN, class IO, typename R = typename IO::T>
 __device__ __forceinline__ void hop(const IO& io, int nb, int link_site, bool neg, cx<R> (&acc)[12]) {
   cx<R> p[12];
-  io.spinor(nb, p);
+  R sc = (R)1;
+  if constexpr (IO::kScaled)
+    io.spinor_raw(nb, p, sc);  // the scale is applied in the expansion
+  else
+    io.spinor(nb, p);
   cx<R> h[6];
   project<MU, SIGN>(p, h);
   cx<R> u[9];
@@ -107,7 +125,10 @@ __device__ __forceinline__ void hop(const IO& io, int nb, int link_site, bool ne
       uh[a * 3 + i] = s;
     }
   }
-  expand_add<MU, SIGN>(uh, acc);
+  if constexpr (IO::kScaled)
+    expand_add_scaled<MU, SIGN>(uh, sc, acc);
+  else
+    expand_add<MU, SIGN>(uh, acc);
 }
 
 // One thread per site; blockIdx.y = right-hand side.  Padding sites
@@ -180,7 +201,7 @@ __device__ __forceinline__ void box_block(const BoxOrder& o, int n, int rg, int&
 // result independent of scheduling.
 template <typename R>
 __device__ __forceinline__ void wave_dots(bool live, const cx<R> (&out)[12], const cx<R> (&in)[12], double* dots,
-                                          size_t slot) {
+                                          size_t slot, R in_scale = (R)1) {
   double d0 = 0.0, d1 = 0.0, d2 = 0.0;
   if (live) {
 #pragma unroll
@@ -190,6 +211,8 @@ __device__ __forceinline__ void wave_dots(bool live, const cx<R> (&out)[12], con
       d1 += ore * iim - oim * ire;
       d2 += ore * ore + oim * oim;
     }
+    d0 *= (double)in_scale;  // in = in_scale x the values passed (16-bit storage)
+    d1 *= (double)in_scale;
   }
   d0 = wave_sum(d0);
   d1 = wave_sum(d1);
@@ -213,6 +236,7 @@ __global__ __launch_bounds__(kDslashThreads) void k_dslash(Geom g, IO io, R diag
   for (int k = 0; k < 12; ++k) acc[k] = mk<R>(0, 0);
   const bool live = s < g.vol;
   cx<R> p[12];
+  R psc = (R)1;  // storage scale of p (16-bit fields read raw)
   if (live) {
     int c[4];
     coords_of(g, s, c);
@@ -238,14 +262,19 @@ __global__ __launch_bounds__(kDslashThreads) void k_dslash(Geom g, IO io, R diag
       hop<3, -1>(io, b, b, tfirst, acc);
     }
     const R half = (R)0.5;
-    io.spinor(s, p);
+    if constexpr (IO::kScaled)
+      io.spinor_raw(s, p, psc);
+    else
+      io.spinor(s, p);
+    const R dg = diag * psc;
 #pragma unroll
-    for (int k = 0; k < 12; ++k) acc[k] = mk<R>(diag * p[k].re - half * acc[k].re, diag * p[k].im - half * acc[k].im);
+    for (int k = 0; k < 12; ++k) acc[k] = mk<R>(dg * p[k].re - half * acc[k].re, dg * p[k].im - half * acc[k].im);
   }
   if (s < g.vpad) io.store(s, acc);  // padding sites: zeros
   if constexpr (DOTS)
     wave_dots(live, acc, p, dots,
-              (size_t)rhs * nsb * (kDslashThreads / 64) + (size_t)sb * (kDslashThreads / 64) + (threadIdx.x >> 6));
+              (size_t)rhs * nsb * (kDslashThreads / 64) + (size_t)sb * (kDslashThreads / 64) + (threadIdx.x >> 6),
+              psc);
 }
 
 // Direction-split form: a workgroup of four waves covers one 64-site block;
@@ -306,16 +335,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MINW))) voi
   // uniform over the wave
   if (mu != 0 || s >= g.vpad) return;
   cx<R> p[12];
+  R psc = (R)1;  // storage scale of p (16-bit fields read raw)
   if (live) {
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[k] = acc[k] + part[0][k][lane] + part[1][k][lane] + part[2][k][lane];
     const R half = (R)0.5;
-    io.spinor(s, p);
+    if constexpr (IO::kScaled)
+      io.spinor_raw(s, p, psc);
+    else
+      io.spinor(s, p);
+    const R dg = diag * psc;
 #pragma unroll
-    for (int k = 0; k < 12; ++k) acc[k] = mk<R>(diag * p[k].re - half * acc[k].re, diag * p[k].im - half * acc[k].im);
+    for (int k = 0; k < 12; ++k) acc[k] = mk<R>(dg * p[k].re - half * acc[k].re, dg * p[k].im - half * acc[k].im);
   }
   io.store(s, acc);  // padding sites: zeros
-  if constexpr (DOTS) wave_dots(live, acc, p, dots, (size_t)rhs * nsb + sb);
+  if constexpr (DOTS) wave_dots(live, acc, p, dots, (size_t)rhs * nsb + sb, psc);
 }
 
 // Register-blocked direction-split form for batches: the workgroup layout of
@@ -335,7 +369,11 @@ __device__ __forceinline__ void hop_rb(const IO& io, int vpad, int nb, int link_
 #pragma unroll
   for (int r = 0; r < RB; ++r) {
     cx<R> p[12];
-    io.spinor_r(r, vpad, nb, p);
+    R sc = (R)1;
+    if constexpr (IO::kScaled)
+      io.spinor_r_raw(r, vpad, nb, p, sc);
+    else
+      io.spinor_r(r, vpad, nb, p);
     cx<R> h[6];
     project<MU, SIGN>(p, h);
     cx<R> uh[6];
@@ -354,7 +392,10 @@ __device__ __forceinline__ void hop_rb(const IO& io, int vpad, int nb, int link_
         uh[a * 3 + i] = t;
       }
     }
-    expand_add<MU, SIGN>(uh, acc[r]);
+    if constexpr (IO::kScaled)
+      expand_add_scaled<MU, SIGN>(uh, sc, acc[r]);
+    else
+      expand_add<MU, SIGN>(uh, acc[r]);
   }
 }
 
@@ -407,17 +448,22 @@ __global__ __launch_bounds__(256) void k_dslash4_rb(Geom g, IO io, R diag, int t
     __syncthreads();
     if (mu == 0) {
       cx<R> p[12];
+      R psc = (R)1;  // storage scale of p (16-bit fields read raw)
       if (live) {
 #pragma unroll
         for (int k = 0; k < 12; ++k)
           acc[r][k] = acc[r][k] + part[r & 1][0][k][lane] + part[r & 1][1][k][lane] + part[r & 1][2][k][lane];
-        io.spinor_r(r, g.vpad, s, p);
+        if constexpr (IO::kScaled)
+          io.spinor_r_raw(r, g.vpad, s, p, psc);
+        else
+          io.spinor_r(r, g.vpad, s, p);
+        const R dg = diag * psc;
 #pragma unroll
         for (int k = 0; k < 12; ++k)
-          acc[r][k] = mk<R>(diag * p[k].re - half * acc[r][k].re, diag * p[k].im - half * acc[r][k].im);
+          acc[r][k] = mk<R>(dg * p[k].re - half * acc[r][k].re, dg * p[k].im - half * acc[r][k].im);
       }
       io.store_r(r, g.vpad, s, acc[r]);  // padding sites: zeros
-      if constexpr (DOTS) wave_dots(live, acc[r], p, dots, (size_t)(ch * RB + r) * nsb + sb);
+      if constexpr (DOTS) wave_dots(live, acc[r], p, dots, (size_t)(ch * RB + r) * nsb + sb, psc);
     }
   }
 }

@@ -53,4 +53,45 @@ __device__ __forceinline__ void expand_add(const cx<R> (&h)[6], cx<R> (&acc)[12]
   }
 }
 
+// acc += sc * (full four-spin image of h): the expansion of a hop whose
+// neighbour spinor was read without its 16-bit storage scale sc (the scale
+// commutes with the projection and the link product, and every add of the
+// expansion becomes one fused multiply-add).
+template <int MU, int SIGN, typename R>
+__device__ __forceinline__ void expand_add_scaled(const cx<R> (&h)[6], R sc, cx<R> (&acc)[12]) {
+  const R ms = -sc;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const cx<R> h0 = h[c], h1 = h[3 + c];
+    acc[c] = mk<R>(fma(sc, h0.re, acc[c].re), fma(sc, h0.im, acc[c].im));
+    acc[3 + c] = mk<R>(fma(sc, h1.re, acc[3 + c].re), fma(sc, h1.im, acc[3 + c].im));
+    // the image's components 2 and 3 as (coefficient of h.re / h.im) pairs
+    if (MU == 0) {  // (1 - g1): (-i h1, -i h0); (1 + g1): (i h1, i h0)
+      if (SIGN > 0) {
+        acc[6 + c] = mk<R>(fma(sc, h1.im, acc[6 + c].re), fma(ms, h1.re, acc[6 + c].im));
+        acc[9 + c] = mk<R>(fma(sc, h0.im, acc[9 + c].re), fma(ms, h0.re, acc[9 + c].im));
+      } else {
+        acc[6 + c] = mk<R>(fma(ms, h1.im, acc[6 + c].re), fma(sc, h1.re, acc[6 + c].im));
+        acc[9 + c] = mk<R>(fma(ms, h0.im, acc[9 + c].re), fma(sc, h0.re, acc[9 + c].im));
+      }
+    } else if (MU == 1) {  // (-h1, h0) ; (h1, -h0)
+      const R s2 = SIGN > 0 ? ms : sc, s3 = SIGN > 0 ? sc : ms;
+      acc[6 + c] = mk<R>(fma(s2, h1.re, acc[6 + c].re), fma(s2, h1.im, acc[6 + c].im));
+      acc[9 + c] = mk<R>(fma(s3, h0.re, acc[9 + c].re), fma(s3, h0.im, acc[9 + c].im));
+    } else if (MU == 2) {  // (-i h0, i h1) ; (i h0, -i h1)
+      if (SIGN > 0) {
+        acc[6 + c] = mk<R>(fma(sc, h0.im, acc[6 + c].re), fma(ms, h0.re, acc[6 + c].im));
+        acc[9 + c] = mk<R>(fma(ms, h1.im, acc[9 + c].re), fma(sc, h1.re, acc[9 + c].im));
+      } else {
+        acc[6 + c] = mk<R>(fma(ms, h0.im, acc[6 + c].re), fma(sc, h0.re, acc[6 + c].im));
+        acc[9 + c] = mk<R>(fma(sc, h1.im, acc[9 + c].re), fma(ms, h1.re, acc[9 + c].im));
+      }
+    } else {  // (-h0, -h1) ; (h0, h1)
+      const R s23 = SIGN > 0 ? ms : sc;
+      acc[6 + c] = mk<R>(fma(s23, h0.re, acc[6 + c].re), fma(s23, h0.im, acc[6 + c].im));
+      acc[9 + c] = mk<R>(fma(s23, h1.re, acc[9 + c].re), fma(s23, h1.im, acc[9 + c].im));
+    }
+  }
+}
+
 }  // namespace wdmg
