@@ -215,6 +215,9 @@ def parse(argv=None):
     ap.add_argument("--autotune", action="store_true",
                     help="let the library's autotuner pick every Wilson form (default: the forms pinned for the "
                          "default workload)")
+    ap.add_argument("--in-place", action="store_true",
+                    help="solve in place (x written over b, no internal copy of b; the host copy of the rhs "
+                         "refills b before every step, outside the timing): room for the largest batches")
     ap.add_argument("--release-unused", action="store_true",
                     help="after each setup, free the FP64/FP32 copies of P and D_c that the 16-bit V-cycle "
                          "does not read (room for larger batches)")
@@ -619,7 +622,8 @@ def main(argv=None):
         return torch.randn(v0_shape, dtype=torch.complex128, device=dev, generator=g)
     bh = np.stack([synthetic.gaussian_spinor(dims, synthetic.rhs_seed(cfg, j)) for j in range(a.nrhs)])
     b = torch.from_numpy(bh).to(dev)
-    del bh
+    if not a.in_place:
+        del bh  # with --in-place the host copy refills b before every step, outside the timing
     levels = [{"block": (4, 4, 4, 4), "nv": a.nv, "setup_iters": a.setup_iters, "adapt_iters": a.adapt_iters,
                "vectors": v0, "setup_prec": a.setup_prec}]
     if a.levels == 3:
@@ -641,24 +645,33 @@ def main(argv=None):
         if a.release_unused:
             ctx.release_unused(a.mg_prec)
         x, st = ctx.solve(b, tol=1e-10, restart=a.restart, maxit=3000, mg_prec=a.mg_prec, graph=a.graph,
-                          outer=a.outer)
+                          outer=a.outer, in_place=a.in_place)
         torch.cuda.synchronize()
         return x, st, t1 - t0, time.perf_counter() - t1
 
+    def refill():
+        """In place, the previous step left its solution in b: restore the rhs (untimed)."""
+        if a.in_place:
+            b.copy_(torch.from_numpy(bh))
+            torch.cuda.synchronize()
+
     for i in range(a.warmup):
+        refill()
         step()
         progress(f"warm-up step {i + 1}/{a.warmup} done")
     torch.cuda.synchronize()
     ctx.profile(True)
-    t_start = time.perf_counter()
+    elapsed = 0.0
     setups, solves, stats = [], [], []
     for _ in range(a.steps):
+        refill()
+        t_step = time.perf_counter()
         x, st, ts, tv = step()
+        elapsed += time.perf_counter() - t_step
         setups.append(ts)
         solves.append(tv)
         stats.append(st)
     torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
     prof = ctx.profile_read()
     ctx.profile(False)
     progress(f"{a.steps} timed steps done in {elapsed:.1f} s")
@@ -676,12 +689,14 @@ def main(argv=None):
         raise SystemExit(f"solve did not reach 1e-10: {last}")
     # independent check of the final residual with the library's FP64 D, one
     # rhs at a time (a batch-sized temporary may not fit beside the solver's memory)
-    rr = 0.0
+    rr = bb = 0.0
     for j in range(a.nrhs):
-        rj = b[j] - ctx.apply_D(x[j])
+        bj = torch.from_numpy(bh[j]).to(dev) if a.in_place else b[j]
+        rj = bj - ctx.apply_D(x[j])
         rr += float(torch.linalg.vector_norm(rj)) ** 2
-        del rj
-    true_res = rr ** 0.5 / float(torch.linalg.vector_norm(b))
+        bb += float(torch.linalg.vector_norm(bj)) ** 2
+        del rj, bj
+    true_res = (rr / bb) ** 0.5
     del x
 
     ms_per_step = elapsed / a.steps * 1e3
@@ -726,10 +741,12 @@ def main(argv=None):
                    "nrhs": a.nrhs, "mg_prec": a.mg_prec, "setup_prec": a.setup_prec, "coarse_tol": a.coarse_tol,
                    "setup_iters": a.setup_iters, "adapt_iters": a.adapt_iters, "outer": a.outer,
                    "restart": a.restart, "alpha_step": a.alpha, "graph": a.graph,
-                   "nullvec_source": a.nullvec_source, "release_unused": a.release_unused},
+                   "nullvec_source": a.nullvec_source, "release_unused": a.release_unused,
+                   "in_place": a.in_place},
         "setup_s": float(np.median(setups)), "solve_s_per_rhs": float(np.median(solves)) / a.nrhs,
         "mg_iters": [s["iters"] for s in last], "mg_n_D": [s["n_D"] for s in last],
         "mg_n_Dc": [s["n_Dc"][1] for s in last], "true_res": true_res,
+        "device_memory_peak_gb": torch.cuda.max_memory_allocated() / 1e9,
         "roofline": roofline, "rooflines": roofs, "kernels": kinfo, "dc_mfma": dc_mfma_util(kinfo, w, a.nrhs),
         "tuning": tuning,
     }
@@ -738,12 +755,16 @@ def main(argv=None):
     if a.precision_report:
         result["precision_error"] = precision_report(ctx, torch, synthetic, dims)
     comps = {}
+
+    def b1():
+        """The first right-hand side (in place, b now holds the solution)."""
+        return torch.from_numpy(bh[0]).to(dev) if a.in_place else b[0].contiguous()
     if not a.no_fp64_mg:
         v64 = v0 if v0 is not None else device_v0()
-        comps["fp64_single_rhs_mg"] = fp64_mg_comparator(ctx, b[0].contiguous(), a, v64, torch)
+        comps["fp64_single_rhs_mg"] = fp64_mg_comparator(ctx, b1(), a, v64, torch)
         del v64
     if not a.no_bicgstab:
-        comps["bicgstab"] = bicgstab_comparator(ctx, b[0].contiguous(), a.bicgstab_budget, torch)
+        comps["bicgstab"] = bicgstab_comparator(ctx, b1(), a.bicgstab_budget, torch)
     if comps:
         for c in comps.values():
             c["ratio_to_value"] = c["s_per_rhs"] / value

@@ -147,6 +147,14 @@ typedef struct {
                             hierarchy (wdmg_mg_params.normal; coarse solve by CG to
                             coarse_tol).  2 and 3 run in FP64, one rhs after another,
                             from x = 0, and stop on the true residual of D x = b.      */
+  int in_place;          /* 1 (FGCR with a V-cycle below FP64, restart >= 2, no graph):
+                            the solve starts from x = 0 (x on input is ignored) and
+                            keeps no internal copy of b; b is read from the caller's
+                            buffer whenever the true residual is recomputed, so it must
+                            stay unchanged during the call, and x may be the same
+                            buffer as b (the solution then replaces b at the end).  Saves
+                            one FP64 field per rhs, for the largest batches.  0: x and b
+                            must be different buffers.                              */
 } wdmg_solve_params;
 
 typedef struct {

@@ -234,15 +234,20 @@ void smooth_impl(Ctx& c, int level, void* x, const void* b, int nrhs, int iters)
   }
 }
 
-void ensure_solve_io(Ctx& c, int nrhs) {
+// Internal x (and, unless the solve runs in place, b) for nrhs right-hand sides.
+void ensure_solve_io(Ctx& c, int nrhs, bool need_b = true) {
   const size_t n = (size_t)c.g0.vpad * 12;
   if (nrhs > c.sol_cap) {
     WDMG_HIP(hipStreamSynchronize(c.stream));
     dev_free(c, c.sol_x);
-    dev_free(c, c.sol_b);
     c.sol_x = static_cast<cx<double>*>(dev_alloc(c, (size_t)nrhs * n * sizeof(cx<double>)));
-    c.sol_b = static_cast<cx<double>*>(dev_alloc(c, (size_t)nrhs * n * sizeof(cx<double>)));
     c.sol_cap = nrhs;
+  }
+  if (need_b && nrhs > c.sol_bcap) {
+    WDMG_HIP(hipStreamSynchronize(c.stream));
+    dev_free(c, c.sol_b);
+    c.sol_b = static_cast<cx<double>*>(dev_alloc(c, (size_t)nrhs * n * sizeof(cx<double>)));
+    c.sol_bcap = nrhs;
   }
 }
 
@@ -285,6 +290,7 @@ void wdmg_default_solve_params(wdmg_solve_params* p) {
   p->mg_prec = WDMG_F64;
   p->use_graph = 0;
   p->outer = 0;
+  p->in_place = 0;
 }
 
 int wdmg_create(wdmg_ctx** out, const int dims[4], const wdmg_alloc* alloc, void* hip_stream) {
@@ -681,15 +687,27 @@ int wdmg_solve(wdmg_ctx* c, void* x, const void* b, int nrhs, const wdmg_solve_p
       }
       return worst;
     }
-    ensure_solve_io(*c, nrhs);
+    const bool in_place = p->in_place != 0;
+    if (in_place && (!p->precond || p->mg_prec == WDMG_F64 || p->restart < 2 || p->use_graph))
+      throw Error(WDMG_ERR_ARG, "in-place solves need FGCR with a V-cycle below FP64, restart >= 2 and no graph");
+    if (!in_place && x == b) throw Error(WDMG_ERR_ARG, "x and b are the same buffer: set in_place");
+    ensure_solve_io(*c, nrhs, !in_place);
     std::vector<wdmg_solve_stats> st(nrhs);
     c->n_D = 0;
     for (int l = 0; l < WDMG_MAX_LEVELS; ++l) c->n_Dc[l] = 0;
 
     const double t0 = now();
-    fine_in<double>(*c, b, c->sol_b, nrhs);
-    fine_in<double>(*c, x, c->sol_x, nrhs);
-    const int rc = fgcr(*c, c->sol_x, c->sol_b, nrhs, *p, st.data());
+    int rc;
+    if (in_place) {
+      // x starts from zero; b is read from the caller's buffer whenever the
+      // residual is recomputed, and x is written over it at the end
+      zero<double>(*c, c->sol_x, (size_t)nrhs * c->g0.vpad * 12);
+      rc = fgcr(*c, c->sol_x, nullptr, nrhs, *p, st.data(), b);
+    } else {
+      fine_in<double>(*c, b, c->sol_b, nrhs);
+      fine_in<double>(*c, x, c->sol_x, nrhs);
+      rc = fgcr(*c, c->sol_x, c->sol_b, nrhs, *p, st.data());
+    }
     fine_out<double>(*c, c->sol_x, x, nrhs);
     WDMG_HIP(hipStreamSynchronize(c->stream));
     const double secs = now() - t0;

@@ -219,7 +219,8 @@ struct Ctx {
   cx<double>* bicg[8] = {};
   cx<double>* sol_x = nullptr;   // internal x, b of a solve
   cx<double>* sol_b = nullptr;
-  int sol_cap = 0;
+  int sol_cap = 0;    // rhs capacity of sol_x
+  int sol_bcap = 0;   // rhs capacity of sol_b (in-place solves keep none)
   int outer_cap = 0;             // rhs capacity of outer_r
   int outer_capB = 0;            // rhs capacity of the FP64 outer basis
   int outer_cap32 = 0;

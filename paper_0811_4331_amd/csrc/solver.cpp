@@ -422,7 +422,8 @@ template void vcycle_h<bf16_t>(Ctx&, HF, HF, int);
 // lockstep, each with its own coefficients; a converged right-hand side is
 // frozen (its steps are zero).  b (input) and x (initial guess, output) are
 // nrhs internal fields.
-int fgcr(Ctx& c, cx<double>* x, const cx<double>* b, int nrhs, const wdmg_solve_params& p, wdmg_solve_stats* st) {
+int fgcr(Ctx& c, cx<double>* x, const cx<double>* b, int nrhs, const wdmg_solve_params& p, wdmg_solve_stats* st,
+         const void* b_canon) {
   Level& L = c.lev[0];
   const size_t n = L.n;
   const size_t bs = n * nrhs;
@@ -433,7 +434,18 @@ int fgcr(Ctx& c, cx<double>* x, const cx<double>* b, int nrhs, const wdmg_solve_
   // in FP32 (z_j comes out of the V-cycle in FP32 or 16 bits anyway); x, r and
   // every restart's true residual stay FP64.
   const bool basis32 = f32 || half;
-  ensure_outer(c, k, nrhs, basis32, basis32);
+  // FP32 copies of r and z: the FP32 V-cycle's input, and the fixed output of
+  // a graph-captured V-cycle
+  ensure_outer(c, k, nrhs, f32 || (p.use_graph && basis32), basis32);
+  // in place: b in the internal layout lives in the FP32 W basis (two slots'
+  // worth) while that basis is idle, at the start and at the end of a cycle
+  if (!b && (!basis32 || k < 2 || !b_canon))
+    throw Error(WDMG_ERR_ARG, "an in-place solve needs an FP32 outer basis of at least two directions");
+  cx<double>* bslot = b ? nullptr : reinterpret_cast<cx<double>*>(c.outer_W32);
+  auto load_b = [&]() {
+    if (bslot) fine_to_internal<double, double>(c, c.g0, static_cast<const cx<double>*>(b_canon), bslot, nrhs);
+  };
+  if (bslot) b = bslot;
   if (p.precond) ensure_mg_work(c, nrhs, f32 || half ? WDMG_F32 : WDMG_F64, half ? 1 : 0);
   if (half) ensure_work_h(c, nrhs);
   HalfScope hs(c, half ? p.mg_prec : 0);
@@ -497,6 +509,7 @@ int fgcr(Ctx& c, cx<double>* x, const cx<double>* b, int nrhs, const wdmg_solve_
   constexpr double kReliable = 1e-5;
   double rstart2[kMaxRhs];
   set_scalar(c, S_ERR, 0.0, 0.0);
+  load_b();
   norm2_b(c, b, n, nrhs, G, c.dring);
   WDMG_HIP(hipStreamSynchronize(c.stream));
   double bn2[kMaxRhs], tol2[kMaxRhs], act[kMaxRhs];
@@ -628,6 +641,7 @@ int fgcr(Ctx& c, cx<double>* x, const cx<double>* b, int nrhs, const wdmg_solve_
     else
       gcr_combine<double>(c, x, c.outer_Z, c.outer_hist, c.outer_av, c.outer_y, n, nrhs, jn, k);
     dslash<double>(c, r, x, nrhs);
+    load_b();
     xmy_norm_b(c, b, r, n, nrhs, G);
     read_rn(rn2);
     bool again = false;

@@ -39,7 +39,11 @@ template <typename R>
 void ensure_work(Ctx& c, int l, int nrhs);
 void ensure_mg_work(Ctx& c, int nrhs, int prec, int first = 0);
 
-int fgcr(Ctx& c, cx<double>* x, const cx<double>* b, int nrhs, const wdmg_solve_params& p, wdmg_solve_stats* st);
+// b_canon (with b == nullptr): the right-hand sides in the caller's canonical
+// layout, converted into the idle FP32 W basis whenever the residual is
+// recomputed (in-place solves keep no internal copy of b).
+int fgcr(Ctx& c, cx<double>* x, const cx<double>* b, int nrhs, const wdmg_solve_params& p, wdmg_solve_stats* st,
+         const void* b_canon = nullptr);
 // BiCGStab from x = 0; with pc (precond set) the V-cycle of pc's precision is
 // the right preconditioner.
 int bicgstab(Ctx& c, cx<double>* x, const cx<double>* b, double tol, int maxit, wdmg_solve_stats& st,

@@ -57,7 +57,7 @@ class MgParams(ctypes.Structure):
 class SolveParams(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("maxit", ctypes.c_int),
                 ("precond", ctypes.c_int), ("mg_prec", ctypes.c_int), ("use_graph", ctypes.c_int),
-                ("outer", ctypes.c_int)]
+                ("outer", ctypes.c_int), ("in_place", ctypes.c_int)]
 
 
 class SolveStats(ctypes.Structure):
@@ -361,15 +361,23 @@ class Context:
         return x
 
     def solve(self, b: torch.Tensor, x0: torch.Tensor | None = None, *, tol=1e-10, restart=50,
-              maxit=1000, precond=True, mg_prec="f64", graph=False, outer="fgcr"):
+              maxit=1000, precond=True, mg_prec="f64", graph=False, outer="fgcr", in_place=False):
         """MG-preconditioned solve; ``outer`` is "fgcr" (flexible GCR(restart)),
         "bicgstab" (BiCGStab with the V-cycle as right preconditioner, x0 = 0),
         "cgnr" (CG on the normal equations) or "mgcg" (flexible CG on the normal
-        equations with the normal-equation V-cycle)."""
+        equations with the normal-equation V-cycle).  ``in_place``: FGCR from
+        x = 0 with the solution written over ``b`` (which is returned), no
+        internal copy of b kept; for the largest batches."""
         nrhs = self._nrhs(b, 6)
-        x = torch.zeros_like(b) if x0 is None else x0.clone()
+        if in_place:
+            if x0 is not None:
+                raise ValueError("an in-place solve starts from x = 0")
+            x = b
+        else:
+            x = torch.zeros_like(b) if x0 is None else x0.clone()
         p = SolveParams(float(tol), int(restart), int(maxit), 1 if precond else 0, PREC[mg_prec],
-                        1 if graph else 0, {"fgcr": 0, "bicgstab": 1, "cgnr": 2, "mgcg": 3}[outer])
+                        1 if graph else 0, {"fgcr": 0, "bicgstab": 1, "cgnr": 2, "mgcg": 3}[outer],
+                        1 if in_place else 0)
         stats = (SolveStats * nrhs)()
         rc = self.lib.wdmg_solve(self.h, _ptr(x, torch.complex128, "x"), _ptr(b, torch.complex128, "b"),
                                  nrhs, ctypes.byref(p), stats)

@@ -300,3 +300,40 @@ def test_setup_relaxation_in_reduced_precision(setup_prec):
     print(f"outer iterations: {iters}")
     assert iters[setup_prec] <= iters["f64"] + 2, iters
     ctx.close()
+
+
+def test_in_place_solve_equals_the_regular_solve():
+    """An in-place FGCR solve (x from zero, written over b, b read from the
+    caller's buffer at every restart) gives the regular solve's iterates: the
+    same kernels on the same values."""
+    dims = (8, 8, 8, 8)
+    seed = synthetic.gauge_seed(1, 1)
+    m = MCRIT[f"8x8x8x8_eps0.3_seed{seed}"]["m_crit"] + 0.05
+    u = synthetic.gauge_field(dims, 0.3, seed)
+    ctx = wdmg.Context(dims, DEV)
+    ctx.set_gauge(gpu(u))
+    ctx.set_mass(m)
+    v0 = synthetic.gaussian_vectors((12,) + ctx.fine_shape(), synthetic.null_seed(1))
+    ctx.mg_setup([{"block": (4, 4, 4, 4), "nv": 12, "setup_iters": 20, "vectors": gpu(v0)}], coarse_tol=1e-2)
+    b = synthetic.gaussian_spinor(dims, seed=synthetic.rhs_seed(1, 3), nrhs=4)
+    for kind in KINDS:
+        x, st = ctx.solve(gpu(b), tol=1e-10, restart=6, maxit=300, mg_prec=kind)
+        bg = gpu(b)
+        xi, sti = ctx.solve(bg, tol=1e-10, restart=6, maxit=300, mg_prec=kind, in_place=True)
+        assert xi.data_ptr() == bg.data_ptr()
+        xh, xih = x.cpu().numpy(), xi.cpu().numpy()
+        for j in range(4):
+            assert sti[j]["converged"] and sti[j]["iters"] == st[j]["iters"], (kind, j, st[j], sti[j])
+            assert np.abs(xih[j] - xh[j]).max() <= 1e-13 * np.abs(xh[j]).max(), (kind, j)
+            res = np.linalg.norm(b[j] - wilson.apply_D(u, xih[j], m)) / np.linalg.norm(b[j])
+            assert res <= 1e-10, (kind, j, res)
+    bg = gpu(b)
+    import ctypes
+    params = wdmg.SolveParams(1e-10, 6, 300, 1, wdmg.PREC["bf16"], 0, 0, 0)
+    with pytest.raises(wdmg.WdmgError) as e:  # the same buffer without in_place
+        ctx._check(ctx.lib.wdmg_solve(ctx.h, bg.data_ptr(), bg.data_ptr(), 4, ctypes.byref(params), None))
+    assert e.value.name == "WDMG_ERR_ARG" and "in_place" in str(e.value)
+    with pytest.raises(wdmg.WdmgError) as e:  # an FP64 V-cycle has no FP32 basis to hold b
+        ctx.solve(bg, tol=1e-10, restart=6, maxit=300, mg_prec="f64", in_place=True)
+    assert e.value.name == "WDMG_ERR_ARG"
+    ctx.close()
