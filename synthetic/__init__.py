@@ -13,7 +13,10 @@ Canonical layouts (host, numpy):
 
 The paper measures on Monte-Carlo gauge ensembles (Sec. 4 and 5) that are not
 available; links ``U = exp(i eps H)`` with random traceless Hermitian ``H``
-stand in for them, ``eps`` setting the roughness.
+stand in for them, ``eps`` setting the roughness.  The 2d U(1) fields of
+Sec. 4 are drawn from the compact U(1) plaquette weight itself
+(``u1_gauge_field``): building links from independently drawn plaquette
+angles is input generation, not part of the solver.
 """
 from __future__ import annotations
 
@@ -114,3 +117,50 @@ def rhs_seed(cfg: int, j: int = 0) -> int:
 
 def null_seed(cfg: int, k: int = 0) -> int:
     return 3000 * cfg + k
+
+
+def u1_gauge_field(dims2, beta: float, seed: int) -> np.ndarray:
+    """2d compact U(1) links ``U[t, x, mu] = exp(i theta_mu(x))``, ``mu`` = 0 (x),
+    1 (t), distributed with the plaquette weight ``exp(beta cos theta_P)``.
+
+    In two dimensions the plaquette angles of that weight are independent,
+    up to one global constraint on the torus, so a field is built from them:
+    in an axial gauge (t links zero except on the last time slice) the
+    x links of slice t + 1 follow from those of slice t and the plaquettes
+    between them, and the t links of the last slice follow from the
+    plaquettes of that slice; the one plaquette left closes the torus.  A
+    random gauge transformation ``theta_mu(x) += g(x) - g(x + mu)`` is
+    applied last.  Plaquette: ``theta_P(x) = theta_0(x) + theta_1(x + 0hat)
+    - theta_0(x + 1hat) - theta_1(x)``.
+
+    Draws, in this order: the x-link angles of slice 0 (``Lx`` values,
+    uniform on [-pi, pi)); the free plaquette angles (slices 0 .. Lt-2 with x
+    fastest, then x = 0 .. Lx-2 of slice Lt-1; von Mises with mean 0 and
+    concentration ``beta``); the t-link angle at (x = 0, t = Lt-1) (uniform);
+    one gauge angle per site (uniform, [t, x] order).  ``dims2 = (Lx, Lt)``.
+    """
+    lx, lt = (int(d) for d in dims2)
+    rng = np.random.default_rng(seed)
+    th0 = np.zeros((lt, lx))
+    th1 = np.zeros((lt, lx))
+    th0[0] = rng.uniform(-np.pi, np.pi, lx)
+    plaq = rng.vonmises(0.0, beta, (lt - 1) * lx + lx - 1)
+    rows, last = plaq[:(lt - 1) * lx].reshape(lt - 1, lx), plaq[(lt - 1) * lx:]
+    for t in range(lt - 1):
+        th0[t + 1] = th0[t] - rows[t]
+    a = th0[lt - 1] - th0[0]
+    th1[lt - 1, 0] = rng.uniform(-np.pi, np.pi)
+    for x in range(lx - 1):
+        th1[lt - 1, x + 1] = th1[lt - 1, x] + last[x] - a[x]
+    g = rng.uniform(-np.pi, np.pi, (lt, lx))
+    th0 = th0 + g - np.roll(g, -1, axis=1)
+    th1 = th1 + g - np.roll(g, -1, axis=0)
+    return np.exp(1j * np.stack([th0, th1], axis=-1))
+
+
+def gaussian_spinor_2d(dims2, seed: int, nrhs: int | None = None) -> np.ndarray:
+    """Complex Gaussian 2d fermion field(s) ``[t, x, 2]`` (or ``[nrhs, t, x, 2]``):
+    all real parts first, then all imaginary parts, each N(0,1)."""
+    lx, lt = (int(d) for d in dims2)
+    shp = (lt, lx, 2) if nrhs is None else (int(nrhs), lt, lx, 2)
+    return gaussian_vectors(shp, seed)
