@@ -253,6 +253,11 @@ def parse(argv=None):
                     help="start with a plain 1 GiB device copy (the reference for hardware byte counters)")
     ap.add_argument("--only-dslash", type=int, default=0, metavar="L",
                     help="only time Dslash on L^4 plus a plain 1 GiB device copy, then exit")
+    ap.add_argument("--qed2d", action="store_true",
+                    help="the 2d U(1) comparison of Sec. 4 instead of the 4d step (128^2, beta 6)")
+    ap.add_argument("--qed2d-deltas", type=float, nargs="+", default=[0.1, 0.03, 0.01, 0.003],
+                    help="m - m_crit of the 2d masses")
+    ap.add_argument("--qed2d-rhs", type=int, default=1, help="rhs per launch of the timed 2d Wilson launch")
     ap.add_argument("--traffic-entry", nargs=5, metavar=("FETCH_CSV", "WRITE_CSV", "BENCH_JSON", "KERNEL", "COMMAND"),
                     help="no GPU work: turn two rocprofv3 --pmc runs of this benchmark (FETCH_SIZE, then "
                          "WRITE_SIZE, each started with --copy-calibration) and the JSON line of the first into "
@@ -388,6 +393,92 @@ def only_dslash(L, reps=10):
     res = {"copy_1GiB": copy_calibration(torch, dev),
            "dslash": dslash_bandwidth(wdmg, synthetic, torch, dev, L, reps=reps)}
     print(json.dumps(res), flush=True)
+
+
+# The 2d U(1) workload (Sec. 4): 128^2 lattice, compact U(1) links at beta = 6
+# (seed 7000, the stored m_crit), right-hand side seed 7100, candidate seeds
+# 7200 (fine) and 7201 (level 1).  Bytes of one FP64 2d Wilson application per
+# site: spinor in and out (2 x 32 B) and the site's two links (32 B).
+QED2D_BYTES_PER_SITE = 96
+QED2D_FLOPS_PER_SITE = 8 * 18
+
+
+def qed2d_bench(a):
+    """Sec. 4 comparison on one GPU: for each mass m_crit + delta, CG, MG-CG and
+    MG-BiCGstab to ||b - D x|| / ||b|| <= 1e-10; Wilson products, operator flops,
+    setup and solve seconds; one JSON line."""
+    import torch
+
+    import synthetic
+    from paper_0811_4331_amd import qed2d
+
+    dev = torch.device("cuda:0")
+    with open(os.path.join(ROOT, "tests", "golden", "mcrit_2d.json")) as fh:
+        e = json.load(fh)["128x128_beta6.0_seed7000"]
+    dims = tuple(e["dims"])
+    lx, lt = dims
+    u = torch.from_numpy(synthetic.u1_gauge_field(dims, e["beta"], e["gauge_seed"])).to(dev)
+    b = torch.from_numpy(synthetic.gaussian_spinor_2d(dims, 7100)).to(dev)
+    ctx = qed2d.Context2d(dims, dev)
+    ctx.set_gauge(u, -1)
+    configs = [  # (name, method, nvs, coarse cycles)
+        ("CG", "cg", None, 1),
+        ("MG-CG Nv=8, V-cycle", "mg-cg", [8, 8], 1),
+        ("MG-CG Nv=8/16, 4 level-1 cycles", "mg-cg", [8, 16], 4),
+        ("MG-BiCGstab Nv=3, V-cycle", "mg-bicgstab", [3, 3], 1),
+        ("MG-BiCGstab Nv=8, V-cycle", "mg-bicgstab", [8, 8], 1),
+        ("MG-BiCGstab Nv=8/16, 4 level-1 cycles", "mg-bicgstab", [8, 16], 4),
+    ]
+    rows = []
+    for delta in a.qed2d_deltas:
+        m = e["m_crit"] + delta
+        ctx.set_mass(m)
+        for name, method, nvs, cyc in configs:
+            setup_s = 0.0
+            if nvs:
+                vecs = [torch.from_numpy(synthetic.gaussian_vectors((nvs[0], lt, lx, 2, 1), 7200)).to(dev),
+                        torch.from_numpy(synthetic.gaussian_vectors((nvs[1], lt // 4, lx // 4, 2, nvs[0]),
+                                                                    7201)).to(dev)]
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ctx.mg_setup(nvs, vecs, setup_iters=100, normal=(method == "mg-cg"), coarse_cycles=cyc)
+                torch.cuda.synchronize()
+                setup_s = time.perf_counter() - t0
+            ctx.solve(b, method=method, tol=1e-10, maxit=50000)  # warm-up
+            x, st = ctx.solve(b, method=method, tol=1e-10, maxit=50000)
+            r = b - ctx.apply_D(x)
+            res = float(torch.linalg.vector_norm(r) / torch.linalg.vector_norm(b))
+            rows.append({"delta": delta, "solver": name, "iters": st["iters"], "wilson": st["wilson"],
+                         "operator_gflop": st["flops"] / 1e9, "setup_s": setup_s, "solve_s": st["seconds"],
+                         "true_res": res, "converged": bool(st["converged"] and res <= 1e-10)})
+            print(json.dumps({"progress": rows[-1]}), flush=True)
+    # the 2d Wilson launch on its own (HIP events on the context's stream)
+    reps = 2000
+    bb = b.reshape(1, lt, lx, 2).repeat(a.qed2d_rhs, 1, 1, 1).contiguous()
+    ctx.apply_D(bb)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        ctx.apply_D(bb)
+    ev1.record()
+    torch.cuda.synchronize()
+    us = ev0.elapsed_time(ev1) * 1e3 / reps
+    site_rhs = lx * lt * a.qed2d_rhs
+    gbs = (lx * lt * 32 + site_rhs * 64) / (us * 1e-6) / 1e9
+    ctx.close()
+    best = next(r for r in rows if r["delta"] == min(a.qed2d_deltas) and r["solver"] == configs[-1][0])
+    cg = next(r for r in rows if r["delta"] == best["delta"] and r["solver"] == "CG")
+    line = {"metric": "2d U(1) time-to-solution @ rel.res 1e-10 (s/RHS, setup included); Wilson products",
+            "value": best["setup_s"] + best["solve_s"], "unit": "s/RHS", "n_gpus": 1, "higher_is_better": False,
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"2d U(1) {lx}x{lt}, beta {e['beta']}, m = m_crit + {best['delta']}",
+                       "solver": best["solver"], "m_crit": e["m_crit"]},
+            "wilson_products": {"mg": best["wilson"], "cg": cg["wilson"], "ratio": cg["wilson"] / best["wilson"]},
+            "cg_s": cg["solve_s"],
+            "wilson_launch": {"rhs": a.qed2d_rhs, "us": us, "GB_s": gbs, "frac_hbm_peak": gbs / HBM_PEAK_GBS,
+                              "bytes_model": "links 32 B per site once, spinor in and out 64 B per site and rhs"},
+            "rows": rows}
+    print(json.dumps(line), flush=True)
 
 
 def precision_report(ctx, torch, synthetic, dims):
@@ -581,6 +672,9 @@ def main(argv=None):
         sys.exit(2)
     if a.only_dslash:
         only_dslash(a.only_dslash)
+        return
+    if a.qed2d:
+        qed2d_bench(a)
         return
     import torch
 

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libwdmg.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["layout.hip", "half.hip", "dslash.hip", "blas.hip", "transfer.hip", "coarse.hip", "normal.hip", "solver.cpp",
+SOURCES = ["layout.hip", "half.hip", "dslash.hip", "blas.hip", "transfer.hip", "coarse.hip", "normal.hip", "qed2d.hip", "solver.cpp",
            "abi.cpp"]
 ARCH = "gfx950"
 

@@ -104,10 +104,15 @@ def _torch_allocator(alloc_fn, delete_fn, dev_index, stream):
 _LIB = None
 
 
+HEADERS = [HEADER, os.path.join(os.path.dirname(HERE), "include", "wdmg_2d.h")]
+
+
 def header_symbols() -> list[str]:
-    """Entry points declared in include/wdmg.h."""
-    with open(HEADER) as fh:
-        text = fh.read()
+    """Entry points declared in include/wdmg.h and include/wdmg_2d.h."""
+    text = ""
+    for path in HEADERS:
+        with open(path) as fh:
+            text += fh.read()
     return sorted(set(re.findall(r"\b(wdmg_[a-z_A-Z0-9]+)\s*\(", text)))
 
 

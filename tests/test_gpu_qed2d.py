@@ -1,0 +1,181 @@
+"""GPU parity of the 2d U(1) workload (Sec. 4) against the oracle, through the C ABI."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import synthetic
+from oracle import qed2d as O
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEV = "cuda:0"
+
+
+def _ctx(dims, u, m, t_bc=-1):
+    from paper_0811_4331_amd import qed2d
+    c = qed2d.Context2d(dims, DEV)
+    c.set_gauge(torch.from_numpy(u).to(DEV), t_bc)
+    c.set_mass(m)
+    return c
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.mark.parametrize("dims,t_bc,nrhs", [((128, 128), -1, 3), ((12, 20), 1, 1), ((6, 4), -1, 2)])
+def test_wilson_operator_and_its_adjoint(dims, t_bc, nrhs):
+    u = synthetic.u1_gauge_field(dims, 6.0, seed=100)
+    m = -0.05
+    psi = synthetic.gaussian_spinor_2d(dims, seed=101, nrhs=nrhs)
+    c = _ctx(dims, u, m, t_bc)
+    d = torch.from_numpy(psi).to(DEV)
+    got = c.apply_D(d).cpu().numpy()
+    want = O.apply_D(u, psi, m, float(t_bc))
+    # every entry is a sum of at most 9 products of unit-modulus links and O(1) values
+    assert np.abs(got - want).max() <= 1e-14 * np.abs(want).max() * 10
+    got = c.apply_D(d, dagger=True).cpu().numpy()
+    want = O.apply_Ddag(u, psi, m, float(t_bc))
+    assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max()
+    c.close()
+
+
+def _setup_pair(dims, m, nvs, normal, setup_iters, seeds, block=(4, 4), cycles=1):
+    u = synthetic.u1_gauge_field(dims, 6.0, seed=200)
+    lx, lt = dims
+    vecs, shapes = [], []
+    lt_l, lx_l, n = lt, lx, 1
+    for nv, sd in zip(nvs, seeds):
+        vecs.append(synthetic.gaussian_vectors((nv, lt_l, lx_l, 2, n), sd))
+        lt_l, lx_l, n = lt_l // block[1], lx_l // block[0], nv
+    c = _ctx(dims, u, m)
+    c.mg_setup(nvs, [torch.from_numpy(v).to(DEV) for v in vecs], block=block, setup_iters=setup_iters,
+               normal=normal, coarse_cycles=cycles)
+    h = O.build(u, m, -1.0, nvs=nvs, block=block, setup_iters=setup_iters, seeds=seeds, normal=normal,
+                coarse_cycles=[cycles, 1])
+    return u, c, h
+
+
+@pytest.mark.parametrize("normal,cycles", [(False, 1), (True, 1), (False, 4), (True, 3)])
+def test_setup_matches_the_oracle_level_by_level(normal, cycles):
+    dims, m = (48, 48), -0.03
+    nvs = [4, 4] if normal else [3, 3]
+    u, c, h = _setup_pair(dims, m, nvs, normal, setup_iters=20, seeds=[301, 302], cycles=cycles)
+    offs = O.OFFSETS_NORMAL if normal else O.OFFSETS_DIRECT
+    cdims = [(12, 12), (3, 3)]
+    for l in range(2):
+        q = c.get_prolongator(l).cpu().numpy()
+        qo = h.qs[l].reshape(q.shape)
+        # Q after 20 MR steps and a QR: rounding of both sides, amplified by the
+        # conditioning of the candidate blocks
+        assert np.abs(q - qo).max() <= 1e-9, (l, np.abs(q - qo).max())
+        B = c.get_coarse_operator(l + 1).cpu().numpy()
+        Bo = O.stencil_blocks(h.mats[l], cdims[l], nvs[l], offs)
+        assert np.abs(B - Bo).max() <= 1e-9 * np.abs(Bo).max(), (l, np.abs(B - Bo).max())
+    # transfer and coarse operators on the library's own P and blocks, element by element
+    q0 = c.get_prolongator(0).cpu().numpy()
+    f = synthetic.gaussian_spinor_2d(dims, seed=303, nrhs=2)
+    rc = c.restrict(0, torch.from_numpy(f).to(DEV)).cpu().numpy()
+    P0 = O.prolongator_matrix(O.as_level(q0), (4, 4))
+    want = (P0.conj().T @ f.reshape(2, -1).T).T.reshape(rc.shape)
+    assert np.abs(rc - want).max() <= 1e-13 * np.abs(want).max()
+    cc = synthetic.gaussian_vectors((2, 12, 12, 2, nvs[0]), seed=304)
+    pf = c.prolong(0, torch.from_numpy(cc).to(DEV)).cpu().numpy()
+    want = (P0 @ cc.reshape(2, -1).T).T.reshape(pf.shape)
+    assert np.abs(pf - want).max() <= 1e-13 * np.abs(want).max()
+    B1 = c.get_coarse_operator(1).cpu().numpy()
+    got = c.apply_coarse(1, torch.from_numpy(cc).to(DEV)).cpu().numpy()
+    want = np.zeros_like(cc)
+    for o, (dx, dt) in enumerate(offs):
+        nb = np.roll(np.roll(cc, -dt, axis=1), -dx, axis=2).reshape(2, 12, 12, -1)
+        want += np.einsum("tsij,rtsj->rtsi", B1[o], nb).reshape(cc.shape)
+    assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max()
+    # one V-cycle from the same residual
+    r = synthetic.gaussian_spinor_2d(dims, seed=305)
+    x = c.vcycle(torch.from_numpy(r).to(DEV)).cpu().numpy()
+    xo = h.vcycle(0, O.as_level(r[..., None])).reshape(r.shape)
+    assert _rel(x, xo) <= 1e-9, _rel(x, xo)
+    c.close()
+
+
+@pytest.mark.parametrize("method", ["mg-bicgstab", "mg-cg", "cg"])
+def test_solvers_converge_like_the_oracle(method):
+    dims, m = (48, 48), -0.03
+    normal = method == "mg-cg"
+    nvs = [4, 4] if normal else [3, 3]
+    u, c, h = _setup_pair(dims, m, nvs, normal, setup_iters=30, seeds=[311, 312])
+    b = synthetic.gaussian_spinor_2d(dims, seed=313)
+    x, st = c.solve(torch.from_numpy(b).to(DEV), method=method, tol=1e-10, maxit=5000)
+    x = x.cpu().numpy()
+    res = np.linalg.norm(b - O.apply_D(u, x, m, -1.0)) / np.linalg.norm(b)
+    assert st["converged"] and res <= 1e-10, (st, res)
+    if method == "mg-bicgstab":
+        xo, info = O.mg_bicgstab(h, b, 1e-10)
+    elif method == "mg-cg":
+        xo, info = O.mg_cg(h, b, 1e-10)
+    else:
+        xo, info = O.cgnr(u, m, -1.0, b, 1e-10)
+    # the same iteration: counts differ only through rounding order, which a
+    # few hundred CG steps with one kept direction amplify to a few percent
+    assert abs(st["iters"] - info["iters"]) <= max(2, info["iters"] // 10), (st["iters"], info["iters"])
+    # both residuals are <= 1e-10; the solutions then agree to cond(D) 1e-10
+    assert _rel(x, xo) <= 1e-7
+    c.close()
+
+
+def test_the_papers_workload_at_full_size():
+    # 128^2, beta = 6, m = m_crit + 0.01: both hierarchies, every solver,
+    # true residuals recomputed by the oracle
+    with open(os.path.join(HERE, "golden", "mcrit_2d.json")) as fh:
+        e = json.load(fh)["128x128_beta6.0_seed7000"]
+    dims = tuple(e["dims"])
+    u = synthetic.u1_gauge_field(dims, e["beta"], e["gauge_seed"])
+    m = e["m_crit"] + 0.01
+    b = synthetic.gaussian_spinor_2d(dims, seed=7100)
+    c = _ctx(dims, u, m)
+    bt = torch.from_numpy(b).to(DEV)
+    iters = {}
+    for method, nvs, normal in (("mg-bicgstab", [8, 16], False), ("mg-cg", [8, 16], True), ("cg", None, False)):
+        if nvs:
+            vecs = [synthetic.gaussian_vectors((8, 128, 128, 2, 1), 7200), synthetic.gaussian_vectors(
+                (16, 32, 32, 2, 8), 7201)]
+            c.mg_setup(nvs, [torch.from_numpy(v).to(DEV) for v in vecs], setup_iters=100, normal=normal,
+                       coarse_cycles=4)
+        x, st = c.solve(bt, method=method, tol=1e-10, maxit=20000)
+        res = np.linalg.norm(b - O.apply_D(u, x.cpu().numpy(), m, -1.0)) / np.linalg.norm(b)
+        assert st["converged"] and res <= 1e-10, (method, st, res)
+        iters[method] = st["wilson"]
+    # multigrid on D removes an order of magnitude of CG's Wilson products (Sec. 4)
+    assert iters["mg-bicgstab"] * 10 < iters["cg"], iters
+    c.close()
+
+
+def test_error_paths():
+    from paper_0811_4331_amd import qed2d, wdmg
+    u = synthetic.u1_gauge_field((16, 16), 6.0, seed=1)
+    c = _ctx((16, 16), u, 0.1)
+    b = torch.from_numpy(synthetic.gaussian_spinor_2d((16, 16), seed=2)).to(DEV)
+    with pytest.raises(wdmg.WdmgError) as e:
+        c.solve(b, method="mg-bicgstab")
+    assert e.value.name == "WDMG_ERR_NOT_SETUP"
+    v = [torch.from_numpy(synthetic.gaussian_vectors((2, 16, 16, 2, 1), 3)).to(DEV),
+         torch.from_numpy(synthetic.gaussian_vectors((2, 4, 4, 2, 2), 4)).to(DEV)]
+    with pytest.raises(wdmg.WdmgError) as e:  # 16 -> 4 -> 1: coarse extent below 3
+        c.mg_setup([2, 2], v)
+    assert e.value.name == "WDMG_ERR_DIMS"
+    z = [torch.zeros((2, 16, 16, 2, 1), dtype=torch.complex128, device=DEV)]
+    with pytest.raises(wdmg.WdmgError) as e:
+        c.mg_setup([2], z, setup_iters=0)
+    assert e.value.name == "WDMG_ERR_RANK_DEFICIENT"
+    # a working two-level hierarchy after the failures
+    c.mg_setup([2], v[:1], setup_iters=10)
+    x, st = c.solve(b, method="mg-bicgstab", tol=1e-10)
+    assert st["converged"]
+    with pytest.raises(wdmg.WdmgError) as e:
+        c.solve(b, method="mg-cg")
+    assert e.value.name == "WDMG_ERR_NOT_SETUP"
+    c.close()
+    del qed2d
