@@ -57,6 +57,8 @@ __constant__ int c_off[2][kMaxOff] = {{0, 1, -1, 0, 0, 1, -1, 1, -1}, {0, 0, 0, 
 
 // Device scalar slots.
 enum { S_RHO = 0, S_ALPHA, S_OMEGA, S_BETA, S_PQ, S_RR, S_FLAG, S_MR, S_TOTAL = S_MR + 64 };
+// Workgroups of one reduction per rhs, and rhs of one reduction launch.
+constexpr int kMaxDotGroups = 128, kMaxDotRhs = 64;
 
 __device__ __forceinline__ C neg(C a) { return mk(-a.re, -a.im); }
 __device__ __forceinline__ C cdiv(C a, C b) {
@@ -157,6 +159,38 @@ __global__ void __launch_bounds__(256) k_stencil(C* __restrict__ out, const C* _
   out[gid] = acc;
 }
 
+// The same stencil for N = 8, 16 or 32 dof per site: 64 / N rows of one
+// site per wavefront, lane (row, j) multiplying B[o](s)[i][j] by in(s + d_o)[j],
+// so that a wavefront reads 64 consecutive block entries per offset; the
+// N lanes of a row are summed with cross-lane adds.
+template <int N>
+__global__ void __launch_bounds__(256) k_stencil_w(C* __restrict__ out, const C* __restrict__ in,
+                                                   const C* __restrict__ B, int lx, int lt, int S, int nrhs) {
+  static_assert(N >= 8 && N <= 64 && (N & (N - 1)) == 0, "N must be a power of two in 8..64");
+  constexpr int R = 64 / N;  // rows per wavefront
+  constexpr int W = N / R;   // wavefronts per site
+  const int vol = lx * lt;
+  const size_t wave = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (wave >= (size_t)nrhs * vol * W) return;
+  const int grp = (int)(wave % W);
+  const size_t rest = wave / W;
+  const int s = (int)(rest % vol), r = (int)(rest / vol);
+  const int i = grp * R + lane / N, j = lane % N;
+  const int x = s % lx, t = s / lx;
+  C acc = mk(0.0, 0.0);
+  for (int o = 0; o < S; ++o) {
+    const int xn = (x + c_off[0][o] + lx) % lx, tn = (t + c_off[1][o] + lt) % lt;
+    cmadd(acc, B[(((size_t)o * vol + s) * N + i) * N + j], in[((size_t)r * vol + tn * lx + xn) * N + j]);
+  }
+#pragma unroll
+  for (int h = N / 2; h > 0; h >>= 1) {
+    acc.re += __shfl_xor(acc.re, h, 64);
+    acc.im += __shfl_xor(acc.im, h, 64);
+  }
+  if (j == 0) out[((size_t)r * vol + s) * N + i] = acc;
+}
+
 // Restriction P^dagger: out(sc, chi, k) = sum_{s in aggregate} sum_i conj(Q_k(s)_{chi,i}) in(s)_{chi,i}.
 __global__ void __launch_bounds__(256) k_restrict(C* __restrict__ out, const C* __restrict__ in,
                                                   const C* __restrict__ Q, int lx, int lt, int bx, int bt,
@@ -178,6 +212,36 @@ __global__ void __launch_bounds__(256) k_restrict(C* __restrict__ out, const C* 
       for (int i = 0; i < n; ++i) cmaddc(acc, q[i], f[i]);
     }
   out[gid] = acc;
+}
+
+// The same restriction with one lane per site of the aggregate (A = bx * bt
+// lanes per output, A a power of two <= 64): lane a adds the n products of
+// site a, and the A lanes of an output are summed with cross-lane adds.
+template <int A>
+__global__ void __launch_bounds__(256) k_restrict_w(C* __restrict__ out, const C* __restrict__ in,
+                                                    const C* __restrict__ Q, int lx, int lt, int bx, int n, int nv,
+                                                    int nrhs) {
+  const int bt = A / bx;
+  const int vol = lx * lt, lxc = lx / bx, volc = vol / A;
+  const size_t item = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) / A;  // output index
+  const int a = threadIdx.x % A;
+  if (item >= (size_t)nrhs * volc * 2 * nv) return;
+  const int k = (int)(item % nv);
+  const int chi = (int)((item / nv) % 2);
+  const int sc = (int)((item / (2 * nv)) % volc);
+  const int r = (int)(item / ((size_t)2 * nv * volc));
+  const int xc = sc % lxc, tc = sc / lxc;
+  const int s = (tc * bt + a / bx) * lx + xc * bx + a % bx;
+  const C* q = Q + (((size_t)k * vol + s) * 2 + chi) * n;
+  const C* f = in + (((size_t)r * vol + s) * 2 + chi) * n;
+  C acc = mk(0.0, 0.0);
+  for (int i = 0; i < n; ++i) cmaddc(acc, q[i], f[i]);
+#pragma unroll
+  for (int h = A / 2; h > 0; h >>= 1) {
+    acc.re += __shfl_xor(acc.re, h, 64);
+    acc.im += __shfl_xor(acc.im, h, 64);
+  }
+  if (a == 0) out[item] = acc;
 }
 
 // Prolongation P: out(s)_{chi,i} = sum_k Q_k(s)_{chi,i} in(aggregate(s), chi, k).
@@ -399,25 +463,11 @@ enum {
   M_FCG_ALPHA     // <p,q>, <p,r>:  pq = <p,q>, alpha = <p,r> / pq
 };
 
+// The coefficient logic of the solvers, from the summed dot products.
 template <int MODE>
-__global__ void __launch_bounds__(1024) k_dots(const C* __restrict__ a0, const C* __restrict__ b0,
-                                               const C* __restrict__ a1, const C* __restrict__ b1, size_t n,
-                                               C* __restrict__ sc, double omega) {
-  __shared__ double lds[4 * 16];
-  constexpr bool two = MODE == M_MR || MODE == M_OMEGA || MODE == M_FCG_ALPHA;
-  const size_t off = (size_t)blockIdx.x * n;
-  C d0 = mk(0.0, 0.0), d1 = mk(0.0, 0.0);
-  for (size_t e = threadIdx.x; e < n; e += blockDim.x) {
-    cmaddc(d0, a0[off + e], b0[off + e]);
-    if (two) cmaddc(d1, a1[off + e], b1[off + e]);
-  }
-  double v[4] = {d0.re, d0.im, d1.re, d1.im};
-  wdmg::block_sum<4>(v, lds);
-  if (threadIdx.x != 0) return;
-  d0 = mk(v[0], v[1]);
-  d1 = mk(v[2], v[3]);
+__device__ void finish_dots(C d0, C d1, int rhs, C* sc, double omega) {
   if (MODE == M_MR) {
-    sc[S_MR + blockIdx.x] = d0.re == 0.0 ? mk(0.0, 0.0) : (omega / d0.re) * d1;
+    sc[S_MR + rhs] = d0.re == 0.0 ? mk(0.0, 0.0) : (omega / d0.re) * d1;
   } else if (MODE == M_NORM) {
     sc[S_RR] = mk(d0.re, 0.0);
   } else if (MODE == M_RHO) {
@@ -443,6 +493,70 @@ __global__ void __launch_bounds__(1024) k_dots(const C* __restrict__ a0, const C
     sc[S_PQ] = d0;
     sc[S_ALPHA] = cdiv(d1, d0);
   }
+}
+
+// One or two dot products per rhs over gridDim.x workgroups (grid y = rhs):
+// each workgroup stores its partial sums [rhs][group][4]; the consumer (the
+// next launch) adds them.  Kernel boundaries order the two, so no fence or
+// atomic is needed inside the reduction.
+template <int MODE>
+__global__ void __launch_bounds__(256) k_dots(const C* __restrict__ a0, const C* __restrict__ b0,
+                                              const C* __restrict__ a1, const C* __restrict__ b1, size_t n,
+                                              double* __restrict__ part) {
+  __shared__ double lds[4 * 4];
+  constexpr bool two = MODE == M_MR || MODE == M_OMEGA || MODE == M_FCG_ALPHA;
+  const int G = gridDim.x, g = blockIdx.x, rhs = blockIdx.y;
+  const size_t off = (size_t)rhs * n;
+  C d0 = mk(0.0, 0.0), d1 = mk(0.0, 0.0);
+  for (size_t e = (size_t)g * blockDim.x + threadIdx.x; e < n; e += (size_t)G * blockDim.x) {
+    cmaddc(d0, a0[off + e], b0[off + e]);
+    if (two) cmaddc(d1, a1[off + e], b1[off + e]);
+  }
+  double v[4] = {d0.re, d0.im, d1.re, d1.im};
+  wdmg::block_sum<4>(v, lds);
+  if (threadIdx.x == 0) {
+    double* p = part + ((size_t)rhs * G + g) * 4;
+    for (int q = 0; q < 4; ++q) p[q] = v[q];
+  }
+}
+
+// The partials of one rhs summed by one wavefront (lane k adds workgroups k
+// and k + 64, G <= 128, then a fixed cross-lane tree).  Every lane of the
+// wavefront must call it.
+__device__ __forceinline__ void sum_partials(const double* __restrict__ part, int rhs, int G, double t[4]) {
+  const int lane = threadIdx.x & 63;
+  const double* p = part + (size_t)rhs * G * 4;
+  for (int q = 0; q < 4; ++q) {
+    t[q] = lane < G ? p[lane * 4 + q] : 0.0;
+    if (lane + 64 < G) t[q] += p[(lane + 64) * 4 + q];
+    t[q] = wdmg::wave_sum(t[q]);
+  }
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(64) k_finish(const double* __restrict__ part, int G, C* __restrict__ sc,
+                                               double omega) {
+  double t[4];
+  sum_partials(part, blockIdx.x, G, t);
+  if (threadIdx.x == 0) finish_dots<MODE>(mk(t[0], t[1]), mk(t[2], t[3]), blockIdx.x, sc, omega);
+}
+
+// The MR step (and the minimal-residual step after a prolongation) in one
+// launch: every wavefront sums the partials of <p,p> and <p,r> of its rhs,
+// c = omega <p,r> / <p,p> (0 when <p,p> = 0), then x += c dx, r -= c dr.
+// Needs n % 64 == 0, so that a wavefront never spans two right-hand sides.
+__global__ void __launch_bounds__(256) k_update_mr(C* __restrict__ x, C* r, const C* dx, const C* __restrict__ dr,
+                                                   const double* __restrict__ part, int G, double omega, size_t n,
+                                                   int nrhs) {
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if ((gid & ~(size_t)63) >= n * nrhs) return;  // whole wavefronts
+  const int rhs = (int)(gid / n);
+  double t[4];
+  sum_partials(part, rhs, G, t);
+  const C c = t[0] == 0.0 ? mk(0.0, 0.0) : (omega / t[0]) * mk(t[2], t[3]);
+  const C d = dx[gid];
+  x[gid] = x[gid] + c * d;
+  r[gid] = r[gid] - c * dr[gid];
 }
 
 // x += c dx; r -= c dr with c = coefficient slot `slot + rhs` (fields of n elements).
@@ -542,6 +656,7 @@ struct wdmg_2d_ctx {
   C* sc = nullptr;               // device scalars
   C* hsc = nullptr;              // pinned host copy of the scalars
   int* status = nullptr;
+  double* part = nullptr;        // reduction partials [rhs][group][4]
   C* tmp = nullptr;              // fine work for D^dagger D
   size_t tmp_fields = 0;
   std::vector<C*> sol;           // solver fields (fine, one rhs)
@@ -656,7 +771,15 @@ void apply_level(Ctx& c, int l, C* out, const C* in, int nrhs) {
   const Lev2& L = c.lev[l];
   const int N = 2 * L.n;
   const size_t tot = (size_t)nrhs * L.vol * N;
-  k_stencil<<<blocks_for(tot, 256), 256, 0, c.stream>>>(out, in, L.B, L.lx, L.lt, N, L.S, nrhs);
+  const size_t lanes = tot * N;
+  if (N == 8)
+    k_stencil_w<8><<<blocks_for(lanes, 256), 256, 0, c.stream>>>(out, in, L.B, L.lx, L.lt, L.S, nrhs);
+  else if (N == 16)
+    k_stencil_w<16><<<blocks_for(lanes, 256), 256, 0, c.stream>>>(out, in, L.B, L.lx, L.lt, L.S, nrhs);
+  else if (N == 32)
+    k_stencil_w<32><<<blocks_for(lanes, 256), 256, 0, c.stream>>>(out, in, L.B, L.lx, L.lt, L.S, nrhs);
+  else
+    k_stencil<<<blocks_for(tot, 256), 256, 0, c.stream>>>(out, in, L.B, L.lx, L.lt, N, L.S, nrhs);
   launch_check();
   c.capp[l] += nrhs;
   c.flops += 8.0 * L.S * (double)L.vol * N * N * nrhs;
@@ -665,7 +788,16 @@ void apply_level(Ctx& c, int l, C* out, const C* in, int nrhs) {
 void restrict_to(Ctx& c, int l, C* out, const C* in, int nrhs, const int blk[2]) {
   const Lev2& L = c.lev[l];
   const size_t tot = (size_t)nrhs * (L.vol / (blk[0] * blk[1])) * 2 * L.nv;
-  k_restrict<<<blocks_for(tot, 256), 256, 0, c.stream>>>(out, in, L.Q, L.lx, L.lt, blk[0], blk[1], L.n, L.nv, nrhs);
+  const int A = blk[0] * blk[1];
+  if (A == 16)
+    k_restrict_w<16><<<blocks_for(tot * 16, 256), 256, 0, c.stream>>>(out, in, L.Q, L.lx, L.lt, blk[0], L.n, L.nv,
+                                                                      nrhs);
+  else if (A == 4)
+    k_restrict_w<4><<<blocks_for(tot * 4, 256), 256, 0, c.stream>>>(out, in, L.Q, L.lx, L.lt, blk[0], L.n, L.nv,
+                                                                    nrhs);
+  else
+    k_restrict<<<blocks_for(tot, 256), 256, 0, c.stream>>>(out, in, L.Q, L.lx, L.lt, blk[0], blk[1], L.n, L.nv,
+                                                           nrhs);
   launch_check();
   c.flops += 8.0 * (double)L.vol * 2 * L.n * L.nv * nrhs;
 }
@@ -678,9 +810,30 @@ void prolong_from(Ctx& c, int l, C* out, const C* in, int nrhs, const int blk[2]
   c.flops += 8.0 * (double)L.vol * 2 * L.n * L.nv * nrhs;
 }
 
+// about two elements per thread, at most kMaxDotGroups workgroups
+int dot_groups(size_t n) { return (int)std::min<size_t>(kMaxDotGroups, std::max<size_t>(1, (n + 511) / 512)); }
+
+// dot products and the coefficient logic of MODE, coefficients left in sc
 template <int MODE>
 void dots(Ctx& c, const C* a0, const C* b0, const C* a1, const C* b1, size_t n, int nrhs, double omega = 1.0) {
-  k_dots<MODE><<<nrhs, 1024, 0, c.stream>>>(a0, b0, a1, b1, n, c.sc, omega);
+  const int G = dot_groups(n);
+  k_dots<MODE><<<dim3(G, nrhs), 256, 0, c.stream>>>(a0, b0, a1, b1, n, c.part);
+  k_finish<MODE><<<nrhs, 64, 0, c.stream>>>(c.part, G, c.sc, omega);
+  launch_check();
+}
+
+// One MR step's coefficient and update: c = omega <p,r>/<p,p> per rhs, then
+// x += c dx, r -= c dr (dx = r, dr = p for the smoother; the prolonged
+// correction and its image for the minimal-residual step).
+void mr_update(Ctx& c, C* x, C* r, const C* dx, const C* dr, const C* p, size_t n, int nrhs, double omega) {
+  const int G = dot_groups(n);
+  k_dots<M_MR><<<dim3(G, nrhs), 256, 0, c.stream>>>(p, p, p, r, n, c.part);
+  if (n % 64 == 0) {
+    k_update_mr<<<blocks_for(n * nrhs, 256), 256, 0, c.stream>>>(x, r, dx, dr, c.part, G, omega, n, nrhs);
+  } else {
+    k_finish<M_MR><<<nrhs, 64, 0, c.stream>>>(c.part, G, c.sc, omega);
+    k_update<<<blocks_for(n * nrhs, 256), 256, 0, c.stream>>>(x, r, dx, dr, c.sc, S_MR, n, nrhs);
+  }
   launch_check();
 }
 
@@ -725,8 +878,7 @@ void vcycle(Ctx& c, int l, C* x, const C* r) {
   auto mr_steps = [&](int k) {
     for (int i = 0; i < k; ++i) {
       apply_level(c, l, L.T, L.R, 1);
-      dots<M_MR>(c, L.T, L.T, L.T, L.R, L.nf, 1, c.omega);
-      update(c, x, L.R, L.R, L.T, L.nf, 1);
+      mr_update(c, x, L.R, L.R, L.T, L.T, L.nf, 1, c.omega);
     }
   };
   mr_steps(c.nu_pre);
@@ -759,12 +911,12 @@ void vcycle(Ctx& c, int l, C* x, const C* r) {
   prolong_from(c, l, L.Y, Cc.X, 1, blk);
   apply_level(c, l, L.T, L.Y, 1);
   if (c.use_alpha)
-    dots<M_MR>(c, L.T, L.T, L.T, L.R, L.nf, 1, 1.0);
+    mr_update(c, x, L.R, L.Y, L.T, L.T, L.nf, 1, 1.0);
   else {
     k_set<<<1, 1, 0, c.stream>>>(c.sc, S_MR, 1.0);
     launch_check();
+    update(c, x, L.R, L.Y, L.T, L.nf, 1);
   }
-  update(c, x, L.R, L.Y, L.T, L.nf, 1);
   mr_steps(c.nu_post);
 }
 
@@ -832,8 +984,7 @@ void mg_setup(Ctx& c, const wdmg_2d_mg_params& p) {
         launch_check();
         for (int it = 0; it < p.setup_iters; ++it) {
           apply_level(c, l, T, R, nv);
-          dots<M_MR>(c, T, T, T, R, L.nf, nv, c.omega);
-          update(c, L.Q, R, R, T, L.nf, nv);
+          mr_update(c, L.Q, R, R, T, T, L.nf, nv, c.omega);
         }
       }
       Q2_HIP(hipMemsetAsync(c.status, 0, sizeof(int), c.stream));
@@ -1061,6 +1212,8 @@ int wdmg_2d_create(wdmg_2d_ctx** out, const int dims[2], const wdmg_alloc* alloc
     cc.U = calloc_fields(cc, (size_t)cc.lx * cc.lt * 2, cc.bufs);
     cc.sc = calloc_fields(cc, S_TOTAL, cc.bufs);
     cc.status = static_cast<int*>(dalloc(cc, 256, cc.bufs));
+    cc.part = static_cast<double*>(dalloc(cc, (size_t)kMaxDotRhs * kMaxDotGroups * 4 * sizeof(double), cc.bufs));
+
     Q2_HIP(hipHostMalloc(reinterpret_cast<void**>(&cc.hsc), S_TOTAL * sizeof(C), hipHostMallocDefault));
     Q2_HIP(hipMemsetAsync(cc.sc, 0, S_TOTAL * sizeof(C), cc.stream));
     return (int)WDMG_OK;

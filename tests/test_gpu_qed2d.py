@@ -59,13 +59,17 @@ def _setup_pair(dims, m, nvs, normal, setup_iters, seeds, block=(4, 4), cycles=1
     return u, c, h
 
 
-@pytest.mark.parametrize("normal,cycles", [(False, 1), (True, 1), (False, 4), (True, 3)])
-def test_setup_matches_the_oracle_level_by_level(normal, cycles):
-    dims, m = (48, 48), -0.03
-    nvs = [4, 4] if normal else [3, 3]
-    u, c, h = _setup_pair(dims, m, nvs, normal, setup_iters=20, seeds=[301, 302], cycles=cycles)
+@pytest.mark.parametrize("normal,cycles,nvs,block", [
+    (False, 1, [3, 3], (4, 4)), (True, 1, [4, 4], (4, 4)), (False, 4, [3, 3], (4, 4)), (True, 3, [4, 4], (4, 4)),
+    (False, 2, [8, 16], (4, 4)), (True, 1, [8, 16], (4, 4)), (False, 1, [2, 3], (2, 2)), (True, 1, [3, 3], (4, 2))])
+def test_setup_matches_the_oracle_level_by_level(normal, cycles, nvs, block):
+    # 2 Nv = 6 runs the thread-per-row stencil, 8, 16 and 32 the wavefront one;
+    # 2 x 2 and 4 x 4 aggregates the lane-per-site restriction, 4 x 2 the other
+    dims, m = {(4, 4): (48, 48), (2, 2): (24, 24), (4, 2): (48, 24)}[block], -0.03
+    u, c, h = _setup_pair(dims, m, nvs, normal, setup_iters=20, seeds=[301, 302], cycles=cycles, block=block)
     offs = O.OFFSETS_NORMAL if normal else O.OFFSETS_DIRECT
-    cdims = [(12, 12), (3, 3)]
+    c1 = (dims[1] // block[1], dims[0] // block[0])
+    cdims = [(c1[1], c1[0]), (c1[1] // block[0], c1[0] // block[1])]  # (x, t) extents per coarse level
     for l in range(2):
         q = c.get_prolongator(l).cpu().numpy()
         qo = h.qs[l].reshape(q.shape)
@@ -79,20 +83,22 @@ def test_setup_matches_the_oracle_level_by_level(normal, cycles):
     q0 = c.get_prolongator(0).cpu().numpy()
     f = synthetic.gaussian_spinor_2d(dims, seed=303, nrhs=2)
     rc = c.restrict(0, torch.from_numpy(f).to(DEV)).cpu().numpy()
-    P0 = O.prolongator_matrix(O.as_level(q0), (4, 4))
+    P0 = O.prolongator_matrix(O.as_level(q0), block)
     want = (P0.conj().T @ f.reshape(2, -1).T).T.reshape(rc.shape)
     assert np.abs(rc - want).max() <= 1e-13 * np.abs(want).max()
-    cc = synthetic.gaussian_vectors((2, 12, 12, 2, nvs[0]), seed=304)
+    cc = synthetic.gaussian_vectors((2, c1[0], c1[1], 2, nvs[0]), seed=304)
     pf = c.prolong(0, torch.from_numpy(cc).to(DEV)).cpu().numpy()
     want = (P0 @ cc.reshape(2, -1).T).T.reshape(pf.shape)
     assert np.abs(pf - want).max() <= 1e-13 * np.abs(want).max()
-    B1 = c.get_coarse_operator(1).cpu().numpy()
-    got = c.apply_coarse(1, torch.from_numpy(cc).to(DEV)).cpu().numpy()
-    want = np.zeros_like(cc)
-    for o, (dx, dt) in enumerate(offs):
-        nb = np.roll(np.roll(cc, -dt, axis=1), -dx, axis=2).reshape(2, 12, 12, -1)
-        want += np.einsum("tsij,rtsj->rtsi", B1[o], nb).reshape(cc.shape)
-    assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max()
+    for lev, (cx_, ct), n in ((1, cdims[0], nvs[0]), (2, cdims[1], nvs[1])):
+        cv = synthetic.gaussian_vectors((2, ct, cx_, 2, n), seed=304 + lev)
+        B1 = c.get_coarse_operator(lev).cpu().numpy()
+        got = c.apply_coarse(lev, torch.from_numpy(cv).to(DEV)).cpu().numpy()
+        want = np.zeros_like(cv)
+        for o, (dx, dt) in enumerate(offs):
+            nb = np.roll(np.roll(cv, -dt, axis=1), -dx, axis=2).reshape(2, ct, cx_, -1)
+            want += np.einsum("tsij,rtsj->rtsi", B1[o], nb).reshape(cv.shape)
+        assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max(), lev
     # one V-cycle from the same residual
     r = synthetic.gaussian_spinor_2d(dims, seed=305)
     x = c.vcycle(torch.from_numpy(r).to(DEV)).cpu().numpy()
