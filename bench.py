@@ -452,6 +452,22 @@ def qed2d_bench(a):
                          "operator_gflop": st["flops"] / 1e9, "setup_s": setup_s, "solve_s": st["seconds"],
                          "true_res": res, "converged": bool(st["converged"] and res <= 1e-10)})
             print(json.dumps({"progress": rows[-1]}), flush=True)
+    # roofline of the level-1 stencil of the last hierarchy (MG-BiCGstab, 2Nv = 16, 5 offsets): it
+    # reads its blocks once per application (HIP events on the context's stream)
+    lt1, lx1, n1 = ctx.levels[1]
+    N1, S1 = 2 * n1, (9 if ctx.normal else 5)
+    v1 = torch.from_numpy(synthetic.gaussian_vectors((lt1, lx1, 2, n1), 7300)).to(dev)
+    ctx.apply_coarse(1, v1)
+    st_reps = 500
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(st_reps):
+        ctx.apply_coarse(1, v1)
+    ev1.record()
+    torch.cuda.synchronize()
+    st_us = ev0.elapsed_time(ev1) * 1e3 / st_reps
+    st_bytes = (S1 * N1 * N1 + 2 * N1) * lx1 * lt1 * 16
+    st_gbs = st_bytes / (st_us * 1e-6) / 1e9
     # the 2d Wilson launch on its own (HIP events on the context's stream)
     reps = 2000
     bb = b.reshape(1, lt, lx, 2).repeat(a.qed2d_rhs, 1, 1, 1).contiguous()
@@ -477,8 +493,36 @@ def qed2d_bench(a):
             "cg_s": cg["solve_s"],
             "wilson_launch": {"rhs": a.qed2d_rhs, "us": us, "GB_s": gbs, "frac_hbm_peak": gbs / HBM_PEAK_GBS,
                               "bytes_model": "links 32 B per site once, spinor in and out 64 B per site and rhs"},
+            "roofline": {"kernel": f"k_stencil_w<{N1}> (level-1 stencil, {S1} offsets)", "bound": "hbm",
+                         "achieved": st_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": st_gbs / HBM_PEAK_GBS,
+                         "traffic": None, "us_per_launch": st_us, "bytes_per_launch": st_bytes,
+                         "bytes_model": "S (2Nv)^2 block entries and two coarse vectors per coarse site, 16 B each"},
             "rows": rows}
+    if not a.no_cpu_baseline:
+        line["cpu_baseline"] = qed2d_cpu_baseline(e, 0.01)
     print(json.dumps(line), flush=True)
+
+
+def qed2d_cpu_baseline(e, delta):
+    """The oracle's MG-BiCGstab (Nv 8 then 16, four level-1 cycles, 100 MR setup
+    steps) on the same 128^2 field at m_crit + delta, setup and solve, timed on
+    the host."""
+    import torch
+
+    import synthetic
+    from oracle import qed2d as O
+    dims = tuple(e["dims"])
+    u = synthetic.u1_gauge_field(dims, e["beta"], e["gauge_seed"])
+    b = synthetic.gaussian_spinor_2d(dims, 7100)
+    m = e["m_crit"] + delta
+    t0 = time.perf_counter()
+    h = O.build(u, m, -1.0, nvs=[8, 16], block=(4, 4), setup_iters=100, seeds=[7200, 7201], coarse_cycles=[4, 1])
+    t1 = time.perf_counter()
+    _, info = O.mg_bicgstab(h, b, 1e-10)
+    t2 = time.perf_counter()
+    return {"value": t2 - t0, "unit": "s/RHS", "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": f"one rhs at m_crit + {delta}, setup {t1 - t0:.1f} s and solve {t2 - t1:.1f} s, "
+                      f"{info['iters']} iterations, {O.wilson_products(h)} Wilson products"}
 
 
 def precision_report(ctx, torch, synthetic, dims):
