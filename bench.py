@@ -258,6 +258,7 @@ def parse(argv=None):
     ap.add_argument("--qed2d-deltas", type=float, nargs="+", default=[0.1, 0.03, 0.01, 0.003],
                     help="m - m_crit of the 2d masses")
     ap.add_argument("--qed2d-rhs", type=int, default=1, help="rhs per launch of the timed 2d Wilson launch")
+    ap.add_argument("--qed2d-setup-iters", type=int, default=300, help="MR setup steps per coarsening (2d)")
     ap.add_argument("--traffic-entry", nargs=5, metavar=("FETCH_CSV", "WRITE_CSV", "BENCH_JSON", "KERNEL", "COMMAND"),
                     help="no GPU work: turn two rocprofv3 --pmc runs of this benchmark (FETCH_SIZE, then "
                          "WRITE_SIZE, each started with --copy-calibration) and the JSON line of the first into "
@@ -441,7 +442,8 @@ def qed2d_bench(a):
                                                                     7201)).to(dev)]
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                ctx.mg_setup(nvs, vecs, setup_iters=100, normal=(method == "mg-cg"), coarse_cycles=cyc)
+                ctx.mg_setup(nvs, vecs, setup_iters=a.qed2d_setup_iters, normal=(method == "mg-cg"),
+                             coarse_cycles=cyc)
                 torch.cuda.synchronize()
                 setup_s = time.perf_counter() - t0
             ctx.solve(b, method=method, tol=1e-10, maxit=50000)  # warm-up
@@ -488,7 +490,7 @@ def qed2d_bench(a):
             "value": best["setup_s"] + best["solve_s"], "unit": "s/RHS", "n_gpus": 1, "higher_is_better": False,
             "vs_baseline": None, "dtype": "f64", "data": "synthetic",
             "config": {"workload": f"2d U(1) {lx}x{lt}, beta {e['beta']}, m = m_crit + {best['delta']}",
-                       "solver": best["solver"], "m_crit": e["m_crit"]},
+                       "solver": best["solver"], "m_crit": e["m_crit"], "setup_iters": a.qed2d_setup_iters},
             "wilson_products": {"mg": best["wilson"], "cg": cg["wilson"], "ratio": cg["wilson"] / best["wilson"]},
             "cg_s": cg["solve_s"],
             "wilson_launch": {"rhs": a.qed2d_rhs, "us": us, "GB_s": gbs, "frac_hbm_peak": gbs / HBM_PEAK_GBS,
@@ -499,14 +501,14 @@ def qed2d_bench(a):
                          "bytes_model": "S (2Nv)^2 block entries and two coarse vectors per coarse site, 16 B each"},
             "rows": rows}
     if not a.no_cpu_baseline:
-        line["cpu_baseline"] = qed2d_cpu_baseline(e, 0.01)
+        line["cpu_baseline"] = qed2d_cpu_baseline(e, 0.01, a.qed2d_setup_iters)
     print(json.dumps(line), flush=True)
 
 
-def qed2d_cpu_baseline(e, delta):
-    """The oracle's MG-BiCGstab (Nv 8 then 16, four level-1 cycles, 100 MR setup
-    steps) on the same 128^2 field at m_crit + delta, setup and solve, timed on
-    the host."""
+def qed2d_cpu_baseline(e, delta, setup_iters):
+    """The oracle's MG-BiCGstab (Nv 8 then 16, four level-1 cycles, the
+    benchmark's MR setup steps) on the same 128^2 field at m_crit + delta, setup
+    and solve, timed on the host."""
     import torch
 
     import synthetic
@@ -516,7 +518,8 @@ def qed2d_cpu_baseline(e, delta):
     b = synthetic.gaussian_spinor_2d(dims, 7100)
     m = e["m_crit"] + delta
     t0 = time.perf_counter()
-    h = O.build(u, m, -1.0, nvs=[8, 16], block=(4, 4), setup_iters=100, seeds=[7200, 7201], coarse_cycles=[4, 1])
+    h = O.build(u, m, -1.0, nvs=[8, 16], block=(4, 4), setup_iters=setup_iters, seeds=[7200, 7201],
+                coarse_cycles=[4, 1])
     t1 = time.perf_counter()
     _, info = O.mg_bicgstab(h, b, 1e-10)
     t2 = time.perf_counter()
