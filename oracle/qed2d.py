@@ -36,6 +36,10 @@ and the cycle of ``oracle.mg`` apply unchanged, with blocks ``(b_x, b_t, 1, 1)``
 * ``build``: candidates relaxed on ``A v = 0`` by MR from Gaussian starts
   (Sec. 2), block QR per chirality, Galerkin operators; ``mg_bicgstab``,
   ``mg_cg`` and ``cgnr`` are the three solvers of the comparison.
+* ``build(..., blocking=1 or 2)``: the negative control of the Sec. 3
+  footnote on two levels: both spins in one block per aggregate, restricted
+  with ``P^dagger gamma5`` (left null vectors through gamma5; ill-defined for
+  the free-field constant) or with ``P^dagger``.
 
 Readings (the paper is silent): the 2d operator, gamma matrices and boundary
 conditions above; the number of relaxation steps of the setup and the
@@ -150,20 +154,21 @@ def block4(block2):
 
 def prolongator_matrix(q, block2):
     """P as a sparse matrix from the block-orthonormal columns ``q`` of
-    ``transfer.block_orthonormalize`` (``[Nv, 1, 1, t, x, 2, n]``): row index
-    ``((t * Lx + x) * 2 + chi) * n + i``, column index
-    ``((tc * Lxc + xc) * 2 + chi) * Nv + k``."""
+    ``transfer.block_orthonormalize`` (``[Nv, 1, 1, t, x, g, n]`` with g = 2
+    chirality groups, or g = 1 when the spin is blocked): row index
+    ``((t * Lx + x) * g + chi) * n + i``, column index
+    ``((tc * Lxc + xc) * g + chi) * Nv + k``."""
     nv = q.shape[0]
-    lt, lx, _, n = q.shape[-4:]
+    lt, lx, g, n = q.shape[-4:]
     bx, bt = block2
     lxc = lx // bx
-    t, x, chi, i, k = np.meshgrid(np.arange(lt), np.arange(lx), np.arange(2), np.arange(n), np.arange(nv),
+    t, x, chi, i, k = np.meshgrid(np.arange(lt), np.arange(lx), np.arange(g), np.arange(n), np.arange(nv),
                                   indexing="ij")
-    rows = ((t * lx + x) * 2 + chi) * n + i
-    cols = (((t // bt) * lxc + x // bx) * 2 + chi) * nv + k
-    vals = q.reshape(nv, lt, lx, 2, n)[k, t, x, chi, i]
-    ncoarse = (lt // bt) * lxc * 2 * nv
-    return sp.csr_matrix((vals.ravel(), (rows.ravel(), cols.ravel())), shape=(lt * lx * 2 * n, ncoarse))
+    rows = ((t * lx + x) * g + chi) * n + i
+    cols = (((t // bt) * lxc + x // bx) * g + chi) * nv + k
+    vals = q.reshape(nv, lt, lx, g, n)[k, t, x, chi, i]
+    ncoarse = (lt // bt) * lxc * g * nv
+    return sp.csr_matrix((vals.ravel(), (rows.ravel(), cols.ravel())), shape=(lt * lx * g * n, ncoarse))
 
 
 def galerkin(A, P):
@@ -172,12 +177,12 @@ def galerkin(A, P):
 
 
 class SparseLevel:
-    """A level operator held as a sparse matrix over fields ``[..., 1, 1, t, x, 2, n]``."""
+    """A level operator held as a sparse matrix over fields ``[..., 1, 1, t, x, g, n]``."""
 
-    def __init__(self, M, site_shape, n):
+    def __init__(self, M, site_shape, n, groups=2):
         self.M = M.tocsr()
         self.site_shape = tuple(site_shape)  # (1, 1, t, x)
-        self.dof = (2, n)
+        self.dof = (groups, n)
 
     def apply(self, f):
         lead = f.shape[:-6]
@@ -213,13 +218,15 @@ def stencil_blocks(M, dims2, n, offsets):
 # ---------------------------------------------------------------------------
 # Levels and hierarchy
 class Wilson2d:
-    """The fine operator D on level fields ``[..., 1, 1, t, x, 2, 1]``."""
+    """The fine operator D on level fields ``[..., 1, 1, t, x, 2, 1]`` (the two
+    spins as two chirality groups), or ``[..., 1, 1, t, x, 1, 2]`` when the
+    spin is blocked (one group of both spins)."""
 
-    def __init__(self, u, m, t_bc=-1.0):
+    def __init__(self, u, m, t_bc=-1.0, dof=(2, 1)):
         self.u, self.m, self.t_bc = u, float(m), float(t_bc)
         lt, lx = u.shape[:2]
         self.site_shape = (1, 1, lt, lx)
-        self.dof = (2, 1)
+        self.dof = tuple(dof)
 
     def _spinor(self, f):
         return f.reshape(f.shape[:-6] + self.site_shape[2:] + (2,))
@@ -243,51 +250,73 @@ class Normal2d(Wilson2d):
 
 class Hierarchy2d(mg.Hierarchy):
     """``oracle.mg.Hierarchy`` with the coarsest level solved by LU (Sec. 4:
-    machine precision on the coarsest lattice) and plain V-cycles."""
+    machine precision on the coarsest lattice) and plain V-cycles.  With
+    ``gamma5_restriction`` the fine-level restriction is ``P^dagger gamma5``
+    (Sec. 3: left null vectors from right ones through gamma5), as the
+    footnote's spin-blocked variant uses it."""
 
-    def __init__(self, ops, qs, blocks, **kw):
+    def __init__(self, ops, qs, blocks, gamma5_restriction=False, **kw):
         kw.setdefault("coarse_cycles", [1] * (len(ops) - 1))
         super().__init__(ops, qs, blocks, **kw)
+        self.gamma5_restriction = gamma5_restriction
         self.lu = sla.lu_factor(ops[-1].M.toarray())
+
+    def correction(self, l, r):
+        if l == 0 and self.gamma5_restriction:
+            r = apply_gamma5(r.reshape(r.shape[:-2] + (2,))).reshape(r.shape)
+        return super().correction(l, r)
 
     def coarsest_solve(self, rc):
         self.counts[-1] += 1
         return sla.lu_solve(self.lu, rc.reshape(-1)).reshape(rc.shape)
 
 
-def build(u, m, t_bc, *, nvs, block=(4, 4), setup_iters=100, seeds=None, null_vectors=None, normal=False, **kw):
+def build(u, m, t_bc, *, nvs, block=(4, 4), setup_iters=100, seeds=None, null_vectors=None, normal=False,
+          blocking=0, **kw):
     """Hierarchy for D (``normal=False``, MG-BiCGstab) or for ``D^dagger D``
     (``normal=True``, MG-CG): per coarsening, ``nvs[l]`` candidates relaxed
     with ``setup_iters`` MR steps on ``A_l v = 0`` from Gaussian starts
     (``seeds[l]``) or given (``null_vectors[l]``, level-field shaped
-    ``[Nv, t, x, 2, n]``), block QR on ``block`` aggregates, Galerkin operator."""
+    ``[Nv, t, x, 2, n]``), block QR on ``block`` aggregates, Galerkin operator.
+
+    ``blocking`` (two levels of D only): 0 keeps chirality intact (Sec. 3);
+    1 blocks both spins into one block per aggregate and restricts with
+    ``P^dagger gamma5`` (the variant of the Sec. 3 footnote, coarse operator
+    ``P^dagger gamma5 D P``); 2 blocks the spins and restricts with ``P^dagger``."""
     from synthetic import gaussian_vectors
 
-    fine = Normal2d(u, m, t_bc) if normal else Wilson2d(u, m, t_bc)
+    if blocking and (normal or len(nvs) != 1):
+        raise ValueError("spin blocking is built for two-level hierarchies of D")
+    fine = Normal2d(u, m, t_bc) if normal else Wilson2d(u, m, t_bc, dof=(1, 2) if blocking else (2, 1))
     lt, lx = u.shape[:2]
     A = sparse_D(u, m, t_bc)
     if normal:
         A = (sparse_gamma5(lt * lx) @ A @ sparse_gamma5(lt * lx) @ A).tocsr()
     ops, qs, blocks, mats = [fine], [], [], []
     dims2, n = (lx, lt), 1
+    groups = 1 if blocking else 2
     for l, nv in enumerate(nvs):
         op = ops[-1]
         shape = (nv, dims2[1], dims2[0], 2, n)
+        lshape = (nv, 1, 1, dims2[1], dims2[0]) + op.dof
         if null_vectors is not None and null_vectors[l] is not None:
-            vecs = as_level(null_vectors[l])
+            vecs = null_vectors[l].reshape(lshape)
         else:
-            v0 = as_level(gaussian_vectors(shape, seeds[l]))
+            v0 = gaussian_vectors(shape, seeds[l]).reshape(lshape)
             vecs = mg.relax_null_vectors(op.apply, v0, setup_iters, kw.get("omega", 0.8))
         q, _ = transfer.block_orthonormalize(vecs, block4(block))
         P = prolongator_matrix(q, block)
-        A = galerkin(A, P)
+        if blocking == 1:
+            A = (P.conj().T @ sparse_gamma5(lt * lx) @ A @ P).tocsr()
+        else:
+            A = galerkin(A, P)
         dims2 = (dims2[0] // block[0], dims2[1] // block[1])
         n = nv
         qs.append(q)
         blocks.append(block4(block))
         mats.append(A)
-        ops.append(SparseLevel(A, (1, 1, dims2[1], dims2[0]), n))
-    h = Hierarchy2d(ops, qs, blocks, **kw)
+        ops.append(SparseLevel(A, (1, 1, dims2[1], dims2[0]), n, groups))
+    h = Hierarchy2d(ops, qs, blocks, gamma5_restriction=blocking == 1, **kw)
     h.mats = mats
     return h
 
@@ -301,7 +330,7 @@ def wilson_products(h: mg.Hierarchy) -> int:
 def mg_bicgstab(h, b, tol, maxit=10000):
     """MG-BiCGstab (Sec. 4): BiCGstab on ``D x = b`` with the V-cycle of the
     direct hierarchy as right preconditioner.  ``b``: ``[t, x, 2]``."""
-    bl = as_level(b.reshape(b.shape[-3:] + (1,)))
+    bl = b.reshape((1, 1) + b.shape[-3:-1] + h.ops[0].dof)
     x, info = mg.bicgstab(lambda f: h._apply(0, f), bl, tol, maxit=maxit, precond=lambda r: h.vcycle(0, r))
     return x.reshape(b.shape), info
 

@@ -173,3 +173,48 @@ def test_stored_mcrit_values_come_from_the_stored_recipe():
     u = synthetic.u1_gauge_field(tuple(e["dims"]), e["beta"], e["gauge_seed"])
     mc, _, _ = qed2d.mcrit(u, ncv=40)
     assert abs(mc - e["m_crit"]) < 1e-9
+
+
+def test_spin_blocking_footnote_in_2d():
+    # Sec. 3 footnote: blocking the spin makes P^dagger gamma5 P vanish for the
+    # free-field constant, so the correction through gamma5 has no inverse;
+    # keeping chirality (or restricting with P^dagger) keeps the mode's eigenvalue m
+    lx, lt, m = 16, 12, 0.05
+    D = qed2d.sparse_D(_free(lx, lt), m, 1.0)
+    G = qed2d.sparse_gamma5(lx * lt)
+    q, _ = transfer.block_orthonormalize(np.ones((1, 1, 1, lt, lx, 1, 2), dtype=np.complex128), (4, 4, 1, 1))
+    P = qed2d.prolongator_matrix(q, (4, 4))
+    assert abs((P.conj().T @ G @ P).toarray()).max() < 1e-15
+    c = np.ones(P.shape[1])
+    Dc_g5 = P.conj().T @ G @ D @ P
+    assert np.linalg.norm(Dc_g5 @ c) < 1e-14 * np.linalg.norm(c) and abs(Dc_g5).max() > 0.1
+    np.testing.assert_allclose((P.conj().T @ D @ P) @ c, m * c, atol=1e-14)
+    # chirality kept: P^dagger gamma5 P is the coarse gamma5, and the constant keeps m
+    qc, _ = transfer.block_orthonormalize(qed2d.as_level(_const_candidates(lx, lt)), (4, 4, 1, 1))
+    Pc = qed2d.prolongator_matrix(qc, (4, 4))
+    g5c = np.tile([1.0, -1.0], Pc.shape[1] // 2)
+    np.testing.assert_allclose((Pc.conj().T @ G @ Pc).toarray(), np.diag(g5c), atol=1e-14)
+    cc = np.ones(Pc.shape[1])
+    np.testing.assert_allclose((Pc.conj().T @ G @ D @ Pc) @ cc, m * g5c, atol=1e-14)
+
+
+def test_spin_blocked_hierarchies():
+    # on a beta = 6 field the spin-blocked P with R = P^dagger is a well-defined
+    # Galerkin method reaching the direct solution; with R = P^dagger gamma5 its
+    # coarse operator is far worse conditioned and the solve needs more iterations
+    lx = lt = 32
+    u = synthetic.u1_gauge_field((lx, lt), 6.0, seed=10)
+    b = synthetic.gaussian_spinor_2d((lx, lt), seed=11)
+    exact = spla.spsolve(qed2d.sparse_D(u, 0.05, -1.0).tocsc(), b.ravel()).reshape(b.shape)
+    its, conds = {}, {}
+    for blk, nv in ((0, 4), (2, 8), (1, 8)):
+        h = qed2d.build(u, 0.05, -1.0, nvs=[nv], block=(4, 4), setup_iters=50, seeds=[12], blocking=blk)
+        sv = np.linalg.svd(h.mats[0].toarray(), compute_uv=False)
+        conds[blk] = sv[0] / sv[-1]
+        x, info = qed2d.mg_bicgstab(h, b, 1e-10, maxit=2000)
+        assert info["converged"]
+        np.testing.assert_allclose(x, exact, atol=1e-8 * np.abs(exact).max())
+        its[blk] = info["iters"]
+    assert conds[1] > 10 * conds[2] and its[1] > 2 * max(its[0], its[2]), (conds, its)
+    with pytest.raises(ValueError):
+        qed2d.build(u, 0.05, -1.0, nvs=[4, 4], block=(4, 4), setup_iters=5, seeds=[1, 2], blocking=1)
