@@ -456,9 +456,9 @@ def qed2d_bench(a):
             print(json.dumps({"progress": rows[-1]}), flush=True)
     # roofline of the level-1 stencil of the last hierarchy (MG-BiCGstab, 2Nv = 16, 5 offsets): it
     # reads its blocks once per application (HIP events on the context's stream)
-    lt1, lx1, n1 = ctx.levels[1]
-    N1, S1 = 2 * n1, (9 if ctx.normal else 5)
-    v1 = torch.from_numpy(synthetic.gaussian_vectors((lt1, lx1, 2, n1), 7300)).to(dev)
+    lt1, lx1, g1, n1 = ctx.levels[1]
+    N1, S1 = g1 * n1, (9 if ctx.normal else 5)
+    v1 = torch.from_numpy(synthetic.gaussian_vectors((lt1, lx1, g1, n1), 7300)).to(dev)
     ctx.apply_coarse(1, v1)
     st_reps = 500
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

@@ -21,11 +21,12 @@
  * Canonical layouts (x fastest, complex interleaved re/im):
  *   links        : [T][X][mu=2] complex128, U_mu(x) of modulus 1;
  *   fine field   : [nrhs][T][X][spin=2];
- *   level-l field: [nrhs][Tl][Xl][chirality=2][n_l], n_0 = 1, n_l = Nv_{l-1};
- *   prolongator of coarsening l: [Nv][Tl][Xl][2][n_l], the block-orthonormal
- *     columns: column (aggregate, chi, k) is entry k restricted to the
- *     aggregate and chirality chi;
- *   coarse operator of level l >= 1: S blocks per site (S = 5 for D_c: offsets
+ *   level-l field: [nrhs][Tl][Xl][chirality=2][n_l], n_0 = 1, n_l = Nv_{l-1}
+ *     (with spin blocking: [nrhs][Tl][Xl][1][n_l], n_0 = 2);
+ *   prolongator of coarsening l: [Nv][Tl][Xl][g][n_l] (g = 2, or 1 with spin
+ *     blocking), the block-orthonormal columns: column (aggregate, chi, k) is
+ *     entry k restricted to the aggregate and group chi;
+ *   coarse operator of level l >= 1: S blocks of (g n_l)^2 per site (S = 5 for D_c: offsets
  *     (0,0), (+1,0), (-1,0), (0,+1), (0,-1) in (x, t); S = 9 for the normal
  *     operator: those and (+1,+1), (-1,+1), (+1,-1), (-1,-1)),
  *     (A_c c)(xhat) = sum_o B_o(xhat) c(xhat + d_o), periodic coarse indexing.
@@ -62,6 +63,13 @@ typedef struct {
                               levels): 1 is the V-cycle of Sec. 4; k > 1 runs
                               e <- e + M_1 (r_c - A_1 e) k times from e = 0, the
                               modified cycle of Sec. 5 (k = 4 there), 1..64          */
+  int blocking;            /* 0: chirality kept intact (Sec. 3), the method.  The
+                              negative control of the Sec. 3 footnote, two levels of D
+                              only (else WDMG_ERR_ARG): both spins in one block per
+                              aggregate (coarse dof per site Nv, level-1 fields
+                              [Tl][Xl][1][Nv]), restricted with 1: P^dagger gamma5
+                              (coarse operator P^dagger gamma5 D P, singular for the
+                              free-field constant) or 2: P^dagger                   */
 } wdmg_2d_mg_params;
 
 typedef struct {
@@ -127,7 +135,8 @@ int wdmg_2d_vcycle(wdmg_2d_ctx* ctx, void* x, const void* r);
  *             of the normal hierarchy (Sec. 3, Sec. 4);
  *   method 2: CG on D^dagger D x = D^dagger b (the CG of Sec. 4), no hierarchy.
  * The CG methods drive the normal residual to 1e-2 tol ||b|| and then check the
- * true residual.  x and b must not overlap.  stats may be NULL. */
+ * true residual.  x and b must not overlap.  stats may be NULL.  A b holding
+ * NaN or Inf, or a residual turning NaN, ends the solve with WDMG_ERR_NAN. */
 int wdmg_2d_solve(wdmg_2d_ctx* ctx, void* x, const void* b, int method, double tol, int maxit,
                   wdmg_2d_stats* stats);
 

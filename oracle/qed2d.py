@@ -191,13 +191,13 @@ class SparseLevel:
         return out.reshape(lead + self.site_shape + self.dof)
 
 
-def stencil_blocks(M, dims2, n, offsets):
-    """The blocks ``B[o][t, x, 2n, 2n]`` of a coarse operator with
-    ``(M c)(xhat) = sum_o B[o](xhat) c(xhat + d_o)`` (periodic coarse
+def stencil_blocks(M, dims2, n, offsets, groups=2):
+    """The blocks ``B[o][t, x, g n, g n]`` (g = ``groups``) of a coarse operator
+    with ``(M c)(xhat) = sum_o B[o](xhat) c(xhat + d_o)`` (periodic coarse
     indexing), read off the sparse matrix; every entry of M must lie on one
     of the offsets (checked)."""
     lx, lt = dims2
-    nn = 2 * n
+    nn = groups * n
     B = np.zeros((len(offsets), lt, lx, nn, nn), dtype=np.complex128)
     C = M.tocoo()
     rs, cs = C.row // nn, C.col // nn

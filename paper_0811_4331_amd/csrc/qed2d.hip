@@ -191,25 +191,28 @@ __global__ void __launch_bounds__(256) k_stencil_w(C* __restrict__ out, const C*
   if (j == 0) out[((size_t)r * vol + s) * N + i] = acc;
 }
 
-// Restriction P^dagger: out(sc, chi, k) = sum_{s in aggregate} sum_i conj(Q_k(s)_{chi,i}) in(s)_{chi,i}.
+// Restriction P^dagger: out(sc, chi, k) = sum_{s in aggregate} sum_i conj(Q_k(s)_{chi,i}) in(s)_{chi,i}
+// over g groups per site (g = 2 chiralities; g = 1 when the spin is blocked).
+// With g5 (fine level only, where a site holds the two spins as its
+// components chi * n + i) the restriction is P^dagger gamma5.
 __global__ void __launch_bounds__(256) k_restrict(C* __restrict__ out, const C* __restrict__ in,
                                                   const C* __restrict__ Q, int lx, int lt, int bx, int bt,
-                                                  int n, int nv, int nrhs) {
+                                                  int g, int n, int nv, int g5, int nrhs) {
   const int vol = lx * lt, lxc = lx / bx, volc = vol / (bx * bt);
   const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= (size_t)nrhs * volc * 2 * nv) return;
+  if (gid >= (size_t)nrhs * volc * g * nv) return;
   const int k = (int)(gid % nv);
-  const int chi = (int)((gid / nv) % 2);
-  const int sc = (int)((gid / (2 * nv)) % volc);
-  const int r = (int)(gid / ((size_t)2 * nv * volc));
+  const int chi = (int)((gid / nv) % g);
+  const int sc = (int)((gid / ((size_t)g * nv)) % volc);
+  const int r = (int)(gid / ((size_t)g * nv * volc));
   const int xc = sc % lxc, tc = sc / lxc;
   C acc = mk(0.0, 0.0);
   for (int dt = 0; dt < bt; ++dt)
     for (int dx = 0; dx < bx; ++dx) {
       const int s = (tc * bt + dt) * lx + xc * bx + dx;
-      const C* q = Q + (((size_t)k * vol + s) * 2 + chi) * n;
-      const C* f = in + (((size_t)r * vol + s) * 2 + chi) * n;
-      for (int i = 0; i < n; ++i) cmaddc(acc, q[i], f[i]);
+      const C* q = Q + (((size_t)k * vol + s) * g + chi) * n;
+      const C* f = in + (((size_t)r * vol + s) * g + chi) * n;
+      for (int i = 0; i < n; ++i) cmaddc(acc, q[i], (g5 && chi * n + i == 1) ? neg(f[i]) : f[i]);
     }
   out[gid] = acc;
 }
@@ -219,23 +222,23 @@ __global__ void __launch_bounds__(256) k_restrict(C* __restrict__ out, const C* 
 // site a, and the A lanes of an output are summed with cross-lane adds.
 template <int A>
 __global__ void __launch_bounds__(256) k_restrict_w(C* __restrict__ out, const C* __restrict__ in,
-                                                    const C* __restrict__ Q, int lx, int lt, int bx, int n, int nv,
-                                                    int nrhs) {
+                                                    const C* __restrict__ Q, int lx, int lt, int bx, int g, int n,
+                                                    int nv, int g5, int nrhs) {
   const int bt = A / bx;
   const int vol = lx * lt, lxc = lx / bx, volc = vol / A;
   const size_t item = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) / A;  // output index
   const int a = threadIdx.x % A;
-  if (item >= (size_t)nrhs * volc * 2 * nv) return;
+  if (item >= (size_t)nrhs * volc * g * nv) return;
   const int k = (int)(item % nv);
-  const int chi = (int)((item / nv) % 2);
-  const int sc = (int)((item / (2 * nv)) % volc);
-  const int r = (int)(item / ((size_t)2 * nv * volc));
+  const int chi = (int)((item / nv) % g);
+  const int sc = (int)((item / ((size_t)g * nv)) % volc);
+  const int r = (int)(item / ((size_t)g * nv * volc));
   const int xc = sc % lxc, tc = sc / lxc;
   const int s = (tc * bt + a / bx) * lx + xc * bx + a % bx;
-  const C* q = Q + (((size_t)k * vol + s) * 2 + chi) * n;
-  const C* f = in + (((size_t)r * vol + s) * 2 + chi) * n;
+  const C* q = Q + (((size_t)k * vol + s) * g + chi) * n;
+  const C* f = in + (((size_t)r * vol + s) * g + chi) * n;
   C acc = mk(0.0, 0.0);
-  for (int i = 0; i < n; ++i) cmaddc(acc, q[i], f[i]);
+  for (int i = 0; i < n; ++i) cmaddc(acc, q[i], (g5 && chi * n + i == 1) ? neg(f[i]) : f[i]);
 #pragma unroll
   for (int h = A / 2; h > 0; h >>= 1) {
     acc.re += __shfl_xor(acc.re, h, 64);
@@ -247,39 +250,39 @@ __global__ void __launch_bounds__(256) k_restrict_w(C* __restrict__ out, const C
 // Prolongation P: out(s)_{chi,i} = sum_k Q_k(s)_{chi,i} in(aggregate(s), chi, k).
 __global__ void __launch_bounds__(256) k_prolong(C* __restrict__ out, const C* __restrict__ in,
                                                  const C* __restrict__ Q, int lx, int lt, int bx, int bt,
-                                                 int n, int nv, int nrhs) {
+                                                 int g, int n, int nv, int nrhs) {
   const int vol = lx * lt, lxc = lx / bx, volc = vol / (bx * bt);
   const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= (size_t)nrhs * vol * 2 * n) return;
+  if (gid >= (size_t)nrhs * vol * g * n) return;
   const int i = (int)(gid % n);
-  const int chi = (int)((gid / n) % 2);
-  const int s = (int)((gid / (2 * n)) % vol);
-  const int r = (int)(gid / ((size_t)2 * n * vol));
+  const int chi = (int)((gid / n) % g);
+  const int s = (int)((gid / ((size_t)g * n)) % vol);
+  const int r = (int)(gid / ((size_t)g * n * vol));
   const int x = s % lx, t = s / lx;
   const int sc = (t / bt) * lxc + x / bx;
   C acc = mk(0.0, 0.0);
-  const C* c = in + (((size_t)r * volc + sc) * 2 + chi) * nv;
-  for (int k = 0; k < nv; ++k) cmadd(acc, Q[(((size_t)k * vol + s) * 2 + chi) * n + i], c[k]);
+  const C* c = in + (((size_t)r * volc + sc) * g + chi) * nv;
+  for (int k = 0; k < nv; ++k) cmadd(acc, Q[(((size_t)k * vol + s) * g + chi) * n + i], c[k]);
   out[gid] = acc;
 }
 
 // Block QR of the candidates (Sec. 2, P V_c = V with P^dagger P = I; Sec. 3,
 // one block per aggregate and chirality): modified Gram-Schmidt applied twice
 // per column, which yields the thin QR with a real positive diagonal of R.
-// One thread per (aggregate, chirality); Q is overwritten in place.  A column
+// One thread per (aggregate, group); Q is overwritten in place.  A column
 // whose remaining norm falls to 1e-12 of its original norm sets *status = 1.
-__global__ void k_block_qr(C* __restrict__ Q, int lx, int lt, int bx, int bt, int n, int nv,
+__global__ void k_block_qr(C* __restrict__ Q, int lx, int lt, int bx, int bt, int g, int n, int nv,
                            int* __restrict__ status) {
   const int vol = lx * lt, lxc = lx / bx, volc = vol / (bx * bt);
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= volc * 2) return;
-  const int chi = gid % 2, sc = gid / 2;
+  if (gid >= volc * g) return;
+  const int chi = gid % g, sc = gid / g;
   const int xc = sc % lxc, tc = sc / lxc;
   const int m = bx * bt * n;
   auto at = [&](int k, int e) -> C& {
     const int i = e % n, b = e / n;
     const int s = (tc * bt + b / bx) * lx + xc * bx + b % bx;
-    return Q[(((size_t)k * vol + s) * 2 + chi) * n + i];
+    return Q[(((size_t)k * vol + s) * g + chi) * n + i];
   };
   for (int k = 0; k < nv; ++k) {
     double orig = 0.0;
@@ -632,10 +635,11 @@ __global__ void __launch_bounds__(256) k_fcg_p(C* __restrict__ p, const C* __res
 // ---------------------------------------------------------------------------
 // Context.
 struct Lev2 {
-  int lx = 0, lt = 0, vol = 0, n = 1;  // n: dof per chirality
-  size_t nf = 0;                       // complex elements per field
+  int lx = 0, lt = 0, vol = 0;
+  int g = 2, n = 1;                    // groups per site (2 chiralities, or 1: spin blocked), dof per group
+  size_t nf = 0;                       // complex elements per field: vol * g * n
   int nv = 0;                          // candidates of the coarsening from this level
-  C* Q = nullptr;                      // [nv][vol][2][n]
+  C* Q = nullptr;                      // [nv][vol][g][n]
   C* B = nullptr;                      // stencil of this level (l >= 1)
   int S = 0;
   C *X = nullptr, *R = nullptr, *T = nullptr, *Y = nullptr, *Bv = nullptr;  // cycle work
@@ -665,6 +669,7 @@ struct wdmg_2d_ctx {
   bool setup = false, normal = false;
   double omega = 0.8;
   int nu_pre = 2, nu_post = 2, use_alpha = 1, coarse_cycles = 1;
+  int blocking = 0;              // 0 chirality kept; 1 spin blocked, R = P^dagger gamma5; 2 spin blocked, R = P^dagger
   C* Maug = nullptr;             // coarsest [M^-1 reduced | ...]: [nc][2 nc]
   C* gjcol = nullptr;
   int nc = 0;
@@ -769,7 +774,7 @@ void apply_level(Ctx& c, int l, C* out, const C* in, int nrhs) {
     return;
   }
   const Lev2& L = c.lev[l];
-  const int N = 2 * L.n;
+  const int N = L.g * L.n;
   const size_t tot = (size_t)nrhs * L.vol * N;
   const size_t lanes = tot * N;
   if (N == 8)
@@ -785,29 +790,32 @@ void apply_level(Ctx& c, int l, C* out, const C* in, int nrhs) {
   c.flops += 8.0 * L.S * (double)L.vol * N * N * nrhs;
 }
 
+// P^dagger (or P^dagger gamma5 at the fine level of the spin-blocked control with blocking = 1)
 void restrict_to(Ctx& c, int l, C* out, const C* in, int nrhs, const int blk[2]) {
   const Lev2& L = c.lev[l];
-  const size_t tot = (size_t)nrhs * (L.vol / (blk[0] * blk[1])) * 2 * L.nv;
+  const size_t tot = (size_t)nrhs * (L.vol / (blk[0] * blk[1])) * L.g * L.nv;
   const int A = blk[0] * blk[1];
+  const int g5 = (l == 0 && c.blocking == 1) ? 1 : 0;
   if (A == 16)
-    k_restrict_w<16><<<blocks_for(tot * 16, 256), 256, 0, c.stream>>>(out, in, L.Q, L.lx, L.lt, blk[0], L.n, L.nv,
-                                                                      nrhs);
+    k_restrict_w<16><<<blocks_for(tot * 16, 256), 256, 0, c.stream>>>(out, in, L.Q, L.lx, L.lt, blk[0], L.g, L.n,
+                                                                      L.nv, g5, nrhs);
   else if (A == 4)
-    k_restrict_w<4><<<blocks_for(tot * 4, 256), 256, 0, c.stream>>>(out, in, L.Q, L.lx, L.lt, blk[0], L.n, L.nv,
-                                                                    nrhs);
+    k_restrict_w<4><<<blocks_for(tot * 4, 256), 256, 0, c.stream>>>(out, in, L.Q, L.lx, L.lt, blk[0], L.g, L.n,
+                                                                    L.nv, g5, nrhs);
   else
-    k_restrict<<<blocks_for(tot, 256), 256, 0, c.stream>>>(out, in, L.Q, L.lx, L.lt, blk[0], blk[1], L.n, L.nv,
-                                                           nrhs);
+    k_restrict<<<blocks_for(tot, 256), 256, 0, c.stream>>>(out, in, L.Q, L.lx, L.lt, blk[0], blk[1], L.g, L.n,
+                                                           L.nv, g5, nrhs);
   launch_check();
-  c.flops += 8.0 * (double)L.vol * 2 * L.n * L.nv * nrhs;
+  c.flops += 8.0 * (double)L.vol * L.g * L.n * L.nv * nrhs;
 }
 
 void prolong_from(Ctx& c, int l, C* out, const C* in, int nrhs, const int blk[2]) {
   const Lev2& L = c.lev[l];
   const size_t tot = (size_t)nrhs * L.nf;
-  k_prolong<<<blocks_for(tot, 256), 256, 0, c.stream>>>(out, in, L.Q, L.lx, L.lt, blk[0], blk[1], L.n, L.nv, nrhs);
+  k_prolong<<<blocks_for(tot, 256), 256, 0, c.stream>>>(out, in, L.Q, L.lx, L.lt, blk[0], blk[1], L.g, L.n, L.nv,
+                                                        nrhs);
   launch_check();
-  c.flops += 8.0 * (double)L.vol * 2 * L.n * L.nv * nrhs;
+  c.flops += 8.0 * (double)L.vol * L.g * L.n * L.nv * nrhs;
 }
 
 // about two elements per thread, at most kMaxDotGroups workgroups
@@ -937,6 +945,10 @@ void mg_setup(Ctx& c, const wdmg_2d_mg_params& p) {
   if (p.setup_iters < 0 || p.nu_pre < 0 || p.nu_post < 0 || !(p.omega > 0.0))
     throw Err{WDMG_ERR_ARG, "negative iteration count or non-positive omega"};
   if (p.coarse_cycles < 1 || p.coarse_cycles > 64) throw Err{WDMG_ERR_ARG, "coarse_cycles must be 1..64"};
+  if (p.blocking < 0 || p.blocking > 2) throw Err{WDMG_ERR_ARG, "blocking must be 0, 1 or 2"};
+  if (p.blocking && (p.n_levels != 2 || p.normal))
+    throw Err{WDMG_ERR_ARG, "spin blocking is built for two-level hierarchies of D"};
+  const int groups = p.blocking ? 1 : 2;
   {
     int lx = c.lx, lt = c.lt;
     for (int l = 0; l + 1 < p.n_levels; ++l) {
@@ -947,10 +959,10 @@ void mg_setup(Ctx& c, const wdmg_2d_mg_params& p) {
       lt /= p.block[1];
       if (!smallest_divisor_ge3(lx) || !smallest_divisor_ge3(lt))
         throw Err{WDMG_ERR_DIMS, "coarse extents must be >= 3 (coloured probing)"};
-      if (p.block[0] * p.block[1] * (l == 0 ? 1 : p.nv[l - 1]) < p.nv[l])
+      if (p.block[0] * p.block[1] * (l == 0 ? 2 / groups : p.nv[l - 1]) < p.nv[l])
         throw Err{WDMG_ERR_DIMS, "aggregate too small for nv candidates"};
     }
-    const long long ncl = (long long)lx * lt * 2 * p.nv[p.n_levels - 2];
+    const long long ncl = (long long)lx * lt * groups * p.nv[p.n_levels - 2];
     if (ncl > 4096) throw Err{WDMG_ERR_DIMS, "coarsest level above 4096 unknowns"};
   }
   drop_hierarchy(c);
@@ -960,11 +972,13 @@ void mg_setup(Ctx& c, const wdmg_2d_mg_params& p) {
   c.nu_post = p.nu_post;
   c.use_alpha = p.use_alpha != 0;
   c.coarse_cycles = p.coarse_cycles;
+  c.blocking = p.blocking;
   Lev2 L0;
   L0.lx = c.lx;
   L0.lt = c.lt;
   L0.vol = c.lx * c.lt;
-  L0.n = 1;
+  L0.g = groups;
+  L0.n = 2 / groups;  // the two spins: two chirality groups of one, or one group of two
   L0.nf = (size_t)L0.vol * 2;
   c.lev.push_back(L0);
   const int blk[2] = {p.block[0], p.block[1]};
@@ -988,8 +1002,8 @@ void mg_setup(Ctx& c, const wdmg_2d_mg_params& p) {
         }
       }
       Q2_HIP(hipMemsetAsync(c.status, 0, sizeof(int), c.stream));
-      const int nagg = L.vol / (blk[0] * blk[1]) * 2;
-      k_block_qr<<<blocks_for(nagg, 64), 64, 0, c.stream>>>(L.Q, L.lx, L.lt, blk[0], blk[1], L.n, nv, c.status);
+      const int nagg = L.vol / (blk[0] * blk[1]) * L.g;
+      k_block_qr<<<blocks_for(nagg, 64), 64, 0, c.stream>>>(L.Q, L.lx, L.lt, blk[0], blk[1], L.g, L.n, nv, c.status);
       launch_check();
       int st = 0;
       Q2_HIP(hipMemcpyAsync(&st, c.status, sizeof(int), hipMemcpyDeviceToHost, c.stream));
@@ -1000,10 +1014,11 @@ void mg_setup(Ctx& c, const wdmg_2d_mg_params& p) {
     Cl.lx = c.lev[l].lx / blk[0];
     Cl.lt = c.lev[l].lt / blk[1];
     Cl.vol = Cl.lx * Cl.lt;
+    Cl.g = groups;
     Cl.n = nv;
-    Cl.nf = (size_t)Cl.vol * 2 * nv;
+    Cl.nf = (size_t)Cl.vol * groups * nv;
     Cl.S = c.normal ? 9 : 5;
-    const int N = 2 * nv;
+    const int N = groups * nv;
     Cl.B = calloc_fields(c, (size_t)Cl.S * Cl.vol * N * N, c.hier);
     c.lev.push_back(Cl);
     // Galerkin operator P^dagger A_l P by coloured probing
@@ -1028,7 +1043,7 @@ void mg_setup(Ctx& c, const wdmg_2d_mg_params& p) {
   // the coarsest operator, inverted
   {
     const Lev2& Cc = c.lev.back();
-    const int N = 2 * Cc.n;
+    const int N = Cc.g * Cc.n;
     const int n = Cc.vol * N;
     c.nc = n;
     c.Maug = calloc_fields(c, (size_t)n * 2 * n, c.hier);
@@ -1081,6 +1096,7 @@ void bicgstab(Ctx& c, C* x, const C* b, double tol, int maxit, wdmg_2d_stats& st
   Q2_HIP(hipMemsetAsync(x, 0, n * sizeof(C), c.stream));
   const double bn = std::sqrt(norm2(c, b, n));
   st.true_res = 1.0;
+  if (!std::isfinite(bn)) throw Err{WDMG_ERR_NAN, "right-hand side holds NaN or Inf"};
   if (bn == 0.0) {
     st.converged = 1;
     st.true_res = 0.0;
@@ -1108,6 +1124,7 @@ void bicgstab(Ctx& c, C* x, const C* b, double tol, int maxit, wdmg_2d_stats& st
       dots<M_NORM>(c, r, r, nullptr, nullptr, n, 1);
       read_scalars(c);
       if (c.hsc[S_FLAG].re != 0.0) break;  // breakdown: restart from the true residual
+      if (!std::isfinite(c.hsc[S_RR].re)) throw Err{WDMG_ERR_NAN, "NaN or Inf in the BiCGstab residual"};
       st.iters += 1;
       const C om = c.hsc[S_OMEGA];
       if (std::sqrt(c.hsc[S_RR].re) <= tol * bn || (om.re == 0.0 && om.im == 0.0)) break;
@@ -1132,6 +1149,7 @@ void fcg_normal(Ctx& c, C* x, const C* b, double tol, int maxit, bool precond, w
   Q2_HIP(hipMemsetAsync(x, 0, n * sizeof(C), c.stream));
   const double bn = std::sqrt(norm2(c, b, n));
   st.true_res = 1.0;
+  if (!std::isfinite(bn)) throw Err{WDMG_ERR_NAN, "right-hand side holds NaN or Inf"};
   if (bn == 0.0) {
     st.converged = 1;
     st.true_res = 0.0;
@@ -1163,7 +1181,9 @@ void fcg_normal(Ctx& c, C* x, const C* b, double tol, int maxit, bool precond, w
     k_update<<<blocks_for(n, 256), 256, 0, c.stream>>>(x, r, p, q, c.sc, S_ALPHA, n, 1);
     launch_check();
     st.iters += 1;
-    if (std::sqrt(norm2(c, r, n)) <= tol2 * rn) {
+    const double rr = norm2(c, r, n);
+    if (!std::isfinite(rr)) throw Err{WDMG_ERR_NAN, "NaN or Inf in the CG residual"};
+    if (std::sqrt(rr) <= tol2 * rn) {
       st.true_res = true_res();
       if (st.true_res <= tol) {
         st.converged = 1;
@@ -1330,7 +1350,7 @@ int wdmg_2d_get_coarse_operator(wdmg_2d_ctx* h, int level, void* blocks) {
     check_level(c, level, 1, (int)c.lev.size() - 1);
     if (!blocks) throw Err{WDMG_ERR_ARG, "blocks required"};
     const Lev2& L = c.lev[level];
-    const size_t N = 2 * (size_t)L.n;
+    const size_t N = (size_t)L.g * L.n;
     Q2_HIP(hipMemcpyAsync(blocks, L.B, (size_t)L.S * L.vol * N * N * sizeof(C), hipMemcpyDeviceToDevice, c.stream));
     return (int)WDMG_OK;
   });

@@ -22,7 +22,8 @@ class MgParams2d(ctypes.Structure):
     _fields_ = [("n_levels", ctypes.c_int), ("block", ctypes.c_int * 2), ("nv", ctypes.c_int * (MAX_LEVELS - 1)),
                 ("setup_iters", ctypes.c_int), ("vectors", ctypes.c_void_p * (MAX_LEVELS - 1)),
                 ("normal", ctypes.c_int), ("omega", ctypes.c_double), ("nu_pre", ctypes.c_int),
-                ("nu_post", ctypes.c_int), ("use_alpha", ctypes.c_int), ("coarse_cycles", ctypes.c_int)]
+                ("nu_post", ctypes.c_int), ("use_alpha", ctypes.c_int), ("coarse_cycles", ctypes.c_int),
+                ("blocking", ctypes.c_int)]
 
 
 class Stats2d(ctypes.Structure):
@@ -96,7 +97,7 @@ class Context2d:
         if rc != wdmg.WDMG_OK:
             raise wdmg.WdmgError(rc, "wdmg_2d_create failed")
         self.h = h
-        self.levels = []  # (lt, lx, n) per level after setup
+        self.levels = []  # (lt, lx, g, n) per level after setup
         self.normal = False
 
     def _check(self, rc: int, allow_not_converged: bool = False) -> int:
@@ -120,8 +121,8 @@ class Context2d:
         return (self.lt, self.lx, 2)
 
     def level_shape(self, level):
-        lt, lx, n = self.levels[level]
-        return (lt, lx, 2, n)
+        lt, lx, g, n = self.levels[level]
+        return (lt, lx, g, n)
 
     def set_gauge(self, U: torch.Tensor, t_bc: int = -1):
         if tuple(U.shape) != (self.lt, self.lx, 2):
@@ -142,40 +143,45 @@ class Context2d:
         return out
 
     def mg_setup(self, nvs, vectors, *, block=(4, 4), setup_iters=100, normal=False, omega=0.8, nu_pre=2,
-                 nu_post=2, use_alpha=True, coarse_cycles=1):
+                 nu_post=2, use_alpha=True, coarse_cycles=1, blocking=0):
         """``nvs[l]`` candidates per coarsening, ``vectors[l]`` their complex128
-        device starting vectors ``[nv, Tl, Xl, 2, n_l]``."""
+        device starting vectors ``[nv, Tl, Xl, 2, n_l]`` (the fine level as
+        ``[nv, T, X, 2, 1]`` in every case); ``blocking`` 1 or 2 selects the
+        spin-blocked control (two levels of D)."""
         p = MgParams2d()
         p.n_levels = len(nvs) + 1
         p.block = (ctypes.c_int * 2)(*[int(b) for b in block])
-        levels = [(self.lt, self.lx, 1)]
+        g = 1 if blocking else 2
+        levels = [(self.lt, self.lx, g, 2 // g)]
         for i, (nv, v) in enumerate(zip(nvs, vectors)):
-            lt, lx, n = levels[-1]
-            if tuple(v.shape) != (nv, lt, lx, 2, n):
-                raise ValueError(f"level {i} vectors: shape {tuple(v.shape)} != {(nv, lt, lx, 2, n)}")
+            lt, lx, _, n = levels[-1]
+            want = (nv, lt, lx, 2, 1) if i == 0 else (nv, lt, lx, g, n)
+            if tuple(v.shape) != want:
+                raise ValueError(f"level {i} vectors: shape {tuple(v.shape)} != {want}")
             p.nv[i] = int(nv)
             p.vectors[i] = _c128(v, f"level {i} vectors")
-            levels.append((lt // block[1], lx // block[0], int(nv)))
+            levels.append((lt // block[1], lx // block[0], g, int(nv)))
         p.setup_iters = int(setup_iters)
         p.normal = 1 if normal else 0
         p.omega, p.nu_pre, p.nu_post = float(omega), int(nu_pre), int(nu_post)
         p.use_alpha = 1 if use_alpha else 0
         p.coarse_cycles = int(coarse_cycles)
+        p.blocking = int(blocking)
         self._check(self.lib.wdmg_2d_mg_setup(self.h, ctypes.byref(p)))
         self.levels = levels
         self.normal = bool(normal)
 
     def get_prolongator(self, level: int):
-        lt, lx, n = self.levels[level]
-        nv = self.levels[level + 1][2]
-        out = torch.empty((nv, lt, lx, 2, n), dtype=torch.complex128, device=self.device)
+        lt, lx, g, n = self.levels[level]
+        nv = self.levels[level + 1][3]
+        out = torch.empty((nv, lt, lx, g, n), dtype=torch.complex128, device=self.device)
         self._check(self.lib.wdmg_2d_get_prolongator(self.h, int(level), out.data_ptr()))
         return out
 
     def get_coarse_operator(self, level: int):
-        lt, lx, n = self.levels[level]
+        lt, lx, g, n = self.levels[level]
         S = 9 if self.normal else 5
-        out = torch.empty((S, lt, lx, 2 * n, 2 * n), dtype=torch.complex128, device=self.device)
+        out = torch.empty((S, lt, lx, g * n, g * n), dtype=torch.complex128, device=self.device)
         self._check(self.lib.wdmg_2d_get_coarse_operator(self.h, int(level), out.data_ptr()))
         return out
 

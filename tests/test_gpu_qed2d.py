@@ -183,5 +183,53 @@ def test_error_paths():
     with pytest.raises(wdmg.WdmgError) as e:
         c.solve(b, method="mg-cg")
     assert e.value.name == "WDMG_ERR_NOT_SETUP"
+    bad = b.clone()
+    bad[3, 5, 1] = float("nan")
+    for method in ("mg-bicgstab", "cg"):
+        with pytest.raises(wdmg.WdmgError) as e:
+            c.solve(bad, method=method)
+        assert e.value.name == "WDMG_ERR_NAN"
+    x, st = c.solve(b, method="cg", tol=1e-10)  # the context still works
+    assert st["converged"]
     c.close()
     del qed2d
+
+
+@pytest.mark.parametrize("blocking", [1, 2])
+def test_spin_blocked_control_matches_the_oracle(blocking):
+    # the Sec. 3 footnote's control: both spins in one block, restricted with
+    # P^dagger gamma5 (1) or P^dagger (2); two levels of D
+    dims, m, nv = (24, 24), 0.05, 8
+    u = synthetic.u1_gauge_field(dims, 6.0, seed=400)
+    v0 = synthetic.gaussian_vectors((nv, 24, 24, 2, 1), 401)
+    c = _ctx(dims, u, m)
+    c.mg_setup([nv], [torch.from_numpy(v0).to(DEV)], setup_iters=20, blocking=blocking)
+    h = O.build(u, m, -1.0, nvs=[nv], block=(4, 4), setup_iters=20, seeds=[401], blocking=blocking)
+    q = c.get_prolongator(0).cpu().numpy()
+    assert q.shape == (nv, 24, 24, 1, 2)
+    assert np.abs(q - h.qs[0].reshape(q.shape)).max() <= 1e-9
+    B = c.get_coarse_operator(1).cpu().numpy()
+    Bo = O.stencil_blocks(h.mats[0], (6, 6), nv, O.OFFSETS_DIRECT, groups=1)
+    assert np.abs(B - Bo).max() <= 1e-9 * np.abs(Bo).max()
+    P = O.prolongator_matrix(h.qs[0], (4, 4))
+    f = synthetic.gaussian_spinor_2d(dims, seed=402)
+    rc = c.restrict(0, torch.from_numpy(f).to(DEV)).cpu().numpy()
+    g5f = (O.sparse_gamma5(24 * 24) @ f.ravel()) if blocking == 1 else f.ravel()
+    want = (P.conj().T @ g5f).reshape(rc.shape)
+    assert np.abs(rc - want).max() <= 1e-12 * np.abs(want).max()
+    r = synthetic.gaussian_spinor_2d(dims, seed=403)
+    x = c.vcycle(torch.from_numpy(r).to(DEV)).cpu().numpy()
+    xo = h.vcycle(0, r.reshape((1, 1, 24, 24, 1, 2))).reshape(r.shape)
+    assert _rel(x, xo) <= 1e-9, _rel(x, xo)
+    b = synthetic.gaussian_spinor_2d(dims, seed=404)
+    xs, st = c.solve(torch.from_numpy(b).to(DEV), method="mg-bicgstab", tol=1e-10, maxit=2000)
+    res = np.linalg.norm(b - O.apply_D(u, xs.cpu().numpy(), m, -1.0)) / np.linalg.norm(b)
+    assert st["converged"] and res <= 1e-10
+    _, info = O.mg_bicgstab(h, b, 1e-10, maxit=2000)
+    assert abs(st["iters"] - info["iters"]) <= max(2, info["iters"] // 10), (st["iters"], info["iters"])
+    from paper_0811_4331_amd import wdmg
+    with pytest.raises(wdmg.WdmgError) as e:  # three levels with spin blocking are refused
+        c.mg_setup([nv, 4], [torch.from_numpy(v0).to(DEV), torch.zeros((4, 6, 6, 1, nv), dtype=torch.complex128,
+                                                                       device=DEV)], blocking=blocking)
+    assert e.value.name == "WDMG_ERR_ARG"
+    c.close()
