@@ -103,8 +103,9 @@ int wdmg_2d_apply_D(wdmg_2d_ctx* ctx, void* out, const void* in, int nrhs, int d
 /* Adaptive setup (Sec. 2) of the hierarchy of D or D^dagger D: per coarsening,
  * relaxation of the starting vectors, block QR per aggregate and chirality
  * (Sec. 3, chirality kept intact), Galerkin operator P^dagger A P (read off by
- * coloured probing: every coarse extent must be >= 3 and have a divisor
- * K with 3 <= K; WDMG_ERR_DIMS otherwise), and on the coarsest level the
+ * coloured probing, the colours repeating with the smallest divisor >= 3 of
+ * each coarse extent: every coarse extent must be >= 3, else WDMG_ERR_DIMS;
+ * the coarsest level may hold at most 4096 unknowns), and on the coarsest level the
  * explicit inverse of its operator (Gauss-Jordan with partial pivoting), which
  * makes the coarsest solve exact to rounding (Sec. 4).  Errors:
  * WDMG_ERR_RANK_DEFICIENT (candidates dependent on an aggregate),

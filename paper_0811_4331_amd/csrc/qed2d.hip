@@ -720,26 +720,42 @@ void drop_hierarchy(Ctx& c) {
   c.nc = 0;
 }
 
+void free_tmp(Ctx& c) {
+  if (!c.tmp) return;
+  Q2_HIP(hipStreamSynchronize(c.stream));
+  for (size_t i = 0; i < c.bufs.size(); ++i)
+    if (c.bufs[i] == c.tmp) {
+      if (c.alloc.free)
+        c.alloc.free(c.tmp, c.alloc.user);
+      else
+        (void)hipFree(c.tmp);
+      c.bufs.erase(c.bufs.begin() + i);
+      break;
+    }
+  c.tmp = nullptr;
+  c.tmp_fields = 0;
+}
+
 C* ensure_tmp(Ctx& c, int nrhs) {
   const size_t need = (size_t)nrhs;
   if (c.tmp_fields < need) {
-    if (c.tmp) {
-      Q2_HIP(hipStreamSynchronize(c.stream));
-      for (size_t i = 0; i < c.bufs.size(); ++i)
-        if (c.bufs[i] == c.tmp) {
-          if (c.alloc.free)
-            c.alloc.free(c.tmp, c.alloc.user);
-          else
-            (void)hipFree(c.tmp);
-          c.bufs.erase(c.bufs.begin() + i);
-          break;
-        }
-    }
+    free_tmp(c);
     c.tmp = calloc_fields(c, need * c.lx * c.lt * 2, c.bufs);
     c.tmp_fields = need;
   }
   return c.tmp;
 }
+
+// Work buffers of one setup, released when it ends (also when it fails).
+struct SetupScratch {
+  Ctx& c;
+  std::vector<void*> bufs;
+  explicit SetupScratch(Ctx& cc) : c(cc) {}
+  ~SetupScratch() {
+    (void)hipStreamSynchronize(c.stream);
+    release(c, bufs);
+  }
+};
 
 void launch_check() {
   hipError_t e = hipGetLastError();
@@ -982,6 +998,7 @@ void mg_setup(Ctx& c, const wdmg_2d_mg_params& p) {
   L0.nf = (size_t)L0.vol * 2;
   c.lev.push_back(L0);
   const int blk[2] = {p.block[0], p.block[1]};
+  SetupScratch scratch(c);
   for (int l = 0; l + 1 < p.n_levels; ++l) {
     const int nv = p.nv[l];
     {
@@ -991,8 +1008,8 @@ void mg_setup(Ctx& c, const wdmg_2d_mg_params& p) {
       Q2_HIP(hipMemcpyAsync(L.Q, p.vectors[l], (size_t)nv * L.nf * sizeof(C), hipMemcpyDeviceToDevice, c.stream));
       if (p.setup_iters > 0) {
         // relax A v = 0 (Sec. 2): r = -A v, then MR steps with one step size per vector
-        C* R = calloc_fields(c, (size_t)nv * L.nf, c.hier);
-        C* T = calloc_fields(c, (size_t)nv * L.nf, c.hier);
+        C* R = calloc_fields(c, (size_t)nv * L.nf, scratch.bufs);
+        C* T = calloc_fields(c, (size_t)nv * L.nf, scratch.bufs);
         apply_level(c, l, T, L.Q, nv);
         k_neg<<<blocks_for(nv * L.nf, 256), 256, 0, c.stream>>>(R, T, nv * L.nf);
         launch_check();
@@ -1027,9 +1044,9 @@ void mg_setup(Ctx& c, const wdmg_2d_mg_params& p) {
       const Lev2& Cc = c.lev[l + 1];
       const int K0 = smallest_divisor_ge3(Cc.lx), K1 = smallest_divisor_ge3(Cc.lt);
       const int np = K0 * K1 * N;
-      C* probes = calloc_fields(c, (size_t)np * Cc.nf, c.hier);
-      C* fine = calloc_fields(c, (size_t)np * L.nf, c.hier);
-      C* fine2 = calloc_fields(c, (size_t)np * L.nf, c.hier);
+      C* probes = calloc_fields(c, (size_t)np * Cc.nf, scratch.bufs);
+      C* fine = calloc_fields(c, (size_t)np * L.nf, scratch.bufs);
+      C* fine2 = calloc_fields(c, (size_t)np * L.nf, scratch.bufs);
       k_probe_fill<<<blocks_for((size_t)np * Cc.nf, 256), 256, 0, c.stream>>>(probes, Cc.lx, Cc.lt, N, K0, K1);
       launch_check();
       prolong_from(c, l, fine, probes, np, blk);
@@ -1071,6 +1088,7 @@ void mg_setup(Ctx& c, const wdmg_2d_mg_params& p) {
     L.Rs = calloc_fields(c, L.nf, c.hier);
     L.T2 = calloc_fields(c, L.nf, c.hier);
   }
+  if (c.tmp_fields > 1) free_tmp(c);  // the probes' D^dagger D work field
   ensure_tmp(c, 1);
   Q2_HIP(hipStreamSynchronize(c.stream));
   c.setup = true;
