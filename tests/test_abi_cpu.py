@@ -106,3 +106,35 @@ def test_allocator_callbacks_never_raise_into_the_library():
     ok, _ = wdmg._torch_allocator(lambda n, d, s: 4096 * n, boom, 0, None)
     ok_c = wdmg._ALLOC_FN(ok)
     assert wdmg._ALLOC_FN(ctypes.cast(ok_c, ctypes.c_void_p).value)(3, None) == 3 * 4096
+
+
+def test_2d_struct_layouts_match_the_binding():
+    # wdmg_2d.h compiled as C with gcc: the parameter and statistics structs
+    # have the sizes and field offsets the ctypes binding assumes
+    from paper_0811_4331_amd import qed2d
+    src = r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "wdmg_2d.h"
+int main(void){printf("%zu %zu %zu %zu %zu\n", sizeof(wdmg_2d_mg_params), sizeof(wdmg_2d_stats),
+ offsetof(wdmg_2d_mg_params, omega), offsetof(wdmg_2d_mg_params, blocking), offsetof(wdmg_2d_stats, flops));
+ return 0;}
+'''
+    import tempfile
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "s.c")
+        exe = os.path.join(d, "s")
+        open(c, "w").write(src)
+        subprocess.run(["gcc", "-I", os.path.dirname(wdmg.HEADER), c, "-o", exe], check=True)
+        got = [int(v) for v in subprocess.run([exe], capture_output=True, text=True).stdout.split()]
+    assert got == [ctypes.sizeof(qed2d.MgParams2d), ctypes.sizeof(qed2d.Stats2d), qed2d.MgParams2d.omega.offset,
+                   qed2d.MgParams2d.blocking.offset, qed2d.Stats2d.flops.offset]
+
+
+def test_2d_create_rejects_bad_dims_without_a_gpu_call():
+    from paper_0811_4331_amd import qed2d
+    lib = qed2d.load()
+    h = ctypes.c_void_p()
+    for dims in ((3, 8), (8, 2), (6, 7)):
+        assert lib.wdmg_2d_create(ctypes.byref(h), (ctypes.c_int * 2)(*dims), None, None) == -2
+    assert lib.wdmg_2d_create(None, (ctypes.c_int * 2)(8, 8), None, None) == -1
