@@ -12,6 +12,9 @@ import synthetic
 from oracle import qed2d, transfer
 
 HERE = os.path.dirname(os.path.abspath(__file__))
+# the gamma matrices of the 2d reading, written out here rather than taken
+# from the oracle: gamma_0 = sigma_1, gamma_1 = sigma_2 (gamma5 = sigma_3)
+PAULI = np.array([[[0, 1], [1, 0]], [[0, -1j], [1j, 0]]], dtype=np.complex128)
 
 
 def _free(lx, lt):
@@ -47,7 +50,7 @@ def test_plane_wave_in_a_constant_background_is_shifted():
     psi = wave[..., None] * chi
     q = (p[0] + th[0], p[1] + th[1])
     Dp = (m + 2 - np.cos(q[0]) - np.cos(q[1])) * np.eye(2) + 1j * (
-        qed2d.SIGMA[0] * np.sin(q[0]) + qed2d.SIGMA[1] * np.sin(q[1]))
+        PAULI[0] * np.sin(q[0]) + PAULI[1] * np.sin(q[1]))
     np.testing.assert_allclose(qed2d.apply_D(u, psi, m, 1.0), wave[..., None] * (Dp @ chi), atol=1e-13)
 
 
@@ -102,7 +105,7 @@ def test_galerkin_of_the_free_field_with_constant_candidates(block):
     for mu in range(2):
         for s in (1, -1):
             d = (s, 0) if mu == 0 else (0, s)
-            want[d] = -(qed2d.ID2 - s * qed2d.SIGMA[mu]) / (2 * block[mu])
+            want[d] = -(np.eye(2) - s * PAULI[mu]) / (2 * block[mu])
     for o, d in enumerate(qed2d.OFFSETS_DIRECT):
         np.testing.assert_allclose(B[o], np.broadcast_to(want[d], B[o].shape), atol=1e-14)
 
