@@ -9,6 +9,14 @@ import synthetic
 from oracle import wilson
 
 RTOL = 1e-13
+# the chiral basis of the reading, written out here rather than taken from the
+# oracle (gamma_1..gamma_3 on x, y, z; gamma_4 on t; gamma5 = diag(1, 1, -1, -1))
+CHIRAL_GAMMAS = np.array([
+    [[0, 0, 0, -1j], [0, 0, -1j, 0], [0, 1j, 0, 0], [1j, 0, 0, 0]],
+    [[0, 0, 0, -1], [0, 0, 1, 0], [0, 1, 0, 0], [-1, 0, 0, 0]],
+    [[0, 0, -1j, 0], [0, 0, 0, 1j], [1j, 0, 0, 0], [0, -1j, 0, 0]],
+    [[0, 0, 1, 0], [0, 0, 0, 1], [1, 0, 0, 0], [0, 1, 0, 0]],
+], dtype=np.complex128)
 
 
 def rel(a, b):
@@ -76,6 +84,11 @@ def test_free_field_plane_wave_spectrum(t_bc):
             # no leakage out of the plane wave: the same coefficients everywhere
             assert np.allclose(coeff, coeff[0, 0, 0, 0], atol=1e-13)
             mk[:, j] = coeff[0, 0, 0, 0].reshape(12)
+        # the matrix itself: D(p) = (m + sum (1 - cos p)) + i sum gamma_mu sin p_mu, per colour;
+        # this fixes D against D^dagger, which has the same spectrum
+        dp = (m + sum(1 - np.cos(q) for q in p)) * np.eye(4) + 1j * sum(
+            CHIRAL_GAMMAS[mu] * np.sin(p[mu]) for mu in range(4))
+        assert np.allclose(mk, np.kron(dp, np.eye(3)), atol=1e-12)
         ev = np.linalg.eigvals(mk)
         ev = ev[np.lexsort((ev.real, np.round(ev.imag, 9)))]
         re = m + sum(1 - np.cos(q) for q in p)
@@ -146,3 +159,11 @@ def test_per_site_operator_matches_whole_lattice_forms():
     for n, (x, y, z, t) in enumerate(sites2):
         i = x + 2 * (y + 2 * (z + 2 * t))
         assert np.abs(pt2[n].reshape(-1) - dense[12 * i:12 * i + 12]).max() < 1e-14
+
+
+def test_exchanged_projectors_fail_the_plane_wave_pin(monkeypatch):
+    # a planted mistake: (1 - gamma) and (1 + gamma) exchanged, i.e. D^dagger
+    # computed in place of D; gamma5-Hermiticity and the spectrum cannot tell
+    monkeypatch.setattr(wilson, "GAMMA", -wilson.GAMMA)
+    with pytest.raises(AssertionError):
+        test_free_field_plane_wave_spectrum(-1.0)
