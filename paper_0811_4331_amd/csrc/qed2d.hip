@@ -881,14 +881,10 @@ double norm2(Ctx& c, const C* v, size_t n) {
 
 namespace {
 
-int blk_of(const Ctx& c, int l, int d) {
-  // aggregate extent of coarsening l in direction d (the same at every coarsening)
-  return c.lev[l].lx / c.lev[l + 1].lx * (d == 0) + c.lev[l].lt / c.lev[l + 1].lt * (d == 1);
-}
-
+// aggregate extents (b_x, b_t) of coarsening l
 void blk_pair(const Ctx& c, int l, int out[2]) {
-  out[0] = blk_of(c, l, 0);
-  out[1] = blk_of(c, l, 1);
+  out[0] = c.lev[l].lx / c.lev[l + 1].lx;
+  out[1] = c.lev[l].lt / c.lev[l + 1].lt;
 }
 
 // x = M r, V-cycle from x = 0 at level l (Sec. 2; Sec. 3 alpha step; Sec. 4 exact coarsest solve).
