@@ -303,3 +303,21 @@ def test_three_level_correction_without_smoothing_is_one_galerkin_solve():
     want = transfer.prolong(q1, transfer.prolong(q2, e2, blk2), blk1)
     got = h.correction(0, r)
     assert np.linalg.norm(got - want) / np.linalg.norm(want) < 1e-10
+
+
+def test_alpha_step_leaves_a_residual_orthogonal_to_the_correction_image():
+    # Sec. 3 step size: alpha = <D y, r> / <D y, D y> minimises ||r - alpha D y||,
+    # so the new residual is orthogonal to D y (no smoothing around it here)
+    dims, blk, nv = (4, 4, 4, 4), (2, 2, 2, 2), 3
+    lev = _wilson_level(dims, seed=21)
+    v = synthetic.gaussian_vectors((nv, 4, 4, 4, 4, 2, 6), 22)
+    q, _ = transfer.block_orthonormalize(v, blk)
+    st = coarse.build_stencil(lev, q, blk)
+    h = mg.Hierarchy([lev, st], [q], [blk], nu_pre=0, nu_post=0, coarse_tol=1e-14, coarse_maxit=2000)
+    r = transfer.as_chiral(synthetic.gaussian_spinor(dims, seed=23))
+    x = h.vcycle(0, r)
+    dy = lev.apply(h.correction(0, r))
+    rn = r - lev.apply(x)
+    assert abs(mg.dot(dy, rn)) <= 1e-12 * np.linalg.norm(dy) * np.linalg.norm(r)
+    a = mg.dot(dy, r) / mg.dot(dy, dy)
+    assert abs(a.imag) > 1e-3  # a complex step: a conjugated formula would not pass
