@@ -66,3 +66,40 @@ def test_conjugated_step_size_is_caught(monkeypatch):
     with pytest.raises(AssertionError):
         pins_mg.test_alpha_step_leaves_a_residual_orthogonal_to_the_correction_image()
     assert calls["n"] >= 1
+
+
+def test_flexible_cg_with_a_flipped_beta_is_caught(monkeypatch):
+    from oracle import normal
+    import test_oracle_normal as pins_normal
+
+    def mutant(apply, b, tol, maxit=10000, precond=None, true_res=None, x0=None):
+        m = precond if precond is not None else (lambda f: f.copy())
+        x = np.zeros_like(b)
+        r = b.copy()
+        bn = mg.norm(b)
+        info = {"iters": 0, "converged": False, "true_res": 1.0}
+        p = q = None
+        while info["iters"] < maxit:
+            z = m(r)
+            p = z if p is None else z + (mg.dot(q, z) / mg.dot(p, q)) * p  # sign of beta flipped
+            q = apply(p)
+            alpha = mg.dot(p, r) / mg.dot(p, q)
+            x, r = x + alpha * p, r - alpha * q
+            info["iters"] += 1
+            if mg.norm(r) <= tol * bn:
+                info["converged"] = True
+                break
+        info["true_res"] = mg.norm(b - apply(x)) / bn
+        return x, info
+    monkeypatch.setattr(normal, "fcg", mutant)
+    with pytest.raises(AssertionError):
+        pins_normal.test_fcg_is_cg_and_exact_with_the_inverse()
+
+
+def test_probing_colours_that_alias_offsets_are_caught(monkeypatch):
+    # colours repeating every 2 coarse sites: the +mu and -mu neighbours share a colour
+    from oracle import normal
+    import test_oracle_normal as pins_normal
+    monkeypatch.setattr(normal, "colouring", lambda cdims: [2 if e % 2 == 0 else e for e in cdims])
+    with pytest.raises(AssertionError):
+        pins_normal.test_stencil_equals_the_literal_galerkin_map((12, 6, 6, 8), (4, 2, 2, 2), 2)
