@@ -422,12 +422,15 @@ def qed2d_bench(a):
     b = torch.from_numpy(synthetic.gaussian_spinor_2d(dims, 7100)).to(dev)
     ctx = qed2d.Context2d(dims, dev)
     ctx.set_gauge(u, -1)
-    configs = [  # (name, method, nvs, coarse cycles)
+    configs = [  # (name, method, nvs, coarse cycles); the last one gives the line's value
         ("CG", "cg", None, 1),
         ("MG-CG Nv=8, V-cycle", "mg-cg", [8, 8], 1),
+        ("MG-CG Nv=8, 4 level-1 cycles", "mg-cg", [8, 8], 4),
         ("MG-CG Nv=8/16, 4 level-1 cycles", "mg-cg", [8, 16], 4),
         ("MG-BiCGstab Nv=3, V-cycle", "mg-bicgstab", [3, 3], 1),
+        ("MG-BiCGstab Nv=3, 4 level-1 cycles", "mg-bicgstab", [3, 3], 4),
         ("MG-BiCGstab Nv=8, V-cycle", "mg-bicgstab", [8, 8], 1),
+        ("MG-BiCGstab Nv=8, 4 level-1 cycles", "mg-bicgstab", [8, 8], 4),
         ("MG-BiCGstab Nv=8/16, 4 level-1 cycles", "mg-bicgstab", [8, 16], 4),
     ]
     rows = []
