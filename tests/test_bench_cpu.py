@@ -126,3 +126,16 @@ def test_default_workload_and_single_gpu(bench, capsys):
         bench.main(["--gpus", "2"])
     assert e.value.code == 2
     assert "one GPU" in capsys.readouterr().out
+
+
+def test_2d_mode_defaults():
+    import bench
+    a = bench.parse(["--qed2d"])
+    assert a.qed2d and a.qed2d_deltas == [0.1, 0.03, 0.01, 0.003]
+    assert a.qed2d_setup_iters == 300 and a.qed2d_rhs == 1
+    # the 2d workload's stored critical mass is there for the benchmark to read
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(bench.__file__), "tests", "golden", "mcrit_2d.json")) as fh:
+        e = json.load(fh)["128x128_beta6.0_seed7000"]
+    assert e["dims"] == [128, 128] and -0.1 < e["m_crit"] < -0.05
