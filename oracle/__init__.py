@@ -26,6 +26,10 @@ Conventions shared with the GPU path (a specification, not code):
   a spinor ``[..., 4, 3]`` reshaped to ``[..., 2, 6]`` is its chirality split.
 * coarse dof order at every level: ``(chi, k)``, index ``chi * Nv + k``.
 * ``<a, b> = sum conj(a) * b``.
+* 2d workload (``qed2d``): dims ``(Lx, Lt)``, arrays ``[t, x, ...]``; links
+  ``[t, x, mu]`` of modulus one; spinors ``[t, x, 2]`` with ``gamma_0 = sigma_1``,
+  ``gamma_1 = sigma_2``, ``gamma5 = sigma_3``; coarse stencils of 5 (D) or 9
+  (``D^dagger D``) offsets ``(d_x, d_t)`` in the order of ``qed2d.OFFSETS_NORMAL``.
 
 Parity status: every function here is pinned by a test in ``tests/`` against
 a closed form, an invariant, a brute-force construction or a library routine,
