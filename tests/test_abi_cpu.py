@@ -138,3 +138,22 @@ def test_2d_create_rejects_bad_dims_without_a_gpu_call():
     for dims in ((3, 8), (8, 2), (6, 7)):
         assert lib.wdmg_2d_create(ctypes.byref(h), (ctypes.c_int * 2)(*dims), None, None) == -2
     assert lib.wdmg_2d_create(None, (ctypes.c_int * 2)(8, 8), None, None) == -1
+
+
+def test_2d_entry_points_reject_a_null_context_without_a_gpu_call():
+    from paper_0811_4331_amd import qed2d
+    lib = qed2d.load()
+    null = None
+    assert lib.wdmg_2d_set_gauge(null, null, -1) == -1
+    assert lib.wdmg_2d_set_mass(null, 0.1) == -1
+    assert lib.wdmg_2d_apply_D(null, null, null, 1, 0) == -1
+    assert lib.wdmg_2d_mg_setup(null, None) == -1
+    assert lib.wdmg_2d_get_prolongator(null, 0, null) == -1
+    assert lib.wdmg_2d_apply_coarse(null, 1, null, null, 1) == -1
+    assert lib.wdmg_2d_restrict(null, 0, null, null, 1) == -1
+    assert lib.wdmg_2d_prolong(null, 0, null, null, 1) == -1
+    assert lib.wdmg_2d_get_coarse_operator(null, 1, null) == -1
+    assert lib.wdmg_2d_vcycle(null, null, null) == -1
+    assert lib.wdmg_2d_solve(null, null, null, 0, 1e-10, 10, None) == -1
+    assert lib.wdmg_2d_last_error(null) == b"null context"
+    lib.wdmg_2d_destroy(null)
