@@ -264,3 +264,27 @@ def test_full_size_hierarchy_element_by_element():
     xo = h.vcycle(0, O.as_level(r[..., None])).reshape(r.shape)
     assert _rel(x, xo) <= 1e-8, _rel(x, xo)
     c.close()
+
+
+@pytest.mark.parametrize("block,nv,blocking", [((2, 2), 4, 0), ((4, 4), 12, 0), ((4, 2), 7, 2)])
+def test_block_qr_of_given_candidates(block, nv, blocking):
+    # setup_iters = 0: P is the block QR of the caller's vectors themselves, so
+    # it must equal the oracle's QR of the same vectors to rounding
+    from oracle import transfer
+    dims = (24, 24)
+    u = synthetic.u1_gauge_field(dims, 6.0, seed=500)
+    v = synthetic.gaussian_vectors((nv, 24, 24, 2, 1), 501)
+    c = _ctx(dims, u, 0.1)
+    c.mg_setup([nv], [torch.from_numpy(v).to(DEV)], block=block, setup_iters=0, blocking=blocking)
+    q = c.get_prolongator(0).cpu().numpy()
+    groups = (1, 2) if blocking else (2, 1)
+    qo, _ = transfer.block_orthonormalize(v.reshape((nv, 1, 1, 24, 24) + groups), O.block4(block))
+    assert np.abs(q - qo.reshape(q.shape)).max() <= 1e-12
+    # the Galerkin blocks of the library against the oracle's sparse product of the same P
+    P = O.prolongator_matrix(qo, block)
+    D = O.sparse_D(u, 0.1, -1.0)
+    Bo = O.stencil_blocks(O.galerkin(D, P), (24 // block[0], 24 // block[1]), nv, O.OFFSETS_DIRECT,
+                          groups=1 if blocking else 2)
+    B = c.get_coarse_operator(1).cpu().numpy()
+    assert np.abs(B - Bo).max() <= 1e-12 * np.abs(Bo).max()
+    c.close()
